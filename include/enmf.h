@@ -1,0 +1,203 @@
+/*
+ * enmf.h -- C ABI of the MI355X (gfx950) exterior-NMF library, libenmf.so.
+ *
+ * Problem (paper "An Exterior Method for Nonnegative Matrix Factorization",
+ * problem statement, eq. 1): given X >= 0 (m x n) and a rank r, find U (m x r)
+ * and V (n x r), both >= 0, minimising f(U,V) = 1/2 ||X - U V^T||_F^2.
+ * The method (Algorithm 3) runs four blocks, one entry point each:
+ *   enmf_svd_init      truncated (randomized) SVD, balanced factors      (section 3, Algorithm 3 step 2)
+ *   enmf_rotate        ADMM rotation toward the nonnegative orthant       (section 3.1, Algorithm 1, eq. 7)
+ *   enmf_iterate       exterior push + PBCD until feasible, then HALS     (sections 3.2-3.3, Algorithms 2-3)
+ *   enmf_objective_kkt objective, relative errors and KKT residual        (appendix, eq. kkt-nmf)
+ * plus the streaming products they are built from (enmf_xv, enmf_xtu, enmf_gram;
+ * appendix on computational complexity: X V, X^T U and the r x r Grams).
+ *
+ * Conventions for every call
+ *   - Matrices are dense, row-major.  X is described by enmf_matrix (leading
+ *     dimension ld >= n, in elements).  Factor matrices are float32 with
+ *     leading dimension r (row i of U starts at U + i*r).
+ *   - Every pointer argument named *_host is host memory; every other pointer
+ *     is device memory on the context's device.  All device buffers are owned
+ *     by the caller; the library never frees them and keeps no pointer to
+ *     them after a call returns.  Workspace is owned by the context.
+ *   - Work is enqueued on the context's stream.  Calls that return host
+ *     values synchronise that stream; no other stream is touched.
+ *   - Calls return an enmf_status and never abort.  Arguments are validated
+ *     on the host before anything is launched; enmf_last_error() then
+ *     describes the failure.  X >= 0 is the caller's contract (eq. 1).
+ *   - A context is not thread-safe; use one per host thread.
+ */
+#ifndef ENMF_H
+#define ENMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ENMF_OK = 0,
+  ENMF_EINVAL = 1,    /* bad argument: null pointer, bad shape, r out of range, bad dtype, ld < n */
+  ENMF_ENOMEM = 2,    /* device workspace could not be allocated */
+  ENMF_EDEVICE = 3,   /* a HIP runtime error (message in enmf_last_error) */
+  ENMF_ENUMERIC = 4,  /* non-finite objective or residual; U, V hold the last iterate */
+  ENMF_EBUSY = 5,
+  ENMF_ECLOSED = 6
+} enmf_status;
+
+typedef enum { ENMF_F32 = 0, ENMF_BF16 = 1, ENMF_F16 = 2 } enmf_dtype;
+
+/* Largest supported rank and oversampled width (r + oversample). */
+#define ENMF_MAX_RANK 64
+#define ENMF_MAX_WIDTH 80
+
+typedef struct enmf_ctx enmf_ctx;
+
+/* Data matrix X (eq. 1).  data: device pointer to m rows of ld elements of
+ * the given dtype; only the first n of each row are read.  X >= 0. */
+typedef struct {
+  const void* data;
+  int64_t m, n, ld;
+  int32_t dtype;      /* enmf_dtype */
+  int32_t reserved;
+} enmf_matrix;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t enmf_version(void);
+
+/* Static text for a status code. */
+const char* enmf_status_string(int32_t status);
+
+/* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
+ * NULL = the default stream).  Returns ENMF_EDEVICE when no usable device
+ * exists.  *out is set to NULL on failure. */
+enmf_status enmf_create(enmf_ctx** out, int32_t device, void* hip_stream);
+
+/* Free the context and its workspace (synchronises its stream first). */
+void enmf_destroy(enmf_ctx* ctx);
+
+/* Message for the last failed call on this context (never NULL). */
+const char* enmf_last_error(const enmf_ctx* ctx);
+
+/* Change the stream later calls enqueue on. */
+enmf_status enmf_set_stream(enmf_ctx* ctx, void* hip_stream);
+
+/* Block until the context's stream is idle. */
+enmf_status enmf_synchronize(enmf_ctx* ctx);
+
+/* Round X (float32, m x n, leading dimension ld_in) to BF16 or FP16 storage
+ * with round-to-nearest-even, writing m rows of ld_out elements (ld_out >= n)
+ * to `out`.  This produces the reduced-storage form of X that every call
+ * below accepts. */
+enmf_status enmf_convert(enmf_ctx* ctx, const float* x32, int64_t m, int64_t n, int64_t ld_in,
+                         int32_t to_dtype, void* out, int64_t ld_out);
+
+/* ---- streaming products (appendix on complexity: the O(mnr) core kernel) ----
+ * enmf_xv:  P = X B, B is n x k (leading dimension k), P is m x k.
+ * enmf_xtu: Q = X^T A, A is m x k (leading dimension k), Q is n x k.
+ * X is streamed once; products accumulate in float32 whatever X's storage.
+ * 1 <= k <= ENMF_MAX_WIDTH. */
+enmf_status enmf_xv(enmf_ctx* ctx, const enmf_matrix* X, const float* B, int32_t k, float* P);
+enmf_status enmf_xtu(enmf_ctx* ctx, const enmf_matrix* X, const float* A, int32_t k, float* Q);
+
+/* Gram matrix G = A^T A (k x k, float64, row-major) of the float32 rows x k
+ * matrix A, accumulated in float64 (the r x r Grams V^T V, U^T U). */
+enmf_status enmf_gram(enmf_ctx* ctx, const float* A, int64_t rows, int32_t k, double* G);
+
+/* ---- block (i): truncated SVD (section 3; randomized variant, remark after Algorithm 3) ----
+ * Randomized range finder with Gaussian test matrix omega (n x (r+oversample),
+ * float32, leading dimension r+oversample, device, required) and power_iters
+ * re-orthonormalised power iterations, then the SVD of the small projected
+ * matrix.  Output: balanced factors U* = U Sigma^(1/2) (m x r) and
+ * V* = V Sigma^(1/2) (n x r) in float32, each column pair signed so that the
+ * column sum of U is positive; sigma_host (r values, descending) and
+ * relerr_svd_host = sqrt(||X||^2 - sum sigma^2)/||X|| (either may be NULL).
+ * Orthonormalisation and the small eigenproblem run in float64 on the GPU.
+ * Requires 1 <= r <= min(m, n, ENMF_MAX_RANK) and r + oversample <= ENMF_MAX_WIDTH. */
+typedef struct {
+  const float* omega;
+  int32_t oversample;    /* p, default 10 */
+  int32_t power_iters;   /* q, default 2 */
+} enmf_svd_opts;
+
+enmf_status enmf_svd_init(enmf_ctx* ctx, const enmf_matrix* X, int32_t r, const enmf_svd_opts* opts,
+                          float* U, float* V, double* sigma_host, double* relerr_svd_host);
+
+/* ---- block (ii): rotation (section 3.1, Algorithm 1, eq. 7, Procrustes step) ----
+ * ADMM on min_R sum h(W R) s.t. R^T R = I with W = [U; V], h(q) = max(0, -q).
+ * rho = rho0 * sqrt((m+n) r) / ||W||_F, R0 = I, Y0 = 0.  Stops when
+ * ||R_{k+1} - R_k||_F <= tol (tested every check_every steps) or after
+ * max_iter steps; tol = 0 runs exactly max_iter steps.  U and V (float32,
+ * in place) are replaced by U R and V R with the last R.  All ADMM state is
+ * float64.  R_host (r x r, may be NULL), steps_host, neg_mass_*_host (the
+ * rotation objective sum h before and after; may be NULL). */
+typedef struct {
+  double rho0;          /* default 1.0 */
+  double tol;           /* default 1e-10 */
+  int32_t max_iter;     /* default 100 */
+  int32_t check_every;  /* default 10 */
+} enmf_rotate_opts;
+
+enmf_status enmf_rotate(enmf_ctx* ctx, int64_t m, int64_t n, int32_t r, float* U, float* V,
+                        const enmf_rotate_opts* opts, double* R_host, int32_t* steps_host,
+                        double* neg_mass_before_host, double* neg_mass_after_host);
+
+/* ---- blocks (iii)-(iv): exterior phase and HALS (sections 3.2-3.3, Algorithms 2-3) ----
+ * One iteration = U half then V half (the V half uses the new U, eq. t_i).
+ * Phase per iteration: EXT while U or V has a negative entry (push negatives
+ * by step_u / step_v, eq. negup; mask of nonnegative entries; PBCD sweeps with
+ * the optimal row step, eqs. pbcdu and d_i), else HALS (one Gauss-Seidel
+ * sweep over columns per half).  The state after k iterations is checked when
+ * k is a multiple of check_every and at k = max_iter; the run stops early when
+ * U, V >= 0 and (kkt <= kkt_tol or relerr - relerr_svd <= relerr_tol).
+ * U and V (float32) are updated in place.  trace_dev (optional, device,
+ * trace_cap records of ENMF_TRACE_FIELDS float64) receives one record per check. */
+typedef struct {
+  double step_u, step_v;   /* push sizes; <= 0: max(-min, 0)/(ext_iters - 0.5) of the input */
+  double pbcd_eps;         /* PBCD stop: ||M o grad|| < eps ||M o grad_init||; 0 = fixed count */
+  double relerr_tol;       /* < 0: off */
+  double kkt_tol;          /* < 0: off */
+  double relerr_svd;       /* Eckart-Young floor from enmf_svd_init (for relerr_tol and re_paper) */
+  int32_t ext_iters;       /* default 10 */
+  int32_t pbcd_max_iter;   /* default 5 */
+  int32_t max_iter;        /* outer iterations */
+  int32_t check_every;     /* default 1 */
+  int32_t mode;            /* 0 full eNMF; 1 project to the orthant then HALS; 3 stop once feasible */
+  int32_t reserved;
+} enmf_iter_opts;
+
+typedef struct {
+  int32_t iters, ext_iters_done, phase, converged;
+  double step_u, step_v;    /* resolved push sizes (pass them back to resume identically) */
+  double f, relerr, re_paper, kkt, kkt_feas, kkt_pg_u, kkt_pg_v, delta_w, sigma_w;
+} enmf_iter_report;
+
+/* Trace record: k, f (expanded form), relerr, kkt, min(U,V), phase, device time (ns), negatives. */
+#define ENMF_TRACE_FIELDS 8
+
+enmf_status enmf_iterate(enmf_ctx* ctx, const enmf_matrix* X, int32_t r, float* U, float* V,
+                         const enmf_iter_opts* opts, enmf_iter_report* report_host,
+                         double* trace_dev, int32_t trace_cap);
+
+/* ---- KKT check (appendix, eq. kkt-nmf; (delta_W, sigma_W) of the KKT table) ----
+ * f = 1/2 ||X - U V^T||^2 summed directly in float64; relerr = sqrt(2f)/||X||;
+ * re_paper = relerr / relerr_svd (NaN when relerr_svd <= 0); gradients
+ * grad_U = U V^T V - X V, grad_V = V U^T U - X^T U; projected gradient (grad
+ * where W > 0, min(grad, 0) where W <= 0); kkt_pg_u = ||pg_U||/(||X|| ||V||),
+ * kkt_pg_v = ||pg_V||/(||X|| ||U||), kkt_feas = max ||min(W,0)||/||W||,
+ * kkt = max of the three; delta_w = max(grad o W), sigma_w = sum(grad o W). */
+typedef struct {
+  double f, relerr, re_paper, kkt, kkt_feas, kkt_pg_u, kkt_pg_v;
+  double delta_w, sigma_w, sigma_u, sigma_v, min_w;
+} enmf_kkt;
+
+enmf_status enmf_objective_kkt(enmf_ctx* ctx, const enmf_matrix* X, int32_t r, const float* U,
+                               const float* V, double relerr_svd, enmf_kkt* out_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ENMF_H */

@@ -1,0 +1,641 @@
+// Host side of libenmf: argument validation, context-owned device workspace
+// and the launch sequences of the entry points declared in include/enmf.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "enmf_internal.h"
+
+using namespace enmf;
+
+namespace {
+
+enum Slot {
+  S_BP, S_AP, S_SPLIT, S_P, S_Q, S_GPART, S_G, S_H, S_RUPART, S_CHK, S_XPART, S_STAT, S_UD, S_RES,
+  S_Y, S_QM64, S_QM32, S_Z, S_QN64, S_QN32, S_TMP64, S_T, S_C, S_COLP, S_COLS, S_SIG, S_TU, S_TV,
+  S_W64, S_YA, S_ZA, S_BA, S_R, S_NEGP, S_WSQ, S_MPART, N_SLOTS
+};
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct enmf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  Buf bufs[N_SLOTS];
+  DevState* st = nullptr;
+  double ns_per_tick = 10.0;
+};
+
+namespace {
+
+enmf_status fail(enmf_ctx* c, enmf_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+void* ws(enmf_ctx* c, int slot, size_t bytes) {
+  Buf& b = c->bufs[slot];
+  if (bytes < 256) bytes = 256;
+  if (b.bytes >= bytes) return b.p;
+  if (b.p) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  const size_t want = bytes + bytes / 8;
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return nullptr;
+  }
+  b.bytes = want;
+  return b.p;
+}
+
+#define CK(expr)                                                                          \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(c, ENMF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+#define WS(var, type, slot, bytes)                                                          \
+  type* var = reinterpret_cast<type*>(ws(c, slot, (size_t)(bytes)));                       \
+  if (!var) return fail(c, ENMF_ENOMEM, "device workspace allocation failed (" #var ")")
+
+#define TRY(expr)                          \
+  do {                                     \
+    enmf_status s_ = (expr);               \
+    if (s_ != ENMF_OK) return s_;          \
+  } while (0)
+
+int64_t esize(int dtype) { return dtype == ENMF_F32 ? 4 : 2; }
+
+enmf_status check_ctx(enmf_ctx* c) {
+  if (!c) return ENMF_EINVAL;
+  c->err.clear();
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, ENMF_EDEVICE, "hipSetDevice failed");
+  return ENMF_OK;
+}
+
+enmf_status check_matrix(enmf_ctx* c, const enmf_matrix* X) {
+  if (!X || !X->data) return fail(c, ENMF_EINVAL, "X is null");
+  if (X->m < 1 || X->n < 1) return fail(c, ENMF_EINVAL, "X must have m >= 1 and n >= 1");
+  if (X->ld < X->n) return fail(c, ENMF_EINVAL, "X leading dimension must be >= n");
+  if (X->dtype != ENMF_F32 && X->dtype != ENMF_BF16 && X->dtype != ENMF_F16)
+    return fail(c, ENMF_EINVAL, "unsupported X dtype");
+  if (reinterpret_cast<uintptr_t>(X->data) % esize(X->dtype) != 0)
+    return fail(c, ENMF_EINVAL, "X data must be aligned to its element size");
+  return ENMF_OK;
+}
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// P = X B (B: n x k, ld k).
+enmf_status do_xv(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, float* P) {
+  const int kp = pad_width(k);
+  const int64_t rows_pad = round_up(X->n, xv_tile_width(X->dtype));
+  WS(Bp, float, S_BP, rows_pad * kp * 4);
+  CK(launch_pad_rows_cols(B, X->n, k, kp, rows_pad, Bp, c->stream));
+  const int splits = xv_splits(X->m, X->n, X->dtype);
+  float* part = nullptr;
+  if (splits > 1) {
+    WS(pp, float, S_SPLIT, (int64_t)splits * X->m * k * 4);
+    part = pp;
+  }
+  CK(launch_xv(X->data, X->dtype, X->m, X->n, X->ld, Bp, k, kp, splits, part, P, c->stream));
+  return ENMF_OK;
+}
+
+// Q = X^T A (A: m x k, ld k).
+enmf_status do_xtu(enmf_ctx* c, const enmf_matrix* X, const float* A, int k, float* Q) {
+  const int kp = pad_width(k);
+  WS(Ap, float, S_AP, X->m * kp * 4);
+  CK(launch_pad_cols(A, X->m, k, kp, Ap, c->stream));
+  const int splits = xtu_splits(X->m, X->n);
+  float* part = nullptr;
+  if (splits > 1) {
+    WS(pp, float, S_SPLIT, (int64_t)splits * X->n * k * 4);
+    part = pp;
+  }
+  CK(launch_xtu(X->data, X->dtype, X->m, X->n, X->ld, Ap, k, kp, splits, part, Q, c->stream));
+  return ENMF_OK;
+}
+
+// out (kp x kp, zero padded) = A^T A for A (rows x k float32 or float64, ld lda).
+enmf_status do_gram(enmf_ctx* c, const void* A, int a_f64, int64_t lda, int64_t rows, int k, int kp,
+                    double* out) {
+  const int nb = gram_blocks(rows);
+  WS(part, double, S_GPART, (int64_t)nb * k * k * 8);
+  CK(launch_tsgram(A, a_f64, lda, A, a_f64, lda, rows, k, k, part, 0, nb, c->stream));
+  CK(launch_gram_finalize(part, nb, k, k, kp, out, c->stream));
+  return ENMF_OK;
+}
+
+// Orthonormal basis of the columns of A32 (N x k float32), written to out64
+// and out32 (N x k).  Two passes of Q = A E diag(lambda^-1/2) with the
+// eigenpairs of A^T A; directions with lambda <= tau lambda_max become zero
+// columns.
+enmf_status do_orth(enmf_ctx* c, const float* A32, int64_t N, int k, double* out64, float* out32) {
+  const double tau = 1e-15;
+  WS(G, double, S_C, k * k * 8);
+  WS(T, double, S_T, k * k * 8);
+  WS(tmp, double, S_TMP64, N * k * 8);
+  TRY(do_gram(c, A32, 0, k, N, k, k, G));
+  CK(launch_orth_factor(G, k, tau, T, c->stream));
+  CK(launch_apply_small(A32, 0, k, N, k, T, k, k, tmp, 1, k, c->stream));
+  TRY(do_gram(c, tmp, 1, k, N, k, k, G));
+  CK(launch_orth_factor(G, k, tau, T, c->stream));
+  CK(launch_apply_small(tmp, 1, k, N, k, T, k, k, out64, 1, k, c->stream));
+  CK(launch_apply_small(tmp, 1, k, N, k, T, k, k, out32, 0, k, c->stream));
+  return ENMF_OK;
+}
+
+// Direct residual f = 1/2 ||X - U V^T||^2 (float64), synchronising.
+enmf_status direct_objective(enmf_ctx* c, const enmf_matrix* X, int r, const float* U,
+                             const float* V, double* f) {
+  hipStream_t s = c->stream;
+  const int kp = pad_width(r);
+  WS(Ud, double, S_UD, X->m * kp * 8);
+  CK(launch_pad_cols_f64(U, X->m, r, kp, Ud, s));
+  const int64_t cb = (X->n + 255) / 256;
+  WS(res, double, S_RES, (cb * 2048 + 4096) * 8);
+  WS(o, double, S_SIG, 64 * 8);
+  int np = 0;
+  CK(launch_residual(X->data, X->dtype, X->m, X->n, X->ld, Ud, V, r, res, &np, s));
+  CK(launch_sum_parts(res, np, 1, 1, o, s));
+  double v = 0.0;
+  CK(hipMemcpyAsync(&v, o, 8, hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  *f = 0.5 * v;
+  return ENMF_OK;
+}
+
+enmf_status read_sumsq_x(enmf_ctx* c, const enmf_matrix* X, double* nx2) {
+  WS(xp, double, S_XPART, 1024 * 8);
+  WS(o, double, S_SIG, 64 * 8);
+  int nx = 0;
+  CK(launch_sumsq_x(X->data, X->dtype, X->m, X->n, X->ld, xp, &nx, c->stream));
+  CK(launch_sum_parts(xp, nx, 1, 1, o, c->stream));
+  CK(hipMemcpyAsync(nx2, o, 8, hipMemcpyDeviceToHost, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  return ENMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t enmf_version(void) { return 100; }
+
+const char* enmf_status_string(int32_t s) {
+  switch (s) {
+    case ENMF_OK: return "ok";
+    case ENMF_EINVAL: return "invalid argument";
+    case ENMF_ENOMEM: return "out of device memory";
+    case ENMF_EDEVICE: return "device error";
+    case ENMF_ENUMERIC: return "non-finite objective";
+    case ENMF_EBUSY: return "busy";
+    case ENMF_ECLOSED: return "closed";
+    default: return "unknown status";
+  }
+}
+
+enmf_status enmf_create(enmf_ctx** out, int32_t device, void* hip_stream) {
+  if (!out) return ENMF_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+    (void)hipGetLastError();
+    return ENMF_EDEVICE;
+  }
+  if (device < 0 || device >= count) return ENMF_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return ENMF_EDEVICE;
+  enmf_ctx* c = new enmf_ctx();
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipMalloc(&c->st, sizeof(DevState)) != hipSuccess) {
+    delete c;
+    return ENMF_ENOMEM;
+  }
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+    c->ns_per_tick = 1e6 / (double)khz;
+  *out = c;
+  return ENMF_OK;
+}
+
+void enmf_destroy(enmf_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& b : c->bufs)
+    if (b.p) (void)hipFree(b.p);
+  if (c->st) (void)hipFree(c->st);
+  delete c;
+}
+
+const char* enmf_last_error(const enmf_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+enmf_status enmf_set_stream(enmf_ctx* c, void* hip_stream) {
+  if (!c) return ENMF_EINVAL;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return ENMF_OK;
+}
+
+enmf_status enmf_synchronize(enmf_ctx* c) {
+  TRY(check_ctx(c));
+  CK(hipStreamSynchronize(c->stream));
+  return ENMF_OK;
+}
+
+enmf_status enmf_convert(enmf_ctx* c, const float* x32, int64_t m, int64_t n, int64_t ld_in,
+                         int32_t to, void* out, int64_t ld_out) {
+  TRY(check_ctx(c));
+  if (!x32 || !out) return fail(c, ENMF_EINVAL, "null pointer");
+  if (m < 1 || n < 1 || ld_in < n || ld_out < n) return fail(c, ENMF_EINVAL, "bad shape");
+  if (to != ENMF_BF16 && to != ENMF_F16) return fail(c, ENMF_EINVAL, "target dtype must be BF16 or F16");
+  CK(launch_convert(x32, m, n, ld_in, to, out, ld_out, c->stream));
+  return ENMF_OK;
+}
+
+enmf_status enmf_xv(enmf_ctx* c, const enmf_matrix* X, const float* B, int32_t k, float* P) {
+  TRY(check_ctx(c));
+  TRY(check_matrix(c, X));
+  if (!B || !P) return fail(c, ENMF_EINVAL, "null pointer");
+  if (k < 1 || k > ENMF_MAX_WIDTH) return fail(c, ENMF_EINVAL, "k out of range");
+  return do_xv(c, X, B, k, P);
+}
+
+enmf_status enmf_xtu(enmf_ctx* c, const enmf_matrix* X, const float* A, int32_t k, float* Q) {
+  TRY(check_ctx(c));
+  TRY(check_matrix(c, X));
+  if (!A || !Q) return fail(c, ENMF_EINVAL, "null pointer");
+  if (k < 1 || k > ENMF_MAX_WIDTH) return fail(c, ENMF_EINVAL, "k out of range");
+  return do_xtu(c, X, A, k, Q);
+}
+
+enmf_status enmf_gram(enmf_ctx* c, const float* A, int64_t rows, int32_t k, double* G) {
+  TRY(check_ctx(c));
+  if (!A || !G) return fail(c, ENMF_EINVAL, "null pointer");
+  if (rows < 1 || k < 1 || k > ENMF_MAX_WIDTH) return fail(c, ENMF_EINVAL, "bad shape");
+  return do_gram(c, A, 0, k, rows, k, k, G);
+}
+
+enmf_status enmf_svd_init(enmf_ctx* c, const enmf_matrix* X, int32_t r, const enmf_svd_opts* o,
+                          float* U, float* V, double* sigma_host, double* relerr_host) {
+  TRY(check_ctx(c));
+  TRY(check_matrix(c, X));
+  if (!o || !o->omega) return fail(c, ENMF_EINVAL, "svd opts with a device omega are required");
+  if (!U || !V) return fail(c, ENMF_EINVAL, "null output pointer");
+  const int64_t m = X->m, n = X->n;
+  if (r < 1 || r > ENMF_MAX_RANK || r > m || r > n) return fail(c, ENMF_EINVAL, "r out of range");
+  if (o->oversample < 0 || o->power_iters < 0) return fail(c, ENMF_EINVAL, "bad svd opts");
+  const int k = r + o->oversample;
+  if (k > ENMF_MAX_WIDTH) return fail(c, ENMF_EINVAL, "r + oversample exceeds ENMF_MAX_WIDTH");
+  hipStream_t s = c->stream;
+
+  WS(Y, float, S_Y, m * k * 4);
+  WS(Qm64, double, S_QM64, m * k * 8);
+  WS(Qm32, float, S_QM32, m * k * 4);
+  WS(Z, float, S_Z, n * k * 4);
+  WS(Qn64, double, S_QN64, n * k * 8);
+  WS(Qn32, float, S_QN32, n * k * 4);
+
+  TRY(do_xv(c, X, o->omega, k, Y));
+  for (int it = 0; it < o->power_iters; ++it) {
+    TRY(do_orth(c, Y, m, k, Qm64, Qm32));
+    TRY(do_xtu(c, X, Qm32, k, Z));
+    TRY(do_orth(c, Z, n, k, Qn64, Qn32));
+    TRY(do_xv(c, X, Qn32, k, Y));
+  }
+  TRY(do_orth(c, Y, m, k, Qm64, Qm32));
+  TRY(do_xtu(c, X, Qm32, k, Z));
+  WS(C, double, S_C, k * k * 8);
+  TRY(do_gram(c, Z, 0, k, n, k, k, C));
+  WS(colp, double, S_COLP, 256 * k * 8);
+  WS(cols, double, S_COLS, k * 8);
+  int ncp = 0;
+  CK(launch_colsum(Qm64, k, m, k, colp, &ncp, s));
+  CK(launch_sum_parts(colp, ncp, k, k, cols, s));
+  WS(sig, double, S_SIG, 64 * 8);
+  WS(TU, double, S_TU, k * r * 8);
+  WS(TV, double, S_TV, k * r * 8);
+  CK(launch_svd_factor(C, cols, k, r, sig, TU, TV, s));
+  CK(launch_apply_small(Qm64, 1, k, m, k, TU, r, r, U, 0, r, s));
+  CK(launch_apply_small(Z, 0, k, n, k, TV, r, r, V, 0, r, s));
+
+  std::vector<double> sg(r);
+  CK(hipMemcpyAsync(sg.data(), sig, r * 8, hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  if (sigma_host) std::memcpy(sigma_host, sg.data(), r * 8);
+  if (relerr_host) {
+    // Eckart-Young floor evaluated directly as ||X - U* V*^T|| / ||X|| in
+    // float64: sqrt(||X||^2 - sum sigma^2) cancels catastrophically.
+    double nx2 = 0.0, f = 0.0;
+    TRY(read_sumsq_x(c, X, &nx2));
+    TRY(direct_objective(c, X, r, U, V, &f));
+    *relerr_host = nx2 > 0.0 ? std::sqrt(2.0 * f / nx2) : 0.0;
+  }
+  return ENMF_OK;
+}
+
+enmf_status enmf_rotate(enmf_ctx* c, int64_t m, int64_t n, int32_t r, float* U, float* V,
+                        const enmf_rotate_opts* o, double* R_host, int32_t* steps_host,
+                        double* neg_before_host, double* neg_after_host) {
+  TRY(check_ctx(c));
+  if (!U || !V) return fail(c, ENMF_EINVAL, "null pointer");
+  if (m < 1 || n < 1 || r < 1 || r > ENMF_MAX_RANK) return fail(c, ENMF_EINVAL, "bad shape");
+  enmf_rotate_opts d{1.0, 1e-10, 100, 10};
+  if (o) d = *o;
+  if (d.rho0 <= 0.0 || d.max_iter < 0 || d.tol < 0.0) return fail(c, ENMF_EINVAL, "bad rotate opts");
+  if (d.check_every < 1) d.check_every = 1;
+  hipStream_t s = c->stream;
+  const int64_t N = m + n;
+  const int kp = pad_width(r);
+  WS(W, double, S_W64, N * kp * 8);
+  WS(Ya, double, S_YA, N * kp * 8);
+  WS(Za, double, S_ZA, N * kp * 8);
+  WS(Ba, double, S_BA, N * kp * 8);
+  WS(R, double, S_R, kp * kp * 8);
+  const int nbr = (int)((N + 255) / 256);
+  WS(negp, double, S_NEGP, nbr * 8);
+  WS(wsq, double, S_WSQ, 512 * 8);
+  const int nbm = gram_blocks(N);
+  WS(mpart, double, S_MPART, (int64_t)nbm * r * r * 8);
+  WS(stat, double, S_STAT, 4 * 512 * 8);
+  WS(tot, double, S_SIG, 64 * 8);
+
+  // rotation objective before: sum h(W)
+  const int fbU = factor_blocks(m * r), fbV = factor_blocks(n * r);
+  CK(launch_factor_stats(U, m * r, r, stat, 0, fbU, s));
+  CK(launch_factor_stats(V, n * r, r, stat, fbU, fbV, s));
+  CK(launch_sum_parts(stat, fbU + fbV, 4, 4, tot, s));
+  double before[4];
+  CK(hipMemcpyAsync(before, tot, 32, hipMemcpyDeviceToHost, s));
+
+  CK(launch_pack_w(U, m, V, n, r, kp, W, s));
+  int nw = 0;
+  CK(launch_w_sumsq(W, N * kp, wsq, &nw, s));
+  CK(launch_rho_init(wsq, nw, N, r, d.rho0, c->st, s));
+  std::vector<double> eye(kp * kp, 0.0);
+  for (int i = 0; i < r; ++i) eye[i * kp + i] = 1.0;
+  CK(hipMemcpyAsync(R, eye.data(), kp * kp * 8, hipMemcpyHostToDevice, s));
+  CK(hipStreamSynchronize(s));
+
+  int steps = 0;
+  for (int t = 0; t < d.max_iter; ++t) {
+    CK(launch_admm_rows(W, N, r, kp, R, Ya, Za, Ba, c->st, t, negp, s));
+    CK(launch_tsgram(W, 1, kp, Ba, 1, kp, N, r, r, mpart, 0, nbm, s));
+    CK(launch_polar(mpart, nbm, r, kp, R, c->st, s));
+    steps = t + 1;
+    if (d.tol > 0.0 && (steps % d.check_every == 0)) {
+      double dR = 0.0;
+      CK(hipMemcpyAsync(&dR, &c->st->dR, 8, hipMemcpyDeviceToHost, s));
+      CK(hipStreamSynchronize(s));
+      if (dR <= d.tol) break;
+    }
+  }
+  CK(launch_apply_small(W, 1, kp, m, r, R, kp, r, U, 0, r, s));
+  CK(launch_apply_small(W + m * kp, 1, kp, n, r, R, kp, r, V, 0, r, s));
+  CK(launch_factor_stats(U, m * r, r, stat, 0, fbU, s));
+  CK(launch_factor_stats(V, n * r, r, stat, fbU, fbV, s));
+  CK(launch_sum_parts(stat, fbU + fbV, 4, 4, tot, s));
+  double after[4];
+  CK(hipMemcpyAsync(after, tot, 32, hipMemcpyDeviceToHost, s));
+  std::vector<double> Rh(kp * kp);
+  CK(hipMemcpyAsync(Rh.data(), R, kp * kp * 8, hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  if (R_host)
+    for (int a = 0; a < r; ++a)
+      for (int b = 0; b < r; ++b) R_host[a * r + b] = Rh[a * kp + b];
+  if (steps_host) *steps_host = steps;
+  if (neg_before_host) *neg_before_host = before[3];
+  if (neg_after_host) *neg_after_host = after[3];
+  return ENMF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct IterBufs {
+  float *P, *Q;
+  double *G, *H, *rupart, *chk, *stat, *xpart;
+  int nbU, nbV, fbU, fbV;
+};
+
+// Prepares DevState and the buffers shared by enmf_iterate and enmf_objective_kkt.
+enmf_status iter_setup(enmf_ctx* c, const enmf_matrix* X, int r, const float* U, const float* V,
+                       const enmf_iter_opts& o, IterBufs& b) {
+  hipStream_t s = c->stream;
+  const int64_t m = X->m, n = X->n;
+  const int kp = pad_width(r);
+  WS(P, float, S_P, m * r * 4);
+  WS(Q, float, S_Q, n * r * 4);
+  WS(G, double, S_G, kp * kp * 8);
+  WS(H, double, S_H, kp * kp * 8);
+  b.P = P; b.Q = Q; b.G = G; b.H = H;
+  b.nbU = rowupdate_blocks(m);
+  b.nbV = rowupdate_blocks(n);
+  WS(rup, double, S_RUPART, 3 * (int64_t)(b.nbU + b.nbV) * 8);
+  WS(chk, double, S_CHK, (int64_t)kCheckFields * (b.nbU + b.nbV) * 8);
+  b.rupart = rup; b.chk = chk;
+  b.fbU = factor_blocks(m * r);
+  b.fbV = factor_blocks(n * r);
+  WS(stat, double, S_STAT, 4 * (int64_t)(b.fbU + b.fbV + 512) * 8);
+  WS(xp, double, S_XPART, 1024 * 8);
+  b.stat = stat; b.xpart = xp;
+  // pre-size the shared split buffers so the loop never reallocates
+  const int kpw = pad_width(r);
+  const int64_t rows_pad = round_up(n, xv_tile_width(X->dtype));
+  if (!ws(c, S_BP, rows_pad * kpw * 4) || !ws(c, S_AP, m * kpw * 4))
+    return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
+  const int64_t sx = (int64_t)xv_splits(m, n, X->dtype) * m * r * 4;
+  const int64_t su = (int64_t)xtu_splits(m, n) * n * r * 4;
+  if (!ws(c, S_SPLIT, sx > su ? sx : su)) return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
+  if (!ws(c, S_GPART, (int64_t)gram_blocks(m > n ? m : n) * r * r * 8))
+    return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
+
+  DevState h;
+  std::memset(&h, 0, sizeof(h));
+  h.pbcd_eps = o.pbcd_eps;
+  h.kkt_tol = o.kkt_tol;
+  h.relerr_tol = o.relerr_tol;
+  h.relerr_svd = o.relerr_svd;
+  h.ns_per_tick = c->ns_per_tick;
+  h.mode = o.mode;
+  CK(hipMemcpyAsync(c->st, &h, sizeof(h), hipMemcpyHostToDevice, s));
+  CK(hipStreamSynchronize(s));
+  int nx = 0;
+  CK(launch_sumsq_x(X->data, X->dtype, m, n, X->ld, xp, &nx, s));
+  CK(launch_factor_stats(U, m * r, r, stat, 0, b.fbU, s));
+  CK(launch_factor_stats(V, n * r, r, stat, b.fbU, b.fbV, s));
+  CK(launch_setup_state2(stat, b.fbU, b.fbV, xp, nx, o.step_u, o.step_v, o.ext_iters, c->st, rup,
+                         b.nbU + b.nbV, s));
+  return ENMF_OK;
+}
+
+enmf_status set_trace_cap(enmf_ctx* c, int cap) {
+  CK(hipMemcpyAsync(&c->st->trace_cap, &cap, 4, hipMemcpyHostToDevice, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  return ENMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U, float* V,
+                         const enmf_iter_opts* opts, enmf_iter_report* rep, double* trace,
+                         int32_t trace_cap) {
+  TRY(check_ctx(c));
+  TRY(check_matrix(c, X));
+  if (!U || !V || !opts) return fail(c, ENMF_EINVAL, "null pointer");
+  const int64_t m = X->m, n = X->n;
+  if (r < 1 || r > ENMF_MAX_RANK || r > m || r > n) return fail(c, ENMF_EINVAL, "r out of range");
+  enmf_iter_opts o = *opts;
+  if (o.max_iter < 0) return fail(c, ENMF_EINVAL, "max_iter must be >= 0");
+  if (o.ext_iters < 1) o.ext_iters = 10;
+  if (o.pbcd_max_iter < 1) o.pbcd_max_iter = 5;
+  if (o.check_every < 1) o.check_every = 1;
+  if (o.pbcd_eps < 0.0) return fail(c, ENMF_EINVAL, "pbcd_eps must be >= 0");
+  if (o.mode != 0 && o.mode != 1 && o.mode != 3) return fail(c, ENMF_EINVAL, "unsupported mode");
+  if (trace && trace_cap < 0) return fail(c, ENMF_EINVAL, "bad trace capacity");
+  hipStream_t s = c->stream;
+  const int kp = pad_width(r);
+  if (o.mode == 1) {
+    CK(launch_clip(U, m * r, s));
+    CK(launch_clip(V, n * r, s));
+  }
+  IterBufs b;
+  TRY(iter_setup(c, X, r, U, V, o, b));
+  TRY(set_trace_cap(c, trace ? trace_cap : 0));
+  DevState* st = c->st;
+  double* rupU = b.rupart;
+  double* rupV = b.rupart + 3 * b.nbU;
+  const bool fixed = o.pbcd_eps == 0.0;
+
+  TRY(do_gram(c, U, 0, r, m, r, kp, b.H));
+  TRY(do_xtu(c, X, U, r, b.Q));
+  for (int k = 0; k <= o.max_iter; ++k) {
+    TRY(do_gram(c, V, 0, r, n, r, kp, b.G));
+    TRY(do_xv(c, X, V, r, b.P));
+    if (k % o.check_every == 0 || k == o.max_iter) {
+      int nbU = 0, nbV = 0;
+      CK(launch_check(U, m, b.P, b.G, V, n, b.Q, b.H, r, kp, b.chk, &nbU, &nbV, st, s));
+      CK(launch_check_finalize(b.chk, nbU, nbV, b.G, b.H, kp, k, k == o.max_iter, st, trace, s));
+    }
+    if (k == o.max_iter) break;
+    CK(launch_head(b.rupart, b.nbU + b.nbV, st, s));
+    if (fixed) {
+      CK(launch_rowupdate(U, m, r, kp, b.P, b.G, st, 0, o.pbcd_max_iter, 1, 0, rupU, s));
+    } else {
+      for (int t = 0; t < o.pbcd_max_iter; ++t) {
+        CK(launch_rowupdate(U, m, r, kp, b.P, b.G, st, 0, 1, t == 0, 1, rupU, s));
+        CK(launch_pbcd_decide(rupU, b.nbU, 0, t == 0, st, s));
+      }
+    }
+    TRY(do_gram(c, U, 0, r, m, r, kp, b.H));
+    TRY(do_xtu(c, X, U, r, b.Q));
+    if (fixed) {
+      CK(launch_rowupdate(V, n, r, kp, b.Q, b.H, st, 1, o.pbcd_max_iter, 1, 0, rupV, s));
+    } else {
+      for (int t = 0; t < o.pbcd_max_iter; ++t) {
+        CK(launch_rowupdate(V, n, r, kp, b.Q, b.H, st, 1, 1, t == 0, 1, rupV, s));
+        CK(launch_pbcd_decide(rupV, b.nbV, 1, t == 0, st, s));
+      }
+    }
+    CK(launch_tail(st, s));
+    if ((k + 1) % 32 == 0) {
+      int32_t stop = 0;
+      CK(hipMemcpyAsync(&stop, &st->stop, 4, hipMemcpyDeviceToHost, s));
+      CK(hipStreamSynchronize(s));
+      if (stop) break;
+    }
+  }
+  DevState h;
+  CK(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->iters = h.iters;
+    rep->ext_iters_done = h.ext_done;
+    rep->phase = h.negs > 0 ? kPhaseExt : kPhaseHals;
+    rep->converged = h.converged;
+    rep->step_u = h.step[0];
+    rep->step_v = h.step[1];
+    double f = 0.0;
+    TRY(direct_objective(c, X, r, U, V, &f));
+    rep->f = f;
+    rep->relerr = h.nx2 > 0.0 ? std::sqrt(2.0 * f / h.nx2) : 0.0;
+    rep->re_paper = o.relerr_svd > 0.0 ? rep->relerr / o.relerr_svd : NAN;
+    rep->kkt = h.kkt;
+    rep->kkt_feas = h.kkt_feas;
+    rep->kkt_pg_u = h.kkt_pg_u;
+    rep->kkt_pg_v = h.kkt_pg_v;
+    rep->delta_w = h.delta_w;
+    rep->sigma_w = h.sigma_w;
+  }
+  if (h.numeric_error) return fail(c, ENMF_ENUMERIC, "non-finite objective or KKT residual");
+  return ENMF_OK;
+}
+
+enmf_status enmf_objective_kkt(enmf_ctx* c, const enmf_matrix* X, int32_t r, const float* U,
+                               const float* V, double relerr_svd, enmf_kkt* out) {
+  TRY(check_ctx(c));
+  TRY(check_matrix(c, X));
+  if (!U || !V || !out) return fail(c, ENMF_EINVAL, "null pointer");
+  const int64_t m = X->m, n = X->n;
+  if (r < 1 || r > ENMF_MAX_RANK || r > m || r > n) return fail(c, ENMF_EINVAL, "r out of range");
+  hipStream_t s = c->stream;
+  const int kp = pad_width(r);
+  enmf_iter_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.kkt_tol = -1.0;
+  o.relerr_tol = -1.0;
+  o.relerr_svd = relerr_svd;
+  o.ext_iters = 10;
+  IterBufs b;
+  TRY(iter_setup(c, X, r, U, V, o, b));
+  TRY(set_trace_cap(c, 0));
+  TRY(do_gram(c, U, 0, r, m, r, kp, b.H));
+  TRY(do_gram(c, V, 0, r, n, r, kp, b.G));
+  TRY(do_xv(c, X, V, r, b.P));
+  TRY(do_xtu(c, X, U, r, b.Q));
+  int nbU = 0, nbV = 0;
+  CK(launch_check(U, m, b.P, b.G, V, n, b.Q, b.H, r, kp, b.chk, &nbU, &nbV, c->st, s));
+  CK(launch_check_finalize(b.chk, nbU, nbV, b.G, b.H, kp, 0, 1, c->st, nullptr, s));
+  DevState h;
+  CK(hipMemcpyAsync(&h, c->st, sizeof(h), hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  double f = 0.0;
+  TRY(direct_objective(c, X, r, U, V, &f));
+  out->f = f;
+  out->relerr = h.nx2 > 0.0 ? std::sqrt(2.0 * f / h.nx2) : 0.0;
+  out->re_paper = relerr_svd > 0.0 ? out->relerr / relerr_svd : NAN;
+  out->kkt = h.kkt;
+  out->kkt_feas = h.kkt_feas;
+  out->kkt_pg_u = h.kkt_pg_u;
+  out->kkt_pg_v = h.kkt_pg_v;
+  out->delta_w = h.delta_w;
+  out->sigma_w = h.sigma_w;
+  out->sigma_u = h.sigma_u;
+  out->sigma_v = h.sigma_v;
+  out->min_w = h.min_w;
+  if (!std::isfinite(f)) return fail(c, ENMF_ENUMERIC, "non-finite objective");
+  return ENMF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Device helpers shared by the libenmf kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace enmf {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ float bf16_bits_to_f32(unsigned short h) {
+  return __uint_as_float(((unsigned)h) << 16);
+}
+
+__device__ __forceinline__ float f16_bits_to_f32(unsigned short h) {
+  _Float16 v;
+  __builtin_memcpy(&v, &h, 2);
+  return (float)v;
+}
+
+// Element type of X for storage code XT (0 float32, 1 bfloat16, 2 float16).
+template <int XT> struct XElem { using T = unsigned short; };
+template <> struct XElem<0> { using T = float; };
+
+template <int XT>
+__device__ __forceinline__ float to_f32(typename XElem<XT>::T v) {
+  if constexpr (XT == 0) return v;
+  else if constexpr (XT == 1) return bf16_bits_to_f32(v);
+  else return f16_bits_to_f32(v);
+}
+
+// Butterfly sum over the 64 lanes of a wave; every lane gets the same value
+// and the combination order does not depend on scheduling.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Fixed-order block reductions for blocks of NT threads (NT a multiple of 64).
+// `sh` must hold NT/64 doubles.  The result is valid in every thread.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x % kWave) == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / kWave; ++i) t += sh[i];
+  return t;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  v = wave_max(v);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x % kWave) == 0) sh[w] = v;
+  __syncthreads();
+  double t = sh[0];
+#pragma unroll
+  for (int i = 1; i < NT / kWave; ++i) t = fmax(t, sh[i]);
+  return t;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_min(double v, double* sh) {
+  v = wave_min(v);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x % kWave) == 0) sh[w] = v;
+  __syncthreads();
+  double t = sh[0];
+#pragma unroll
+  for (int i = 1; i < NT / kWave; ++i) t = fmin(t, sh[i]);
+  return t;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+}  // namespace enmf

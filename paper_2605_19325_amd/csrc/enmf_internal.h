@@ -1,0 +1,135 @@
+// Internal declarations shared by the host library and the HIP kernels of libenmf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "enmf.h"
+
+namespace enmf {
+
+// Device-resident scalars of one solve.  Written and read by kernels only;
+// the host copies it back once at the end of a call.
+struct DevState {
+  double nx2;            // ||X||_F^2
+  double step[2];        // push sizes for U (0) and V (1)
+  double rho;            // ADMM penalty
+  double dR;             // ||R_new - R_old||_F of the last ADMM step
+  double thr2[2];        // PBCD stop threshold eps^2 ||M o grad_init||^2, per half
+  double relerr_svd;
+  double ns_per_tick;    // device wall clock period
+  double f, relerr, kkt, kkt_feas, kkt_pg_u, kkt_pg_v;
+  double delta_w, sigma_w, sigma_u, sigma_v, min_w, re_paper;
+  double neg_mass;       // rotation objective of the last rotated point
+  double pbcd_eps;
+  double kkt_tol, relerr_tol;
+  int32_t phase;         // phase of the current iteration (0 EXT, 1 HALS)
+  int32_t stop;          // set once the run has stopped; every kernel then returns at once
+  int32_t converged;
+  int32_t iters;         // completed outer iterations
+  int32_t ext_done;
+  int32_t pbcd_done[2];
+  int32_t ntrace;
+  int32_t trace_cap;
+  int32_t mode;
+  int32_t numeric_error;
+  int32_t negs;          // negative entries in U and V at the last head
+  int32_t pad_[2];
+};
+
+// Number of float64 fields in one check-partial record.
+constexpr int kCheckFields = 12;
+constexpr int kTraceFields = ENMF_TRACE_FIELDS;
+
+constexpr int kPhaseExt = 0;
+constexpr int kPhaseHals = 1;
+
+// Padded widths the templated kernels are built for.
+inline int pad_width(int k) {
+  if (k <= 8) return 8;
+  if (k <= 16) return 16;
+  if (k <= 32) return 32;
+  if (k <= 48) return 48;
+  if (k <= 64) return 64;
+  return 80;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files).  All enqueue on `s`, return
+// hipSuccess or the launch error.
+// ---------------------------------------------------------------------------
+
+// k_stream.hip
+int64_t xv_tile_width(int xt);
+int xv_splits(int64_t m, int64_t n, int xt);
+int xtu_splits(int64_t m, int64_t n);
+hipError_t launch_pad_cols(const float* in, int64_t rows, int k, int kp, float* out, hipStream_t s);
+hipError_t launch_pad_rows_cols(const float* in, int64_t rows_in, int k, int kp, int64_t rows_out,
+                                float* out, hipStream_t s);
+hipError_t launch_pad_cols_f64(const float* in, int64_t rows, int k, int kp, double* out,
+                               hipStream_t s);
+hipError_t launch_xv(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* Bp, int k,
+                     int kp, int splits, float* part, float* out, hipStream_t s);
+hipError_t launch_xtu(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* Ap, int k,
+                      int kp, int splits, float* part, float* out, hipStream_t s);
+hipError_t launch_residual(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const double* Ud,
+                           const float* V, int r, double* part, int* nparts, hipStream_t s);
+hipError_t launch_sumsq_x(const void* X, int xt, int64_t m, int64_t n, int64_t ld, double* part,
+                          int* nparts, hipStream_t s);
+hipError_t launch_sum_parts(const double* part, int nparts, int stride, int nfields, double* out,
+                            hipStream_t s);
+hipError_t launch_convert(const float* x, int64_t m, int64_t n, int64_t ldi, int to, void* out,
+                          int64_t ldo, hipStream_t s);
+
+// k_small.hip
+int gram_blocks(int64_t rows);
+hipError_t launch_tsgram(const void* A, int a_is_f64, int64_t lda, const void* B, int b_is_f64,
+                         int64_t ldb, int64_t rows, int ka, int kb, double* part, int block_offset,
+                         int nblocks, hipStream_t s);
+hipError_t launch_gram_finalize(const double* part, int nparts, int ka, int kb, int kp, double* out,
+                                hipStream_t s);
+hipError_t launch_apply_small(const void* A, int a_is_f64, int64_t lda, int64_t rows, int ka,
+                              const double* T, int ldt, int kb, void* out, int out_is_f64,
+                              int64_t ldo, hipStream_t s);
+hipError_t launch_orth_factor(const double* Gm, int k, double tau, double* T, hipStream_t s);
+hipError_t launch_colsum(const double* A, int64_t lda, int64_t rows, int k, double* part, int* nparts,
+                         hipStream_t s);
+hipError_t launch_svd_factor(const double* C, const double* colsum, int k, int r, double* sigma,
+                             double* TU, double* TV, hipStream_t s);
+hipError_t launch_pack_w(const float* U, int64_t m, const float* V, int64_t n, int r, int kp,
+                         double* W, hipStream_t s);
+hipError_t launch_w_sumsq(const double* W, int64_t count, double* part, int* nparts, hipStream_t s);
+hipError_t launch_rho_init(const double* part, int nparts, int64_t N, int r, double rho0, DevState* st,
+                           hipStream_t s);
+hipError_t launch_admm_rows(const double* W, int64_t N, int r, int kp, const double* R, double* Y,
+                            double* Z, double* B, DevState* st, int step, double* negpart,
+                            hipStream_t s);
+hipError_t launch_polar(const double* Mpart, int nparts, int r, int kp, double* R, DevState* st,
+                        hipStream_t s);
+
+// k_update.hip
+int factor_blocks(int64_t count);
+int rowupdate_blocks(int64_t rows);
+hipError_t launch_factor_stats(const float* A, int64_t count, int r, double* part, int block_offset,
+                               int nblocks, hipStream_t s);
+hipError_t launch_setup_state2(const double* statpart, int nbU, int nbV, const double* xpart,
+                               int nxpart, double step_u, double step_v, int ext_iters,
+                               DevState* st, double* negpart, int nneg, hipStream_t s);
+hipError_t launch_head(const double* negpart, int nparts, DevState* st, hipStream_t s);
+hipError_t launch_tail(DevState* st, hipStream_t s);
+hipError_t launch_rowupdate(float* A, int64_t rows, int r, int kp, const float* P, const double* G,
+                            DevState* st, int half, int sweeps, int first, int want_pg,
+                            double* part, hipStream_t s);
+hipError_t launch_pbcd_decide(const double* part, int nparts, int half, int first, DevState* st,
+                              hipStream_t s);
+hipError_t launch_check(const float* U, int64_t m, const float* P, const double* G, const float* V,
+                        int64_t n, const float* Q, const double* H, int r, int kp, double* part,
+                        int* nbU, int* nbV, DevState* st, hipStream_t s);
+hipError_t launch_check_finalize(const double* part, int nbU, int nbV, const double* G,
+                                 const double* H, int kp, int k, int final_check, DevState* st,
+                                 double* trace, hipStream_t s);
+hipError_t launch_clip(float* A, int64_t count, hipStream_t s);
+
+}  // namespace enmf

@@ -1,0 +1,546 @@
+// X-streaming kernels: P = X B, Q = X^T A, the direct residual, ||X||^2 and
+// the FP32 -> BF16/FP16 conversion.  These read X (m x n, row-major) once per
+// launch; they are the O(mnr) core of every iteration (appendix on
+// computational complexity).
+//
+// Vector-ALU forms, used for every width (matrix-core forms for wide ranks
+// live in k_mfma.hip):
+//   X B   : one lane per row of X.  A 64-row x 512-byte tile of X is staged
+//           through LDS with coalesced 16-byte loads; each lane then reads its
+//           own row back and multiplies it with rows of B that are uniform
+//           across the wave (scalar loads, one SGPR operand per FMA).
+//   X^T A : one lane per column of X; rows of X are read coalesced straight
+//           from HBM and the matching row of A is uniform across the wave.
+// Both split the contraction over blocks ("split-K") and reduce the float32
+// partials in a fixed order, so results do not depend on scheduling.
+#include <type_traits>
+
+#include "dev_common.h"
+#include "enmf_internal.h"
+
+namespace enmf {
+
+namespace {
+
+constexpr int kRows = 64;      // rows of X per X B block (one per lane)
+constexpr int kThreads = 256;  // 4 waves
+constexpr int kTargetBlocks = 2048;
+
+template <int XT> struct Tile {
+  using ET = typename XElem<XT>::T;
+  static constexpr int EPV = 16 / sizeof(ET);     // elements per 16-byte vector
+  static constexpr int TW = 512 / sizeof(ET);     // tile width in elements (512 bytes per row)
+  static constexpr int LDT = TW + EPV;            // padded LDS row (breaks bank aliasing)
+  static constexpr int VPR = TW / EPV;            // 32 vectors per tile row
+  static constexpr int VPT = kRows * VPR / kThreads;  // 8 vectors per thread per tile
+  static constexpr int WCOLS = TW / 4;            // columns per wave per tile
+};
+
+template <int XT>
+__device__ __forceinline__ void unpack(const uint4& q, float* xs) {
+  if constexpr (XT == 0) {
+    xs[0] = __uint_as_float(q.x);
+    xs[1] = __uint_as_float(q.y);
+    xs[2] = __uint_as_float(q.z);
+    xs[3] = __uint_as_float(q.w);
+  } else {
+    const unsigned w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      xs[2 * i] = to_f32<XT>((unsigned short)(w[i] & 0xffffu));
+      xs[2 * i + 1] = to_f32<XT>((unsigned short)(w[i] >> 16));
+    }
+  }
+}
+
+// Zero the elements of a 16-byte vector whose column index is >= n.
+template <int XT>
+__device__ __forceinline__ uint4 mask_tail(uint4 q, int64_t col, int64_t n) {
+  using T = Tile<XT>;
+  if (col + T::EPV <= n) return q;
+  unsigned w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+  for (int e = 0; e < T::EPV; ++e) {
+    if (col + e >= n) {
+      if constexpr (XT == 0) w[e] = 0u;
+      else w[e / 2] &= (e & 1) ? 0x0000ffffu : 0xffff0000u;
+    }
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Loads this thread's share of a 64-row x TW-column tile of X.  With
+// `vec` (16-byte aligned rows) each share is one 16-byte load; otherwise the
+// same vector is assembled from element loads (any leading dimension).
+template <int XT>
+__device__ __forceinline__ void load_tile(const typename XElem<XT>::T* __restrict__ X, int64_t m,
+                                          int64_t n, int64_t ld, int64_t i0, int64_t jt, bool vec,
+                                          uint4* vb) {
+  using T = Tile<XT>;
+  using ET = typename XElem<XT>::T;
+#pragma unroll
+  for (int u = 0; u < T::VPT; ++u) {
+    const int q = threadIdx.x + kThreads * u;
+    const int row = q / T::VPR;
+    const int vc = q % T::VPR;
+    const int64_t col = jt + (int64_t)vc * T::EPV;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (i0 + row < m && col < n) {
+      const ET* src = X + (i0 + row) * ld + col;
+      if (vec) {
+        v = mask_tail<XT>(*reinterpret_cast<const uint4*>(src), col, n);
+      } else {
+        unsigned w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int e = 0; e < T::EPV; ++e) {
+          if (col + e < n) {
+            if constexpr (XT == 0) w[e] = __float_as_uint(src[e]);
+            else w[e / 2] |= ((unsigned)src[e]) << (16 * (e & 1));
+          }
+        }
+        v = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    }
+    vb[u] = v;
+  }
+}
+
+// P_part[s] (rows i0..i0+63, k columns) = X[i0.., tiles of split s] * Bp.
+// Bp: zero-padded copy of B, KP floats per row, rows up to the tiled width.
+template <int XT, int KP>
+__global__ __launch_bounds__(kThreads) void k_xv(const void* __restrict__ Xv, int64_t m, int64_t n,
+                                                 int64_t ld, const float* __restrict__ Bp, int k,
+                                                 int tiles_per_split, int64_t ntiles, int vec,
+                                                 float* __restrict__ out, int64_t split_stride) {
+  using T = Tile<XT>;
+  using ET = typename T::ET;
+  constexpr int kTileBytes = kRows * T::LDT * (int)sizeof(ET);
+  constexpr int kRedBytes = 2 * kRows * KP * 4;
+  constexpr int kSmem = kTileBytes > kRedBytes ? kTileBytes : kRedBytes;
+  __shared__ __align__(16) unsigned char smem[kSmem];
+  ET* tile = reinterpret_cast<ET*>(smem);
+
+  const ET* __restrict__ X = reinterpret_cast<const ET*>(Xv);
+  const int lane = threadIdx.x % kWave;
+  const int w = uniform(threadIdx.x / kWave);
+  const int64_t i0 = (int64_t)blockIdx.x * kRows;
+  const int64_t t0 = (int64_t)blockIdx.y * tiles_per_split;
+  const int64_t t1 = t0 + tiles_per_split < ntiles ? t0 + tiles_per_split : ntiles;
+
+  float acc[KP];
+#pragma unroll
+  for (int c = 0; c < KP; ++c) acc[c] = 0.f;
+
+  uint4 vb[T::VPT];
+  if (t0 < t1) load_tile<XT>(X, m, n, ld, i0, t0 * T::TW, vec != 0, vb);
+  for (int64_t t = t0; t < t1; ++t) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < T::VPT; ++u) {
+      const int q = threadIdx.x + kThreads * u;
+      *reinterpret_cast<uint4*>(tile + (q / T::VPR) * T::LDT + (q % T::VPR) * T::EPV) = vb[u];
+    }
+    __syncthreads();
+    if (t + 1 < t1) load_tile<XT>(X, m, n, ld, i0, (t + 1) * T::TW, vec != 0, vb);
+
+    const ET* trow = tile + lane * T::LDT + w * T::WCOLS;
+    const float* __restrict__ bbase = Bp + (t * T::TW + (int64_t)w * T::WCOLS) * KP;
+#pragma unroll
+    for (int v = 0; v < T::WCOLS / T::EPV; ++v) {
+      const uint4 q = *reinterpret_cast<const uint4*>(trow + v * T::EPV);
+      float xs[T::EPV];
+      unpack<XT>(q, xs);
+#pragma unroll
+      for (int e = 0; e < T::EPV; ++e) {
+        const float* __restrict__ brow = bbase + (v * T::EPV + e) * KP;
+#pragma unroll
+        for (int c = 0; c < KP; ++c) acc[c] = fmaf(xs[e], brow[c], acc[c]);
+      }
+    }
+  }
+
+  // Fixed-order reduction of the four waves: (w0 + w2) + (w1 + w3).
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(smem);   // [2][KP][64]
+  if (w >= 2) {
+#pragma unroll
+    for (int c = 0; c < KP; ++c) red[((w - 2) * KP + c) * kWave + lane] = acc[c];
+  }
+  __syncthreads();
+  if (w < 2) {
+#pragma unroll
+    for (int c = 0; c < KP; ++c) acc[c] += red[(w * KP + c) * kWave + lane];
+  }
+  __syncthreads();
+  if (w == 1) {
+#pragma unroll
+    for (int c = 0; c < KP; ++c) red[c * kWave + lane] = acc[c];
+  }
+  __syncthreads();
+  if (w == 0 && i0 + lane < m) {
+    float* o = out + (int64_t)blockIdx.y * split_stride + (i0 + lane) * k;
+#pragma unroll
+    for (int c = 0; c < KP; ++c)
+      if (c < k) o[c] = acc[c] + red[c * kWave + lane];
+  }
+}
+
+// Q_part[s] (columns j0..j0+255, k values each) = X[rows of split s, j]^T Ap.
+template <int XT, int KP>
+__global__ __launch_bounds__(kThreads) void k_xtu(const void* __restrict__ Xv, int64_t m, int64_t n,
+                                                  int64_t ld, const float* __restrict__ Ap, int k,
+                                                  int64_t rows_per_split, float* __restrict__ out,
+                                                  int64_t split_stride) {
+  using ET = typename XElem<XT>::T;
+  const ET* __restrict__ X = reinterpret_cast<const ET*>(Xv);
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const bool valid = j < n;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t r1 = r0 + rows_per_split < m ? r0 + rows_per_split : m;
+  const int64_t jc = valid ? j : 0;
+
+  float acc[KP];
+#pragma unroll
+  for (int c = 0; c < KP; ++c) acc[c] = 0.f;
+
+  constexpr int U = 8;
+  int64_t i = r0;
+  for (; i + U <= r1; i += U) {
+    float xs[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xs[u] = valid ? to_f32<XT>(X[(i + u) * ld + jc]) : 0.f;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const float* __restrict__ arow = Ap + (i + u) * KP;
+#pragma unroll
+      for (int c = 0; c < KP; ++c) acc[c] = fmaf(xs[u], arow[c], acc[c]);
+    }
+  }
+  for (; i < r1; ++i) {
+    const float x = valid ? to_f32<XT>(X[i * ld + jc]) : 0.f;
+    const float* __restrict__ arow = Ap + i * KP;
+#pragma unroll
+    for (int c = 0; c < KP; ++c) acc[c] = fmaf(x, arow[c], acc[c]);
+  }
+  if (valid) {
+    float* o = out + (int64_t)blockIdx.y * split_stride + j * k;
+#pragma unroll
+    for (int c = 0; c < KP; ++c)
+      if (c < k) o[c] = acc[c];
+  }
+}
+
+// out[e] = sum_s part[s * stride + e], s in order.
+__global__ void k_reduce_splits(const float* __restrict__ part, int splits, int64_t stride,
+                                int64_t count, float* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    float s = part[e];
+    for (int q = 1; q < splits; ++q) s += part[q * stride + e];
+    out[e] = s;
+  }
+}
+
+// out[j][c] = c < k ? in[j][c] : 0, rows j < rows_out (rows >= rows_in are zero).
+template <typename TO>
+__global__ void k_pad_cols(const float* __restrict__ in, int64_t rows_in, int k, int kp,
+                           int64_t rows_out, TO* __restrict__ out) {
+  const int64_t count = rows_out * kp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / kp;
+    const int c = (int)(e % kp);
+    out[e] = (j < rows_in && c < k) ? (TO)in[j * k + c] : (TO)0;
+  }
+}
+
+// Direct residual: part[b] = sum over this block's (i, j) of (X_ij - U_i . V_j)^2,
+// with the dot product and the square accumulated in float64.  Lane = column j.
+template <int XT, int KP>
+__global__ __launch_bounds__(kThreads) void k_residual(const void* __restrict__ Xv, int64_t m,
+                                                       int64_t n, int64_t ld,
+                                                       const double* __restrict__ Ud,
+                                                       const float* __restrict__ V, int r,
+                                                       int64_t rows_per_split,
+                                                       double* __restrict__ part) {
+  __shared__ double sh[kThreads / kWave];
+  using ET = typename XElem<XT>::T;
+  const ET* __restrict__ X = reinterpret_cast<const ET*>(Xv);
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const bool valid = j < n;
+  double v[KP];
+#pragma unroll
+  for (int c = 0; c < KP; ++c) v[c] = (valid && c < r) ? (double)V[j * r + c] : 0.0;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t r1 = r0 + rows_per_split < m ? r0 + rows_per_split : m;
+  double acc = 0.0;
+  if (valid) {
+    for (int64_t i = r0; i < r1; ++i) {
+      const double* __restrict__ urow = Ud + i * KP;
+      double d = 0.0;
+#pragma unroll
+      for (int c = 0; c < KP; ++c) d = fma(urow[c], v[c], d);
+      const double e = (double)to_f32<XT>(X[i * ld + j]) - d;
+      acc = fma(e, e, acc);
+    }
+  }
+  const double t = block_sum<kThreads>(acc, sh);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+}
+
+// part[b] = sum of x^2 over the rows of block b.
+template <int XT>
+__global__ __launch_bounds__(kThreads) void k_sumsq(const void* __restrict__ Xv, int64_t m,
+                                                    int64_t n, int64_t ld, int64_t rows_per_block,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[kThreads / kWave];
+  using ET = typename XElem<XT>::T;
+  const ET* __restrict__ X = reinterpret_cast<const ET*>(Xv);
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = r0 + rows_per_block < m ? r0 + rows_per_block : m;
+  double acc = 0.0;
+  for (int64_t i = r0; i < r1; ++i) {
+    float rowacc = 0.f;
+    for (int64_t j = threadIdx.x; j < n; j += kThreads) {
+      const float x = to_f32<XT>(X[i * ld + j]);
+      rowacc = fmaf(x, x, rowacc);
+    }
+    acc += (double)rowacc;
+  }
+  const double t = block_sum<kThreads>(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// out[f] = sum_b part[b * stride + f] for f < nfields, b in order.
+__global__ void k_sum_parts(const double* __restrict__ part, int nparts, int stride, int nfields,
+                            double* __restrict__ out) {
+  const int f = threadIdx.x;
+  if (f >= nfields) return;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * stride + f];
+  out[f] = s;
+}
+
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x0040u);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+__global__ void k_convert(const float* __restrict__ x, int64_t m, int64_t n, int64_t ldi, int to,
+                          unsigned short* __restrict__ out, int64_t ldo) {
+  const int64_t count = m * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / n, j = e % n;
+    const float v = x[i * ldi + j];
+    unsigned short h;
+    if (to == ENMF_BF16) {
+      h = f32_to_bf16_rne(v);
+    } else {
+      const _Float16 hv = (_Float16)v;
+      __builtin_memcpy(&h, &hv, 2);
+    }
+    out[i * ldo + j] = h;
+  }
+}
+
+int grid_for(int64_t count, int threads = 256, int cap = 8192) {
+  int64_t g = (count + threads - 1) / threads;
+  if (g < 1) g = 1;
+  return (int)(g < cap ? g : cap);
+}
+
+template <int XT, int KP>
+void xv_launch(dim3 grid, const void* X, int64_t m, int64_t n, int64_t ld, const float* Bp, int k,
+               int tps, int64_t ntiles, float* out, int64_t stride, hipStream_t s) {
+  const int vec = (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
+                  ((ld * (int64_t)sizeof(typename XElem<XT>::T)) % 16 == 0);
+  hipLaunchKernelGGL((k_xv<XT, KP>), grid, dim3(kThreads), 0, s, X, m, n, ld, Bp, k, tps, ntiles,
+                     vec, out, stride);
+}
+
+template <int XT, int KP>
+void xtu_launch(dim3 grid, const void* X, int64_t m, int64_t n, int64_t ld, const float* Ap, int k,
+                int64_t rps, float* out, int64_t stride, hipStream_t s) {
+  hipLaunchKernelGGL((k_xtu<XT, KP>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ap, k, rps, out,
+                     stride);
+}
+
+template <int XT>
+void xv_dispatch_kp(int kp, dim3 grid, const void* X, int64_t m, int64_t n, int64_t ld,
+                    const float* Bp, int k, int tps, int64_t ntiles, float* out, int64_t stride,
+                    hipStream_t s) {
+  switch (kp) {
+    case 8: xv_launch<XT, 8>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s); break;
+    case 16: xv_launch<XT, 16>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s); break;
+    case 32: xv_launch<XT, 32>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s); break;
+    case 48: xv_launch<XT, 48>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s); break;
+    case 64: xv_launch<XT, 64>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s); break;
+    default: xv_launch<XT, 80>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s); break;
+  }
+}
+
+template <int XT>
+void xtu_dispatch_kp(int kp, dim3 grid, const void* X, int64_t m, int64_t n, int64_t ld,
+                     const float* Ap, int k, int64_t rps, float* out, int64_t stride,
+                     hipStream_t s) {
+  switch (kp) {
+    case 8: xtu_launch<XT, 8>(grid, X, m, n, ld, Ap, k, rps, out, stride, s); break;
+    case 16: xtu_launch<XT, 16>(grid, X, m, n, ld, Ap, k, rps, out, stride, s); break;
+    case 32: xtu_launch<XT, 32>(grid, X, m, n, ld, Ap, k, rps, out, stride, s); break;
+    case 48: xtu_launch<XT, 48>(grid, X, m, n, ld, Ap, k, rps, out, stride, s); break;
+    case 64: xtu_launch<XT, 64>(grid, X, m, n, ld, Ap, k, rps, out, stride, s); break;
+    default: xtu_launch<XT, 80>(grid, X, m, n, ld, Ap, k, rps, out, stride, s); break;
+  }
+}
+
+template <int XT>
+void residual_dispatch(int kp, dim3 grid, const void* X, int64_t m, int64_t n, int64_t ld,
+                       const double* Ud, const float* V, int r, int64_t rps, double* part,
+                       hipStream_t s) {
+  switch (kp) {
+    case 8: hipLaunchKernelGGL((k_residual<XT, 8>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, V, r, rps, part); break;
+    case 16: hipLaunchKernelGGL((k_residual<XT, 16>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, V, r, rps, part); break;
+    case 32: hipLaunchKernelGGL((k_residual<XT, 32>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, V, r, rps, part); break;
+    case 48: hipLaunchKernelGGL((k_residual<XT, 48>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, V, r, rps, part); break;
+    default: hipLaunchKernelGGL((k_residual<XT, 64>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, V, r, rps, part); break;
+  }
+}
+
+}  // namespace
+
+int64_t xv_tile_width(int xt) { return xt == ENMF_F32 ? 128 : 256; }
+
+int xv_splits(int64_t m, int64_t n, int xt) {
+  const int64_t rb = (m + kRows - 1) / kRows;
+  const int64_t nt = (n + xv_tile_width(xt) - 1) / xv_tile_width(xt);
+  int64_t s = (kTargetBlocks + rb - 1) / rb;
+  if (s > nt) s = nt;
+  if (s < 1) s = 1;
+  return (int)s;
+}
+
+int xtu_splits(int64_t m, int64_t n) {
+  const int64_t cb = (n + kThreads - 1) / kThreads;
+  int64_t s = (kTargetBlocks + cb - 1) / cb;
+  const int64_t smax = (m + 31) / 32;
+  if (s > smax) s = smax;
+  if (s < 1) s = 1;
+  return (int)s;
+}
+
+hipError_t launch_pad_cols(const float* in, int64_t rows, int k, int kp, float* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_pad_cols<float>), dim3(grid_for(rows * kp)), dim3(256), 0, s, in, rows, k,
+                     kp, rows, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_rows_cols(const float* in, int64_t rows_in, int k, int kp, int64_t rows_out,
+                                float* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_pad_cols<float>), dim3(grid_for(rows_out * kp)), dim3(256), 0, s, in,
+                     rows_in, k, kp, rows_out, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_cols_f64(const float* in, int64_t rows, int k, int kp, double* out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL((k_pad_cols<double>), dim3(grid_for(rows * kp)), dim3(256), 0, s, in, rows, k,
+                     kp, rows, out);
+  return hipGetLastError();
+}
+
+// P = X B.  Bp is B zero padded to kp columns and to ntiles*TW rows;
+// part must hold splits*m*k floats when splits > 1.
+hipError_t launch_xv(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* Bp, int k,
+                     int kp, int splits, float* part, float* out, hipStream_t s) {
+  const int64_t tw = xv_tile_width(xt);
+  const int64_t ntiles = (n + tw - 1) / tw;
+  const int tps = (int)((ntiles + splits - 1) / splits);
+  const int eff = (int)((ntiles + tps - 1) / tps);
+  const int64_t rb = (m + kRows - 1) / kRows;
+  float* dst = eff > 1 ? part : out;
+  const int64_t stride = m * k;
+  dim3 grid((unsigned)rb, (unsigned)eff);
+  switch (xt) {
+    case ENMF_F32: xv_dispatch_kp<0>(kp, grid, X, m, n, ld, Bp, k, tps, ntiles, dst, stride, s); break;
+    case ENMF_BF16: xv_dispatch_kp<1>(kp, grid, X, m, n, ld, Bp, k, tps, ntiles, dst, stride, s); break;
+    default: xv_dispatch_kp<2>(kp, grid, X, m, n, ld, Bp, k, tps, ntiles, dst, stride, s); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || eff <= 1) return e;
+  hipLaunchKernelGGL(k_reduce_splits, dim3(grid_for(stride)), dim3(256), 0, s, part, eff, stride,
+                     stride, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_xtu(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* Ap, int k,
+                      int kp, int splits, float* part, float* out, hipStream_t s) {
+  const int64_t rps = (m + splits - 1) / splits;
+  const int eff = (int)((m + rps - 1) / rps);
+  const int64_t cb = (n + kThreads - 1) / kThreads;
+  float* dst = eff > 1 ? part : out;
+  const int64_t stride = n * k;
+  dim3 grid((unsigned)cb, (unsigned)eff);
+  switch (xt) {
+    case ENMF_F32: xtu_dispatch_kp<0>(kp, grid, X, m, n, ld, Ap, k, rps, dst, stride, s); break;
+    case ENMF_BF16: xtu_dispatch_kp<1>(kp, grid, X, m, n, ld, Ap, k, rps, dst, stride, s); break;
+    default: xtu_dispatch_kp<2>(kp, grid, X, m, n, ld, Ap, k, rps, dst, stride, s); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || eff <= 1) return e;
+  hipLaunchKernelGGL(k_reduce_splits, dim3(grid_for(stride)), dim3(256), 0, s, part, eff, stride,
+                     stride, out);
+  return hipGetLastError();
+}
+
+// Residual partials: Ud is U padded to kp float64 columns (m rows).
+hipError_t launch_residual(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const double* Ud,
+                           const float* V, int r, double* part, int* nparts, hipStream_t s) {
+  const int kp = pad_width(r) > 64 ? 64 : pad_width(r);
+  const int64_t cb = (n + kThreads - 1) / kThreads;
+  int64_t sp = (kTargetBlocks + cb - 1) / cb;
+  if (sp > m) sp = m;
+  if (sp < 1) sp = 1;
+  const int64_t rps = (m + sp - 1) / sp;
+  sp = (m + rps - 1) / rps;
+  dim3 grid((unsigned)cb, (unsigned)sp);
+  switch (xt) {
+    case ENMF_F32: residual_dispatch<0>(kp, grid, X, m, n, ld, Ud, V, r, rps, part, s); break;
+    case ENMF_BF16: residual_dispatch<1>(kp, grid, X, m, n, ld, Ud, V, r, rps, part, s); break;
+    default: residual_dispatch<2>(kp, grid, X, m, n, ld, Ud, V, r, rps, part, s); break;
+  }
+  *nparts = (int)(cb * sp);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq_x(const void* X, int xt, int64_t m, int64_t n, int64_t ld, double* part,
+                          int* nparts, hipStream_t s) {
+  int64_t nb = m < 1024 ? m : 1024;
+  if (nb < 1) nb = 1;
+  const int64_t rpb = (m + nb - 1) / nb;
+  nb = (m + rpb - 1) / rpb;
+  switch (xt) {
+    case ENMF_F32: hipLaunchKernelGGL((k_sumsq<0>), dim3((unsigned)nb), dim3(kThreads), 0, s, X, m, n, ld, rpb, part); break;
+    case ENMF_BF16: hipLaunchKernelGGL((k_sumsq<1>), dim3((unsigned)nb), dim3(kThreads), 0, s, X, m, n, ld, rpb, part); break;
+    default: hipLaunchKernelGGL((k_sumsq<2>), dim3((unsigned)nb), dim3(kThreads), 0, s, X, m, n, ld, rpb, part); break;
+  }
+  *nparts = (int)nb;
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_parts(const double* part, int nparts, int stride, int nfields, double* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, nparts, stride, nfields, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(const float* x, int64_t m, int64_t n, int64_t ldi, int to, void* out,
+                          int64_t ldo, hipStream_t s) {
+  hipLaunchKernelGGL(k_convert, dim3(grid_for(m * n)), dim3(256), 0, s, x, m, n, ldi, to,
+                     reinterpret_cast<unsigned short*>(out), ldo);
+  return hipGetLastError();
+}
+
+}  // namespace enmf

@@ -1,0 +1,269 @@
+"""Python binding of libenmf (ctypes).  Argument marshalling only.
+
+Every computation runs in the HIP kernels of libenmf.so; PyTorch supplies
+device memory and the current stream.  The names mirror the C ABI in
+include/enmf.h.  There is no CPU fallback: a missing library, a tensor that
+is not on the GPU or a failing call raises.
+"""
+
+import ctypes
+import os
+from ctypes import POINTER, Structure, byref, c_char_p, c_double, c_int32, c_int64, c_void_p
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libenmf.so")
+
+F32, BF16, F16 = 0, 1, 2
+_DTYPES = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}
+MAX_RANK = 64
+MAX_WIDTH = 80
+TRACE_FIELDS = 8
+
+
+class EnmfError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"enmf status {status}: {message}")
+        self.status = status
+
+
+class Matrix(Structure):
+    _fields_ = [("data", c_void_p), ("m", c_int64), ("n", c_int64), ("ld", c_int64),
+                ("dtype", c_int32), ("reserved", c_int32)]
+
+
+class SvdOpts(Structure):
+    _fields_ = [("omega", c_void_p), ("oversample", c_int32), ("power_iters", c_int32)]
+
+
+class RotateOpts(Structure):
+    _fields_ = [("rho0", c_double), ("tol", c_double), ("max_iter", c_int32),
+                ("check_every", c_int32)]
+
+
+class IterOpts(Structure):
+    _fields_ = [("step_u", c_double), ("step_v", c_double), ("pbcd_eps", c_double),
+                ("relerr_tol", c_double), ("kkt_tol", c_double), ("relerr_svd", c_double),
+                ("ext_iters", c_int32), ("pbcd_max_iter", c_int32), ("max_iter", c_int32),
+                ("check_every", c_int32), ("mode", c_int32), ("reserved", c_int32)]
+
+
+class IterReport(Structure):
+    _fields_ = [("iters", c_int32), ("ext_iters_done", c_int32), ("phase", c_int32),
+                ("converged", c_int32), ("step_u", c_double), ("step_v", c_double),
+                ("f", c_double), ("relerr", c_double), ("re_paper", c_double), ("kkt", c_double),
+                ("kkt_feas", c_double), ("kkt_pg_u", c_double), ("kkt_pg_v", c_double),
+                ("delta_w", c_double), ("sigma_w", c_double)]
+
+
+class Kkt(Structure):
+    _fields_ = [(k, c_double) for k in ("f", "relerr", "re_paper", "kkt", "kkt_feas", "kkt_pg_u",
+                                        "kkt_pg_v", "delta_w", "sigma_w", "sigma_u", "sigma_v",
+                                        "min_w")]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point.
+SIGNATURES = [
+    ("enmf_version", c_int32, []),
+    ("enmf_status_string", c_char_p, [c_int32]),
+    ("enmf_create", c_int32, [POINTER(c_void_p), c_int32, c_void_p]),
+    ("enmf_destroy", None, [c_void_p]),
+    ("enmf_last_error", c_char_p, [c_void_p]),
+    ("enmf_set_stream", c_int32, [c_void_p, c_void_p]),
+    ("enmf_synchronize", c_int32, [c_void_p]),
+    ("enmf_convert", c_int32, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_int32, c_void_p,
+                               c_int64]),
+    ("enmf_xv", c_int32, [c_void_p, POINTER(Matrix), c_void_p, c_int32, c_void_p]),
+    ("enmf_xtu", c_int32, [c_void_p, POINTER(Matrix), c_void_p, c_int32, c_void_p]),
+    ("enmf_gram", c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p]),
+    ("enmf_svd_init", c_int32, [c_void_p, POINTER(Matrix), c_int32, POINTER(SvdOpts), c_void_p,
+                                c_void_p, POINTER(c_double), POINTER(c_double)]),
+    ("enmf_rotate", c_int32, [c_void_p, c_int64, c_int64, c_int32, c_void_p, c_void_p,
+                              POINTER(RotateOpts), POINTER(c_double), POINTER(c_int32),
+                              POINTER(c_double), POINTER(c_double)]),
+    ("enmf_iterate", c_int32, [c_void_p, POINTER(Matrix), c_int32, c_void_p, c_void_p,
+                               POINTER(IterOpts), POINTER(IterReport), c_void_p, c_int32]),
+    ("enmf_objective_kkt", c_int32, [c_void_p, POINTER(Matrix), c_int32, c_void_p, c_void_p,
+                                     c_double, POINTER(Kkt)]),
+]
+
+
+def load_library(path=LIB_PATH):
+    """Load libenmf.so and declare its signatures (no device call is made)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr())
+
+
+def _dev(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    return t
+
+
+def _factor(t, rows, r, name):
+    _dev(t, name)
+    if t.dtype != torch.float32 or tuple(t.shape) != (rows, r) or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 tensor of shape ({rows}, {r})")
+    return t
+
+
+def matrix(X):
+    """enmf_matrix view of a 2-D row-major CUDA tensor (float32, bfloat16 or float16)."""
+    _dev(X, "X")
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a 2-D tensor with unit column stride")
+    if X.dtype not in _DTYPES:
+        raise ValueError("X dtype must be float32, bfloat16 or float16")
+    return Matrix(X.data_ptr(), X.shape[0], X.shape[1], X.stride(0), _DTYPES[X.dtype], 0)
+
+
+class Context:
+    """One libenmf context on a device; calls enqueue on torch's current stream."""
+
+    def __init__(self, device=0):
+        self._lib = load_library()
+        self.device = device
+        h = c_void_p()
+        st = self._lib.enmf_create(byref(h), device, None)
+        if st != 0:
+            raise EnmfError(st, self._lib.enmf_status_string(st).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.enmf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, fn, *args):
+        self._lib.enmf_set_stream(self._h, c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+        st = fn(self._h, *args)
+        if st != 0:
+            raise EnmfError(st, self._lib.enmf_last_error(self._h).decode())
+
+    def synchronize(self):
+        self._call(self._lib.enmf_synchronize)
+
+    # ---- building blocks ----
+    def convert(self, X32, dtype=torch.bfloat16):
+        _dev(X32, "X32")
+        if X32.dtype != torch.float32 or X32.dim() != 2 or X32.stride(1) != 1:
+            raise ValueError("X32 must be a 2-D float32 tensor with unit column stride")
+        m, n = X32.shape
+        ld = (n + 7) // 8 * 8
+        buf = torch.empty((m, ld), dtype=dtype, device=X32.device)
+        self._call(self._lib.enmf_convert, _ptr(X32), m, n, X32.stride(0), _DTYPES[dtype], _ptr(buf), ld)
+        return buf[:, :n]
+
+    def xv(self, X, B):
+        M = matrix(X)
+        k = B.shape[1]
+        _factor(B, X.shape[1], k, "B")
+        P = torch.empty((X.shape[0], k), dtype=torch.float32, device=X.device)
+        self._call(self._lib.enmf_xv, byref(M), _ptr(B), k, _ptr(P))
+        return P
+
+    def xtu(self, X, A):
+        M = matrix(X)
+        k = A.shape[1]
+        _factor(A, X.shape[0], k, "A")
+        Q = torch.empty((X.shape[1], k), dtype=torch.float32, device=X.device)
+        self._call(self._lib.enmf_xtu, byref(M), _ptr(A), k, _ptr(Q))
+        return Q
+
+    def gram(self, A):
+        _factor(A, A.shape[0], A.shape[1], "A")
+        k = A.shape[1]
+        G = torch.empty((k, k), dtype=torch.float64, device=A.device)
+        self._call(self._lib.enmf_gram, _ptr(A), A.shape[0], k, _ptr(G))
+        return G
+
+    # ---- the four blocks of the method ----
+    def svd_init(self, X, r, omega, oversample=10, power_iters=2):
+        M = matrix(X)
+        m, n = X.shape
+        _factor(omega, n, r + oversample, "omega")
+        U = torch.empty((m, r), dtype=torch.float32, device=X.device)
+        V = torch.empty((n, r), dtype=torch.float32, device=X.device)
+        sig = (c_double * r)()
+        rel = c_double()
+        o = SvdOpts(omega.data_ptr(), oversample, power_iters)
+        self._call(self._lib.enmf_svd_init, byref(M), r, byref(o), _ptr(U), _ptr(V), sig, byref(rel))
+        return U, V, [sig[i] for i in range(r)], rel.value
+
+    def rotate(self, U, V, rho0=1.0, max_iter=100, tol=1e-10, check_every=10):
+        m, r = U.shape
+        n = V.shape[0]
+        _factor(U, m, r, "U")
+        _factor(V, n, r, "V")
+        o = RotateOpts(rho0, tol, max_iter, check_every)
+        R = (c_double * (r * r))()
+        steps = c_int32()
+        g0, g1 = c_double(), c_double()
+        self._call(self._lib.enmf_rotate, m, n, r, _ptr(U), _ptr(V), byref(o), R, byref(steps),
+                   byref(g0), byref(g1))
+        return dict(R=[R[i] for i in range(r * r)], steps=steps.value, neg_mass_before=g0.value,
+                    neg_mass_after=g1.value)
+
+    def iterate(self, X, U, V, max_iter, ext_iters=10, pbcd_max_iter=5, pbcd_eps=0.0,
+                step_u=0.0, step_v=0.0, check_every=1, kkt_tol=-1.0, relerr_tol=-1.0,
+                relerr_svd=0.0, mode=0, trace_cap=0):
+        M = matrix(X)
+        m, n = X.shape
+        r = U.shape[1]
+        _factor(U, m, r, "U")
+        _factor(V, n, r, "V")
+        o = IterOpts(step_u, step_v, pbcd_eps, relerr_tol, kkt_tol, relerr_svd, ext_iters,
+                     pbcd_max_iter, max_iter, check_every, mode, 0)
+        rep = IterReport()
+        trace = None
+        if trace_cap > 0:
+            trace = torch.zeros((trace_cap, TRACE_FIELDS), dtype=torch.float64, device=X.device)
+        self._call(self._lib.enmf_iterate, byref(M), r, _ptr(U), _ptr(V), byref(o), byref(rep),
+                   _ptr(trace) if trace is not None else None, trace_cap)
+        out = {name: getattr(rep, name) for name, _ in IterReport._fields_}
+        if trace is not None:
+            out["trace"] = trace
+        return out
+
+    def objective_kkt(self, X, U, V, relerr_svd=0.0):
+        M = matrix(X)
+        m, n = X.shape
+        r = U.shape[1]
+        _factor(U, m, r, "U")
+        _factor(V, n, r, "V")
+        k = Kkt()
+        self._call(self._lib.enmf_objective_kkt, byref(M), r, _ptr(U), _ptr(V), relerr_svd, byref(k))
+        return {name: getattr(k, name) for name, _ in Kkt._fields_}
+
+    def solve(self, X, r, omega, oversample=10, power_iters=2, rho0=1.0, rot_max_iter=100,
+              rot_tol=1e-10, **iter_opts):
+        """Algorithm 3 end to end: SVD init, rotation, exterior phase and HALS."""
+        U, V, sigma, rsvd = self.svd_init(X, r, omega, oversample, power_iters)
+        rot = self.rotate(U, V, rho0, rot_max_iter, rot_tol)
+        iter_opts.setdefault("relerr_svd", rsvd)
+        rep = self.iterate(X, U, V, **iter_opts)
+        rep.update(sigma=sigma, relerr_svd=rsvd, rotation=rot)
+        return U, V, rep

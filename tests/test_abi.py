@@ -1,0 +1,67 @@
+"""CPU checks of the C ABI: the library loads and exports every declared symbol.
+
+No compute call is made here; on a machine without a GPU, context creation
+must fail cleanly with ENMF_EDEVICE instead of crashing.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2605_19325_amd import enmf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "enmf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(enmf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("enmf_svd_init", "enmf_rotate", "enmf_iterate", "enmf_objective_kkt",
+                 "enmf_xv", "enmf_xtu", "enmf_gram", "enmf_convert", "enmf_create"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = enmf.load_library()
+    raw = ctypes.CDLL(enmf.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(raw, name), name
+    # the binding declares the same set
+    assert sorted(n for n, _, _ in enmf.SIGNATURES) == declared_functions()
+    assert lib.enmf_version() >= 100
+
+
+def test_status_strings():
+    lib = enmf.load_library()
+    assert lib.enmf_status_string(0) == b"ok"
+    assert lib.enmf_status_string(1) == b"invalid argument"
+    assert lib.enmf_status_string(99) == b"unknown status"
+
+
+def test_struct_layouts_match_header():
+    # sizes follow the header: all doubles first or 8-byte aligned groups
+    assert ctypes.sizeof(enmf.Matrix) == 40
+    assert ctypes.sizeof(enmf.SvdOpts) == 16
+    assert ctypes.sizeof(enmf.RotateOpts) == 24
+    assert ctypes.sizeof(enmf.IterOpts) == 72
+    assert ctypes.sizeof(enmf.IterReport) == 16 + 11 * 8
+    assert ctypes.sizeof(enmf.Kkt) == 12 * 8
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = enmf.load_library()
+    h = ctypes.c_void_p()
+    st = lib.enmf_create(ctypes.byref(h), 0, None)
+    assert st == 3 and not h.value          # ENMF_EDEVICE, no context
+    assert lib.enmf_last_error(None) == b"null context"

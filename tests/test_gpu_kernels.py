@@ -1,0 +1,90 @@
+"""GPU parity of the building blocks against the FP64 oracle's definitions.
+
+Streaming products X B and X^T A are compared element by element with the
+float64 product under the float32 accumulation bound
+|P - P64| <= c * eps32 * sqrt(n) * (|X| |B|) elementwise (c = 8); Grams are
+float64 accumulations of exact float32 products (1e-12 relative);
+the BF16 conversion is bit-exact against round-to-nearest-even.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2605_19325_amd import enmf, inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+EPS32 = 2.0 ** -24
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def ref_bound(Xd, Bd, n):
+    return 8 * EPS32 * np.sqrt(n) * (np.abs(Xd) @ np.abs(Bd)) + 1e-30
+
+
+SHAPES = [(1, 1), (7, 5), (65, 129), (300, 1000), (130, 515), (1000, 77)]
+
+
+@pytest.mark.parametrize("m,n", SHAPES)
+@pytest.mark.parametrize("k", [1, 3, 10, 16, 20, 49, 64, 80])
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_xv_xtu(lib, m, n, k, dt):
+    say(f"xv/xtu m={m} n={n} k={k} dt={dt}")
+    rng = np.random.default_rng(m * 1000 + n + k)
+    X = rng.random((m, n)).astype(np.float32)
+    B = rng.standard_normal((n, k)).astype(np.float32)
+    A = rng.standard_normal((m, k)).astype(np.float32)
+    Xt = torch.from_numpy(X).to(DEV)
+    if dt == "bf16":
+        Xt = lib.convert(Xt, torch.bfloat16)
+        Xd = Xt.float().cpu().double().numpy()
+    else:
+        Xd = X.astype(np.float64)
+    P = lib.xv(Xt, torch.from_numpy(B).to(DEV)).cpu().double().numpy()
+    Q = lib.xtu(Xt, torch.from_numpy(A).to(DEV)).cpu().double().numpy()
+    Bd, Ad = B.astype(np.float64), A.astype(np.float64)
+    assert np.all(np.abs(P - Xd @ Bd) <= ref_bound(Xd, Bd, n))
+    assert np.all(np.abs(Q - Xd.T @ Ad) <= ref_bound(Xd.T, Ad, m))
+
+
+def test_xv_padded_leading_dimension(lib):
+    say("xv ld padding")
+    rng = np.random.default_rng(5)
+    full = rng.random((50, 136)).astype(np.float32)
+    full[:, 130:] = np.nan                      # padding beyond n must never be read into results
+    Xt = torch.from_numpy(full).to(DEV)[:, :130]
+    B = rng.standard_normal((130, 7)).astype(np.float32)
+    P = lib.xv(Xt, torch.from_numpy(B).to(DEV)).cpu().double().numpy()
+    Xd = full[:, :130].astype(np.float64)
+    assert np.all(np.abs(P - Xd @ B) <= ref_bound(Xd, B.astype(np.float64), 130))
+    A = rng.standard_normal((50, 7)).astype(np.float32)
+    Q = lib.xtu(Xt, torch.from_numpy(A).to(DEV)).cpu().double().numpy()
+    assert np.all(np.abs(Q - Xd.T @ A) <= ref_bound(Xd.T, A.astype(np.float64), 50))
+
+
+@pytest.mark.parametrize("rows,k", [(1, 1), (33, 5), (1000, 49), (4097, 64), (513, 80)])
+def test_gram(lib, rows, k):
+    say(f"gram rows={rows} k={k}")
+    A = np.random.default_rng(rows + k).standard_normal((rows, k)).astype(np.float32)
+    G = lib.gram(torch.from_numpy(A).to(DEV)).cpu().numpy()
+    Ad = A.astype(np.float64)
+    ref = Ad.T @ Ad
+    assert np.allclose(G, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_convert_bf16_rne_bitexact(lib):
+    say("convert bf16/f16")
+    rng = np.random.default_rng(3)
+    X = (rng.standard_normal((37, 101)) * 10.0 ** rng.integers(-20, 20, (37, 101))).astype(np.float32)
+    X[0, :5] = [0.0, -0.0, np.inf, -np.inf, 1.0 + 2.0 ** -8]   # includes a tie
+    Xt = torch.from_numpy(X).to(DEV)
+    b = lib.convert(Xt, torch.bfloat16).cpu()
+    ref = torch.from_numpy(X).to(torch.bfloat16)
+    assert torch.equal(b.view(torch.int16), ref.view(torch.int16))
+    h = lib.convert(Xt, torch.float16).cpu()
+    assert torch.equal(h.view(torch.int16), torch.from_numpy(X).to(torch.float16).view(torch.int16))
