@@ -113,7 +113,8 @@ enmf_status enmf_gram(enmf_ctx* ctx, const float* A, int64_t rows, int32_t k, do
  * matrix.  Output: balanced factors U* = U Sigma^(1/2) (m x r) and
  * V* = V Sigma^(1/2) (n x r) in float32, each column pair signed so that the
  * column sum of U is positive; sigma_host (r values, descending) and
- * relerr_svd_host = sqrt(||X||^2 - sum sigma^2)/||X|| (either may be NULL).
+ * relerr_svd_host = ||X - U* V*^T||_F / ||X||_F, the Eckart-Young floor
+ * sqrt(||X||^2 - sum sigma^2)/||X|| evaluated directly in float64 (either may be NULL).
  * Orthonormalisation and the small eigenproblem run in float64 on the GPU.
  * Requires 1 <= r <= min(m, n, ENMF_MAX_RANK) and r + oversample <= ENMF_MAX_WIDTH. */
 typedef struct {
@@ -195,6 +196,15 @@ typedef struct {
 
 enmf_status enmf_objective_kkt(enmf_ctx* ctx, const enmf_matrix* X, int32_t r, const float* U,
                                const float* V, double relerr_svd, enmf_kkt* out_host);
+
+/* ---- instrumentation ----
+ * Average device time (ms) of one launch of the X B and of the X^T A
+ * streaming kernels at width k, over `reps` back-to-back launches of each,
+ * timed with HIP events on the context stream (operand padding and the
+ * split-K reduction are excluded; operands are zero).  Either output may be
+ * NULL.  Synchronises the stream. */
+enmf_status enmf_time_products(enmf_ctx* ctx, const enmf_matrix* X, int32_t k, int32_t reps,
+                               double* xv_ms_host, double* xtu_ms_host);
 
 #ifdef __cplusplus
 }

@@ -638,4 +638,46 @@ enmf_status enmf_objective_kkt(enmf_ctx* c, const enmf_matrix* X, int32_t r, con
   return ENMF_OK;
 }
 
+enmf_status enmf_time_products(enmf_ctx* c, const enmf_matrix* X, int32_t k, int32_t reps,
+                               double* xv_ms, double* xtu_ms) {
+  TRY(check_ctx(c));
+  TRY(check_matrix(c, X));
+  if (k < 1 || k > ENMF_MAX_WIDTH || reps < 1) return fail(c, ENMF_EINVAL, "bad k or reps");
+  hipStream_t s = c->stream;
+  const int64_t m = X->m, n = X->n;
+  const int kp = pad_width(k);
+  const int64_t rows_pad = round_up(n, xv_tile_width(X->dtype));
+  WS(Bp, float, S_BP, rows_pad * kp * 4);
+  WS(Ap, float, S_AP, m * kp * 4);
+  WS(P, float, S_P, m * k * 4);
+  WS(Q, float, S_Q, n * k * 4);
+  const int sx = xv_splits(m, n, X->dtype), su = xtu_splits(m, n);
+  const int64_t bx = (int64_t)sx * m * k * 4, bu = (int64_t)su * n * k * 4;
+  WS(part, float, S_SPLIT, bx > bu ? bx : bu);
+  CK(hipMemsetAsync(Bp, 0, rows_pad * kp * 4, s));
+  CK(hipMemsetAsync(Ap, 0, m * kp * 4, s));
+  hipEvent_t e0, e1, e2;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  CK(hipEventCreate(&e2));
+  // one untimed launch of each first
+  CK(launch_xv(X->data, X->dtype, m, n, X->ld, Bp, k, kp, sx, part, P, s, 0));
+  CK(launch_xtu(X->data, X->dtype, m, n, X->ld, Ap, k, kp, su, part, Q, s, 0));
+  CK(hipEventRecord(e0, s));
+  for (int i = 0; i < reps; ++i) CK(launch_xv(X->data, X->dtype, m, n, X->ld, Bp, k, kp, sx, part, P, s, 0));
+  CK(hipEventRecord(e1, s));
+  for (int i = 0; i < reps; ++i) CK(launch_xtu(X->data, X->dtype, m, n, X->ld, Ap, k, kp, su, part, Q, s, 0));
+  CK(hipEventRecord(e2, s));
+  CK(hipEventSynchronize(e2));
+  float a = 0.f, b = 0.f;
+  CK(hipEventElapsedTime(&a, e0, e1));
+  CK(hipEventElapsedTime(&b, e1, e2));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  if (xv_ms) *xv_ms = a / reps;
+  if (xtu_ms) *xtu_ms = b / reps;
+  return ENMF_OK;
+}
+
 }  // extern "C"

@@ -70,10 +70,11 @@ hipError_t launch_pad_rows_cols(const float* in, int64_t rows_in, int k, int kp,
                                 float* out, hipStream_t s);
 hipError_t launch_pad_cols_f64(const float* in, int64_t rows, int k, int kp, double* out,
                                hipStream_t s);
+// `reduce` = 0 launches only the streaming kernel (split partials are left in part).
 hipError_t launch_xv(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* Bp, int k,
-                     int kp, int splits, float* part, float* out, hipStream_t s);
+                     int kp, int splits, float* part, float* out, hipStream_t s, int reduce = 1);
 hipError_t launch_xtu(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* Ap, int k,
-                      int kp, int splits, float* part, float* out, hipStream_t s);
+                      int kp, int splits, float* part, float* out, hipStream_t s, int reduce = 1);
 hipError_t launch_residual(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const double* Ud,
                            const float* V, int r, double* part, int* nparts, hipStream_t s);
 hipError_t launch_sumsq_x(const void* X, int xt, int64_t m, int64_t n, int64_t ld, double* part,

@@ -88,6 +88,8 @@ SIGNATURES = [
                                POINTER(IterOpts), POINTER(IterReport), c_void_p, c_int32]),
     ("enmf_objective_kkt", c_int32, [c_void_p, POINTER(Matrix), c_int32, c_void_p, c_void_p,
                                      c_double, POINTER(Kkt)]),
+    ("enmf_time_products", c_int32, [c_void_p, POINTER(Matrix), c_int32, c_int32,
+                                     POINTER(c_double), POINTER(c_double)]),
 ]
 
 
@@ -257,6 +259,13 @@ class Context:
         k = Kkt()
         self._call(self._lib.enmf_objective_kkt, byref(M), r, _ptr(U), _ptr(V), relerr_svd, byref(k))
         return {name: getattr(k, name) for name, _ in Kkt._fields_}
+
+    def time_products(self, X, k, reps=20):
+        """Average device ms per launch of the X B and X^T A streaming kernels."""
+        M = matrix(X)
+        a, b = c_double(), c_double()
+        self._call(self._lib.enmf_time_products, byref(M), k, reps, byref(a), byref(b))
+        return a.value, b.value
 
     def solve(self, X, r, omega, oversample=10, power_iters=2, rho0=1.0, rot_max_iter=100,
               rot_tol=1e-10, **iter_opts):
