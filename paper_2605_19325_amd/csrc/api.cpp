@@ -34,6 +34,7 @@ struct enmf_ctx {
   Buf bufs[N_SLOTS];
   DevState* st = nullptr;
   double ns_per_tick = 10.0;
+  bool use_mfma = true;   // ENMF_FORCE_VALU=1 at creation selects the vector-ALU products
 };
 
 namespace {
@@ -102,8 +103,33 @@ enmf_status check_matrix(enmf_ctx* c, const enmf_matrix* X) {
 
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+bool use_mfma(const enmf_ctx* c, const enmf_matrix* X, int k) {
+  return c->use_mfma && mfma_eligible(X->dtype, k);
+}
+
+// Split-partial bytes needed by either form of the products at width k.
+size_t split_bytes(const enmf_ctx* c, const enmf_matrix* X, int k) {
+  size_t a = 0, b = 0, pa = 0, pb = 0;
+  if (use_mfma(c, X, k)) {
+    mfma_xv_ws(X->dtype, X->m, X->n, k, &pa, &a);
+    mfma_xtu_ws(X->dtype, X->m, X->n, k, &pb, &b);
+  } else {
+    a = (size_t)xv_splits(X->m, X->n, X->dtype) * X->m * k * 4;
+    b = (size_t)xtu_splits(X->m, X->n) * X->n * k * 4;
+  }
+  return a > b ? a : b;
+}
+
 // P = X B (B: n x k, ld k).
 enmf_status do_xv(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, float* P) {
+  if (use_mfma(c, X, k)) {
+    size_t pb = 0, sb = 0;
+    mfma_xv_ws(X->dtype, X->m, X->n, k, &pb, &sb);
+    WS(pack, void, S_BP, pb);
+    WS(part, float, S_SPLIT, sb);
+    CK(launch_xv_mfma(X->data, X->dtype, X->m, X->n, X->ld, B, k, pack, part, P, c->stream, 1, 1));
+    return ENMF_OK;
+  }
   const int kp = pad_width(k);
   const int64_t rows_pad = round_up(X->n, xv_tile_width(X->dtype));
   WS(Bp, float, S_BP, rows_pad * kp * 4);
@@ -120,6 +146,14 @@ enmf_status do_xv(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, floa
 
 // Q = X^T A (A: m x k, ld k).
 enmf_status do_xtu(enmf_ctx* c, const enmf_matrix* X, const float* A, int k, float* Q) {
+  if (use_mfma(c, X, k)) {
+    size_t pb = 0, sb = 0;
+    mfma_xtu_ws(X->dtype, X->m, X->n, k, &pb, &sb);
+    WS(pack, void, S_AP, pb);
+    WS(part, float, S_SPLIT, sb);
+    CK(launch_xtu_mfma(X->data, X->dtype, X->m, X->n, X->ld, A, k, pack, part, Q, c->stream, 1, 1));
+    return ENMF_OK;
+  }
   const int kp = pad_width(k);
   WS(Ap, float, S_AP, X->m * kp * 4);
   CK(launch_pad_cols(A, X->m, k, kp, Ap, c->stream));
@@ -232,6 +266,8 @@ enmf_status enmf_create(enmf_ctx** out, int32_t device, void* hip_stream) {
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
     c->ns_per_tick = 1e6 / (double)khz;
+  const char* fv = std::getenv("ENMF_FORCE_VALU");
+  c->use_mfma = !(fv && fv[0] == '1');
   *out = c;
   return ENMF_OK;
 }
@@ -374,6 +410,7 @@ enmf_status enmf_rotate(enmf_ctx* c, int64_t m, int64_t n, int32_t r, float* U, 
   WS(wsq, double, S_WSQ, 512 * 8);
   const int nbm = gram_blocks(N);
   WS(mpart, double, S_MPART, (int64_t)nbm * r * r * 8);
+  WS(Mf, double, S_C, kp * kp * 8);
   WS(stat, double, S_STAT, 4 * 512 * 8);
   WS(tot, double, S_SIG, 64 * 8);
 
@@ -398,7 +435,8 @@ enmf_status enmf_rotate(enmf_ctx* c, int64_t m, int64_t n, int32_t r, float* U, 
   for (int t = 0; t < d.max_iter; ++t) {
     CK(launch_admm_rows(W, N, r, kp, R, Ya, Za, Ba, c->st, t, negp, s));
     CK(launch_tsgram(W, 1, kp, Ba, 1, kp, N, r, r, mpart, 0, nbm, s));
-    CK(launch_polar(mpart, nbm, r, kp, R, c->st, s));
+    CK(launch_gram_finalize(mpart, nbm, r, r, kp, Mf, s));
+    CK(launch_polar(Mf, r, kp, R, c->st, s));
     steps = t + 1;
     if (d.tol > 0.0 && (steps % d.check_every == 0)) {
       double dR = 0.0;
@@ -441,14 +479,14 @@ enmf_status iter_setup(enmf_ctx* c, const enmf_matrix* X, int r, const float* U,
                        const enmf_iter_opts& o, IterBufs& b) {
   hipStream_t s = c->stream;
   const int64_t m = X->m, n = X->n;
-  const int kp = pad_width(r);
+  const int kp = row_pad(r);
   WS(P, float, S_P, m * r * 4);
   WS(Q, float, S_Q, n * r * 4);
   WS(G, double, S_G, kp * kp * 8);
   WS(H, double, S_H, kp * kp * 8);
   b.P = P; b.Q = Q; b.G = G; b.H = H;
-  b.nbU = rowupdate_blocks(m);
-  b.nbV = rowupdate_blocks(n);
+  b.nbU = rowupdate_blocks(m, kp);
+  b.nbV = rowupdate_blocks(n, kp);
   WS(rup, double, S_RUPART, 3 * (int64_t)(b.nbU + b.nbV) * 8);
   WS(chk, double, S_CHK, (int64_t)kCheckFields * (b.nbU + b.nbV) * 8);
   b.rupart = rup; b.chk = chk;
@@ -460,11 +498,16 @@ enmf_status iter_setup(enmf_ctx* c, const enmf_matrix* X, int r, const float* U,
   // pre-size the shared split buffers so the loop never reallocates
   const int kpw = pad_width(r);
   const int64_t rows_pad = round_up(n, xv_tile_width(X->dtype));
-  if (!ws(c, S_BP, rows_pad * kpw * 4) || !ws(c, S_AP, m * kpw * 4))
+  size_t pbx = (size_t)rows_pad * kpw * 4, pbu = (size_t)m * kpw * 4;
+  if (use_mfma(c, X, r)) {
+    size_t t = 0;
+    mfma_xv_ws(X->dtype, m, n, r, &pbx, &t);
+    mfma_xtu_ws(X->dtype, m, n, r, &pbu, &t);
+  }
+  if (!ws(c, S_BP, pbx) || !ws(c, S_AP, pbu))
     return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
-  const int64_t sx = (int64_t)xv_splits(m, n, X->dtype) * m * r * 4;
-  const int64_t su = (int64_t)xtu_splits(m, n) * n * r * 4;
-  if (!ws(c, S_SPLIT, sx > su ? sx : su)) return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
+  if (!ws(c, S_SPLIT, split_bytes(c, X, r)))
+    return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
   if (!ws(c, S_GPART, (int64_t)gram_blocks(m > n ? m : n) * r * r * 8))
     return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
 
@@ -514,7 +557,7 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
   if (o.mode != 0 && o.mode != 1 && o.mode != 3) return fail(c, ENMF_EINVAL, "unsupported mode");
   if (trace && trace_cap < 0) return fail(c, ENMF_EINVAL, "bad trace capacity");
   hipStream_t s = c->stream;
-  const int kp = pad_width(r);
+  const int kp = row_pad(r);
   if (o.mode == 1) {
     CK(launch_clip(U, m * r, s));
     CK(launch_clip(V, n * r, s));
@@ -600,7 +643,7 @@ enmf_status enmf_objective_kkt(enmf_ctx* c, const enmf_matrix* X, int32_t r, con
   const int64_t m = X->m, n = X->n;
   if (r < 1 || r > ENMF_MAX_RANK || r > m || r > n) return fail(c, ENMF_EINVAL, "r out of range");
   hipStream_t s = c->stream;
-  const int kp = pad_width(r);
+  const int kp = row_pad(r);
   enmf_iter_opts o;
   std::memset(&o, 0, sizeof(o));
   o.kkt_tol = -1.0;
@@ -646,27 +689,42 @@ enmf_status enmf_time_products(enmf_ctx* c, const enmf_matrix* X, int32_t k, int
   hipStream_t s = c->stream;
   const int64_t m = X->m, n = X->n;
   const int kp = pad_width(k);
+  const bool mf = use_mfma(c, X, k);
   const int64_t rows_pad = round_up(n, xv_tile_width(X->dtype));
-  WS(Bp, float, S_BP, rows_pad * kp * 4);
-  WS(Ap, float, S_AP, m * kp * 4);
+  size_t pbx = (size_t)rows_pad * kp * 4, pbu = (size_t)m * kp * 4, t = 0;
+  if (mf) {
+    mfma_xv_ws(X->dtype, m, n, k, &pbx, &t);
+    mfma_xtu_ws(X->dtype, m, n, k, &pbu, &t);
+  }
+  WS(Bp, float, S_BP, pbx);
+  WS(Ap, float, S_AP, pbu);
   WS(P, float, S_P, m * k * 4);
   WS(Q, float, S_Q, n * k * 4);
+  WS(Z, float, S_Z, (m > n ? m : n) * k * 4);
+  WS(part, float, S_SPLIT, split_bytes(c, X, k));
+  CK(hipMemsetAsync(Z, 0, (m > n ? m : n) * k * 4, s));
+  CK(hipMemsetAsync(Bp, 0, pbx, s));
+  CK(hipMemsetAsync(Ap, 0, pbu, s));
   const int sx = xv_splits(m, n, X->dtype), su = xtu_splits(m, n);
-  const int64_t bx = (int64_t)sx * m * k * 4, bu = (int64_t)su * n * k * 4;
-  WS(part, float, S_SPLIT, bx > bu ? bx : bu);
-  CK(hipMemsetAsync(Bp, 0, rows_pad * kp * 4, s));
-  CK(hipMemsetAsync(Ap, 0, m * kp * 4, s));
+  auto run_xv = [&](int pack) {
+    return mf ? launch_xv_mfma(X->data, X->dtype, m, n, X->ld, Z, k, Bp, part, P, s, 0, pack)
+              : launch_xv(X->data, X->dtype, m, n, X->ld, Bp, k, kp, sx, part, P, s, 0);
+  };
+  auto run_xtu = [&](int pack) {
+    return mf ? launch_xtu_mfma(X->data, X->dtype, m, n, X->ld, Z, k, Ap, part, Q, s, 0, pack)
+              : launch_xtu(X->data, X->dtype, m, n, X->ld, Ap, k, kp, su, part, Q, s, 0);
+  };
   hipEvent_t e0, e1, e2;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
   CK(hipEventCreate(&e2));
-  // one untimed launch of each first
-  CK(launch_xv(X->data, X->dtype, m, n, X->ld, Bp, k, kp, sx, part, P, s, 0));
-  CK(launch_xtu(X->data, X->dtype, m, n, X->ld, Ap, k, kp, su, part, Q, s, 0));
+  // one untimed launch of each first (packs the zero operand)
+  CK(run_xv(1));
+  CK(run_xtu(1));
   CK(hipEventRecord(e0, s));
-  for (int i = 0; i < reps; ++i) CK(launch_xv(X->data, X->dtype, m, n, X->ld, Bp, k, kp, sx, part, P, s, 0));
+  for (int i = 0; i < reps; ++i) CK(run_xv(0));
   CK(hipEventRecord(e1, s));
-  for (int i = 0; i < reps; ++i) CK(launch_xtu(X->data, X->dtype, m, n, X->ld, Ap, k, kp, su, part, Q, s, 0));
+  for (int i = 0; i < reps; ++i) CK(run_xtu(0));
   CK(hipEventRecord(e2, s));
   CK(hipEventSynchronize(e2));
   float a = 0.f, b = 0.f;

@@ -84,6 +84,17 @@ hipError_t launch_sum_parts(const double* part, int nparts, int stride, int nfie
 hipError_t launch_convert(const float* x, int64_t m, int64_t n, int64_t ldi, int to, void* out,
                           int64_t ldo, hipStream_t s);
 
+// k_mfma.hip (matrix-core products, k >= 16, float32 or bfloat16 X)
+bool mfma_eligible(int xt, int k);
+void mfma_xv_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes);
+void mfma_xtu_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes);
+hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* B,
+                          int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
+                          int do_pack);
+hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* A,
+                           int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
+                           int do_pack);
+
 // k_small.hip
 int gram_blocks(int64_t rows);
 hipError_t launch_tsgram(const void* A, int a_is_f64, int64_t lda, const void* B, int b_is_f64,
@@ -107,12 +118,14 @@ hipError_t launch_rho_init(const double* part, int nparts, int64_t N, int r, dou
 hipError_t launch_admm_rows(const double* W, int64_t N, int r, int kp, const double* R, double* Y,
                             double* Z, double* B, DevState* st, int step, double* negpart,
                             hipStream_t s);
-hipError_t launch_polar(const double* Mpart, int nparts, int r, int kp, double* R, DevState* st,
-                        hipStream_t s);
+// R <- polar factor of Mf (r x r, leading dimension kp); R is kp x kp.
+hipError_t launch_polar(const double* Mf, int r, int kp, double* R, DevState* st, hipStream_t s);
 
 // k_update.hip
 int factor_blocks(int64_t count);
-int rowupdate_blocks(int64_t rows);
+// Padded width of the r x r Grams consumed by the row-update and check kernels.
+int row_pad(int r);
+int rowupdate_blocks(int64_t rows, int kp);
 hipError_t launch_factor_stats(const float* A, int64_t count, int r, double* part, int block_offset,
                                int nblocks, hipStream_t s);
 hipError_t launch_setup_state2(const double* statpart, int nbU, int nbV, const double* xpart,

@@ -1,0 +1,688 @@
+// Matrix-core (MFMA) forms of the X-streaming products for ranks >= 16,
+// where each product is a real dense contraction (appendix on complexity:
+// X V and X^T U, O(mnr) per half-iteration).
+//
+//   float32 X: v_mfma_f32_16x16x4_f32, float32 accumulate.
+//   bfloat16 X: v_mfma_f32_16x16x32_bf16, float32 accumulate, with the float32
+//     factor split into three bfloat16 terms (hi = rne(v), mid = rne(v - hi),
+//     lo = rne(v - hi - mid), |v - hi - mid - lo| <= 2^-24 |v|), so that
+//     X . v = X . hi + X . mid + X . lo keeps the factor to float32 precision
+//     (the split-precision refinement of Henry et al. 2019); X itself is exact.
+//
+// MFMA 16x16 tiles on gfx950 (wave64): lane l = 16 g + i (i = l % 16,
+// g = l / 16).  16x16x4 f32: A operand = A[i][g], B operand = B[g][i].
+// 16x16x32 bf16: A = A[i][8g .. 8g+7], B = B[8g .. 8g+7][i].  Result:
+// D[4g + v][i] in accumulator element v.  The contraction index of a tile is
+// free to be permuted as long as A and B agree, which lets every lane load
+// contiguous runs of a row of X.
+//
+// X V  : lanes take rows of X (16 per tile); the factor chunk sits in LDS.
+// X^T U: lanes take 16-byte runs along a row of X; a tile covers a strided
+//        set of 16 columns.  For bfloat16 the 8 x 8 blocks are transposed
+//        in registers (v_perm) so that each lane holds 8 rows of one column.
+// Both split the contraction over blocks; partials are reduced in fixed
+// order by the caller.
+#include <stdint.h>
+
+#include "dev_common.h"
+#include "enmf_internal.h"
+
+namespace enmf {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kT = 256;
+
+__device__ __forceinline__ f32x4 zero4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x0040u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(const uint4& q) { return __builtin_bit_cast(bf16x8, q); }
+
+// Zero the elements of a vector of E elements starting at column col that are >= n.
+template <typename ET>
+__device__ __forceinline__ uint4 mask_cols(uint4 q, int64_t col, int64_t n) {
+  constexpr int E = 16 / sizeof(ET);
+  if (col + E <= n) return q;
+  unsigned w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (col + e >= n) {
+      if constexpr (sizeof(ET) == 4) w[e] = 0u;
+      else w[e / 2] &= (e & 1) ? 0x0000ffffu : 0xffff0000u;
+    }
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// 16 bytes of row `row` of X starting at column col (zero outside the matrix).
+template <typename ET>
+__device__ __forceinline__ uint4 load16(const ET* __restrict__ X, int64_t rows, int64_t n,
+                                        int64_t ld, int64_t row, int64_t col, bool vec) {
+  constexpr int E = 16 / sizeof(ET);
+  if (row >= rows || col >= n) return make_uint4(0u, 0u, 0u, 0u);
+  const ET* src = X + row * ld + col;
+  if (vec) return mask_cols<ET>(*reinterpret_cast<const uint4*>(src), col, n);
+  unsigned w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (col + e < n) {
+      if constexpr (sizeof(ET) == 4) w[e] = __float_as_uint(src[e]);
+      else w[e / 2] |= ((unsigned)src[e]) << (16 * (e & 1));
+    }
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Store a 16x16 accumulator tile: element v of lane (i, g) is D[4g + v][i],
+// written to out[(row_of(4g+v)) * k + col0 + i].
+__device__ __forceinline__ void store_tile_rows(float* __restrict__ out, int64_t m, int k,
+                                                int64_t row0, int col0, const f32x4& d) {
+  const int lane = threadIdx.x % kWave;
+  const int i = lane % 16, g = lane / 16;
+  const int col = col0 + i;
+  if (col >= k) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t row = row0 + 4 * g + v;
+    if (row < m) out[row * k + col] = d[v];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// float32 X: P = X B.  Block = 4 waves x 64 rows; chunk = 32 columns of X.
+// Lane (i, g) of row tile rt loads X[row0 + 16 rt + i][kc + 8g .. 8g+7]; MFMA
+// step s (0..7) contracts column kc + 8g + s, whose B operand is
+// Bs[8g + s][16 jt + i] from the LDS copy of the chunk of B.
+// ---------------------------------------------------------------------------
+template <int KP>
+__global__ __launch_bounds__(kT) void k_xv_f32(const float* __restrict__ X, int64_t m, int64_t n,
+                                               int64_t ld, const float* __restrict__ Bp, int k,
+                                               int chunks_per_split, int64_t nchunks, int vec,
+                                               float* __restrict__ out, int64_t split_stride) {
+  constexpr int NT = KP / 16;
+  constexpr int RT = 4;
+  constexpr int C = 32;
+  constexpr int LDB = KP + 2;
+  __shared__ float Bs[2][C * LDB];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int i = lane % 16, g = lane / 16;
+  const int64_t row0 = (int64_t)blockIdx.x * (4 * 64) + 64 * w;
+  const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
+  const int64_t c1 = c0 + chunks_per_split < nchunks ? c0 + chunks_per_split : nchunks;
+
+  f32x4 acc[RT][NT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int jt = 0; jt < NT; ++jt) acc[rt][jt] = zero4();
+
+  uint4 xa[RT][2], xb[RT][2];
+  auto load_x = [&](int64_t ch, uint4 (&dst)[RT][2]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        dst[rt][h] = load16<float>(X, m, n, ld, row0 + 16 * rt + i, ch * C + 8 * g + 4 * h, vec != 0);
+  };
+  auto load_b = [&](int64_t ch, int buf) {
+    for (int e = threadIdx.x; e < C * KP; e += kT) {
+      const int kr = e / KP, col = e % KP;
+      Bs[buf][kr * LDB + col] = Bp[(ch * C + kr) * KP + col];
+    }
+  };
+  if (c0 < c1) {
+    load_x(c0, xa);
+    load_b(c0, 0);
+  }
+  int buf = 0;
+  for (int64_t ch = c0; ch < c1; ++ch) {
+    __syncthreads();
+    const bool more = ch + 1 < c1;
+    if (more) {
+      load_x(ch + 1, xb);
+      load_b(ch + 1, buf ^ 1);
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      float bv[NT];
+#pragma unroll
+      for (int jt = 0; jt < NT; ++jt) bv[jt] = Bs[buf][(8 * g + s) * LDB + 16 * jt + i];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const uint4 q = xa[rt][s / 4];
+        const unsigned wv = (s % 4 == 0) ? q.x : (s % 4 == 1) ? q.y : (s % 4 == 2) ? q.z : q.w;
+        const float a = __uint_as_float(wv);
+#pragma unroll
+        for (int jt = 0; jt < NT; ++jt)
+          acc[rt][jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[jt], acc[rt][jt], 0, 0, 0);
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) { xa[rt][0] = xb[rt][0]; xa[rt][1] = xb[rt][1]; }
+    }
+    buf ^= 1;
+  }
+  float* o = out + (int64_t)blockIdx.y * split_stride;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int jt = 0; jt < NT; ++jt) store_tile_rows(o, m, k, row0 + 16 * rt, 16 * jt, acc[rt][jt]);
+}
+
+// ---------------------------------------------------------------------------
+// float32 X: Q = X^T A.  Block = 4 waves x 128 columns; chunk = 16 rows of X
+// (4 MFMA steps of 4 rows).  Lane (i, g) loads X[r][j0 + 64h + 4i .. +3] for
+// the row r = 4 kk + g of step kk; tile (h, t) holds columns
+// j0 + 64h + 4 mm + t (mm = 0..15).  B operand = As[4 kk + g][16 nt + i].
+// ---------------------------------------------------------------------------
+template <int KP>
+__global__ __launch_bounds__(kT) void k_xtu_f32(const float* __restrict__ X, int64_t m, int64_t n,
+                                                int64_t ld, const float* __restrict__ Ap, int k,
+                                                int64_t rows_per_split, int vec,
+                                                float* __restrict__ out, int64_t split_stride) {
+  constexpr int NT = KP / 16;
+  constexpr int C = 16;
+  constexpr int LDA = KP + 16;
+  __shared__ float As[2][C * LDA];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int i = lane % 16, g = lane / 16;
+  const int64_t j0 = (int64_t)blockIdx.x * (4 * 128) + 128 * w;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t r1 = r0 + rows_per_split < m ? r0 + rows_per_split : m;
+
+  f32x4 acc[8][NT];
+#pragma unroll
+  for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = zero4();
+
+  uint4 xa[4][2], xb[4][2];
+  auto load_x = [&](int64_t rc, uint4 (&dst)[4][2]) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int64_t row = rc + 4 * kk + g;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        dst[kk][h] = load16<float>(X, row < r1 ? m : 0, n, ld, row, j0 + 64 * h + 4 * i, vec != 0);
+    }
+  };
+  auto load_a = [&](int64_t rc, int buf) {
+    for (int e = threadIdx.x; e < C * KP; e += kT) {
+      const int kr = e / KP, col = e % KP;
+      const int64_t row = rc + kr;
+      As[buf][kr * LDA + col] = row < r1 ? Ap[row * KP + col] : 0.f;
+    }
+  };
+  if (r0 < r1) {
+    load_x(r0, xa);
+    load_a(r0, 0);
+  }
+  int buf = 0;
+  for (int64_t rc = r0; rc < r1; rc += C) {
+    __syncthreads();
+    const bool more = rc + C < r1;
+    if (more) {
+      load_x(rc + C, xb);
+      load_a(rc + C, buf ^ 1);
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      float bv[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) bv[nt] = As[buf][(4 * kk + g) * LDA + 16 * nt + i];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint4 q = xa[kk][h];
+        const float av[4] = {__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z),
+                             __uint_as_float(q.w)};
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            acc[4 * h + t][nt] =
+                __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[nt], acc[4 * h + t][nt], 0, 0, 0);
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) { xa[kk][0] = xb[kk][0]; xa[kk][1] = xb[kk][1]; }
+    }
+    buf ^= 1;
+  }
+  // element v of lane (i, g) in tile (h, t) is column j0 + 64h + 4 (4g + v) + t, factor column 16 nt + i
+  float* o = out + (int64_t)blockIdx.y * split_stride;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int col = 16 * nt + i;
+        if (col < k) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t j = j0 + 64 * h + 4 * (4 * g + v) + t;
+            if (j < n) o[j * k + col] = acc[4 * h + t][nt][v];
+          }
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// bfloat16 X: P = X B with B = Bhi + Bmid + Blo.  Block = 4 waves x 64 rows; chunk =
+// 64 columns of X (two MFMA steps of 32).  Lane (i, g) of row tile rt loads
+// X[row0 + 16 rt + i][kc + 32 s + 8g .. +7] (one A operand per step s).  The
+// B operand is Bt[part][16 nt + i][32 s + 8g .. +7] of the LDS copy of the
+// chunk, stored transposed (factor column major) with rows padded to 72.
+// ---------------------------------------------------------------------------
+constexpr int kBtLd = 72;   // padded LDS row (elements) of the transposed factor chunk, 64 rows
+
+template <int KP>
+__global__ __launch_bounds__(kT) void k_xv_bf16(const unsigned short* __restrict__ X, int64_t m,
+                                                int64_t n, int64_t ld,
+                                                const unsigned short* __restrict__ Bt, int k,
+                                                int chunks_per_split, int64_t nchunks, int vec,
+                                                float* __restrict__ out, int64_t split_stride) {
+  constexpr int NT = KP / 16;
+  constexpr int RT = 4;
+  constexpr int CH = 3 * KP * kBtLd;   // elements of one packed chunk (hi, mid, lo)
+  __shared__ __align__(16) unsigned short Bs[2][CH];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int i = lane % 16, g = lane / 16;
+  const int64_t row0 = (int64_t)blockIdx.x * (4 * 64) + 64 * w;
+  const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
+  const int64_t c1 = c0 + chunks_per_split < nchunks ? c0 + chunks_per_split : nchunks;
+
+  f32x4 acc[RT][NT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = zero4();
+
+  uint4 xa[RT][2], xb[RT][2];
+  auto load_x = [&](int64_t ch, uint4 (&dst)[RT][2]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+        dst[rt][s] = load16<unsigned short>(X, m, n, ld, row0 + 16 * rt + i, ch * 64 + 32 * s + 8 * g,
+                                            vec != 0);
+  };
+  auto load_b = [&](int64_t ch, int buf) {
+    const uint4* src = reinterpret_cast<const uint4*>(Bt + ch * CH);
+    uint4* dst = reinterpret_cast<uint4*>(Bs[buf]);
+    for (int e = threadIdx.x; e < CH / 8; e += kT) dst[e] = src[e];
+  };
+  if (c0 < c1) {
+    load_x(c0, xa);
+    load_b(c0, 0);
+  }
+  int buf = 0;
+  for (int64_t ch = c0; ch < c1; ++ch) {
+    __syncthreads();
+    const bool more = ch + 1 < c1;
+    if (more) {
+      load_x(ch + 1, xb);
+      load_b(ch + 1, buf ^ 1);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+        for (int hl = 0; hl < 3; ++hl) {
+          const uint4 bq = *reinterpret_cast<const uint4*>(
+              &Bs[buf][(hl * KP + 16 * nt + i) * kBtLd + 32 * s + 8 * g]);
+          const bf16x8 b = as_bf16x8(bq);
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt)
+            acc[rt][nt] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(xa[rt][s]), b, acc[rt][nt], 0, 0, 0);
+        }
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) { xa[rt][0] = xb[rt][0]; xa[rt][1] = xb[rt][1]; }
+    }
+    buf ^= 1;
+  }
+  float* o = out + (int64_t)blockIdx.y * split_stride;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) store_tile_rows(o, m, k, row0 + 16 * rt, 16 * nt, acc[rt][nt]);
+}
+
+// ---------------------------------------------------------------------------
+// bfloat16 X: Q = X^T A with A = Ahi + Amid + Alo.  Block = 4 waves x 128 columns;
+// chunk = 32 rows (one MFMA step).  Lane (i, g) loads the 8 x 8 block
+// X[rc + 8g + e][j0 + 8i .. 8i+7] (e = 0..7) and transposes it in registers:
+// operand t holds X[rc + 8g + 0..7][j0 + 8i + t], so tile t covers columns
+// j0 + 8 mm + t.  B operand = At[part][16 nt + i][8g .. 8g+7] (transposed
+// chunk in LDS, rows padded to 40).
+// ---------------------------------------------------------------------------
+constexpr int kAtLd = 40;
+
+template <int KP>
+__global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restrict__ X, int64_t m,
+                                                 int64_t n, int64_t ld,
+                                                 const unsigned short* __restrict__ At, int k,
+                                                 int64_t chunks_per_split, int64_t nchunks, int vec,
+                                                 float* __restrict__ out, int64_t split_stride) {
+  constexpr int NT = KP / 16;
+  constexpr int CH = 3 * KP * kAtLd;
+  __shared__ __align__(16) unsigned short As[2][CH];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int i = lane % 16, g = lane / 16;
+  const int64_t j0 = (int64_t)blockIdx.x * (4 * 128) + 128 * w;
+  const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
+  const int64_t c1 = c0 + chunks_per_split < nchunks ? c0 + chunks_per_split : nchunks;
+
+  f32x4 acc[8][NT];
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[t][nt] = zero4();
+
+  uint4 xa[8], xb[8];
+  auto load_x = [&](int64_t ch, uint4 (&dst)[8]) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      dst[e] = load16<unsigned short>(X, m, n, ld, ch * 32 + 8 * g + e, j0 + 8 * i, vec != 0);
+  };
+  auto load_a = [&](int64_t ch, int buf) {
+    const uint4* src = reinterpret_cast<const uint4*>(At + ch * CH);
+    uint4* dst = reinterpret_cast<uint4*>(As[buf]);
+    for (int e = threadIdx.x; e < CH / 8; e += kT) dst[e] = src[e];
+  };
+  if (c0 < c1) {
+    load_x(c0, xa);
+    load_a(c0, 0);
+  }
+  int buf = 0;
+  for (int64_t ch = c0; ch < c1; ++ch) {
+    __syncthreads();
+    const bool more = ch + 1 < c1;
+    if (more) {
+      load_x(ch + 1, xb);
+      load_a(ch + 1, buf ^ 1);
+    }
+    // transpose: op[t] dword d = (X[2d][t], X[2d+1][t]) of the lane's 8 x 8 block
+    uint4 op[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      unsigned d[4];
+#pragma unroll
+      for (int dd = 0; dd < 4; ++dd) {
+        const uint4& lo = xa[2 * dd];
+        const uint4& hi = xa[2 * dd + 1];
+        const unsigned a = (t / 2 == 0) ? lo.x : (t / 2 == 1) ? lo.y : (t / 2 == 2) ? lo.z : lo.w;
+        const unsigned b = (t / 2 == 0) ? hi.x : (t / 2 == 1) ? hi.y : (t / 2 == 2) ? hi.z : hi.w;
+        // low halves (t even) or high halves (t odd) of a and b, a in the low half of the result
+        d[dd] = (t % 2 == 0) ? __builtin_amdgcn_perm(b, a, 0x05040100u)
+                             : __builtin_amdgcn_perm(b, a, 0x07060302u);
+      }
+      op[t] = make_uint4(d[0], d[1], d[2], d[3]);
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+      for (int hl = 0; hl < 3; ++hl) {
+        const uint4 bq =
+            *reinterpret_cast<const uint4*>(&As[buf][(hl * KP + 16 * nt + i) * kAtLd + 8 * g]);
+        const bf16x8 b = as_bf16x8(bq);
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          acc[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(op[t]), b, acc[t][nt], 0, 0, 0);
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xa[e] = xb[e];
+    }
+    buf ^= 1;
+  }
+  // element v of lane (i, g) in tile t is column j0 + 8 (4g + v) + t, factor column 16 nt + i
+  float* o = out + (int64_t)blockIdx.y * split_stride;
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int col = 16 * nt + i;
+      if (col < k) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t j = j0 + 8 * (4 * g + v) + t;
+          if (j < n) o[j * k + col] = acc[t][nt][v];
+        }
+      }
+    }
+}
+
+// Packs a float32 factor F (rows x k, leading dimension k) into transposed
+// bfloat16 hi/mid/lo chunks: out[ch][part][c][kr] (row stride ldt) = split
+// of F[ch * C + kr][c] for kr < C, c < KP (zero outside F).
+__global__ void k_pack_split_t(const float* __restrict__ F, int64_t rows, int k, int KP, int C,
+                               int ldt, int64_t nchunks, unsigned short* __restrict__ out) {
+  const int64_t count = nchunks * C * KP;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ch = e / ((int64_t)C * KP);
+    const int rem = (int)(e % ((int64_t)C * KP));
+    const int kr = rem / KP, c = rem % KP;
+    const int64_t row = ch * C + kr;
+    const float v = (row < rows && c < k) ? F[row * k + c] : 0.f;
+    const unsigned short hi = bf16_rne(v);
+    const float r1 = v - __uint_as_float((unsigned)hi << 16);
+    const unsigned short mid = bf16_rne(r1);
+    const unsigned short lo = bf16_rne(r1 - __uint_as_float((unsigned)mid << 16));
+    unsigned short* base = out + ch * (int64_t)(3 * KP * ldt);
+    base[(int64_t)c * ldt + kr] = hi;
+    base[(int64_t)(KP + c) * ldt + kr] = mid;
+    base[(int64_t)(2 * KP + c) * ldt + kr] = lo;
+  }
+}
+
+// out (rows_out x KP) = F (rows_in x k) zero padded, float32.
+__global__ void k_pad_f32(const float* __restrict__ F, int64_t rows_in, int k, int KP,
+                          int64_t rows_out, float* __restrict__ out) {
+  const int64_t count = rows_out * KP;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / KP;
+    const int c = (int)(e % KP);
+    out[e] = (r < rows_in && c < k) ? F[r * k + c] : 0.f;
+  }
+}
+
+__global__ void k_reduce(const float* __restrict__ part, int splits, int64_t stride,
+                         float* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < stride;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    float s = part[e];
+    for (int q = 1; q < splits; ++q) s += part[q * stride + e];
+    out[e] = s;
+  }
+}
+
+int grid_for(int64_t count) {
+  int64_t g = (count + 255) / 256;
+  if (g < 1) g = 1;
+  return (int)(g < 8192 ? g : 8192);
+}
+
+int mfma_kp(int k) { return k <= 16 ? 16 : k <= 32 ? 32 : k <= 48 ? 48 : k <= 64 ? 64 : 80; }
+
+bool aligned_rows(const void* X, int64_t ld, int esz) {
+  return (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((ld * esz) % 16 == 0);
+}
+
+// Number of contraction splits for a grid of `tiles` output blocks.
+int64_t choose_splits(int64_t tiles, int64_t units, int64_t min_units) {
+  int64_t s = (1536 + tiles - 1) / tiles;
+  const int64_t smax = (units + min_units - 1) / min_units;
+  if (s > smax) s = smax;
+  if (s < 1) s = 1;
+  return s;
+}
+
+}  // namespace
+
+bool mfma_eligible(int xt, int k) { return k >= 16 && k <= ENMF_MAX_WIDTH && (xt == ENMF_F32 || xt == ENMF_BF16); }
+
+// Workspace (bytes) of the MFMA products: packed factor and split partials.
+void mfma_xv_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes) {
+  const int KP = mfma_kp(k);
+  if (xt == ENMF_F32) {
+    const int64_t nch = (n + 31) / 32;
+    *pack_bytes = (size_t)(nch * 32) * KP * 4;
+    const int64_t s = choose_splits((m + 255) / 256, nch, 8);
+    *part_bytes = (size_t)s * m * k * 4;
+  } else {
+    const int64_t nch = (n + 63) / 64;
+    *pack_bytes = (size_t)nch * 3 * KP * kBtLd * 2;
+    const int64_t s = choose_splits((m + 255) / 256, nch, 4);
+    *part_bytes = (size_t)s * m * k * 4;
+  }
+}
+
+void mfma_xtu_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes) {
+  const int KP = mfma_kp(k);
+  const int64_t tiles = (n + 511) / 512;
+  if (xt == ENMF_F32) {
+    *pack_bytes = (size_t)m * KP * 4;
+    const int64_t s = choose_splits(tiles, (m + 15) / 16, 4);
+    *part_bytes = (size_t)s * n * k * 4;
+  } else {
+    const int64_t nch = (m + 31) / 32;
+    *pack_bytes = (size_t)nch * 3 * KP * kAtLd * 2;
+    const int64_t s = choose_splits(tiles, nch, 4);
+    *part_bytes = (size_t)s * n * k * 4;
+  }
+}
+
+// P = X B through the matrix cores.  pack and part are workspace of the
+// sizes given by mfma_xv_ws.  reduce = 0 leaves the split partials unsummed
+// (instrumentation).
+hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* B,
+                          int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
+                          int do_pack) {
+  const int KP = mfma_kp(k);
+  const int64_t rb = (m + 255) / 256;
+  const bool vec = aligned_rows(X, ld, xt == ENMF_F32 ? 4 : 2);
+  if (xt == ENMF_F32) {
+    const int64_t nch = (n + 31) / 32;
+    if (do_pack)
+      hipLaunchKernelGGL(k_pad_f32, dim3(grid_for(nch * 32 * KP)), dim3(256), 0, s, B, n, k, KP,
+                         nch * 32, (float*)pack);
+    const int64_t sp = choose_splits(rb, nch, 8);
+    const int64_t cps = (nch + sp - 1) / sp;
+    const int64_t eff = (nch + cps - 1) / cps;
+    float* dst = eff > 1 ? part : out;
+    dim3 grid((unsigned)rb, (unsigned)eff);
+    const float* Xf = reinterpret_cast<const float*>(X);
+    const float* Bp = reinterpret_cast<const float*>(pack);
+    switch (KP) {
+      case 16: hipLaunchKernelGGL((k_xv_f32<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bp, k, (int)cps, nch, (int)vec, dst, m * k); break;
+      case 32: hipLaunchKernelGGL((k_xv_f32<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bp, k, (int)cps, nch, (int)vec, dst, m * k); break;
+      case 48: hipLaunchKernelGGL((k_xv_f32<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bp, k, (int)cps, nch, (int)vec, dst, m * k); break;
+      case 64: hipLaunchKernelGGL((k_xv_f32<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bp, k, (int)cps, nch, (int)vec, dst, m * k); break;
+      default: hipLaunchKernelGGL((k_xv_f32<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bp, k, (int)cps, nch, (int)vec, dst, m * k); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || eff <= 1 || !reduce) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(grid_for(m * k)), dim3(256), 0, s, part, (int)eff, m * k, out);
+    return hipGetLastError();
+  }
+  const int64_t nch = (n + 63) / 64;
+  if (do_pack)
+    hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 64 * KP)), dim3(256), 0, s, B, n, k, KP, 64,
+                       kBtLd, nch, (unsigned short*)pack);
+  const int64_t sp = choose_splits(rb, nch, 4);
+  const int64_t cps = (nch + sp - 1) / sp;
+  const int64_t eff = (nch + cps - 1) / cps;
+  float* dst = eff > 1 ? part : out;
+  dim3 grid((unsigned)rb, (unsigned)eff);
+  const unsigned short* Xb = reinterpret_cast<const unsigned short*>(X);
+  const unsigned short* Bt = reinterpret_cast<const unsigned short*>(pack);
+  switch (KP) {
+    case 16: hipLaunchKernelGGL((k_xv_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
+    case 32: hipLaunchKernelGGL((k_xv_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
+    case 48: hipLaunchKernelGGL((k_xv_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
+    case 64: hipLaunchKernelGGL((k_xv_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
+    default: hipLaunchKernelGGL((k_xv_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || eff <= 1 || !reduce) return e;
+  hipLaunchKernelGGL(k_reduce, dim3(grid_for(m * k)), dim3(256), 0, s, part, (int)eff, m * k, out);
+  return hipGetLastError();
+}
+
+// Q = X^T A through the matrix cores (workspace from mfma_xtu_ws).
+hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* A,
+                           int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
+                           int do_pack) {
+  const int KP = mfma_kp(k);
+  const int64_t tiles = (n + 511) / 512;
+  const bool vec = aligned_rows(X, ld, xt == ENMF_F32 ? 4 : 2);
+  if (xt == ENMF_F32) {
+    if (do_pack)
+      hipLaunchKernelGGL(k_pad_f32, dim3(grid_for(m * KP)), dim3(256), 0, s, A, m, k, KP, m,
+                         (float*)pack);
+    const int64_t units = (m + 15) / 16;
+    const int64_t sp = choose_splits(tiles, units, 4);
+    const int64_t ups = (units + sp - 1) / sp;
+    const int64_t eff = (units + ups - 1) / ups;
+    const int64_t rps = ups * 16;
+    float* dst = eff > 1 ? part : out;
+    dim3 grid((unsigned)tiles, (unsigned)eff);
+    const float* Xf = reinterpret_cast<const float*>(X);
+    const float* Ap = reinterpret_cast<const float*>(pack);
+    switch (KP) {
+      case 16: hipLaunchKernelGGL((k_xtu_f32<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, Ap, k, rps, (int)vec, dst, n * k); break;
+      case 32: hipLaunchKernelGGL((k_xtu_f32<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, Ap, k, rps, (int)vec, dst, n * k); break;
+      case 48: hipLaunchKernelGGL((k_xtu_f32<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, Ap, k, rps, (int)vec, dst, n * k); break;
+      case 64: hipLaunchKernelGGL((k_xtu_f32<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, Ap, k, rps, (int)vec, dst, n * k); break;
+      default: hipLaunchKernelGGL((k_xtu_f32<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, Ap, k, rps, (int)vec, dst, n * k); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || eff <= 1 || !reduce) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(grid_for(n * k)), dim3(256), 0, s, part, (int)eff, n * k, out);
+    return hipGetLastError();
+  }
+  const int64_t nch = (m + 31) / 32;
+  if (do_pack)
+    hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 32 * KP)), dim3(256), 0, s, A, m, k, KP, 32,
+                       kAtLd, nch, (unsigned short*)pack);
+  const int64_t sp = choose_splits(tiles, nch, 4);
+  const int64_t cps = (nch + sp - 1) / sp;
+  const int64_t eff = (nch + cps - 1) / cps;
+  float* dst = eff > 1 ? part : out;
+  dim3 grid((unsigned)tiles, (unsigned)eff);
+  const unsigned short* Xb = reinterpret_cast<const unsigned short*>(X);
+  const unsigned short* At = reinterpret_cast<const unsigned short*>(pack);
+  switch (KP) {
+    case 16: hipLaunchKernelGGL((k_xtu_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
+    case 32: hipLaunchKernelGGL((k_xtu_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
+    case 48: hipLaunchKernelGGL((k_xtu_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
+    case 64: hipLaunchKernelGGL((k_xtu_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
+    default: hipLaunchKernelGGL((k_xtu_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || eff <= 1 || !reduce) return e;
+  hipLaunchKernelGGL(k_reduce, dim3(grid_for(n * k)), dim3(256), 0, s, part, (int)eff, n * k, out);
+  return hipGetLastError();
+}
+
+}  // namespace enmf

@@ -30,58 +30,75 @@ int grid_for(int64_t count, int threads = 256, int cap = 8192) {
 template <typename T> __device__ __forceinline__ double ld64(const T* p) { return (double)*p; }
 
 // part[block_offset + b][a * kb + c] = sum over the block's rows of A[i][a] * B[i][c].
-template <typename TA, typename TB>
+// Rows are staged through LDS 32 at a time as float64 (products of float32
+// inputs are exact); the 16 x 16 threads own a strided (KP/16) x (KP/16)
+// tile of the output, so each staged row costs 2 KP/16 LDS reads per
+// (KP/16)^2 FMAs.
+template <typename TA, typename TB, int KP>
 __global__ __launch_bounds__(kT) void k_tsgram(const TA* __restrict__ A, int64_t lda,
                                                const TB* __restrict__ B, int64_t ldb, int64_t rows,
                                                int ka, int kb, int64_t rows_per_block,
                                                double* __restrict__ part, int block_offset) {
-  constexpr int kTile = 32;
-  constexpr int kQ = (kMaxW * kMaxW + kT - 1) / kT;
-  __shared__ double sA[kTile][kMaxW];
-  __shared__ double sB[kTile][kMaxW];
-  const int ne = ka * kb;
+  constexpr int TT = KP / 16;
+  constexpr int RC = 32;
+  __shared__ double sA[RC][KP];
+  __shared__ double sB[RC][KP];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
-  int oa[kQ], ob[kQ];
-  double acc[kQ];
+  double acc[TT][TT];
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const int e = threadIdx.x + kT * q;
-    oa[q] = e < ne ? e / kb : 0;
-    ob[q] = e < ne ? e % kb : 0;
-    acc[q] = 0.0;
-  }
-  for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
-    const int nr = (int)(r1 - t0 < kTile ? r1 - t0 : kTile);
+  for (int i = 0; i < TT; ++i)
+#pragma unroll
+    for (int j = 0; j < TT; ++j) acc[i][j] = 0.0;
+  for (int64_t t0 = r0; t0 < r1; t0 += RC) {
+    const int nr = (int)(r1 - t0 < RC ? r1 - t0 : RC);
     __syncthreads();
-    for (int e = threadIdx.x; e < nr * ka; e += kT) sA[e / ka][e % ka] = ld64(A + (t0 + e / ka) * lda + e % ka);
-    for (int e = threadIdx.x; e < nr * kb; e += kT) sB[e / kb][e % kb] = ld64(B + (t0 + e / kb) * ldb + e % kb);
+    for (int e = threadIdx.x; e < RC * KP; e += kT) {
+      const int row = e / KP, col = e % KP;
+      const bool ok = row < nr;
+      sA[row][col] = (ok && col < ka) ? ld64(A + (t0 + row) * lda + col) : 0.0;
+      sB[row][col] = (ok && col < kb) ? ld64(B + (t0 + row) * ldb + col) : 0.0;
+    }
     __syncthreads();
     for (int rr = 0; rr < nr; ++rr) {
+      double av[TT], bv[TT];
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) acc[q] = fma(sA[rr][oa[q]], sB[rr][ob[q]], acc[q]);
+      for (int i = 0; i < TT; ++i) av[i] = sA[rr][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < TT; ++j) bv[j] = sB[rr][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < TT; ++i)
+#pragma unroll
+        for (int j = 0; j < TT; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
     }
   }
-  double* o = part + (int64_t)(block_offset + blockIdx.x) * ne;
+  double* o = part + (int64_t)(block_offset + blockIdx.x) * ka * kb;
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const int e = threadIdx.x + kT * q;
-    if (e < ne) o[e] = acc[q];
-  }
+  for (int i = 0; i < TT; ++i)
+#pragma unroll
+    for (int j = 0; j < TT; ++j) {
+      const int a = ty + 16 * i, c = tx + 16 * j;
+      if (a < ka && c < kb) o[a * kb + c] = acc[i][j];
+    }
 }
 
-// out (kp x kp, zero padded) = sum_b part[b] (ka x kb), b in order.
+// out (kp x kp, zero padded) = sum_b part[b] (ka x kb).  One wave per output
+// element: lane l adds partials l, l+64, ... in order, then a butterfly sum,
+// so the result does not depend on scheduling.
 __global__ void k_gram_finalize(const double* __restrict__ part, int nparts, int ka, int kb, int kp,
                                 double* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x % kWave;
   if (e >= kp * kp) return;
   const int a = e / kp, c = e % kp;
   double s = 0.0;
   if (a < ka && c < kb) {
-    const int ne = ka * kb;
-    for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * ne + a * kb + c];
+    const int64_t ne = (int64_t)ka * kb;
+    for (int b = lane; b < nparts; b += kWave) s += part[b * ne + a * kb + c];
   }
-  out[e] = s;
+  s = wave_sum(s);
+  if (lane == 0) out[e] = s;
 }
 
 // out[i][c] = sum_a A[i][a] T[a][c] for c < kb (float64 arithmetic).
@@ -164,28 +181,36 @@ __device__ void jacobi_eig(JacobiSmem& sm, int k) {
         sm.cs[2 * threadIdx.x + 1] = s;
       }
       __syncthreads();
+      // S <- J^T S J in one pass: the pairs partition the indices, so every
+      // 2 x 2 block (pair P1 rows, pair P2 columns) transforms on its own as
+      // J1^T S_block J2.  E <- E J column pair by column pair.
+      for (int task = threadIdx.x; task < npairs * npairs; task += kT) {
+        const int P1 = task / npairs, P2 = task % npairs;
+        const double c1 = sm.cs[2 * P1], s1 = sm.cs[2 * P1 + 1];
+        const double c2 = sm.cs[2 * P2], s2 = sm.cs[2 * P2 + 1];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const int p1 = sm.pq[2 * P1], q1 = sm.pq[2 * P1 + 1];
+        const int p2 = sm.pq[2 * P2], q2 = sm.pq[2 * P2 + 1];
+        const double a = S[p1 * kLdJ + p2], b = S[p1 * kLdJ + q2];
+        const double cc = S[q1 * kLdJ + p2], d = S[q1 * kLdJ + q2];
+        const double ra = c1 * a - s1 * cc, rb = c1 * b - s1 * d;     // rows: J1^T
+        const double rc = s1 * a + c1 * cc, rd = s1 * b + c1 * d;
+        double na = c2 * ra - s2 * rb, nb = s2 * ra + c2 * rb;        // columns: J2
+        double nc = c2 * rc - s2 * rd, nd = s2 * rc + c2 * rd;
+        if (P1 == P2) { nb = 0.0; nc = 0.0; }                        // the annihilated pair
+        S[p1 * kLdJ + p2] = na;
+        S[p1 * kLdJ + q2] = nb;
+        S[q1 * kLdJ + p2] = nc;
+        S[q1 * kLdJ + q2] = nd;
+      }
       for (int task = threadIdx.x; task < npairs * n2; task += kT) {
         const int pr = task / n2, x = task % n2;
         const double c = sm.cs[2 * pr], s = sm.cs[2 * pr + 1];
         if (s == 0.0) continue;
         const int p = sm.pq[2 * pr], q = sm.pq[2 * pr + 1];
-        double a = S[x * kLdJ + p], b = S[x * kLdJ + q];
-        S[x * kLdJ + p] = c * a - s * b;
-        S[x * kLdJ + q] = s * a + c * b;
-        a = E[x * kLdJ + p];
-        b = E[x * kLdJ + q];
+        const double a = E[x * kLdJ + p], b = E[x * kLdJ + q];
         E[x * kLdJ + p] = c * a - s * b;
         E[x * kLdJ + q] = s * a + c * b;
-      }
-      __syncthreads();
-      for (int task = threadIdx.x; task < npairs * n2; task += kT) {
-        const int pr = task / n2, x = task % n2;
-        const double c = sm.cs[2 * pr], s = sm.cs[2 * pr + 1];
-        if (s == 0.0) continue;
-        const int p = sm.pq[2 * pr], q = sm.pq[2 * pr + 1];
-        const double a = S[p * kLdJ + x], b = S[q * kLdJ + x];
-        S[p * kLdJ + x] = c * a - s * b;
-        S[q * kLdJ + x] = s * a + c * b;
       }
       __syncthreads();
     }
@@ -348,52 +373,96 @@ __global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, 
   if (threadIdx.x == 0) negpart[blockIdx.x] = neg;
 }
 
-// R <- polar factor of M = sum_b Mpart[b] (r x r): with M^T M = E diag(l) E^T,
-// R = M E diag(l^-1/2) E^T (the orthogonal Procrustes solution C D^T of
-// section 3.1).  Records ||R_new - R_old||_F in st->dR.  R is kp x kp padded.
-__global__ __launch_bounds__(kT) void k_polar(const double* __restrict__ Mpart, int nparts, int r,
-                                              int kp, double* __restrict__ R, DevState* st) {
-  __shared__ JacobiSmem sm;
-  __shared__ double M[64 * 64];
-  __shared__ double lam[64];
+// R <- polar factor of M (r x r, leading dimension kp): the orthogonal
+// Procrustes solution C D^T of section 3.1 (W^T B = C S D^T), computed by the
+// Newton-Schulz iteration X <- 1.5 X - 0.5 X X^T X from X0 = 1.5 M / ||M||_F
+// (singular values of X0 in (0, 1.5], inside the convergence interval
+// (0, sqrt 3)), in float64 until ||X_{k+1} - X_k||_F <= 1e-13 or 100 steps.
+// Records ||R_new - R_old||_F in st->dR.  R is kp x kp, zero padded.
+template <int KP>
+__global__ __launch_bounds__(kT) void k_polar_ns(const double* __restrict__ Mf, int r, int kp,
+                                                 double* __restrict__ R, DevState* st) {
+  constexpr int TT = KP / 16;
+  __shared__ double X[KP][KP + 1];
+  __shared__ double T[KP][KP + 1];
   __shared__ double red[kT / kWave];
-  const int ne = r * r;
-  for (int e = threadIdx.x; e < ne; e += kT) {
-    double s = 0.0;
-    for (int b = 0; b < nparts; ++b) s += Mpart[(int64_t)b * ne + e];
-    M[e] = s;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double nrm = 0.0;
+  for (int e = threadIdx.x; e < KP * KP; e += kT) {
+    const int a = e / KP, c = e % KP;
+    const double v = (a < r && c < r) ? Mf[a * kp + c] : 0.0;
+    X[a][c] = v;
+    nrm = fma(v, v, nrm);
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < ne; e += kT) {
-    const int a = e / r, c = e % r;
-    double s = 0.0;
-    for (int q = 0; q < r; ++q) s = fma(M[q * r + a], M[q * r + c], s);
-    sm.S[a * kLdJ + c] = s;
+  nrm = sqrt(block_sum<kT>(nrm, red));
+  if (!(nrm > 0.0) || !isfinite(nrm)) {
+    if (threadIdx.x == 0) st->dR = 0.0;
+    return;
   }
+  const double sc = 1.5 / nrm;
+  for (int e = threadIdx.x; e < KP * KP; e += kT) X[e / KP][e % KP] *= sc;
   __syncthreads();
-  jacobi_eig(sm, r);
-  if (threadIdx.x < r) lam[threadIdx.x] = eigval(sm, threadIdx.x);
-  __syncthreads();
-  const double lmax = lam[0];
-  // K = E diag(l^-1/2) E^T, written over S (no longer needed).
-  for (int e = threadIdx.x; e < ne; e += kT) {
-    const int a = e / r, c = e % r;
-    double s = 0.0;
-    for (int j = 0; j < r; ++j) {
-      const double l = lam[j];
-      const double sc = (l > 1e-28 * lmax && l > 0.0) ? 1.0 / sqrt(l) : 0.0;
-      s = fma(eigvec(sm, a, j) * sc, eigvec(sm, c, j), s);
+  for (int it = 0; it < 100; ++it) {
+    // T = X^T X
+    double acc[TT][TT];
+#pragma unroll
+    for (int i = 0; i < TT; ++i)
+#pragma unroll
+      for (int j = 0; j < TT; ++j) acc[i][j] = 0.0;
+    for (int q = 0; q < KP; ++q) {
+      double av[TT], bv[TT];
+#pragma unroll
+      for (int i = 0; i < TT; ++i) av[i] = X[q][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < TT; ++j) bv[j] = X[q][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < TT; ++i)
+#pragma unroll
+        for (int j = 0; j < TT; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
     }
-    sm.S[a * kLdJ + c] = s;
+#pragma unroll
+    for (int i = 0; i < TT; ++i)
+#pragma unroll
+      for (int j = 0; j < TT; ++j) T[ty + 16 * i][tx + 16 * j] = acc[i][j];
+    __syncthreads();
+    // X_new = 1.5 X - 0.5 X T
+#pragma unroll
+    for (int i = 0; i < TT; ++i)
+#pragma unroll
+      for (int j = 0; j < TT; ++j) acc[i][j] = 0.0;
+    for (int q = 0; q < KP; ++q) {
+      double av[TT], bv[TT];
+#pragma unroll
+      for (int i = 0; i < TT; ++i) av[i] = X[ty + 16 * i][q];
+#pragma unroll
+      for (int j = 0; j < TT; ++j) bv[j] = T[q][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < TT; ++i)
+#pragma unroll
+        for (int j = 0; j < TT; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    }
+    double d2 = 0.0;
+    double xn[TT][TT];
+#pragma unroll
+    for (int i = 0; i < TT; ++i)
+#pragma unroll
+      for (int j = 0; j < TT; ++j) {
+        const double x = X[ty + 16 * i][tx + 16 * j];
+        xn[i][j] = 1.5 * x - 0.5 * acc[i][j];
+        d2 = fma(xn[i][j] - x, xn[i][j] - x, d2);
+      }
+    d2 = block_sum<kT>(d2, red);   // also orders every read of X before the writes below
+#pragma unroll
+    for (int i = 0; i < TT; ++i)
+#pragma unroll
+      for (int j = 0; j < TT; ++j) X[ty + 16 * i][tx + 16 * j] = xn[i][j];
+    __syncthreads();
+    if (d2 <= 1e-26) break;
   }
-  __syncthreads();
   double d2 = 0.0;
   for (int e = threadIdx.x; e < kp * kp; e += kT) {
     const int a = e / kp, c = e % kp;
-    double v = 0.0;
-    if (a < r && c < r) {
-      for (int q = 0; q < r; ++q) v = fma(M[a * r + q], sm.S[q * kLdJ + c], v);
-    }
+    const double v = (a < r && c < r) ? X[a][c] : 0.0;
     const double dv = v - R[e];
     d2 = fma(dv, dv, d2);
     R[e] = v;
@@ -402,20 +471,34 @@ __global__ __launch_bounds__(kT) void k_polar(const double* __restrict__ Mpart, 
   if (threadIdx.x == 0) st->dR = sqrt(d2);
 }
 
+template <typename TA, typename TB, int KP>
+void tsgram_launch_kp(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t rows, int ka,
+                      int kb, int nblocks, double* part, int off, hipStream_t s) {
+  const int64_t rpb = (rows + nblocks - 1) / nblocks;
+  hipLaunchKernelGGL((k_tsgram<TA, TB, KP>), dim3(nblocks), dim3(kT), 0, s,
+                     reinterpret_cast<const TA*>(A), lda, reinterpret_cast<const TB*>(B), ldb, rows,
+                     ka, kb, rpb, part, off);
+}
+
 template <typename TA, typename TB>
 void tsgram_launch(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t rows, int ka,
                    int kb, int nblocks, double* part, int off, hipStream_t s) {
-  const int64_t rpb = (rows + nblocks - 1) / nblocks;
-  hipLaunchKernelGGL((k_tsgram<TA, TB>), dim3(nblocks), dim3(kT), 0, s,
-                     reinterpret_cast<const TA*>(A), lda, reinterpret_cast<const TB*>(B), ldb, rows,
-                     ka, kb, rpb, part, off);
+  const int kq = pad_width(ka > kb ? ka : kb);
+  switch (kq) {
+    case 8:
+    case 16: tsgram_launch_kp<TA, TB, 16>(A, lda, B, ldb, rows, ka, kb, nblocks, part, off, s); break;
+    case 32: tsgram_launch_kp<TA, TB, 32>(A, lda, B, ldb, rows, ka, kb, nblocks, part, off, s); break;
+    case 48: tsgram_launch_kp<TA, TB, 48>(A, lda, B, ldb, rows, ka, kb, nblocks, part, off, s); break;
+    case 64: tsgram_launch_kp<TA, TB, 64>(A, lda, B, ldb, rows, ka, kb, nblocks, part, off, s); break;
+    default: tsgram_launch_kp<TA, TB, 80>(A, lda, B, ldb, rows, ka, kb, nblocks, part, off, s); break;
+  }
 }
 
 }  // namespace
 
 int gram_blocks(int64_t rows) {
-  int64_t b = (rows + 63) / 64;
-  if (b > 240) b = 240;
+  int64_t b = (rows + 127) / 128;
+  if (b > 256) b = 256;
   if (b < 1) b = 1;
   const int64_t rpb = (rows + b - 1) / b;
   return (int)((rows + rpb - 1) / rpb);
@@ -433,8 +516,9 @@ hipError_t launch_tsgram(const void* A, int a_is_f64, int64_t lda, const void* B
 
 hipError_t launch_gram_finalize(const double* part, int nparts, int ka, int kb, int kp, double* out,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_gram_finalize, dim3((kp * kp + 255) / 256), dim3(256), 0, s, part, nparts, ka,
-                     kb, kp, out);
+  const int waves = kp * kp;
+  hipLaunchKernelGGL(k_gram_finalize, dim3((waves + 3) / 4), dim3(256), 0, s, part, nparts, ka, kb,
+                     kp, out);
   return hipGetLastError();
 }
 
@@ -514,9 +598,14 @@ hipError_t launch_admm_rows(const double* W, int64_t N, int r, int kp, const dou
   return hipGetLastError();
 }
 
-hipError_t launch_polar(const double* Mpart, int nparts, int r, int kp, double* R, DevState* st,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_polar, dim3(1), dim3(kT), 0, s, Mpart, nparts, r, kp, R, st);
+hipError_t launch_polar(const double* Mf, int r, int kp, double* R, DevState* st, hipStream_t s) {
+  switch (pad_width(r)) {
+    case 8:
+    case 16: hipLaunchKernelGGL((k_polar_ns<16>), dim3(1), dim3(kT), 0, s, Mf, r, kp, R, st); break;
+    case 32: hipLaunchKernelGGL((k_polar_ns<32>), dim3(1), dim3(kT), 0, s, Mf, r, kp, R, st); break;
+    case 48: hipLaunchKernelGGL((k_polar_ns<48>), dim3(1), dim3(kT), 0, s, Mf, r, kp, R, st); break;
+    default: hipLaunchKernelGGL((k_polar_ns<64>), dim3(1), dim3(kT), 0, s, Mf, r, kp, R, st); break;
+  }
   return hipGetLastError();
 }
 

@@ -1,11 +1,13 @@
 // Row-local kernels of the exterior phase and of HALS, the KKT check and
 // the per-iteration bookkeeping (sections 3.2-3.3, Algorithms 2-3, the KKT
-// appendix).  One thread owns one row of the factor being updated: the
-// paper notes that the PBCD updates of different rows are independent, and
-// the HALS column update is row-local too.  The r x r Gram (G = V^T V for the
-// U half, H = U^T U for the V half) is zero padded to KP x KP float64 and read
-// with wave-uniform loads.  Row state is float32; every dot product, step and
-// reduction is float64.
+// appendix).  The paper notes that the PBCD updates of different rows are
+// independent, and the HALS column update is row-local too, so rows are the
+// unit of parallelism: a team of KP/8 consecutive lanes owns one row, each
+// lane holding 8 of its columns in registers.  The r x r Gram (G = V^T V for
+// the U half, H = U^T U for the V half) is zero padded to KP x KP float64 and
+// staged in LDS; the team exchanges row vectors through LDS and reduces with
+// xor shuffles.  Row state is float32; dot products, steps and reductions
+// are float64.
 #include <math.h>
 
 #include "dev_common.h"
@@ -90,59 +92,44 @@ __global__ __launch_bounds__(kT) void k_head(const double* __restrict__ negpart,
   }
 }
 
-// Row state in LDS: each thread keeps its row in 8-column blocks
-// (layout [block][thread][8]) so that the loops over column blocks can be
-// runtime loops around fully unrolled 8 x 8 bodies.
-constexpr int kRT = 128;   // threads (rows) per row-update / check block
+// Team geometry: KP/8 lanes per row, teams aligned inside a wave.
+template <int KP> struct Team {
+  static constexpr int T = KP / 8;
+  static constexpr int RB = T <= 4 ? 64 : 32;   // rows per block
+  static constexpr int NT = RB * T;             // threads per block
+};
 
-struct F8 { float v[8]; };
-
-__device__ __forceinline__ F8 ld8(const float* base, int blk, int t) {
-  F8 r;
-  const float4* p = reinterpret_cast<const float4*>(base + ((int64_t)blk * kRT + t) * 8);
-  const float4 x = p[0], y = p[1];
-  r.v[0] = x.x; r.v[1] = x.y; r.v[2] = x.z; r.v[3] = x.w;
-  r.v[4] = y.x; r.v[5] = y.y; r.v[6] = y.z; r.v[7] = y.w;
-  return r;
+template <int T>
+__device__ __forceinline__ double team_sum(double v) {
+#pragma unroll
+  for (int o = T / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
 }
 
-__device__ __forceinline__ void st8(float* base, int blk, int t, const F8& r) {
-  float4* p = reinterpret_cast<float4*>(base + ((int64_t)blk * kRT + t) * 8);
-  p[0] = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
-  p[1] = make_float4(r.v[4], r.v[5], r.v[6], r.v[7]);
-}
-
-// s[e] = sum_b a_b G[b][cb*8+e] - p[e] for the 8 columns of block cb
-// (G symmetric, KP x KP, zero padded).
 template <int KP>
-__device__ __forceinline__ void grad_block(const float* sa, int t, const double* __restrict__ G,
-                                           int cb, const double* pv, double* s) {
-#pragma unroll
-  for (int e = 0; e < 8; ++e) s[e] = -pv[e];
-  for (int bb = 0; bb < KP / 8; ++bb) {
-    const F8 av = ld8(sa, bb, t);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const double ai = (double)av.v[i];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) s[e] = fma(ai, G[(bb * 8 + i) * KP + cb * 8 + e], s[e]);
-    }
-  }
+__device__ __forceinline__ void load_gram(const double* __restrict__ G, double* sG) {
+  for (int e = threadIdx.x; e < KP * KP; e += Team<KP>::NT) sG[e] = G[e];
 }
 
-__device__ __forceinline__ void load_p8(const float* __restrict__ P, bool valid, int64_t i, int r,
-                                        int cb, double* pv) {
+// s[e] = sum_b row[b] G[b][c0+e] for the 8 columns c0..c0+7 (G symmetric).
+template <int KP, typename RT>
+__device__ __forceinline__ void row_times_g(const RT* row, const double* sG, int c0, double* s) {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int c = cb * 8 + e;
-    pv[e] = (valid && c < r) ? (double)P[i * r + c] : 0.0;
+  for (int e = 0; e < 8; ++e) s[e] = 0.0;
+  for (int b = 0; b < KP; ++b) {
+    const double x = (double)row[b];
+    const double* g = sG + b * KP + c0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] = fma(x, g[e], s[e]);
   }
 }
 
 // One half of an outer iteration on the rows of A (U with P = X V, G = V^T V,
 // or V with P = X^T U, G = U^T U), in the phase chosen by k_head.
 //   HALS: for j = 1..r, a_j <- max(0, a_j + (p_j - a . G_:j) / G_jj), skipped
-//         when G_jj = 0 (textbook HALS, Gauss-Seidel over columns).
+//         when G_jj = 0 (textbook HALS, Gauss-Seidel over columns).  The
+//         team keeps t = a G up to date: the owner of column j computes the
+//         change of a_j from t_j and the others add it times row j of G.
 //   EXT:  (first launch) push negatives by the step (eq. negup); mask of
 //         nonnegative entries; then `sweeps` PBCD sweeps (eqs. pbcdu, d_i):
 //         g = M o (a G - p), d = |g|^2 / (g G g^T) (0 if not positive),
@@ -150,139 +137,134 @@ __device__ __forceinline__ void load_p8(const float* __restrict__ P, bool valid,
 // part[b] = {#negative after the update, |M o grad|^2 before the sweeps,
 //            |M o grad|^2 after the sweeps}.
 template <int KP>
-__global__ __launch_bounds__(kRT) void k_rowupdate(float* __restrict__ A, int64_t rows, int r,
-                                                   const float* __restrict__ P,
-                                                   const double* __restrict__ G, DevState* st,
-                                                   int half, int sweeps, int first, int want_pg,
-                                                   double* __restrict__ part) {
-  constexpr int NB = KP / 8;
-  __shared__ __align__(16) float sa[NB * kRT * 8];
-  __shared__ __align__(16) float sg[NB * kRT * 8];
-  __shared__ double sh[kRT / kWave];
+__global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(float* __restrict__ A, int64_t rows,
+                                                            int r, const float* __restrict__ P,
+                                                            const double* __restrict__ G,
+                                                            DevState* st, int half, int sweeps,
+                                                            int first, int want_pg,
+                                                            double* __restrict__ part) {
+  using TM = Team<KP>;
+  constexpr int T = TM::T;
+  __shared__ double sG[KP * KP];
+  __shared__ float sa[TM::RB][KP + 1];
+  __shared__ float sgv[TM::RB][KP + 1];
+  __shared__ double sh[(TM::NT + kWave - 1) / kWave];
   if (st->stop) return;
   const int phase = st->phase;
   if (!first && (phase == kPhaseHals || st->pbcd_done[half])) return;
-  const int t = threadIdx.x;
-  const int64_t i = (int64_t)blockIdx.x * kRT + t;
+  const int team = threadIdx.x / T, q = threadIdx.x % T, c0 = 8 * q;
+  const int64_t i = (int64_t)blockIdx.x * TM::RB + team;
   const bool valid = i < rows;
   const int64_t ic = valid ? i : 0;
+  load_gram<KP>(G, sG);
 
-  for (int cb = 0; cb < NB; ++cb) {
-    F8 x;
+  float a[8];
+  double p[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int c = cb * 8 + e;
-      x.v[e] = (valid && c < r) ? A[ic * r + c] : 0.f;
-    }
-    st8(sa, cb, t, x);
+  for (int e = 0; e < 8; ++e) {
+    const int c = c0 + e;
+    a[e] = (valid && c < r) ? A[ic * r + c] : 0.f;
+    p[e] = (valid && c < r) ? (double)P[ic * r + c] : 0.0;
   }
   double negc = 0.0, gi2 = 0.0, pg2 = 0.0;
 
   if (phase == kPhaseHals) {
-    for (int j = 0; j < r; ++j) {
-      const double gjj = G[j * KP + j];
-      if (gjj > 0.0) {
-        double s = 0.0;
-        for (int cb = 0; cb < NB; ++cb) {
-          const F8 av = ld8(sa, cb, t);
 #pragma unroll
-          for (int e = 0; e < 8; ++e) s = fma((double)av.v[e], G[(cb * 8 + e) * KP + j], s);
+    for (int e = 0; e < 8; ++e) sa[team][c0 + e] = a[e];
+    __syncthreads();
+    double t[8];
+    row_times_g<KP>(sa[team], sG, c0, t);
+    const int base = (threadIdx.x % kWave) - q;
+    for (int j = 0; j < r; ++j) {
+      const int o = j / 8, ej = j % 8;
+      double delta = 0.0;
+      if (q == o) {
+        const double gjj = sG[j * KP + j];
+        if (gjj > 0.0) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            if (e == ej) {
+              const double v = (double)a[e] + (p[e] - t[e]) / gjj;
+              const float nv = (float)(v > 0.0 ? v : 0.0);
+              delta = (double)nv - (double)a[e];
+              a[e] = nv;
+            }
+          }
         }
-        float* aj = sa + ((int64_t)(j / 8) * kRT + t) * 8 + (j % 8);
-        const double pj = valid ? (double)P[ic * r + j] : 0.0;
-        const double v = (double)*aj + (pj - s) / gjj;
-        *aj = (float)(v > 0.0 ? v : 0.0);
       }
+      delta = __shfl(delta, base + o);
+      const double* gj = sG + j * KP + c0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) t[e] = fma(delta, gj[e], t[e]);
     }
   } else {
     if (first) {
       const double step = st->step[half];
-      for (int cb = 0; cb < NB; ++cb) {
-        F8 x = ld8(sa, cb, t);
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-          if (x.v[e] < 0.f) x.v[e] = (float)((double)x.v[e] + step);
-        st8(sa, cb, t, x);
-      }
+      for (int e = 0; e < 8; ++e)
+        if (a[e] < 0.f) a[e] = (float)((double)a[e] + step);
     }
     // mask M = (a >= 0); padded columns carry zeros and stay inert.
     for (int sw = 0; sw < sweeps; ++sw) {
-      double num = 0.0;
-      for (int cb = 0; cb < NB; ++cb) {
-        double pv[8], s[8];
-        load_p8(P, valid, ic, r, cb, pv);
-        grad_block<KP>(sa, t, G, cb, pv, s);
-        const F8 av = ld8(sa, cb, t);
-        F8 g;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          g.v[e] = av.v[e] >= 0.f ? (float)s[e] : 0.f;
-          num = fma((double)g.v[e], (double)g.v[e], num);
-        }
-        st8(sg, cb, t, g);
+      for (int e = 0; e < 8; ++e) sa[team][c0 + e] = a[e];
+      __syncthreads();
+      double s[8];
+      row_times_g<KP>(sa[team], sG, c0, s);
+      float g[8];
+      double num = 0.0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        g[e] = a[e] >= 0.f ? (float)(s[e] - p[e]) : 0.f;
+        num = fma((double)g[e], (double)g[e], num);
+        sgv[team][c0 + e] = g[e];
       }
       if (sw == 0 && first) gi2 = num;
+      __syncthreads();
+      double h[8];
+      row_times_g<KP>(sgv[team], sG, c0, h);
       double den = 0.0;
-      for (int cb = 0; cb < NB; ++cb) {
-        double h[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) h[e] = 0.0;
-        for (int bb = 0; bb < NB; ++bb) {
-          const F8 gv = ld8(sg, bb, t);
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const double gq = (double)gv.v[q];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) h[e] = fma(G[(bb * 8 + q) * KP + cb * 8 + e], gq, h[e]);
-          }
-        }
-        const F8 gc = ld8(sg, cb, t);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) den = fma((double)gc.v[e], h[e], den);
-      }
+      for (int e = 0; e < 8; ++e) den = fma((double)g[e], h[e], den);
+      num = team_sum<T>(num);
+      den = team_sum<T>(den);
       const double d = den > 0.0 ? num / den : 0.0;
-      for (int cb = 0; cb < NB; ++cb) {
-        F8 av = ld8(sa, cb, t);
-        const F8 gv = ld8(sg, cb, t);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          if (av.v[e] >= 0.f) {
-            const double v = (double)av.v[e] - d * (double)gv.v[e];
-            av.v[e] = (float)(v > 0.0 ? v : 0.0);
-          }
+      for (int e = 0; e < 8; ++e) {
+        if (a[e] >= 0.f) {
+          const double v = (double)a[e] - d * (double)g[e];
+          a[e] = (float)(v > 0.0 ? v : 0.0);
         }
-        st8(sa, cb, t, av);
       }
     }
     if (want_pg) {
-      for (int cb = 0; cb < NB; ++cb) {
-        double pv[8], s[8];
-        load_p8(P, valid, ic, r, cb, pv);
-        grad_block<KP>(sa, t, G, cb, pv, s);
-        const F8 av = ld8(sa, cb, t);
+      __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-          if (av.v[e] >= 0.f) pg2 = fma(s[e], s[e], pg2);
+      for (int e = 0; e < 8; ++e) sa[team][c0 + e] = a[e];
+      __syncthreads();
+      double s[8];
+      row_times_g<KP>(sa[team], sG, c0, s);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const double gv = s[e] - p[e];
+        if (a[e] >= 0.f) pg2 = fma(gv, gv, pg2);
       }
     }
   }
   if (valid) {
-    for (int cb = 0; cb < NB; ++cb) {
-      const F8 av = ld8(sa, cb, t);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int c = cb * 8 + e;
-        if (c < r) {
-          A[i * r + c] = av.v[e];
-          negc += av.v[e] < 0.f ? 1.0 : 0.0;
-        }
+    for (int e = 0; e < 8; ++e) {
+      const int c = c0 + e;
+      if (c < r) {
+        A[i * r + c] = a[e];
+        negc += a[e] < 0.f ? 1.0 : 0.0;
       }
     }
   }
-  negc = block_sum<kRT>(negc, sh);
-  gi2 = block_sum<kRT>(gi2, sh);
-  pg2 = block_sum<kRT>(pg2, sh);
-  if (t == 0) {
+  negc = block_sum<TM::NT>(negc, sh);
+  gi2 = block_sum<TM::NT>(gi2, sh);
+  pg2 = block_sum<TM::NT>(pg2, sh);
+  if (threadIdx.x == 0) {
     double* o = part + 3 * (int64_t)blockIdx.x;
     if (first) o[0] = negc;   // later sweeps never change the sign pattern
     o[1] = gi2;
@@ -315,68 +297,69 @@ __global__ __launch_bounds__(kT) void k_pbcd_decide(const double* __restrict__ p
 // a <= 0.  Record: {|pg|^2, sum a grad, max a grad, |min(a,0)|^2, |a|^2,
 // sum a p, #negative, min a, 0...}.
 template <int KP>
-__global__ __launch_bounds__(kRT) void k_check(const float* __restrict__ U, int64_t m,
-                                               const float* __restrict__ P,
-                                               const double* __restrict__ G,
-                                               const float* __restrict__ V, int64_t n,
-                                               const float* __restrict__ Q,
-                                               const double* __restrict__ H, int r, int nbU,
-                                               const DevState* st, double* __restrict__ part) {
-  constexpr int NB = KP / 8;
-  __shared__ __align__(16) float sa[NB * kRT * 8];
-  __shared__ double sh[kRT / kWave];
+__global__ __launch_bounds__(Team<KP>::NT) void k_check(const float* __restrict__ U, int64_t m,
+                                                        const float* __restrict__ P,
+                                                        const double* __restrict__ G,
+                                                        const float* __restrict__ V, int64_t n,
+                                                        const float* __restrict__ Q,
+                                                        const double* __restrict__ H, int r,
+                                                        int nbU, const DevState* st,
+                                                        double* __restrict__ part) {
+  using TM = Team<KP>;
+  constexpr int T = TM::T;
+  __shared__ double sG[KP * KP];
+  __shared__ float sa[TM::RB][KP + 1];
+  __shared__ double sh[(TM::NT + kWave - 1) / kWave];
   if (st->stop) return;
   const bool isU = (int)blockIdx.x < nbU;
   const float* A = isU ? U : V;
   const float* Pm = isU ? P : Q;
-  const double* Gm = isU ? G : H;
   const int64_t rows = isU ? m : n;
-  const int t = threadIdx.x;
-  const int64_t i = (int64_t)(isU ? blockIdx.x : blockIdx.x - nbU) * kRT + t;
+  const int team = threadIdx.x / T, q = threadIdx.x % T, c0 = 8 * q;
+  const int64_t i = (int64_t)(isU ? blockIdx.x : blockIdx.x - nbU) * TM::RB + team;
   const bool valid = i < rows;
   const int64_t ic = valid ? i : 0;
-  for (int cb = 0; cb < NB; ++cb) {
-    F8 x;
+  load_gram<KP>(isU ? G : H, sG);
+  float a[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int c = cb * 8 + e;
-      x.v[e] = (valid && c < r) ? A[ic * r + c] : 0.f;
-    }
-    st8(sa, cb, t, x);
+  for (int e = 0; e < 8; ++e) {
+    const int c = c0 + e;
+    a[e] = (valid && c < r) ? A[ic * r + c] : 0.f;
+    sa[team][c] = a[e];
   }
+  __syncthreads();
+  double s[8];
+  row_times_g<KP>(sa[team], sG, c0, s);
   double pg2 = 0.0, sg = 0.0, mx = -INFINITY, ng2 = 0.0, sq = 0.0, ap = 0.0, nneg = 0.0,
          mn = INFINITY;
   if (valid) {
-    for (int cb = 0; cb < NB; ++cb) {
-      double pv[8], s[8];
-      load_p8(Pm, valid, ic, r, cb, pv);
-      grad_block<KP>(sa, t, Gm, cb, pv, s);
-      const F8 av = ld8(sa, cb, t);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        if (cb * 8 + e < r) {
-          const double a = (double)av.v[e];
-          const double pgc = a > 0.0 ? s[e] : fmin(s[e], 0.0);
-          pg2 = fma(pgc, pgc, pg2);
-          sg = fma(a, s[e], sg);
-          mx = fmax(mx, a * s[e]);
-          if (a < 0.0) { ng2 = fma(a, a, ng2); nneg += 1.0; }
-          sq = fma(a, a, sq);
-          ap = fma(a, pv[e], ap);
-          mn = fmin(mn, a);
-        }
+    for (int e = 0; e < 8; ++e) {
+      const int c = c0 + e;
+      if (c < r) {
+        const double pc = (double)Pm[ic * r + c];
+        const double gv = s[e] - pc;
+        const double av = (double)a[e];
+        const double pgc = av > 0.0 ? gv : fmin(gv, 0.0);
+        pg2 = fma(pgc, pgc, pg2);
+        sg = fma(av, gv, sg);
+        mx = fmax(mx, av * gv);
+        if (av < 0.0) { ng2 = fma(av, av, ng2); nneg += 1.0; }
+        sq = fma(av, av, sq);
+        ap = fma(av, pc, ap);
+        mn = fmin(mn, av);
       }
     }
   }
-  pg2 = block_sum<kRT>(pg2, sh);
-  sg = block_sum<kRT>(sg, sh);
-  mx = block_max<kRT>(mx, sh);
-  ng2 = block_sum<kRT>(ng2, sh);
-  sq = block_sum<kRT>(sq, sh);
-  ap = block_sum<kRT>(ap, sh);
-  nneg = block_sum<kRT>(nneg, sh);
-  mn = block_min<kRT>(mn, sh);
-  if (t == 0) {
+  pg2 = block_sum<TM::NT>(pg2, sh);
+  sg = block_sum<TM::NT>(sg, sh);
+  mx = block_max<TM::NT>(mx, sh);
+  ng2 = block_sum<TM::NT>(ng2, sh);
+  sq = block_sum<TM::NT>(sq, sh);
+  ap = block_sum<TM::NT>(ap, sh);
+  nneg = block_sum<TM::NT>(nneg, sh);
+  mn = block_min<TM::NT>(mn, sh);
+  if (threadIdx.x == 0) {
     double* o = part + (int64_t)blockIdx.x * kCheckFields;
     o[0] = pg2; o[1] = sg; o[2] = mx; o[3] = ng2; o[4] = sq; o[5] = ap; o[6] = nneg; o[7] = mn;
     o[8] = 0.0; o[9] = 0.0; o[10] = 0.0; o[11] = 0.0;
@@ -466,7 +449,35 @@ __global__ void k_clip(float* __restrict__ A, int64_t count) {
     A[e] = A[e] > 0.f ? A[e] : 0.f;
 }
 
+template <int KP>
+void rowupdate_launch(float* A, int64_t rows, int r, const float* P, const double* G, DevState* st,
+                      int half, int sweeps, int first, int want_pg, double* part, hipStream_t s) {
+  using TM = Team<KP>;
+  dim3 g((unsigned)((rows + TM::RB - 1) / TM::RB)), b(TM::NT);
+  hipLaunchKernelGGL((k_rowupdate<KP>), g, b, 0, s, A, rows, r, P, G, st, half, sweeps, first,
+                     want_pg, part);
+}
+
+template <int KP>
+void check_launch(const float* U, int64_t m, const float* P, const double* G, const float* V,
+                  int64_t n, const float* Q, const double* H, int r, double* part, int* nbU,
+                  int* nbV, DevState* st, hipStream_t s) {
+  using TM = Team<KP>;
+  const int bu = (int)((m + TM::RB - 1) / TM::RB), bv = (int)((n + TM::RB - 1) / TM::RB);
+  *nbU = bu;
+  *nbV = bv;
+  hipLaunchKernelGGL((k_check<KP>), dim3((unsigned)(bu + bv)), dim3(TM::NT), 0, s, U, m, P, G, V, n,
+                     Q, H, r, bu, st, part);
+}
+
 }  // namespace
+
+int row_pad(int r) {
+  if (r <= 8) return 8;
+  if (r <= 16) return 16;
+  if (r <= 32) return 32;
+  return 64;
+}
 
 int factor_blocks(int64_t count) {
   int64_t nb = (count + 4095) / 4096;
@@ -474,6 +485,11 @@ int factor_blocks(int64_t count) {
   if (nb < 1) nb = 1;
   const int64_t per = (count + nb - 1) / nb;
   return (int)((count + per - 1) / per);
+}
+
+int rowupdate_blocks(int64_t rows, int kp) {
+  const int rb = kp / 8 <= 4 ? 64 : 32;
+  return (int)((rows + rb - 1) / rb);
 }
 
 hipError_t launch_factor_stats(const float* A, int64_t count, int r, double* part, int block_offset,
@@ -503,18 +519,14 @@ hipError_t launch_tail(DevState* st, hipStream_t s) {
   return hipGetLastError();
 }
 
-int rowupdate_blocks(int64_t rows) { return (int)((rows + kRT - 1) / kRT); }
-
 hipError_t launch_rowupdate(float* A, int64_t rows, int r, int kp, const float* P, const double* G,
                             DevState* st, int half, int sweeps, int first, int want_pg,
                             double* part, hipStream_t s) {
-  dim3 g((unsigned)rowupdate_blocks(rows)), b(kRT);
   switch (kp) {
-    case 8: hipLaunchKernelGGL((k_rowupdate<8>), g, b, 0, s, A, rows, r, P, G, st, half, sweeps, first, want_pg, part); break;
-    case 16: hipLaunchKernelGGL((k_rowupdate<16>), g, b, 0, s, A, rows, r, P, G, st, half, sweeps, first, want_pg, part); break;
-    case 32: hipLaunchKernelGGL((k_rowupdate<32>), g, b, 0, s, A, rows, r, P, G, st, half, sweeps, first, want_pg, part); break;
-    case 48: hipLaunchKernelGGL((k_rowupdate<48>), g, b, 0, s, A, rows, r, P, G, st, half, sweeps, first, want_pg, part); break;
-    default: hipLaunchKernelGGL((k_rowupdate<64>), g, b, 0, s, A, rows, r, P, G, st, half, sweeps, first, want_pg, part); break;
+    case 8: rowupdate_launch<8>(A, rows, r, P, G, st, half, sweeps, first, want_pg, part, s); break;
+    case 16: rowupdate_launch<16>(A, rows, r, P, G, st, half, sweeps, first, want_pg, part, s); break;
+    case 32: rowupdate_launch<32>(A, rows, r, P, G, st, half, sweeps, first, want_pg, part, s); break;
+    default: rowupdate_launch<64>(A, rows, r, P, G, st, half, sweeps, first, want_pg, part, s); break;
   }
   return hipGetLastError();
 }
@@ -528,16 +540,11 @@ hipError_t launch_pbcd_decide(const double* part, int nparts, int half, int firs
 hipError_t launch_check(const float* U, int64_t m, const float* P, const double* G, const float* V,
                         int64_t n, const float* Q, const double* H, int r, int kp, double* part,
                         int* nbU, int* nbV, DevState* st, hipStream_t s) {
-  const int bu = (int)((m + kRT - 1) / kRT), bv = (int)((n + kRT - 1) / kRT);
-  *nbU = bu;
-  *nbV = bv;
-  dim3 g((unsigned)(bu + bv)), b(kRT);
   switch (kp) {
-    case 8: hipLaunchKernelGGL((k_check<8>), g, b, 0, s, U, m, P, G, V, n, Q, H, r, bu, st, part); break;
-    case 16: hipLaunchKernelGGL((k_check<16>), g, b, 0, s, U, m, P, G, V, n, Q, H, r, bu, st, part); break;
-    case 32: hipLaunchKernelGGL((k_check<32>), g, b, 0, s, U, m, P, G, V, n, Q, H, r, bu, st, part); break;
-    case 48: hipLaunchKernelGGL((k_check<48>), g, b, 0, s, U, m, P, G, V, n, Q, H, r, bu, st, part); break;
-    default: hipLaunchKernelGGL((k_check<64>), g, b, 0, s, U, m, P, G, V, n, Q, H, r, bu, st, part); break;
+    case 8: check_launch<8>(U, m, P, G, V, n, Q, H, r, part, nbU, nbV, st, s); break;
+    case 16: check_launch<16>(U, m, P, G, V, n, Q, H, r, part, nbU, nbV, st, s); break;
+    case 32: check_launch<32>(U, m, P, G, V, n, Q, H, r, part, nbU, nbV, st, s); break;
+    default: check_launch<64>(U, m, P, G, V, n, Q, H, r, part, nbU, nbV, st, s); break;
   }
   return hipGetLastError();
 }

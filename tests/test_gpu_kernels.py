@@ -23,8 +23,12 @@ def say(msg):
     print(msg, flush=True)
 
 
-def ref_bound(Xd, Bd, n):
-    return 8 * EPS32 * np.sqrt(n) * (np.abs(Xd) @ np.abs(Bd)) + 1e-30
+def ref_bound(Xd, Bd, n, split=True):
+    """float32 accumulation bound, plus the representation error of the three-term
+    bfloat16 split of the factor (|b - hi - mid - lo| <= 2^-24 |b|) that the
+    matrix-core form of bf16 X adds."""
+    c = 8 * EPS32 * np.sqrt(n) + (2.0 ** -23 if split else 0.0)
+    return c * (np.abs(Xd) @ np.abs(Bd)) + 1e-30
 
 
 SHAPES = [(1, 1), (7, 5), (65, 129), (300, 1000), (130, 515), (1000, 77)]
@@ -48,8 +52,49 @@ def test_xv_xtu(lib, m, n, k, dt):
     P = lib.xv(Xt, torch.from_numpy(B).to(DEV)).cpu().double().numpy()
     Q = lib.xtu(Xt, torch.from_numpy(A).to(DEV)).cpu().double().numpy()
     Bd, Ad = B.astype(np.float64), A.astype(np.float64)
-    assert np.all(np.abs(P - Xd @ Bd) <= ref_bound(Xd, Bd, n))
-    assert np.all(np.abs(Q - Xd.T @ Ad) <= ref_bound(Xd.T, Ad, m))
+    sp = dt == "bf16"
+    assert np.all(np.abs(P - Xd @ Bd) <= ref_bound(Xd, Bd, n, sp))
+    assert np.all(np.abs(Q - Xd.T @ Ad) <= ref_bound(Xd.T, Ad, m, sp))
+
+
+@pytest.fixture(scope="module")
+def valu_lib():
+    """A second context whose products always take the vector-ALU form."""
+    import os
+    os.environ["ENMF_FORCE_VALU"] = "1"
+    try:
+        ctx = enmf.Context(0)
+    finally:
+        del os.environ["ENMF_FORCE_VALU"]
+    yield ctx
+    ctx.close()
+
+
+@pytest.mark.parametrize("m,n,k", [(300, 1000, 20), (130, 515, 49), (1000, 77, 80), (65, 129, 16)])
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16"])
+def test_valu_form_matches_fp64(valu_lib, lib, m, n, k, dt):
+    say(f"vector-ALU form m={m} n={n} k={k} dt={dt}")
+    rng = np.random.default_rng(m + n + k)
+    X = rng.random((m, n)).astype(np.float32)
+    B = rng.standard_normal((n, k)).astype(np.float32)
+    A = rng.standard_normal((m, k)).astype(np.float32)
+    Xt = torch.from_numpy(X).to(DEV)
+    if dt != "f32":
+        Xt = lib.convert(Xt, torch.bfloat16 if dt == "bf16" else torch.float16)
+    Xd = Xt.float().cpu().double().numpy()
+    for ctx in (valu_lib, lib):
+        P = ctx.xv(Xt, torch.from_numpy(B).to(DEV)).cpu().double().numpy()
+        Q = ctx.xtu(Xt, torch.from_numpy(A).to(DEV)).cpu().double().numpy()
+        assert np.all(np.abs(P - Xd @ B) <= ref_bound(Xd, B.astype(np.float64), n))
+        assert np.all(np.abs(Q - Xd.T @ A) <= ref_bound(Xd.T, A.astype(np.float64), m))
+
+
+def test_time_products_runs(lib, valu_lib):
+    say("kernel timing entry point")
+    X = torch.rand((512, 700), device=DEV)
+    for ctx in (lib, valu_lib):
+        a, b = ctx.time_products(X, 32, reps=3)
+        assert a > 0 and b > 0
 
 
 def test_xv_padded_leading_dimension(lib):
@@ -61,10 +106,10 @@ def test_xv_padded_leading_dimension(lib):
     B = rng.standard_normal((130, 7)).astype(np.float32)
     P = lib.xv(Xt, torch.from_numpy(B).to(DEV)).cpu().double().numpy()
     Xd = full[:, :130].astype(np.float64)
-    assert np.all(np.abs(P - Xd @ B) <= ref_bound(Xd, B.astype(np.float64), 130))
+    assert np.all(np.abs(P - Xd @ B) <= ref_bound(Xd, B.astype(np.float64), 130, False))
     A = rng.standard_normal((50, 7)).astype(np.float32)
     Q = lib.xtu(Xt, torch.from_numpy(A).to(DEV)).cpu().double().numpy()
-    assert np.all(np.abs(Q - Xd.T @ A) <= ref_bound(Xd.T, A.astype(np.float64), 50))
+    assert np.all(np.abs(Q - Xd.T @ A) <= ref_bound(Xd.T, A.astype(np.float64), 50, False))
 
 
 @pytest.mark.parametrize("rows,k", [(1, 1), (33, 5), (1000, 49), (4097, 64), (513, 80)])
