@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only time the two X-streaming kernels (for hardware-counter passes)")
     return ap.parse_args()
 
 
@@ -82,6 +84,10 @@ def main():
     X = torch.from_numpy(X_np).to(dev)
     om = torch.from_numpy(om_np).to(dev)
     torch.cuda.synchronize()
+    if args.kernels_only:
+        xv_ms, xtu_ms = ctx.time_products(X, r, reps=20)
+        print(json.dumps({"xv_ms": xv_ms, "xtu_ms": xtu_ms, "m": m, "n": n, "r": r}), flush=True)
+        return
 
     def step(trace_cap=0):
         U, V, rep = ctx.solve(X, r, om, OVERSAMPLE, POWER_ITERS, max_iter=ITERS, check_every=1,

@@ -82,6 +82,11 @@ __device__ __forceinline__ uint4 load16(const ET* __restrict__ X, int64_t rows, 
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// Unconditional 16-byte load (interior chunks: no data-dependent masking, so
+// the loads stay in flight until their first use).
+template <typename ET>
+__device__ __forceinline__ uint4 ldg16(const ET* p) { return *reinterpret_cast<const uint4*>(p); }
+
 // Store a 16x16 accumulator tile: element v of lane (i, g) is D[4g + v][i],
 // written to out[(row_of(4g+v)) * k + col0 + i].
 __device__ __forceinline__ void store_tile_rows(float* __restrict__ out, int64_t m, int k,
@@ -98,24 +103,26 @@ __device__ __forceinline__ void store_tile_rows(float* __restrict__ out, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// float32 X: P = X B.  Block = 4 waves x 64 rows; chunk = 32 columns of X.
-// Lane (i, g) of row tile rt loads X[row0 + 16 rt + i][kc + 8g .. 8g+7]; MFMA
-// step s (0..7) contracts column kc + 8g + s, whose B operand is
-// Bs[8g + s][16 jt + i] from the LDS copy of the chunk of B.
+// float32 X: P = X B.  A block's 4 waves share 64 rows (4 tiles of 16) and
+// split the block's range of 32-column chunks four ways (chunk c goes to wave
+// c mod 4), so no barrier is needed inside the loop; the waves are summed in
+// LDS at the end in a fixed order.  Lane (i, g) of row tile rt loads
+// X[row0 + 16 rt + i][kc + 16h + 4g .. +3] for h = 0, 1 (each load instruction
+// reads 64 contiguous bytes of 16 rows); MFMA step s (0..7) contracts column
+// kc + 16 (s/4) + 4g + s%4.  The factor comes pre-packed in operand order:
+// Bf[chunk][jt][lane][s] = B[kc + 16 (s/4) + 4g + s%4][16 jt + i].
 // ---------------------------------------------------------------------------
 template <int KP>
-__global__ __launch_bounds__(kT) void k_xv_f32(const float* __restrict__ X, int64_t m, int64_t n,
-                                               int64_t ld, const float* __restrict__ Bp, int k,
-                                               int chunks_per_split, int64_t nchunks, int vec,
-                                               float* __restrict__ out, int64_t split_stride) {
+__global__ __launch_bounds__(kT, 2) void k_xv_f32(const float* __restrict__ X, int64_t m, int64_t n,
+                                                  int64_t ld, const float4* __restrict__ Bf, int k,
+                                                  int chunks_per_split, int64_t nchunks, int vec,
+                                                  float* __restrict__ out, int64_t split_stride) {
   constexpr int NT = KP / 16;
   constexpr int RT = 4;
-  constexpr int C = 32;
-  constexpr int LDB = KP + 2;
-  __shared__ float Bs[2][C * LDB];
+  __shared__ f32x4 red[3][RT * NT][kWave];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int i = lane % 16, g = lane / 16;
-  const int64_t row0 = (int64_t)blockIdx.x * (4 * 64) + 64 * w;
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
   const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
   const int64_t c1 = c0 + chunks_per_split < nchunks ? c0 + chunks_per_split : nchunks;
 
@@ -125,157 +132,221 @@ __global__ __launch_bounds__(kT) void k_xv_f32(const float* __restrict__ X, int6
 #pragma unroll
     for (int jt = 0; jt < NT; ++jt) acc[rt][jt] = zero4();
 
-  uint4 xa[RT][2], xb[RT][2];
-  auto load_x = [&](int64_t ch, uint4 (&dst)[RT][2]) {
+  // Interior chunks (whole 64-row group in range, 32 full columns, 16-byte
+  // aligned rows) take unconditional loads into two register sets used in
+  // turn, so each chunk's loads stay in flight while the previous chunk is
+  // multiplied.  Edge chunks (at most the last one) use masked loads.
+  auto load_b = [&](int64_t ch, float4 (&bs)[NT][2]) {
+    const float4* b = Bf + ((ch * NT) * kWave + lane) * 2;
+#pragma unroll
+    for (int jt = 0; jt < NT; ++jt) {
+      bs[jt][0] = b[jt * kWave * 2];
+      bs[jt][1] = b[jt * kWave * 2 + 1];
+    }
+  };
+  auto load_fast = [&](int64_t ch, uint4 (&xs)[RT][2], float4 (&bs)[NT][2]) {
+    const float* base = X + (row0 + i) * ld + ch * 32 + 4 * g;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) xs[rt][h] = ldg16(base + 16 * rt * ld + 16 * h);
+    load_b(ch, bs);
+  };
+  auto load_slow = [&](int64_t ch, uint4 (&xs)[RT][2], float4 (&bs)[NT][2]) {
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int h = 0; h < 2; ++h)
-        dst[rt][h] = load16<float>(X, m, n, ld, row0 + 16 * rt + i, ch * C + 8 * g + 4 * h, vec != 0);
+        xs[rt][h] = load16<float>(X, m, n, ld, row0 + 16 * rt + i, ch * 32 + 16 * h + 4 * g, vec != 0);
+    load_b(ch, bs);
   };
-  auto load_b = [&](int64_t ch, int buf) {
-    for (int e = threadIdx.x; e < C * KP; e += kT) {
-      const int kr = e / KP, col = e % KP;
-      Bs[buf][kr * LDB + col] = Bp[(ch * C + kr) * KP + col];
-    }
-  };
-  if (c0 < c1) {
-    load_x(c0, xa);
-    load_b(c0, 0);
-  }
-  int buf = 0;
-  for (int64_t ch = c0; ch < c1; ++ch) {
-    __syncthreads();
-    const bool more = ch + 1 < c1;
-    if (more) {
-      load_x(ch + 1, xb);
-      load_b(ch + 1, buf ^ 1);
-    }
+  auto compute = [&](const uint4 (&xs)[RT][2], const float4 (&bs)[NT][2]) {
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-      float bv[NT];
-#pragma unroll
-      for (int jt = 0; jt < NT; ++jt) bv[jt] = Bs[buf][(8 * g + s) * LDB + 16 * jt + i];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
-        const uint4 q = xa[rt][s / 4];
+        const uint4 q = xs[rt][s / 4];
         const unsigned wv = (s % 4 == 0) ? q.x : (s % 4 == 1) ? q.y : (s % 4 == 2) ? q.z : q.w;
         const float a = __uint_as_float(wv);
 #pragma unroll
-        for (int jt = 0; jt < NT; ++jt)
-          acc[rt][jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[jt], acc[rt][jt], 0, 0, 0);
+        for (int jt = 0; jt < NT; ++jt) {
+          const float4 bq = bs[jt][s / 4];
+          const float bv = (s % 4 == 0) ? bq.x : (s % 4 == 1) ? bq.y : (s % 4 == 2) ? bq.z : bq.w;
+          acc[rt][jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[rt][jt], 0, 0, 0);
+        }
       }
     }
-    if (more) {
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) { xa[rt][0] = xb[rt][0]; xa[rt][1] = xb[rt][1]; }
+  };
+  const bool rows_ok = vec && row0 + 64 <= m;
+  const int64_t full = n / 32;
+  const int64_t cfull = rows_ok ? (c1 < full ? c1 : full) : c0;
+  int64_t ch = c0 + w;
+  if (ch < cfull) {
+    uint4 xA[RT][2], xB[RT][2];
+    float4 bA[NT][2], bB[NT][2];
+    // Pairs of chunks per loop trip keep each prefetch in the same basic block
+    // as the multiply it overlaps (so it is not sunk past a branch); the
+    // scheduling barrier keeps it ahead of that multiply.
+    const int64_t cnt = (cfull - ch + 3) / 4;
+    const int64_t last = ch + 4 * (cnt - 1);
+    load_fast(ch, xA, bA);
+    int64_t c = ch;
+    for (int64_t p = 0; p + 1 < cnt; p += 2) {
+      load_fast(c + 4, xB, bB);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(xA, bA);
+      load_fast(c + 8 < last ? c + 8 : last, xA, bA);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(xB, bB);
+      c += 8;
     }
-    buf ^= 1;
+    if (cnt & 1) compute(xA, bA);
+    ch += 4 * cnt;
   }
+  for (; ch < c1; ch += 4) {
+    uint4 xs[RT][2];
+    float4 bs[NT][2];
+    load_slow(ch, xs, bs);
+    compute(xs, bs);
+  }
+  if (w > 0) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int jt = 0; jt < NT; ++jt) red[w - 1][rt * NT + jt][lane] = acc[rt][jt];
+  }
+  __syncthreads();
+  if (w != 0) return;
   float* o = out + (int64_t)blockIdx.y * split_stride;
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int jt = 0; jt < NT; ++jt) store_tile_rows(o, m, k, row0 + 16 * rt, 16 * jt, acc[rt][jt]);
+    for (int jt = 0; jt < NT; ++jt) {
+      f32x4 v = acc[rt][jt];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) v += red[q][rt * NT + jt][lane];
+      store_tile_rows(o, m, k, row0 + 16 * rt, 16 * jt, v);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// float32 X: Q = X^T A.  Block = 4 waves x 128 columns; chunk = 16 rows of X
-// (4 MFMA steps of 4 rows).  Lane (i, g) loads X[r][j0 + 64h + 4i .. +3] for
-// the row r = 4 kk + g of step kk; tile (h, t) holds columns
-// j0 + 64h + 4 mm + t (mm = 0..15).  B operand = As[4 kk + g][16 nt + i].
+// float32 X: Q = X^T A.  A block's 4 waves share 64 columns and split the
+// block's range of 16-row chunks four ways; summed in LDS at the end.  In
+// MFMA step kk (rows rc + 4 kk .. +3) lane (i, g) loads X[rc + 4 kk + g][j0 +
+// 4i .. 4i+3]; tile t holds the columns j0 + 4 mm + t (mm = 0..15).  The
+// factor comes pre-packed: Af[chunk][nt][lane][kk] = A[rc + 4 kk + g][16 nt + i].
 // ---------------------------------------------------------------------------
 template <int KP>
-__global__ __launch_bounds__(kT) void k_xtu_f32(const float* __restrict__ X, int64_t m, int64_t n,
-                                                int64_t ld, const float* __restrict__ Ap, int k,
-                                                int64_t rows_per_split, int vec,
-                                                float* __restrict__ out, int64_t split_stride) {
+__global__ __launch_bounds__(kT, 2) void k_xtu_f32(const float* __restrict__ X, int64_t m,
+                                                   int64_t n, int64_t ld,
+                                                   const float4* __restrict__ Af, int k,
+                                                   int chunks_per_split, int64_t nchunks, int vec,
+                                                   float* __restrict__ out, int64_t split_stride) {
   constexpr int NT = KP / 16;
-  constexpr int C = 16;
-  constexpr int LDA = KP + 16;
-  __shared__ float As[2][C * LDA];
+  __shared__ f32x4 red[3][4 * NT][kWave];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int i = lane % 16, g = lane / 16;
-  const int64_t j0 = (int64_t)blockIdx.x * (4 * 128) + 128 * w;
-  const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
-  const int64_t r1 = r0 + rows_per_split < m ? r0 + rows_per_split : m;
+  const int64_t j0 = (int64_t)blockIdx.x * 64;
+  const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
+  const int64_t c1 = c0 + chunks_per_split < nchunks ? c0 + chunks_per_split : nchunks;
 
-  f32x4 acc[8][NT];
+  f32x4 acc[4][NT];
 #pragma unroll
-  for (int mt = 0; mt < 8; ++mt)
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = zero4();
+    for (int nt = 0; nt < NT; ++nt) acc[t][nt] = zero4();
 
-  uint4 xa[4][2], xb[4][2];
-  auto load_x = [&](int64_t rc, uint4 (&dst)[4][2]) {
+  auto load_a = [&](int64_t ch, float4 (&as)[NT]) {
+    const float4* a = Af + (ch * NT) * kWave + lane;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) as[nt] = a[nt * kWave];
+  };
+  auto load_fast = [&](int64_t ch, uint4 (&xs)[4], float4 (&as)[NT]) {
+    const float* base = X + (ch * 16 + g) * ld + j0 + 4 * i;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) xs[kk] = ldg16(base + 4 * kk * ld);
+    load_a(ch, as);
+  };
+  auto load_slow = [&](int64_t ch, uint4 (&xs)[4], float4 (&as)[NT]) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      xs[kk] = load16<float>(X, m, n, ld, ch * 16 + 4 * kk + g, j0 + 4 * i, vec != 0);
+    load_a(ch, as);
+  };
+  auto compute = [&](const uint4 (&xs)[4], const float4 (&as)[NT]) {
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const int64_t row = rc + 4 * kk + g;
+      const uint4 q = xs[kk];
+      const float av[4] = {__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z),
+                           __uint_as_float(q.w)};
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
-        dst[kk][h] = load16<float>(X, row < r1 ? m : 0, n, ld, row, j0 + 64 * h + 4 * i, vec != 0);
-    }
-  };
-  auto load_a = [&](int64_t rc, int buf) {
-    for (int e = threadIdx.x; e < C * KP; e += kT) {
-      const int kr = e / KP, col = e % KP;
-      const int64_t row = rc + kr;
-      As[buf][kr * LDA + col] = row < r1 ? Ap[row * KP + col] : 0.f;
-    }
-  };
-  if (r0 < r1) {
-    load_x(r0, xa);
-    load_a(r0, 0);
-  }
-  int buf = 0;
-  for (int64_t rc = r0; rc < r1; rc += C) {
-    __syncthreads();
-    const bool more = rc + C < r1;
-    if (more) {
-      load_x(rc + C, xb);
-      load_a(rc + C, buf ^ 1);
-    }
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      float bv[NT];
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) bv[nt] = As[buf][(4 * kk + g) * LDA + 16 * nt + i];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const uint4 q = xa[kk][h];
-        const float av[4] = {__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z),
-                             __uint_as_float(q.w)};
+      for (int nt = 0; nt < NT; ++nt) {
+        const float4 aq = as[nt];
+        const float bv = (kk == 0) ? aq.x : (kk == 1) ? aq.y : (kk == 2) ? aq.z : aq.w;
 #pragma unroll
         for (int t = 0; t < 4; ++t)
-#pragma unroll
-          for (int nt = 0; nt < NT; ++nt)
-            acc[4 * h + t][nt] =
-                __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[nt], acc[4 * h + t][nt], 0, 0, 0);
+          acc[t][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv, acc[t][nt], 0, 0, 0);
       }
     }
-    if (more) {
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) { xa[kk][0] = xb[kk][0]; xa[kk][1] = xb[kk][1]; }
+  };
+  const bool cols_ok = vec && j0 + 64 <= n;
+  const int64_t full = m / 16;
+  const int64_t cfull = cols_ok ? (c1 < full ? c1 : full) : c0;
+  int64_t ch = c0 + w;
+  if (ch < cfull) {
+    uint4 xA[4], xB[4];
+    float4 aA[NT], aB[NT];
+    // Pairs of chunks per loop trip keep each prefetch in the same basic block
+    // as the multiply it overlaps (so it is not sunk past a branch); the
+    // scheduling barrier keeps it ahead of that multiply.
+    const int64_t cnt = (cfull - ch + 3) / 4;
+    const int64_t last = ch + 4 * (cnt - 1);
+    load_fast(ch, xA, aA);
+    int64_t c = ch;
+    for (int64_t p = 0; p + 1 < cnt; p += 2) {
+      load_fast(c + 4, xB, aB);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(xA, aA);
+      load_fast(c + 8 < last ? c + 8 : last, xA, aA);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(xB, aB);
+      c += 8;
     }
-    buf ^= 1;
+    if (cnt & 1) compute(xA, aA);
+    ch += 4 * cnt;
   }
-  // element v of lane (i, g) in tile (h, t) is column j0 + 64h + 4 (4g + v) + t, factor column 16 nt + i
-  float* o = out + (int64_t)blockIdx.y * split_stride;
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (; ch < c1; ch += 4) {
+    uint4 xs[4];
+    float4 as[NT];
+    load_slow(ch, xs, as);
+    compute(xs, as);
+  }
+  if (w > 0) {
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int col = 16 * nt + i;
-        if (col < k) {
+      for (int nt = 0; nt < NT; ++nt) red[w - 1][t * NT + nt][lane] = acc[t][nt];
+  }
+  __syncthreads();
+  if (w != 0) return;
+  // element v of lane (i, g) in tile t is column j0 + 4 (4g + v) + t, factor column 16 nt + i
+  float* o = out + (int64_t)blockIdx.y * split_stride;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int64_t j = j0 + 64 * h + 4 * (4 * g + v) + t;
-            if (j < n) o[j * k + col] = acc[4 * h + t][nt][v];
-          }
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      f32x4 v = acc[t][nt];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) v += red[q][t * NT + nt][lane];
+      const int col = 16 * nt + i;
+      if (col < k) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t j = j0 + 4 * (4 * g + e) + t;
+          if (j < n) o[j * k + col] = v[e];
         }
       }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -311,12 +382,21 @@ __global__ __launch_bounds__(kT) void k_xv_bf16(const unsigned short* __restrict
 
   uint4 xa[RT][2], xb[RT][2];
   auto load_x = [&](int64_t ch, uint4 (&dst)[RT][2]) {
+    const bool interior = vec && row0 + 64 <= m && (ch + 1) * 64 <= n;   // wave-uniform
+    if (interior) {
+      const unsigned short* base = X + (row0 + i) * ld + ch * 64 + 8 * g;
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+      for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
-        dst[rt][s] = load16<unsigned short>(X, m, n, ld, row0 + 16 * rt + i, ch * 64 + 32 * s + 8 * g,
-                                            vec != 0);
+        for (int s = 0; s < 2; ++s) dst[rt][s] = ldg16(base + 16 * rt * ld + 32 * s);
+    } else {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+          dst[rt][s] = load16<unsigned short>(X, m, n, ld, row0 + 16 * rt + i,
+                                              ch * 64 + 32 * s + 8 * g, vec != 0);
+    }
   };
   auto load_b = [&](int64_t ch, int buf) {
     const uint4* src = reinterpret_cast<const uint4*>(Bt + ch * CH);
@@ -397,9 +477,16 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
 
   uint4 xa[8], xb[8];
   auto load_x = [&](int64_t ch, uint4 (&dst)[8]) {
+    const bool interior = vec && (ch + 1) * 32 <= m && j0 + 128 <= n;   // wave-uniform
+    if (interior) {
+      const unsigned short* base = X + (ch * 32 + 8 * g) * ld + j0 + 8 * i;
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
-      dst[e] = load16<unsigned short>(X, m, n, ld, ch * 32 + 8 * g + e, j0 + 8 * i, vec != 0);
+      for (int e = 0; e < 8; ++e) dst[e] = ldg16(base + e * ld);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        dst[e] = load16<unsigned short>(X, m, n, ld, ch * 32 + 8 * g + e, j0 + 8 * i, vec != 0);
+    }
   };
   auto load_a = [&](int64_t ch, int buf) {
     const uint4* src = reinterpret_cast<const uint4*>(At + ch * CH);
@@ -494,15 +581,27 @@ __global__ void k_pack_split_t(const float* __restrict__ F, int64_t rows, int k,
   }
 }
 
-// out (rows_out x KP) = F (rows_in x k) zero padded, float32.
-__global__ void k_pad_f32(const float* __restrict__ F, int64_t rows_in, int k, int KP,
-                          int64_t rows_out, float* __restrict__ out) {
-  const int64_t count = rows_out * KP;
+// float32 factor fragments in MFMA operand order.
+// xv  (xtu = 0): Bf[ch][jt][lane][s] = B[32 ch + 16 (s/4) + 4g + s%4][16 jt + i] (s = 0..7)
+// xtu (xtu = 1): Af[ch][nt][lane][kk] = A[16 ch + 4 kk + g][16 nt + i]         (kk = 0..3)
+// with lane = 16 g + i; zero outside the factor (rows x k).
+__global__ void k_pack_frag_f32(const float* __restrict__ F, int64_t rows, int k, int NT,
+                                int rows_per_chunk, int per_lane, int xtu, int64_t nchunks,
+                                float* __restrict__ out) {
+  const int64_t count = nchunks * NT * kWave * per_lane;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / KP;
-    const int c = (int)(e % KP);
-    out[e] = (r < rows_in && c < k) ? F[r * k + c] : 0.f;
+    const int s = (int)(e % per_lane);
+    const int64_t q = e / per_lane;
+    const int lane = (int)(q % kWave);
+    const int64_t q2 = q / kWave;
+    const int jt = (int)(q2 % NT);
+    const int64_t ch = q2 / NT;
+    const int i = lane % 16, g = lane / 16;
+    const int off = xtu ? 4 * s + g : 16 * (s / 4) + 4 * g + (s % 4);
+    const int64_t row = ch * rows_per_chunk + off;
+    const int col = 16 * jt + i;
+    out[e] = (row < rows && col < k) ? F[row * k + col] : 0.f;
   }
 }
 
@@ -528,10 +627,21 @@ bool aligned_rows(const void* X, int64_t ld, int esz) {
   return (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((ld * esz) % 16 == 0);
 }
 
-// Number of contraction splits for a grid of `tiles` output blocks.
+// Number of contraction splits for a grid of `tiles` output blocks (bf16 kernels).
 int64_t choose_splits(int64_t tiles, int64_t units, int64_t min_units) {
   int64_t s = (1536 + tiles - 1) / tiles;
   const int64_t smax = (units + min_units - 1) / min_units;
+  if (s > smax) s = smax;
+  if (s < 1) s = 1;
+  return s;
+}
+
+// float32 kernels: two resident blocks per CU on 256 CUs fill the chip in
+// one round; at least 8 chunks (2 per wave) per split.
+constexpr int64_t kResidentBlocks = 512;
+int64_t f32_splits(int64_t tiles, int64_t nchunks) {
+  int64_t s = kResidentBlocks / tiles;
+  const int64_t smax = (nchunks + 7) / 8;
   if (s > smax) s = smax;
   if (s < 1) s = 1;
   return s;
@@ -546,9 +656,8 @@ void mfma_xv_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t*
   const int KP = mfma_kp(k);
   if (xt == ENMF_F32) {
     const int64_t nch = (n + 31) / 32;
-    *pack_bytes = (size_t)(nch * 32) * KP * 4;
-    const int64_t s = choose_splits((m + 255) / 256, nch, 8);
-    *part_bytes = (size_t)s * m * k * 4;
+    *pack_bytes = (size_t)nch * 32 * KP * 4;
+    *part_bytes = (size_t)f32_splits((m + 63) / 64, nch) * m * k * 4;
   } else {
     const int64_t nch = (n + 63) / 64;
     *pack_bytes = (size_t)nch * 3 * KP * kBtLd * 2;
@@ -559,12 +668,12 @@ void mfma_xv_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t*
 
 void mfma_xtu_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes) {
   const int KP = mfma_kp(k);
-  const int64_t tiles = (n + 511) / 512;
   if (xt == ENMF_F32) {
-    *pack_bytes = (size_t)m * KP * 4;
-    const int64_t s = choose_splits(tiles, (m + 15) / 16, 4);
-    *part_bytes = (size_t)s * n * k * 4;
+    const int64_t nch = (m + 15) / 16;
+    *pack_bytes = (size_t)nch * 16 * KP * 4;
+    *part_bytes = (size_t)f32_splits((n + 63) / 64, nch) * n * k * 4;
   } else {
+    const int64_t tiles = (n + 511) / 512;
     const int64_t nch = (m + 31) / 32;
     *pack_bytes = (size_t)nch * 3 * KP * kAtLd * 2;
     const int64_t s = choose_splits(tiles, nch, 4);
@@ -574,54 +683,53 @@ void mfma_xtu_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t
 
 // P = X B through the matrix cores.  pack and part are workspace of the
 // sizes given by mfma_xv_ws.  reduce = 0 leaves the split partials unsummed
-// (instrumentation).
+// and do_pack = 0 reuses the packed factor (instrumentation).
 hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* B,
                           int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
                           int do_pack) {
   const int KP = mfma_kp(k);
-  const int64_t rb = (m + 255) / 256;
   const bool vec = aligned_rows(X, ld, xt == ENMF_F32 ? 4 : 2);
+  int64_t eff = 1;
   if (xt == ENMF_F32) {
     const int64_t nch = (n + 31) / 32;
+    const int64_t rg = (m + 63) / 64;
     if (do_pack)
-      hipLaunchKernelGGL(k_pad_f32, dim3(grid_for(nch * 32 * KP)), dim3(256), 0, s, B, n, k, KP,
-                         nch * 32, (float*)pack);
-    const int64_t sp = choose_splits(rb, nch, 8);
+      hipLaunchKernelGGL(k_pack_frag_f32, dim3(grid_for(nch * 32 * KP)), dim3(256), 0, s, B, n, k,
+                         KP / 16, 32, 8, 0, nch, (float*)pack);
+    const int64_t sp = f32_splits(rg, nch);
     const int64_t cps = (nch + sp - 1) / sp;
-    const int64_t eff = (nch + cps - 1) / cps;
+    eff = (nch + cps - 1) / cps;
+    float* dst = eff > 1 ? part : out;
+    dim3 grid((unsigned)rg, (unsigned)eff);
+    const float* Xf = reinterpret_cast<const float*>(X);
+    const float4* Bf = reinterpret_cast<const float4*>(pack);
+    switch (KP) {
+      case 16: hipLaunchKernelGGL((k_xv_f32<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k); break;
+      case 32: hipLaunchKernelGGL((k_xv_f32<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k); break;
+      case 48: hipLaunchKernelGGL((k_xv_f32<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k); break;
+      case 64: hipLaunchKernelGGL((k_xv_f32<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k); break;
+      default: hipLaunchKernelGGL((k_xv_f32<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k); break;
+    }
+  } else {
+    const int64_t nch = (n + 63) / 64;
+    const int64_t rb = (m + 255) / 256;
+    if (do_pack)
+      hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 64 * KP)), dim3(256), 0, s, B, n, k, KP, 64,
+                         kBtLd, nch, (unsigned short*)pack);
+    const int64_t sp = choose_splits(rb, nch, 4);
+    const int64_t cps = (nch + sp - 1) / sp;
+    eff = (nch + cps - 1) / cps;
     float* dst = eff > 1 ? part : out;
     dim3 grid((unsigned)rb, (unsigned)eff);
-    const float* Xf = reinterpret_cast<const float*>(X);
-    const float* Bp = reinterpret_cast<const float*>(pack);
+    const unsigned short* Xb = reinterpret_cast<const unsigned short*>(X);
+    const unsigned short* Bt = reinterpret_cast<const unsigned short*>(pack);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xv_f32<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bp, k, (int)cps, nch, (int)vec, dst, m * k); break;
-      case 32: hipLaunchKernelGGL((k_xv_f32<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bp, k, (int)cps, nch, (int)vec, dst, m * k); break;
-      case 48: hipLaunchKernelGGL((k_xv_f32<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bp, k, (int)cps, nch, (int)vec, dst, m * k); break;
-      case 64: hipLaunchKernelGGL((k_xv_f32<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bp, k, (int)cps, nch, (int)vec, dst, m * k); break;
-      default: hipLaunchKernelGGL((k_xv_f32<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bp, k, (int)cps, nch, (int)vec, dst, m * k); break;
+      case 16: hipLaunchKernelGGL((k_xv_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
+      case 32: hipLaunchKernelGGL((k_xv_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
+      case 48: hipLaunchKernelGGL((k_xv_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
+      case 64: hipLaunchKernelGGL((k_xv_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
+      default: hipLaunchKernelGGL((k_xv_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || eff <= 1 || !reduce) return e;
-    hipLaunchKernelGGL(k_reduce, dim3(grid_for(m * k)), dim3(256), 0, s, part, (int)eff, m * k, out);
-    return hipGetLastError();
-  }
-  const int64_t nch = (n + 63) / 64;
-  if (do_pack)
-    hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 64 * KP)), dim3(256), 0, s, B, n, k, KP, 64,
-                       kBtLd, nch, (unsigned short*)pack);
-  const int64_t sp = choose_splits(rb, nch, 4);
-  const int64_t cps = (nch + sp - 1) / sp;
-  const int64_t eff = (nch + cps - 1) / cps;
-  float* dst = eff > 1 ? part : out;
-  dim3 grid((unsigned)rb, (unsigned)eff);
-  const unsigned short* Xb = reinterpret_cast<const unsigned short*>(X);
-  const unsigned short* Bt = reinterpret_cast<const unsigned short*>(pack);
-  switch (KP) {
-    case 16: hipLaunchKernelGGL((k_xv_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
-    case 32: hipLaunchKernelGGL((k_xv_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
-    case 48: hipLaunchKernelGGL((k_xv_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
-    case 64: hipLaunchKernelGGL((k_xv_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
-    default: hipLaunchKernelGGL((k_xv_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || eff <= 1 || !reduce) return e;
@@ -634,50 +742,48 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
                            int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
                            int do_pack) {
   const int KP = mfma_kp(k);
-  const int64_t tiles = (n + 511) / 512;
   const bool vec = aligned_rows(X, ld, xt == ENMF_F32 ? 4 : 2);
+  int64_t eff = 1;
   if (xt == ENMF_F32) {
+    const int64_t nch = (m + 15) / 16;
+    const int64_t cg = (n + 63) / 64;
     if (do_pack)
-      hipLaunchKernelGGL(k_pad_f32, dim3(grid_for(m * KP)), dim3(256), 0, s, A, m, k, KP, m,
-                         (float*)pack);
-    const int64_t units = (m + 15) / 16;
-    const int64_t sp = choose_splits(tiles, units, 4);
-    const int64_t ups = (units + sp - 1) / sp;
-    const int64_t eff = (units + ups - 1) / ups;
-    const int64_t rps = ups * 16;
+      hipLaunchKernelGGL(k_pack_frag_f32, dim3(grid_for(nch * 16 * KP)), dim3(256), 0, s, A, m, k,
+                         KP / 16, 16, 4, 1, nch, (float*)pack);
+    const int64_t sp = f32_splits(cg, nch);
+    const int64_t cps = (nch + sp - 1) / sp;
+    eff = (nch + cps - 1) / cps;
+    float* dst = eff > 1 ? part : out;
+    dim3 grid((unsigned)cg, (unsigned)eff);
+    const float* Xf = reinterpret_cast<const float*>(X);
+    const float4* Af = reinterpret_cast<const float4*>(pack);
+    switch (KP) {
+      case 16: hipLaunchKernelGGL((k_xtu_f32<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k); break;
+      case 32: hipLaunchKernelGGL((k_xtu_f32<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k); break;
+      case 48: hipLaunchKernelGGL((k_xtu_f32<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k); break;
+      case 64: hipLaunchKernelGGL((k_xtu_f32<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k); break;
+      default: hipLaunchKernelGGL((k_xtu_f32<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k); break;
+    }
+  } else {
+    const int64_t tiles = (n + 511) / 512;
+    const int64_t nch = (m + 31) / 32;
+    if (do_pack)
+      hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 32 * KP)), dim3(256), 0, s, A, m, k, KP, 32,
+                         kAtLd, nch, (unsigned short*)pack);
+    const int64_t sp = choose_splits(tiles, nch, 4);
+    const int64_t cps = (nch + sp - 1) / sp;
+    eff = (nch + cps - 1) / cps;
     float* dst = eff > 1 ? part : out;
     dim3 grid((unsigned)tiles, (unsigned)eff);
-    const float* Xf = reinterpret_cast<const float*>(X);
-    const float* Ap = reinterpret_cast<const float*>(pack);
+    const unsigned short* Xb = reinterpret_cast<const unsigned short*>(X);
+    const unsigned short* At = reinterpret_cast<const unsigned short*>(pack);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xtu_f32<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, Ap, k, rps, (int)vec, dst, n * k); break;
-      case 32: hipLaunchKernelGGL((k_xtu_f32<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, Ap, k, rps, (int)vec, dst, n * k); break;
-      case 48: hipLaunchKernelGGL((k_xtu_f32<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, Ap, k, rps, (int)vec, dst, n * k); break;
-      case 64: hipLaunchKernelGGL((k_xtu_f32<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, Ap, k, rps, (int)vec, dst, n * k); break;
-      default: hipLaunchKernelGGL((k_xtu_f32<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, Ap, k, rps, (int)vec, dst, n * k); break;
+      case 16: hipLaunchKernelGGL((k_xtu_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
+      case 32: hipLaunchKernelGGL((k_xtu_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
+      case 48: hipLaunchKernelGGL((k_xtu_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
+      case 64: hipLaunchKernelGGL((k_xtu_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
+      default: hipLaunchKernelGGL((k_xtu_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || eff <= 1 || !reduce) return e;
-    hipLaunchKernelGGL(k_reduce, dim3(grid_for(n * k)), dim3(256), 0, s, part, (int)eff, n * k, out);
-    return hipGetLastError();
-  }
-  const int64_t nch = (m + 31) / 32;
-  if (do_pack)
-    hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 32 * KP)), dim3(256), 0, s, A, m, k, KP, 32,
-                       kAtLd, nch, (unsigned short*)pack);
-  const int64_t sp = choose_splits(tiles, nch, 4);
-  const int64_t cps = (nch + sp - 1) / sp;
-  const int64_t eff = (nch + cps - 1) / cps;
-  float* dst = eff > 1 ? part : out;
-  dim3 grid((unsigned)tiles, (unsigned)eff);
-  const unsigned short* Xb = reinterpret_cast<const unsigned short*>(X);
-  const unsigned short* At = reinterpret_cast<const unsigned short*>(pack);
-  switch (KP) {
-    case 16: hipLaunchKernelGGL((k_xtu_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
-    case 32: hipLaunchKernelGGL((k_xtu_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
-    case 48: hipLaunchKernelGGL((k_xtu_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
-    case 64: hipLaunchKernelGGL((k_xtu_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
-    default: hipLaunchKernelGGL((k_xtu_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || eff <= 1 || !reduce) return e;
