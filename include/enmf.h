@@ -206,6 +206,17 @@ enmf_status enmf_objective_kkt(enmf_ctx* ctx, const enmf_matrix* X, int32_t r, c
 enmf_status enmf_time_products(enmf_ctx* ctx, const enmf_matrix* X, int32_t k, int32_t reps,
                                double* xv_ms_host, double* xtu_ms_host);
 
+/* In-solve sampling of the two streaming kernels.  With period > 0, every
+ * later enmf_iterate on this context brackets the X V and X^T U kernel
+ * launches of every period-th outer iteration with HIP events on the context
+ * stream (the events enclose the streaming kernel alone, not the factor
+ * packing); period = 0 switches sampling off.  Each call returns the average
+ * device time (ms) per sampled launch and the number of samples collected
+ * since the previous call, then clears the accumulators.  Outputs may be
+ * NULL. */
+enmf_status enmf_kernel_timing(enmf_ctx* ctx, int32_t period, double* xv_ms_host,
+                               double* xtu_ms_host, int32_t* samples_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,10 +15,12 @@ using namespace enmf;
 namespace {
 
 enum Slot {
-  S_BP, S_AP, S_SPLIT, S_P, S_Q, S_GPART, S_G, S_H, S_RUPART, S_CHK, S_XPART, S_STAT, S_UD, S_RES,
+  S_BP, S_AP, S_SPLIT, S_P, S_Q, S_GPART, S_G, S_H, S_RUPART, S_XPART, S_U2, S_GPU, S_GPV, S_STAT, S_UD, S_RES,
   S_Y, S_QM64, S_QM32, S_Z, S_QN64, S_QN32, S_TMP64, S_T, S_C, S_COLP, S_COLS, S_SIG, S_TU, S_TV,
   S_W64, S_YA, S_ZA, S_BA, S_R, S_NEGP, S_WSQ, S_MPART, N_SLOTS
 };
+
+constexpr int kTimingPairs = 64;   // sampled launches per kind and iterate call
 
 struct Buf {
   void* p = nullptr;
@@ -35,7 +37,15 @@ struct enmf_ctx {
   DevState* st = nullptr;
   double ns_per_tick = 10.0;
   bool use_mfma = true;   // ENMF_FORCE_VALU=1 at creation selects the vector-ALU products
+  // in-solve sampling of the streaming kernels (enmf_kernel_timing)
+  int timing_period = 0;
+  std::vector<hipEvent_t> events;       // pool: [kind][pair][2]
+  int pending[2] = {0, 0};              // pairs recorded in the current iterate call
+  int pending_k[2][kTimingPairs] = {};            // outer iteration of each recorded pair
+  double timing_sum[2] = {0.0, 0.0};
+  int timing_n[2] = {0, 0};
 };
+
 
 namespace {
 
@@ -167,6 +177,75 @@ enmf_status do_xtu(enmf_ctx* c, const enmf_matrix* X, const float* A, int k, flo
   return ENMF_OK;
 }
 
+// A product left as split partials: value = sum over s < n of p[s * stride + e].
+struct Parts {
+  const float* p = nullptr;
+  int n = 1;
+  int64_t stride = 0;
+};
+
+// P = X B as partials (B: n x k, ld k); P_out receives the product when it
+// is not split.
+enmf_status xv_parts(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, float* P_out,
+                     Parts* out, hipEvent_t* ev = nullptr) {
+  hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
+  int ns = 1;
+  if (use_mfma(c, X, k)) {
+    size_t pb = 0, sb = 0;
+    mfma_xv_ws(X->dtype, X->m, X->n, k, &pb, &sb);
+    WS(pack, void, S_BP, pb);
+    WS(part, float, S_SPLIT, sb);
+    CK(launch_xv_mfma(X->data, X->dtype, X->m, X->n, X->ld, B, k, pack, part, P_out, c->stream, 0,
+                      1, &ns, &c->st->stop, e0, e1));
+    out->p = ns > 1 ? part : P_out;
+  } else {
+    const int kp = pad_width(k);
+    const int64_t rows_pad = round_up(X->n, xv_tile_width(X->dtype));
+    WS(Bp, float, S_BP, rows_pad * kp * 4);
+    CK(launch_pad_rows_cols(B, X->n, k, kp, rows_pad, Bp, c->stream));
+    const int splits = xv_splits(X->m, X->n, X->dtype);
+    WS(part, float, S_SPLIT, (int64_t)splits * X->m * k * 4);
+    if (e0) CK(hipEventRecord(e0, c->stream));
+    CK(launch_xv(X->data, X->dtype, X->m, X->n, X->ld, Bp, k, kp, splits, part, P_out, c->stream, 0,
+                 &ns));
+    if (e1) CK(hipEventRecord(e1, c->stream));
+    out->p = ns > 1 ? part : P_out;
+  }
+  out->n = ns;
+  out->stride = X->m * k;
+  return ENMF_OK;
+}
+
+// Q = X^T A as partials (A: m x k, ld k).
+enmf_status xtu_parts(enmf_ctx* c, const enmf_matrix* X, const float* A, int k, float* Q_out,
+                      Parts* out, hipEvent_t* ev = nullptr) {
+  hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
+  int ns = 1;
+  if (use_mfma(c, X, k)) {
+    size_t pb = 0, sb = 0;
+    mfma_xtu_ws(X->dtype, X->m, X->n, k, &pb, &sb);
+    WS(pack, void, S_AP, pb);
+    WS(part, float, S_SPLIT, sb);
+    CK(launch_xtu_mfma(X->data, X->dtype, X->m, X->n, X->ld, A, k, pack, part, Q_out, c->stream, 0,
+                       1, &ns, &c->st->stop, e0, e1));
+    out->p = ns > 1 ? part : Q_out;
+  } else {
+    const int kp = pad_width(k);
+    WS(Ap, float, S_AP, X->m * kp * 4);
+    CK(launch_pad_cols(A, X->m, k, kp, Ap, c->stream));
+    const int splits = xtu_splits(X->m, X->n);
+    WS(part, float, S_SPLIT, (int64_t)splits * X->n * k * 4);
+    if (e0) CK(hipEventRecord(e0, c->stream));
+    CK(launch_xtu(X->data, X->dtype, X->m, X->n, X->ld, Ap, k, kp, splits, part, Q_out, c->stream, 0,
+                  &ns));
+    if (e1) CK(hipEventRecord(e1, c->stream));
+    out->p = ns > 1 ? part : Q_out;
+  }
+  out->n = ns;
+  out->stride = X->n * k;
+  return ENMF_OK;
+}
+
 // out (kp x kp, zero padded) = A^T A for A (rows x k float32 or float64, ld lda).
 enmf_status do_gram(enmf_ctx* c, const void* A, int a_f64, int64_t lda, int64_t rows, int k, int kp,
                     double* out) {
@@ -279,6 +358,7 @@ void enmf_destroy(enmf_ctx* c) {
   for (auto& b : c->bufs)
     if (b.p) (void)hipFree(b.p);
   if (c->st) (void)hipFree(c->st);
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -469,9 +549,11 @@ enmf_status enmf_rotate(enmf_ctx* c, int64_t m, int64_t n, int32_t r, float* U, 
 namespace {
 
 struct IterBufs {
-  float *P, *Q;
-  double *G, *H, *rupart, *chk, *stat, *xpart;
+  float *P, *Q, *U2;
+  double *G, *H, *rec, *gpU, *gpV, *stat, *xpart;
   int nbU, nbV, fbU, fbV;
+  double* recU(int slot) { return rec + (int64_t)slot * kRecFields * nbU; }
+  double* recV(int slot) { return rec + (int64_t)kRecFields * (2 * nbU + slot * nbV); }
 };
 
 // Prepares DevState and the buffers shared by enmf_iterate and enmf_objective_kkt.
@@ -482,14 +564,16 @@ enmf_status iter_setup(enmf_ctx* c, const enmf_matrix* X, int r, const float* U,
   const int kp = row_pad(r);
   WS(P, float, S_P, m * r * 4);
   WS(Q, float, S_Q, n * r * 4);
+  WS(U2, float, S_U2, m * r * 4);
   WS(G, double, S_G, kp * kp * 8);
   WS(H, double, S_H, kp * kp * 8);
-  b.P = P; b.Q = Q; b.G = G; b.H = H;
+  b.P = P; b.Q = Q; b.U2 = U2; b.G = G; b.H = H;
   b.nbU = rowupdate_blocks(m, kp);
   b.nbV = rowupdate_blocks(n, kp);
-  WS(rup, double, S_RUPART, 3 * (int64_t)(b.nbU + b.nbV) * 8);
-  WS(chk, double, S_CHK, (int64_t)kCheckFields * (b.nbU + b.nbV) * 8);
-  b.rupart = rup; b.chk = chk;
+  WS(rec, double, S_RUPART, 2 * (int64_t)kRecFields * (b.nbU + b.nbV) * 8);
+  WS(gpU, double, S_GPU, (int64_t)gram_part_len(kp) * b.nbU * 8);
+  WS(gpV, double, S_GPV, (int64_t)gram_part_len(kp) * b.nbV * 8);
+  b.rec = rec; b.gpU = gpU; b.gpV = gpV;
   b.fbU = factor_blocks(m * r);
   b.fbV = factor_blocks(n * r);
   WS(stat, double, S_STAT, 4 * (int64_t)(b.fbU + b.fbV + 512) * 8);
@@ -506,10 +590,11 @@ enmf_status iter_setup(enmf_ctx* c, const enmf_matrix* X, int r, const float* U,
   }
   if (!ws(c, S_BP, pbx) || !ws(c, S_AP, pbu))
     return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
-  if (!ws(c, S_SPLIT, split_bytes(c, X, r)))
-    return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
-  if (!ws(c, S_GPART, (int64_t)gram_blocks(m > n ? m : n) * r * r * 8))
-    return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
+  size_t sb = split_bytes(c, X, r);
+  const size_t sv = (size_t)xv_splits(m, n, X->dtype) * m * r * 4;
+  const size_t su = (size_t)xtu_splits(m, n) * n * r * 4;
+  if (!use_mfma(c, X, r)) sb = sv > su ? sv : su;
+  if (!ws(c, S_SPLIT, sb)) return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
 
   DevState h;
   std::memset(&h, 0, sizeof(h));
@@ -525,8 +610,7 @@ enmf_status iter_setup(enmf_ctx* c, const enmf_matrix* X, int r, const float* U,
   CK(launch_sumsq_x(X->data, X->dtype, m, n, X->ld, xp, &nx, s));
   CK(launch_factor_stats(U, m * r, r, stat, 0, b.fbU, s));
   CK(launch_factor_stats(V, n * r, r, stat, b.fbU, b.fbV, s));
-  CK(launch_setup_state2(stat, b.fbU, b.fbV, xp, nx, o.step_u, o.step_v, o.ext_iters, c->st, rup,
-                         b.nbU + b.nbV, s));
+  CK(launch_setup_state(stat, b.fbU, b.fbV, xp, nx, o.step_u, o.step_v, o.ext_iters, c->st, s));
   return ENMF_OK;
 }
 
@@ -540,6 +624,15 @@ enmf_status set_trace_cap(enmf_ctx* c, int cap) {
 
 extern "C" {
 
+// Launch sequence of one solve (per outer iteration k):
+//   xv(V^k) -> G^k = gram_fin(partial Grams of V^k)
+//   rowupdate U: phase from the previous records, check partials of U^k,
+//                update into the other U buffer, partial Grams of U^(k+1)
+//   finalize: check of iteration k (stop, trace, iteration count)
+//   H^(k+1) = gram_fin(...), xtu(U^(k+1)), rowupdate V (in place): check
+//                partials of V^(k+1) and its partial Grams.
+// The U update of iteration k runs before its stop decision, into a second
+// buffer, so a stop at k keeps U^k; U^k lives in buffer k mod 2.
 enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U, float* V,
                          const enmf_iter_opts* opts, enmf_iter_report* rep, double* trace,
                          int32_t trace_cap) {
@@ -566,41 +659,64 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
   TRY(iter_setup(c, X, r, U, V, o, b));
   TRY(set_trace_cap(c, trace ? trace_cap : 0));
   DevState* st = c->st;
-  double* rupU = b.rupart;
-  double* rupV = b.rupart + 3 * b.nbU;
   const bool fixed = o.pbcd_eps == 0.0;
+  float* Ub[2] = {U, b.U2};
+  Parts pp;
+  c->pending[0] = c->pending[1] = 0;
+  auto sample = [&](int kind, int k) -> hipEvent_t* {
+    if (c->timing_period <= 0 || k % c->timing_period != 0 || c->pending[kind] >= kTimingPairs)
+      return nullptr;
+    c->pending_k[kind][c->pending[kind]] = k;
+    return &c->events[2 * (kind * kTimingPairs + c->pending[kind]++)];
+  };
 
-  TRY(do_gram(c, U, 0, r, m, r, kp, b.H));
-  TRY(do_xtu(c, X, U, r, b.Q));
+  // prologue: records and Grams of U^0 and V^0 (slot 1 = "iteration -1")
+  CK(launch_rowupdate(U, U, m, r, kp, nullptr, 1, 0, nullptr, st, 0, 0, kRowGram, b.recU(1), b.gpU,
+                      nullptr, 0, nullptr, 0, s));
+  CK(launch_gram_fin(b.gpU, b.nbU, kp, b.H, s));
+  TRY(xtu_parts(c, X, U, r, b.Q, &pp));
+  CK(launch_rowupdate(V, V, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, 0,
+                      kRowGram | kRowWriteCheck, b.recV(1), b.gpV, nullptr, 0, nullptr, 0, s));
   for (int k = 0; k <= o.max_iter; ++k) {
-    TRY(do_gram(c, V, 0, r, n, r, kp, b.G));
-    TRY(do_xv(c, X, V, r, b.P));
-    if (k % o.check_every == 0 || k == o.max_iter) {
-      int nbU = 0, nbV = 0;
-      CK(launch_check(U, m, b.P, b.G, V, n, b.Q, b.H, r, kp, b.chk, &nbU, &nbV, st, s));
-      CK(launch_check_finalize(b.chk, nbU, nbV, b.G, b.H, kp, k, k == o.max_iter, st, trace, s));
-    }
-    if (k == o.max_iter) break;
-    CK(launch_head(b.rupart, b.nbU + b.nbV, st, s));
-    if (fixed) {
-      CK(launch_rowupdate(U, m, r, kp, b.P, b.G, st, 0, o.pbcd_max_iter, 1, 0, rupU, s));
+    const int cur = k & 1, prev = cur ^ 1;
+    const bool last = k == o.max_iter;
+    const bool due = (k % o.check_every == 0) || last;
+    TRY(xv_parts(c, X, V, r, b.P, &pp, sample(0, k)));
+    CK(launch_gram_fin(b.gpV, b.nbV, kp, b.G, s));
+    const int head = kRowHead | kRowCheckPre | (due ? kRowWriteCheck : 0);
+    if (last) {
+      CK(launch_rowupdate(Ub[cur], Ub[cur], m, r, kp, pp.p, pp.n, pp.stride, b.G, st, 0, 0, head,
+                          b.recU(cur), b.gpU, b.recU(prev), b.nbU, b.recV(prev), b.nbV, s));
+    } else if (fixed) {
+      CK(launch_rowupdate(Ub[cur], Ub[prev], m, r, kp, pp.p, pp.n, pp.stride, b.G, st, 0,
+                          o.pbcd_max_iter, head | kRowUpdate | kRowFirst | kRowGram, b.recU(cur),
+                          b.gpU, b.recU(prev), b.nbU, b.recV(prev), b.nbV, s));
     } else {
       for (int t = 0; t < o.pbcd_max_iter; ++t) {
-        CK(launch_rowupdate(U, m, r, kp, b.P, b.G, st, 0, 1, t == 0, 1, rupU, s));
-        CK(launch_pbcd_decide(rupU, b.nbU, 0, t == 0, st, s));
+        const int fl = kRowUpdate | kRowWantPg | kRowGram | (t == 0 ? head | kRowFirst : 0);
+        CK(launch_rowupdate(t == 0 ? Ub[cur] : Ub[prev], Ub[prev], m, r, kp, pp.p, pp.n, pp.stride,
+                            b.G, st, 0, 1, fl, b.recU(cur), b.gpU, b.recU(prev), b.nbU,
+                            b.recV(prev), b.nbV, s));
+        CK(launch_pbcd_decide(b.recU(cur), b.nbU, 0, t == 0, st, s));
       }
     }
-    TRY(do_gram(c, U, 0, r, m, r, kp, b.H));
-    TRY(do_xtu(c, X, U, r, b.Q));
+    CK(launch_finalize(b.recU(cur), b.nbU, b.recV(prev), b.nbV, b.G, b.H, kp, k, due ? 1 : 0,
+                       last ? 1 : 0, st, trace, s));
+    if (last) break;
+    CK(launch_gram_fin(b.gpU, b.nbU, kp, b.H, s));
+    TRY(xtu_parts(c, X, Ub[prev], r, b.Q, &pp, sample(1, k)));
     if (fixed) {
-      CK(launch_rowupdate(V, n, r, kp, b.Q, b.H, st, 1, o.pbcd_max_iter, 1, 0, rupV, s));
+      CK(launch_rowupdate(V, V, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, o.pbcd_max_iter,
+                          kRowUpdate | kRowFirst | kRowGram | kRowWriteCheck, b.recV(cur), b.gpV,
+                          nullptr, 0, nullptr, 0, s));
     } else {
       for (int t = 0; t < o.pbcd_max_iter; ++t) {
-        CK(launch_rowupdate(V, n, r, kp, b.Q, b.H, st, 1, 1, t == 0, 1, rupV, s));
-        CK(launch_pbcd_decide(rupV, b.nbV, 1, t == 0, st, s));
+        const int fl = kRowUpdate | kRowWantPg | kRowGram | kRowWriteCheck | (t == 0 ? kRowFirst : 0);
+        CK(launch_rowupdate(V, V, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, 1, fl, b.recV(cur),
+                            b.gpV, nullptr, 0, nullptr, 0, s));
+        CK(launch_pbcd_decide(b.recV(cur), b.nbV, 1, t == 0, st, s));
       }
     }
-    CK(launch_tail(st, s));
     if ((k + 1) % 32 == 0) {
       int32_t stop = 0;
       CK(hipMemcpyAsync(&stop, &st->stop, 4, hipMemcpyDeviceToHost, s));
@@ -611,6 +727,22 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
   DevState h;
   CK(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
   CK(hipStreamSynchronize(s));
+  for (int kind = 0; kind < 2; ++kind) {
+    for (int q = 0; q < c->pending[kind]; ++q) {
+      float ms = 0.f;
+      hipEvent_t* e = &c->events[2 * (kind * kTimingPairs + q)];
+      // the X V launch of the stopping iteration ran in full, later ones exit at once
+      const int kq = c->pending_k[kind][q];
+      const bool ran = kind == 0 ? kq <= h.iters : kq < h.iters;
+      if (ran && hipEventElapsedTime(&ms, e[0], e[1]) == hipSuccess) {
+        c->timing_sum[kind] += ms;
+        c->timing_n[kind] += 1;
+      }
+    }
+    c->pending[kind] = 0;
+  }
+  (void)hipGetLastError();
+  if (h.iters & 1) CK(hipMemcpyAsync(U, b.U2, m * r * 4, hipMemcpyDeviceToDevice, s));
   if (rep) {
     std::memset(rep, 0, sizeof(*rep));
     rep->iters = h.iters;
@@ -630,6 +762,8 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
     rep->kkt_pg_v = h.kkt_pg_v;
     rep->delta_w = h.delta_w;
     rep->sigma_w = h.sigma_w;
+  } else {
+    CK(hipStreamSynchronize(s));
   }
   if (h.numeric_error) return fail(c, ENMF_ENUMERIC, "non-finite objective or KKT residual");
   return ENMF_OK;
@@ -653,13 +787,23 @@ enmf_status enmf_objective_kkt(enmf_ctx* c, const enmf_matrix* X, int32_t r, con
   IterBufs b;
   TRY(iter_setup(c, X, r, U, V, o, b));
   TRY(set_trace_cap(c, 0));
-  TRY(do_gram(c, U, 0, r, m, r, kp, b.H));
-  TRY(do_gram(c, V, 0, r, n, r, kp, b.G));
-  TRY(do_xv(c, X, V, r, b.P));
-  TRY(do_xtu(c, X, U, r, b.Q));
-  int nbU = 0, nbV = 0;
-  CK(launch_check(U, m, b.P, b.G, V, n, b.Q, b.H, r, kp, b.chk, &nbU, &nbV, c->st, s));
-  CK(launch_check_finalize(b.chk, nbU, nbV, b.G, b.H, kp, 0, 1, c->st, nullptr, s));
+  DevState* st = c->st;
+  float* Uw = const_cast<float*>(U);   // never written: no kRowUpdate below
+  float* Vw = const_cast<float*>(V);
+  Parts pp;
+  CK(launch_rowupdate(U, Uw, m, r, kp, nullptr, 1, 0, nullptr, st, 0, 0, kRowGram, b.recU(0), b.gpU,
+                      nullptr, 0, nullptr, 0, s));
+  CK(launch_gram_fin(b.gpU, b.nbU, kp, b.H, s));
+  CK(launch_rowupdate(V, Vw, n, r, kp, nullptr, 1, 0, nullptr, st, 1, 0, kRowGram, b.recV(0), b.gpV,
+                      nullptr, 0, nullptr, 0, s));
+  CK(launch_gram_fin(b.gpV, b.nbV, kp, b.G, s));
+  TRY(xtu_parts(c, X, U, r, b.Q, &pp));
+  CK(launch_rowupdate(V, Vw, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, 0, kRowWriteCheck,
+                      b.recV(0), b.gpV, nullptr, 0, nullptr, 0, s));
+  TRY(xv_parts(c, X, V, r, b.P, &pp));
+  CK(launch_rowupdate(U, Uw, m, r, kp, pp.p, pp.n, pp.stride, b.G, st, 0, 0,
+                      kRowCheckPre | kRowWriteCheck, b.recU(0), b.gpU, nullptr, 0, nullptr, 0, s));
+  CK(launch_finalize(b.recU(0), b.nbU, b.recV(0), b.nbV, b.G, b.H, kp, 0, 1, 1, st, nullptr, s));
   DevState h;
   CK(hipMemcpyAsync(&h, c->st, sizeof(h), hipMemcpyDeviceToHost, s));
   CK(hipStreamSynchronize(s));
@@ -678,6 +822,24 @@ enmf_status enmf_objective_kkt(enmf_ctx* c, const enmf_matrix* X, int32_t r, con
   out->sigma_v = h.sigma_v;
   out->min_w = h.min_w;
   if (!std::isfinite(f)) return fail(c, ENMF_ENUMERIC, "non-finite objective");
+  return ENMF_OK;
+}
+
+enmf_status enmf_kernel_timing(enmf_ctx* c, int32_t period, double* xv_ms, double* xtu_ms,
+                               int32_t* samples) {
+  TRY(check_ctx(c));
+  if (period < 0) return fail(c, ENMF_EINVAL, "period must be >= 0");
+  if (period > 0 && c->events.empty()) {
+    c->events.resize(2 * 2 * kTimingPairs, nullptr);
+    for (auto& e : c->events) CK(hipEventCreate(&e));
+  }
+  const int n0 = c->timing_n[0], n1 = c->timing_n[1];
+  if (xv_ms) *xv_ms = n0 ? c->timing_sum[0] / n0 : 0.0;
+  if (xtu_ms) *xtu_ms = n1 ? c->timing_sum[1] / n1 : 0.0;
+  if (samples) *samples = n0 < n1 ? n0 : n1;
+  c->timing_sum[0] = c->timing_sum[1] = 0.0;
+  c->timing_n[0] = c->timing_n[1] = 0;
+  c->timing_period = period;
   return ENMF_OK;
 }
 

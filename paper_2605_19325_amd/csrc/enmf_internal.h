@@ -39,9 +39,26 @@ struct DevState {
   int32_t pad_[2];
 };
 
-// Number of float64 fields in one check-partial record.
-constexpr int kCheckFields = 12;
+// Per-block record written by the row-update kernel (float64 fields):
+// negative count of the output rows, PBCD gradient norms before/after the
+// sweeps, and 8 KKT-check partials starting at kRecChk.
+constexpr int kRecFields = 16;
+constexpr int kRecNeg = 0;
+constexpr int kRecGi = 1;
+constexpr int kRecPg = 2;
+constexpr int kRecChk = 4;
 constexpr int kTraceFields = ENMF_TRACE_FIELDS;
+
+// Work selected in one row-update launch (see k_rowupdate).
+enum RowFlags {
+  kRowUpdate = 1,       // apply the EXT or HALS update
+  kRowFirst = 2,        // first launch of the half: push negatives, record |grad_0|
+  kRowCheckPre = 4,     // check partials at the input state (else at the output)
+  kRowHead = 8,         // decide the phase from the previous records
+  kRowWantPg = 16,      // masked gradient norm after the sweeps (PBCD tolerance stop)
+  kRowGram = 32,        // partial Gram of the output rows
+  kRowWriteCheck = 64,  // write the check partials
+};
 
 constexpr int kPhaseExt = 0;
 constexpr int kPhaseHals = 1;
@@ -71,10 +88,14 @@ hipError_t launch_pad_rows_cols(const float* in, int64_t rows_in, int k, int kp,
 hipError_t launch_pad_cols_f64(const float* in, int64_t rows, int k, int kp, double* out,
                                hipStream_t s);
 // `reduce` = 0 launches only the streaming kernel (split partials are left in part).
+// With reduce = 0 and nsplit != nullptr the product is left as *nsplit
+// partials (part when *nsplit > 1, else out) of stride rows * k.
 hipError_t launch_xv(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* Bp, int k,
-                     int kp, int splits, float* part, float* out, hipStream_t s, int reduce = 1);
+                     int kp, int splits, float* part, float* out, hipStream_t s, int reduce = 1,
+                     int* nsplit = nullptr);
 hipError_t launch_xtu(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* Ap, int k,
-                      int kp, int splits, float* part, float* out, hipStream_t s, int reduce = 1);
+                      int kp, int splits, float* part, float* out, hipStream_t s, int reduce = 1,
+                      int* nsplit = nullptr);
 hipError_t launch_residual(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const double* Ud,
                            const float* V, int r, double* part, int* nparts, hipStream_t s);
 hipError_t launch_sumsq_x(const void* X, int xt, int64_t m, int64_t n, int64_t ld, double* part,
@@ -90,10 +111,12 @@ void mfma_xv_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t*
 void mfma_xtu_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes);
 hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* B,
                           int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
-                          int do_pack);
+                          int do_pack, int* nsplit = nullptr, const int32_t* stop = nullptr,
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* A,
                            int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
-                           int do_pack);
+                           int do_pack, int* nsplit = nullptr, const int32_t* stop = nullptr,
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // k_small.hip
 int gram_blocks(int64_t rows);
@@ -126,24 +149,26 @@ int factor_blocks(int64_t count);
 // Padded width of the r x r Grams consumed by the row-update and check kernels.
 int row_pad(int r);
 int rowupdate_blocks(int64_t rows, int kp);
+// float64 entries of one block's partial Gram at padded width kp.
+int gram_part_len(int kp);
 hipError_t launch_factor_stats(const float* A, int64_t count, int r, double* part, int block_offset,
                                int nblocks, hipStream_t s);
-hipError_t launch_setup_state2(const double* statpart, int nbU, int nbV, const double* xpart,
-                               int nxpart, double step_u, double step_v, int ext_iters,
-                               DevState* st, double* negpart, int nneg, hipStream_t s);
-hipError_t launch_head(const double* negpart, int nparts, DevState* st, hipStream_t s);
-hipError_t launch_tail(DevState* st, hipStream_t s);
-hipError_t launch_rowupdate(float* A, int64_t rows, int r, int kp, const float* P, const double* G,
-                            DevState* st, int half, int sweeps, int first, int want_pg,
-                            double* part, hipStream_t s);
-hipError_t launch_pbcd_decide(const double* part, int nparts, int half, int first, DevState* st,
+hipError_t launch_setup_state(const double* statpart, int nbU, int nbV, const double* xpart,
+                              int nxpart, double step_u, double step_v, int ext_iters,
+                              DevState* st, hipStream_t s);
+// One row pass (flags from RowFlags).  P: nsplit partials of stride pstride.
+// rec: kRecFields doubles per block; gpart: gram_part_len(kp) doubles per
+// block; headU/headV: the previous records of both halves (kRowHead).
+hipError_t launch_rowupdate(const float* A, float* Aout, int64_t rows, int r, int kp, const float* P,
+                            int nsplit, int64_t pstride, const double* G, DevState* st, int half,
+                            int sweeps, int flags, double* rec, double* gpart, const double* headU,
+                            int nbU, const double* headV, int nbV, hipStream_t s);
+hipError_t launch_gram_fin(const double* gpart, int nparts, int kp, double* out, hipStream_t s);
+hipError_t launch_pbcd_decide(const double* rec, int nparts, int half, int first, DevState* st,
                               hipStream_t s);
-hipError_t launch_check(const float* U, int64_t m, const float* P, const double* G, const float* V,
-                        int64_t n, const float* Q, const double* H, int r, int kp, double* part,
-                        int* nbU, int* nbV, DevState* st, hipStream_t s);
-hipError_t launch_check_finalize(const double* part, int nbU, int nbV, const double* G,
-                                 const double* H, int kp, int k, int final_check, DevState* st,
-                                 double* trace, hipStream_t s);
+hipError_t launch_finalize(const double* recU, int nbU, const double* recV, int nbV, const double* G,
+                           const double* H, int kp, int k, int due, int final_check, DevState* st,
+                           double* trace, hipStream_t s);
 hipError_t launch_clip(float* A, int64_t count, hipStream_t s);
 
 }  // namespace enmf

@@ -116,7 +116,9 @@ template <int KP>
 __global__ __launch_bounds__(kT, 2) void k_xv_f32(const float* __restrict__ X, int64_t m, int64_t n,
                                                   int64_t ld, const float4* __restrict__ Bf, int k,
                                                   int chunks_per_split, int64_t nchunks, int vec,
-                                                  float* __restrict__ out, int64_t split_stride) {
+                                                  float* __restrict__ out, int64_t split_stride,
+    const int32_t* __restrict__ stop) {
+  if (stop != nullptr && *stop) return;
   constexpr int NT = KP / 16;
   constexpr int RT = 4;
   __shared__ f32x4 red[3][RT * NT][kWave];
@@ -241,7 +243,9 @@ __global__ __launch_bounds__(kT, 2) void k_xtu_f32(const float* __restrict__ X, 
                                                    int64_t n, int64_t ld,
                                                    const float4* __restrict__ Af, int k,
                                                    int chunks_per_split, int64_t nchunks, int vec,
-                                                   float* __restrict__ out, int64_t split_stride) {
+                                                   float* __restrict__ out, int64_t split_stride,
+    const int32_t* __restrict__ stop) {
+  if (stop != nullptr && *stop) return;
   constexpr int NT = KP / 16;
   __shared__ f32x4 red[3][4 * NT][kWave];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
@@ -363,7 +367,9 @@ __global__ __launch_bounds__(kT) void k_xv_bf16(const unsigned short* __restrict
                                                 int64_t n, int64_t ld,
                                                 const unsigned short* __restrict__ Bt, int k,
                                                 int chunks_per_split, int64_t nchunks, int vec,
-                                                float* __restrict__ out, int64_t split_stride) {
+                                                float* __restrict__ out, int64_t split_stride,
+    const int32_t* __restrict__ stop) {
+  if (stop != nullptr && *stop) return;
   constexpr int NT = KP / 16;
   constexpr int RT = 4;
   constexpr int CH = 3 * KP * kBtLd;   // elements of one packed chunk (hi, mid, lo)
@@ -459,7 +465,9 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
                                                  int64_t n, int64_t ld,
                                                  const unsigned short* __restrict__ At, int k,
                                                  int64_t chunks_per_split, int64_t nchunks, int vec,
-                                                 float* __restrict__ out, int64_t split_stride) {
+                                                 float* __restrict__ out, int64_t split_stride,
+    const int32_t* __restrict__ stop) {
+  if (stop != nullptr && *stop) return;
   constexpr int NT = KP / 16;
   constexpr int CH = 3 * KP * kAtLd;
   __shared__ __align__(16) unsigned short As[2][CH];
@@ -686,7 +694,8 @@ void mfma_xtu_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t
 // and do_pack = 0 reuses the packed factor (instrumentation).
 hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* B,
                           int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
-                          int do_pack) {
+                          int do_pack, int* nsplit, const int32_t* stop,
+                           hipEvent_t ev0, hipEvent_t ev1) {
   const int KP = mfma_kp(k);
   const bool vec = aligned_rows(X, ld, xt == ENMF_F32 ? 4 : 2);
   int64_t eff = 1;
@@ -703,13 +712,15 @@ hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t l
     dim3 grid((unsigned)rg, (unsigned)eff);
     const float* Xf = reinterpret_cast<const float*>(X);
     const float4* Bf = reinterpret_cast<const float4*>(pack);
+    if (ev0) (void)hipEventRecord(ev0, s);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xv_f32<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k); break;
-      case 32: hipLaunchKernelGGL((k_xv_f32<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k); break;
-      case 48: hipLaunchKernelGGL((k_xv_f32<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k); break;
-      case 64: hipLaunchKernelGGL((k_xv_f32<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k); break;
-      default: hipLaunchKernelGGL((k_xv_f32<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k); break;
+      case 16: hipLaunchKernelGGL((k_xv_f32<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
+      case 32: hipLaunchKernelGGL((k_xv_f32<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
+      case 48: hipLaunchKernelGGL((k_xv_f32<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
+      case 64: hipLaunchKernelGGL((k_xv_f32<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
+      default: hipLaunchKernelGGL((k_xv_f32<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
     }
+    if (ev1) (void)hipEventRecord(ev1, s);
   } else {
     const int64_t nch = (n + 63) / 64;
     const int64_t rb = (m + 255) / 256;
@@ -723,15 +734,18 @@ hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t l
     dim3 grid((unsigned)rb, (unsigned)eff);
     const unsigned short* Xb = reinterpret_cast<const unsigned short*>(X);
     const unsigned short* Bt = reinterpret_cast<const unsigned short*>(pack);
+    if (ev0) (void)hipEventRecord(ev0, s);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xv_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
-      case 32: hipLaunchKernelGGL((k_xv_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
-      case 48: hipLaunchKernelGGL((k_xv_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
-      case 64: hipLaunchKernelGGL((k_xv_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
-      default: hipLaunchKernelGGL((k_xv_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k); break;
+      case 16: hipLaunchKernelGGL((k_xv_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
+      case 32: hipLaunchKernelGGL((k_xv_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
+      case 48: hipLaunchKernelGGL((k_xv_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
+      case 64: hipLaunchKernelGGL((k_xv_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
+      default: hipLaunchKernelGGL((k_xv_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
     }
+    if (ev1) (void)hipEventRecord(ev1, s);
   }
   hipError_t e = hipGetLastError();
+  if (nsplit) *nsplit = (e == hipSuccess && !reduce) ? (int)eff : 1;
   if (e != hipSuccess || eff <= 1 || !reduce) return e;
   hipLaunchKernelGGL(k_reduce, dim3(grid_for(m * k)), dim3(256), 0, s, part, (int)eff, m * k, out);
   return hipGetLastError();
@@ -740,7 +754,8 @@ hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t l
 // Q = X^T A through the matrix cores (workspace from mfma_xtu_ws).
 hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* A,
                            int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
-                           int do_pack) {
+                           int do_pack, int* nsplit, const int32_t* stop,
+                           hipEvent_t ev0, hipEvent_t ev1) {
   const int KP = mfma_kp(k);
   const bool vec = aligned_rows(X, ld, xt == ENMF_F32 ? 4 : 2);
   int64_t eff = 1;
@@ -757,13 +772,15 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
     dim3 grid((unsigned)cg, (unsigned)eff);
     const float* Xf = reinterpret_cast<const float*>(X);
     const float4* Af = reinterpret_cast<const float4*>(pack);
+    if (ev0) (void)hipEventRecord(ev0, s);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xtu_f32<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k); break;
-      case 32: hipLaunchKernelGGL((k_xtu_f32<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k); break;
-      case 48: hipLaunchKernelGGL((k_xtu_f32<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k); break;
-      case 64: hipLaunchKernelGGL((k_xtu_f32<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k); break;
-      default: hipLaunchKernelGGL((k_xtu_f32<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k); break;
+      case 16: hipLaunchKernelGGL((k_xtu_f32<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k, stop); break;
+      case 32: hipLaunchKernelGGL((k_xtu_f32<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k, stop); break;
+      case 48: hipLaunchKernelGGL((k_xtu_f32<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k, stop); break;
+      case 64: hipLaunchKernelGGL((k_xtu_f32<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k, stop); break;
+      default: hipLaunchKernelGGL((k_xtu_f32<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k, stop); break;
     }
+    if (ev1) (void)hipEventRecord(ev1, s);
   } else {
     const int64_t tiles = (n + 511) / 512;
     const int64_t nch = (m + 31) / 32;
@@ -777,15 +794,18 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
     dim3 grid((unsigned)tiles, (unsigned)eff);
     const unsigned short* Xb = reinterpret_cast<const unsigned short*>(X);
     const unsigned short* At = reinterpret_cast<const unsigned short*>(pack);
+    if (ev0) (void)hipEventRecord(ev0, s);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xtu_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
-      case 32: hipLaunchKernelGGL((k_xtu_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
-      case 48: hipLaunchKernelGGL((k_xtu_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
-      case 64: hipLaunchKernelGGL((k_xtu_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
-      default: hipLaunchKernelGGL((k_xtu_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k); break;
+      case 16: hipLaunchKernelGGL((k_xtu_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
+      case 32: hipLaunchKernelGGL((k_xtu_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
+      case 48: hipLaunchKernelGGL((k_xtu_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
+      case 64: hipLaunchKernelGGL((k_xtu_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
+      default: hipLaunchKernelGGL((k_xtu_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
     }
+    if (ev1) (void)hipEventRecord(ev1, s);
   }
   hipError_t e = hipGetLastError();
+  if (nsplit) *nsplit = (e == hipSuccess && !reduce) ? (int)eff : 1;
   if (e != hipSuccess || eff <= 1 || !reduce) return e;
   hipLaunchKernelGGL(k_reduce, dim3(grid_for(n * k)), dim3(256), 0, s, part, (int)eff, n * k, out);
   return hipGetLastError();

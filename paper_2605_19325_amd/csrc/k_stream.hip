@@ -454,7 +454,8 @@ hipError_t launch_pad_cols_f64(const float* in, int64_t rows, int k, int kp, dou
 // P = X B.  Bp is B zero padded to kp columns and to ntiles*TW rows;
 // part must hold splits*m*k floats when splits > 1.
 hipError_t launch_xv(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* Bp, int k,
-                     int kp, int splits, float* part, float* out, hipStream_t s, int reduce) {
+                     int kp, int splits, float* part, float* out, hipStream_t s, int reduce,
+                     int* nsplit) {
   const int64_t tw = xv_tile_width(xt);
   const int64_t ntiles = (n + tw - 1) / tw;
   const int tps = (int)((ntiles + splits - 1) / splits);
@@ -469,6 +470,7 @@ hipError_t launch_xv(const void* X, int xt, int64_t m, int64_t n, int64_t ld, co
     default: xv_dispatch_kp<2>(kp, grid, X, m, n, ld, Bp, k, tps, ntiles, dst, stride, s); break;
   }
   hipError_t e = hipGetLastError();
+  if (nsplit) *nsplit = (e == hipSuccess && !reduce) ? (int)eff : 1;
   if (e != hipSuccess || eff <= 1 || !reduce) return e;
   hipLaunchKernelGGL(k_reduce_splits, dim3(grid_for(stride)), dim3(256), 0, s, part, eff, stride,
                      stride, out);
@@ -476,7 +478,8 @@ hipError_t launch_xv(const void* X, int xt, int64_t m, int64_t n, int64_t ld, co
 }
 
 hipError_t launch_xtu(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* Ap, int k,
-                      int kp, int splits, float* part, float* out, hipStream_t s, int reduce) {
+                      int kp, int splits, float* part, float* out, hipStream_t s, int reduce,
+                     int* nsplit) {
   const int64_t rps = (m + splits - 1) / splits;
   const int eff = (int)((m + rps - 1) / rps);
   const int64_t cb = (n + kThreads - 1) / kThreads;
@@ -489,6 +492,7 @@ hipError_t launch_xtu(const void* X, int xt, int64_t m, int64_t n, int64_t ld, c
     default: xtu_dispatch_kp<2>(kp, grid, X, m, n, ld, Ap, k, rps, dst, stride, s); break;
   }
   hipError_t e = hipGetLastError();
+  if (nsplit) *nsplit = (e == hipSuccess && !reduce) ? (int)eff : 1;
   if (e != hipSuccess || eff <= 1 || !reduce) return e;
   hipLaunchKernelGGL(k_reduce_splits, dim3(grid_for(stride)), dim3(256), 0, s, part, eff, stride,
                      stride, out);

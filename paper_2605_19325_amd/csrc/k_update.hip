@@ -44,52 +44,32 @@ __global__ __launch_bounds__(kT) void k_factor_stats(const float* __restrict__ A
   }
 }
 
-// Initial state of an iterate call: ||X||^2, push sizes resolved from the
-// input (eq. negup has a fixed step the paper does not give; the reading is
-// max(-min, 0) / (ext_iters - 0.5)), and the negative count of U and V.
+// Initial state of an iterate call: ||X||^2 and the push sizes resolved from
+// the input (eq. negup has a fixed step the paper does not give; the reading
+// is max(-min, 0) / (ext_iters - 0.5)).  The phase of the first iteration is
+// decided later from the row-update records, like every other iteration's.
 __global__ void k_setup_state(const double* __restrict__ stat, int nbU, int nbV,
                               const double* __restrict__ xpart, int nx, double step_u,
-                              double step_v, int ext_iters, DevState* st,
-                              double* __restrict__ negpart, int nneg) {
-  if (threadIdx.x == 0) {
-    double nx2 = 0.0;
-    for (int b = 0; b < nx; ++b) nx2 += xpart[b];
-    double negs = 0.0, mnU = INFINITY, mnV = INFINITY;
-    for (int b = 0; b < nbU; ++b) { negs += stat[4 * b]; mnU = fmin(mnU, stat[4 * b + 1]); }
-    for (int b = nbU; b < nbU + nbV; ++b) { negs += stat[4 * b]; mnV = fmin(mnV, stat[4 * b + 1]); }
-    const double d = (double)ext_iters - 0.5;
-    st->nx2 = nx2;
-    st->step[0] = step_u > 0.0 ? step_u : fmax(-mnU, 0.0) / d;
-    st->step[1] = step_v > 0.0 ? step_v : fmax(-mnV, 0.0) / d;
-    st->phase = negs > 0.0 ? kPhaseExt : kPhaseHals;
-    st->negs = (int)negs;
-    st->stop = 0;
-    st->converged = 0;
-    st->iters = 0;
-    st->ext_done = 0;
-    st->ntrace = 0;
-    st->numeric_error = 0;
-    st->pbcd_done[0] = st->pbcd_done[1] = 0;
-    negpart[0] = negs;
-  }
-  for (int b = 1 + threadIdx.x; b < nneg; b += blockDim.x) negpart[3 * b] = 0.0;
-}
-
-// Top of an outer iteration: the phase is EXT while U or V has a negative
-// entry (Algorithm 3 repeats the exterior block until U, V >= 0), else HALS.
-// negpart holds the row-update partial records (3 doubles per block, the
-// negative count first) of the U half followed by those of the V half.
-__global__ __launch_bounds__(kT) void k_head(const double* __restrict__ negpart, int nparts,
-                                             DevState* st) {
-  __shared__ double sh[kT / kWave];
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += kT) s += negpart[3 * b];
-  s = block_sum<kT>(s, sh);
-  if (threadIdx.x == 0 && !st->stop) {
-    st->negs = (int)s;
-    st->phase = s > 0.0 ? kPhaseExt : kPhaseHals;
-    st->pbcd_done[0] = st->pbcd_done[1] = 0;
-  }
+                              double step_v, int ext_iters, DevState* st) {
+  if (threadIdx.x != 0) return;
+  double nx2 = 0.0;
+  for (int b = 0; b < nx; ++b) nx2 += xpart[b];
+  double negs = 0.0, mnU = INFINITY, mnV = INFINITY;
+  for (int b = 0; b < nbU; ++b) { negs += stat[4 * b]; mnU = fmin(mnU, stat[4 * b + 1]); }
+  for (int b = nbU; b < nbU + nbV; ++b) { negs += stat[4 * b]; mnV = fmin(mnV, stat[4 * b + 1]); }
+  const double d = (double)ext_iters - 0.5;
+  st->nx2 = nx2;
+  st->step[0] = step_u > 0.0 ? step_u : fmax(-mnU, 0.0) / d;
+  st->step[1] = step_v > 0.0 ? step_v : fmax(-mnV, 0.0) / d;
+  st->phase = negs > 0.0 ? kPhaseExt : kPhaseHals;
+  st->negs = (int)negs;
+  st->stop = 0;
+  st->converged = 0;
+  st->iters = 0;
+  st->ext_done = 0;
+  st->ntrace = 0;
+  st->numeric_error = 0;
+  st->pbcd_done[0] = st->pbcd_done[1] = 0;
 }
 
 // Team geometry: KP/8 lanes per row, teams aligned inside a wave.
@@ -106,9 +86,57 @@ __device__ __forceinline__ double team_sum(double v) {
   return v;
 }
 
+// G (KP x KP float64) into LDS; all of a thread's loads are issued before
+// the first is consumed.
 template <int KP>
 __device__ __forceinline__ void load_gram(const double* __restrict__ G, double* sG) {
-  for (int e = threadIdx.x; e < KP * KP; e += Team<KP>::NT) sG[e] = G[e];
+  constexpr int NT = Team<KP>::NT;
+  constexpr int PER = KP * KP / NT;
+  static_assert(KP * KP % NT == 0, "Gram tile must split evenly over the block");
+  double v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) v[u] = G[threadIdx.x + u * NT];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) sG[threadIdx.x + u * NT] = v[u];
+}
+
+// The block's rows [row0, row0 + nrow) of a row-major rows x r float32
+// matrix form one contiguous range of nrow * r floats.  stage_rows copies it
+// into dst[row][col] (LDS, row pitch LD) with coalesced loads, summing
+// `nsplit` partials of stride pstride in split order; columns >= r and rows
+// >= nrow are zero filled.  Each thread owns at most KP / T = 8 elements.
+template <int KP, int LD>
+__device__ __forceinline__ void stage_rows(const float* __restrict__ src, int nsplit,
+                                           int64_t pstride, int64_t row0, int nrow, int r,
+                                           float (*dst)[LD]) {
+  using TM = Team<KP>;
+  constexpr int PER = TM::RB * KP / TM::NT;
+  const int cnt = nrow * r;
+  const float* base = src + row0 * r;
+  float v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * TM::NT;
+    v[u] = e < cnt ? base[e] : 0.f;
+  }
+  for (int sp = 1; sp < nsplit; ++sp) {
+    float w[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * TM::NT;
+      w[u] = e < cnt ? base[(int64_t)sp * pstride + e] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) v[u] += w[u];
+  }
+  for (int e = threadIdx.x; e < TM::RB * KP; e += TM::NT) dst[e / KP][e % KP] = 0.f;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * TM::NT;
+    if (e < cnt) dst[e / r][e % r] = v[u];
+  }
+  __syncthreads();
 }
 
 // s[e] = sum_b row[b] G[b][c0+e] for the 8 columns c0..c0+7 (G symmetric).
@@ -124,8 +152,72 @@ __device__ __forceinline__ void row_times_g(const RT* row, const double* sG, int
   }
 }
 
+// Upper-triangle 4x4 tile `task` of a KP x KP matrix -> (ti, tj), ti <= tj.
+template <int KP>
+__device__ __forceinline__ void gram_tile(int task, int& ti, int& tj) {
+  constexpr int NTILE = KP / 4;
+  int i = 0, rem = task;
+  while (rem >= NTILE - i) { rem -= NTILE - i; ++i; }
+  ti = i;
+  tj = i + rem;
+}
+
+// Check-record accumulators for one row: grad = a G - p (the gradient of
+// eq. 1 through the Gram identity), projected gradient = grad where a > 0
+// and min(grad, 0) where a <= 0 (the KKT appendix).
+struct CheckAcc {
+  double pg2 = 0.0, sg = 0.0, mx = -INFINITY, ng2 = 0.0, sq = 0.0, ap = 0.0, nneg = 0.0,
+         mn = INFINITY;
+  __device__ __forceinline__ void add(const float* a, const double* s, const double* p, int c0,
+                                      int r) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      if (c0 + e < r) {
+        const double gv = s[e] - p[e];
+        const double av = (double)a[e];
+        const double pgc = av > 0.0 ? gv : fmin(gv, 0.0);
+        pg2 = fma(pgc, pgc, pg2);
+        sg = fma(av, gv, sg);
+        mx = fmax(mx, av * gv);
+        if (av < 0.0) { ng2 = fma(av, av, ng2); nneg += 1.0; }
+        sq = fma(av, av, sq);
+        ap = fma(av, p[e], ap);
+        mn = fmin(mn, av);
+      }
+    }
+  }
+};
+
+// Fixed-order reduction of NF per-thread values over a block of NT threads.
+// kind[f]: 0 sum, 1 max, 2 min.  The result lands in out[] of thread 0.
+template <int NT, int NF>
+__device__ __forceinline__ void block_reduce_fields(double* v, const int* kind, double* sh,
+                                                    double* out) {
+  constexpr int NW = NT / kWave;
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+    v[f] = kind[f] == 1 ? wave_max(v[f]) : (kind[f] == 2 ? wave_min(v[f]) : wave_sum(v[f]));
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) sh[f * NW + w] = v[f];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      double t = sh[f * NW];
+      for (int i = 1; i < NW; ++i)
+        t = kind[f] == 1 ? fmax(t, sh[f * NW + i]) : (kind[f] == 2 ? fmin(t, sh[f * NW + i]) : t + sh[f * NW + i]);
+      out[f] = t;
+    }
+  }
+}
+
 // One half of an outer iteration on the rows of A (U with P = X V, G = V^T V,
-// or V with P = X^T U, G = U^T U), in the phase chosen by k_head.
+// or V with P = X^T U, G = U^T U).  P arrives as `nsplit` float32 partial
+// products (stride pstride) summed here in split order.
 //   HALS: for j = 1..r, a_j <- max(0, a_j + (p_j - a . G_:j) / G_jj), skipped
 //         when G_jj = 0 (textbook HALS, Gauss-Seidel over columns).  The
 //         team keeps t = a G up to date: the owner of column j computes the
@@ -134,46 +226,90 @@ __device__ __forceinline__ void row_times_g(const RT* row, const double* sG, int
 //         nonnegative entries; then `sweeps` PBCD sweeps (eqs. pbcdu, d_i):
 //         g = M o (a G - p), d = |g|^2 / (g G g^T) (0 if not positive),
 //         a <- (a - d g)_+ on the mask, unmasked entries unchanged.
-// part[b] = {#negative after the update, |M o grad|^2 before the sweeps,
-//            |M o grad|^2 after the sweeps}.
+// Flags select the extra work fused into the pass:
+//   kRowHead        phase of this iteration from the negative counts in the
+//                   previous records of both halves (EXT while U or V has a
+//                   negative entry, Algorithm 3); block 0 publishes it.
+//   kRowWriteCheck  KKT-check partials of the rows, at the input state with
+//                   kRowCheckPre, else at the output state.
+//   kRowGram        this block's partial Gram (upper 4x4 tiles, float64) of
+//                   the output rows, for k_gram_fin.
+// The result goes to Aout (which may be A).  rec[b] = {#negative of the
+// output, |M o grad|^2 before the sweeps, |M o grad|^2 after, 0, check...}.
 template <int KP>
-__global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(float* __restrict__ A, int64_t rows,
-                                                            int r, const float* __restrict__ P,
-                                                            const double* __restrict__ G,
-                                                            DevState* st, int half, int sweeps,
-                                                            int first, int want_pg,
-                                                            double* __restrict__ part) {
+__global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
+    const float* A, float* Aout, int64_t rows, int r,
+    const float* __restrict__ P, int nsplit, int64_t pstride, const double* __restrict__ G,
+    DevState* st, int half, int sweeps, int flags, double* __restrict__ rec,
+    double* __restrict__ gpart, const double* __restrict__ headU, int nbU,
+    const double* __restrict__ headV, int nbV) {
   using TM = Team<KP>;
   constexpr int T = TM::T;
+  constexpr int NW = TM::NT / kWave;
+  constexpr int NF = 3 + 8;
   __shared__ double sG[KP * KP];
-  __shared__ float sa[TM::RB][KP + 1];
+  __shared__ __align__(16) float sa[TM::RB][KP + 4];
   __shared__ float sgv[TM::RB][KP + 1];
-  __shared__ double sh[(TM::NT + kWave - 1) / kWave];
+  __shared__ double sh[NF * NW];
   if (st->stop) return;
-  const int phase = st->phase;
-  if (!first && (phase == kPhaseHals || st->pbcd_done[half])) return;
+  const bool update = (flags & kRowUpdate) != 0;
+  const bool first = (flags & kRowFirst) != 0;
+  const bool chk = (flags & kRowWriteCheck) != 0;
+  const bool pre = (flags & kRowCheckPre) != 0;
+  const bool want_pg = (flags & kRowWantPg) != 0;
+  int phase;
+  if (flags & kRowHead) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nbU; b += TM::NT) s += headU[(int64_t)b * kRecFields + kRecNeg];
+    for (int b = threadIdx.x; b < nbV; b += TM::NT) s += headV[(int64_t)b * kRecFields + kRecNeg];
+    s = block_sum<TM::NT>(s, sh);
+    phase = s > 0.0 ? kPhaseExt : kPhaseHals;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->negs = (int)s;
+      st->phase = phase;
+      st->pbcd_done[0] = st->pbcd_done[1] = 0;
+    }
+  } else {
+    phase = st->phase;
+  }
+  if (update && !first && (phase == kPhaseHals || st->pbcd_done[half])) return;
   const int team = threadIdx.x / T, q = threadIdx.x % T, c0 = 8 * q;
-  const int64_t i = (int64_t)blockIdx.x * TM::RB + team;
-  const bool valid = i < rows;
-  const int64_t ic = valid ? i : 0;
-  load_gram<KP>(G, sG);
+  const bool valid = (int64_t)blockIdx.x * TM::RB + team < rows;
+  const bool needG = update || chk;
+  if (needG) load_gram<KP>(G, sG);
+  const int64_t row0 = (int64_t)blockIdx.x * TM::RB;
+  const int nrow = (int)(rows - row0 < TM::RB ? rows - row0 : TM::RB);
 
   float a[8];
   double p[8];
+  stage_rows<KP, KP + 4>(A, 1, 0, row0, nrow, r, sa);
+  if (needG) stage_rows<KP, KP + 1>(P, nsplit, pstride, row0, nrow, r, sgv);
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    const int c = c0 + e;
-    a[e] = (valid && c < r) ? A[ic * r + c] : 0.f;
-    p[e] = (valid && c < r) ? (double)P[ic * r + c] : 0.0;
+    a[e] = sa[team][c0 + e];
+    p[e] = needG ? (double)sgv[team][c0 + e] : 0.0;
   }
-  double negc = 0.0, gi2 = 0.0, pg2 = 0.0;
-
-  if (phase == kPhaseHals) {
+  __syncthreads();
+  CheckAcc ck;
+  double gi2 = 0.0, pg2 = 0.0;
+  double t[8];
+  bool have_t = false;   // t == a G for the current a
+  if (chk && pre) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) sa[team][c0 + e] = a[e];
     __syncthreads();
-    double t[8];
     row_times_g<KP>(sa[team], sG, c0, t);
+    have_t = true;
+    if (valid) ck.add(a, t, p, c0, r);
+  }
+
+  if (update && phase == kPhaseHals) {
+    if (!have_t) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sa[team][c0 + e] = a[e];
+      __syncthreads();
+      row_times_g<KP>(sa[team], sG, c0, t);
+    }
     const int base = (threadIdx.x % kWave) - q;
     for (int j = 0; j < r; ++j) {
       const int o = j / 8, ej = j % 8;
@@ -197,7 +333,8 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(float* __restrict__ 
 #pragma unroll
       for (int e = 0; e < 8; ++e) t[e] = fma(delta, gj[e], t[e]);
     }
-  } else {
+    have_t = true;
+  } else if (update) {
     if (first) {
       const double step = st->step[half];
 #pragma unroll
@@ -206,6 +343,7 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(float* __restrict__ 
     }
     // mask M = (a >= 0); padded columns carry zeros and stay inert.
     for (int sw = 0; sw < sweeps; ++sw) {
+      __syncthreads();
 #pragma unroll
       for (int e = 0; e < 8; ++e) sa[team][c0 + e] = a[e];
       __syncthreads();
@@ -237,50 +375,119 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(float* __restrict__ 
         }
       }
     }
-    if (want_pg) {
+    have_t = false;
+  }
+  // gradient at the output state, when wanted
+  if ((chk && !pre) || (want_pg && update && phase == kPhaseExt)) {
+    if (!have_t) {
       __syncthreads();
 #pragma unroll
       for (int e = 0; e < 8; ++e) sa[team][c0 + e] = a[e];
       __syncthreads();
-      double s[8];
-      row_times_g<KP>(sa[team], sG, c0, s);
+      row_times_g<KP>(sa[team], sG, c0, t);
+    }
+    if (want_pg && update && phase == kPhaseExt) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const double gv = s[e] - p[e];
+        const double gv = t[e] - p[e];
         if (a[e] >= 0.f) pg2 = fma(gv, gv, pg2);
       }
     }
+    if (chk && !pre && valid) ck.add(a, t, p, c0, r);
   }
+  double negc = 0.0;
   if (valid) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int c = c0 + e;
-      if (c < r) {
-        A[i * r + c] = a[e];
-        negc += a[e] < 0.f ? 1.0 : 0.0;
-      }
+    for (int e = 0; e < 8; ++e)
+      if (c0 + e < r) negc += a[e] < 0.f ? 1.0 : 0.0;
+  }
+  // output rows through LDS: coalesced stores, and the operand of the Gram
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 8; ++e) sa[team][c0 + e] = valid ? a[e] : 0.f;
+  __syncthreads();
+  if (update) {
+    constexpr int PER = TM::RB * KP / TM::NT;
+    const int cnt = nrow * r;
+    float* base = Aout + row0 * r;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * TM::NT;
+      if (e < cnt) base[e] = sa[e / r][e % r];
     }
   }
-  negc = block_sum<TM::NT>(negc, sh);
-  gi2 = block_sum<TM::NT>(gi2, sh);
-  pg2 = block_sum<TM::NT>(pg2, sh);
+  if (flags & kRowGram) {
+    constexpr int NTILE = KP / 4;
+    constexpr int NTASK = NTILE * (NTILE + 1) / 2;
+    for (int task = threadIdx.x; task < NTASK; task += TM::NT) {
+      int ti, tj;
+      gram_tile<KP>(task, ti, tj);
+      double acc[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+      for (int row = 0; row < TM::RB; ++row) {
+        const float4 x = *reinterpret_cast<const float4*>(&sa[row][4 * ti]);
+        const float4 y = *reinterpret_cast<const float4*>(&sa[row][4 * tj]);
+        const double xv[4] = {(double)x.x, (double)x.y, (double)x.z, (double)x.w};
+        const double yv[4] = {(double)y.x, (double)y.y, (double)y.z, (double)y.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[4 * u + v] = fma(xv[u], yv[v], acc[4 * u + v]);
+      }
+      double* o = gpart + (int64_t)blockIdx.x * (16 * NTASK) + 16 * task;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) o[e] = acc[e];
+    }
+  }
+  double vals[NF] = {negc, gi2, pg2, ck.pg2, ck.sg, ck.mx, ck.ng2, ck.sq, ck.ap, ck.nneg, ck.mn};
+  const int kind[NF] = {0, 0, 0, 0, 0, 1, 0, 0, 0, 0, 2};
+  double red[NF];
+  block_reduce_fields<TM::NT, NF>(vals, kind, sh, red);
   if (threadIdx.x == 0) {
-    double* o = part + 3 * (int64_t)blockIdx.x;
-    if (first) o[0] = negc;   // later sweeps never change the sign pattern
-    o[1] = gi2;
-    o[2] = pg2;
+    double* o = rec + (int64_t)blockIdx.x * kRecFields;
+    o[kRecNeg] = red[0];
+    o[kRecGi] = red[1];
+    o[kRecPg] = red[2];
+    if (chk) {
+#pragma unroll
+      for (int f = 0; f < 8; ++f) o[kRecChk + f] = red[3 + f];
+    }
+  }
+}
+
+// G (KP x KP, symmetric, zero padded) = sum over blocks of the partial Grams
+// written by k_rowupdate, in block order.  One wave per upper-triangle entry;
+// lanes take the blocks round robin and combine by butterfly.
+template <int KP>
+__global__ __launch_bounds__(256) void k_gram_fin(const double* __restrict__ gpart, int nparts,
+                                                  double* __restrict__ out) {
+  constexpr int NTILE = KP / 4;
+  constexpr int NE = 16 * (NTILE * (NTILE + 1) / 2);
+  const int e = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  const int lane = threadIdx.x % kWave;
+  if (e >= NE) return;
+  double s = 0.0;
+  for (int b = lane; b < nparts; b += kWave) s += gpart[(int64_t)b * NE + e];
+  s = wave_sum(s);
+  if (lane == 0) {
+    int ti, tj;
+    gram_tile<KP>(e / 16, ti, tj);
+    const int ii = 4 * ti + (e % 16) / 4, jj = 4 * tj + (e % 4);
+    out[ii * KP + jj] = s;
+    out[jj * KP + ii] = s;
   }
 }
 
 // PBCD stop test of Algorithm 2 between sweep launches:
 // stop when |M o grad| < eps |M o grad_init|.
-__global__ __launch_bounds__(kT) void k_pbcd_decide(const double* __restrict__ part, int nparts,
+__global__ __launch_bounds__(kT) void k_pbcd_decide(const double* __restrict__ rec, int nparts,
                                                     int half, int first, DevState* st) {
   __shared__ double sh[kT / kWave];
   double gi = 0.0, pg = 0.0;
   for (int b = threadIdx.x; b < nparts; b += kT) {
-    gi += part[3 * b + 1];
-    pg += part[3 * b + 2];
+    gi += rec[(int64_t)b * kRecFields + kRecGi];
+    pg += rec[(int64_t)b * kRecFields + kRecPg];
   }
   gi = block_sum<kT>(gi, sh);
   pg = block_sum<kT>(pg, sh);
@@ -290,157 +497,93 @@ __global__ __launch_bounds__(kT) void k_pbcd_decide(const double* __restrict__ p
   }
 }
 
-// Per-block KKT partials.  Blocks [0, nbU) cover the rows of U with
-// (P = X V, G = V^T V); blocks [nbU, nbU + nbV) the rows of V with
-// (Q = X^T U, H = U^T U).  grad = a G - p (the gradient of eq. 1 through the
-// Gram identity), projected gradient = grad where a > 0, min(grad, 0) where
-// a <= 0.  Record: {|pg|^2, sum a grad, max a grad, |min(a,0)|^2, |a|^2,
-// sum a p, #negative, min a, 0...}.
-template <int KP>
-__global__ __launch_bounds__(Team<KP>::NT) void k_check(const float* __restrict__ U, int64_t m,
-                                                        const float* __restrict__ P,
-                                                        const double* __restrict__ G,
-                                                        const float* __restrict__ V, int64_t n,
-                                                        const float* __restrict__ Q,
-                                                        const double* __restrict__ H, int r,
-                                                        int nbU, const DevState* st,
-                                                        double* __restrict__ part) {
-  using TM = Team<KP>;
-  constexpr int T = TM::T;
-  __shared__ double sG[KP * KP];
-  __shared__ float sa[TM::RB][KP + 1];
-  __shared__ double sh[(TM::NT + kWave - 1) / kWave];
+// Check of iteration k (the KKT appendix): combine the check records of the
+// U half (input state U^k) and of the V half (V^k) in block order, evaluate
+// f through the expansion 1/2||X||^2 - <U, X V> + 1/2 <U^T U, V^T V>, the
+// relative error and the normalised KKT residual documented in enmf.h,
+// decide whether to stop, append a trace record, and count the iteration.
+// `due` = 0 skips the evaluation (check_every > 1) and only counts.
+__global__ __launch_bounds__(kT) void k_finalize(const double* __restrict__ recU, int nbU,
+                                                 const double* __restrict__ recV, int nbV,
+                                                 const double* __restrict__ G,
+                                                 const double* __restrict__ H, int kp, int k,
+                                                 int due, int final_check, DevState* st,
+                                                 double* __restrict__ trace) {
+  constexpr int NF = 17;
+  __shared__ double sh[NF * (kT / kWave)];
   if (st->stop) return;
-  const bool isU = (int)blockIdx.x < nbU;
-  const float* A = isU ? U : V;
-  const float* Pm = isU ? P : Q;
-  const int64_t rows = isU ? m : n;
-  const int team = threadIdx.x / T, q = threadIdx.x % T, c0 = 8 * q;
-  const int64_t i = (int64_t)(isU ? blockIdx.x : blockIdx.x - nbU) * TM::RB + team;
-  const bool valid = i < rows;
-  const int64_t ic = valid ? i : 0;
-  load_gram<KP>(isU ? G : H, sG);
-  float a[8];
+  bool stop = final_check != 0;
+  bool hit = false;
+  if (due || final_check) {
+    double v[NF];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int c = c0 + e;
-    a[e] = (valid && c < r) ? A[ic * r + c] : 0.f;
-    sa[team][c] = a[e];
-  }
-  __syncthreads();
-  double s[8];
-  row_times_g<KP>(sa[team], sG, c0, s);
-  double pg2 = 0.0, sg = 0.0, mx = -INFINITY, ng2 = 0.0, sq = 0.0, ap = 0.0, nneg = 0.0,
-         mn = INFINITY;
-  if (valid) {
+    for (int side = 0; side < 2; ++side) {
+      const double* rc = side == 0 ? recU : recV;
+      const int nb = side == 0 ? nbU : nbV;
+      double acc[8] = {0.0, 0.0, -INFINITY, 0.0, 0.0, 0.0, 0.0, INFINITY};
+      for (int b = threadIdx.x; b < nb; b += kT) {
+        const double* o = rc + (int64_t)b * kRecFields + kRecChk;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int c = c0 + e;
-      if (c < r) {
-        const double pc = (double)Pm[ic * r + c];
-        const double gv = s[e] - pc;
-        const double av = (double)a[e];
-        const double pgc = av > 0.0 ? gv : fmin(gv, 0.0);
-        pg2 = fma(pgc, pgc, pg2);
-        sg = fma(av, gv, sg);
-        mx = fmax(mx, av * gv);
-        if (av < 0.0) { ng2 = fma(av, av, ng2); nneg += 1.0; }
-        sq = fma(av, av, sq);
-        ap = fma(av, pc, ap);
-        mn = fmin(mn, av);
+        for (int f = 0; f < 8; ++f)
+          acc[f] = f == 2 ? fmax(acc[f], o[f]) : (f == 7 ? fmin(acc[f], o[f]) : acc[f] + o[f]);
       }
+#pragma unroll
+      for (int f = 0; f < 8; ++f) v[8 * side + f] = acc[f];
     }
-  }
-  pg2 = block_sum<TM::NT>(pg2, sh);
-  sg = block_sum<TM::NT>(sg, sh);
-  mx = block_max<TM::NT>(mx, sh);
-  ng2 = block_sum<TM::NT>(ng2, sh);
-  sq = block_sum<TM::NT>(sq, sh);
-  ap = block_sum<TM::NT>(ap, sh);
-  nneg = block_sum<TM::NT>(nneg, sh);
-  mn = block_min<TM::NT>(mn, sh);
-  if (threadIdx.x == 0) {
-    double* o = part + (int64_t)blockIdx.x * kCheckFields;
-    o[0] = pg2; o[1] = sg; o[2] = mx; o[3] = ng2; o[4] = sq; o[5] = ap; o[6] = nneg; o[7] = mn;
-    o[8] = 0.0; o[9] = 0.0; o[10] = 0.0; o[11] = 0.0;
-  }
-}
-
-// Combine the KKT partials (fixed order), evaluate f through the expansion
-// 1/2||X||^2 - <U, X V> + 1/2 <U^T U, V^T V>, the relative error, the KKT
-// residual of the KKT appendix (normalised as documented in enmf.h), decide
-// whether to stop, and append a trace record.
-__global__ __launch_bounds__(kT) void k_check_finalize(const double* __restrict__ part, int nbU,
-                                                       int nbV, const double* __restrict__ G,
-                                                       const double* __restrict__ H, int kp, int k,
-                                                       int final_check, DevState* st,
-                                                       double* __restrict__ trace) {
-  __shared__ double sh[kT / kWave];
-  __shared__ double acc[2][8];
-  if (st->stop) return;
-  for (int side = 0; side < 2; ++side) {
-    const int b0 = side == 0 ? 0 : nbU;
-    const int b1 = side == 0 ? nbU : nbU + nbV;
-    for (int f = 0; f < 8; ++f) {
-      double v = (f == 2) ? -INFINITY : (f == 7 ? INFINITY : 0.0);
-      for (int b = b0 + threadIdx.x; b < b1; b += kT) {
-        const double x = part[(int64_t)b * kCheckFields + f];
-        v = (f == 2) ? fmax(v, x) : (f == 7 ? fmin(v, x) : v + x);
-      }
-      v = (f == 2) ? block_max<kT>(v, sh) : (f == 7 ? block_min<kT>(v, sh) : block_sum<kT>(v, sh));
-      if (threadIdx.x == 0) acc[side][f] = v;
+    double hg = 0.0;
+    for (int e = threadIdx.x; e < kp * kp; e += kT) hg = fma(H[e], G[e], hg);
+    v[16] = hg;
+    const int kind[NF] = {0, 0, 1, 0, 0, 0, 0, 2, 0, 0, 1, 0, 0, 0, 0, 2, 0};
+    double a[NF];
+    block_reduce_fields<kT, NF>(v, kind, sh, a);
+    if (threadIdx.x != 0) return;
+    const double nx2 = st->nx2;
+    const double f = 0.5 * nx2 - a[5] + 0.5 * a[16];
+    const double nx = sqrt(nx2);
+    const double nU = sqrt(a[4]), nV = sqrt(a[12]);
+    const double feas = fmax(nU > 0.0 ? sqrt(a[3]) / nU : 0.0, nV > 0.0 ? sqrt(a[11]) / nV : 0.0);
+    const double pgu = (nV > 0.0 && nx > 0.0) ? sqrt(a[0]) / (nx * nV) : 0.0;
+    const double pgv = (nU > 0.0 && nx > 0.0) ? sqrt(a[8]) / (nx * nU) : 0.0;
+    const double kkt = fmax(feas, fmax(pgu, pgv));
+    const double relerr = nx > 0.0 ? sqrt(fmax(2.0 * f, 0.0)) / nx : 0.0;
+    const double negs = a[6] + a[14];
+    st->f = f;
+    st->relerr = relerr;
+    st->kkt = kkt;
+    st->kkt_feas = feas;
+    st->kkt_pg_u = pgu;
+    st->kkt_pg_v = pgv;
+    st->delta_w = fmax(a[2], a[10]);
+    st->sigma_u = a[1];
+    st->sigma_v = a[9];
+    st->sigma_w = a[1] + a[9];
+    st->min_w = fmin(a[7], a[15]);
+    st->re_paper = st->relerr_svd > 0.0 ? relerr / st->relerr_svd : NAN;
+    const bool feasible = negs == 0.0;
+    hit = feasible && ((st->kkt_tol >= 0.0 && kkt <= st->kkt_tol) ||
+                       (st->relerr_tol >= 0.0 && relerr - st->relerr_svd <= st->relerr_tol) ||
+                       st->mode == 3);
+    if (!isfinite(f) || !isfinite(kkt)) st->numeric_error = 1;
+    if (trace != nullptr && st->ntrace < st->trace_cap) {
+      double* o = trace + (int64_t)st->ntrace * kTraceFields;
+      o[0] = (double)k; o[1] = f; o[2] = relerr; o[3] = kkt; o[4] = st->min_w;
+      o[5] = (double)(negs > 0.0 ? kPhaseExt : kPhaseHals);
+      o[6] = (double)wall_clock64() * st->ns_per_tick;
+      o[7] = negs;
+      st->ntrace += 1;
     }
+    if (hit || st->numeric_error) stop = true;
+  } else if (threadIdx.x != 0) {
+    return;
   }
-  double hg = 0.0;
-  for (int e = threadIdx.x; e < kp * kp; e += kT) hg = fma(H[e], G[e], hg);
-  hg = block_sum<kT>(hg, sh);
-  if (threadIdx.x != 0) return;
-  const double nx2 = st->nx2;
-  const double f = 0.5 * nx2 - acc[0][5] + 0.5 * hg;
-  const double nx = sqrt(nx2);
-  const double nU = sqrt(acc[0][4]), nV = sqrt(acc[1][4]);
-  const double feas = fmax(nU > 0.0 ? sqrt(acc[0][3]) / nU : 0.0, nV > 0.0 ? sqrt(acc[1][3]) / nV : 0.0);
-  const double pgu = (nV > 0.0 && nx > 0.0) ? sqrt(acc[0][0]) / (nx * nV) : 0.0;
-  const double pgv = (nU > 0.0 && nx > 0.0) ? sqrt(acc[1][0]) / (nx * nU) : 0.0;
-  const double kkt = fmax(feas, fmax(pgu, pgv));
-  const double relerr = nx > 0.0 ? sqrt(fmax(2.0 * f, 0.0)) / nx : 0.0;
-  const double negs = acc[0][6] + acc[1][6];
-  st->f = f;
-  st->relerr = relerr;
-  st->kkt = kkt;
-  st->kkt_feas = feas;
-  st->kkt_pg_u = pgu;
-  st->kkt_pg_v = pgv;
-  st->delta_w = fmax(acc[0][2], acc[1][2]);
-  st->sigma_u = acc[0][1];
-  st->sigma_v = acc[1][1];
-  st->sigma_w = acc[0][1] + acc[1][1];
-  st->min_w = fmin(acc[0][7], acc[1][7]);
-  st->re_paper = st->relerr_svd > 0.0 ? relerr / st->relerr_svd : NAN;
-  const bool feasible = negs == 0.0;
-  const bool hit = feasible && ((st->kkt_tol >= 0.0 && kkt <= st->kkt_tol) ||
-                                (st->relerr_tol >= 0.0 && relerr - st->relerr_svd <= st->relerr_tol) ||
-                                st->mode == 3);
-  if (!isfinite(f) || !isfinite(kkt)) st->numeric_error = 1;
-  if (trace != nullptr && st->ntrace < st->trace_cap) {
-    double* o = trace + (int64_t)st->ntrace * kTraceFields;
-    o[0] = (double)k; o[1] = f; o[2] = relerr; o[3] = kkt; o[4] = st->min_w;
-    o[5] = (double)(negs > 0.0 ? kPhaseExt : kPhaseHals);
-    o[6] = (double)wall_clock64() * st->ns_per_tick;
-    o[7] = negs;
-    st->ntrace += 1;
-  }
-  if (hit || final_check || st->numeric_error) {
+  if (stop) {
     st->stop = 1;
     st->converged = hit ? 1 : 0;
+    st->iters = k;
+  } else {
+    st->iters = k + 1;
+    if (st->phase == kPhaseExt) st->ext_done += 1;
   }
-}
-
-// Counts a completed outer iteration (runs after the V half).
-__global__ void k_tail(DevState* st) {
-  if (threadIdx.x != 0 || st->stop) return;
-  st->iters += 1;
-  if (st->phase == kPhaseExt) st->ext_done += 1;
 }
 
 __global__ void k_clip(float* __restrict__ A, int64_t count) {
@@ -450,24 +593,20 @@ __global__ void k_clip(float* __restrict__ A, int64_t count) {
 }
 
 template <int KP>
-void rowupdate_launch(float* A, int64_t rows, int r, const float* P, const double* G, DevState* st,
-                      int half, int sweeps, int first, int want_pg, double* part, hipStream_t s) {
+void rowupdate_launch(const float* A, float* Aout, int64_t rows, int r, const float* P, int nsplit,
+                      int64_t pstride, const double* G, DevState* st, int half, int sweeps,
+                      int flags, double* rec, double* gpart, const double* headU, int nbU,
+                      const double* headV, int nbV, hipStream_t s) {
   using TM = Team<KP>;
   dim3 g((unsigned)((rows + TM::RB - 1) / TM::RB)), b(TM::NT);
-  hipLaunchKernelGGL((k_rowupdate<KP>), g, b, 0, s, A, rows, r, P, G, st, half, sweeps, first,
-                     want_pg, part);
+  hipLaunchKernelGGL((k_rowupdate<KP>), g, b, 0, s, A, Aout, rows, r, P, nsplit, pstride, G, st,
+                     half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV);
 }
 
 template <int KP>
-void check_launch(const float* U, int64_t m, const float* P, const double* G, const float* V,
-                  int64_t n, const float* Q, const double* H, int r, double* part, int* nbU,
-                  int* nbV, DevState* st, hipStream_t s) {
-  using TM = Team<KP>;
-  const int bu = (int)((m + TM::RB - 1) / TM::RB), bv = (int)((n + TM::RB - 1) / TM::RB);
-  *nbU = bu;
-  *nbV = bv;
-  hipLaunchKernelGGL((k_check<KP>), dim3((unsigned)(bu + bv)), dim3(TM::NT), 0, s, U, m, P, G, V, n,
-                     Q, H, r, bu, st, part);
+void gram_fin_launch(const double* gpart, int nparts, double* out, hipStream_t s) {
+  constexpr int NE = 16 * ((KP / 4) * (KP / 4 + 1) / 2);
+  hipLaunchKernelGGL((k_gram_fin<KP>), dim3((NE + 3) / 4), dim3(256), 0, s, gpart, nparts, out);
 }
 
 }  // namespace
@@ -501,58 +640,49 @@ hipError_t launch_factor_stats(const float* A, int64_t count, int r, double* par
   return hipGetLastError();
 }
 
-hipError_t launch_setup_state2(const double* statpart, int nbU, int nbV, const double* xpart,
-                               int nxpart, double step_u, double step_v, int ext_iters,
-                               DevState* st, double* negpart, int nneg, hipStream_t s) {
-  hipLaunchKernelGGL(k_setup_state, dim3(1), dim3(256), 0, s, statpart, nbU, nbV, xpart, nxpart,
-                     step_u, step_v, ext_iters, st, negpart, nneg);
+hipError_t launch_setup_state(const double* statpart, int nbU, int nbV, const double* xpart,
+                              int nxpart, double step_u, double step_v, int ext_iters,
+                              DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_setup_state, dim3(1), dim3(64), 0, s, statpart, nbU, nbV, xpart, nxpart,
+                     step_u, step_v, ext_iters, st);
   return hipGetLastError();
 }
 
-hipError_t launch_head(const double* negpart, int nparts, DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_head, dim3(1), dim3(kT), 0, s, negpart, nparts, st);
-  return hipGetLastError();
-}
+int gram_part_len(int kp) { return 16 * ((kp / 4) * (kp / 4 + 1) / 2); }
 
-hipError_t launch_tail(DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_tail, dim3(1), dim3(64), 0, s, st);
-  return hipGetLastError();
-}
-
-hipError_t launch_rowupdate(float* A, int64_t rows, int r, int kp, const float* P, const double* G,
-                            DevState* st, int half, int sweeps, int first, int want_pg,
-                            double* part, hipStream_t s) {
+hipError_t launch_rowupdate(const float* A, float* Aout, int64_t rows, int r, int kp, const float* P,
+                            int nsplit, int64_t pstride, const double* G, DevState* st, int half,
+                            int sweeps, int flags, double* rec, double* gpart, const double* headU,
+                            int nbU, const double* headV, int nbV, hipStream_t s) {
   switch (kp) {
-    case 8: rowupdate_launch<8>(A, rows, r, P, G, st, half, sweeps, first, want_pg, part, s); break;
-    case 16: rowupdate_launch<16>(A, rows, r, P, G, st, half, sweeps, first, want_pg, part, s); break;
-    case 32: rowupdate_launch<32>(A, rows, r, P, G, st, half, sweeps, first, want_pg, part, s); break;
-    default: rowupdate_launch<64>(A, rows, r, P, G, st, half, sweeps, first, want_pg, part, s); break;
+    case 8: rowupdate_launch<8>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, s); break;
+    case 16: rowupdate_launch<16>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, s); break;
+    case 32: rowupdate_launch<32>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, s); break;
+    default: rowupdate_launch<64>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, s); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_pbcd_decide(const double* part, int nparts, int half, int first, DevState* st,
+hipError_t launch_gram_fin(const double* gpart, int nparts, int kp, double* out, hipStream_t s) {
+  switch (kp) {
+    case 8: gram_fin_launch<8>(gpart, nparts, out, s); break;
+    case 16: gram_fin_launch<16>(gpart, nparts, out, s); break;
+    case 32: gram_fin_launch<32>(gpart, nparts, out, s); break;
+    default: gram_fin_launch<64>(gpart, nparts, out, s); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pbcd_decide(const double* rec, int nparts, int half, int first, DevState* st,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_pbcd_decide, dim3(1), dim3(kT), 0, s, part, nparts, half, first, st);
+  hipLaunchKernelGGL(k_pbcd_decide, dim3(1), dim3(kT), 0, s, rec, nparts, half, first, st);
   return hipGetLastError();
 }
 
-hipError_t launch_check(const float* U, int64_t m, const float* P, const double* G, const float* V,
-                        int64_t n, const float* Q, const double* H, int r, int kp, double* part,
-                        int* nbU, int* nbV, DevState* st, hipStream_t s) {
-  switch (kp) {
-    case 8: check_launch<8>(U, m, P, G, V, n, Q, H, r, part, nbU, nbV, st, s); break;
-    case 16: check_launch<16>(U, m, P, G, V, n, Q, H, r, part, nbU, nbV, st, s); break;
-    case 32: check_launch<32>(U, m, P, G, V, n, Q, H, r, part, nbU, nbV, st, s); break;
-    default: check_launch<64>(U, m, P, G, V, n, Q, H, r, part, nbU, nbV, st, s); break;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_check_finalize(const double* part, int nbU, int nbV, const double* G,
-                                 const double* H, int kp, int k, int final_check, DevState* st,
-                                 double* trace, hipStream_t s) {
-  hipLaunchKernelGGL(k_check_finalize, dim3(1), dim3(kT), 0, s, part, nbU, nbV, G, H, kp, k,
+hipError_t launch_finalize(const double* recU, int nbU, const double* recV, int nbV, const double* G,
+                           const double* H, int kp, int k, int due, int final_check, DevState* st,
+                           double* trace, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kT), 0, s, recU, nbU, recV, nbV, G, H, kp, k, due,
                      final_check, st, trace);
   return hipGetLastError();
 }

@@ -90,6 +90,8 @@ SIGNATURES = [
                                      c_double, POINTER(Kkt)]),
     ("enmf_time_products", c_int32, [c_void_p, POINTER(Matrix), c_int32, c_int32,
                                      POINTER(c_double), POINTER(c_double)]),
+    ("enmf_kernel_timing", c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double),
+                                     POINTER(c_int32)]),
 ]
 
 
@@ -266,6 +268,13 @@ class Context:
         a, b = c_double(), c_double()
         self._call(self._lib.enmf_time_products, byref(M), k, reps, byref(a), byref(b))
         return a.value, b.value
+
+    def kernel_timing(self, period):
+        """Set the in-solve sampling period of the streaming kernels (0 = off) and
+        return (xv_ms, xtu_ms, samples) accumulated since the previous call."""
+        a, b, n = c_double(), c_double(), c_int32()
+        self._call(self._lib.enmf_kernel_timing, period, byref(a), byref(b), byref(n))
+        return a.value, b.value, n.value
 
     def solve(self, X, r, omega, oversample=10, power_iters=2, rho0=1.0, rot_max_iter=100,
               rot_tol=1e-10, **iter_opts):
