@@ -43,8 +43,8 @@ typedef enum {
   ENMF_ENOMEM = 2,    /* device workspace could not be allocated */
   ENMF_EDEVICE = 3,   /* a HIP runtime error (message in enmf_last_error) */
   ENMF_ENUMERIC = 4,  /* non-finite objective or residual; U, V hold the last iterate */
-  ENMF_EBUSY = 5,
-  ENMF_ECLOSED = 6
+  ENMF_EBUSY = 5,     /* enmf_serve_poll: the request has not finished yet */
+  ENMF_ECLOSED = 6    /* enmf_serve_submit after enmf_serve_stop began */
 } enmf_status;
 
 typedef enum { ENMF_F32 = 0, ENMF_BF16 = 1, ENMF_F16 = 2 } enmf_dtype;
@@ -196,6 +196,69 @@ typedef struct {
 
 enmf_status enmf_objective_kkt(enmf_ctx* ctx, const enmf_matrix* X, int32_t r, const float* U,
                                const float* V, double relerr_svd, enmf_kkt* out_host);
+
+/* ---- serving (many solves of uneven shape in flight together) ----
+ * A server runs Algorithm 3 end to end (randomized SVD init, ADMM rotation,
+ * exterior phase and HALS with the KKT check, final objective) for every
+ * submitted request.  Requests are admitted into slots as slots and device
+ * memory free up, and all admitted solves advance together: each device
+ * launch gives every running solve one workgroup and a bounded amount of work
+ * (tick_budget), so requests that arrive while others run join at the next
+ * launch.  A solve's arithmetic does not depend on what else is in flight.
+ * Served solves support r <= 32 and r + oversample <= 48, a fixed number of
+ * PBCD sweeps (pbcd_eps = 0) and modes 0, 1 and 3.  The request's trace is
+ * not recorded.
+ *
+ * Ownership: X, the omega of svd, U_out and V_out are caller-owned device
+ * buffers that must stay valid and untouched until the request has finished
+ * (enmf_serve_poll returned something other than ENMF_EBUSY).  U_out and
+ * V_out receive the factors (m x r and n x r, float32).  The server owns a
+ * device arena of hbm_budget_bytes for the solves' workspace; a request is
+ * admitted only when its workspace fits in what is free, and one whose
+ * workspace can never fit is refused at submission.  The server uses its
+ * own stream on the context's device.  Submit and poll are thread-safe. */
+typedef struct enmf_server enmf_server;
+
+typedef struct {
+  uint64_t hbm_budget_bytes;  /* device arena for admitted solves' workspace; 0 = 1 GiB */
+  int32_t max_slots;          /* solves in flight, one workgroup each; 0 = 512 */
+  int32_t tick_budget;        /* work per solve per launch, in units of 2^20 multiply-adds; 0 = 64 */
+} enmf_serve_opts;
+
+typedef struct {
+  enmf_matrix X;
+  int32_t r;
+  int32_t reserved;
+  enmf_svd_opts svd;          /* omega required (n x (r + oversample)) */
+  enmf_rotate_opts rot;
+  enmf_iter_opts it;          /* pbcd_eps must be 0; relerr_svd is computed by the server */
+  float* U_out;
+  float* V_out;
+} enmf_request;
+
+/* Start a server on ctx's device (the context itself is not used afterwards
+ * and may serve other calls).  ENMF_ENOMEM if the arena cannot be allocated. */
+enmf_status enmf_serve_start(enmf_ctx* ctx, const enmf_serve_opts* opts, enmf_server** out);
+
+/* Queue a request without blocking; *ticket identifies it.  ENMF_EINVAL for a
+ * bad request, ENMF_ENOMEM if its workspace exceeds hbm_budget_bytes,
+ * ENMF_ECLOSED after stop. */
+enmf_status enmf_serve_submit(enmf_server* srv, const enmf_request* req, uint64_t* ticket_host);
+
+/* ENMF_EBUSY while the request is queued or running.  Once finished: fills
+ * *report_host (iters, phase, f, relerr, kkt, ...; re_paper = relerr /
+ * relerr_svd) and *latency_s_host (seconds from submission to completion),
+ * returns the solve's status (ENMF_OK, or ENMF_ENUMERIC), and forgets the
+ * ticket.  ENMF_EINVAL for an unknown ticket. */
+enmf_status enmf_serve_poll(enmf_server* srv, uint64_t ticket, enmf_iter_report* report_host,
+                            double* latency_s_host);
+
+/* Stop accepting requests, finish every queued and running one, then free
+ * the server (results not yet polled are dropped). */
+enmf_status enmf_serve_stop(enmf_server* srv);
+
+/* Text of the server's last failed submit or poll. */
+const char* enmf_serve_last_error(const enmf_server* srv);
 
 /* ---- instrumentation ----
  * Average device time (ms) of one launch of the X B and of the X^T A

@@ -47,6 +47,9 @@ struct enmf_ctx {
 };
 
 
+int enmf::ctx_device(const enmf_ctx* c) { return c->device; }
+void enmf::ctx_set_error(enmf_ctx* c, const char* msg) { c->err = msg; }
+
 namespace {
 
 enmf_status fail(enmf_ctx* c, enmf_status s, const std::string& msg) {

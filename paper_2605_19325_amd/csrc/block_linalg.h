@@ -1,0 +1,212 @@
+// Block-level float64 linear algebra shared by the kernels of libenmf: one
+// workgroup of kBlk threads owns a small matrix in LDS.
+#pragma once
+
+#include <math.h>
+
+#include "dev_common.h"
+
+namespace enmf {
+
+constexpr int kBlk = 256;   // threads of the workgroups that call these routines
+
+// ---------------------------------------------------------------------------
+// Symmetric eigensolver: parallel cyclic Jacobi (Brent-Luk round-robin
+// ordering) on an LDS-resident k x k float64 matrix S with eigenvector
+// matrix E.  Each round applies n2/2 disjoint plane rotations, chosen with
+// the stable formula of Golub & Van Loan (sym.schur2), first to the
+// columns of S and E, then to the rows of S.  An odd k is padded with one
+// zero row/column that no rotation ever touches.  On return diag(S) holds
+// the eigenvalues and the columns of E the eigenvectors; perm lists the
+// first k indices by descending eigenvalue.
+// ---------------------------------------------------------------------------
+template <int MAXW>
+struct JacobiT {
+  static constexpr int LD = MAXW + 1;
+  double S[MAXW * LD];
+  double E[MAXW * LD];
+  double cs[MAXW];
+  double red[kBlk / kWave];
+  int pq[MAXW];
+  int perm[MAXW];
+};
+
+__device__ __forceinline__ int rr_player(int pos, int round, int n2) {
+  return pos == 0 ? 0 : ((pos - 1 + round) % (n2 - 1)) + 1;
+}
+
+template <int MAXW>
+__device__ void jacobi_eig(JacobiT<MAXW>& sm, int k) {
+  constexpr int kLdJ = JacobiT<MAXW>::LD;
+  const int n2 = k + (k & 1);
+  double* S = sm.S;
+  double* E = sm.E;
+  for (int e = threadIdx.x; e < n2 * n2; e += kBlk) {
+    const int a = e / n2, c = e % n2;
+    E[a * kLdJ + c] = (a == c) ? 1.0 : 0.0;
+    if (a >= k || c >= k) S[a * kLdJ + c] = 0.0;
+  }
+  __syncthreads();
+  const int npairs = n2 / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int e = threadIdx.x; e < k * k; e += kBlk) {
+      const int a = e / k, c = e % k;
+      const double v = S[a * kLdJ + c];
+      if (a == c) dia += v * v; else off += v * v;
+    }
+    off = block_sum<kBlk>(off, sm.red);
+    dia = block_sum<kBlk>(dia, sm.red);
+    if (!(off > 1e-30 * dia) || off == 0.0) break;
+    for (int round = 0; round < n2 - 1; ++round) {
+      if (threadIdx.x < npairs) {
+        int p = rr_player(threadIdx.x, round, n2);
+        int q = rr_player(n2 - 1 - threadIdx.x, round, n2);
+        if (p > q) { const int t = p; p = q; q = t; }
+        const double apq = S[p * kLdJ + q];
+        double c = 1.0, s = 0.0;
+        if (fabs(apq) > 1e-300) {
+          const double tau = (S[q * kLdJ + q] - S[p * kLdJ + p]) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+        }
+        sm.pq[2 * threadIdx.x] = p;
+        sm.pq[2 * threadIdx.x + 1] = q;
+        sm.cs[2 * threadIdx.x] = c;
+        sm.cs[2 * threadIdx.x + 1] = s;
+      }
+      __syncthreads();
+      // S <- J^T S J in one pass: the pairs partition the indices, so every
+      // 2 x 2 block (pair P1 rows, pair P2 columns) transforms on its own as
+      // J1^T S_block J2.  E <- E J column pair by column pair.
+      for (int task = threadIdx.x; task < npairs * npairs; task += kBlk) {
+        const int P1 = task / npairs, P2 = task % npairs;
+        const double c1 = sm.cs[2 * P1], s1 = sm.cs[2 * P1 + 1];
+        const double c2 = sm.cs[2 * P2], s2 = sm.cs[2 * P2 + 1];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const int p1 = sm.pq[2 * P1], q1 = sm.pq[2 * P1 + 1];
+        const int p2 = sm.pq[2 * P2], q2 = sm.pq[2 * P2 + 1];
+        const double a = S[p1 * kLdJ + p2], b = S[p1 * kLdJ + q2];
+        const double cc = S[q1 * kLdJ + p2], d = S[q1 * kLdJ + q2];
+        const double ra = c1 * a - s1 * cc, rb = c1 * b - s1 * d;     // rows: J1^T
+        const double rc = s1 * a + c1 * cc, rd = s1 * b + c1 * d;
+        double na = c2 * ra - s2 * rb, nb = s2 * ra + c2 * rb;        // columns: J2
+        double nc = c2 * rc - s2 * rd, nd = s2 * rc + c2 * rd;
+        if (P1 == P2) { nb = 0.0; nc = 0.0; }                        // the annihilated pair
+        S[p1 * kLdJ + p2] = na;
+        S[p1 * kLdJ + q2] = nb;
+        S[q1 * kLdJ + p2] = nc;
+        S[q1 * kLdJ + q2] = nd;
+      }
+      for (int task = threadIdx.x; task < npairs * n2; task += kBlk) {
+        const int pr = task / n2, x = task % n2;
+        const double c = sm.cs[2 * pr], s = sm.cs[2 * pr + 1];
+        if (s == 0.0) continue;
+        const int p = sm.pq[2 * pr], q = sm.pq[2 * pr + 1];
+        const double a = E[x * kLdJ + p], b = E[x * kLdJ + q];
+        E[x * kLdJ + p] = c * a - s * b;
+        E[x * kLdJ + q] = s * a + c * b;
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < k; ++i) sm.perm[i] = i;
+    for (int i = 0; i < k; ++i) {
+      int best = i;
+      for (int j = i + 1; j < k; ++j)
+        if (S[sm.perm[j] * kLdJ + sm.perm[j]] > S[sm.perm[best] * kLdJ + sm.perm[best]]) best = j;
+      const int t = sm.perm[i]; sm.perm[i] = sm.perm[best]; sm.perm[best] = t;
+    }
+  }
+  __syncthreads();
+}
+
+template <int MAXW>
+__device__ __forceinline__ double eigval(const JacobiT<MAXW>& sm, int j) {
+  return sm.S[sm.perm[j] * JacobiT<MAXW>::LD + sm.perm[j]];
+}
+template <int MAXW>
+__device__ __forceinline__ double eigvec(const JacobiT<MAXW>& sm, int a, int j) {
+  return sm.E[a * JacobiT<MAXW>::LD + sm.perm[j]];
+}
+
+// Polar factor of the KP x KP matrix M held in X (zero padded), in place:
+// the Newton-Schulz iteration X <- 1.5 X - 0.5 X X^T X from X0 = 1.5 M /
+// ||M||_F (singular values in (0, 1.5], inside the convergence interval
+// (0, sqrt 3)), in float64 until ||X_{k+1} - X_k||_F^2 <= 1e-26 or 100 steps.
+// T is scratch.  Returns false (X untouched) when ||M||_F is 0 or not finite.
+template <int KP>
+__device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double* red) {
+  constexpr int TT = KP / 16;
+  static_assert(KP % 16 == 0, "polar_ns_block needs KP a multiple of 16");
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double nrm = 0.0;
+  for (int e = threadIdx.x; e < KP * KP; e += kBlk) nrm = fma(X[e / KP][e % KP], X[e / KP][e % KP], nrm);
+  nrm = sqrt(block_sum<kBlk>(nrm, red));
+  if (!(nrm > 0.0) || !isfinite(nrm)) return false;
+  const double sc = 1.5 / nrm;
+  for (int e = threadIdx.x; e < KP * KP; e += kBlk) X[e / KP][e % KP] *= sc;
+  __syncthreads();
+  for (int it = 0; it < 100; ++it) {
+    // T = X^T X
+    double acc[TT][TT];
+#pragma unroll
+    for (int i = 0; i < TT; ++i)
+#pragma unroll
+      for (int j = 0; j < TT; ++j) acc[i][j] = 0.0;
+    for (int q = 0; q < KP; ++q) {
+      double av[TT], bv[TT];
+#pragma unroll
+      for (int i = 0; i < TT; ++i) av[i] = X[q][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < TT; ++j) bv[j] = X[q][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < TT; ++i)
+#pragma unroll
+        for (int j = 0; j < TT; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < TT; ++i)
+#pragma unroll
+      for (int j = 0; j < TT; ++j) T[ty + 16 * i][tx + 16 * j] = acc[i][j];
+    __syncthreads();
+    // X_new = 1.5 X - 0.5 X T
+#pragma unroll
+    for (int i = 0; i < TT; ++i)
+#pragma unroll
+      for (int j = 0; j < TT; ++j) acc[i][j] = 0.0;
+    for (int q = 0; q < KP; ++q) {
+      double av[TT], bv[TT];
+#pragma unroll
+      for (int i = 0; i < TT; ++i) av[i] = X[ty + 16 * i][q];
+#pragma unroll
+      for (int j = 0; j < TT; ++j) bv[j] = T[q][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < TT; ++i)
+#pragma unroll
+        for (int j = 0; j < TT; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    }
+    double d2 = 0.0;
+    double xn[TT][TT];
+#pragma unroll
+    for (int i = 0; i < TT; ++i)
+#pragma unroll
+      for (int j = 0; j < TT; ++j) {
+        const double x = X[ty + 16 * i][tx + 16 * j];
+        xn[i][j] = 1.5 * x - 0.5 * acc[i][j];
+        d2 = fma(xn[i][j] - x, xn[i][j] - x, d2);
+      }
+    d2 = block_sum<kBlk>(d2, red);   // also orders every read of X before the writes below
+#pragma unroll
+    for (int i = 0; i < TT; ++i)
+#pragma unroll
+      for (int j = 0; j < TT; ++j) X[ty + 16 * i][tx + 16 * j] = xn[i][j];
+    __syncthreads();
+    if (d2 <= 1e-26) break;
+  }
+  return true;
+}
+
+}  // namespace enmf

@@ -73,6 +73,10 @@ inline int pad_width(int k) {
   return 80;
 }
 
+// Context accessors for the serving front end (api.cpp).
+int ctx_device(const enmf_ctx* c);
+void ctx_set_error(enmf_ctx* c, const char* msg);
+
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip files).  All enqueue on `s`, return
 // hipSuccess or the launch error.

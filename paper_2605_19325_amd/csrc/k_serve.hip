@@ -1,0 +1,896 @@
+// Serving loop: many independent eNMF solves of uneven shape, advanced
+// together one launch ("tick") at a time.  One workgroup owns one request and
+// runs its whole solve as a resumable state machine: the randomized SVD
+// initialisation (section 3 opening, Algorithm 3 step 2), the ADMM rotation
+// (section 3.1, Algorithm 1), the exterior phase and HALS (sections 3.2-3.3,
+// Algorithms 2-3) with the KKT check of every iteration, and the final
+// objective.  Everything that survives a tick lives in device memory (the
+// slot's state and workspace), so a request computes the same numbers
+// whether it runs alone or beside others, and whatever the tick budget.
+//
+// Within a workgroup every step is a block-level routine: tall-skinny
+// products X B and X^T A stream X in LDS tiles and accumulate in float32
+// (X is float32, bfloat16 or float16); Grams and cross products are float64
+// with fixed-order combination; the range finder orthonormalises with the
+// eigenpairs of the Gram (Jacobi in LDS); the Procrustes step takes the
+// Newton-Schulz polar factor; row updates reuse the row-team code of the
+// per-iteration kernels at a padded width of 32.
+#include <math.h>
+
+#include "block_linalg.h"
+#include "dev_common.h"
+#include "enmf_internal.h"
+#include "row_team.h"
+#include "serve_internal.h"
+
+namespace enmf {
+
+namespace {
+
+constexpr int SNT = kBlk;        // threads per serving workgroup
+constexpr int SKP = kServeKP;    // padded factor width
+constexpr int SKB = kServeKK;    // padded range-finder width
+constexpr double kOrthTau = 1e-15;
+
+template <int XT> using XE = typename XElem<XT>::T;
+
+// LDS of the phases; one union per workgroup.
+struct ProdSmem {
+  float X[128 * 33];
+  float B[32 * SKB];
+};
+struct GramSmem {
+  double A[32 * SKB];
+  double B[32 * SKB];
+};
+struct RowSmem {
+  double G[SKP * SKP];
+  __align__(16) float a[64][SKP + 4];
+  float g[64][SKP + 1];
+  double sh[16 * (SNT / kWave)];
+  double out[16];
+};
+struct EigSmem {
+  JacobiT<SKB> j;
+  double aux[2 * SKB];
+};
+struct AdmmSmem {
+  double R[SKP * SKP];
+  double X[SKP][SKP + 1];
+  double T[SKP][SKP + 1];
+  double red[SNT / kWave];
+};
+union ServeSmem {
+  ProdSmem p;
+  GramSmem g;
+  RowSmem w;
+  EigSmem e;
+  AdmmSmem a;
+};
+
+__device__ __forceinline__ int64_t imin(int64_t a, int64_t b) { return a < b ? a : b; }
+
+// ---------------------------------------------------------------------------
+// Tall-skinny products (float32 accumulation).  Tiles of 128 output rows; the
+// contraction advances 32 at a time through LDS.  Thread t owns one output
+// row and KB/2 of its columns; the next chunk's global loads are issued
+// before the barrier that retires the current one.
+// ---------------------------------------------------------------------------
+
+// out (m x k, ld ldo) = X (m x n, ld) B (n x k, ld ldb).
+template <int XT, int KB>
+__device__ void bx_xb(const XE<XT>* __restrict__ X, int64_t m, int64_t n, int64_t ld,
+                      const float* __restrict__ B, int ldb, int k, float* __restrict__ out, int ldo,
+                      ProdSmem& sm) {
+  constexpr int CPT = KB / 2;
+  constexpr int NB = 32 * KB / SNT;
+  const int t = threadIdx.x, row = t & 127, cg = t >> 7;
+  for (int64_t r0 = 0; r0 < m; r0 += 128) {
+    float acc[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) acc[c] = 0.f;
+    for (int64_t j0 = 0; j0 < n; j0 += 32) {
+      float xv[16], bv[NB];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = t + SNT * u, rr = e >> 5, cc = e & 31;
+        const int64_t gi = r0 + rr, gj = j0 + cc;
+        xv[u] = (gi < m && gj < n) ? to_f32<XT>(X[gi * ld + gj]) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int e = t + SNT * u, rr = e / KB, cc = e % KB;
+        const int64_t gj = j0 + rr;
+        bv[u] = (gj < n && cc < k) ? B[gj * ldb + cc] : 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = t + SNT * u;
+        sm.X[(e >> 5) * 33 + (e & 31)] = xv[u];
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) sm.B[t + SNT * u] = bv[u];
+      __syncthreads();
+#pragma unroll 8
+      for (int kk = 0; kk < 32; ++kk) {
+        const float x = sm.X[row * 33 + kk];
+        const float* b = sm.B + kk * KB + cg * CPT;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) acc[c] = fmaf(x, b[c], acc[c]);
+      }
+    }
+    const int64_t gi = r0 + row;
+    if (gi < m) {
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int col = cg * CPT + c;
+        if (col < k) out[gi * ldo + col] = acc[c];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// out (n x k, ld ldo) = X^T (X m x n, ld) A (m x k, ld lda).
+template <int XT, int KB>
+__device__ void bx_xta(const XE<XT>* __restrict__ X, int64_t m, int64_t n, int64_t ld,
+                       const float* __restrict__ A, int lda, int k, float* __restrict__ out, int ldo,
+                       ProdSmem& sm) {
+  constexpr int CPT = KB / 2;
+  constexpr int NB = 32 * KB / SNT;
+  const int t = threadIdx.x, jr = t & 127, cg = t >> 7;
+  for (int64_t j0 = 0; j0 < n; j0 += 128) {
+    float acc[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) acc[c] = 0.f;
+    for (int64_t i0 = 0; i0 < m; i0 += 32) {
+      float xv[16], av[NB];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = t + SNT * u, ii = e >> 7, jj = e & 127;
+        const int64_t gi = i0 + ii, gj = j0 + jj;
+        xv[u] = (gi < m && gj < n) ? to_f32<XT>(X[gi * ld + gj]) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int e = t + SNT * u, rr = e / KB, cc = e % KB;
+        const int64_t gi = i0 + rr;
+        av[u] = (gi < m && cc < k) ? A[gi * lda + cc] : 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = t + SNT * u;
+        sm.X[(e >> 7) * 129 + (e & 127)] = xv[u];
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) sm.B[t + SNT * u] = av[u];
+      __syncthreads();
+#pragma unroll 8
+      for (int kk = 0; kk < 32; ++kk) {
+        const float x = sm.X[kk * 129 + jr];
+        const float* a = sm.B + kk * KB + cg * CPT;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) acc[c] = fmaf(x, a[c], acc[c]);
+      }
+    }
+    const int64_t gj = j0 + jr;
+    if (gj < n) {
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int col = cg * CPT + c;
+        if (col < k) out[gj * ldo + col] = acc[c];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int XT>
+__device__ void xb(const XE<XT>* X, int64_t m, int64_t n, int64_t ld, const float* B, int ldb, int k,
+                   float* out, int ldo, ProdSmem& sm) {
+  if (k <= 8) bx_xb<XT, 8>(X, m, n, ld, B, ldb, k, out, ldo, sm);
+  else if (k <= 16) bx_xb<XT, 16>(X, m, n, ld, B, ldb, k, out, ldo, sm);
+  else if (k <= 32) bx_xb<XT, 32>(X, m, n, ld, B, ldb, k, out, ldo, sm);
+  else bx_xb<XT, 48>(X, m, n, ld, B, ldb, k, out, ldo, sm);
+}
+
+template <int XT>
+__device__ void xta(const XE<XT>* X, int64_t m, int64_t n, int64_t ld, const float* A, int lda, int k,
+                    float* out, int ldo, ProdSmem& sm) {
+  if (k <= 8) bx_xta<XT, 8>(X, m, n, ld, A, lda, k, out, ldo, sm);
+  else if (k <= 16) bx_xta<XT, 16>(X, m, n, ld, A, lda, k, out, ldo, sm);
+  else if (k <= 32) bx_xta<XT, 32>(X, m, n, ld, A, lda, k, out, ldo, sm);
+  else bx_xta<XT, 48>(X, m, n, ld, A, lda, k, out, ldo, sm);
+}
+
+// ---------------------------------------------------------------------------
+// out (KB x KB, ld KB) = A^T B for tall A (rows x ka), B (rows x kb), float64
+// (products of the float32 inputs are exact).  Rows are staged 32 at a time;
+// thread groups of RG consecutive lanes own one 4 x 4 output tile and take
+// its rows round robin; the groups combine by butterfly, so every entry has
+// a fixed summation order (and A^T A comes out exactly symmetric).
+// ---------------------------------------------------------------------------
+template <typename TA, typename TB, int KB>
+__device__ void bx_cross(const TA* __restrict__ A, int lda, int ka, const TB* __restrict__ B,
+                         int ldb, int kb, int64_t rows, double* __restrict__ out, GramSmem& sm) {
+  constexpr int NTILE = KB / 4;
+  constexpr int NTASK = NTILE * NTILE;
+  constexpr int RG = NTASK >= SNT ? 1 : SNT / NTASK;
+  constexpr int NL = 32 * KB / SNT;
+  static_assert(RG == 1 || RG == 4 || RG == 16 || RG == 64, "row groups must tile a wave");
+  const int t = threadIdx.x, task = t / RG, rg = t % RG;
+  const bool act = task < NTASK;
+  const int ti = act ? task / NTILE : 0, tj = act ? task % NTILE : 0;
+  double acc[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+  for (int64_t i0 = 0; i0 < rows; i0 += 32) {
+    double av[NL], bv[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int e = t + SNT * u, rr = e / KB, cc = e % KB;
+      const int64_t gi = i0 + rr;
+      av[u] = (gi < rows && cc < ka) ? (double)A[gi * lda + cc] : 0.0;
+      bv[u] = (gi < rows && cc < kb) ? (double)B[gi * ldb + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      sm.A[t + SNT * u] = av[u];
+      sm.B[t + SNT * u] = bv[u];
+    }
+    __syncthreads();
+    if (act) {
+      for (int rr = rg; rr < 32; rr += RG) {
+        const double* x = sm.A + rr * KB + 4 * ti;
+        const double* y = sm.B + rr * KB + 4 * tj;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[4 * u + v] = fma(x[u], y[v], acc[4 * u + v]);
+      }
+    }
+  }
+#pragma unroll
+  for (int o = RG / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] += __shfl_xor(acc[e], o);
+  if (act && rg == 0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(4 * ti + u) * KB + 4 * tj + v] = acc[4 * u + v];
+  }
+  __syncthreads();
+}
+
+// out[i][c] = sum_a A[i][a] T[a][c] for c < kb (T: LDS, ld KB), float64; a
+// row is read whole before it is written, so out may alias A.  out32, when
+// given, receives a float32 copy.
+template <typename TA, typename TO, int KB>
+__device__ void bx_apply(const TA* A, int lda, int ka, int64_t rows, const double* T, int kb, TO* out,
+                         int ldo, float* out32 = nullptr, int ld32 = 0) {
+  for (int64_t i = threadIdx.x; i < rows; i += SNT) {
+    double a[KB];
+#pragma unroll
+    for (int q = 0; q < KB; ++q) a[q] = q < ka ? (double)A[i * lda + q] : 0.0;
+    for (int c = 0; c < kb; ++c) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < KB; ++q) s = fma(a[q], T[q * KB + c], s);
+      out[i * ldo + c] = (TO)s;
+      if (out32) out32[i * ld32 + c] = (float)s;
+    }
+  }
+  __syncthreads();
+}
+
+// sum over all threads, valid in every thread
+__device__ __forceinline__ double bsum(double v, double* red) { return block_sum<SNT>(v, red); }
+
+// ---------------------------------------------------------------------------
+// Range finder
+// ---------------------------------------------------------------------------
+
+// Eigenpairs of the k x k Gram in `g` (global, ld SKB); leaves the sorted
+// eigenvalues in aux[0..k) and the eigenvectors in the Jacobi state.
+__device__ void eig_of(const double* g, int k, EigSmem& sm) {
+  for (int e = threadIdx.x; e < k * k; e += SNT)
+    sm.j.S[(e / k) * JacobiT<SKB>::LD + e % k] = g[(e / k) * SKB + e % k];
+  __syncthreads();
+  jacobi_eig<SKB>(sm.j, k);
+  if (threadIdx.x < k) sm.aux[threadIdx.x] = eigval<SKB>(sm.j, threadIdx.x);
+  __syncthreads();
+}
+
+// T (into the S area, ld SKB) = E diag(lambda^-1/2), zero for lambda <= tau lambda_max.
+__device__ double* orth_factor_lds(int k, EigSmem& sm) {
+  double* T = sm.j.S;
+  const double lmax = sm.aux[0];
+  for (int e = threadIdx.x; e < SKB * SKB; e += SNT) {
+    const int a = e / SKB, j = e % SKB;
+    double v = 0.0;
+    if (a < k && j < k) {
+      const double l = sm.aux[j];
+      const double sc = (l > kOrthTau * lmax && l > 0.0) ? 1.0 / sqrt(l) : 0.0;
+      v = eigvec<SKB>(sm.j, a, j) * sc;
+    }
+    T[e] = v;
+  }
+  __syncthreads();
+  return T;
+}
+
+// Orthonormal basis of the columns of A32 (rows x k): two passes of
+// Q = A E diag(lambda^-1/2) with the eigenpairs of A^T A.  out64 (float64)
+// and out32 (float32) both rows x k; out32 may alias A32.
+__device__ void orth(const float* A32, int64_t rows, int k, double* out64, float* out32,
+                     double* scratch, ServeSmem& sm) {
+  bx_cross<float, float, SKB>(A32, k, k, A32, k, k, rows, scratch, sm.g);
+  eig_of(scratch, k, sm.e);
+  const double* T = orth_factor_lds(k, sm.e);
+  bx_apply<float, double, SKB>(A32, k, k, rows, T, k, out64, k);
+  bx_cross<double, double, SKB>(out64, k, k, out64, k, k, rows, scratch, sm.g);
+  eig_of(scratch, k, sm.e);
+  T = orth_factor_lds(k, sm.e);
+  bx_apply<double, double, SKB>(out64, k, k, rows, T, k, out64, k, out32, k);
+}
+
+// ||X||_F^2 in float64.
+template <int XT>
+__device__ double sumsq_x(const XE<XT>* X, int64_t m, int64_t n, int64_t ld, double* red) {
+  double s = 0.0;
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t j = threadIdx.x; j < n; j += SNT) {
+      const double v = (double)to_f32<XT>(X[i * ld + j]);
+      s = fma(v, v, s);
+    }
+  return bsum(s, red);
+}
+
+// 1/2 ||X - U V^T||_F^2 evaluated directly, float64 (U m x r, V n x r).
+template <int XT>
+__device__ double residual(const XE<XT>* X, int64_t m, int64_t n, int64_t ld, const float* U,
+                           const float* V, int r, ProdSmem& sm, double* red) {
+  // V chunk (32 rows) in sm.B as float; U row in registers.
+  double s = 0.0;
+  const int t = threadIdx.x;
+  for (int64_t j0 = 0; j0 < n; j0 += 32) {
+    __syncthreads();
+    for (int e = t; e < 32 * SKP; e += SNT) {
+      const int rr = e / SKP, cc = e % SKP;
+      const int64_t gj = j0 + rr;
+      sm.B[e] = (gj < n && cc < r) ? V[gj * r + cc] : 0.f;
+    }
+    __syncthreads();
+    const int jn = (int)imin(32, n - j0);
+    for (int64_t i = t; i < m; i += SNT) {
+      double u[SKP];
+#pragma unroll
+      for (int c = 0; c < SKP; ++c) u[c] = c < r ? (double)U[i * r + c] : 0.0;
+      for (int jj = 0; jj < jn; ++jj) {
+        double e = (double)to_f32<XT>(X[i * ld + j0 + jj]);
+        const float* v = sm.B + jj * SKP;
+#pragma unroll
+        for (int c = 0; c < SKP; ++c) e = fma(-u[c], (double)v[c], e);
+        s = fma(e, e, s);
+      }
+    }
+  }
+  return 0.5 * bsum(s, red);
+}
+
+// ---------------------------------------------------------------------------
+// Row passes (exterior phase / HALS / KKT partials) at padded width 32.
+// ---------------------------------------------------------------------------
+
+// One pass over the rows of A (rows x r, ld r) with P (rows x r, ld r) and
+// the Gram already in sm.G.  update: the EXT (push, mask, `sweeps` PBCD
+// sweeps; eqs. negup, pbcdu, d_i) or HALS update of every row, in place.
+// pre: KKT partials at the input rows, else at the output rows.  Leaves in
+// sm.out the 8 check fields (CheckAcc order) and the negative count of the
+// output rows.
+__device__ void row_pass(float* A, int64_t rows, int r, const float* P, RowSmem& sm, bool update,
+                         bool pre, int phase, double step, int sweeps) {
+  using TM = Team<SKP>;
+  constexpr int T = TM::T;
+  const int team = threadIdx.x / T, q = threadIdx.x % T, c0 = 8 * q;
+  const double* sG = sm.G;
+  CheckAcc ck;
+  double negc = 0.0;
+  for (int64_t row0 = 0; row0 < rows; row0 += TM::RB) {
+    const int nrow = (int)imin(rows - row0, TM::RB);
+    const bool valid = team < nrow;
+    stage_rows<SKP, SKP + 4>(A, 1, 0, row0, nrow, r, sm.a);
+    stage_rows<SKP, SKP + 1>(P, 1, 0, row0, nrow, r, sm.g);
+    float a[8];
+    double p[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      a[e] = sm.a[team][c0 + e];
+      p[e] = (double)sm.g[team][c0 + e];
+    }
+    __syncthreads();
+    double t[8];
+    bool have_t = false;
+    if (pre) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sm.a[team][c0 + e] = a[e];
+      __syncthreads();
+      row_times_g<SKP>(sm.a[team], sG, c0, t);
+      have_t = true;
+      if (valid) ck.add(a, t, p, c0, r);
+    }
+    if (update && phase == kPhaseHals) {
+      if (!have_t) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) sm.a[team][c0 + e] = a[e];
+        __syncthreads();
+        row_times_g<SKP>(sm.a[team], sG, c0, t);
+      }
+      const int base = (threadIdx.x % kWave) - q;
+      for (int j = 0; j < r; ++j) {
+        const int o = j / 8, ej = j % 8;
+        double delta = 0.0;
+        if (q == o) {
+          const double gjj = sG[j * SKP + j];
+          if (gjj > 0.0) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              if (e == ej) {
+                const double v = (double)a[e] + (p[e] - t[e]) / gjj;
+                const float nv = (float)(v > 0.0 ? v : 0.0);
+                delta = (double)nv - (double)a[e];
+                a[e] = nv;
+              }
+            }
+          }
+        }
+        delta = __shfl(delta, base + o);
+        const double* gj = sG + j * SKP + c0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] = fma(delta, gj[e], t[e]);
+      }
+      have_t = true;
+    } else if (update) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (a[e] < 0.f) a[e] = (float)((double)a[e] + step);
+      for (int sw = 0; sw < sweeps; ++sw) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) sm.a[team][c0 + e] = a[e];
+        __syncthreads();
+        double s[8];
+        row_times_g<SKP>(sm.a[team], sG, c0, s);
+        float g[8];
+        double num = 0.0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          g[e] = a[e] >= 0.f ? (float)(s[e] - p[e]) : 0.f;
+          num = fma((double)g[e], (double)g[e], num);
+          sm.g[team][c0 + e] = g[e];
+        }
+        __syncthreads();
+        double h[8];
+        row_times_g<SKP>(sm.g[team], sG, c0, h);
+        double den = 0.0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) den = fma((double)g[e], h[e], den);
+        num = team_sum<T>(num);
+        den = team_sum<T>(den);
+        const double d = den > 0.0 ? num / den : 0.0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          if (a[e] >= 0.f) {
+            const double v = (double)a[e] - d * (double)g[e];
+            a[e] = (float)(v > 0.0 ? v : 0.0);
+          }
+        }
+      }
+      have_t = false;
+    }
+    if (!pre) {
+      if (!have_t) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) sm.a[team][c0 + e] = a[e];
+        __syncthreads();
+        row_times_g<SKP>(sm.a[team], sG, c0, t);
+      }
+      if (valid) ck.add(a, t, p, c0, r);
+    }
+    if (valid) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (c0 + e < r) negc += a[e] < 0.f ? 1.0 : 0.0;
+    }
+    if (update) {
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sm.a[team][c0 + e] = valid ? a[e] : 0.f;
+      __syncthreads();
+      float* base = A + row0 * r;
+      for (int e = threadIdx.x; e < nrow * r; e += SNT) base[e] = sm.a[e / r][e % r];
+    }
+    __syncthreads();
+  }
+  double vals[9] = {ck.pg2, ck.sg, ck.mx, ck.ng2, ck.sq, ck.ap, ck.nneg, ck.mn, negc};
+  const int kind[9] = {0, 0, 1, 0, 0, 0, 0, 2, 0};
+  block_reduce_fields<SNT, 9>(vals, kind, sm.sh, sm.out);
+  __syncthreads();
+}
+
+__device__ void load_gram32(const double* G, RowSmem& sm) {
+  for (int e = threadIdx.x; e < SKP * SKP; e += SNT) sm.G[e] = G[e];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// The state machine.  Each call runs one step and returns its cost in
+// multiply-adds; thread 0 updates ctl, and every path ends at a barrier.
+// ---------------------------------------------------------------------------
+template <int XT>
+__device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& ctl, ServeSmem& sm,
+                              double* red) {
+  const XE<XT>* X = reinterpret_cast<const XE<XT>*>(q.X);
+  const int64_t m = q.m, n = q.n, ld = q.ld;
+  const int r = q.r, kk = q.kk;
+  const int t0 = threadIdx.x == 0;
+  const int stage = ctl.stage, sub = ctl.sub;
+
+  if (stage == kStSvd) {
+    const int last_orth = 2 * q.power_iters;   // subs 0..last_orth end with an orthonormalisation
+    if (sub == 0) {
+      xb<XT>(X, m, n, ld, q.omega, kk, kk, q.Y32, kk, sm.p);
+      orth(q.Y32, m, kk, q.Qm64, q.Y32, st.scratch, sm);
+    } else if (sub <= last_orth) {
+      if (sub & 1) {
+        xta<XT>(X, m, n, ld, q.Y32, kk, kk, q.Z32, kk, sm.p);
+        orth(q.Z32, n, kk, q.Qn64, q.Z32, st.scratch, sm);
+      } else {
+        xb<XT>(X, m, n, ld, q.Z32, kk, kk, q.Y32, kk, sm.p);
+        orth(q.Y32, m, kk, q.Qm64, q.Y32, st.scratch, sm);
+      }
+    } else if (sub == last_orth + 1) {
+      // B = Q^T X through Z = X^T Q; SVD of B from the eigenpairs of Z^T Z
+      xta<XT>(X, m, n, ld, q.Y32, kk, kk, q.Z32, kk, sm.p);
+      bx_cross<float, float, SKB>(q.Z32, kk, kk, q.Z32, kk, kk, n, st.scratch, sm.g);
+      eig_of(st.scratch, kk, sm.e);
+      // column sums of Q (float64, fixed order per column)
+      double* colsum = sm.e.aux + SKB;
+      if (threadIdx.x < kk) {
+        double cs = 0.0;
+        for (int64_t i = 0; i < m; ++i) cs += q.Qm64[i * kk + threadIdx.x];
+        colsum[threadIdx.x] = cs;
+      }
+      __syncthreads();
+      // signs (column sum of U positive), sigma, TU into S, TV into scratch
+      double* TU = sm.e.j.S;
+      __shared__ double sgn[SKP], sq[SKP];
+      if (threadIdx.x < r) {
+        const int j = threadIdx.x;
+        double cs = 0.0;
+        for (int a = 0; a < kk; ++a) cs = fma(colsum[a], eigvec<SKB>(sm.e.j, a, j), cs);
+        sgn[j] = cs < 0.0 ? -1.0 : 1.0;
+        const double l = sm.e.aux[j];
+        const double sg = l > 0.0 ? sqrt(l) : 0.0;
+        st.sigma[j] = sg;
+        sq[j] = sqrt(sg);
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < SKB * SKB; e += SNT) {
+        const int a = e / SKB, j = e % SKB;
+        double w = 0.0;
+        if (a < kk && j < r) w = eigvec<SKB>(sm.e.j, a, j) * sgn[j];
+        st.scratch[e] = (j < r && sq[j] > 0.0) ? w / sq[j] : 0.0;
+        TU[e] = j < r ? w * sq[j] : 0.0;
+      }
+      __syncthreads();
+      bx_apply<double, float, SKB>(q.Qm64, kk, kk, m, TU, r, q.U, r);
+      for (int e = threadIdx.x; e < SKB * SKB; e += SNT) TU[e] = st.scratch[e];
+      __syncthreads();
+      bx_apply<float, float, SKB>(q.Z32, kk, kk, n, TU, r, q.V, r);
+    } else {
+      // Eckart-Young floor evaluated directly: ||X - U* V*^T|| / ||X||
+      const double nx2 = sumsq_x<XT>(X, m, n, ld, red);
+      const double f = residual<XT>(X, m, n, ld, q.U, q.V, r, sm.p, red);
+      if (t0) {
+        ctl.nx2 = nx2;
+        ctl.relerr_svd = nx2 > 0.0 ? sqrt(2.0 * f / nx2) : 0.0;
+      }
+    }
+    if (t0) {
+      if (sub >= last_orth + 2) {
+        ctl.stage = kStRot;
+        ctl.sub = 0;
+      } else {
+        ctl.sub = sub + 1;
+      }
+    }
+    __syncthreads();
+    return sub <= last_orth + 1 ? m * n * (int64_t)kk + (m + n) * (int64_t)kk * kk * 2
+                                : m * n * (int64_t)(r + 1);
+  }
+
+  if (stage == kStRot) {
+    const int64_t N = m + n;
+    double* Rs = sm.a.R;
+    if (sub == 0) {
+      // W = [U*; V*] (float64, width 32), rho = rho0 sqrt(N r) / ||W||_F, R = I
+      double s = 0.0;
+      for (int64_t e = threadIdx.x; e < N * SKP; e += SNT) {
+        const int64_t i = e / SKP;
+        const int c = (int)(e % SKP);
+        double v = 0.0;
+        if (c < r) v = i < m ? (double)q.U[i * r + c] : (double)q.V[(i - m) * r + c];
+        q.W[e] = v;
+        s = fma(v, v, s);
+      }
+      s = bsum(s, red);
+      for (int e = threadIdx.x; e < SKP * SKP; e += SNT)
+        st.R[e] = (e / SKP == e % SKP && e / SKP < r) ? 1.0 : 0.0;
+      if (t0) {
+        ctl.rho = s > 0.0 ? q.rho0 * sqrt((double)N * r) / sqrt(s) : 1.0;
+        ctl.dR = INFINITY;
+        ctl.rot_steps = 0;
+        if (q.rot_max_iter > 0) {
+          ctl.sub = 1;
+        } else {
+          ctl.stage = kStSetup;
+          ctl.sub = 0;
+        }
+      }
+      __syncthreads();
+      return N * SKP;
+    }
+    if (sub == 1) {
+      // one ADMM step (Algorithm 1): rows, then M = W^T B, then R = polar(M)
+      const int step = ctl.rot_steps;
+      for (int e = threadIdx.x; e < SKP * SKP; e += SNT) Rs[e] = st.R[e];
+      __syncthreads();
+      const double rho = ctl.rho, irho = 1.0 / rho;
+      for (int64_t i = threadIdx.x; i < N; i += SNT) {
+        double w[SKP];
+#pragma unroll
+        for (int c = 0; c < SKP; ++c) w[c] = q.W[i * SKP + c];
+        for (int c = 0; c < r; ++c) {
+          double wr = 0.0;
+#pragma unroll
+          for (int a = 0; a < SKP; ++a) wr = fma(w[a], Rs[a * SKP + c], wr);
+          double y = 0.0;
+          if (step > 0) y = q.Ya[i * SKP + c] + rho * (q.Za[i * SKP + c] - wr);
+          const double b = wr - y * irho;
+          const double z = b > 0.0 ? b : (b >= -irho ? 0.0 : b + irho);
+          q.Ya[i * SKP + c] = y;
+          q.Za[i * SKP + c] = z;
+          q.Ba[i * SKP + c] = z + y * irho;
+        }
+      }
+      __syncthreads();
+      bx_cross<double, double, SKP>(q.W, SKP, r, q.Ba, SKP, r, N, st.scratch, sm.g);
+      for (int e = threadIdx.x; e < SKP * SKP; e += SNT) {
+        const int a = e / SKP, c = e % SKP;
+        sm.a.X[a][c] = (a < r && c < r) ? st.scratch[e] : 0.0;
+      }
+      __syncthreads();
+      const bool ok = polar_ns_block<SKP>(sm.a.X, sm.a.T, sm.a.red);
+      double d2 = 0.0;
+      if (ok) {
+        for (int e = threadIdx.x; e < SKP * SKP; e += SNT) {
+          const int a = e / SKP, c = e % SKP;
+          const double v = (a < r && c < r) ? sm.a.X[a][c] : 0.0;
+          const double dv = v - st.R[e];
+          d2 = fma(dv, dv, d2);
+          st.R[e] = v;
+        }
+      }
+      d2 = bsum(d2, red);
+      if (t0) {
+        ctl.dR = ok ? sqrt(d2) : 0.0;
+        ctl.rot_steps = step + 1;
+        const bool tol_hit = q.rot_tol > 0.0 && (step + 1) % q.rot_check_every == 0 && ctl.dR <= q.rot_tol;
+        if (tol_hit || step + 1 >= q.rot_max_iter) ctl.sub = 2;
+      }
+      __syncthreads();
+      return N * (int64_t)SKP * r * 2 + (int64_t)SKP * SKP * SKP * 20;
+    }
+    // U = W_U R, V = W_V R with the last R
+    for (int e = threadIdx.x; e < SKP * SKP; e += SNT) Rs[e] = st.R[e];
+    __syncthreads();
+    bx_apply<double, float, SKP>(q.W, SKP, r, m, Rs, r, q.U, r);
+    bx_apply<double, float, SKP>(q.W + m * SKP, SKP, r, n, Rs, r, q.V, r);
+    if (t0) {
+      ctl.stage = kStSetup;
+      ctl.sub = 0;
+    }
+    __syncthreads();
+    return N * (int64_t)r * r;
+  }
+
+  if (stage == kStSetup) {
+    // resolved push sizes, phase, H = U^T U, Q = X^T U, KKT partials of V
+    if (q.mode == 1) {
+      for (int64_t e = threadIdx.x; e < m * r; e += SNT) q.U[e] = q.U[e] > 0.f ? q.U[e] : 0.f;
+      for (int64_t e = threadIdx.x; e < n * r; e += SNT) q.V[e] = q.V[e] > 0.f ? q.V[e] : 0.f;
+      __syncthreads();
+    }
+    double mnU = INFINITY, mnV = INFINITY, negs = 0.0;
+    for (int64_t e = threadIdx.x; e < m * r; e += SNT) {
+      mnU = fmin(mnU, (double)q.U[e]);
+      negs += q.U[e] < 0.f ? 1.0 : 0.0;
+    }
+    for (int64_t e = threadIdx.x; e < n * r; e += SNT) {
+      mnV = fmin(mnV, (double)q.V[e]);
+      negs += q.V[e] < 0.f ? 1.0 : 0.0;
+    }
+    mnU = block_min<SNT>(mnU, red);
+    mnV = block_min<SNT>(mnV, red);
+    negs = bsum(negs, red);
+    bx_cross<float, float, SKP>(q.U, r, r, q.U, r, r, m, st.H, sm.g);
+    xta<XT>(X, m, n, ld, q.U, r, r, q.Z32, r, sm.p);
+    load_gram32(st.H, sm.w);
+    row_pass(q.V, n, r, q.Z32, sm.w, false, false, kPhaseHals, 0.0, 0);
+    if (t0) {
+      const double d = (double)q.ext_iters - 0.5;
+      ctl.step[0] = q.step_u > 0.0 ? q.step_u : fmax(-mnU, 0.0) / d;
+      ctl.step[1] = q.step_v > 0.0 ? q.step_v : fmax(-mnV, 0.0) / d;
+      ctl.iphase = negs > 0.0 ? kPhaseExt : kPhaseHals;
+      for (int f = 0; f < 8; ++f) ctl.recV[f] = sm.w.out[f];
+      ctl.negsV = sm.w.out[8];
+      ctl.k = 0;
+      ctl.iters = 0;
+      ctl.ext_done = 0;
+      ctl.stage = kStIter;
+    }
+    __syncthreads();
+    return m * n * (int64_t)r + (m + n) * (int64_t)SKP * SKP;
+  }
+
+  if (stage == kStIter) {
+    const int k = ctl.k;
+    // G = V^T V, P = X V, KKT partials of U^k (pre-update)
+    bx_cross<float, float, SKP>(q.V, r, r, q.V, r, r, n, st.G, sm.g);
+    xb<XT>(X, m, n, ld, q.V, r, r, q.Y32, r, sm.p);
+    load_gram32(st.G, sm.w);
+    row_pass(q.U, m, r, q.Y32, sm.w, false, true, kPhaseHals, 0.0, 0);
+    // check of iteration k (the KKT appendix), same expressions as k_finalize
+    double hg = 0.0;
+    for (int e = threadIdx.x; e < SKP * SKP; e += SNT) hg = fma(st.H[e], st.G[e], hg);
+    hg = bsum(hg, red);
+    __shared__ int s_stop;
+    if (t0) {
+      const double* a = sm.w.out;       // U side
+      const double* b = ctl.recV;       // V side
+      const double negsU = a[8];
+      const double nx2 = ctl.nx2;
+      const double f = 0.5 * nx2 - a[5] + 0.5 * hg;
+      const double nx = sqrt(nx2);
+      const double nU = sqrt(a[4]), nV = sqrt(b[4]);
+      const double feas = fmax(nU > 0.0 ? sqrt(a[3]) / nU : 0.0, nV > 0.0 ? sqrt(b[3]) / nV : 0.0);
+      const double pgu = (nV > 0.0 && nx > 0.0) ? sqrt(a[0]) / (nx * nV) : 0.0;
+      const double pgv = (nU > 0.0 && nx > 0.0) ? sqrt(b[0]) / (nx * nU) : 0.0;
+      const double kkt = fmax(feas, fmax(pgu, pgv));
+      const double relerr = nx > 0.0 ? sqrt(fmax(2.0 * f, 0.0)) / nx : 0.0;
+      const double negs = a[6] + b[6];
+      const bool due = (k % q.check_every == 0) || k == q.max_iter;
+      bool stop = k >= q.max_iter;
+      bool hit = false;
+      if (due) {
+        ctl.f = f;
+        ctl.relerr = relerr;
+        ctl.kkt = kkt;
+        ctl.kkt_feas = feas;
+        ctl.kkt_pg_u = pgu;
+        ctl.kkt_pg_v = pgv;
+        ctl.delta_w = fmax(a[2], b[2]);
+        ctl.sigma_w = a[1] + b[1];
+        ctl.min_w = fmin(a[7], b[7]);
+        hit = negs == 0.0 && ((q.kkt_tol >= 0.0 && kkt <= q.kkt_tol) ||
+                              (q.relerr_tol >= 0.0 && relerr - ctl.relerr_svd <= q.relerr_tol) ||
+                              q.mode == 3);
+        if (!isfinite(f) || !isfinite(kkt)) ctl.numeric_error = 1;
+        if (hit || ctl.numeric_error) stop = true;
+      }
+      ctl.iphase = negsU + ctl.negsV > 0.0 ? kPhaseExt : kPhaseHals;
+      if (stop) {
+        ctl.converged = hit ? 1 : 0;
+        ctl.iters = k;
+        ctl.stage = kStFinal;
+      }
+      s_stop = stop ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_stop) return m * n * (int64_t)r + (m + n) * (int64_t)SKP * SKP;
+    const int phase = ctl.iphase;
+    // U half: update in place, then H = U^T U and Q = X^T U
+    row_pass(q.U, m, r, q.Y32, sm.w, true, true, phase, ctl.step[0], q.sweeps);
+    bx_cross<float, float, SKP>(q.U, r, r, q.U, r, r, m, st.H, sm.g);
+    xta<XT>(X, m, n, ld, q.U, r, r, q.Z32, r, sm.p);
+    // V half with the new U; KKT partials of V^(k+1)
+    load_gram32(st.H, sm.w);
+    row_pass(q.V, n, r, q.Z32, sm.w, true, false, phase, ctl.step[1], q.sweeps);
+    if (t0) {
+      for (int f = 0; f < 8; ++f) ctl.recV[f] = sm.w.out[f];
+      ctl.negsV = sm.w.out[8];
+      if (phase == kPhaseExt) ctl.ext_done += 1;
+      ctl.k = k + 1;
+      ctl.iters = k + 1;
+    }
+    __syncthreads();
+    return 2 * m * n * (int64_t)r + 4 * (m + n) * (int64_t)SKP * SKP;
+  }
+
+  // final objective, evaluated directly
+  const double f = residual<XT>(X, m, n, ld, q.U, q.V, r, sm.p, red);
+  if (t0) {
+    ctl.f = f;
+    ctl.relerr = ctl.nx2 > 0.0 ? sqrt(2.0 * f / ctl.nx2) : 0.0;
+    if (!isfinite(f)) ctl.numeric_error = 1;
+    ctl.stage = kStDone;
+  }
+  __syncthreads();
+  return m * n * (int64_t)r;
+}
+
+template <int XT>
+__global__ __launch_bounds__(SNT) void k_serve_tick(ServeSlot* __restrict__ slots,
+                                                    ServeStatus* __restrict__ status, int nslots,
+                                                    int64_t budget) {
+  __shared__ ServeSmem sm;
+  __shared__ ServeScalars ctl;
+  __shared__ double red[SNT / kWave];
+  const int b = blockIdx.x;
+  if (b >= nslots) return;
+  ServeStatus* stt = status + b;
+  ServeSlot* sl = slots + b;
+  if (stt->status != kSlotRunning || sl->q.xt != XT) return;
+  if (threadIdx.x == 0) ctl = sl->s.c;
+  __syncthreads();
+  int64_t spent = 0;
+  while (ctl.stage != kStDone) {
+    spent += serve_step<XT>(sl->q, sl->s, ctl, sm, red);
+    if (spent >= budget) break;
+  }
+  if (threadIdx.x == 0) {
+    sl->s.c = ctl;
+    const bool done = ctl.stage == kStDone;
+    stt->stage = ctl.stage;
+    stt->iters = ctl.iters;
+    stt->ext_done = ctl.ext_done;
+    stt->converged = ctl.converged;
+    stt->phase = ctl.iphase;
+    stt->rot_steps = ctl.rot_steps;
+    stt->numeric_error = ctl.numeric_error;
+    stt->f = ctl.f;
+    stt->relerr = ctl.relerr;
+    stt->kkt = ctl.kkt;
+    stt->kkt_feas = ctl.kkt_feas;
+    stt->kkt_pg_u = ctl.kkt_pg_u;
+    stt->kkt_pg_v = ctl.kkt_pg_v;
+    stt->delta_w = ctl.delta_w;
+    stt->sigma_w = ctl.sigma_w;
+    stt->step_u = ctl.step[0];
+    stt->step_v = ctl.step[1];
+    stt->relerr_svd = ctl.relerr_svd;
+    stt->status = done ? kSlotDone : kSlotRunning;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_serve_tick(int xt, ServeSlot* slots, ServeStatus* status, int nslots,
+                             int64_t budget, hipStream_t s) {
+  if (nslots < 1) return hipSuccess;
+  if (xt == ENMF_F32)
+    hipLaunchKernelGGL((k_serve_tick<0>), dim3(nslots), dim3(SNT), 0, s, slots, status, nslots, budget);
+  else if (xt == ENMF_BF16)
+    hipLaunchKernelGGL((k_serve_tick<1>), dim3(nslots), dim3(SNT), 0, s, slots, status, nslots, budget);
+  else
+    hipLaunchKernelGGL((k_serve_tick<2>), dim3(nslots), dim3(SNT), 0, s, slots, status, nslots, budget);
+  return hipGetLastError();
+}
+
+}  // namespace enmf

@@ -10,6 +10,7 @@
 //   * the row-parallel ADMM step (W R, the prox of eq. 7, the dual update).
 #include <math.h>
 
+#include "block_linalg.h"
 #include "dev_common.h"
 #include "enmf_internal.h"
 
@@ -19,7 +20,7 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kMaxW = ENMF_MAX_WIDTH;   // 80
-constexpr int kLdJ = kMaxW + 1;         // LDS leading dimension of the Jacobi matrices
+using JacobiSmem = JacobiT<kMaxW>;
 
 int grid_for(int64_t count, int threads = 256, int cap = 8192) {
   int64_t g = (count + threads - 1) / threads;
@@ -118,136 +119,20 @@ __global__ void k_apply_small(const TA* __restrict__ A, int64_t lda, int64_t row
   }
 }
 
-// ---------------------------------------------------------------------------
-// Symmetric eigensolver: parallel cyclic Jacobi (Brent-Luk round-robin
-// ordering) on an LDS-resident k x k float64 matrix S with eigenvector
-// matrix E.  Each round applies n2/2 disjoint plane rotations, chosen with
-// the stable formula of Golub & Van Loan (sym.schur2), first to the
-// columns of S and E, then to the rows of S.  An odd k is padded with one
-// zero row/column that no rotation ever touches.  On return diag(S) holds
-// the eigenvalues and the columns of E the eigenvectors; perm lists the
-// first k indices by descending eigenvalue.
-// ---------------------------------------------------------------------------
-struct JacobiSmem {
-  double S[kMaxW * kLdJ];
-  double E[kMaxW * kLdJ];
-  double cs[kMaxW];
-  double red[kT / kWave];
-  int pq[kMaxW];
-  int perm[kMaxW];
-};
-
-__device__ __forceinline__ int rr_player(int pos, int round, int n2) {
-  return pos == 0 ? 0 : ((pos - 1 + round) % (n2 - 1)) + 1;
-}
-
-__device__ void jacobi_eig(JacobiSmem& sm, int k) {
-  const int n2 = k + (k & 1);
-  double* S = sm.S;
-  double* E = sm.E;
-  for (int e = threadIdx.x; e < n2 * n2; e += kT) {
-    const int a = e / n2, c = e % n2;
-    E[a * kLdJ + c] = (a == c) ? 1.0 : 0.0;
-    if (a >= k || c >= k) S[a * kLdJ + c] = 0.0;
-  }
-  __syncthreads();
-  const int npairs = n2 / 2;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int e = threadIdx.x; e < k * k; e += kT) {
-      const int a = e / k, c = e % k;
-      const double v = S[a * kLdJ + c];
-      if (a == c) dia += v * v; else off += v * v;
-    }
-    off = block_sum<kT>(off, sm.red);
-    dia = block_sum<kT>(dia, sm.red);
-    if (!(off > 1e-30 * dia) || off == 0.0) break;
-    for (int round = 0; round < n2 - 1; ++round) {
-      if (threadIdx.x < npairs) {
-        int p = rr_player(threadIdx.x, round, n2);
-        int q = rr_player(n2 - 1 - threadIdx.x, round, n2);
-        if (p > q) { const int t = p; p = q; q = t; }
-        const double apq = S[p * kLdJ + q];
-        double c = 1.0, s = 0.0;
-        if (fabs(apq) > 1e-300) {
-          const double tau = (S[q * kLdJ + q] - S[p * kLdJ + p]) / (2.0 * apq);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
-        }
-        sm.pq[2 * threadIdx.x] = p;
-        sm.pq[2 * threadIdx.x + 1] = q;
-        sm.cs[2 * threadIdx.x] = c;
-        sm.cs[2 * threadIdx.x + 1] = s;
-      }
-      __syncthreads();
-      // S <- J^T S J in one pass: the pairs partition the indices, so every
-      // 2 x 2 block (pair P1 rows, pair P2 columns) transforms on its own as
-      // J1^T S_block J2.  E <- E J column pair by column pair.
-      for (int task = threadIdx.x; task < npairs * npairs; task += kT) {
-        const int P1 = task / npairs, P2 = task % npairs;
-        const double c1 = sm.cs[2 * P1], s1 = sm.cs[2 * P1 + 1];
-        const double c2 = sm.cs[2 * P2], s2 = sm.cs[2 * P2 + 1];
-        if (s1 == 0.0 && s2 == 0.0) continue;
-        const int p1 = sm.pq[2 * P1], q1 = sm.pq[2 * P1 + 1];
-        const int p2 = sm.pq[2 * P2], q2 = sm.pq[2 * P2 + 1];
-        const double a = S[p1 * kLdJ + p2], b = S[p1 * kLdJ + q2];
-        const double cc = S[q1 * kLdJ + p2], d = S[q1 * kLdJ + q2];
-        const double ra = c1 * a - s1 * cc, rb = c1 * b - s1 * d;     // rows: J1^T
-        const double rc = s1 * a + c1 * cc, rd = s1 * b + c1 * d;
-        double na = c2 * ra - s2 * rb, nb = s2 * ra + c2 * rb;        // columns: J2
-        double nc = c2 * rc - s2 * rd, nd = s2 * rc + c2 * rd;
-        if (P1 == P2) { nb = 0.0; nc = 0.0; }                        // the annihilated pair
-        S[p1 * kLdJ + p2] = na;
-        S[p1 * kLdJ + q2] = nb;
-        S[q1 * kLdJ + p2] = nc;
-        S[q1 * kLdJ + q2] = nd;
-      }
-      for (int task = threadIdx.x; task < npairs * n2; task += kT) {
-        const int pr = task / n2, x = task % n2;
-        const double c = sm.cs[2 * pr], s = sm.cs[2 * pr + 1];
-        if (s == 0.0) continue;
-        const int p = sm.pq[2 * pr], q = sm.pq[2 * pr + 1];
-        const double a = E[x * kLdJ + p], b = E[x * kLdJ + q];
-        E[x * kLdJ + p] = c * a - s * b;
-        E[x * kLdJ + q] = s * a + c * b;
-      }
-      __syncthreads();
-    }
-  }
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < k; ++i) sm.perm[i] = i;
-    for (int i = 0; i < k; ++i) {
-      int best = i;
-      for (int j = i + 1; j < k; ++j)
-        if (S[sm.perm[j] * kLdJ + sm.perm[j]] > S[sm.perm[best] * kLdJ + sm.perm[best]]) best = j;
-      const int t = sm.perm[i]; sm.perm[i] = sm.perm[best]; sm.perm[best] = t;
-    }
-  }
-  __syncthreads();
-}
-
-__device__ __forceinline__ double eigval(const JacobiSmem& sm, int j) {
-  return sm.S[sm.perm[j] * kLdJ + sm.perm[j]];
-}
-__device__ __forceinline__ double eigvec(const JacobiSmem& sm, int a, int j) {
-  return sm.E[a * kLdJ + sm.perm[j]];
-}
-
 // T = E diag(lambda^-1/2) (zero for lambda <= tau * lambda_max): Q = A T has
 // orthonormal columns when A^T A = Gm (range finder orthonormalisation).
 __global__ __launch_bounds__(kT) void k_orth_factor(const double* __restrict__ Gm, int k, double tau,
                                                     double* __restrict__ T) {
   __shared__ JacobiSmem sm;
-  for (int e = threadIdx.x; e < k * k; e += kT) sm.S[(e / k) * kLdJ + e % k] = Gm[e];
+  for (int e = threadIdx.x; e < k * k; e += kT) sm.S[(e / k) * JacobiSmem::LD + e % k] = Gm[e];
   __syncthreads();
-  jacobi_eig(sm, k);
-  const double lmax = eigval(sm, 0);
+  jacobi_eig<kMaxW>(sm, k);
+  const double lmax = eigval<kMaxW>(sm, 0);
   for (int e = threadIdx.x; e < k * k; e += kT) {
     const int a = e / k, j = e % k;
-    const double l = eigval(sm, j);
+    const double l = eigval<kMaxW>(sm, j);
     const double sc = (l > tau * lmax && l > 0.0) ? 1.0 / sqrt(l) : 0.0;
-    T[e] = eigvec(sm, a, j) * sc;
+    T[e] = eigvec<kMaxW>(sm, a, j) * sc;
   }
 }
 
@@ -263,15 +148,15 @@ __global__ __launch_bounds__(kT) void k_svd_factor(const double* __restrict__ C,
   __shared__ JacobiSmem sm;
   __shared__ double sgn[kMaxW];
   __shared__ double sq[kMaxW];
-  for (int e = threadIdx.x; e < k * k; e += kT) sm.S[(e / k) * kLdJ + e % k] = C[e];
+  for (int e = threadIdx.x; e < k * k; e += kT) sm.S[(e / k) * JacobiSmem::LD + e % k] = C[e];
   __syncthreads();
-  jacobi_eig(sm, k);
+  jacobi_eig<kMaxW>(sm, k);
   if (threadIdx.x < r) {
     const int j = threadIdx.x;
     double cs = 0.0;
-    for (int a = 0; a < k; ++a) cs = fma(colsum[a], eigvec(sm, a, j), cs);
+    for (int a = 0; a < k; ++a) cs = fma(colsum[a], eigvec<kMaxW>(sm, a, j), cs);
     sgn[j] = cs < 0.0 ? -1.0 : 1.0;
-    const double l = eigval(sm, j);
+    const double l = eigval<kMaxW>(sm, j);
     const double sg = l > 0.0 ? sqrt(l) : 0.0;
     sigma[j] = sg;
     sq[j] = sqrt(sg);
@@ -279,7 +164,7 @@ __global__ __launch_bounds__(kT) void k_svd_factor(const double* __restrict__ C,
   __syncthreads();
   for (int e = threadIdx.x; e < k * r; e += kT) {
     const int a = e / r, j = e % r;
-    const double w = eigvec(sm, a, j) * sgn[j];
+    const double w = eigvec<kMaxW>(sm, a, j) * sgn[j];
     TU[e] = w * sq[j];
     TV[e] = sq[j] > 0.0 ? w / sq[j] : 0.0;
   }
@@ -374,90 +259,23 @@ __global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, 
 }
 
 // R <- polar factor of M (r x r, leading dimension kp): the orthogonal
-// Procrustes solution C D^T of section 3.1 (W^T B = C S D^T), computed by the
-// Newton-Schulz iteration X <- 1.5 X - 0.5 X X^T X from X0 = 1.5 M / ||M||_F
-// (singular values of X0 in (0, 1.5], inside the convergence interval
-// (0, sqrt 3)), in float64 until ||X_{k+1} - X_k||_F <= 1e-13 or 100 steps.
-// Records ||R_new - R_old||_F in st->dR.  R is kp x kp, zero padded.
+// Procrustes solution C D^T of section 3.1 (W^T B = C S D^T), by
+// polar_ns_block.  Records ||R_new - R_old||_F in st->dR.  R is kp x kp,
+// zero padded.
 template <int KP>
 __global__ __launch_bounds__(kT) void k_polar_ns(const double* __restrict__ Mf, int r, int kp,
                                                  double* __restrict__ R, DevState* st) {
-  constexpr int TT = KP / 16;
   __shared__ double X[KP][KP + 1];
   __shared__ double T[KP][KP + 1];
   __shared__ double red[kT / kWave];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  double nrm = 0.0;
   for (int e = threadIdx.x; e < KP * KP; e += kT) {
     const int a = e / KP, c = e % KP;
-    const double v = (a < r && c < r) ? Mf[a * kp + c] : 0.0;
-    X[a][c] = v;
-    nrm = fma(v, v, nrm);
+    X[a][c] = (a < r && c < r) ? Mf[a * kp + c] : 0.0;
   }
-  nrm = sqrt(block_sum<kT>(nrm, red));
-  if (!(nrm > 0.0) || !isfinite(nrm)) {
+  __syncthreads();
+  if (!polar_ns_block<KP>(X, T, red)) {
     if (threadIdx.x == 0) st->dR = 0.0;
     return;
-  }
-  const double sc = 1.5 / nrm;
-  for (int e = threadIdx.x; e < KP * KP; e += kT) X[e / KP][e % KP] *= sc;
-  __syncthreads();
-  for (int it = 0; it < 100; ++it) {
-    // T = X^T X
-    double acc[TT][TT];
-#pragma unroll
-    for (int i = 0; i < TT; ++i)
-#pragma unroll
-      for (int j = 0; j < TT; ++j) acc[i][j] = 0.0;
-    for (int q = 0; q < KP; ++q) {
-      double av[TT], bv[TT];
-#pragma unroll
-      for (int i = 0; i < TT; ++i) av[i] = X[q][ty + 16 * i];
-#pragma unroll
-      for (int j = 0; j < TT; ++j) bv[j] = X[q][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < TT; ++i)
-#pragma unroll
-        for (int j = 0; j < TT; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
-    }
-#pragma unroll
-    for (int i = 0; i < TT; ++i)
-#pragma unroll
-      for (int j = 0; j < TT; ++j) T[ty + 16 * i][tx + 16 * j] = acc[i][j];
-    __syncthreads();
-    // X_new = 1.5 X - 0.5 X T
-#pragma unroll
-    for (int i = 0; i < TT; ++i)
-#pragma unroll
-      for (int j = 0; j < TT; ++j) acc[i][j] = 0.0;
-    for (int q = 0; q < KP; ++q) {
-      double av[TT], bv[TT];
-#pragma unroll
-      for (int i = 0; i < TT; ++i) av[i] = X[ty + 16 * i][q];
-#pragma unroll
-      for (int j = 0; j < TT; ++j) bv[j] = T[q][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < TT; ++i)
-#pragma unroll
-        for (int j = 0; j < TT; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
-    }
-    double d2 = 0.0;
-    double xn[TT][TT];
-#pragma unroll
-    for (int i = 0; i < TT; ++i)
-#pragma unroll
-      for (int j = 0; j < TT; ++j) {
-        const double x = X[ty + 16 * i][tx + 16 * j];
-        xn[i][j] = 1.5 * x - 0.5 * acc[i][j];
-        d2 = fma(xn[i][j] - x, xn[i][j] - x, d2);
-      }
-    d2 = block_sum<kT>(d2, red);   // also orders every read of X before the writes below
-#pragma unroll
-    for (int i = 0; i < TT; ++i)
-#pragma unroll
-      for (int j = 0; j < TT; ++j) X[ty + 16 * i][tx + 16 * j] = xn[i][j];
-    __syncthreads();
-    if (d2 <= 1e-26) break;
   }
   double d2 = 0.0;
   for (int e = threadIdx.x; e < kp * kp; e += kT) {

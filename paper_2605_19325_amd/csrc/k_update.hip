@@ -12,6 +12,7 @@
 
 #include "dev_common.h"
 #include "enmf_internal.h"
+#include "row_team.h"
 
 namespace enmf {
 
@@ -70,149 +71,6 @@ __global__ void k_setup_state(const double* __restrict__ stat, int nbU, int nbV,
   st->ntrace = 0;
   st->numeric_error = 0;
   st->pbcd_done[0] = st->pbcd_done[1] = 0;
-}
-
-// Team geometry: KP/8 lanes per row, teams aligned inside a wave.
-template <int KP> struct Team {
-  static constexpr int T = KP / 8;
-  static constexpr int RB = T <= 4 ? 64 : 32;   // rows per block
-  static constexpr int NT = RB * T;             // threads per block
-};
-
-template <int T>
-__device__ __forceinline__ double team_sum(double v) {
-#pragma unroll
-  for (int o = T / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
-// G (KP x KP float64) into LDS; all of a thread's loads are issued before
-// the first is consumed.
-template <int KP>
-__device__ __forceinline__ void load_gram(const double* __restrict__ G, double* sG) {
-  constexpr int NT = Team<KP>::NT;
-  constexpr int PER = KP * KP / NT;
-  static_assert(KP * KP % NT == 0, "Gram tile must split evenly over the block");
-  double v[PER];
-#pragma unroll
-  for (int u = 0; u < PER; ++u) v[u] = G[threadIdx.x + u * NT];
-#pragma unroll
-  for (int u = 0; u < PER; ++u) sG[threadIdx.x + u * NT] = v[u];
-}
-
-// The block's rows [row0, row0 + nrow) of a row-major rows x r float32
-// matrix form one contiguous range of nrow * r floats.  stage_rows copies it
-// into dst[row][col] (LDS, row pitch LD) with coalesced loads, summing
-// `nsplit` partials of stride pstride in split order; columns >= r and rows
-// >= nrow are zero filled.  Each thread owns at most KP / T = 8 elements.
-template <int KP, int LD>
-__device__ __forceinline__ void stage_rows(const float* __restrict__ src, int nsplit,
-                                           int64_t pstride, int64_t row0, int nrow, int r,
-                                           float (*dst)[LD]) {
-  using TM = Team<KP>;
-  constexpr int PER = TM::RB * KP / TM::NT;
-  const int cnt = nrow * r;
-  const float* base = src + row0 * r;
-  float v[PER];
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = threadIdx.x + u * TM::NT;
-    v[u] = e < cnt ? base[e] : 0.f;
-  }
-  for (int sp = 1; sp < nsplit; ++sp) {
-    float w[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = threadIdx.x + u * TM::NT;
-      w[u] = e < cnt ? base[(int64_t)sp * pstride + e] : 0.f;
-    }
-#pragma unroll
-    for (int u = 0; u < PER; ++u) v[u] += w[u];
-  }
-  for (int e = threadIdx.x; e < TM::RB * KP; e += TM::NT) dst[e / KP][e % KP] = 0.f;
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = threadIdx.x + u * TM::NT;
-    if (e < cnt) dst[e / r][e % r] = v[u];
-  }
-  __syncthreads();
-}
-
-// s[e] = sum_b row[b] G[b][c0+e] for the 8 columns c0..c0+7 (G symmetric).
-template <int KP, typename RT>
-__device__ __forceinline__ void row_times_g(const RT* row, const double* sG, int c0, double* s) {
-#pragma unroll
-  for (int e = 0; e < 8; ++e) s[e] = 0.0;
-  for (int b = 0; b < KP; ++b) {
-    const double x = (double)row[b];
-    const double* g = sG + b * KP + c0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) s[e] = fma(x, g[e], s[e]);
-  }
-}
-
-// Upper-triangle 4x4 tile `task` of a KP x KP matrix -> (ti, tj), ti <= tj.
-template <int KP>
-__device__ __forceinline__ void gram_tile(int task, int& ti, int& tj) {
-  constexpr int NTILE = KP / 4;
-  int i = 0, rem = task;
-  while (rem >= NTILE - i) { rem -= NTILE - i; ++i; }
-  ti = i;
-  tj = i + rem;
-}
-
-// Check-record accumulators for one row: grad = a G - p (the gradient of
-// eq. 1 through the Gram identity), projected gradient = grad where a > 0
-// and min(grad, 0) where a <= 0 (the KKT appendix).
-struct CheckAcc {
-  double pg2 = 0.0, sg = 0.0, mx = -INFINITY, ng2 = 0.0, sq = 0.0, ap = 0.0, nneg = 0.0,
-         mn = INFINITY;
-  __device__ __forceinline__ void add(const float* a, const double* s, const double* p, int c0,
-                                      int r) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      if (c0 + e < r) {
-        const double gv = s[e] - p[e];
-        const double av = (double)a[e];
-        const double pgc = av > 0.0 ? gv : fmin(gv, 0.0);
-        pg2 = fma(pgc, pgc, pg2);
-        sg = fma(av, gv, sg);
-        mx = fmax(mx, av * gv);
-        if (av < 0.0) { ng2 = fma(av, av, ng2); nneg += 1.0; }
-        sq = fma(av, av, sq);
-        ap = fma(av, p[e], ap);
-        mn = fmin(mn, av);
-      }
-    }
-  }
-};
-
-// Fixed-order reduction of NF per-thread values over a block of NT threads.
-// kind[f]: 0 sum, 1 max, 2 min.  The result lands in out[] of thread 0.
-template <int NT, int NF>
-__device__ __forceinline__ void block_reduce_fields(double* v, const int* kind, double* sh,
-                                                    double* out) {
-  constexpr int NW = NT / kWave;
-  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-#pragma unroll
-  for (int f = 0; f < NF; ++f)
-    v[f] = kind[f] == 1 ? wave_max(v[f]) : (kind[f] == 2 ? wave_min(v[f]) : wave_sum(v[f]));
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int f = 0; f < NF; ++f) sh[f * NW + w] = v[f];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      double t = sh[f * NW];
-      for (int i = 1; i < NW; ++i)
-        t = kind[f] == 1 ? fmax(t, sh[f * NW + i]) : (kind[f] == 2 ? fmin(t, sh[f * NW + i]) : t + sh[f * NW + i]);
-      out[f] = t;
-    }
-  }
 }
 
 // One half of an outer iteration on the rows of A (U with P = X V, G = V^T V,

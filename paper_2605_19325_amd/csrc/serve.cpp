@@ -1,0 +1,443 @@
+// Host side of the serving loop: admission by device-memory footprint,
+// slot assignment, and the launch loop that advances every running solve by
+// one tick (k_serve.hip) until it finishes.  One worker thread per server
+// drives the device; submit and poll only touch the queues under the lock.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "enmf_internal.h"
+#include "serve_internal.h"
+
+using namespace enmf;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+// Workspace of one served solve, laid out in its arena block.
+struct Layout {
+  int64_t y32, qm64, z32, qn64, w, ya, za, ba, total;
+};
+
+Layout layout_for(int64_t m, int64_t n, int kk) {
+  Layout L;
+  int64_t o = 0;
+  L.y32 = o;  o += align256(m * kk * 4);
+  L.qm64 = o; o += align256(m * kk * 8);
+  L.z32 = o;  o += align256(n * kk * 4);
+  L.qn64 = o; o += align256(n * kk * 8);
+  const int64_t wb = align256((m + n) * kServeKP * 8);
+  L.w = o;  o += wb;
+  L.ya = o; o += wb;
+  L.za = o; o += wb;
+  L.ba = o; o += wb;
+  L.total = o;
+  return L;
+}
+
+// First-fit allocator over [0, size) with coalescing frees.
+class Arena {
+ public:
+  explicit Arena(int64_t size) : size_(size) { free_[0] = size; }
+  int64_t alloc(int64_t bytes) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const int64_t off = it->first, rest = it->second - bytes;
+        free_.erase(it);
+        if (rest > 0) free_[off + bytes] = rest;
+        return off;
+      }
+    }
+    return -1;
+  }
+  void release(int64_t off, int64_t bytes) {
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  int64_t size() const { return size_; }
+
+ private:
+  int64_t size_;
+  std::map<int64_t, int64_t> free_;
+};
+
+struct Pending {
+  uint64_t ticket;
+  enmf_request req;
+  Clock::time_point t_submit;
+  int64_t bytes;
+};
+
+struct Running {
+  bool used = false;
+  uint64_t ticket = 0;
+  int xt = 0;
+  int64_t off = 0, bytes = 0;
+  Clock::time_point t_submit;
+};
+
+struct Result {
+  enmf_status status;
+  enmf_iter_report rep;
+  double latency_s;
+};
+
+}  // namespace
+
+struct enmf_server {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int max_slots = 512;
+  int64_t budget = 64LL << 20;
+  char* arena_base = nullptr;
+  Arena* arena = nullptr;
+  ServeSlot* d_slots = nullptr;
+  ServeStatus* d_status = nullptr;
+  ServeStatus* h_status = nullptr;   // pinned
+  ServeSlot* h_stage = nullptr;      // pinned staging of newly admitted slots
+  std::vector<Running> slots;
+  std::deque<Pending> pending;
+  std::unordered_map<uint64_t, Result> done;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::thread worker;
+  bool stopping = false;
+  bool failed = false;
+  std::string err;
+  uint64_t next_ticket = 1;
+};
+
+namespace {
+
+enmf_status fail_srv(enmf_server* s, enmf_status st, const std::string& msg) {
+  s->err = msg;
+  return st;
+}
+
+void fill_report(const ServeStatus& h, enmf_iter_report* rep) {
+  std::memset(rep, 0, sizeof(*rep));
+  rep->iters = h.iters;
+  rep->ext_iters_done = h.ext_done;
+  rep->phase = h.phase;
+  rep->converged = h.converged;
+  rep->step_u = h.step_u;
+  rep->step_v = h.step_v;
+  rep->f = h.f;
+  rep->relerr = h.relerr;
+  rep->re_paper = h.relerr_svd > 0.0 ? h.relerr / h.relerr_svd : NAN;
+  rep->kkt = h.kkt;
+  rep->kkt_feas = h.kkt_feas;
+  rep->kkt_pg_u = h.kkt_pg_u;
+  rep->kkt_pg_v = h.kkt_pg_v;
+  rep->delta_w = h.delta_w;
+  rep->sigma_w = h.sigma_w;
+}
+
+// Host image of a newly admitted slot: the request and a fresh state.
+void build_slot(enmf_server* s, const Pending& p, int64_t off, ServeSlot* out) {
+  const enmf_request& rq = p.req;
+  const Layout L = layout_for(rq.X.m, rq.X.n, rq.r + rq.svd.oversample);
+  std::memset(out, 0, offsetof(ServeSlot, s) + sizeof(ServeScalars));
+  ServeReq& q = out->q;
+  char* base = s->arena_base + off;
+  q.X = rq.X.data;
+  q.m = rq.X.m;
+  q.n = rq.X.n;
+  q.ld = rq.X.ld;
+  q.xt = rq.X.dtype;
+  q.r = rq.r;
+  q.omega = rq.svd.omega;
+  q.kk = rq.r + rq.svd.oversample;
+  q.power_iters = rq.svd.power_iters;
+  q.rho0 = rq.rot.rho0;
+  q.rot_tol = rq.rot.tol;
+  q.rot_max_iter = rq.rot.max_iter;
+  q.rot_check_every = rq.rot.check_every < 1 ? 1 : rq.rot.check_every;
+  q.step_u = rq.it.step_u;
+  q.step_v = rq.it.step_v;
+  q.kkt_tol = rq.it.kkt_tol;
+  q.relerr_tol = rq.it.relerr_tol;
+  q.ext_iters = rq.it.ext_iters < 1 ? 10 : rq.it.ext_iters;
+  q.sweeps = rq.it.pbcd_max_iter < 1 ? 5 : rq.it.pbcd_max_iter;
+  q.max_iter = rq.it.max_iter;
+  q.check_every = rq.it.check_every < 1 ? 1 : rq.it.check_every;
+  q.mode = rq.it.mode;
+  q.U = rq.U_out;
+  q.V = rq.V_out;
+  q.Y32 = reinterpret_cast<float*>(base + L.y32);
+  q.Qm64 = reinterpret_cast<double*>(base + L.qm64);
+  q.Z32 = reinterpret_cast<float*>(base + L.z32);
+  q.Qn64 = reinterpret_cast<double*>(base + L.qn64);
+  q.W = reinterpret_cast<double*>(base + L.w);
+  q.Ya = reinterpret_cast<double*>(base + L.ya);
+  q.Za = reinterpret_cast<double*>(base + L.za);
+  q.Ba = reinterpret_cast<double*>(base + L.ba);
+  out->s.c.stage = kStSvd;
+}
+
+void fail_all(enmf_server* s, const std::string& msg) {
+  // called with the lock held
+  s->failed = true;
+  s->err = msg;
+  Result r{};
+  r.status = ENMF_EDEVICE;
+  for (auto& p : s->pending) s->done[p.ticket] = r;
+  s->pending.clear();
+  for (auto& sl : s->slots)
+    if (sl.used) {
+      s->done[sl.ticket] = r;
+      sl.used = false;
+    }
+  s->cv.notify_all();
+}
+
+void worker_loop(enmf_server* s) {
+  (void)hipSetDevice(s->device);
+  std::vector<int> fresh;
+  for (;;) {
+    int hi = 0;
+    bool types[3] = {false, false, false};
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      for (;;) {
+        // admit in arrival order while a slot and arena space are free
+        fresh.clear();
+        while (!s->pending.empty() && !s->failed) {
+          int slot = -1;
+          for (int i = 0; i < s->max_slots; ++i)
+            if (!s->slots[i].used) { slot = i; break; }
+          if (slot < 0) break;
+          const Pending& p = s->pending.front();
+          const int64_t off = s->arena->alloc(p.bytes);
+          if (off < 0) break;
+          Running& r = s->slots[slot];
+          r.used = true;
+          r.ticket = p.ticket;
+          r.xt = p.req.X.dtype;
+          r.off = off;
+          r.bytes = p.bytes;
+          r.t_submit = p.t_submit;
+          build_slot(s, p, off, &s->h_stage[fresh.size()]);
+          fresh.push_back(slot);
+          s->pending.pop_front();
+        }
+        bool any = false;
+        for (int i = 0; i < s->max_slots; ++i)
+          if (s->slots[i].used) { any = true; hi = i + 1; types[s->slots[i].xt] = true; }
+        if (any || !fresh.empty()) break;
+        if (s->stopping && s->pending.empty()) return;
+        s->cv.wait(lk);
+      }
+    }
+    // upload the new slots and mark them running
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < fresh.size() && e == hipSuccess; ++i) {
+      const int slot = fresh[i];
+      e = hipMemcpyAsync(s->d_slots + slot, &s->h_stage[i], offsetof(ServeSlot, s) + sizeof(ServeScalars),
+                         hipMemcpyHostToDevice, s->stream);
+      if (e == hipSuccess) {
+        ServeStatus st{};
+        st.status = kSlotRunning;
+        s->h_status[slot] = st;
+        e = hipMemcpyAsync(s->d_status + slot, &s->h_status[slot], sizeof(ServeStatus),
+                           hipMemcpyHostToDevice, s->stream);
+      }
+    }
+    for (int xt = 0; xt < 3 && e == hipSuccess; ++xt)
+      if (types[xt]) e = launch_serve_tick(xt, s->d_slots, s->d_status, hi, s->budget, s->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->h_status, s->d_status, hi * sizeof(ServeStatus), hipMemcpyDeviceToHost,
+                         s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    const auto now = Clock::now();
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (e != hipSuccess) {
+      fail_all(s, std::string("serving launch failed: ") + hipGetErrorString(e));
+      if (s->stopping) return;
+      continue;
+    }
+    bool finished = false;
+    for (int i = 0; i < hi; ++i) {
+      Running& r = s->slots[i];
+      if (!r.used || s->h_status[i].status != kSlotDone) continue;
+      Result res;
+      fill_report(s->h_status[i], &res.rep);
+      res.status = s->h_status[i].numeric_error ? ENMF_ENUMERIC : ENMF_OK;
+      res.latency_s = std::chrono::duration<double>(now - r.t_submit).count();
+      s->done[r.ticket] = res;
+      s->arena->release(r.off, r.bytes);
+      r.used = false;
+      finished = true;
+    }
+    if (finished) s->cv.notify_all();
+  }
+}
+
+enmf_status check_request(enmf_server* s, const enmf_request* q) {
+  if (!q) return fail_srv(s, ENMF_EINVAL, "null request");
+  const enmf_matrix& X = q->X;
+  if (!X.data) return fail_srv(s, ENMF_EINVAL, "X is null");
+  if (X.m < 1 || X.n < 1 || X.ld < X.n) return fail_srv(s, ENMF_EINVAL, "bad X shape");
+  if (X.dtype != ENMF_F32 && X.dtype != ENMF_BF16 && X.dtype != ENMF_F16)
+    return fail_srv(s, ENMF_EINVAL, "unsupported X dtype");
+  const int esz = X.dtype == ENMF_F32 ? 4 : 2;
+  if (reinterpret_cast<uintptr_t>(X.data) % esz != 0)
+    return fail_srv(s, ENMF_EINVAL, "X data must be aligned to its element size");
+  if (q->r < 1 || q->r > kServeKP || q->r > X.m || q->r > X.n)
+    return fail_srv(s, ENMF_EINVAL, "served solves need 1 <= r <= min(m, n, 32)");
+  if (!q->svd.omega) return fail_srv(s, ENMF_EINVAL, "svd.omega is required");
+  if (q->svd.oversample < 0 || q->svd.power_iters < 0 || q->r + q->svd.oversample > kServeKK)
+    return fail_srv(s, ENMF_EINVAL, "served solves need r + oversample <= 48");
+  if (!(q->rot.rho0 > 0.0) || q->rot.max_iter < 0 || q->rot.tol < 0.0)
+    return fail_srv(s, ENMF_EINVAL, "bad rotation options");
+  const enmf_iter_opts& it = q->it;
+  if (it.max_iter < 0) return fail_srv(s, ENMF_EINVAL, "max_iter must be >= 0");
+  if (it.pbcd_eps != 0.0) return fail_srv(s, ENMF_EINVAL, "served solves use a fixed PBCD sweep count");
+  if (it.mode != 0 && it.mode != 1 && it.mode != 3) return fail_srv(s, ENMF_EINVAL, "unsupported mode");
+  if (!q->U_out || !q->V_out) return fail_srv(s, ENMF_EINVAL, "null output pointer");
+  return ENMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+enmf_status enmf_serve_start(enmf_ctx* c, const enmf_serve_opts* opts, enmf_server** out) {
+  if (!out) return ENMF_EINVAL;
+  *out = nullptr;
+  if (!c) return ENMF_EINVAL;
+  enmf_serve_opts o{};
+  if (opts) o = *opts;
+  if (o.max_slots < 0 || o.tick_budget < 0) return ENMF_EINVAL;
+  auto* s = new enmf_server();
+  s->device = ctx_device(c);
+  s->max_slots = o.max_slots > 0 ? o.max_slots : 512;
+  s->budget = (int64_t)(o.tick_budget > 0 ? o.tick_budget : 64) << 20;
+  const int64_t arena_bytes = o.hbm_budget_bytes > 0 ? (int64_t)o.hbm_budget_bytes : (1LL << 30);
+  auto bail = [&](enmf_status st, const char* msg) {
+    ctx_set_error(c, msg);
+    if (s->d_slots) (void)hipFree(s->d_slots);
+    if (s->d_status) (void)hipFree(s->d_status);
+    if (s->arena_base) (void)hipFree(s->arena_base);
+    if (s->h_status) (void)hipHostFree(s->h_status);
+    if (s->h_stage) (void)hipHostFree(s->h_stage);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return st;
+  };
+  if (hipSetDevice(s->device) != hipSuccess) return bail(ENMF_EDEVICE, "hipSetDevice failed");
+  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(ENMF_EDEVICE, "stream creation failed");
+  if (hipMalloc(&s->arena_base, arena_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    s->arena_base = nullptr;
+    return bail(ENMF_ENOMEM, "serving arena allocation failed");
+  }
+  if (hipMalloc(&s->d_slots, sizeof(ServeSlot) * s->max_slots) != hipSuccess ||
+      hipMalloc(&s->d_status, sizeof(ServeStatus) * s->max_slots) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(ENMF_ENOMEM, "serving slot allocation failed");
+  }
+  if (hipHostMalloc(&s->h_status, sizeof(ServeStatus) * s->max_slots) != hipSuccess ||
+      hipHostMalloc(&s->h_stage, sizeof(ServeSlot) * s->max_slots) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(ENMF_ENOMEM, "pinned host allocation failed");
+  }
+  if (hipMemset(s->d_status, 0, sizeof(ServeStatus) * s->max_slots) != hipSuccess)
+    return bail(ENMF_EDEVICE, "status initialisation failed");
+  s->arena = new Arena(arena_bytes);
+  s->slots.resize(s->max_slots);
+  s->worker = std::thread(worker_loop, s);
+  *out = s;
+  return ENMF_OK;
+}
+
+enmf_status enmf_serve_submit(enmf_server* s, const enmf_request* q, uint64_t* ticket) {
+  if (!s || !ticket) return ENMF_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stopping) return fail_srv(s, ENMF_ECLOSED, "server is stopping");
+  if (s->failed) return fail_srv(s, ENMF_EDEVICE, s->err);
+  const enmf_status v = check_request(s, q);
+  if (v != ENMF_OK) return v;
+  const int64_t bytes = layout_for(q->X.m, q->X.n, q->r + q->svd.oversample).total;
+  if (bytes > s->arena->size())
+    return fail_srv(s, ENMF_ENOMEM, "request workspace exceeds the serving memory budget");
+  Pending p;
+  p.ticket = s->next_ticket++;
+  p.req = *q;
+  p.t_submit = Clock::now();
+  p.bytes = bytes;
+  s->pending.push_back(p);
+  *ticket = p.ticket;
+  s->cv.notify_all();
+  return ENMF_OK;
+}
+
+enmf_status enmf_serve_poll(enmf_server* s, uint64_t ticket, enmf_iter_report* rep, double* latency_s) {
+  if (!s) return ENMF_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->done.find(ticket);
+  if (it != s->done.end()) {
+    const Result r = it->second;
+    s->done.erase(it);
+    if (rep) *rep = r.rep;
+    if (latency_s) *latency_s = r.latency_s;
+    if (r.status == ENMF_EDEVICE) s->err = s->err.empty() ? "device failure" : s->err;
+    return r.status;
+  }
+  for (const auto& p : s->pending)
+    if (p.ticket == ticket) return ENMF_EBUSY;
+  for (const auto& r : s->slots)
+    if (r.used && r.ticket == ticket) return ENMF_EBUSY;
+  return fail_srv(s, ENMF_EINVAL, "unknown ticket");
+}
+
+const char* enmf_serve_last_error(const enmf_server* s) { return s ? s->err.c_str() : "null server"; }
+
+enmf_status enmf_serve_stop(enmf_server* s) {
+  if (!s) return ENMF_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
+  }
+  s->cv.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  const bool failed = s->failed;
+  (void)hipSetDevice(s->device);
+  (void)hipStreamSynchronize(s->stream);
+  (void)hipFree(s->d_slots);
+  (void)hipFree(s->d_status);
+  (void)hipFree(s->arena_base);
+  (void)hipHostFree(s->h_status);
+  (void)hipHostFree(s->h_stage);
+  (void)hipStreamDestroy(s->stream);
+  delete s->arena;
+  delete s;
+  return failed ? ENMF_EDEVICE : ENMF_OK;
+}
+
+}  // extern "C"

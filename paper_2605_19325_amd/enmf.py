@@ -63,6 +63,16 @@ class Kkt(Structure):
                                         "min_w")]
 
 
+class ServeOpts(Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", c_int32),
+                ("tick_budget", c_int32)]
+
+
+class Request(Structure):
+    _fields_ = [("X", Matrix), ("r", c_int32), ("reserved", c_int32), ("svd", SvdOpts),
+                ("rot", RotateOpts), ("it", IterOpts), ("U_out", c_void_p), ("V_out", c_void_p)]
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported entry point.
@@ -92,6 +102,12 @@ SIGNATURES = [
                                      POINTER(c_double), POINTER(c_double)]),
     ("enmf_kernel_timing", c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double),
                                      POINTER(c_int32)]),
+    ("enmf_serve_start", c_int32, [c_void_p, POINTER(ServeOpts), POINTER(c_void_p)]),
+    ("enmf_serve_submit", c_int32, [c_void_p, POINTER(Request), POINTER(ctypes.c_uint64)]),
+    ("enmf_serve_poll", c_int32, [c_void_p, ctypes.c_uint64, POINTER(IterReport),
+                                  POINTER(c_double)]),
+    ("enmf_serve_stop", c_int32, [c_void_p]),
+    ("enmf_serve_last_error", c_char_p, [c_void_p]),
 ]
 
 
@@ -285,3 +301,90 @@ class Context:
         rep = self.iterate(X, U, V, **iter_opts)
         rep.update(sigma=sigma, relerr_svd=rsvd, rotation=rot)
         return U, V, rep
+
+
+EBUSY = 5
+
+
+class Server:
+    """A libenmf server: many solves of uneven shape in flight on one device.
+
+    submit() queues a request and returns a ticket at once; poll() returns
+    None while the request runs and its report once it has finished.  The
+    tensors of a request (X, omega and the U/V outputs) are kept referenced
+    here until the request has been polled, as the device reads and writes
+    them until then.
+    """
+
+    def __init__(self, ctx, hbm_budget_bytes=0, max_slots=0, tick_budget=0):
+        self._lib = ctx._lib
+        self._ctx = ctx
+        h = c_void_p()
+        o = ServeOpts(hbm_budget_bytes, max_slots, tick_budget)
+        st = self._lib.enmf_serve_start(ctx._h, byref(o), byref(h))
+        if st != 0:
+            raise EnmfError(st, self._lib.enmf_last_error(ctx._h).decode())
+        self._h = h
+        self._live = {}
+
+    def submit(self, X, r, omega, oversample=10, power_iters=2, rho0=1.0, rot_max_iter=100,
+               rot_tol=1e-10, rot_check_every=10, max_iter=300, ext_iters=10, pbcd_max_iter=5,
+               check_every=1, kkt_tol=-1.0, relerr_tol=-1.0, step_u=0.0, step_v=0.0, mode=0):
+        """Queue one solve; returns (ticket, U, V) with U, V the output tensors."""
+        M = matrix(X)
+        m, n = X.shape
+        _factor(omega, n, r + oversample, "omega")
+        U = torch.empty((m, r), dtype=torch.float32, device=X.device)
+        V = torch.empty((n, r), dtype=torch.float32, device=X.device)
+        req = Request(M, r, 0, SvdOpts(omega.data_ptr(), oversample, power_iters),
+                      RotateOpts(rho0, rot_tol, rot_max_iter, rot_check_every),
+                      IterOpts(step_u, step_v, 0.0, relerr_tol, kkt_tol, 0.0, ext_iters,
+                               pbcd_max_iter, max_iter, check_every, mode, 0),
+                      U.data_ptr(), V.data_ptr())
+        # inputs must be on the device before the server's own stream reads them
+        torch.cuda.current_stream(X.device).synchronize()
+        t = ctypes.c_uint64()
+        st = self._lib.enmf_serve_submit(self._h, byref(req), byref(t))
+        if st != 0:
+            raise EnmfError(st, self._lib.enmf_serve_last_error(self._h).decode())
+        self._live[t.value] = (X, omega, U, V)
+        return t.value, U, V
+
+    def poll(self, ticket):
+        """None while running; else dict(report..., latency_s, status)."""
+        rep = IterReport()
+        lat = c_double()
+        st = self._lib.enmf_serve_poll(self._h, ticket, byref(rep), byref(lat))
+        if st == EBUSY:
+            return None
+        if st not in (0, 4):
+            raise EnmfError(st, self._lib.enmf_serve_last_error(self._h).decode())
+        self._live.pop(ticket, None)
+        out = {name: getattr(rep, name) for name, _ in IterReport._fields_}
+        out.update(latency_s=lat.value, status=st)
+        return out
+
+    def wait(self, ticket, timeout=120.0, interval=1e-3):
+        import time
+        t0 = time.perf_counter()
+        while True:
+            res = self.poll(ticket)
+            if res is not None:
+                return res
+            if time.perf_counter() - t0 > timeout:
+                raise TimeoutError(f"request {ticket} did not finish in {timeout} s")
+            time.sleep(interval)
+
+    def stop(self):
+        if getattr(self, "_h", None):
+            st = self._lib.enmf_serve_stop(self._h)
+            self._h = None
+            self._live.clear()
+            if st != 0:
+                raise EnmfError(st, "server stopped after a device failure")
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

@@ -46,14 +46,40 @@ def test_status_strings():
     assert lib.enmf_status_string(99) == b"unknown status"
 
 
-def test_struct_layouts_match_header():
-    # sizes follow the header: all doubles first or 8-byte aligned groups
-    assert ctypes.sizeof(enmf.Matrix) == 40
-    assert ctypes.sizeof(enmf.SvdOpts) == 16
-    assert ctypes.sizeof(enmf.RotateOpts) == 24
-    assert ctypes.sizeof(enmf.IterOpts) == 72
-    assert ctypes.sizeof(enmf.IterReport) == 16 + 11 * 8
-    assert ctypes.sizeof(enmf.Kkt) == 12 * 8
+STRUCTS = [("enmf_matrix", enmf.Matrix), ("enmf_svd_opts", enmf.SvdOpts),
+           ("enmf_rotate_opts", enmf.RotateOpts), ("enmf_iter_opts", enmf.IterOpts),
+           ("enmf_iter_report", enmf.IterReport), ("enmf_kkt", enmf.Kkt),
+           ("enmf_serve_opts", enmf.ServeOpts), ("enmf_request", enmf.Request)]
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Size and every field offset of the ctypes mirrors equal what a C
+    compiler makes of include/enmf.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "enmf.h"', "int main(void) {"]
+    for cname, py in STRUCTS:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n"):
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for cname, py in STRUCTS:
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
 
 
 def test_create_without_gpu_fails_cleanly():

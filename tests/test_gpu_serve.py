@@ -1,0 +1,171 @@
+"""GPU tests of the serving loop (enmf_serve_*), through the C ABI.
+
+Each served solve runs Algorithm 3 end to end in one workgroup.  It is
+compared with the FP64 oracle run of the same algorithm, on the same X and
+test matrix omega:
+* float32 X: the oracle's trajectory, with U and V within 1e-4 and f within 1e-5;
+* bfloat16 X: the oracle's relative error within 1e-3 and a KKT residual <= 1e-5.
+
+A request gives bitwise the same factors when it runs alone, in a mix of
+uneven requests of several dtypes, and under a different tick budget.
+Errors: r beyond the served range, a workspace that can never fit, and an
+unknown ticket.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2605_19325_amd import enmf, inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().double().numpy()
+
+
+@pytest.fixture(scope="module")
+def server(lib):
+    srv = enmf.Server(lib, hbm_budget_bytes=1 << 30, max_slots=64)
+    yield srv
+    srv.stop()
+
+
+def test_served_fp32_tracks_oracle(server):
+    X, r = inputs.config_small()
+    om = inputs.omega(X.shape[1], r + 10, 7)
+    say("served fp32 500x400 r=10, 20 rotation steps, 200 iterations vs oracle")
+    t, U, V = server.submit(to_dev(X), r, to_dev(om), rot_max_iter=20, rot_tol=0.0, max_iter=200)
+    res = server.wait(t)
+    Uo, Vo, ro = O.enmf(X, r, om, rot_max_iter=20, rot_tol=0.0, max_iter=200)
+    say(f"  iters {res['iters']} ext {res['ext_iters_done']} relerr {res['relerr']:.8e} "
+        f"oracle {ro['relerr']:.8e} latency {res['latency_s']:.3f} s")
+    assert res["status"] == 0
+    assert res["iters"] == ro["iters"] == 200
+    assert res["ext_iters_done"] == ro["ext_iters_done"]
+    assert rel(host(U), Uo) <= 1e-4 and rel(host(V), Vo) <= 1e-4
+    assert abs(res["f"] - ro["f"]) <= 1e-5 * ro["f"]
+    assert abs(res["kkt"] - ro["kkt"]) <= 1e-5
+
+
+def test_served_bf16_reaches_oracle_error(lib, server):
+    X, r = inputs.config_small()
+    om = inputs.omega(X.shape[1], r + 10, 7)
+    say("served bf16: relerr within 1e-3 of the oracle, kkt <= 1e-5")
+    Uo, Vo, ro = O.enmf(X, r, om, rot_max_iter=20, rot_tol=0.0, max_iter=400, kkt_tol=1e-6)
+    Xb = lib.convert(to_dev(X), torch.bfloat16)
+    t, U, V = server.submit(Xb, r, to_dev(om), rot_max_iter=20, rot_tol=0.0, max_iter=400,
+                            kkt_tol=1e-6)
+    res = server.wait(t)
+    Ug, Vg = host(U), host(V)
+    err = O.relerr(X, Ug, Vg)
+    say(f"  relerr {err:.6e} oracle {ro['relerr']:.6e} kkt {res['kkt']:.2e}")
+    assert abs(err - ro["relerr"]) <= 1e-3
+    assert res["kkt"] <= 1e-5
+    assert Ug.min() >= 0 and Vg.min() >= 0
+
+
+def _request(i, seed):
+    rng = np.random.default_rng(seed)
+    m, n = (int(v) for v in rng.integers(64, 400, 2))
+    r = int(rng.integers(4, 33))
+    r = min(r, m, n)
+    X, _, _ = inputs.lowrank_plus_noise(m, n, r, seed + 1)
+    om = inputs.omega(n, min(r + 10, 48), seed + 2)
+    return X, r, om
+
+
+def test_same_result_alone_and_in_the_mix(lib):
+    say("one request alone, in a mix of 16 uneven requests, and with a small tick budget")
+    Xa, ra, oma = _request(0, 500)
+    Xa_b = lib.convert(to_dev(Xa), torch.bfloat16)
+    opts = dict(oversample=oma.shape[1] - ra, max_iter=150, kkt_tol=1e-6)
+
+    def run(srv, others):
+        live = []
+        for i, (X, r, om, dt) in enumerate(others):
+            Xd = to_dev(X) if dt == "f32" else lib.convert(to_dev(X), dt)
+            live.append(srv.submit(Xd, r, to_dev(om), oversample=om.shape[1] - r, max_iter=150))
+            if i == len(others) // 2:
+                ta, Ua, Va = srv.submit(Xa_b, ra, to_dev(oma), **opts)
+        if not others:
+            ta, Ua, Va = srv.submit(Xa_b, ra, to_dev(oma), **opts)
+        res = srv.wait(ta)
+        for t, _, _ in live:
+            assert srv.wait(t)["status"] == 0
+        return host(Ua), host(Va), res
+
+    srv = enmf.Server(lib, max_slots=64)
+    try:
+        U1, V1, r1 = run(srv, [])
+        dts = ["f32", torch.bfloat16, torch.float16]
+        mix = [(*_request(i, 600 + 10 * i), dts[i % 3]) for i in range(16)]
+        U2, V2, r2 = run(srv, mix)
+    finally:
+        srv.stop()
+    srv = enmf.Server(lib, max_slots=8, tick_budget=1)
+    try:
+        U3, V3, r3 = run(srv, mix[:6])
+    finally:
+        srv.stop()
+    say(f"  iters {r1['iters']} {r2['iters']} {r3['iters']}  relerr {r1['relerr']:.6e}")
+    assert np.array_equal(U1, U2) and np.array_equal(V1, V2)
+    assert np.array_equal(U1, U3) and np.array_equal(V1, V3)
+    assert r1["iters"] == r2["iters"] == r3["iters"]
+    assert r1["relerr"] == r2["relerr"] == r3["relerr"]
+
+
+def test_served_stream_sample_matches_oracle(lib, server):
+    say("served-stream sample (bf16, stop at relerr - relerr_svd <= 1e-3 or kkt <= 1e-5)")
+    reqs = [q for q in inputs.serve_stream(count=64) if q["m"] * q["n"] <= 150_000][:8]
+    live = []
+    for q in reqs:
+        X, _, _ = inputs.lowrank_plus_noise(q["m"], q["n"], q["r"], q["seed"])
+        om = inputs.omega(q["n"], q["r"] + 10, q["seed"] + 1)
+        Xb = lib.convert(to_dev(X), torch.bfloat16)
+        t, U, V = server.submit(Xb, q["r"], to_dev(om), max_iter=300, relerr_tol=1e-3, kkt_tol=1e-5)
+        live.append((q, X, om, t, U, V))
+    for q, X, om, t, U, V in live:
+        res = server.wait(t)
+        Uo, Vo, ro = O.enmf(X, q["r"], om, max_iter=300, relerr_tol=1e-3, kkt_tol=1e-5)
+        err = O.relerr(X, host(U), host(V))
+        say(f"  {q['m']}x{q['n']} r={q['r']}: iters {res['iters']} relerr {err:.5e} "
+            f"oracle {ro['relerr']:.5e} ({ro['iters']} iters) latency {res['latency_s']:.3f} s")
+        assert res["status"] == 0
+        assert abs(err - ro["relerr"]) <= 1e-3
+        assert host(U).min() >= 0 and host(V).min() >= 0
+
+
+def test_serve_rejects_bad_requests(lib):
+    say("serve: bad rank, workspace beyond the budget, unknown ticket")
+    srv = enmf.Server(lib, hbm_budget_bytes=1 << 20, max_slots=4)
+    try:
+        X = to_dev(np.ones((100, 80), np.float32))
+        with pytest.raises(enmf.EnmfError) as e:
+            srv.submit(X, 33, to_dev(np.ones((80, 43), np.float32)))
+        assert e.value.status == 1
+        Xbig = to_dev(np.ones((2000, 2000), np.float32))
+        with pytest.raises(enmf.EnmfError) as e:
+            srv.submit(Xbig, 30, to_dev(np.ones((2000, 40), np.float32)))
+        assert e.value.status == 2
+        with pytest.raises(enmf.EnmfError) as e:
+            srv.poll(12345)
+        assert e.value.status == 1
+    finally:
+        srv.stop()
