@@ -41,6 +41,11 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only time the two X-streaming kernels (for hardware-counter passes)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
+    ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="open-loop arrival rate as a fraction of the closed-loop solves/s")
+    ap.add_argument("--serve-slots", type=int, default=256)
     return ap.parse_args()
 
 
@@ -64,6 +69,80 @@ def cpu_baseline(X, om, iters):
         "sample": (f"svd init ({t1 - t0:.2f} s) + 100-step rotation ({t2 - t1:.2f} s) + {iters} "
                    f"iterations ({t3 - t2:.2f} s) of the same 4096x10000 r=49 solve; value = "
                    f"{ITERS} / (init + rotation + {ITERS} x measured s/iteration)"),
+    }
+
+
+def ratings_streaming(ctx, torch, m=100000, n=20000, r=20):
+    """HBM view of the streaming products at the ratings shape (X 100000 x 20000,
+    r = 20), where they are bound by HBM: bfloat16 (4 GB) and float32 (8 GB) X,
+    average device time per launch over 5 launches.  X's values do not change
+    the timing, so it is filled on the device."""
+    X = torch.rand((m, n), device="cuda:0", dtype=torch.float32)
+    f_xv, f_xtu = ctx.time_products(X, r, reps=5)
+    Xb = ctx.convert(X, torch.bfloat16)
+    del X
+    b_xv, b_xtu = ctx.time_products(Xb, r, reps=5)
+    del Xb
+    torch.cuda.empty_cache()
+    out = {"workload": f"ratings-shaped X {m}x{n}, r={r}", "peak_gbs": PEAK_HBM_GBS}
+    for name, ms, esz in (("bf16_xv", b_xv, 2), ("bf16_xtu", b_xtu, 2), ("f32_xv", f_xv, 4),
+                          ("f32_xtu", f_xtu, 4)):
+        gbs = m * n * esz / (ms * 1e-3) / 1e9
+        out[name] = {"ms": round(ms, 4), "gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    return out
+
+
+def served(ctx, torch, inputs, enmf, count, load, slots):
+    """Served stream: `count` requests (m, n log-uniform in [64, 2048], r in 4..32,
+    bfloat16 X), each solved to relerr - relerr_svd <= 1e-3, KKT <= 1e-5 or 300
+    iterations.  A closed-loop pass (all submitted at once) gives the saturated
+    solves/s; an open-loop pass with Poisson arrivals at `load` times that rate
+    gives the latency distribution (submission to completion)."""
+    dev = torch.device("cuda:0")
+    reqs = inputs.serve_stream(count)
+    data = []
+    for q in reqs:
+        X, _, _ = inputs.lowrank_plus_noise(q["m"], q["n"], q["r"], q["seed"])
+        Xb = ctx.convert(torch.from_numpy(X).to(dev), torch.bfloat16)
+        om = torch.from_numpy(inputs.omega(q["n"], q["r"] + 10, q["seed"] + 1)).to(dev)
+        data.append((Xb, q["r"], om))
+    torch.cuda.synchronize()
+    opts = dict(max_iter=300, relerr_tol=1e-3, kkt_tol=1e-5)
+
+    def run(arrivals):
+        srv = enmf.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=slots)
+        try:
+            t0 = time.perf_counter()
+            tickets = []
+            for i, (Xb, r, om) in enumerate(data):
+                if arrivals is not None:
+                    wait = arrivals[i] - (time.perf_counter() - t0)
+                    if wait > 0:
+                        time.sleep(wait)
+                tickets.append(srv.submit(Xb, r, om, **opts)[0])
+            res = [srv.wait(t, timeout=600.0) for t in tickets]
+            wall = time.perf_counter() - t0
+        finally:
+            srv.stop()
+        lat = np.array([x["latency_s"] for x in res])
+        iters = np.array([x["iters"] for x in res])
+        conv = float(np.mean([x["converged"] for x in res]))
+        return wall, lat, iters, conv
+
+    wall_c, lat_c, iters_c, conv_c = run(None)
+    sat = count / wall_c
+    arr = inputs.poisson_arrivals(count, load * sat, 7)
+    wall_o, lat_o, iters_o, conv_o = run(arr)
+    return {
+        "requests": count, "dtype": "bf16", "slots": slots,
+        "saturated_solves_per_s": round(sat, 2),
+        "load": load, "arrival_rate_per_s": round(load * sat, 2),
+        "solves_per_s": round(count / wall_o, 2),
+        "p50_latency_s": round(float(np.percentile(lat_o, 50)), 5),
+        "p99_latency_s": round(float(np.percentile(lat_o, 99)), 5),
+        "mean_iters": round(float(iters_o.mean()), 2), "converged_frac": round(conv_o, 4),
+        "closed_loop_p50_s": round(float(np.percentile(lat_c, 50)), 5),
+        "closed_loop_p99_s": round(float(np.percentile(lat_c, 99)), 5),
     }
 
 
@@ -157,6 +236,12 @@ def main():
         "ext_iters": rep["ext_iters_done"], "rotation_steps": rot["steps"],
         "roofline": roof,
     }
+    del X, om
+    torch.cuda.empty_cache()
+    out["hbm_streaming"] = ratings_streaming(ctx, torch)
+    if not args.no_serve:
+        out["served"] = served(ctx, torch, inputs, enmf, args.serve_requests, args.serve_load,
+                               args.serve_slots)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(X_np, om_np, args.cpu_iters)
     print(json.dumps(out), flush=True)

@@ -24,6 +24,9 @@
 // order by the caller.
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+
 #include "dev_common.h"
 #include "enmf_internal.h"
 
@@ -404,22 +407,39 @@ __global__ __launch_bounds__(kT) void k_xv_bf16(const unsigned short* __restrict
                                               ch * 64 + 32 * s + 8 * g, vec != 0);
     }
   };
-  auto load_b = [&](int64_t ch, int buf) {
+  // The next chunk of the factor travels through registers and reaches LDS
+  // only after the current chunk's MFMAs, so waiting for it never stalls the
+  // X prefetch issued behind it.
+  constexpr int NBQ = (CH / 8 + kT - 1) / kT;
+  uint4 bq_next[NBQ];
+  auto fetch_b = [&](int64_t ch) {
     const uint4* src = reinterpret_cast<const uint4*>(Bt + ch * CH);
+#pragma unroll
+    for (int u = 0; u < NBQ; ++u) {
+      const int e = threadIdx.x + u * kT;
+      bq_next[u] = e < CH / 8 ? src[e] : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto store_b = [&](int buf) {
     uint4* dst = reinterpret_cast<uint4*>(Bs[buf]);
-    for (int e = threadIdx.x; e < CH / 8; e += kT) dst[e] = src[e];
+#pragma unroll
+    for (int u = 0; u < NBQ; ++u) {
+      const int e = threadIdx.x + u * kT;
+      if (e < CH / 8) dst[e] = bq_next[u];
+    }
   };
   if (c0 < c1) {
+    fetch_b(c0);
     load_x(c0, xa);
-    load_b(c0, 0);
+    store_b(0);
   }
   int buf = 0;
   for (int64_t ch = c0; ch < c1; ++ch) {
     __syncthreads();
     const bool more = ch + 1 < c1;
     if (more) {
+      fetch_b(ch + 1);
       load_x(ch + 1, xb);
-      load_b(ch + 1, buf ^ 1);
     }
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -438,6 +458,7 @@ __global__ __launch_bounds__(kT) void k_xv_bf16(const unsigned short* __restrict
       }
     }
     if (more) {
+      store_b(buf ^ 1);
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) { xa[rt][0] = xb[rt][0]; xa[rt][1] = xb[rt][1]; }
     }
@@ -496,22 +517,37 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
         dst[e] = load16<unsigned short>(X, m, n, ld, ch * 32 + 8 * g + e, j0 + 8 * i, vec != 0);
     }
   };
-  auto load_a = [&](int64_t ch, int buf) {
+  // factor chunk prefetched into registers, stored to LDS after the MFMAs
+  constexpr int NAQ = (CH / 8 + kT - 1) / kT;
+  uint4 aq_next[NAQ];
+  auto fetch_a = [&](int64_t ch) {
     const uint4* src = reinterpret_cast<const uint4*>(At + ch * CH);
+#pragma unroll
+    for (int u = 0; u < NAQ; ++u) {
+      const int e = threadIdx.x + u * kT;
+      aq_next[u] = e < CH / 8 ? src[e] : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto store_a = [&](int buf) {
     uint4* dst = reinterpret_cast<uint4*>(As[buf]);
-    for (int e = threadIdx.x; e < CH / 8; e += kT) dst[e] = src[e];
+#pragma unroll
+    for (int u = 0; u < NAQ; ++u) {
+      const int e = threadIdx.x + u * kT;
+      if (e < CH / 8) dst[e] = aq_next[u];
+    }
   };
   if (c0 < c1) {
+    fetch_a(c0);
     load_x(c0, xa);
-    load_a(c0, 0);
+    store_a(0);
   }
   int buf = 0;
   for (int64_t ch = c0; ch < c1; ++ch) {
     __syncthreads();
     const bool more = ch + 1 < c1;
     if (more) {
+      fetch_a(ch + 1);
       load_x(ch + 1, xb);
-      load_a(ch + 1, buf ^ 1);
     }
     // transpose: op[t] dword d = (X[2d][t], X[2d+1][t]) of the lane's 8 x 8 block
     uint4 op[8];
@@ -543,6 +579,7 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
       }
     }
     if (more) {
+      store_a(buf ^ 1);
 #pragma unroll
       for (int e = 0; e < 8; ++e) xa[e] = xb[e];
     }
@@ -635,24 +672,112 @@ bool aligned_rows(const void* X, int64_t ld, int esz) {
   return (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((ld * esz) % 16 == 0);
 }
 
-// Number of contraction splits for a grid of `tiles` output blocks (bf16 kernels).
-int64_t choose_splits(int64_t tiles, int64_t units, int64_t min_units) {
-  int64_t s = (1536 + tiles - 1) / tiles;
-  const int64_t smax = (units + min_units - 1) / min_units;
-  if (s > smax) s = smax;
-  if (s < 1) s = 1;
-  return s;
+// Workgroups of `kernel` (256 threads) resident on the device at once.
+int64_t resident_blocks(const void* kernel) {
+  static std::mutex mu;
+  static std::map<const void*, int64_t> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(kernel);
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 0, per = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kT, 0) != hipSuccess) per = 1;
+  (void)hipGetLastError();
+  const int64_t v = (int64_t)(per > 0 ? per : 1) * (cus > 0 ? cus : 256);
+  cache[kernel] = v;
+  return v;
 }
 
-// float32 kernels: two resident blocks per CU on 256 CUs fill the chip in
-// one round; at least 8 chunks (2 per wave) per split.
-constexpr int64_t kResidentBlocks = 512;
-int64_t f32_splits(int64_t tiles, int64_t nchunks) {
-  int64_t s = kResidentBlocks / tiles;
-  const int64_t smax = (nchunks + 7) / 8;
-  if (s > smax) s = smax;
-  if (s < 1) s = 1;
-  return s;
+// Contraction splits for a grid of `tiles` output blocks: the smallest count
+// (at most smax_cap, at least min_units chunks each) whose grid keeps the
+// resident slots best used over whole rounds (blocks / (rounds * capacity)),
+// a larger count being taken only for a gain of more than 2%.
+int64_t choose_splits(int64_t tiles, int64_t units, int64_t min_units, int64_t capacity,
+                      int64_t smax_cap) {
+  int64_t smax = (units + min_units - 1) / min_units;
+  if (smax > smax_cap) smax = smax_cap;
+  if (smax < 1) smax = 1;
+  double best = -1.0;
+  int64_t pick = 1;
+  for (int64_t sp = 1; sp <= smax; ++sp) {
+    const int64_t blocks = tiles * sp;
+    const int64_t rounds = (blocks + capacity - 1) / capacity;
+    const double util = (double)blocks / (double)(rounds * capacity);
+    if (util > best + 0.02) {
+      best = util;
+      pick = sp;
+    }
+  }
+  return pick;
+}
+
+const void* xv_kernel(int xt, int KP) {
+  if (xt == ENMF_F32) {
+    switch (KP) {
+      case 16: return reinterpret_cast<const void*>(&k_xv_f32<16>);
+      case 32: return reinterpret_cast<const void*>(&k_xv_f32<32>);
+      case 48: return reinterpret_cast<const void*>(&k_xv_f32<48>);
+      case 64: return reinterpret_cast<const void*>(&k_xv_f32<64>);
+      default: return reinterpret_cast<const void*>(&k_xv_f32<80>);
+    }
+  }
+  switch (KP) {
+    case 16: return reinterpret_cast<const void*>(&k_xv_bf16<16>);
+    case 32: return reinterpret_cast<const void*>(&k_xv_bf16<32>);
+    case 48: return reinterpret_cast<const void*>(&k_xv_bf16<48>);
+    case 64: return reinterpret_cast<const void*>(&k_xv_bf16<64>);
+    default: return reinterpret_cast<const void*>(&k_xv_bf16<80>);
+  }
+}
+
+const void* xtu_kernel(int xt, int KP) {
+  if (xt == ENMF_F32) {
+    switch (KP) {
+      case 16: return reinterpret_cast<const void*>(&k_xtu_f32<16>);
+      case 32: return reinterpret_cast<const void*>(&k_xtu_f32<32>);
+      case 48: return reinterpret_cast<const void*>(&k_xtu_f32<48>);
+      case 64: return reinterpret_cast<const void*>(&k_xtu_f32<64>);
+      default: return reinterpret_cast<const void*>(&k_xtu_f32<80>);
+    }
+  }
+  switch (KP) {
+    case 16: return reinterpret_cast<const void*>(&k_xtu_bf16<16>);
+    case 32: return reinterpret_cast<const void*>(&k_xtu_bf16<32>);
+    case 48: return reinterpret_cast<const void*>(&k_xtu_bf16<48>);
+    case 64: return reinterpret_cast<const void*>(&k_xtu_bf16<64>);
+    default: return reinterpret_cast<const void*>(&k_xtu_bf16<80>);
+  }
+}
+
+// Grid plan of one product: `tiles` output blocks x `splits` contraction
+// ranges of `cps` chunks each (nch chunks in all).
+struct Plan {
+  int64_t nch, tiles, cps, splits;
+};
+
+Plan make_plan(int64_t nch, int64_t tiles, int64_t min_units, const void* kernel, int64_t smax_cap) {
+  Plan p;
+  p.nch = nch;
+  p.tiles = tiles;
+  const int64_t sp = choose_splits(tiles, nch, min_units, resident_blocks(kernel), smax_cap);
+  p.cps = (nch + sp - 1) / sp;
+  p.splits = (nch + p.cps - 1) / p.cps;
+  return p;
+}
+
+// X B: f32 tiles of 64 rows and 32-column chunks; bf16 tiles of 256 rows and 64-column chunks.
+Plan xv_plan(int xt, int64_t m, int64_t n, int k) {
+  const int KP = mfma_kp(k);
+  if (xt == ENMF_F32) return make_plan((n + 31) / 32, (m + 63) / 64, 8, xv_kernel(xt, KP), 16);
+  return make_plan((n + 63) / 64, (m + 255) / 256, 4, xv_kernel(xt, KP), 64);
+}
+
+// X^T A: f32 tiles of 64 columns and 16-row chunks; bf16 tiles of 512 columns and 32-row chunks.
+Plan xtu_plan(int xt, int64_t m, int64_t n, int k) {
+  const int KP = mfma_kp(k);
+  if (xt == ENMF_F32) return make_plan((m + 15) / 16, (n + 63) / 64, 8, xtu_kernel(xt, KP), 16);
+  return make_plan((m + 31) / 32, (n + 511) / 512, 4, xtu_kernel(xt, KP), 64);
 }
 
 }  // namespace
@@ -662,31 +787,16 @@ bool mfma_eligible(int xt, int k) { return k >= 16 && k <= ENMF_MAX_WIDTH && (xt
 // Workspace (bytes) of the MFMA products: packed factor and split partials.
 void mfma_xv_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes) {
   const int KP = mfma_kp(k);
-  if (xt == ENMF_F32) {
-    const int64_t nch = (n + 31) / 32;
-    *pack_bytes = (size_t)nch * 32 * KP * 4;
-    *part_bytes = (size_t)f32_splits((m + 63) / 64, nch) * m * k * 4;
-  } else {
-    const int64_t nch = (n + 63) / 64;
-    *pack_bytes = (size_t)nch * 3 * KP * kBtLd * 2;
-    const int64_t s = choose_splits((m + 255) / 256, nch, 4);
-    *part_bytes = (size_t)s * m * k * 4;
-  }
+  const Plan p = xv_plan(xt, m, n, k);
+  *pack_bytes = xt == ENMF_F32 ? (size_t)p.nch * 32 * KP * 4 : (size_t)p.nch * 3 * KP * kBtLd * 2;
+  *part_bytes = (size_t)p.splits * m * k * 4;
 }
 
 void mfma_xtu_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes) {
   const int KP = mfma_kp(k);
-  if (xt == ENMF_F32) {
-    const int64_t nch = (m + 15) / 16;
-    *pack_bytes = (size_t)nch * 16 * KP * 4;
-    *part_bytes = (size_t)f32_splits((n + 63) / 64, nch) * n * k * 4;
-  } else {
-    const int64_t tiles = (n + 511) / 512;
-    const int64_t nch = (m + 31) / 32;
-    *pack_bytes = (size_t)nch * 3 * KP * kAtLd * 2;
-    const int64_t s = choose_splits(tiles, nch, 4);
-    *part_bytes = (size_t)s * n * k * 4;
-  }
+  const Plan p = xtu_plan(xt, m, n, k);
+  *pack_bytes = xt == ENMF_F32 ? (size_t)p.nch * 16 * KP * 4 : (size_t)p.nch * 3 * KP * kAtLd * 2;
+  *part_bytes = (size_t)p.splits * n * k * 4;
 }
 
 // P = X B through the matrix cores.  pack and part are workspace of the
@@ -705,9 +815,9 @@ hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t l
     if (do_pack)
       hipLaunchKernelGGL(k_pack_frag_f32, dim3(grid_for(nch * 32 * KP)), dim3(256), 0, s, B, n, k,
                          KP / 16, 32, 8, 0, nch, (float*)pack);
-    const int64_t sp = f32_splits(rg, nch);
-    const int64_t cps = (nch + sp - 1) / sp;
-    eff = (nch + cps - 1) / cps;
+    const Plan pl = xv_plan(xt, m, n, k);
+    const int64_t cps = pl.cps;
+    eff = pl.splits;
     float* dst = eff > 1 ? part : out;
     dim3 grid((unsigned)rg, (unsigned)eff);
     const float* Xf = reinterpret_cast<const float*>(X);
@@ -727,9 +837,9 @@ hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t l
     if (do_pack)
       hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 64 * KP)), dim3(256), 0, s, B, n, k, KP, 64,
                          kBtLd, nch, (unsigned short*)pack);
-    const int64_t sp = choose_splits(rb, nch, 4);
-    const int64_t cps = (nch + sp - 1) / sp;
-    eff = (nch + cps - 1) / cps;
+    const Plan pl = xv_plan(xt, m, n, k);
+    const int64_t cps = pl.cps;
+    eff = pl.splits;
     float* dst = eff > 1 ? part : out;
     dim3 grid((unsigned)rb, (unsigned)eff);
     const unsigned short* Xb = reinterpret_cast<const unsigned short*>(X);
@@ -765,9 +875,9 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
     if (do_pack)
       hipLaunchKernelGGL(k_pack_frag_f32, dim3(grid_for(nch * 16 * KP)), dim3(256), 0, s, A, m, k,
                          KP / 16, 16, 4, 1, nch, (float*)pack);
-    const int64_t sp = f32_splits(cg, nch);
-    const int64_t cps = (nch + sp - 1) / sp;
-    eff = (nch + cps - 1) / cps;
+    const Plan pl = xtu_plan(xt, m, n, k);
+    const int64_t cps = pl.cps;
+    eff = pl.splits;
     float* dst = eff > 1 ? part : out;
     dim3 grid((unsigned)cg, (unsigned)eff);
     const float* Xf = reinterpret_cast<const float*>(X);
@@ -787,9 +897,9 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
     if (do_pack)
       hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 32 * KP)), dim3(256), 0, s, A, m, k, KP, 32,
                          kAtLd, nch, (unsigned short*)pack);
-    const int64_t sp = choose_splits(tiles, nch, 4);
-    const int64_t cps = (nch + sp - 1) / sp;
-    eff = (nch + cps - 1) / cps;
+    const Plan pl = xtu_plan(xt, m, n, k);
+    const int64_t cps = pl.cps;
+    eff = pl.splits;
     float* dst = eff > 1 ? part : out;
     dim3 grid((unsigned)tiles, (unsigned)eff);
     const unsigned short* Xb = reinterpret_cast<const unsigned short*>(X);
