@@ -113,24 +113,35 @@ def config_spectrogram(seed=1003):
     return spectrogram(seed=seed), 40
 
 
-def ratings(m=100000, n=20000, r=20, seed=1004, chunk=5000, rows=None):
+def ratings(m=100000, n=20000, r=20, seed=1004, chunk=5000, rows=None, workers=None):
     """Recommendation-like dense X = clip(U* V*^T + N(0, 0.3^2), 0, 5), float32.
 
     U*, V* ~ U[0, 0.7].  Generated in row chunks from spawned seed sequences
-    so that any row slice can be reproduced on its own.  ``rows`` limits the
+    so that any row slice can be reproduced on its own (and the chunks can be
+    drawn on several threads with identical results).  ``rows`` limits the
     output to the first rows (a row-subsampled slice of the same matrix).
     """
+    from concurrent.futures import ThreadPoolExecutor
+    import os
+
     ss = np.random.SeedSequence(seed)
     kids = ss.spawn(2 + (m + chunk - 1) // chunk)
     Us = np.random.default_rng(kids[0]).uniform(0.0, 0.7, size=(m, r))
     Vs = np.random.default_rng(kids[1]).uniform(0.0, 0.7, size=(n, r))
     mm = m if rows is None else min(rows, m)
     X = np.empty((mm, n), dtype=np.float32)
-    for ci, i0 in enumerate(range(0, mm, chunk)):
+
+    def fill(ci):
+        i0 = ci * chunk
         i1 = min(mm, i0 + chunk)
         rng = np.random.default_rng(kids[2 + ci])
         blk = Us[i0:i1] @ Vs.T + 0.3 * rng.standard_normal((i1 - i0, n))
         X[i0:i1] = np.clip(blk, 0.0, 5.0)
+
+    nchunks = (mm + chunk - 1) // chunk
+    workers = workers or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max(1, min(workers, nchunks))) as ex:
+        list(ex.map(fill, range(nchunks)))
     return X
 
 

@@ -1,0 +1,183 @@
+"""Parity at the full sizes of the workloads, through the C ABI, on outputs the
+oracle computes one by one or on properties that hold at any size.
+
+* image-patch 4096 x 10000, r = 49, float32 (the benchmarked solve): the
+  streaming products on sampled rows and columns against float64 dot
+  products, and a solve (20 fixed rotation steps, 10 iterations) against the
+  oracle run on the same input: U and V within 1e-4.
+* spectrogram 513 x 20000, r = 40, bfloat16 X: sampled products, and the
+  solve run to KKT <= 1e-5 reaches the oracle's relative error (stored in
+  tests/golden/spectrogram_oracle.txt by make_spectrogram_oracle.py) within
+  1e-3.
+* ratings 100000 x 20000, r = 20, float32 and bfloat16 X (the HBM-bound
+  shape): sampled products, and a short solve keeps the invariants of the
+  method (error above the SVD floor, factors nonnegative once the exterior
+  phase is over, objective non-increasing under HALS).
+The product bound is the float32 accumulation bound of test_gpu_kernels, with
+the three-term bfloat16 split of the factor.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2605_19325_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+EPS32 = 2.0 ** -24
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def host(t):
+    return t.detach().cpu().double().numpy()
+
+
+def check_products(lib, Xt, Xd_rows, Xd_cols, rows, cols, k, seed, split):
+    """P = X B on sampled rows and Q = X^T A on sampled columns against float64."""
+    m, n = Xt.shape
+    rng = np.random.default_rng(seed)
+    B = rng.standard_normal((n, k)).astype(np.float32)
+    A = rng.standard_normal((m, k)).astype(np.float32)
+    P = host(lib.xv(Xt, torch.from_numpy(B).to(DEV)))[rows]
+    Q = host(lib.xtu(Xt, torch.from_numpy(A).to(DEV)))[cols]
+    c = 8 * EPS32 * np.sqrt(n) + (2.0 ** -23 if split else 0.0)
+    Pr = Xd_rows @ B.astype(np.float64)
+    assert np.all(np.abs(P - Pr) <= c * (np.abs(Xd_rows) @ np.abs(B.astype(np.float64))) + 1e-30)
+    c = 8 * EPS32 * np.sqrt(m) + (2.0 ** -23 if split else 0.0)
+    Qr = Xd_cols.T @ A.astype(np.float64)
+    assert np.all(np.abs(Q - Qr) <= c * (np.abs(Xd_cols.T) @ np.abs(A.astype(np.float64))) + 1e-30)
+
+
+def sampled(X, Xt_lowp, nrow, ncol, seed):
+    """Sampled rows/columns of X as the device stores it (float64 copies)."""
+    rng = np.random.default_rng(seed)
+    m, n = X.shape
+    rows = np.sort(rng.choice(m, nrow, replace=False))
+    cols = np.sort(rng.choice(n, ncol, replace=False))
+    if Xt_lowp is None:
+        return rows, cols, X[rows].astype(np.float64), X[:, cols].astype(np.float64)
+    r_dev = Xt_lowp[torch.from_numpy(rows).to(DEV)].float().cpu().double().numpy()
+    c_dev = Xt_lowp[:, torch.from_numpy(cols).to(DEV)].float().cpu().double().numpy()
+    return rows, cols, r_dev, c_dev
+
+
+# ---------------------------------------------------------------------------
+# image-patch 4096 x 10000, r = 49, float32
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def image():
+    X, r = inputs.config_image()
+    return X, r, inputs.omega(X.shape[1], r + 10, 1)
+
+
+def test_image_products_sampled(lib, image):
+    X, r, _ = image
+    say("image-patch 4096x10000 fp32: products on 96 sampled rows / columns, k = 49")
+    Xt = torch.from_numpy(X).to(DEV)
+    rows, cols, Xr, Xc = sampled(X, None, 96, 96, 11)
+    check_products(lib, Xt, Xr, Xc, rows, cols, r, 12, False)
+
+
+def test_image_solve_tracks_oracle(lib, image):
+    X, r, om = image
+    say("image-patch 4096x10000 fp32: 20 rotation steps + 10 iterations vs the oracle")
+    Uo, Vo, ro = O.enmf(X, r, om, rot_max_iter=20, rot_tol=0.0, max_iter=10)
+    U, V, rep = lib.solve(torch.from_numpy(X).to(DEV), r, torch.from_numpy(om).to(DEV),
+                          rot_max_iter=20, rot_tol=0.0, max_iter=10)
+    say(f"  U {rel(host(U), Uo):.2e} V {rel(host(V), Vo):.2e} relerr {rep['relerr']:.8e} "
+        f"oracle {ro['relerr']:.8e}")
+    assert rep["iters"] == ro["iters"] == 10
+    assert rel(host(U), Uo) <= 1e-4 and rel(host(V), Vo) <= 1e-4
+    assert abs(rep["relerr"] - ro["relerr"]) <= 1e-5 * ro["relerr"]
+
+
+# ---------------------------------------------------------------------------
+# spectrogram 513 x 20000, r = 40, bfloat16 X
+# ---------------------------------------------------------------------------
+
+def golden(name):
+    out = {}
+    for line in open(os.path.join(HERE, "golden", name)):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v = line.split()
+        out[k] = float(v) if v not in ("True", "False") else v == "True"
+    return out
+
+
+def test_spectrogram_bf16(lib):
+    X, r = inputs.config_spectrogram()
+    om = inputs.omega(X.shape[1], r + 10, 3)
+    say("spectrogram 513x20000 bf16: sampled products; solve to kkt <= 1e-5 vs the oracle's error")
+    Xb = lib.convert(torch.from_numpy(X).to(DEV), torch.bfloat16)
+    rows, cols, Xr, Xc = sampled(X, Xb, 64, 96, 21)
+    check_products(lib, Xb, Xr, Xc, rows, cols, r, 22, True)
+    ref = golden("spectrogram_oracle.txt")
+    U, V, rep = lib.solve(Xb, r, torch.from_numpy(om).to(DEV), max_iter=1500, kkt_tol=1e-5,
+                          check_every=10)
+    err = O.relerr(X, host(U), host(V))       # against the float32 X
+    say(f"  bf16 relerr {err:.6e} (oracle {ref['relerr']:.6e}) kkt {rep['kkt']:.2e} "
+        f"iters {rep['iters']} (oracle {int(ref['iters'])})")
+    assert rep["converged"] == 1 and rep["kkt"] <= 1e-5
+    assert abs(err - ref["relerr"]) <= 1e-3
+
+
+# ---------------------------------------------------------------------------
+# ratings 100000 x 20000, r = 20 (float32 8 GB, bfloat16 4 GB)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def ratings():
+    say("generating the 100000x20000 ratings matrix")
+    X = inputs.ratings()
+    return X, 20
+
+
+def test_ratings_products_sampled(lib, ratings):
+    X, r = ratings
+    say("ratings 100000x20000: fp32 and bf16 products on sampled rows / columns, k = 20")
+    Xt = torch.from_numpy(X).to(DEV)
+    rows, cols, Xr, Xc = sampled(X, None, 48, 48, 31)
+    check_products(lib, Xt, Xr, Xc, rows, cols, r, 32, False)
+    Xb = lib.convert(Xt, torch.bfloat16)
+    del Xt
+    torch.cuda.empty_cache()
+    rows, cols, Xr, Xc = sampled(X, Xb, 48, 48, 33)
+    check_products(lib, Xb, Xr, Xc, rows, cols, r, 34, True)
+
+
+def test_ratings_bf16_solve_invariants(lib, ratings):
+    X, r = ratings
+    say("ratings 100000x20000 bf16: 20 rotation steps + 30 iterations, invariants")
+    Xb = lib.convert(torch.from_numpy(X).to(DEV), torch.bfloat16)
+    torch.cuda.empty_cache()
+    om = torch.from_numpy(inputs.omega(X.shape[1], r + 10, 4)).to(DEV)
+    U, V, rep = lib.solve(Xb, r, om, rot_max_iter=20, rot_tol=0.0, max_iter=30, trace_cap=31)
+    tr = rep["trace"].cpu().numpy()
+    tr = tr[:int(np.count_nonzero(tr[:, 6]))]
+    say(f"  relerr_svd {rep['relerr_svd']:.6e} relerr {rep['relerr']:.6e} kkt {rep['kkt']:.2e} "
+        f"ext {rep['ext_iters_done']}")
+    assert rep["iters"] == 30 and rep["ext_iters_done"] <= 10
+    assert rep["relerr"] >= 0.99 * rep["relerr_svd"] > 0.0
+    assert float(U.min()) >= 0.0 and float(V.min()) >= 0.0
+    # f at the checks of HALS iterations: HALS never increases f; the check
+    # evaluates f through float32 products of the 2e9-entry X (relative noise
+    # up to ~1e-4 of f here), so single steps get that much slack.
+    hals = tr[tr[:, 5] == 1, 1]
+    assert hals.size >= 10
+    assert hals[-1] < hals[0]
+    assert np.all(np.diff(hals) <= 1e-4 * hals[:-1])
