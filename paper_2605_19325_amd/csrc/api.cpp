@@ -260,16 +260,24 @@ enmf_status do_gram(enmf_ctx* c, const void* A, int a_f64, int64_t lda, int64_t 
 }
 
 // Orthonormal basis of the columns of A32 (N x k float32), written to out64
-// and out32 (N x k).  Two passes of Q = A E diag(lambda^-1/2) with the
-// eigenpairs of A^T A; directions with lambda <= tau lambda_max become zero
-// columns.
-enmf_status do_orth(enmf_ctx* c, const float* A32, int64_t N, int k, double* out64, float* out32) {
+// and out32 (N x k).  Passes of Q = A E diag(lambda^-1/2) with the eigenpairs
+// of A^T A; directions with lambda <= tau lambda_max become zero columns.  One
+// pass leaves an orthogonality error of order eps cond(A)^2, enough for the
+// intermediate bases of the power iterations (only their span matters); the
+// second pass brings it to eps.
+enmf_status do_orth(enmf_ctx* c, const float* A32, int64_t N, int k, double* out64, float* out32,
+                    int passes = 2) {
   const double tau = 1e-15;
   WS(G, double, S_C, k * k * 8);
   WS(T, double, S_T, k * k * 8);
-  WS(tmp, double, S_TMP64, N * k * 8);
   TRY(do_gram(c, A32, 0, k, N, k, k, G));
   CK(launch_orth_factor(G, k, tau, T, c->stream));
+  if (passes < 2) {
+    CK(launch_apply_small(A32, 0, k, N, k, T, k, k, out64, 1, k, c->stream));
+    CK(launch_apply_small(A32, 0, k, N, k, T, k, k, out32, 0, k, c->stream));
+    return ENMF_OK;
+  }
+  WS(tmp, double, S_TMP64, N * k * 8);
   CK(launch_apply_small(A32, 0, k, N, k, T, k, k, tmp, 1, k, c->stream));
   TRY(do_gram(c, tmp, 1, k, N, k, k, G));
   CK(launch_orth_factor(G, k, tau, T, c->stream));
@@ -434,9 +442,9 @@ enmf_status enmf_svd_init(enmf_ctx* c, const enmf_matrix* X, int32_t r, const en
 
   TRY(do_xv(c, X, o->omega, k, Y));
   for (int it = 0; it < o->power_iters; ++it) {
-    TRY(do_orth(c, Y, m, k, Qm64, Qm32));
+    TRY(do_orth(c, Y, m, k, Qm64, Qm32, 1));
     TRY(do_xtu(c, X, Qm32, k, Z));
-    TRY(do_orth(c, Z, n, k, Qn64, Qn32));
+    TRY(do_orth(c, Z, n, k, Qn64, Qn32, 1));
     TRY(do_xv(c, X, Qn32, k, Y));
   }
   TRY(do_orth(c, Y, m, k, Qm64, Qm32));

@@ -133,15 +133,24 @@ __device__ __forceinline__ double eigvec(const JacobiT<MAXW>& sm, int a, int j) 
 }
 
 // Polar factor of the KP x KP matrix M held in X (zero padded), in place:
-// the Newton-Schulz iteration X <- 1.5 X - 0.5 X X^T X from X0 = 1.5 M /
+// the Newton-Schulz iteration X <- 1.5 X - 0.5 X (X^T X) from X0 = 1.5 M /
 // ||M||_F (singular values in (0, 1.5], inside the convergence interval
 // (0, sqrt 3)), in float64 until ||X_{k+1} - X_k||_F^2 <= 1e-26 or 100 steps.
 // T is scratch.  Returns false (X untouched) when ||M||_F is 0 or not finite.
+//
+// Both products run on v_mfma_f64_16x16x4f64, 16 x 16 output tiles dealt
+// round robin to the 4 waves.  Lane (i, g) = (l % 16, l / 16) supplies
+// A[i][g] and B[g][i] of each 16 x 4 by 4 x 16 step and receives
+// D[g + 4 v][i] in accumulator element v.
 template <int KP>
 __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double* red) {
-  constexpr int TT = KP / 16;
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int NTL = KP / 16;                  // tiles per side
+  constexpr int NTILE = NTL * NTL;
+  constexpr int PERW = (NTILE + 3) / 4;         // tiles per wave
   static_assert(KP % 16 == 0, "polar_ns_block needs KP a multiple of 16");
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int i = lane % 16, g = lane / 16;
   double nrm = 0.0;
   for (int e = threadIdx.x; e < KP * KP; e += kBlk) nrm = fma(X[e / KP][e % KP], X[e / KP][e % KP], nrm);
   nrm = sqrt(block_sum<kBlk>(nrm, red));
@@ -150,59 +159,57 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
   for (int e = threadIdx.x; e < KP * KP; e += kBlk) X[e / KP][e % KP] *= sc;
   __syncthreads();
   for (int it = 0; it < 100; ++it) {
-    // T = X^T X
-    double acc[TT][TT];
+    // T = X^T X: tile (ti, tj) = sum over k of X[k][16 ti + i] X[k][16 tj + j]
 #pragma unroll
-    for (int i = 0; i < TT; ++i)
+    for (int u = 0; u < PERW; ++u) {
+      const int tile = w + 4 * u;
+      if (tile < NTILE) {
+        const int ti = tile / NTL, tj = tile % NTL;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int k0 = 0; k0 < KP; k0 += 4) {
+          const double a = X[k0 + g][16 * ti + i];
+          const double b = X[k0 + g][16 * tj + i];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
 #pragma unroll
-      for (int j = 0; j < TT; ++j) acc[i][j] = 0.0;
-    for (int q = 0; q < KP; ++q) {
-      double av[TT], bv[TT];
-#pragma unroll
-      for (int i = 0; i < TT; ++i) av[i] = X[q][ty + 16 * i];
-#pragma unroll
-      for (int j = 0; j < TT; ++j) bv[j] = X[q][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < TT; ++i)
-#pragma unroll
-        for (int j = 0; j < TT; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        for (int v = 0; v < 4; ++v) T[16 * ti + g + 4 * v][16 * tj + i] = acc[v];
+      }
     }
-#pragma unroll
-    for (int i = 0; i < TT; ++i)
-#pragma unroll
-      for (int j = 0; j < TT; ++j) T[ty + 16 * i][tx + 16 * j] = acc[i][j];
     __syncthreads();
     // X_new = 1.5 X - 0.5 X T
-#pragma unroll
-    for (int i = 0; i < TT; ++i)
-#pragma unroll
-      for (int j = 0; j < TT; ++j) acc[i][j] = 0.0;
-    for (int q = 0; q < KP; ++q) {
-      double av[TT], bv[TT];
-#pragma unroll
-      for (int i = 0; i < TT; ++i) av[i] = X[ty + 16 * i][q];
-#pragma unroll
-      for (int j = 0; j < TT; ++j) bv[j] = T[q][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < TT; ++i)
-#pragma unroll
-        for (int j = 0; j < TT; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
-    }
+    double xn[PERW][4];
     double d2 = 0.0;
-    double xn[TT][TT];
 #pragma unroll
-    for (int i = 0; i < TT; ++i)
+    for (int u = 0; u < PERW; ++u) {
+      const int tile = w + 4 * u;
+      if (tile < NTILE) {
+        const int ti = tile / NTL, tj = tile % NTL;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int k0 = 0; k0 < KP; k0 += 4) {
+          const double a = X[16 * ti + i][k0 + g];
+          const double b = T[k0 + g][16 * tj + i];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
 #pragma unroll
-      for (int j = 0; j < TT; ++j) {
-        const double x = X[ty + 16 * i][tx + 16 * j];
-        xn[i][j] = 1.5 * x - 0.5 * acc[i][j];
-        d2 = fma(xn[i][j] - x, xn[i][j] - x, d2);
+        for (int v = 0; v < 4; ++v) {
+          const double x = X[16 * ti + g + 4 * v][16 * tj + i];
+          xn[u][v] = 1.5 * x - 0.5 * acc[v];
+          d2 = fma(xn[u][v] - x, xn[u][v] - x, d2);
+        }
       }
+    }
     d2 = block_sum<kBlk>(d2, red);   // also orders every read of X before the writes below
 #pragma unroll
-    for (int i = 0; i < TT; ++i)
+    for (int u = 0; u < PERW; ++u) {
+      const int tile = w + 4 * u;
+      if (tile < NTILE) {
+        const int ti = tile / NTL, tj = tile % NTL;
 #pragma unroll
-      for (int j = 0; j < TT; ++j) X[ty + 16 * i][tx + 16 * j] = xn[i][j];
+        for (int v = 0; v < 4; ++v) X[16 * ti + g + 4 * v][16 * tj + i] = xn[u][v];
+      }
+    }
     __syncthreads();
     if (d2 <= 1e-26) break;
   }

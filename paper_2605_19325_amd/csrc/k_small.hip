@@ -52,14 +52,25 @@ __global__ __launch_bounds__(kT) void k_tsgram(const TA* __restrict__ A, int64_t
   for (int i = 0; i < TT; ++i)
 #pragma unroll
     for (int j = 0; j < TT; ++j) acc[i][j] = 0.0;
+  constexpr int PER = RC * KP / kT;   // staged elements per thread and operand
+  static_assert(RC * KP % kT == 0, "row slab must split evenly over the block");
   for (int64_t t0 = r0; t0 < r1; t0 += RC) {
     const int nr = (int)(r1 - t0 < RC ? r1 - t0 : RC);
-    __syncthreads();
-    for (int e = threadIdx.x; e < RC * KP; e += kT) {
-      const int row = e / KP, col = e % KP;
+    // all of the slab's loads are in flight before the first is stored
+    double va[PER], vb[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * kT, row = e / KP, col = e % KP;
       const bool ok = row < nr;
-      sA[row][col] = (ok && col < ka) ? ld64(A + (t0 + row) * lda + col) : 0.0;
-      sB[row][col] = (ok && col < kb) ? ld64(B + (t0 + row) * ldb + col) : 0.0;
+      va[u] = (ok && col < ka) ? ld64(A + (t0 + row) * lda + col) : 0.0;
+      vb[u] = (ok && col < kb) ? ld64(B + (t0 + row) * ldb + col) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * kT;
+      sA[e / KP][e % KP] = va[u];
+      sB[e / KP][e % KP] = vb[u];
     }
     __syncthreads();
     for (int rr = 0; rr < nr; ++rr) {
@@ -230,6 +241,9 @@ __global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, 
                                                   double* __restrict__ B, const DevState* st,
                                                   int step, double* __restrict__ negpart) {
   __shared__ double sh[kT / kWave];
+  __shared__ double Rs[KP * KP];
+  for (int e = threadIdx.x; e < KP * KP; e += kT) Rs[e] = R[e];
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
   const bool valid = i < N;
   const double rho = st->rho;
@@ -239,11 +253,10 @@ __global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, 
     double w[KP];
 #pragma unroll
     for (int c = 0; c < KP; ++c) w[c] = W[i * KP + c];
-#pragma unroll
     for (int c = 0; c < KP; ++c) {
       double wr = 0.0;
 #pragma unroll
-      for (int a = 0; a < KP; ++a) wr = fma(w[a], R[a * KP + c], wr);
+      for (int a = 0; a < KP; ++a) wr = fma(w[a], Rs[a * KP + c], wr);
       double y = 0.0;
       if (step > 0) y = Y[i * KP + c] + rho * (Z[i * KP + c] - wr);
       const double b = wr - y * irho;
