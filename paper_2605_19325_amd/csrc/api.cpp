@@ -496,8 +496,7 @@ enmf_status enmf_rotate(enmf_ctx* c, int64_t m, int64_t n, int32_t r, float* U, 
   WS(Za, double, S_ZA, N * kp * 8);
   WS(Ba, double, S_BA, N * kp * 8);
   WS(R, double, S_R, kp * kp * 8);
-  const int nbr = (int)((N + 255) / 256);
-  WS(negp, double, S_NEGP, nbr * 8);
+  WS(negp, double, S_NEGP, (int64_t)admm_rows_blocks(N, kp) * 8);
   WS(wsq, double, S_WSQ, 512 * 8);
   const int nbm = gram_blocks(N);
   WS(mpart, double, S_MPART, (int64_t)nbm * r * r * 8);

@@ -142,6 +142,7 @@ hipError_t launch_pack_w(const float* U, int64_t m, const float* V, int64_t n, i
 hipError_t launch_w_sumsq(const double* W, int64_t count, double* part, int* nparts, hipStream_t s);
 hipError_t launch_rho_init(const double* part, int nparts, int64_t N, int r, double rho0, DevState* st,
                            hipStream_t s);
+int admm_rows_blocks(int64_t N, int kp);
 hipError_t launch_admm_rows(const double* W, int64_t N, int r, int kp, const double* R, double* Y,
                             double* Z, double* B, DevState* st, int step, double* negpart,
                             hipStream_t s);

@@ -230,41 +230,61 @@ __global__ void k_rho_init(const double* __restrict__ part, int nparts, int64_t 
   st->dR = INFINITY;
 }
 
-// One row of the ADMM step (Algorithm 1): with WR = W R^k,
+// Rows of the ADMM step (Algorithm 1): with WR = W R^k,
 //   Y <- Y + rho (Z - WR)        (the dual update of the previous step; step > 0)
 //   b = WR - Y / rho,  Z = prox_h(b) (eq. 7),  B = Z + Y / rho.
-// R is kp x kp float64 (zero padded).  negpart[b] = sum h(WR) over the block.
+// R is kp x kp float64 (zero padded), staged in LDS with the block's rows of
+// W; KP/8 threads share a row, 8 columns each, so every thread runs 8
+// independent dot products of length KP.  negpart[b] = sum h(WR) over the
+// block's rows.
+template <int KP> struct AdmmGeom {
+  static constexpr int CG = KP / 8;        // threads per row
+  static constexpr int RB = kT / CG;       // rows per block
+};
+
 template <int KP>
 __global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, int64_t N,
                                                   const double* __restrict__ R,
                                                   double* __restrict__ Y, double* __restrict__ Z,
                                                   double* __restrict__ B, const DevState* st,
                                                   int step, double* __restrict__ negpart) {
+  using AG = AdmmGeom<KP>;
   __shared__ double sh[kT / kWave];
   __shared__ double Rs[KP * KP];
+  __shared__ double Ws[AG::RB * KP];
+  const int64_t row0 = (int64_t)blockIdx.x * AG::RB;
+  const int64_t nrow = N - row0 < AG::RB ? N - row0 : AG::RB;
   for (int e = threadIdx.x; e < KP * KP; e += kT) Rs[e] = R[e];
+  for (int e = threadIdx.x; e < AG::RB * KP; e += kT) Ws[e] = e < nrow * KP ? W[row0 * KP + e] : 0.0;
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
-  const bool valid = i < N;
+  const int rr = threadIdx.x / AG::CG, c0 = 8 * (threadIdx.x % AG::CG);
+  const bool valid = rr < AG::RB && rr < nrow;
   const double rho = st->rho;
   const double irho = 1.0 / rho;
   double neg = 0.0;
   if (valid) {
-    double w[KP];
+    double wr[8];
 #pragma unroll
-    for (int c = 0; c < KP; ++c) w[c] = W[i * KP + c];
-    for (int c = 0; c < KP; ++c) {
-      double wr = 0.0;
+    for (int e = 0; e < 8; ++e) wr[e] = 0.0;
+    const double* w = Ws + rr * KP;
+    for (int a = 0; a < KP; ++a) {
+      const double x = w[a];
+      const double* rrow = Rs + a * KP + c0;
 #pragma unroll
-      for (int a = 0; a < KP; ++a) wr = fma(w[a], Rs[a * KP + c], wr);
+      for (int e = 0; e < 8; ++e) wr[e] = fma(x, rrow[e], wr[e]);
+    }
+    const int64_t i = row0 + rr;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t idx = i * KP + c0 + e;
       double y = 0.0;
-      if (step > 0) y = Y[i * KP + c] + rho * (Z[i * KP + c] - wr);
-      const double b = wr - y * irho;
+      if (step > 0) y = Y[idx] + rho * (Z[idx] - wr[e]);
+      const double b = wr[e] - y * irho;
       const double z = b > 0.0 ? b : (b >= -irho ? 0.0 : b + irho);
-      Y[i * KP + c] = y;
-      Z[i * KP + c] = z;
-      B[i * KP + c] = z + y * irho;
-      neg += wr < 0.0 ? -wr : 0.0;
+      Y[idx] = y;
+      Z[idx] = z;
+      B[idx] = z + y * irho;
+      neg += wr[e] < 0.0 ? -wr[e] : 0.0;
     }
   }
   neg = block_sum<kT>(neg, sh);
@@ -414,17 +434,23 @@ hipError_t launch_rho_init(const double* part, int nparts, int64_t N, int r, dou
   return hipGetLastError();
 }
 
+int admm_rows_blocks(int64_t N, int kp) {
+  const int rb = kT / (kp / 8);
+  return (int)((N + rb - 1) / rb);
+}
+
 hipError_t launch_admm_rows(const double* W, int64_t N, int r, int kp, const double* R, double* Y,
                             double* Z, double* B, DevState* st, int step, double* negpart,
                             hipStream_t s) {
   (void)r;
-  dim3 g((unsigned)((N + kT - 1) / kT)), b(kT);
+  dim3 g((unsigned)admm_rows_blocks(N, kp)), b(kT);
   switch (kp) {
     case 8: hipLaunchKernelGGL((k_admm_rows<8>), g, b, 0, s, W, N, R, Y, Z, B, st, step, negpart); break;
     case 16: hipLaunchKernelGGL((k_admm_rows<16>), g, b, 0, s, W, N, R, Y, Z, B, st, step, negpart); break;
     case 32: hipLaunchKernelGGL((k_admm_rows<32>), g, b, 0, s, W, N, R, Y, Z, B, st, step, negpart); break;
     case 48: hipLaunchKernelGGL((k_admm_rows<48>), g, b, 0, s, W, N, R, Y, Z, B, st, step, negpart); break;
-    default: hipLaunchKernelGGL((k_admm_rows<64>), g, b, 0, s, W, N, R, Y, Z, B, st, step, negpart); break;
+    case 64: hipLaunchKernelGGL((k_admm_rows<64>), g, b, 0, s, W, N, R, Y, Z, B, st, step, negpart); break;
+    default: hipLaunchKernelGGL((k_admm_rows<80>), g, b, 0, s, W, N, R, Y, Z, B, st, step, negpart); break;
   }
   return hipGetLastError();
 }

@@ -108,6 +108,8 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
   __shared__ double sG[KP * KP];
   __shared__ __align__(16) float sa[TM::RB][KP + 4];
   __shared__ float sgv[TM::RB][KP + 1];
+  __shared__ double sT[KP >= 16 ? TM::RB : 1][KP + 1];
+  __shared__ double sinv[KP];
   __shared__ double sh[NF * NW];
   if (st->stop) return;
   const bool update = (flags & kRowUpdate) != 0;
@@ -147,7 +149,22 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
     a[e] = sa[team][c0 + e];
     p[e] = needG ? (double)sgv[team][c0 + e] : 0.0;
   }
+  // reciprocals of the Gram diagonal for the HALS steps (0 skips a column)
+  if (needG && threadIdx.x < KP) {
+    const double gjj = sG[threadIdx.x * KP + threadIdx.x];
+    sinv[threadIdx.x] = gjj > 0.0 ? 1.0 / gjj : 0.0;
+  }
   __syncthreads();
+  // out = (row of `src` owned by this team) G, through the matrix cores when KP >= 16
+  auto times_g = [&](auto src, double* out) {
+    if constexpr (KP >= 16) {
+      block_times_g<KP>(src, sG, sT);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) out[e] = sT[team][c0 + e];
+    } else {
+      row_times_g<KP>(src[team], sG, c0, out);
+    }
+  };
   CheckAcc ck;
   double gi2 = 0.0, pg2 = 0.0;
   double t[8];
@@ -156,7 +173,7 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
 #pragma unroll
     for (int e = 0; e < 8; ++e) sa[team][c0 + e] = a[e];
     __syncthreads();
-    row_times_g<KP>(sa[team], sG, c0, t);
+    times_g(sa, t);
     have_t = true;
     if (valid) ck.add(a, t, p, c0, r);
   }
@@ -166,19 +183,19 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
 #pragma unroll
       for (int e = 0; e < 8; ++e) sa[team][c0 + e] = a[e];
       __syncthreads();
-      row_times_g<KP>(sa[team], sG, c0, t);
+      times_g(sa, t);
     }
     const int base = (threadIdx.x % kWave) - q;
     for (int j = 0; j < r; ++j) {
       const int o = j / 8, ej = j % 8;
       double delta = 0.0;
       if (q == o) {
-        const double gjj = sG[j * KP + j];
-        if (gjj > 0.0) {
+        const double ig = sinv[j];
+        if (ig > 0.0) {
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
             if (e == ej) {
-              const double v = (double)a[e] + (p[e] - t[e]) / gjj;
+              const double v = (double)a[e] + (p[e] - t[e]) * ig;
               const float nv = (float)(v > 0.0 ? v : 0.0);
               delta = (double)nv - (double)a[e];
               a[e] = nv;
@@ -206,7 +223,7 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
       for (int e = 0; e < 8; ++e) sa[team][c0 + e] = a[e];
       __syncthreads();
       double s[8];
-      row_times_g<KP>(sa[team], sG, c0, s);
+      times_g(sa, s);
       float g[8];
       double num = 0.0;
 #pragma unroll
@@ -218,7 +235,7 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
       if (sw == 0 && first) gi2 = num;
       __syncthreads();
       double h[8];
-      row_times_g<KP>(sgv[team], sG, c0, h);
+      times_g(sgv, h);
       double den = 0.0;
 #pragma unroll
       for (int e = 0; e < 8; ++e) den = fma((double)g[e], h[e], den);
@@ -242,7 +259,7 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
 #pragma unroll
       for (int e = 0; e < 8; ++e) sa[team][c0 + e] = a[e];
       __syncthreads();
-      row_times_g<KP>(sa[team], sG, c0, t);
+      times_g(sa, t);
     }
     if (want_pg && update && phase == kPhaseExt) {
 #pragma unroll

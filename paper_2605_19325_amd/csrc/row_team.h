@@ -89,6 +89,39 @@ __device__ __forceinline__ void row_times_g(const RT* row, const double* sG, int
   }
 }
 
+// sT[row][c] = sum_b A[row][b] G[b][c] for the RB rows of a block (A: LDS
+// rows of float32, G: LDS KP x KP float64), on v_mfma_f64_16x16x4f64: the
+// RB x KP result in 16 x 16 tiles dealt round robin to the block's waves.
+// Lane (i, g) supplies A[i][g] and B[g][i] of each 16 x 4 by 4 x 16 step and
+// receives D[g + 4 v][i].  Called by every thread of the block; barriers on
+// entry and exit.
+template <int KP, int LDA>
+__device__ __forceinline__ void block_times_g(const float (*A)[LDA], const double* sG,
+                                              double (*sT)[KP + 1]) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  using TM = Team<KP>;
+  constexpr int TC = KP / 16;
+  constexpr int NTILE = (TM::RB / 16) * TC;
+  constexpr int NW = TM::NT / kWave;
+  static_assert(KP % 16 == 0 && TM::RB % 16 == 0, "matrix-core row products need 16 | KP");
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int i = lane % 16, g = lane / 16;
+  __syncthreads();
+  for (int tile = w; tile < NTILE; tile += NW) {
+    const int ti = tile / TC, tj = tile % TC;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < KP; k0 += 4) {
+      const double a = (double)A[16 * ti + i][k0 + g];
+      const double b = sG[(k0 + g) * KP + 16 * tj + i];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sT[16 * ti + g + 4 * v][16 * tj + i] = acc[v];
+  }
+  __syncthreads();
+}
+
 // Upper-triangle 4x4 tile `task` of a KP x KP matrix -> (ti, tj), ti <= tj.
 template <int KP>
 __device__ __forceinline__ void gram_tile(int task, int& ti, int& tj) {
