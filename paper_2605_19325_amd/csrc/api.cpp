@@ -673,6 +673,7 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
   float* Ub[2] = {U, b.U2};
   Parts pp;
   c->pending[0] = c->pending[1] = 0;
+
   auto sample = [&](int kind, int k) -> hipEvent_t* {
     if (c->timing_period <= 0 || k % c->timing_period != 0 || c->pending[kind] >= kTimingPairs)
       return nullptr;

@@ -159,44 +159,65 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
   for (int e = threadIdx.x; e < KP * KP; e += kBlk) X[e / KP][e % KP] *= sc;
   __syncthreads();
   for (int it = 0; it < 100; ++it) {
-    // T = X^T X: tile (ti, tj) = sum over k of X[k][16 ti + i] X[k][16 tj + j]
+    // T = X^T X: tile (ti, tj) = sum over k of X[k][16 ti + i] X[k][16 tj + j].
+    // A wave's tiles advance together through k (independent MFMA chains).
+    {
+      d4 acc[PERW];
 #pragma unroll
-    for (int u = 0; u < PERW; ++u) {
-      const int tile = w + 4 * u;
-      if (tile < NTILE) {
-        const int ti = tile / NTL, tj = tile % NTL;
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-        for (int k0 = 0; k0 < KP; k0 += 4) {
-          const double a = X[k0 + g][16 * ti + i];
-          const double b = X[k0 + g][16 * tj + i];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      for (int u = 0; u < PERW; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+      for (int k0 = 0; k0 < KP; k0 += 4) {
+#pragma unroll
+        for (int u = 0; u < PERW; ++u) {
+          const int tile = w + 4 * u;
+          if (tile < NTILE) {
+            const int ti = tile / NTL, tj = tile % NTL;
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[k0 + g][16 * ti + i], X[k0 + g][16 * tj + i],
+                                                          acc[u], 0, 0, 0);
+          }
         }
+      }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) T[16 * ti + g + 4 * v][16 * tj + i] = acc[v];
+      for (int u = 0; u < PERW; ++u) {
+        const int tile = w + 4 * u;
+        if (tile < NTILE) {
+          const int ti = tile / NTL, tj = tile % NTL;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) T[16 * ti + g + 4 * v][16 * tj + i] = acc[u][v];
+        }
       }
     }
     __syncthreads();
     // X_new = 1.5 X - 0.5 X T
     double xn[PERW][4];
     double d2 = 0.0;
+    {
+      d4 acc[PERW];
 #pragma unroll
-    for (int u = 0; u < PERW; ++u) {
-      const int tile = w + 4 * u;
-      if (tile < NTILE) {
-        const int ti = tile / NTL, tj = tile % NTL;
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-        for (int k0 = 0; k0 < KP; k0 += 4) {
-          const double a = X[16 * ti + i][k0 + g];
-          const double b = T[k0 + g][16 * tj + i];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      for (int u = 0; u < PERW; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+      for (int k0 = 0; k0 < KP; k0 += 4) {
+#pragma unroll
+        for (int u = 0; u < PERW; ++u) {
+          const int tile = w + 4 * u;
+          if (tile < NTILE) {
+            const int ti = tile / NTL, tj = tile % NTL;
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[16 * ti + i][k0 + g], T[k0 + g][16 * tj + i],
+                                                          acc[u], 0, 0, 0);
+          }
         }
+      }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const double x = X[16 * ti + g + 4 * v][16 * tj + i];
-          xn[u][v] = 1.5 * x - 0.5 * acc[v];
-          d2 = fma(xn[u][v] - x, xn[u][v] - x, d2);
+      for (int u = 0; u < PERW; ++u) {
+        const int tile = w + 4 * u;
+        if (tile < NTILE) {
+          const int ti = tile / NTL, tj = tile % NTL;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double x = X[16 * ti + g + 4 * v][16 * tj + i];
+            xn[u][v] = 1.5 * x - 0.5 * acc[u][v];
+            d2 = fma(xn[u][v] - x, xn[u][v] - x, d2);
+          }
         }
       }
     }

@@ -2,7 +2,9 @@
 // where each product is a real dense contraction (appendix on complexity:
 // X V and X^T U, O(mnr) per half-iteration).
 //
-//   float32 X: v_mfma_f32_16x16x4_f32, float32 accumulate.
+//   float32 X, X B: X and the factor each split into three bfloat16 terms on
+//     v_mfma_f32_16x16x32_bf16 (six of the nine term products), float32
+//     accumulate; X^T A: v_mfma_f32_16x16x4_f32.
 //   bfloat16 X: v_mfma_f32_16x16x32_bf16, float32 accumulate, with the float32
 //     factor split into three bfloat16 terms (hi = rne(v), mid = rne(v - hi),
 //     lo = rne(v - hi - mid), |v - hi - mid - lo| <= 2^-24 |v|), so that
@@ -16,7 +18,8 @@
 // free to be permuted as long as A and B agree, which lets every lane load
 // contiguous runs of a row of X.
 //
-// X V  : lanes take rows of X (16 per tile); the factor chunk sits in LDS.
+// X V  : lanes take rows of X (16 per tile); the factor chunk sits in LDS,
+//        prefetched through registers.
 // X^T U: lanes take 16-byte runs along a row of X; a tile covers a strided
 //        set of 16 columns.  For bfloat16 the 8 x 8 blocks are transposed
 //        in registers (v_perm) so that each lane holds 8 rows of one column.
@@ -103,135 +106,6 @@ __device__ __forceinline__ void store_tile_rows(float* __restrict__ out, int64_t
     const int64_t row = row0 + 4 * g + v;
     if (row < m) out[row * k + col] = d[v];
   }
-}
-
-// ---------------------------------------------------------------------------
-// float32 X: P = X B.  A block's 4 waves share 64 rows (4 tiles of 16) and
-// split the block's range of 32-column chunks four ways (chunk c goes to wave
-// c mod 4), so no barrier is needed inside the loop; the waves are summed in
-// LDS at the end in a fixed order.  Lane (i, g) of row tile rt loads
-// X[row0 + 16 rt + i][kc + 16h + 4g .. +3] for h = 0, 1 (each load instruction
-// reads 64 contiguous bytes of 16 rows); MFMA step s (0..7) contracts column
-// kc + 16 (s/4) + 4g + s%4.  The factor comes pre-packed in operand order:
-// Bf[chunk][jt][lane][s] = B[kc + 16 (s/4) + 4g + s%4][16 jt + i].
-// ---------------------------------------------------------------------------
-template <int KP>
-__global__ __launch_bounds__(kT, 2) void k_xv_f32(const float* __restrict__ X, int64_t m, int64_t n,
-                                                  int64_t ld, const float4* __restrict__ Bf, int k,
-                                                  int chunks_per_split, int64_t nchunks, int vec,
-                                                  float* __restrict__ out, int64_t split_stride,
-    const int32_t* __restrict__ stop) {
-  if (stop != nullptr && *stop) return;
-  constexpr int NT = KP / 16;
-  constexpr int RT = 4;
-  __shared__ f32x4 red[3][RT * NT][kWave];
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const int i = lane % 16, g = lane / 16;
-  const int64_t row0 = (int64_t)blockIdx.x * 64;
-  const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
-  const int64_t c1 = c0 + chunks_per_split < nchunks ? c0 + chunks_per_split : nchunks;
-
-  f32x4 acc[RT][NT];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int jt = 0; jt < NT; ++jt) acc[rt][jt] = zero4();
-
-  // Interior chunks (whole 64-row group in range, 32 full columns, 16-byte
-  // aligned rows) take unconditional loads into two register sets used in
-  // turn, so each chunk's loads stay in flight while the previous chunk is
-  // multiplied.  Edge chunks (at most the last one) use masked loads.
-  auto load_b = [&](int64_t ch, float4 (&bs)[NT][2]) {
-    const float4* b = Bf + ((ch * NT) * kWave + lane) * 2;
-#pragma unroll
-    for (int jt = 0; jt < NT; ++jt) {
-      bs[jt][0] = b[jt * kWave * 2];
-      bs[jt][1] = b[jt * kWave * 2 + 1];
-    }
-  };
-  auto load_fast = [&](int64_t ch, uint4 (&xs)[RT][2], float4 (&bs)[NT][2]) {
-    const float* base = X + (row0 + i) * ld + ch * 32 + 4 * g;
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) xs[rt][h] = ldg16(base + 16 * rt * ld + 16 * h);
-    load_b(ch, bs);
-  };
-  auto load_slow = [&](int64_t ch, uint4 (&xs)[RT][2], float4 (&bs)[NT][2]) {
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-        xs[rt][h] = load16<float>(X, m, n, ld, row0 + 16 * rt + i, ch * 32 + 16 * h + 4 * g, vec != 0);
-    load_b(ch, bs);
-  };
-  auto compute = [&](const uint4 (&xs)[RT][2], const float4 (&bs)[NT][2]) {
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        const uint4 q = xs[rt][s / 4];
-        const unsigned wv = (s % 4 == 0) ? q.x : (s % 4 == 1) ? q.y : (s % 4 == 2) ? q.z : q.w;
-        const float a = __uint_as_float(wv);
-#pragma unroll
-        for (int jt = 0; jt < NT; ++jt) {
-          const float4 bq = bs[jt][s / 4];
-          const float bv = (s % 4 == 0) ? bq.x : (s % 4 == 1) ? bq.y : (s % 4 == 2) ? bq.z : bq.w;
-          acc[rt][jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[rt][jt], 0, 0, 0);
-        }
-      }
-    }
-  };
-  const bool rows_ok = vec && row0 + 64 <= m;
-  const int64_t full = n / 32;
-  const int64_t cfull = rows_ok ? (c1 < full ? c1 : full) : c0;
-  int64_t ch = c0 + w;
-  if (ch < cfull) {
-    uint4 xA[RT][2], xB[RT][2];
-    float4 bA[NT][2], bB[NT][2];
-    // Pairs of chunks per loop trip keep each prefetch in the same basic block
-    // as the multiply it overlaps (so it is not sunk past a branch); the
-    // scheduling barrier keeps it ahead of that multiply.
-    const int64_t cnt = (cfull - ch + 3) / 4;
-    const int64_t last = ch + 4 * (cnt - 1);
-    load_fast(ch, xA, bA);
-    int64_t c = ch;
-    for (int64_t p = 0; p + 1 < cnt; p += 2) {
-      load_fast(c + 4, xB, bB);
-      __builtin_amdgcn_sched_barrier(0);
-      compute(xA, bA);
-      load_fast(c + 8 < last ? c + 8 : last, xA, bA);
-      __builtin_amdgcn_sched_barrier(0);
-      compute(xB, bB);
-      c += 8;
-    }
-    if (cnt & 1) compute(xA, bA);
-    ch += 4 * cnt;
-  }
-  for (; ch < c1; ch += 4) {
-    uint4 xs[RT][2];
-    float4 bs[NT][2];
-    load_slow(ch, xs, bs);
-    compute(xs, bs);
-  }
-  if (w > 0) {
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int jt = 0; jt < NT; ++jt) red[w - 1][rt * NT + jt][lane] = acc[rt][jt];
-  }
-  __syncthreads();
-  if (w != 0) return;
-  float* o = out + (int64_t)blockIdx.y * split_stride;
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int jt = 0; jt < NT; ++jt) {
-      f32x4 v = acc[rt][jt];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) v += red[q][rt * NT + jt][lane];
-      store_tile_rows(o, m, k, row0 + 16 * rt, 16 * jt, v);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -455,6 +329,159 @@ __global__ __launch_bounds__(kT) void k_xv_bf16(const unsigned short* __restrict
             acc[rt][nt] =
                 __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(xa[rt][s]), b, acc[rt][nt], 0, 0, 0);
         }
+      }
+    }
+    if (more) {
+      store_b(buf ^ 1);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) { xa[rt][0] = xb[rt][0]; xa[rt][1] = xb[rt][1]; }
+    }
+    buf ^= 1;
+  }
+  float* o = out + (int64_t)blockIdx.y * split_stride;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) store_tile_rows(o, m, k, row0 + 16 * rt, 16 * nt, acc[rt][nt]);
+}
+
+// ---------------------------------------------------------------------------
+// float32 X through the bfloat16 matrix cores: X = x1 + x2 + x3 and
+// B = b1 + b2 + b3 (three-term bfloat16 splits, |v - v1 - v2 - v3| <= 2^-24 |v|),
+// and X B = sum of the six products xa bc with a + c <= 4; the three dropped
+// ones together stay below 2^-23 |x||b|, so the result keeps float32
+// accuracy while each 32-step costs six 16x16x32 bf16 MFMAs instead of eight
+// 16x16x4 f32 ones of twice the cycles.  Block = 4 waves x 64 rows; chunk =
+// 32 columns of X (one MFMA step).  Lane (i, g) of row tile rt loads
+// X[row0 + 16 rt + i][kc + 8g .. +7] (two 16-byte loads) and splits it in
+// registers; the factor chunk is Bt[part][16 nt + i][8g .. +7] in LDS,
+// transposed with rows padded to 40, prefetched through registers like the
+// bfloat16 kernel's.
+// ---------------------------------------------------------------------------
+constexpr int kBt32Ld = 40;
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ unsigned pk_bf16(f32x2 v) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+}
+
+// Eight floats (lo = elements 0..3, hi = 4..7) -> three packed bf16 terms.
+__device__ __forceinline__ void split3(const uint4& lo, const uint4& hi, uint4& p1, uint4& p2,
+                                       uint4& p3) {
+  const unsigned w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+  unsigned a[4], b[4], c[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const f32x2 x = {__uint_as_float(w[2 * d]), __uint_as_float(w[2 * d + 1])};
+    const unsigned h = pk_bf16(x);
+    const f32x2 fh = {__uint_as_float(h << 16), __uint_as_float(h & 0xffff0000u)};
+    const f32x2 r = x - fh;
+    const unsigned mm = pk_bf16(r);
+    const f32x2 fm = {__uint_as_float(mm << 16), __uint_as_float(mm & 0xffff0000u)};
+    const unsigned l = pk_bf16(r - fm);
+    a[d] = h;
+    b[d] = mm;
+    c[d] = l;
+  }
+  p1 = make_uint4(a[0], a[1], a[2], a[3]);
+  p2 = make_uint4(b[0], b[1], b[2], b[3]);
+  p3 = make_uint4(c[0], c[1], c[2], c[3]);
+}
+
+template <int KP>
+__global__ __launch_bounds__(kT) void k_xv_f32s(const float* __restrict__ X, int64_t m, int64_t n,
+                                                int64_t ld, const unsigned short* __restrict__ Bt,
+                                                int k, int chunks_per_split, int64_t nchunks,
+                                                int vec, float* __restrict__ out,
+                                                int64_t split_stride,
+                                                const int32_t* __restrict__ stop) {
+  if (stop != nullptr && *stop) return;
+  constexpr int NT = KP / 16;
+  constexpr int RT = 4;
+  constexpr int CH = 3 * KP * kBt32Ld;   // elements of one packed chunk (three terms)
+  __shared__ __align__(16) unsigned short Bs[2][CH];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int i = lane % 16, g = lane / 16;
+  const int64_t row0 = (int64_t)blockIdx.x * (4 * 64) + 64 * w;
+  const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
+  const int64_t c1 = c0 + chunks_per_split < nchunks ? c0 + chunks_per_split : nchunks;
+
+  f32x4 acc[RT][NT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = zero4();
+
+  uint4 xa[RT][2], xb[RT][2];
+  auto load_x = [&](int64_t ch, uint4 (&dst)[RT][2]) {
+    const bool interior = vec && row0 + 64 <= m && (ch + 1) * 32 <= n;   // wave-uniform
+    if (interior) {
+      const float* base = X + (row0 + i) * ld + ch * 32 + 8 * g;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) dst[rt][h] = ldg16(base + 16 * rt * ld + 4 * h);
+    } else {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          dst[rt][h] = load16<float>(X, m, n, ld, row0 + 16 * rt + i, ch * 32 + 8 * g + 4 * h,
+                                     vec != 0);
+    }
+  };
+  constexpr int NBQ = (CH / 8 + kT - 1) / kT;
+  uint4 bq_next[NBQ];
+  auto fetch_b = [&](int64_t ch) {
+    const uint4* src = reinterpret_cast<const uint4*>(Bt + ch * CH);
+#pragma unroll
+    for (int u = 0; u < NBQ; ++u) {
+      const int e = threadIdx.x + u * kT;
+      bq_next[u] = e < CH / 8 ? src[e] : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto store_b = [&](int buf) {
+    uint4* dst = reinterpret_cast<uint4*>(Bs[buf]);
+#pragma unroll
+    for (int u = 0; u < NBQ; ++u) {
+      const int e = threadIdx.x + u * kT;
+      if (e < CH / 8) dst[e] = bq_next[u];
+    }
+  };
+  if (c0 < c1) {
+    fetch_b(c0);
+    load_x(c0, xa);
+    store_b(0);
+  }
+  int buf = 0;
+  for (int64_t ch = c0; ch < c1; ++ch) {
+    __syncthreads();
+    const bool more = ch + 1 < c1;
+    if (more) {
+      fetch_b(ch + 1);
+      load_x(ch + 1, xb);
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      uint4 x1, x2, x3;
+      split3(xa[rt][0], xa[rt][1], x1, x2, x3);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const unsigned short* bp = &Bs[buf][(16 * nt + i) * kBt32Ld + 8 * g];
+        const bf16x8 b1 = as_bf16x8(*reinterpret_cast<const uint4*>(bp));
+        const bf16x8 b2 = as_bf16x8(*reinterpret_cast<const uint4*>(bp + KP * kBt32Ld));
+        const bf16x8 b3 = as_bf16x8(*reinterpret_cast<const uint4*>(bp + 2 * KP * kBt32Ld));
+        f32x4 a = acc[rt][nt];
+        // smallest terms first
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(x3), b1, a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(x2), b2, a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(x1), b3, a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(x2), b1, a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(x1), b2, a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(x1), b1, a, 0, 0, 0);
+        acc[rt][nt] = a;
       }
     }
     if (more) {
@@ -715,11 +742,11 @@ int64_t choose_splits(int64_t tiles, int64_t units, int64_t min_units, int64_t c
 const void* xv_kernel(int xt, int KP) {
   if (xt == ENMF_F32) {
     switch (KP) {
-      case 16: return reinterpret_cast<const void*>(&k_xv_f32<16>);
-      case 32: return reinterpret_cast<const void*>(&k_xv_f32<32>);
-      case 48: return reinterpret_cast<const void*>(&k_xv_f32<48>);
-      case 64: return reinterpret_cast<const void*>(&k_xv_f32<64>);
-      default: return reinterpret_cast<const void*>(&k_xv_f32<80>);
+      case 16: return reinterpret_cast<const void*>(&k_xv_f32s<16>);
+      case 32: return reinterpret_cast<const void*>(&k_xv_f32s<32>);
+      case 48: return reinterpret_cast<const void*>(&k_xv_f32s<48>);
+      case 64: return reinterpret_cast<const void*>(&k_xv_f32s<64>);
+      default: return reinterpret_cast<const void*>(&k_xv_f32s<80>);
     }
   }
   switch (KP) {
@@ -766,10 +793,10 @@ Plan make_plan(int64_t nch, int64_t tiles, int64_t min_units, const void* kernel
   return p;
 }
 
-// X B: f32 tiles of 64 rows and 32-column chunks; bf16 tiles of 256 rows and 64-column chunks.
+// X B: tiles of 256 rows; f32 in 32-column chunks, bf16 in 64-column chunks.
 Plan xv_plan(int xt, int64_t m, int64_t n, int k) {
   const int KP = mfma_kp(k);
-  if (xt == ENMF_F32) return make_plan((n + 31) / 32, (m + 63) / 64, 8, xv_kernel(xt, KP), 16);
+  if (xt == ENMF_F32) return make_plan((n + 31) / 32, (m + 255) / 256, 4, xv_kernel(xt, KP), 64);
   return make_plan((n + 63) / 64, (m + 255) / 256, 4, xv_kernel(xt, KP), 64);
 }
 
@@ -788,7 +815,7 @@ bool mfma_eligible(int xt, int k) { return k >= 16 && k <= ENMF_MAX_WIDTH && (xt
 void mfma_xv_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes) {
   const int KP = mfma_kp(k);
   const Plan p = xv_plan(xt, m, n, k);
-  *pack_bytes = xt == ENMF_F32 ? (size_t)p.nch * 32 * KP * 4 : (size_t)p.nch * 3 * KP * kBtLd * 2;
+  *pack_bytes = xt == ENMF_F32 ? (size_t)p.nch * 3 * KP * kBt32Ld * 2 : (size_t)p.nch * 3 * KP * kBtLd * 2;
   *part_bytes = (size_t)p.splits * m * k * 4;
 }
 
@@ -811,24 +838,24 @@ hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t l
   int64_t eff = 1;
   if (xt == ENMF_F32) {
     const int64_t nch = (n + 31) / 32;
-    const int64_t rg = (m + 63) / 64;
+    const int64_t rb = (m + 255) / 256;
     if (do_pack)
-      hipLaunchKernelGGL(k_pack_frag_f32, dim3(grid_for(nch * 32 * KP)), dim3(256), 0, s, B, n, k,
-                         KP / 16, 32, 8, 0, nch, (float*)pack);
+      hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 32 * KP)), dim3(256), 0, s, B, n, k, KP, 32,
+                         kBt32Ld, nch, (unsigned short*)pack);
     const Plan pl = xv_plan(xt, m, n, k);
     const int64_t cps = pl.cps;
     eff = pl.splits;
     float* dst = eff > 1 ? part : out;
-    dim3 grid((unsigned)rg, (unsigned)eff);
+    dim3 grid((unsigned)rb, (unsigned)eff);
     const float* Xf = reinterpret_cast<const float*>(X);
-    const float4* Bf = reinterpret_cast<const float4*>(pack);
+    const unsigned short* Bf = reinterpret_cast<const unsigned short*>(pack);
     if (ev0) (void)hipEventRecord(ev0, s);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xv_f32<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
-      case 32: hipLaunchKernelGGL((k_xv_f32<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
-      case 48: hipLaunchKernelGGL((k_xv_f32<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
-      case 64: hipLaunchKernelGGL((k_xv_f32<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
-      default: hipLaunchKernelGGL((k_xv_f32<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
+      case 16: hipLaunchKernelGGL((k_xv_f32s<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
+      case 32: hipLaunchKernelGGL((k_xv_f32s<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
+      case 48: hipLaunchKernelGGL((k_xv_f32s<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
+      case 64: hipLaunchKernelGGL((k_xv_f32s<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
+      default: hipLaunchKernelGGL((k_xv_f32s<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
     }
     if (ev1) (void)hipEventRecord(ev1, s);
   } else {

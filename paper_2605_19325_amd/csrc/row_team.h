@@ -106,18 +106,32 @@ __device__ __forceinline__ void block_times_g(const float (*A)[LDA], const doubl
   static_assert(KP % 16 == 0 && TM::RB % 16 == 0, "matrix-core row products need 16 | KP");
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int i = lane % 16, g = lane / 16;
+  constexpr int PERW = (NTILE + NW - 1) / NW;
   __syncthreads();
-  for (int tile = w; tile < NTILE; tile += NW) {
-    const int ti = tile / TC, tj = tile % TC;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int k0 = 0; k0 < KP; k0 += 4) {
-      const double a = (double)A[16 * ti + i][k0 + g];
-      const double b = sG[(k0 + g) * KP + 16 * tj + i];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-    }
+  // a wave's tiles advance together through k (independent MFMA chains)
+  d4 acc[PERW];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) sT[16 * ti + g + 4 * v][16 * tj + i] = acc[v];
+  for (int u = 0; u < PERW; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+  for (int k0 = 0; k0 < KP; k0 += 4) {
+#pragma unroll
+    for (int u = 0; u < PERW; ++u) {
+      const int tile = w + NW * u;
+      if (tile < NTILE) {
+        const int ti = tile / TC, tj = tile % TC;
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)A[16 * ti + i][k0 + g],
+                                                      sG[(k0 + g) * KP + 16 * tj + i], acc[u], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PERW; ++u) {
+    const int tile = w + NW * u;
+    if (tile < NTILE) {
+      const int ti = tile / TC, tj = tile % TC;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sT[16 * ti + g + 4 * v][16 * tj + i] = acc[u][v];
+    }
   }
   __syncthreads();
 }

@@ -46,17 +46,18 @@ def host(t):
 
 
 def check_products(lib, Xt, Xd_rows, Xd_cols, rows, cols, k, seed, split):
-    """P = X B on sampled rows and Q = X^T A on sampled columns against float64."""
+    """P = X B on sampled rows and Q = X^T A on sampled columns against float64.
+    split: "bf16" (factor split, 2^-23) or "f32" (X and factor split in X B, 2^-21)."""
     m, n = Xt.shape
     rng = np.random.default_rng(seed)
     B = rng.standard_normal((n, k)).astype(np.float32)
     A = rng.standard_normal((m, k)).astype(np.float32)
     P = host(lib.xv(Xt, torch.from_numpy(B).to(DEV)))[rows]
     Q = host(lib.xtu(Xt, torch.from_numpy(A).to(DEV)))[cols]
-    c = 8 * EPS32 * np.sqrt(n) + (2.0 ** -23 if split else 0.0)
+    c = 8 * EPS32 * np.sqrt(n) + (2.0 ** -23 if split == "bf16" else 2.0 ** -21)
     Pr = Xd_rows @ B.astype(np.float64)
     assert np.all(np.abs(P - Pr) <= c * (np.abs(Xd_rows) @ np.abs(B.astype(np.float64))) + 1e-30)
-    c = 8 * EPS32 * np.sqrt(m) + (2.0 ** -23 if split else 0.0)
+    c = 8 * EPS32 * np.sqrt(m) + (2.0 ** -23 if split == "bf16" else 0.0)
     Qr = Xd_cols.T @ A.astype(np.float64)
     assert np.all(np.abs(Q - Qr) <= c * (np.abs(Xd_cols.T) @ np.abs(A.astype(np.float64))) + 1e-30)
 
@@ -89,7 +90,7 @@ def test_image_products_sampled(lib, image):
     say("image-patch 4096x10000 fp32: products on 96 sampled rows / columns, k = 49")
     Xt = torch.from_numpy(X).to(DEV)
     rows, cols, Xr, Xc = sampled(X, None, 96, 96, 11)
-    check_products(lib, Xt, Xr, Xc, rows, cols, r, 12, False)
+    check_products(lib, Xt, Xr, Xc, rows, cols, r, 12, "f32")
 
 
 def test_image_solve_tracks_oracle(lib, image):
@@ -125,7 +126,7 @@ def test_spectrogram_bf16(lib):
     say("spectrogram 513x20000 bf16: sampled products; solve to kkt <= 1e-5 vs the oracle's error")
     Xb = lib.convert(torch.from_numpy(X).to(DEV), torch.bfloat16)
     rows, cols, Xr, Xc = sampled(X, Xb, 64, 96, 21)
-    check_products(lib, Xb, Xr, Xc, rows, cols, r, 22, True)
+    check_products(lib, Xb, Xr, Xc, rows, cols, r, 22, "bf16")
     ref = golden("spectrogram_oracle.txt")
     U, V, rep = lib.solve(Xb, r, torch.from_numpy(om).to(DEV), max_iter=1500, kkt_tol=1e-5,
                           check_every=10)
@@ -152,12 +153,12 @@ def test_ratings_products_sampled(lib, ratings):
     say("ratings 100000x20000: fp32 and bf16 products on sampled rows / columns, k = 20")
     Xt = torch.from_numpy(X).to(DEV)
     rows, cols, Xr, Xc = sampled(X, None, 48, 48, 31)
-    check_products(lib, Xt, Xr, Xc, rows, cols, r, 32, False)
+    check_products(lib, Xt, Xr, Xc, rows, cols, r, 32, "f32")
     Xb = lib.convert(Xt, torch.bfloat16)
     del Xt
     torch.cuda.empty_cache()
     rows, cols, Xr, Xc = sampled(X, Xb, 48, 48, 33)
-    check_products(lib, Xb, Xr, Xc, rows, cols, r, 34, True)
+    check_products(lib, Xb, Xr, Xc, rows, cols, r, 34, "bf16")
 
 
 def test_ratings_bf16_solve_invariants(lib, ratings):

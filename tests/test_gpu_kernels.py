@@ -23,12 +23,24 @@ def say(msg):
     print(msg, flush=True)
 
 
-def ref_bound(Xd, Bd, n, split=True):
-    """float32 accumulation bound, plus the representation error of the three-term
-    bfloat16 split of the factor (|b - hi - mid - lo| <= 2^-24 |b|) that the
-    matrix-core form of bf16 X adds."""
-    c = 8 * EPS32 * np.sqrt(n) + (2.0 ** -23 if split else 0.0)
+def ref_bound(Xd, Bd, n, split=1):
+    """float32 accumulation bound plus the representation error of the three-term
+    bfloat16 splits the matrix-core forms use: split = 1 for the factor alone
+    (bfloat16 X; |b - b1 - b2 - b3| <= 2^-24 |b|), 2 for X and the factor (float32
+    X through the bfloat16 matrix cores, whose three dropped cross terms add at
+    most 2^-23), 0 for none."""
+    extra = {0: 0.0, 1: 2.0 ** -23, 2: 2.0 ** -21}[split]
+    c = 8 * EPS32 * np.sqrt(n) + extra
     return c * (np.abs(Xd) @ np.abs(Bd)) + 1e-30
+
+
+def mfma_split(dt, k, product):
+    """Split class of the product's matrix-core form (k >= 16) for X stored as dt."""
+    if k < 16:
+        return 0
+    if dt == "bf16":
+        return 1
+    return 2 if (dt == "f32" and product == "xv") else 0
 
 
 SHAPES = [(1, 1), (7, 5), (65, 129), (300, 1000), (130, 515), (1000, 77)]
@@ -52,9 +64,8 @@ def test_xv_xtu(lib, m, n, k, dt):
     P = lib.xv(Xt, torch.from_numpy(B).to(DEV)).cpu().double().numpy()
     Q = lib.xtu(Xt, torch.from_numpy(A).to(DEV)).cpu().double().numpy()
     Bd, Ad = B.astype(np.float64), A.astype(np.float64)
-    sp = dt == "bf16"
-    assert np.all(np.abs(P - Xd @ Bd) <= ref_bound(Xd, Bd, n, sp))
-    assert np.all(np.abs(Q - Xd.T @ Ad) <= ref_bound(Xd.T, Ad, m, sp))
+    assert np.all(np.abs(P - Xd @ Bd) <= ref_bound(Xd, Bd, n, mfma_split(dt, k, "xv")))
+    assert np.all(np.abs(Q - Xd.T @ Ad) <= ref_bound(Xd.T, Ad, m, mfma_split(dt, k, "xtu")))
 
 
 @pytest.fixture(scope="module")
@@ -82,11 +93,13 @@ def test_valu_form_matches_fp64(valu_lib, lib, m, n, k, dt):
     if dt != "f32":
         Xt = lib.convert(Xt, torch.bfloat16 if dt == "bf16" else torch.float16)
     Xd = Xt.float().cpu().double().numpy()
-    for ctx in (valu_lib, lib):
+    for ctx, form in ((valu_lib, "valu"), (lib, "mfma")):
         P = ctx.xv(Xt, torch.from_numpy(B).to(DEV)).cpu().double().numpy()
         Q = ctx.xtu(Xt, torch.from_numpy(A).to(DEV)).cpu().double().numpy()
-        assert np.all(np.abs(P - Xd @ B) <= ref_bound(Xd, B.astype(np.float64), n))
-        assert np.all(np.abs(Q - Xd.T @ A) <= ref_bound(Xd.T, A.astype(np.float64), m))
+        sv = 0 if form == "valu" or dt == "f16" else mfma_split(dt, k, "xv")
+        su = 0 if form == "valu" or dt == "f16" else mfma_split(dt, k, "xtu")
+        assert np.all(np.abs(P - Xd @ B) <= ref_bound(Xd, B.astype(np.float64), n, sv))
+        assert np.all(np.abs(Q - Xd.T @ A) <= ref_bound(Xd.T, A.astype(np.float64), m, su))
 
 
 def test_time_products_runs(lib, valu_lib):
@@ -106,10 +119,10 @@ def test_xv_padded_leading_dimension(lib):
     B = rng.standard_normal((130, 7)).astype(np.float32)
     P = lib.xv(Xt, torch.from_numpy(B).to(DEV)).cpu().double().numpy()
     Xd = full[:, :130].astype(np.float64)
-    assert np.all(np.abs(P - Xd @ B) <= ref_bound(Xd, B.astype(np.float64), 130, False))
+    assert np.all(np.abs(P - Xd @ B) <= ref_bound(Xd, B.astype(np.float64), 130, 0))
     A = rng.standard_normal((50, 7)).astype(np.float32)
     Q = lib.xtu(Xt, torch.from_numpy(A).to(DEV)).cpu().double().numpy()
-    assert np.all(np.abs(Q - Xd.T @ A) <= ref_bound(Xd.T, A.astype(np.float64), 50, False))
+    assert np.all(np.abs(Q - Xd.T @ A) <= ref_bound(Xd.T, A.astype(np.float64), 50, 0))
 
 
 @pytest.mark.parametrize("rows,k", [(1, 1), (33, 5), (1000, 49), (4097, 64), (513, 80)])
