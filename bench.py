@@ -32,9 +32,9 @@ PEAK_HBM_GBS = 8000.0
 SAMPLE_PERIOD = 8            # every 8th outer iteration's streaming kernels are event-timed
 # HBM bytes per launch of the float32 streaming kernels on this workload, from two rocprofv3
 # passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters' reading for a device copy of
-# known size (profiles/k_xv_f32_image_patch_4096x10000_r49_hbm_traffic.txt).  They describe
+# known size (profiles/k_xv_f32s_k_xtu_f32_image_patch_4096x10000_r49_hbm_traffic.txt).  They describe
 # the kernel source they were taken on and are reported only while it is unchanged.
-TRAFFIC = {"k_mfma_sha256_16": "f73e953e43f8dd80", "k_xv_f32": 197.55e6, "k_xtu_f32": 242.69e6}
+TRAFFIC = {"k_mfma_sha256_16": "02959813b17ea9d3", "k_xv_f32s": 253.85e6, "k_xtu_f32": 242.67e6}
 
 
 def parse():
@@ -226,7 +226,7 @@ def main():
     xbytes = m * n * X.element_size()
     dom_ms = max(xv_ms, xtu_ms)
     achieved = flops / (dom_ms * 1e-3) / 1e12
-    kernel = "k_xtu_f32" if xtu_ms >= xv_ms else "k_xv_f32"
+    kernel = "k_xtu_f32" if xtu_ms >= xv_ms else "k_xv_f32s"
     traffic = TRAFFIC[kernel] if kernel_source_hash() == TRAFFIC["k_mfma_sha256_16"] else None
     roof = {
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
