@@ -2,9 +2,9 @@
 // where each product is a real dense contraction (appendix on complexity:
 // X V and X^T U, O(mnr) per half-iteration).
 //
-//   float32 X, X B: X and the factor each split into three bfloat16 terms on
+//   float32 X: X and the factor each split into three bfloat16 terms on
 //     v_mfma_f32_16x16x32_bf16 (six of the nine term products), float32
-//     accumulate; X^T A: v_mfma_f32_16x16x4_f32.
+//     accumulate.
 //   bfloat16 X: v_mfma_f32_16x16x32_bf16, float32 accumulate, with the float32
 //     factor split into three bfloat16 terms (hi = rne(v), mid = rne(v - hi),
 //     lo = rne(v - hi - mid), |v - hi - mid - lo| <= 2^-24 |v|), so that
@@ -12,8 +12,8 @@
 //     (the split-precision refinement of Henry et al. 2019); X itself is exact.
 //
 // MFMA 16x16 tiles on gfx950 (wave64): lane l = 16 g + i (i = l % 16,
-// g = l / 16).  16x16x4 f32: A operand = A[i][g], B operand = B[g][i].
-// 16x16x32 bf16: A = A[i][8g .. 8g+7], B = B[8g .. 8g+7][i].  Result:
+// g = l / 16).  16x16x32 bf16: A = A[i][8g .. 8g+7], B = B[8g .. 8g+7][i].
+// Result:
 // D[4g + v][i] in accumulator element v.  The contraction index of a tile is
 // free to be permuted as long as A and B agree, which lets every lane load
 // contiguous runs of a row of X.
@@ -21,8 +21,8 @@
 // X V  : lanes take rows of X (16 per tile); the factor chunk sits in LDS,
 //        prefetched through registers.
 // X^T U: lanes take 16-byte runs along a row of X; a tile covers a strided
-//        set of 16 columns.  For bfloat16 the 8 x 8 blocks are transposed
-//        in registers (v_perm) so that each lane holds 8 rows of one column.
+//        set of 16 columns, so that each lane holds 8 rows of one column
+//        (for bfloat16 the 8 x 8 blocks are transposed in registers, v_perm).
 // Both split the contraction over blocks; partials are reduced in fixed
 // order by the caller.
 #include <stdint.h>
@@ -106,128 +106,6 @@ __device__ __forceinline__ void store_tile_rows(float* __restrict__ out, int64_t
     const int64_t row = row0 + 4 * g + v;
     if (row < m) out[row * k + col] = d[v];
   }
-}
-
-// ---------------------------------------------------------------------------
-// float32 X: Q = X^T A.  A block's 4 waves share 64 columns and split the
-// block's range of 16-row chunks four ways; summed in LDS at the end.  In
-// MFMA step kk (rows rc + 4 kk .. +3) lane (i, g) loads X[rc + 4 kk + g][j0 +
-// 4i .. 4i+3]; tile t holds the columns j0 + 4 mm + t (mm = 0..15).  The
-// factor comes pre-packed: Af[chunk][nt][lane][kk] = A[rc + 4 kk + g][16 nt + i].
-// ---------------------------------------------------------------------------
-template <int KP>
-__global__ __launch_bounds__(kT, 2) void k_xtu_f32(const float* __restrict__ X, int64_t m,
-                                                   int64_t n, int64_t ld,
-                                                   const float4* __restrict__ Af, int k,
-                                                   int chunks_per_split, int64_t nchunks, int vec,
-                                                   float* __restrict__ out, int64_t split_stride,
-    const int32_t* __restrict__ stop) {
-  if (stop != nullptr && *stop) return;
-  constexpr int NT = KP / 16;
-  __shared__ f32x4 red[3][4 * NT][kWave];
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const int i = lane % 16, g = lane / 16;
-  const int64_t j0 = (int64_t)blockIdx.x * 64;
-  const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
-  const int64_t c1 = c0 + chunks_per_split < nchunks ? c0 + chunks_per_split : nchunks;
-
-  f32x4 acc[4][NT];
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[t][nt] = zero4();
-
-  auto load_a = [&](int64_t ch, float4 (&as)[NT]) {
-    const float4* a = Af + (ch * NT) * kWave + lane;
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) as[nt] = a[nt * kWave];
-  };
-  auto load_fast = [&](int64_t ch, uint4 (&xs)[4], float4 (&as)[NT]) {
-    const float* base = X + (ch * 16 + g) * ld + j0 + 4 * i;
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) xs[kk] = ldg16(base + 4 * kk * ld);
-    load_a(ch, as);
-  };
-  auto load_slow = [&](int64_t ch, uint4 (&xs)[4], float4 (&as)[NT]) {
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
-      xs[kk] = load16<float>(X, m, n, ld, ch * 16 + 4 * kk + g, j0 + 4 * i, vec != 0);
-    load_a(ch, as);
-  };
-  auto compute = [&](const uint4 (&xs)[4], const float4 (&as)[NT]) {
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const uint4 q = xs[kk];
-      const float av[4] = {__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z),
-                           __uint_as_float(q.w)};
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const float4 aq = as[nt];
-        const float bv = (kk == 0) ? aq.x : (kk == 1) ? aq.y : (kk == 2) ? aq.z : aq.w;
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          acc[t][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv, acc[t][nt], 0, 0, 0);
-      }
-    }
-  };
-  const bool cols_ok = vec && j0 + 64 <= n;
-  const int64_t full = m / 16;
-  const int64_t cfull = cols_ok ? (c1 < full ? c1 : full) : c0;
-  int64_t ch = c0 + w;
-  if (ch < cfull) {
-    uint4 xA[4], xB[4];
-    float4 aA[NT], aB[NT];
-    // Pairs of chunks per loop trip keep each prefetch in the same basic block
-    // as the multiply it overlaps (so it is not sunk past a branch); the
-    // scheduling barrier keeps it ahead of that multiply.
-    const int64_t cnt = (cfull - ch + 3) / 4;
-    const int64_t last = ch + 4 * (cnt - 1);
-    load_fast(ch, xA, aA);
-    int64_t c = ch;
-    for (int64_t p = 0; p + 1 < cnt; p += 2) {
-      load_fast(c + 4, xB, aB);
-      __builtin_amdgcn_sched_barrier(0);
-      compute(xA, aA);
-      load_fast(c + 8 < last ? c + 8 : last, xA, aA);
-      __builtin_amdgcn_sched_barrier(0);
-      compute(xB, aB);
-      c += 8;
-    }
-    if (cnt & 1) compute(xA, aA);
-    ch += 4 * cnt;
-  }
-  for (; ch < c1; ch += 4) {
-    uint4 xs[4];
-    float4 as[NT];
-    load_slow(ch, xs, as);
-    compute(xs, as);
-  }
-  if (w > 0) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) red[w - 1][t * NT + nt][lane] = acc[t][nt];
-  }
-  __syncthreads();
-  if (w != 0) return;
-  // element v of lane (i, g) in tile t is column j0 + 4 (4g + v) + t, factor column 16 nt + i
-  float* o = out + (int64_t)blockIdx.y * split_stride;
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      f32x4 v = acc[t][nt];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) v += red[q][t * NT + nt][lane];
-      const int col = 16 * nt + i;
-      if (col < k) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int64_t j = j0 + 4 * (4 * g + e) + t;
-          if (j < n) o[j * k + col] = v[e];
-        }
-      }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -629,51 +507,170 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
     }
 }
 
-// Packs a float32 factor F (rows x k, leading dimension k) into transposed
-// bfloat16 hi/mid/lo chunks: out[ch][part][c][kr] (row stride ldt) = split
-// of F[ch * C + kr][c] for kr < C, c < KP (zero outside F).
-__global__ void k_pack_split_t(const float* __restrict__ F, int64_t rows, int k, int KP, int C,
-                               int ldt, int64_t nchunks, unsigned short* __restrict__ out) {
-  const int64_t count = nchunks * C * KP;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t ch = e / ((int64_t)C * KP);
-    const int rem = (int)(e % ((int64_t)C * KP));
-    const int kr = rem / KP, c = rem % KP;
-    const int64_t row = ch * C + kr;
-    const float v = (row < rows && c < k) ? F[row * k + c] : 0.f;
-    const unsigned short hi = bf16_rne(v);
-    const float r1 = v - __uint_as_float((unsigned)hi << 16);
-    const unsigned short mid = bf16_rne(r1);
-    const unsigned short lo = bf16_rne(r1 - __uint_as_float((unsigned)mid << 16));
-    unsigned short* base = out + ch * (int64_t)(3 * KP * ldt);
-    base[(int64_t)c * ldt + kr] = hi;
-    base[(int64_t)(KP + c) * ldt + kr] = mid;
-    base[(int64_t)(2 * KP + c) * ldt + kr] = lo;
+// ---------------------------------------------------------------------------
+// float32 X through the bfloat16 matrix cores: Q = X^T A with X and A split
+// into three bfloat16 terms each, six term products as in X B.  Block = 4
+// waves x 64 columns; chunk = 32 rows (one MFMA step).  Lane (i, g) loads
+// X[rc + 8g + e][j0 + 4i .. 4i+3] (e = 0..7); operand t gathers element t of
+// the eight loads, so tile t covers the columns j0 + 4 mm + t (mm = 0..15)
+// and needs no register transpose.  B operand = At[part][16 nt + i][8g ..
+// 8g+7] (the transposed split chunk in LDS, rows padded to 40), read once per
+// chunk and shared by the four tiles.
+// ---------------------------------------------------------------------------
+template <int KP>
+__global__ __launch_bounds__(kT) void k_xtu_f32s(const float* __restrict__ X, int64_t m, int64_t n,
+                                                 int64_t ld, const unsigned short* __restrict__ At,
+                                                 int k, int chunks_per_split, int64_t nchunks,
+                                                 int vec, float* __restrict__ out,
+                                                 int64_t split_stride,
+                                                 const int32_t* __restrict__ stop) {
+  if (stop != nullptr && *stop) return;
+  constexpr int NT = KP / 16;
+  constexpr int CH = 3 * KP * kAtLd;
+  __shared__ __align__(16) unsigned short As[2][CH];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int i = lane % 16, g = lane / 16;
+  const int64_t j0 = (int64_t)blockIdx.x * (4 * 64) + 64 * w;
+  const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
+  const int64_t c1 = c0 + chunks_per_split < nchunks ? c0 + chunks_per_split : nchunks;
+
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[t][nt] = zero4();
+
+  uint4 xa[8], xb[8];
+  auto load_x = [&](int64_t ch, uint4 (&dst)[8]) {
+    const bool interior = vec && (ch + 1) * 32 <= m && j0 + 64 <= n;   // wave-uniform
+    if (interior) {
+      const float* base = X + (ch * 32 + 8 * g) * ld + j0 + 4 * i;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) dst[e] = ldg16(base + e * ld);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        dst[e] = load16<float>(X, m, n, ld, ch * 32 + 8 * g + e, j0 + 4 * i, vec != 0);
+    }
+  };
+  constexpr int NAQ = (CH / 8 + kT - 1) / kT;
+  uint4 aq_next[NAQ];
+  auto fetch_a = [&](int64_t ch) {
+    const uint4* src = reinterpret_cast<const uint4*>(At + ch * CH);
+#pragma unroll
+    for (int u = 0; u < NAQ; ++u) {
+      const int e = threadIdx.x + u * kT;
+      aq_next[u] = e < CH / 8 ? src[e] : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto store_a = [&](int buf) {
+    uint4* dst = reinterpret_cast<uint4*>(As[buf]);
+#pragma unroll
+    for (int u = 0; u < NAQ; ++u) {
+      const int e = threadIdx.x + u * kT;
+      if (e < CH / 8) dst[e] = aq_next[u];
+    }
+  };
+  if (c0 < c1) {
+    fetch_a(c0);
+    load_x(c0, xa);
+    store_a(0);
   }
+  int buf = 0;
+  for (int64_t ch = c0; ch < c1; ++ch) {
+    __syncthreads();
+    const bool more = ch + 1 < c1;
+    if (more) {
+      fetch_a(ch + 1);
+      load_x(ch + 1, xb);
+    }
+    // split operands of the four tiles: element t of the eight row loads
+    uint4 x1[4], x2[4], x3[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      uint4 lo, hi;
+      if (t == 0) { lo = make_uint4(xa[0].x, xa[1].x, xa[2].x, xa[3].x); hi = make_uint4(xa[4].x, xa[5].x, xa[6].x, xa[7].x); }
+      if (t == 1) { lo = make_uint4(xa[0].y, xa[1].y, xa[2].y, xa[3].y); hi = make_uint4(xa[4].y, xa[5].y, xa[6].y, xa[7].y); }
+      if (t == 2) { lo = make_uint4(xa[0].z, xa[1].z, xa[2].z, xa[3].z); hi = make_uint4(xa[4].z, xa[5].z, xa[6].z, xa[7].z); }
+      if (t == 3) { lo = make_uint4(xa[0].w, xa[1].w, xa[2].w, xa[3].w); hi = make_uint4(xa[4].w, xa[5].w, xa[6].w, xa[7].w); }
+      split3(lo, hi, x1[t], x2[t], x3[t]);
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const unsigned short* bp = &As[buf][(16 * nt + i) * kAtLd + 8 * g];
+      const bf16x8 b1 = as_bf16x8(*reinterpret_cast<const uint4*>(bp));
+      const bf16x8 b2 = as_bf16x8(*reinterpret_cast<const uint4*>(bp + KP * kAtLd));
+      const bf16x8 b3 = as_bf16x8(*reinterpret_cast<const uint4*>(bp + 2 * KP * kAtLd));
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        f32x4 a = acc[t][nt];
+        // smallest terms first
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(x3[t]), b1, a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(x2[t]), b2, a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(x1[t]), b3, a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(x2[t]), b1, a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(x1[t]), b2, a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(x1[t]), b1, a, 0, 0, 0);
+        acc[t][nt] = a;
+      }
+    }
+    if (more) {
+      store_a(buf ^ 1);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xa[e] = xb[e];
+    }
+    buf ^= 1;
+  }
+  // element v of lane (i, g) in tile t is column j0 + 4 (4g + v) + t, factor column 16 nt + i
+  float* o = out + (int64_t)blockIdx.y * split_stride;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int col = 16 * nt + i;
+      if (col < k) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t j = j0 + 4 * (4 * g + v) + t;
+          if (j < n) o[j * k + col] = acc[t][nt][v];
+        }
+      }
+    }
 }
 
-// float32 factor fragments in MFMA operand order.
-// xv  (xtu = 0): Bf[ch][jt][lane][s] = B[32 ch + 16 (s/4) + 4g + s%4][16 jt + i] (s = 0..7)
-// xtu (xtu = 1): Af[ch][nt][lane][kk] = A[16 ch + 4 kk + g][16 nt + i]         (kk = 0..3)
-// with lane = 16 g + i; zero outside the factor (rows x k).
-__global__ void k_pack_frag_f32(const float* __restrict__ F, int64_t rows, int k, int NT,
-                                int rows_per_chunk, int per_lane, int xtu, int64_t nchunks,
-                                float* __restrict__ out) {
-  const int64_t count = nchunks * NT * kWave * per_lane;
+// Packs a float32 factor F (rows x k, leading dimension k) into transposed
+// bfloat16 hi/mid/lo chunks: out[ch][part][c][kr] (row stride ldt) = split
+// of F[ch * C + kr][c] for kr < C, c < KP (zero outside F).  A thread splits
+// eight consecutive rows of one column and writes each term as one 16-byte
+// run (C and ldt multiples of 8).
+__global__ void k_pack_split_t(const float* __restrict__ F, int64_t rows, int k, int KP, int C,
+                               int ldt, int64_t nchunks, unsigned short* __restrict__ out) {
+  const int runs = C / 8;
+  const int64_t count = nchunks * KP * runs;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int s = (int)(e % per_lane);
-    const int64_t q = e / per_lane;
-    const int lane = (int)(q % kWave);
-    const int64_t q2 = q / kWave;
-    const int jt = (int)(q2 % NT);
-    const int64_t ch = q2 / NT;
-    const int i = lane % 16, g = lane / 16;
-    const int off = xtu ? 4 * s + g : 16 * (s / 4) + 4 * g + (s % 4);
-    const int64_t row = ch * rows_per_chunk + off;
-    const int col = 16 * jt + i;
-    out[e] = (row < rows && col < k) ? F[row * k + col] : 0.f;
+    const int q = (int)(e % runs);
+    const int64_t rest = e / runs;
+    const int c = (int)(rest % KP);
+    const int64_t ch = rest / KP;
+    const int64_t row0 = ch * C + 8 * q;
+    unsigned h[4], md[4], lw[4];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t row = row0 + u;
+      const float v = (row < rows && c < k) ? F[row * k + c] : 0.f;
+      const unsigned short hi = bf16_rne(v);
+      const float r1 = v - __uint_as_float((unsigned)hi << 16);
+      const unsigned short mid = bf16_rne(r1);
+      const unsigned short lo = bf16_rne(r1 - __uint_as_float((unsigned)mid << 16));
+      const int sh = 16 * (u & 1);
+      if ((u & 1) == 0) { h[u / 2] = hi; md[u / 2] = mid; lw[u / 2] = lo; }
+      else { h[u / 2] |= (unsigned)hi << sh; md[u / 2] |= (unsigned)mid << sh; lw[u / 2] |= (unsigned)lo << sh; }
+    }
+    unsigned short* base = out + ch * (int64_t)(3 * KP * ldt) + (int64_t)c * ldt + 8 * q;
+    *reinterpret_cast<uint4*>(base) = make_uint4(h[0], h[1], h[2], h[3]);
+    *reinterpret_cast<uint4*>(base + (int64_t)KP * ldt) = make_uint4(md[0], md[1], md[2], md[3]);
+    *reinterpret_cast<uint4*>(base + (int64_t)2 * KP * ldt) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
   }
 }
 
@@ -716,29 +713,6 @@ int64_t resident_blocks(const void* kernel) {
   return v;
 }
 
-// Contraction splits for a grid of `tiles` output blocks: the smallest count
-// (at most smax_cap, at least min_units chunks each) whose grid keeps the
-// resident slots best used over whole rounds (blocks / (rounds * capacity)),
-// a larger count being taken only for a gain of more than 2%.
-int64_t choose_splits(int64_t tiles, int64_t units, int64_t min_units, int64_t capacity,
-                      int64_t smax_cap) {
-  int64_t smax = (units + min_units - 1) / min_units;
-  if (smax > smax_cap) smax = smax_cap;
-  if (smax < 1) smax = 1;
-  double best = -1.0;
-  int64_t pick = 1;
-  for (int64_t sp = 1; sp <= smax; ++sp) {
-    const int64_t blocks = tiles * sp;
-    const int64_t rounds = (blocks + capacity - 1) / capacity;
-    const double util = (double)blocks / (double)(rounds * capacity);
-    if (util > best + 0.02) {
-      best = util;
-      pick = sp;
-    }
-  }
-  return pick;
-}
-
 const void* xv_kernel(int xt, int KP) {
   if (xt == ENMF_F32) {
     switch (KP) {
@@ -761,11 +735,11 @@ const void* xv_kernel(int xt, int KP) {
 const void* xtu_kernel(int xt, int KP) {
   if (xt == ENMF_F32) {
     switch (KP) {
-      case 16: return reinterpret_cast<const void*>(&k_xtu_f32<16>);
-      case 32: return reinterpret_cast<const void*>(&k_xtu_f32<32>);
-      case 48: return reinterpret_cast<const void*>(&k_xtu_f32<48>);
-      case 64: return reinterpret_cast<const void*>(&k_xtu_f32<64>);
-      default: return reinterpret_cast<const void*>(&k_xtu_f32<80>);
+      case 16: return reinterpret_cast<const void*>(&k_xtu_f32s<16>);
+      case 32: return reinterpret_cast<const void*>(&k_xtu_f32s<32>);
+      case 48: return reinterpret_cast<const void*>(&k_xtu_f32s<48>);
+      case 64: return reinterpret_cast<const void*>(&k_xtu_f32s<64>);
+      default: return reinterpret_cast<const void*>(&k_xtu_f32s<80>);
     }
   }
   switch (KP) {
@@ -783,28 +757,53 @@ struct Plan {
   int64_t nch, tiles, cps, splits;
 };
 
-Plan make_plan(int64_t nch, int64_t tiles, int64_t min_units, const void* kernel, int64_t smax_cap) {
-  Plan p;
-  p.nch = nch;
-  p.tiles = tiles;
-  const int64_t sp = choose_splits(tiles, nch, min_units, resident_blocks(kernel), smax_cap);
-  p.cps = (nch + sp - 1) / sp;
-  p.splits = (nch + p.cps - 1) / p.cps;
-  return p;
+// Splits of the contraction, chosen by a model of the launch time in bytes
+// moved at full bandwidth.  A full set of resident blocks is taken to keep
+// HBM busy, so the streaming part is the larger of the X bytes and the
+// rounds of resident blocks times the chunks of one block (plus one for its
+// first load and write-out); every split adds its partial result, written
+// here and read back by the consumer.  A larger count must win by 1%.
+// chunk_bytes: X bytes one block reads per chunk; out_bytes: one partial.
+Plan make_plan(int64_t nch, int64_t tiles, int64_t min_units, const void* kernel, int64_t smax_cap,
+               double chunk_bytes, double out_bytes) {
+  const int64_t capacity = resident_blocks(kernel);
+  int64_t smax = (nch + min_units - 1) / min_units;
+  if (smax > smax_cap) smax = smax_cap;
+  if (smax < 1) smax = 1;
+  const double xbytes = (double)nch * (double)tiles * chunk_bytes;
+  Plan best{nch, tiles, nch, 1};
+  double best_cost = -1.0;
+  for (int64_t sp = 1; sp <= smax; ++sp) {
+    const int64_t cps = (nch + sp - 1) / sp;
+    const int64_t splits = (nch + cps - 1) / cps;
+    const int64_t rounds = (tiles * splits + capacity - 1) / capacity;
+    const double wave = (double)rounds * (double)(cps + 1) * (double)capacity * chunk_bytes;
+    const double cost = (xbytes > wave ? xbytes : wave) +
+                        (splits > 1 ? 2.0 * (double)splits : 1.0) * out_bytes;
+    if (best_cost < 0.0 || cost < 0.99 * best_cost) {
+      best_cost = cost;
+      best = Plan{nch, tiles, cps, splits};
+    }
+  }
+  return best;
 }
 
 // X B: tiles of 256 rows; f32 in 32-column chunks, bf16 in 64-column chunks.
 Plan xv_plan(int xt, int64_t m, int64_t n, int k) {
   const int KP = mfma_kp(k);
-  if (xt == ENMF_F32) return make_plan((n + 31) / 32, (m + 255) / 256, 4, xv_kernel(xt, KP), 64);
-  return make_plan((n + 63) / 64, (m + 255) / 256, 4, xv_kernel(xt, KP), 64);
+  const double out = (double)m * k * 4;
+  if (xt == ENMF_F32)
+    return make_plan((n + 31) / 32, (m + 255) / 256, 4, xv_kernel(xt, KP), 64, 256.0 * 32 * 4, out);
+  return make_plan((n + 63) / 64, (m + 255) / 256, 4, xv_kernel(xt, KP), 64, 256.0 * 64 * 2, out);
 }
 
-// X^T A: f32 tiles of 64 columns and 16-row chunks; bf16 tiles of 512 columns and 32-row chunks.
+// X^T A: 32-row chunks; f32 tiles of 256 columns, bf16 tiles of 512 columns.
 Plan xtu_plan(int xt, int64_t m, int64_t n, int k) {
   const int KP = mfma_kp(k);
-  if (xt == ENMF_F32) return make_plan((m + 15) / 16, (n + 63) / 64, 8, xtu_kernel(xt, KP), 16);
-  return make_plan((m + 31) / 32, (n + 511) / 512, 4, xtu_kernel(xt, KP), 64);
+  const double out = (double)n * k * 4;
+  if (xt == ENMF_F32)
+    return make_plan((m + 31) / 32, (n + 255) / 256, 4, xtu_kernel(xt, KP), 64, 32.0 * 256 * 4, out);
+  return make_plan((m + 31) / 32, (n + 511) / 512, 4, xtu_kernel(xt, KP), 64, 32.0 * 512 * 2, out);
 }
 
 }  // namespace
@@ -822,7 +821,7 @@ void mfma_xv_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t*
 void mfma_xtu_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes) {
   const int KP = mfma_kp(k);
   const Plan p = xtu_plan(xt, m, n, k);
-  *pack_bytes = xt == ENMF_F32 ? (size_t)p.nch * 16 * KP * 4 : (size_t)p.nch * 3 * KP * kAtLd * 2;
+  *pack_bytes = (size_t)p.nch * 3 * KP * kAtLd * 2;
   *part_bytes = (size_t)p.splits * n * k * 4;
 }
 
@@ -840,7 +839,7 @@ hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t l
     const int64_t nch = (n + 31) / 32;
     const int64_t rb = (m + 255) / 256;
     if (do_pack)
-      hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 32 * KP)), dim3(256), 0, s, B, n, k, KP, 32,
+      hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 4 * KP)), dim3(256), 0, s, B, n, k, KP, 32,
                          kBt32Ld, nch, (unsigned short*)pack);
     const Plan pl = xv_plan(xt, m, n, k);
     const int64_t cps = pl.cps;
@@ -862,7 +861,7 @@ hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t l
     const int64_t nch = (n + 63) / 64;
     const int64_t rb = (m + 255) / 256;
     if (do_pack)
-      hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 64 * KP)), dim3(256), 0, s, B, n, k, KP, 64,
+      hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 8 * KP)), dim3(256), 0, s, B, n, k, KP, 64,
                          kBtLd, nch, (unsigned short*)pack);
     const Plan pl = xv_plan(xt, m, n, k);
     const int64_t cps = pl.cps;
@@ -897,32 +896,32 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
   const bool vec = aligned_rows(X, ld, xt == ENMF_F32 ? 4 : 2);
   int64_t eff = 1;
   if (xt == ENMF_F32) {
-    const int64_t nch = (m + 15) / 16;
-    const int64_t cg = (n + 63) / 64;
+    const int64_t nch = (m + 31) / 32;
+    const int64_t tiles = (n + 255) / 256;
     if (do_pack)
-      hipLaunchKernelGGL(k_pack_frag_f32, dim3(grid_for(nch * 16 * KP)), dim3(256), 0, s, A, m, k,
-                         KP / 16, 16, 4, 1, nch, (float*)pack);
+      hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 4 * KP)), dim3(256), 0, s, A, m, k, KP, 32,
+                         kAtLd, nch, (unsigned short*)pack);
     const Plan pl = xtu_plan(xt, m, n, k);
-    const int64_t cps = pl.cps;
+    const int cps = (int)pl.cps;
     eff = pl.splits;
     float* dst = eff > 1 ? part : out;
-    dim3 grid((unsigned)cg, (unsigned)eff);
+    dim3 grid((unsigned)tiles, (unsigned)eff);
     const float* Xf = reinterpret_cast<const float*>(X);
-    const float4* Af = reinterpret_cast<const float4*>(pack);
+    const unsigned short* At = reinterpret_cast<const unsigned short*>(pack);
     if (ev0) (void)hipEventRecord(ev0, s);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xtu_f32<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k, stop); break;
-      case 32: hipLaunchKernelGGL((k_xtu_f32<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k, stop); break;
-      case 48: hipLaunchKernelGGL((k_xtu_f32<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k, stop); break;
-      case 64: hipLaunchKernelGGL((k_xtu_f32<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k, stop); break;
-      default: hipLaunchKernelGGL((k_xtu_f32<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, Af, k, (int)cps, nch, (int)vec, dst, n * k, stop); break;
+      case 16: hipLaunchKernelGGL((k_xtu_f32s<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
+      case 32: hipLaunchKernelGGL((k_xtu_f32s<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
+      case 48: hipLaunchKernelGGL((k_xtu_f32s<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
+      case 64: hipLaunchKernelGGL((k_xtu_f32s<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
+      default: hipLaunchKernelGGL((k_xtu_f32s<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
     }
     if (ev1) (void)hipEventRecord(ev1, s);
   } else {
     const int64_t tiles = (n + 511) / 512;
     const int64_t nch = (m + 31) / 32;
     if (do_pack)
-      hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 32 * KP)), dim3(256), 0, s, A, m, k, KP, 32,
+      hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 4 * KP)), dim3(256), 0, s, A, m, k, KP, 32,
                          kAtLd, nch, (unsigned short*)pack);
     const Plan pl = xtu_plan(xt, m, n, k);
     const int64_t cps = pl.cps;

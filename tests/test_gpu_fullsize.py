@@ -14,7 +14,8 @@ oracle computes one by one or on properties that hold at any size.
   method (error above the SVD floor, factors nonnegative once the exterior
   phase is over, objective non-increasing under HALS).
 The product bound is the float32 accumulation bound of test_gpu_kernels, with
-the three-term bfloat16 split of the factor.
+the three-term bfloat16 splits of the factor (bfloat16 X) or of X and the
+factor (float32 X).
 """
 
 import os
@@ -47,7 +48,7 @@ def host(t):
 
 def check_products(lib, Xt, Xd_rows, Xd_cols, rows, cols, k, seed, split):
     """P = X B on sampled rows and Q = X^T A on sampled columns against float64.
-    split: "bf16" (factor split, 2^-23) or "f32" (X and factor split in X B, 2^-21)."""
+    split: "bf16" (factor split, 2^-23) or "f32" (X and factor split, 2^-21)."""
     m, n = Xt.shape
     rng = np.random.default_rng(seed)
     B = rng.standard_normal((n, k)).astype(np.float32)
@@ -57,7 +58,7 @@ def check_products(lib, Xt, Xd_rows, Xd_cols, rows, cols, k, seed, split):
     c = 8 * EPS32 * np.sqrt(n) + (2.0 ** -23 if split == "bf16" else 2.0 ** -21)
     Pr = Xd_rows @ B.astype(np.float64)
     assert np.all(np.abs(P - Pr) <= c * (np.abs(Xd_rows) @ np.abs(B.astype(np.float64))) + 1e-30)
-    c = 8 * EPS32 * np.sqrt(m) + (2.0 ** -23 if split == "bf16" else 0.0)
+    c = 8 * EPS32 * np.sqrt(m) + (2.0 ** -23 if split == "bf16" else 2.0 ** -21)
     Qr = Xd_cols.T @ A.astype(np.float64)
     assert np.all(np.abs(Q - Qr) <= c * (np.abs(Xd_cols.T) @ np.abs(A.astype(np.float64))) + 1e-30)
 

@@ -40,7 +40,7 @@ def mfma_split(dt, k, product):
         return 0
     if dt == "bf16":
         return 1
-    return 2 if (dt == "f32" and product == "xv") else 0
+    return 2 if dt == "f32" else 0
 
 
 SHAPES = [(1, 1), (7, 5), (65, 129), (300, 1000), (130, 515), (1000, 77)]
