@@ -69,6 +69,25 @@ __device__ __forceinline__ uint4 mask_cols(uint4 q, int64_t col, int64_t n) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// Logical block (tile bx, contraction range by) of a tiles x splits product
+// grid.  The dispatcher hands consecutive workgroups to the 8 XCDs in turn
+// (workgroup L runs on XCD L % 8); each XCD here takes one contiguous range
+// of the logical blocks in split-major order, so the blocks that read the
+// same factor chunks share that XCD's L2.  Used by X B, whose packed factor
+// outgrows one L2 and is read by every row tile; X^T A keeps the dispatch
+// order (measured: its packed factor stays L2-resident and the remap only
+// spreads its row bands).
+__device__ __forceinline__ void xcd_block(int64_t& bx, int64_t& by) {
+  const int64_t tiles = gridDim.x;
+  const int64_t nb = tiles * gridDim.y;
+  const int64_t L = blockIdx.x + tiles * blockIdx.y;
+  const int64_t xcd = L % 8, slot = L / 8;
+  const int64_t q = nb / 8, rem = nb % 8;
+  const int64_t B = xcd * q + (xcd < rem ? xcd : rem) + slot;
+  bx = B % tiles;
+  by = B / tiles;
+}
+
 // 16 bytes of row `row` of X starting at column col (zero outside the matrix).
 template <typename ET>
 __device__ __forceinline__ uint4 load16(const ET* __restrict__ X, int64_t rows, int64_t n,
@@ -131,8 +150,10 @@ __global__ __launch_bounds__(kT) void k_xv_bf16(const unsigned short* __restrict
   __shared__ __align__(16) unsigned short Bs[2][CH];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int i = lane % 16, g = lane / 16;
-  const int64_t row0 = (int64_t)blockIdx.x * (4 * 64) + 64 * w;
-  const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
+  int64_t bx, by;
+  xcd_block(bx, by);
+  const int64_t row0 = bx * (4 * 64) + 64 * w;
+  const int64_t c0 = by * chunks_per_split;
   const int64_t c1 = c0 + chunks_per_split < nchunks ? c0 + chunks_per_split : nchunks;
 
   f32x4 acc[RT][NT];
@@ -216,7 +237,7 @@ __global__ __launch_bounds__(kT) void k_xv_bf16(const unsigned short* __restrict
     }
     buf ^= 1;
   }
-  float* o = out + (int64_t)blockIdx.y * split_stride;
+  float* o = out + by * split_stride;
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -282,8 +303,10 @@ __global__ __launch_bounds__(kT) void k_xv_f32s(const float* __restrict__ X, int
   __shared__ __align__(16) unsigned short Bs[2][CH];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int i = lane % 16, g = lane / 16;
-  const int64_t row0 = (int64_t)blockIdx.x * (4 * 64) + 64 * w;
-  const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
+  int64_t bx, by;
+  xcd_block(bx, by);
+  const int64_t row0 = bx * (4 * 64) + 64 * w;
+  const int64_t c0 = by * chunks_per_split;
   const int64_t c1 = c0 + chunks_per_split < nchunks ? c0 + chunks_per_split : nchunks;
 
   f32x4 acc[RT][NT];
@@ -369,7 +392,7 @@ __global__ __launch_bounds__(kT) void k_xv_f32s(const float* __restrict__ X, int
     }
     buf ^= 1;
   }
-  float* o = out + (int64_t)blockIdx.y * split_stride;
+  float* o = out + by * split_stride;
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -399,8 +422,9 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
   __shared__ __align__(16) unsigned short As[2][CH];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int i = lane % 16, g = lane / 16;
-  const int64_t j0 = (int64_t)blockIdx.x * (4 * 128) + 128 * w;
-  const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
+  const int64_t bx = blockIdx.x, by = blockIdx.y;
+  const int64_t j0 = bx * (4 * 128) + 128 * w;
+  const int64_t c0 = by * chunks_per_split;
   const int64_t c1 = c0 + chunks_per_split < nchunks ? c0 + chunks_per_split : nchunks;
 
   f32x4 acc[8][NT];
@@ -491,7 +515,7 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
     buf ^= 1;
   }
   // element v of lane (i, g) in tile t is column j0 + 8 (4g + v) + t, factor column 16 nt + i
-  float* o = out + (int64_t)blockIdx.y * split_stride;
+  float* o = out + by * split_stride;
 #pragma unroll
   for (int t = 0; t < 8; ++t)
 #pragma unroll
@@ -530,8 +554,9 @@ __global__ __launch_bounds__(kT) void k_xtu_f32s(const float* __restrict__ X, in
   __shared__ __align__(16) unsigned short As[2][CH];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int i = lane % 16, g = lane / 16;
-  const int64_t j0 = (int64_t)blockIdx.x * (4 * 64) + 64 * w;
-  const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
+  const int64_t bx = blockIdx.x, by = blockIdx.y;
+  const int64_t j0 = bx * (4 * 64) + 64 * w;
+  const int64_t c0 = by * chunks_per_split;
   const int64_t c1 = c0 + chunks_per_split < nchunks ? c0 + chunks_per_split : nchunks;
 
   f32x4 acc[4][NT];
@@ -622,7 +647,7 @@ __global__ __launch_bounds__(kT) void k_xtu_f32s(const float* __restrict__ X, in
     buf ^= 1;
   }
   // element v of lane (i, g) in tile t is column j0 + 4 (4g + v) + t, factor column 16 nt + i
-  float* o = out + (int64_t)blockIdx.y * split_stride;
+  float* o = out + by * split_stride;
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
