@@ -136,14 +136,12 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
   const int team = threadIdx.x / T, q = threadIdx.x % T, c0 = 8 * q;
   const bool valid = (int64_t)blockIdx.x * TM::RB + team < rows;
   const bool needG = update || chk;
-  if (needG) load_gram<KP>(G, sG);
   const int64_t row0 = (int64_t)blockIdx.x * TM::RB;
   const int nrow = (int)(rows - row0 < TM::RB ? rows - row0 : TM::RB);
 
   float a[8];
   double p[8];
-  stage_rows<KP, KP + 4>(A, 1, 0, row0, nrow, r, sa);
-  if (needG) stage_rows<KP, KP + 1>(P, nsplit, pstride, row0, nrow, r, sgv);
+  stage_block<KP, KP + 4, KP + 1>(G, sG, A, sa, P, nsplit, pstride, sgv, row0, nrow, r, needG);
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     a[e] = sa[team][c0 + e];
@@ -185,28 +183,45 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
       __syncthreads();
       times_g(sa, t);
     }
-    const int base = (threadIdx.x % kWave) - q;
-    for (int j = 0; j < r; ++j) {
-      const int o = j / 8, ej = j % 8;
-      double delta = 0.0;
-      if (q == o) {
-        const double ig = sinv[j];
-        if (ig > 0.0) {
+    // Columns in blocks of 8, one block per team lane: the owner runs the
+    // block's steps on its own t (no exchange inside the block), then the
+    // team takes the 8 changes at once and applies them in column order,
+    // the same fma sequence as one column at a time.  The steps are
+    // branch-free so that the Gram rows can be read ahead: a padded column
+    // (j >= r, zero Gram row and diagonal) or one with G_jj = 0 changes
+    // nothing.
+    double ig[8];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            if (e == ej) {
-              const double v = (double)a[e] + (p[e] - t[e]) * ig;
-              const float nv = (float)(v > 0.0 ? v : 0.0);
-              delta = (double)nv - (double)a[e];
-              a[e] = nv;
-            }
-          }
+    for (int e = 0; e < 8; ++e) ig[e] = sinv[c0 + e];
+    const int base = (threadIdx.x % kWave) - q;
+    for (int o = 0; 8 * o < r; ++o) {
+      double dl[8];
+#pragma unroll
+      for (int ej = 0; ej < 8; ++ej) dl[ej] = 0.0;
+      if (q == o) {
+#pragma unroll
+        for (int ej = 0; ej < 8; ++ej) {
+          const double* gj = sG + (c0 + ej) * KP + c0;
+          const bool on = ig[ej] > 0.0;
+          const double v = (double)a[ej] + (p[ej] - t[ej]) * ig[ej];
+          const float nv = (float)(v > 0.0 ? v : 0.0);
+          const double d = on ? (double)nv - (double)a[ej] : 0.0;
+          a[ej] = on ? nv : a[ej];
+          dl[ej] = d;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) t[e] = fma(d, gj[e], t[e]);
         }
       }
-      delta = __shfl(delta, base + o);
-      const double* gj = sG + j * KP + c0;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) t[e] = fma(delta, gj[e], t[e]);
+      for (int ej = 0; ej < 8; ++ej) dl[ej] = __shfl(dl[ej], base + o);
+      if (q != o) {
+#pragma unroll
+        for (int ej = 0; ej < 8; ++ej) {
+          const double* gj = sG + (8 * o + ej) * KP + c0;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) t[e] = fma(dl[ej], gj[e], t[e]);
+        }
+      }
     }
     have_t = true;
   } else if (update) {

@@ -56,15 +56,26 @@ __device__ __forceinline__ void stage_rows(const float* __restrict__ src, int ns
     const int e = threadIdx.x + u * TM::NT;
     v[u] = e < cnt ? base[e] : 0.f;
   }
-  for (int sp = 1; sp < nsplit; ++sp) {
-    float w[PER];
+  // partials in batches of SB splits, all of a batch's loads issued before
+  // the first is added (the additions keep split order)
+  constexpr int SB = 8;
+  for (int sp0 = 1; sp0 < nsplit; sp0 += SB) {
+    float w[SB][PER];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = threadIdx.x + u * TM::NT;
-      w[u] = e < cnt ? base[(int64_t)sp * pstride + e] : 0.f;
+    for (int b = 0; b < SB; ++b) {
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + u * TM::NT;
+        w[b][u] = (sp0 + b < nsplit && e < cnt) ? base[(int64_t)(sp0 + b) * pstride + e] : 0.f;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < PER; ++u) v[u] += w[u];
+    for (int b = 0; b < SB; ++b) {
+      if (sp0 + b < nsplit) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) v[u] += w[b][u];
+      }
+    }
   }
   for (int e = threadIdx.x; e < TM::RB * KP; e += TM::NT) dst[e / KP][e % KP] = 0.f;
   __syncthreads();
@@ -72,6 +83,81 @@ __device__ __forceinline__ void stage_rows(const float* __restrict__ src, int ns
   for (int u = 0; u < PER; ++u) {
     const int e = threadIdx.x + u * TM::NT;
     if (e < cnt) dst[e / r][e % r] = v[u];
+  }
+  __syncthreads();
+}
+
+// One row block's inputs in a single pass: G (KP x KP float64) into sG and,
+// as stage_rows does, the block's rows of A into sa and of the summed split
+// partials of P into sp (the latter two only with_g for G and P).  All
+// loads of G, A and the first partial are issued before any is consumed,
+// so their latencies overlap; the partial sums keep split order.
+template <int KP, int LDA, int LDP>
+__device__ __forceinline__ void stage_block(const double* __restrict__ G, double* sG,
+                                            const float* __restrict__ A, float (*sa)[LDA],
+                                            const float* __restrict__ P, int nsplit,
+                                            int64_t pstride, float (*sp)[LDP], int64_t row0,
+                                            int nrow, int r, bool with_g) {
+  using TM = Team<KP>;
+  constexpr int PER = TM::RB * KP / TM::NT;
+  constexpr int PG = KP * KP / TM::NT;
+  static_assert(KP * KP % TM::NT == 0, "Gram tile must split evenly over the block");
+  const int cnt = nrow * r;
+  double gv[PG];
+  float av[PER], pv[PER];
+  if (with_g) {
+#pragma unroll
+    for (int u = 0; u < PG; ++u) gv[u] = G[threadIdx.x + u * TM::NT];
+  }
+  const float* abase = A + row0 * r;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * TM::NT;
+    av[u] = e < cnt ? abase[e] : 0.f;
+  }
+  if (with_g) {
+    const float* pbase = P + row0 * r;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * TM::NT;
+      pv[u] = e < cnt ? pbase[e] : 0.f;
+    }
+    constexpr int SB = 8;
+    for (int sp0 = 1; sp0 < nsplit; sp0 += SB) {
+      float w[SB][PER];
+#pragma unroll
+      for (int b = 0; b < SB; ++b) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int e = threadIdx.x + u * TM::NT;
+          w[b][u] = (sp0 + b < nsplit && e < cnt) ? pbase[(int64_t)(sp0 + b) * pstride + e] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < SB; ++b) {
+        if (sp0 + b < nsplit) {
+#pragma unroll
+          for (int u = 0; u < PER; ++u) pv[u] += w[b][u];
+        }
+      }
+    }
+  }
+  for (int e = threadIdx.x; e < TM::RB * KP; e += TM::NT) {
+    sa[e / KP][e % KP] = 0.f;
+    if (with_g) sp[e / KP][e % KP] = 0.f;
+  }
+  if (with_g) {
+#pragma unroll
+    for (int u = 0; u < PG; ++u) sG[threadIdx.x + u * TM::NT] = gv[u];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * TM::NT;
+    if (e < cnt) {
+      sa[e / r][e % r] = av[u];
+      if (with_g) sp[e / r][e % r] = pv[u];
+    }
   }
   __syncthreads();
 }
