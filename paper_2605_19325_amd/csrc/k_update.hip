@@ -357,8 +357,19 @@ __global__ __launch_bounds__(256) void k_gram_fin(const double* __restrict__ gpa
   const int e = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   const int lane = threadIdx.x % kWave;
   if (e >= NE) return;
+  // a lane's partials in batches of 8 loads in flight, added in block order
   double s = 0.0;
-  for (int b = lane; b < nparts; b += kWave) s += gpart[(int64_t)b * NE + e];
+  for (int b0 = lane; b0 < nparts; b0 += 8 * kWave) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = b0 + u * kWave;
+      v[u] = b < nparts ? gpart[(int64_t)b * NE + e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (b0 + u * kWave < nparts) s += v[u];
+  }
   s = wave_sum(s);
   if (lane == 0) {
     int ti, tj;
@@ -411,17 +422,44 @@ __global__ __launch_bounds__(kT) void k_finalize(const double* __restrict__ recU
       const double* rc = side == 0 ? recU : recV;
       const int nb = side == 0 ? nbU : nbV;
       double acc[8] = {0.0, 0.0, -INFINITY, 0.0, 0.0, 0.0, 0.0, INFINITY};
-      for (int b = threadIdx.x; b < nb; b += kT) {
-        const double* o = rc + (int64_t)b * kRecFields + kRecChk;
+      // a thread's records in batches of 4 with all loads in flight, combined in block order
+      for (int b0 = threadIdx.x; b0 < nb; b0 += 4 * kT) {
+        double w[4][8];
 #pragma unroll
-        for (int f = 0; f < 8; ++f)
-          acc[f] = f == 2 ? fmax(acc[f], o[f]) : (f == 7 ? fmin(acc[f], o[f]) : acc[f] + o[f]);
+        for (int u = 0; u < 4; ++u) {
+          const int b = b0 + u * kT;
+          const double* o = rc + (int64_t)(b < nb ? b : 0) * kRecFields + kRecChk;
+#pragma unroll
+          for (int f = 0; f < 8; ++f) w[u][f] = o[f];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (b0 + u * kT < nb) {
+#pragma unroll
+            for (int f = 0; f < 8; ++f)
+              acc[f] = f == 2 ? fmax(acc[f], w[u][f])
+                              : (f == 7 ? fmin(acc[f], w[u][f]) : acc[f] + w[u][f]);
+          }
+        }
       }
 #pragma unroll
       for (int f = 0; f < 8; ++f) v[8 * side + f] = acc[f];
     }
+    // <H, G>: a thread's entries (kp <= 64: at most 16) loaded at once, summed in order
     double hg = 0.0;
-    for (int e = threadIdx.x; e < kp * kp; e += kT) hg = fma(H[e], G[e], hg);
+    {
+      constexpr int PE = 64 * 64 / kT;
+      double hv[PE], gv[PE];
+#pragma unroll
+      for (int u = 0; u < PE; ++u) {
+        const int e = threadIdx.x + u * kT;
+        hv[u] = e < kp * kp ? H[e] : 0.0;
+        gv[u] = e < kp * kp ? G[e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < PE; ++u)
+        if (threadIdx.x + u * kT < kp * kp) hg = fma(hv[u], gv[u], hg);
+    }
     v[16] = hg;
     const int kind[NF] = {0, 0, 1, 0, 0, 0, 0, 2, 0, 0, 1, 0, 0, 0, 0, 2, 0};
     double a[NF];
@@ -572,6 +610,7 @@ hipError_t launch_pbcd_decide(const double* rec, int nparts, int half, int first
 hipError_t launch_finalize(const double* recU, int nbU, const double* recV, int nbV, const double* G,
                            const double* H, int kp, int k, int due, int final_check, DevState* st,
                            double* trace, hipStream_t s) {
+  if (kp > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kT), 0, s, recU, nbU, recV, nbV, G, H, kp, k, due,
                      final_check, st, trace);
   return hipGetLastError();
