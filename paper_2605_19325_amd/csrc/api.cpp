@@ -189,8 +189,10 @@ struct Parts {
 
 // P = X B as partials (B: n x k, ld k); P_out receives the product when it
 // is not split.
+// packed = true: the matrix-core form takes B already packed in its slot
+// (written by the row pass that produced B).
 enmf_status xv_parts(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, float* P_out,
-                     Parts* out, hipEvent_t* ev = nullptr) {
+                     Parts* out, hipEvent_t* ev = nullptr, bool packed = false) {
   hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
   int ns = 1;
   if (use_mfma(c, X, k)) {
@@ -199,7 +201,7 @@ enmf_status xv_parts(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, f
     WS(pack, void, S_BP, pb);
     WS(part, float, S_SPLIT, sb);
     CK(launch_xv_mfma(X->data, X->dtype, X->m, X->n, X->ld, B, k, pack, part, P_out, c->stream, 0,
-                      1, &ns, &c->st->stop, e0, e1));
+                      packed ? 0 : 1, &ns, &c->st->stop, e0, e1));
     out->p = ns > 1 ? part : P_out;
   } else {
     const int kp = pad_width(k);
@@ -221,7 +223,7 @@ enmf_status xv_parts(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, f
 
 // Q = X^T A as partials (A: m x k, ld k).
 enmf_status xtu_parts(enmf_ctx* c, const enmf_matrix* X, const float* A, int k, float* Q_out,
-                      Parts* out, hipEvent_t* ev = nullptr) {
+                      Parts* out, hipEvent_t* ev = nullptr, bool packed = false) {
   hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
   int ns = 1;
   if (use_mfma(c, X, k)) {
@@ -230,7 +232,7 @@ enmf_status xtu_parts(enmf_ctx* c, const enmf_matrix* X, const float* A, int k, 
     WS(pack, void, S_AP, pb);
     WS(part, float, S_SPLIT, sb);
     CK(launch_xtu_mfma(X->data, X->dtype, X->m, X->n, X->ld, A, k, pack, part, Q_out, c->stream, 0,
-                       1, &ns, &c->st->stop, e0, e1));
+                       packed ? 0 : 1, &ns, &c->st->stop, e0, e1));
     out->p = ns > 1 ? part : Q_out;
   } else {
     const int kp = pad_width(k);
@@ -638,9 +640,11 @@ extern "C" {
 //   xv(V^k) -> G^k = gram_fin(partial Grams of V^k)
 //   rowupdate U: phase from the previous records, check partials of U^k,
 //                update into the other U buffer, partial Grams of U^(k+1)
+//                (and, for the matrix-core products, U^(k+1) packed for xtu)
 //   finalize: check of iteration k (stop, trace, iteration count)
 //   H^(k+1) = gram_fin(...), xtu(U^(k+1)), rowupdate V (in place): check
-//                partials of V^(k+1) and its partial Grams.
+//                partials of V^(k+1), its partial Grams (and V^(k+1) packed
+//                for the next xv).
 // The U update of iteration k runs before its stop decision, into a second
 // buffer, so a stop at k keeps U^k; U^k lives in buffer k mod 2.
 enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U, float* V,
@@ -673,6 +677,21 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
   float* Ub[2] = {U, b.U2};
   Parts pp;
   c->pending[0] = c->pending[1] = 0;
+  // matrix-core products: each row pass also writes its output rows as the
+  // next product's packed factor (U for X^T U, V for X V)
+  const bool mf = use_mfma(c, X, r);
+  PackOut poU, poV;
+  if (mf) {
+    size_t pbx = 0, pbu = 0, t = 0;
+    mfma_xv_ws(X->dtype, m, n, r, &pbx, &t);
+    mfma_xtu_ws(X->dtype, m, n, r, &pbu, &t);
+    WS(bp, unsigned short, S_BP, pbx);
+    WS(ap, unsigned short, S_AP, pbu);
+    poV.p = bp;
+    mfma_pack_layout(X->dtype, 0, r, &poV.kp, &poV.c, &poV.ldt);
+    poU.p = ap;
+    mfma_pack_layout(X->dtype, 1, r, &poU.kp, &poU.c, &poU.ldt);
+  }
 
   auto sample = [&](int kind, int k) -> hipEvent_t* {
     if (c->timing_period <= 0 || k % c->timing_period != 0 || c->pending[kind] >= kTimingPairs)
@@ -683,16 +702,16 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
 
   // prologue: records and Grams of U^0 and V^0 (slot 1 = "iteration -1")
   CK(launch_rowupdate(U, U, m, r, kp, nullptr, 1, 0, nullptr, st, 0, 0, kRowGram, b.recU(1), b.gpU,
-                      nullptr, 0, nullptr, 0, s));
+                      nullptr, 0, nullptr, 0, s, poU));
   CK(launch_gram_fin(b.gpU, b.nbU, kp, b.H, s));
-  TRY(xtu_parts(c, X, U, r, b.Q, &pp));
+  TRY(xtu_parts(c, X, U, r, b.Q, &pp, nullptr, mf));
   CK(launch_rowupdate(V, V, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, 0,
-                      kRowGram | kRowWriteCheck, b.recV(1), b.gpV, nullptr, 0, nullptr, 0, s));
+                      kRowGram | kRowWriteCheck, b.recV(1), b.gpV, nullptr, 0, nullptr, 0, s, poV));
   for (int k = 0; k <= o.max_iter; ++k) {
     const int cur = k & 1, prev = cur ^ 1;
     const bool last = k == o.max_iter;
     const bool due = (k % o.check_every == 0) || last;
-    TRY(xv_parts(c, X, V, r, b.P, &pp, sample(0, k)));
+    TRY(xv_parts(c, X, V, r, b.P, &pp, sample(0, k), mf));
     CK(launch_gram_fin(b.gpV, b.nbV, kp, b.G, s));
     const int head = kRowHead | kRowCheckPre | (due ? kRowWriteCheck : 0);
     if (last) {
@@ -701,13 +720,13 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
     } else if (fixed) {
       CK(launch_rowupdate(Ub[cur], Ub[prev], m, r, kp, pp.p, pp.n, pp.stride, b.G, st, 0,
                           o.pbcd_max_iter, head | kRowUpdate | kRowFirst | kRowGram, b.recU(cur),
-                          b.gpU, b.recU(prev), b.nbU, b.recV(prev), b.nbV, s));
+                          b.gpU, b.recU(prev), b.nbU, b.recV(prev), b.nbV, s, poU));
     } else {
       for (int t = 0; t < o.pbcd_max_iter; ++t) {
         const int fl = kRowUpdate | kRowWantPg | kRowGram | (t == 0 ? head | kRowFirst : 0);
         CK(launch_rowupdate(t == 0 ? Ub[cur] : Ub[prev], Ub[prev], m, r, kp, pp.p, pp.n, pp.stride,
                             b.G, st, 0, 1, fl, b.recU(cur), b.gpU, b.recU(prev), b.nbU,
-                            b.recV(prev), b.nbV, s));
+                            b.recV(prev), b.nbV, s, poU));
         CK(launch_pbcd_decide(b.recU(cur), b.nbU, 0, t == 0, st, s));
       }
     }
@@ -715,16 +734,16 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
                        last ? 1 : 0, st, trace, s));
     if (last) break;
     CK(launch_gram_fin(b.gpU, b.nbU, kp, b.H, s));
-    TRY(xtu_parts(c, X, Ub[prev], r, b.Q, &pp, sample(1, k)));
+    TRY(xtu_parts(c, X, Ub[prev], r, b.Q, &pp, sample(1, k), mf));
     if (fixed) {
       CK(launch_rowupdate(V, V, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, o.pbcd_max_iter,
                           kRowUpdate | kRowFirst | kRowGram | kRowWriteCheck, b.recV(cur), b.gpV,
-                          nullptr, 0, nullptr, 0, s));
+                          nullptr, 0, nullptr, 0, s, poV));
     } else {
       for (int t = 0; t < o.pbcd_max_iter; ++t) {
         const int fl = kRowUpdate | kRowWantPg | kRowGram | kRowWriteCheck | (t == 0 ? kRowFirst : 0);
         CK(launch_rowupdate(V, V, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, 1, fl, b.recV(cur),
-                            b.gpV, nullptr, 0, nullptr, 0, s));
+                            b.gpV, nullptr, 0, nullptr, 0, s, poV));
         CK(launch_pbcd_decide(b.recV(cur), b.nbV, 1, t == 0, st, s));
       }
     }

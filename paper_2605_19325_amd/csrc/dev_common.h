@@ -29,6 +29,38 @@ __device__ __forceinline__ float to_f32(typename XElem<XT>::T v) {
   else return f16_bits_to_f32(v);
 }
 
+// bfloat16 bits of x, rounded to nearest even (NaN stays NaN).
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x0040u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+// Eight consecutive factor rows of one column, split into three bfloat16
+// terms (hi = rne(v), mid = rne(v - hi), lo = rne(v - hi - mid)), stored as
+// one 16-byte run per term at dst, dst + term_stride, dst + 2 term_stride
+// (the transposed split-chunk layout of the matrix-core products).
+__device__ __forceinline__ void store_split_run8(const float (&v)[8], unsigned short* dst,
+                                                 int64_t term_stride) {
+  unsigned h[4], md[4], lw[4];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const unsigned short hi = bf16_rne(v[u]);
+    const float r1 = v[u] - __uint_as_float((unsigned)hi << 16);
+    const unsigned short mid = bf16_rne(r1);
+    const unsigned short lo = bf16_rne(r1 - __uint_as_float((unsigned)mid << 16));
+    if ((u & 1) == 0) {
+      h[u / 2] = hi; md[u / 2] = mid; lw[u / 2] = lo;
+    } else {
+      h[u / 2] |= (unsigned)hi << 16; md[u / 2] |= (unsigned)mid << 16; lw[u / 2] |= (unsigned)lo << 16;
+    }
+  }
+  *reinterpret_cast<uint4*>(dst) = make_uint4(h[0], h[1], h[2], h[3]);
+  *reinterpret_cast<uint4*>(dst + term_stride) = make_uint4(md[0], md[1], md[2], md[3]);
+  *reinterpret_cast<uint4*>(dst + 2 * term_stride) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+}
+
 // Butterfly sum over the 64 lanes of a wave; every lane gets the same value
 // and the combination order does not depend on scheduling.
 __device__ __forceinline__ double wave_sum(double v) {

@@ -111,6 +111,9 @@ hipError_t launch_convert(const float* x, int64_t m, int64_t n, int64_t ldi, int
 
 // k_mfma.hip (matrix-core products, k >= 16, float32 or bfloat16 X)
 bool mfma_eligible(int xt, int k);
+// Packed split-factor layout read by the matrix-core X B (xtu = 0) or X^T A
+// (xtu = 1) at width k: padded width, rows per chunk, row pitch (elements).
+void mfma_pack_layout(int xt, int xtu, int k, int* kp, int* c, int* ldt);
 void mfma_xv_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes);
 void mfma_xtu_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes);
 hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* B,
@@ -161,13 +164,20 @@ hipError_t launch_factor_stats(const float* A, int64_t count, int r, double* par
 hipError_t launch_setup_state(const double* statpart, int nbU, int nbV, const double* xpart,
                               int nxpart, double step_u, double step_v, int ext_iters,
                               DevState* st, hipStream_t s);
+// Destination of the packed split factor a row pass can write for the next
+// matrix-core product (layout from mfma_pack_layout); p == nullptr: none.
+struct PackOut {
+  unsigned short* p = nullptr;
+  int kp = 0, c = 0, ldt = 0;
+};
 // One row pass (flags from RowFlags).  P: nsplit partials of stride pstride.
 // rec: kRecFields doubles per block; gpart: gram_part_len(kp) doubles per
 // block; headU/headV: the previous records of both halves (kRowHead).
 hipError_t launch_rowupdate(const float* A, float* Aout, int64_t rows, int r, int kp, const float* P,
                             int nsplit, int64_t pstride, const double* G, DevState* st, int half,
                             int sweeps, int flags, double* rec, double* gpart, const double* headU,
-                            int nbU, const double* headV, int nbV, hipStream_t s);
+                            int nbU, const double* headV, int nbV, hipStream_t s,
+                            const PackOut& po = PackOut());
 hipError_t launch_gram_fin(const double* gpart, int nparts, int kp, double* out, hipStream_t s);
 hipError_t launch_pbcd_decide(const double* rec, int nparts, int half, int first, DevState* st,
                               hipStream_t s);

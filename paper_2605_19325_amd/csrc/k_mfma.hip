@@ -44,13 +44,6 @@ constexpr int kT = 256;
 
 __device__ __forceinline__ f32x4 zero4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
 
-__device__ __forceinline__ unsigned short bf16_rne(float x) {
-  unsigned u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x0040u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-
 __device__ __forceinline__ bf16x8 as_bf16x8(const uint4& q) { return __builtin_bit_cast(bf16x8, q); }
 
 // Zero the elements of a vector of E elements starting at column col that are >= n.
@@ -679,23 +672,14 @@ __global__ void k_pack_split_t(const float* __restrict__ F, int64_t rows, int k,
     const int c = (int)(rest % KP);
     const int64_t ch = rest / KP;
     const int64_t row0 = ch * C + 8 * q;
-    unsigned h[4], md[4], lw[4];
+    float v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t row = row0 + u;
-      const float v = (row < rows && c < k) ? F[row * k + c] : 0.f;
-      const unsigned short hi = bf16_rne(v);
-      const float r1 = v - __uint_as_float((unsigned)hi << 16);
-      const unsigned short mid = bf16_rne(r1);
-      const unsigned short lo = bf16_rne(r1 - __uint_as_float((unsigned)mid << 16));
-      const int sh = 16 * (u & 1);
-      if ((u & 1) == 0) { h[u / 2] = hi; md[u / 2] = mid; lw[u / 2] = lo; }
-      else { h[u / 2] |= (unsigned)hi << sh; md[u / 2] |= (unsigned)mid << sh; lw[u / 2] |= (unsigned)lo << sh; }
+      v[u] = (row < rows && c < k) ? F[row * k + c] : 0.f;
     }
-    unsigned short* base = out + ch * (int64_t)(3 * KP * ldt) + (int64_t)c * ldt + 8 * q;
-    *reinterpret_cast<uint4*>(base) = make_uint4(h[0], h[1], h[2], h[3]);
-    *reinterpret_cast<uint4*>(base + (int64_t)KP * ldt) = make_uint4(md[0], md[1], md[2], md[3]);
-    *reinterpret_cast<uint4*>(base + (int64_t)2 * KP * ldt) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    store_split_run8(v, out + ch * (int64_t)(3 * KP * ldt) + (int64_t)c * ldt + 8 * q,
+                     (int64_t)KP * ldt);
   }
 }
 
@@ -832,6 +816,13 @@ Plan xtu_plan(int xt, int64_t m, int64_t n, int k) {
 }
 
 }  // namespace
+
+void mfma_pack_layout(int xt, int xtu, int k, int* kp, int* c, int* ldt) {
+  *kp = mfma_kp(k);
+  if (xtu) { *c = 32; *ldt = kAtLd; }
+  else if (xt == ENMF_F32) { *c = 32; *ldt = kBt32Ld; }
+  else { *c = 64; *ldt = kBtLd; }
+}
 
 bool mfma_eligible(int xt, int k) { return k >= 16 && k <= ENMF_MAX_WIDTH && (xt == ENMF_F32 || xt == ENMF_BF16); }
 

@@ -92,6 +92,10 @@ __global__ void k_setup_state(const double* __restrict__ stat, int nbU, int nbV,
 //                   kRowCheckPre, else at the output state.
 //   kRowGram        this block's partial Gram (upper 4x4 tiles, float64) of
 //                   the output rows, for k_gram_fin.
+// With `pack`, the output rows are also written as the packed split factor
+// the next matrix-core product reads (chunks of pc rows, width pkp <= KP,
+// row pitch pldt; see store_split_run8), the last block zeroing the rest of
+// the last chunk.
 // The result goes to Aout (which may be A).  rec[b] = {#negative of the
 // output, |M o grad|^2 before the sweeps, |M o grad|^2 after, 0, check...}.
 template <int KP>
@@ -100,7 +104,8 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
     const float* __restrict__ P, int nsplit, int64_t pstride, const double* __restrict__ G,
     DevState* st, int half, int sweeps, int flags, double* __restrict__ rec,
     double* __restrict__ gpart, const double* __restrict__ headU, int nbU,
-    const double* __restrict__ headV, int nbV) {
+    const double* __restrict__ headV, int nbV, unsigned short* __restrict__ pack, int pkp, int pc,
+    int pldt) {
   using TM = Team<KP>;
   constexpr int T = TM::T;
   constexpr int NW = TM::NT / kWave;
@@ -304,6 +309,20 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
     for (int u = 0; u < PER; ++u) {
       const int e = threadIdx.x + u * TM::NT;
       if (e < cnt) base[e] = sa[e / r][e % r];
+    }
+  }
+  if (pack != nullptr) {
+    const int64_t chunk_end = (rows + pc - 1) / pc * pc;
+    const int64_t end = blockIdx.x == gridDim.x - 1 ? chunk_end : row0 + TM::RB;
+    const int nruns = (int)((end - row0) / 8);
+    const int64_t term = (int64_t)pkp * pldt;
+    for (int task = threadIdx.x; task < pkp * nruns; task += TM::NT) {
+      const int lr = 8 * (task % nruns), c = task / nruns;
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = lr < TM::RB ? sa[lr + u][c] : 0.f;
+      const int64_t row = row0 + lr;
+      store_split_run8(v, pack + (row / pc) * 3 * term + (int64_t)c * pldt + row % pc, term);
     }
   }
   if (flags & kRowGram) {
@@ -524,11 +543,12 @@ template <int KP>
 void rowupdate_launch(const float* A, float* Aout, int64_t rows, int r, const float* P, int nsplit,
                       int64_t pstride, const double* G, DevState* st, int half, int sweeps,
                       int flags, double* rec, double* gpart, const double* headU, int nbU,
-                      const double* headV, int nbV, hipStream_t s) {
+                      const double* headV, int nbV, const PackOut& po, hipStream_t s) {
   using TM = Team<KP>;
   dim3 g((unsigned)((rows + TM::RB - 1) / TM::RB)), b(TM::NT);
   hipLaunchKernelGGL((k_rowupdate<KP>), g, b, 0, s, A, Aout, rows, r, P, nsplit, pstride, G, st,
-                     half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV);
+                     half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po.p, po.kp, po.c,
+                     po.ldt);
 }
 
 template <int KP>
@@ -581,12 +601,16 @@ int gram_part_len(int kp) { return 16 * ((kp / 4) * (kp / 4 + 1) / 2); }
 hipError_t launch_rowupdate(const float* A, float* Aout, int64_t rows, int r, int kp, const float* P,
                             int nsplit, int64_t pstride, const double* G, DevState* st, int half,
                             int sweeps, int flags, double* rec, double* gpart, const double* headU,
-                            int nbU, const double* headV, int nbV, hipStream_t s) {
+                            int nbU, const double* headV, int nbV, hipStream_t s,
+                            const PackOut& po) {
+  if (po.p != nullptr && (po.kp < 1 || po.kp > kp || po.c < 8 || po.c % 8 != 0 || po.ldt < po.c ||
+                          (po.ldt * 2) % 16 != 0))
+    return hipErrorInvalidValue;
   switch (kp) {
-    case 8: rowupdate_launch<8>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, s); break;
-    case 16: rowupdate_launch<16>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, s); break;
-    case 32: rowupdate_launch<32>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, s); break;
-    default: rowupdate_launch<64>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, s); break;
+    case 8: rowupdate_launch<8>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po, s); break;
+    case 16: rowupdate_launch<16>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po, s); break;
+    case 32: rowupdate_launch<32>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po, s); break;
+    default: rowupdate_launch<64>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po, s); break;
   }
   return hipGetLastError();
 }
