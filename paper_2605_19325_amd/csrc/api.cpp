@@ -191,8 +191,11 @@ struct Parts {
 // is not split.
 // packed = true: the matrix-core form takes B already packed in its slot
 // (written by the row pass that produced B).
+// gj: a Gram combine to run as well (inside the matrix-core product, else
+// as a launch of its own after it).
 enmf_status xv_parts(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, float* P_out,
-                     Parts* out, hipEvent_t* ev = nullptr, bool packed = false) {
+                     Parts* out, hipEvent_t* ev = nullptr, bool packed = false,
+                     const GramJob* gj = nullptr) {
   hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
   int ns = 1;
   if (use_mfma(c, X, k)) {
@@ -201,7 +204,7 @@ enmf_status xv_parts(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, f
     WS(pack, void, S_BP, pb);
     WS(part, float, S_SPLIT, sb);
     CK(launch_xv_mfma(X->data, X->dtype, X->m, X->n, X->ld, B, k, pack, part, P_out, c->stream, 0,
-                      packed ? 0 : 1, &ns, &c->st->stop, e0, e1));
+                      packed ? 0 : 1, &ns, &c->st->stop, e0, e1, gj));
     out->p = ns > 1 ? part : P_out;
   } else {
     const int kp = pad_width(k);
@@ -215,6 +218,7 @@ enmf_status xv_parts(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, f
                  &ns));
     if (e1) CK(hipEventRecord(e1, c->stream));
     out->p = ns > 1 ? part : P_out;
+    if (gj) CK(launch_gram_fin(gj->src, gj->nparts, gj->kp, gj->dst, c->stream));
   }
   out->n = ns;
   out->stride = X->m * k;
@@ -223,7 +227,8 @@ enmf_status xv_parts(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, f
 
 // Q = X^T A as partials (A: m x k, ld k).
 enmf_status xtu_parts(enmf_ctx* c, const enmf_matrix* X, const float* A, int k, float* Q_out,
-                      Parts* out, hipEvent_t* ev = nullptr, bool packed = false) {
+                      Parts* out, hipEvent_t* ev = nullptr, bool packed = false,
+                      const GramJob* gj = nullptr) {
   hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
   int ns = 1;
   if (use_mfma(c, X, k)) {
@@ -232,7 +237,7 @@ enmf_status xtu_parts(enmf_ctx* c, const enmf_matrix* X, const float* A, int k, 
     WS(pack, void, S_AP, pb);
     WS(part, float, S_SPLIT, sb);
     CK(launch_xtu_mfma(X->data, X->dtype, X->m, X->n, X->ld, A, k, pack, part, Q_out, c->stream, 0,
-                       packed ? 0 : 1, &ns, &c->st->stop, e0, e1));
+                       packed ? 0 : 1, &ns, &c->st->stop, e0, e1, gj));
     out->p = ns > 1 ? part : Q_out;
   } else {
     const int kp = pad_width(k);
@@ -245,6 +250,7 @@ enmf_status xtu_parts(enmf_ctx* c, const enmf_matrix* X, const float* A, int k, 
                   &ns));
     if (e1) CK(hipEventRecord(e1, c->stream));
     out->p = ns > 1 ? part : Q_out;
+    if (gj) CK(launch_gram_fin(gj->src, gj->nparts, gj->kp, gj->dst, c->stream));
   }
   out->n = ns;
   out->stride = X->n * k;
@@ -637,14 +643,16 @@ enmf_status set_trace_cap(enmf_ctx* c, int cap) {
 extern "C" {
 
 // Launch sequence of one solve (per outer iteration k):
-//   xv(V^k) -> G^k = gram_fin(partial Grams of V^k)
+//   xv(V^k), which also combines G^k from the partial Grams of V^k
 //   rowupdate U: phase from the previous records, check partials of U^k,
 //                update into the other U buffer, partial Grams of U^(k+1)
 //                (and, for the matrix-core products, U^(k+1) packed for xtu)
-//   finalize: check of iteration k (stop, trace, iteration count)
-//   H^(k+1) = gram_fin(...), xtu(U^(k+1)), rowupdate V (in place): check
-//                partials of V^(k+1), its partial Grams (and V^(k+1) packed
-//                for the next xv).
+//   xtu(U^(k+1)), which also combines H^(k+1)
+//   rowupdate V: first the check of iteration k (stop, trace, iteration
+//                count), then the update in place, check partials of
+//                V^(k+1), its partial Grams (and V^(k+1) packed for xv).
+// Without the matrix-core products the Gram combines are launches of their
+// own.  The last iteration (k = max_iter) only checks.
 // The U update of iteration k runs before its stop decision, into a second
 // buffer, so a stop at k keeps U^k; U^k lives in buffer k mod 2.
 enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U, float* V,
@@ -701,23 +709,31 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
   };
 
   // prologue: records and Grams of U^0 and V^0 (slot 1 = "iteration -1")
+  GramJob gjG, gjH;
+  gjG.src = b.gpV; gjG.nparts = b.nbV; gjG.kp = kp; gjG.dst = b.G;
+  gjH.src = b.gpU; gjH.nparts = b.nbU; gjH.kp = kp; gjH.dst = b.H;
   CK(launch_rowupdate(U, U, m, r, kp, nullptr, 1, 0, nullptr, st, 0, 0, kRowGram, b.recU(1), b.gpU,
                       nullptr, 0, nullptr, 0, s, poU));
-  CK(launch_gram_fin(b.gpU, b.nbU, kp, b.H, s));
-  TRY(xtu_parts(c, X, U, r, b.Q, &pp, nullptr, mf));
+  TRY(xtu_parts(c, X, U, r, b.Q, &pp, nullptr, mf, &gjH));
   CK(launch_rowupdate(V, V, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, 0,
                       kRowGram | kRowWriteCheck, b.recV(1), b.gpV, nullptr, 0, nullptr, 0, s, poV));
   for (int k = 0; k <= o.max_iter; ++k) {
     const int cur = k & 1, prev = cur ^ 1;
     const bool last = k == o.max_iter;
     const bool due = (k % o.check_every == 0) || last;
-    TRY(xv_parts(c, X, V, r, b.P, &pp, sample(0, k), mf));
-    CK(launch_gram_fin(b.gpV, b.nbV, kp, b.G, s));
+    DecideArgs dec;
+    dec.recU = b.recU(cur); dec.nbU = b.nbU;
+    dec.recV = b.recV(prev); dec.nbV = b.nbV;
+    dec.k = k; dec.due = due ? 1 : 0; dec.trace = trace;
+    TRY(xv_parts(c, X, V, r, b.P, &pp, sample(0, k), mf, &gjG));
     const int head = kRowHead | kRowCheckPre | (due ? kRowWriteCheck : 0);
     if (last) {
       CK(launch_rowupdate(Ub[cur], Ub[cur], m, r, kp, pp.p, pp.n, pp.stride, b.G, st, 0, 0, head,
                           b.recU(cur), b.gpU, b.recU(prev), b.nbU, b.recV(prev), b.nbV, s));
-    } else if (fixed) {
+      CK(launch_finalize(dec, 1, st, s));
+      break;
+    }
+    if (fixed) {
       CK(launch_rowupdate(Ub[cur], Ub[prev], m, r, kp, pp.p, pp.n, pp.stride, b.G, st, 0,
                           o.pbcd_max_iter, head | kRowUpdate | kRowFirst | kRowGram, b.recU(cur),
                           b.gpU, b.recU(prev), b.nbU, b.recV(prev), b.nbV, s, poU));
@@ -730,20 +746,19 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
         CK(launch_pbcd_decide(b.recU(cur), b.nbU, 0, t == 0, st, s));
       }
     }
-    CK(launch_finalize(b.recU(cur), b.nbU, b.recV(prev), b.nbV, b.G, b.H, kp, k, due ? 1 : 0,
-                       last ? 1 : 0, st, trace, s));
-    if (last) break;
-    CK(launch_gram_fin(b.gpU, b.nbU, kp, b.H, s));
-    TRY(xtu_parts(c, X, Ub[prev], r, b.Q, &pp, sample(1, k), mf));
+    // X^T U^(k+1) runs before the check of iteration k; the V pass takes the
+    // decision first and leaves V^k in place on a stop
+    TRY(xtu_parts(c, X, Ub[prev], r, b.Q, &pp, sample(1, k), mf, &gjH));
     if (fixed) {
       CK(launch_rowupdate(V, V, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, o.pbcd_max_iter,
-                          kRowUpdate | kRowFirst | kRowGram | kRowWriteCheck, b.recV(cur), b.gpV,
-                          nullptr, 0, nullptr, 0, s, poV));
+                          kRowDecide | kRowUpdate | kRowFirst | kRowGram | kRowWriteCheck,
+                          b.recV(cur), b.gpV, nullptr, 0, nullptr, 0, s, poV, dec));
     } else {
       for (int t = 0; t < o.pbcd_max_iter; ++t) {
-        const int fl = kRowUpdate | kRowWantPg | kRowGram | kRowWriteCheck | (t == 0 ? kRowFirst : 0);
+        const int fl = kRowUpdate | kRowWantPg | kRowGram | kRowWriteCheck |
+                       (t == 0 ? kRowFirst | kRowDecide : 0);
         CK(launch_rowupdate(V, V, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, 1, fl, b.recV(cur),
-                            b.gpV, nullptr, 0, nullptr, 0, s, poV));
+                            b.gpV, nullptr, 0, nullptr, 0, s, poV, dec));
         CK(launch_pbcd_decide(b.recV(cur), b.nbV, 1, t == 0, st, s));
       }
     }
@@ -761,9 +776,9 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
     for (int q = 0; q < c->pending[kind]; ++q) {
       float ms = 0.f;
       hipEvent_t* e = &c->events[2 * (kind * kTimingPairs + q)];
-      // the X V launch of the stopping iteration ran in full, later ones exit at once
+      // both products of the stopping iteration ran in full, later ones exit at once
       const int kq = c->pending_k[kind][q];
-      const bool ran = kind == 0 ? kq <= h.iters : kq < h.iters;
+      const bool ran = kq <= h.iters;
       if (ran && hipEventElapsedTime(&ms, e[0], e[1]) == hipSuccess) {
         c->timing_sum[kind] += ms;
         c->timing_n[kind] += 1;
@@ -833,7 +848,11 @@ enmf_status enmf_objective_kkt(enmf_ctx* c, const enmf_matrix* X, int32_t r, con
   TRY(xv_parts(c, X, V, r, b.P, &pp));
   CK(launch_rowupdate(U, Uw, m, r, kp, pp.p, pp.n, pp.stride, b.G, st, 0, 0,
                       kRowCheckPre | kRowWriteCheck, b.recU(0), b.gpU, nullptr, 0, nullptr, 0, s));
-  CK(launch_finalize(b.recU(0), b.nbU, b.recV(0), b.nbV, b.G, b.H, kp, 0, 1, 1, st, nullptr, s));
+  DecideArgs dec;
+  dec.recU = b.recU(0); dec.nbU = b.nbU;
+  dec.recV = b.recV(0); dec.nbV = b.nbV;
+  dec.k = 0; dec.due = 1;
+  CK(launch_finalize(dec, 1, st, s));
   DevState h;
   CK(hipMemcpyAsync(&h, c->st, sizeof(h), hipMemcpyDeviceToHost, s));
   CK(hipStreamSynchronize(s));

@@ -81,6 +81,50 @@ __device__ __forceinline__ double wave_min(double v) {
   return v;
 }
 
+// (ti, tj), ti <= tj, of upper-triangle tile `task` of an ntile x ntile
+// grid of 4x4 tiles, numbered row by row.
+__device__ __forceinline__ void upper_tile(int task, int ntile, int& ti, int& tj) {
+  int i = 0, rem = task;
+  while (rem >= ntile - i) { rem -= ntile - i; ++i; }
+  ti = i;
+  tj = i + rem;
+}
+
+// out (kp x kp, symmetric, float64) = sum of nparts partial Grams, each the
+// upper 4x4 tiles of one row block (16 doubles per tile, tiles in upper_tile
+// order).  One wave per entry: lane l adds parts l, l + 64, ... in order
+// (8 loads in flight), then the wave combines by butterfly.  The calling
+// wave takes entries wave, wave + nwaves, ...
+__device__ __forceinline__ void gram_combine(const double* __restrict__ gpart, int nparts, int kp,
+                                             double* __restrict__ out, int64_t wave,
+                                             int64_t nwaves) {
+  const int ntile = kp / 4;
+  const int ne = 16 * (ntile * (ntile + 1) / 2);
+  const int lane = threadIdx.x % kWave;
+  for (int64_t e = wave; e < ne; e += nwaves) {
+    double s = 0.0;
+    for (int b0 = lane; b0 < nparts; b0 += 8 * kWave) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int b = b0 + u * kWave;
+        v[u] = b < nparts ? gpart[(int64_t)b * ne + e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (b0 + u * kWave < nparts) s += v[u];
+    }
+    s = wave_sum(s);
+    if (lane == 0) {
+      int ti, tj;
+      upper_tile((int)(e / 16), ntile, ti, tj);
+      const int ii = 4 * ti + (int)(e % 16) / 4, jj = 4 * tj + (int)(e % 4);
+      out[ii * kp + jj] = s;
+      out[jj * kp + ii] = s;
+    }
+  }
+}
+
 // Fixed-order block reductions for blocks of NT threads (NT a multiple of 64).
 // `sh` must hold NT/64 doubles.  The result is valid in every thread.
 template <int NT>

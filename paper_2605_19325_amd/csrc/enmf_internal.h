@@ -41,12 +41,14 @@ struct DevState {
 
 // Per-block record written by the row-update kernel (float64 fields):
 // negative count of the output rows, PBCD gradient norms before/after the
-// sweeps, and 8 KKT-check partials starting at kRecChk.
+// sweeps, and kRecChkN KKT-check partials starting at kRecChk (CheckAcc
+// order: pg2, sg, mx, ng2, sq, ap, nneg, mn, q).
 constexpr int kRecFields = 16;
 constexpr int kRecNeg = 0;
 constexpr int kRecGi = 1;
 constexpr int kRecPg = 2;
 constexpr int kRecChk = 4;
+constexpr int kRecChkN = 9;
 constexpr int kTraceFields = ENMF_TRACE_FIELDS;
 
 // Work selected in one row-update launch (see k_rowupdate).
@@ -58,6 +60,18 @@ enum RowFlags {
   kRowWantPg = 16,      // masked gradient norm after the sweeps (PBCD tolerance stop)
   kRowGram = 32,        // partial Gram of the output rows
   kRowWriteCheck = 64,  // write the check partials
+  kRowDecide = 128,     // first: the check of iteration k and the stop decision (k_finalize's
+                        // work, in every block; block 0 writes the state)
+};
+
+// Arguments of the stop decision folded into a row pass (kRowDecide).
+struct DecideArgs {
+  const double* recU = nullptr;   // check records of U^k (this iteration's U pass)
+  int nbU = 0;
+  const double* recV = nullptr;   // check records of V^k (the previous V pass)
+  int nbV = 0;
+  int k = 0, due = 0;
+  double* trace = nullptr;
 };
 
 constexpr int kPhaseExt = 0;
@@ -116,14 +130,23 @@ bool mfma_eligible(int xt, int k);
 void mfma_pack_layout(int xt, int xtu, int k, int* kp, int* c, int* ldt);
 void mfma_xv_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes);
 void mfma_xtu_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes);
+// A Gram combine (gram_combine) a matrix-core product runs on the side:
+// dst (kp x kp) = sum of the nparts partial Grams at src.
+struct GramJob {
+  const double* src = nullptr;
+  int nparts = 0, kp = 0;
+  double* dst = nullptr;
+};
 hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* B,
                           int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
                           int do_pack, int* nsplit = nullptr, const int32_t* stop = nullptr,
-                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                          const GramJob* gj = nullptr);
 hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* A,
                            int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
                            int do_pack, int* nsplit = nullptr, const int32_t* stop = nullptr,
-                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                           const GramJob* gj = nullptr);
 
 // k_small.hip
 int gram_blocks(int64_t rows);
@@ -177,13 +200,11 @@ hipError_t launch_rowupdate(const float* A, float* Aout, int64_t rows, int r, in
                             int nsplit, int64_t pstride, const double* G, DevState* st, int half,
                             int sweeps, int flags, double* rec, double* gpart, const double* headU,
                             int nbU, const double* headV, int nbV, hipStream_t s,
-                            const PackOut& po = PackOut());
+                            const PackOut& po = PackOut(), const DecideArgs& dec = DecideArgs());
 hipError_t launch_gram_fin(const double* gpart, int nparts, int kp, double* out, hipStream_t s);
 hipError_t launch_pbcd_decide(const double* rec, int nparts, int half, int first, DevState* st,
                               hipStream_t s);
-hipError_t launch_finalize(const double* recU, int nbU, const double* recV, int nbV, const double* G,
-                           const double* H, int kp, int k, int due, int final_check, DevState* st,
-                           double* trace, hipStream_t s);
+hipError_t launch_finalize(const DecideArgs& d, int final_check, DevState* st, hipStream_t s);
 hipError_t launch_clip(float* A, int64_t count, hipStream_t s);
 
 }  // namespace enmf

@@ -135,7 +135,8 @@ __global__ __launch_bounds__(kT) void k_xv_bf16(const unsigned short* __restrict
                                                 const unsigned short* __restrict__ Bt, int k,
                                                 int chunks_per_split, int64_t nchunks, int vec,
                                                 float* __restrict__ out, int64_t split_stride,
-    const int32_t* __restrict__ stop) {
+    const int32_t* __restrict__ stop,
+    const double* __restrict__ gsrc, int gparts, int gkp, double* __restrict__ gdst) {
   if (stop != nullptr && *stop) return;
   constexpr int NT = KP / 16;
   constexpr int RT = 4;
@@ -197,8 +198,13 @@ __global__ __launch_bounds__(kT) void k_xv_bf16(const unsigned short* __restrict
   if (c0 < c1) {
     fetch_b(c0);
     load_x(c0, xa);
-    store_b(0);
   }
+  // side job: one Gram-combine entry per wave, its loads behind the first chunk's
+  if (gsrc != nullptr)
+    gram_combine(gsrc, gparts, gkp, gdst,
+                 ((int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y) * (kT / kWave) + w,
+                 (int64_t)gridDim.x * gridDim.y * (kT / kWave));
+  if (c0 < c1) store_b(0);
   int buf = 0;
   for (int64_t ch = c0; ch < c1; ++ch) {
     __syncthreads();
@@ -288,7 +294,8 @@ __global__ __launch_bounds__(kT) void k_xv_f32s(const float* __restrict__ X, int
                                                 int k, int chunks_per_split, int64_t nchunks,
                                                 int vec, float* __restrict__ out,
                                                 int64_t split_stride,
-                                                const int32_t* __restrict__ stop) {
+                                                const int32_t* __restrict__ stop,
+    const double* __restrict__ gsrc, int gparts, int gkp, double* __restrict__ gdst) {
   if (stop != nullptr && *stop) return;
   constexpr int NT = KP / 16;
   constexpr int RT = 4;
@@ -347,8 +354,13 @@ __global__ __launch_bounds__(kT) void k_xv_f32s(const float* __restrict__ X, int
   if (c0 < c1) {
     fetch_b(c0);
     load_x(c0, xa);
-    store_b(0);
   }
+  // side job: one Gram-combine entry per wave, its loads behind the first chunk's
+  if (gsrc != nullptr)
+    gram_combine(gsrc, gparts, gkp, gdst,
+                 ((int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y) * (kT / kWave) + w,
+                 (int64_t)gridDim.x * gridDim.y * (kT / kWave));
+  if (c0 < c1) store_b(0);
   int buf = 0;
   for (int64_t ch = c0; ch < c1; ++ch) {
     __syncthreads();
@@ -408,7 +420,8 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
                                                  const unsigned short* __restrict__ At, int k,
                                                  int64_t chunks_per_split, int64_t nchunks, int vec,
                                                  float* __restrict__ out, int64_t split_stride,
-    const int32_t* __restrict__ stop) {
+    const int32_t* __restrict__ stop,
+    const double* __restrict__ gsrc, int gparts, int gkp, double* __restrict__ gdst) {
   if (stop != nullptr && *stop) return;
   constexpr int NT = KP / 16;
   constexpr int CH = 3 * KP * kAtLd;
@@ -461,8 +474,13 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
   if (c0 < c1) {
     fetch_a(c0);
     load_x(c0, xa);
-    store_a(0);
   }
+  // side job: one Gram-combine entry per wave, its loads behind the first chunk's
+  if (gsrc != nullptr)
+    gram_combine(gsrc, gparts, gkp, gdst,
+                 ((int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y) * (kT / kWave) + w,
+                 (int64_t)gridDim.x * gridDim.y * (kT / kWave));
+  if (c0 < c1) store_a(0);
   int buf = 0;
   for (int64_t ch = c0; ch < c1; ++ch) {
     __syncthreads();
@@ -540,7 +558,8 @@ __global__ __launch_bounds__(kT) void k_xtu_f32s(const float* __restrict__ X, in
                                                  int k, int chunks_per_split, int64_t nchunks,
                                                  int vec, float* __restrict__ out,
                                                  int64_t split_stride,
-                                                 const int32_t* __restrict__ stop) {
+                                                 const int32_t* __restrict__ stop,
+    const double* __restrict__ gsrc, int gparts, int gkp, double* __restrict__ gdst) {
   if (stop != nullptr && *stop) return;
   constexpr int NT = KP / 16;
   constexpr int CH = 3 * KP * kAtLd;
@@ -592,8 +611,13 @@ __global__ __launch_bounds__(kT) void k_xtu_f32s(const float* __restrict__ X, in
   if (c0 < c1) {
     fetch_a(c0);
     load_x(c0, xa);
-    store_a(0);
   }
+  // side job: one Gram-combine entry per wave, its loads behind the first chunk's
+  if (gsrc != nullptr)
+    gram_combine(gsrc, gparts, gkp, gdst,
+                 ((int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y) * (kT / kWave) + w,
+                 (int64_t)gridDim.x * gridDim.y * (kT / kWave));
+  if (c0 < c1) store_a(0);
   int buf = 0;
   for (int64_t ch = c0; ch < c1; ++ch) {
     __syncthreads();
@@ -847,8 +871,11 @@ void mfma_xtu_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t
 hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* B,
                           int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
                           int do_pack, int* nsplit, const int32_t* stop,
-                           hipEvent_t ev0, hipEvent_t ev1) {
+                           hipEvent_t ev0, hipEvent_t ev1, const GramJob* gj) {
   const int KP = mfma_kp(k);
+  const double* gsrc = gj ? gj->src : nullptr;
+  const int gparts = gj ? gj->nparts : 0, gkp = gj ? gj->kp : 0;
+  double* gdst = gj ? gj->dst : nullptr;
   const bool vec = aligned_rows(X, ld, xt == ENMF_F32 ? 4 : 2);
   int64_t eff = 1;
   if (xt == ENMF_F32) {
@@ -866,11 +893,11 @@ hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t l
     const unsigned short* Bf = reinterpret_cast<const unsigned short*>(pack);
     if (ev0) (void)hipEventRecord(ev0, s);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xv_f32s<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
-      case 32: hipLaunchKernelGGL((k_xv_f32s<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
-      case 48: hipLaunchKernelGGL((k_xv_f32s<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
-      case 64: hipLaunchKernelGGL((k_xv_f32s<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
-      default: hipLaunchKernelGGL((k_xv_f32s<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
+      case 16: hipLaunchKernelGGL((k_xv_f32s<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop, gsrc, gparts, gkp, gdst); break;
+      case 32: hipLaunchKernelGGL((k_xv_f32s<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop, gsrc, gparts, gkp, gdst); break;
+      case 48: hipLaunchKernelGGL((k_xv_f32s<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop, gsrc, gparts, gkp, gdst); break;
+      case 64: hipLaunchKernelGGL((k_xv_f32s<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop, gsrc, gparts, gkp, gdst); break;
+      default: hipLaunchKernelGGL((k_xv_f32s<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, Bf, k, (int)cps, nch, (int)vec, dst, m * k, stop, gsrc, gparts, gkp, gdst); break;
     }
     if (ev1) (void)hipEventRecord(ev1, s);
   } else {
@@ -888,11 +915,11 @@ hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t l
     const unsigned short* Bt = reinterpret_cast<const unsigned short*>(pack);
     if (ev0) (void)hipEventRecord(ev0, s);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xv_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
-      case 32: hipLaunchKernelGGL((k_xv_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
-      case 48: hipLaunchKernelGGL((k_xv_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
-      case 64: hipLaunchKernelGGL((k_xv_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
-      default: hipLaunchKernelGGL((k_xv_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k, stop); break;
+      case 16: hipLaunchKernelGGL((k_xv_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k, stop, gsrc, gparts, gkp, gdst); break;
+      case 32: hipLaunchKernelGGL((k_xv_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k, stop, gsrc, gparts, gkp, gdst); break;
+      case 48: hipLaunchKernelGGL((k_xv_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k, stop, gsrc, gparts, gkp, gdst); break;
+      case 64: hipLaunchKernelGGL((k_xv_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k, stop, gsrc, gparts, gkp, gdst); break;
+      default: hipLaunchKernelGGL((k_xv_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, Bt, k, (int)cps, nch, (int)vec, dst, m * k, stop, gsrc, gparts, gkp, gdst); break;
     }
     if (ev1) (void)hipEventRecord(ev1, s);
   }
@@ -907,8 +934,11 @@ hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t l
 hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* A,
                            int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
                            int do_pack, int* nsplit, const int32_t* stop,
-                           hipEvent_t ev0, hipEvent_t ev1) {
+                           hipEvent_t ev0, hipEvent_t ev1, const GramJob* gj) {
   const int KP = mfma_kp(k);
+  const double* gsrc = gj ? gj->src : nullptr;
+  const int gparts = gj ? gj->nparts : 0, gkp = gj ? gj->kp : 0;
+  double* gdst = gj ? gj->dst : nullptr;
   const bool vec = aligned_rows(X, ld, xt == ENMF_F32 ? 4 : 2);
   int64_t eff = 1;
   if (xt == ENMF_F32) {
@@ -926,11 +956,11 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
     const unsigned short* At = reinterpret_cast<const unsigned short*>(pack);
     if (ev0) (void)hipEventRecord(ev0, s);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xtu_f32s<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
-      case 32: hipLaunchKernelGGL((k_xtu_f32s<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
-      case 48: hipLaunchKernelGGL((k_xtu_f32s<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
-      case 64: hipLaunchKernelGGL((k_xtu_f32s<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
-      default: hipLaunchKernelGGL((k_xtu_f32s<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
+      case 16: hipLaunchKernelGGL((k_xtu_f32s<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
+      case 32: hipLaunchKernelGGL((k_xtu_f32s<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
+      case 48: hipLaunchKernelGGL((k_xtu_f32s<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
+      case 64: hipLaunchKernelGGL((k_xtu_f32s<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
+      default: hipLaunchKernelGGL((k_xtu_f32s<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
     }
     if (ev1) (void)hipEventRecord(ev1, s);
   } else {
@@ -948,11 +978,11 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
     const unsigned short* At = reinterpret_cast<const unsigned short*>(pack);
     if (ev0) (void)hipEventRecord(ev0, s);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xtu_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
-      case 32: hipLaunchKernelGGL((k_xtu_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
-      case 48: hipLaunchKernelGGL((k_xtu_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
-      case 64: hipLaunchKernelGGL((k_xtu_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
-      default: hipLaunchKernelGGL((k_xtu_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop); break;
+      case 16: hipLaunchKernelGGL((k_xtu_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
+      case 32: hipLaunchKernelGGL((k_xtu_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
+      case 48: hipLaunchKernelGGL((k_xtu_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
+      case 64: hipLaunchKernelGGL((k_xtu_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
+      default: hipLaunchKernelGGL((k_xtu_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
     }
     if (ev1) (void)hipEventRecord(ev1, s);
   }

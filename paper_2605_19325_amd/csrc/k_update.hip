@@ -73,6 +73,112 @@ __global__ void k_setup_state(const double* __restrict__ stat, int nbU, int nbV,
   st->pbcd_done[0] = st->pbcd_done[1] = 0;
 }
 
+// Check of iteration k (the KKT appendix): combine the check records of the
+// U half (input state U^k) and of the V half (V^k) in block order, evaluate
+// f through the expansion 1/2||X||^2 - <U, X V> + 1/2 <U^T U, V^T V> (the
+// last term from the U records' a . (a G) shares), the relative error and
+// the normalised KKT residual documented in enmf.h, decide whether to stop,
+// append a trace record, and count the iteration.  `due` = 0 skips the
+// evaluation (check_every > 1) and only counts.  Called by all NT threads of
+// a block; every calling block reaches the same decision, and only the
+// writer block updates the state.  sh: 17 NT/64 doubles; flag: one int (LDS).
+template <int NT>
+__device__ bool check_decide(const DecideArgs& d, int final_check, DevState* st, bool writer,
+                             double* sh, int* flag) {
+  constexpr int NF = 17;
+  if (d.due || final_check) {
+    double v[NF];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const double* rc = side == 0 ? d.recU : d.recV;
+      const int nb = side == 0 ? d.nbU : d.nbV;
+      double acc[kRecChkN] = {0.0, 0.0, -INFINITY, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0};
+      // a thread's records in batches of 4 with all loads in flight, combined in block order
+      for (int b0 = threadIdx.x; b0 < nb; b0 += 4 * NT) {
+        double w[4][kRecChkN];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int b = b0 + u * NT;
+          const double* o = rc + (int64_t)(b < nb ? b : 0) * kRecFields + kRecChk;
+#pragma unroll
+          for (int f = 0; f < kRecChkN; ++f) w[u][f] = o[f];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (b0 + u * NT < nb) {
+#pragma unroll
+            for (int f = 0; f < kRecChkN; ++f)
+              acc[f] = f == 2 ? fmax(acc[f], w[u][f])
+                              : (f == 7 ? fmin(acc[f], w[u][f]) : acc[f] + w[u][f]);
+          }
+        }
+      }
+#pragma unroll
+      for (int f = 0; f < 8; ++f) v[8 * side + f] = acc[f];
+      if (side == 0) v[16] = acc[8];
+    }
+    const int kind[NF] = {0, 0, 1, 0, 0, 0, 0, 2, 0, 0, 1, 0, 0, 0, 0, 2, 0};
+    double a[NF];
+    block_reduce_fields<NT, NF>(v, kind, sh, a);
+    if (threadIdx.x == 0) {
+      const double nx2 = st->nx2;
+      const double f = 0.5 * nx2 - a[5] + 0.5 * a[16];
+      const double nx = sqrt(nx2);
+      const double nU = sqrt(a[4]), nV = sqrt(a[12]);
+      const double feas = fmax(nU > 0.0 ? sqrt(a[3]) / nU : 0.0, nV > 0.0 ? sqrt(a[11]) / nV : 0.0);
+      const double pgu = (nV > 0.0 && nx > 0.0) ? sqrt(a[0]) / (nx * nV) : 0.0;
+      const double pgv = (nU > 0.0 && nx > 0.0) ? sqrt(a[8]) / (nx * nU) : 0.0;
+      const double kkt = fmax(feas, fmax(pgu, pgv));
+      const double relerr = nx > 0.0 ? sqrt(fmax(2.0 * f, 0.0)) / nx : 0.0;
+      const double negs = a[6] + a[14];
+      const bool feasible = negs == 0.0;
+      const bool hit = feasible && ((st->kkt_tol >= 0.0 && kkt <= st->kkt_tol) ||
+                                    (st->relerr_tol >= 0.0 && relerr - st->relerr_svd <= st->relerr_tol) ||
+                                    st->mode == 3);
+      const bool numerr = !isfinite(f) || !isfinite(kkt);
+      if (writer) {
+        st->f = f;
+        st->relerr = relerr;
+        st->kkt = kkt;
+        st->kkt_feas = feas;
+        st->kkt_pg_u = pgu;
+        st->kkt_pg_v = pgv;
+        st->delta_w = fmax(a[2], a[10]);
+        st->sigma_u = a[1];
+        st->sigma_v = a[9];
+        st->sigma_w = a[1] + a[9];
+        st->min_w = fmin(a[7], a[15]);
+        st->re_paper = st->relerr_svd > 0.0 ? relerr / st->relerr_svd : NAN;
+        if (numerr) st->numeric_error = 1;
+        if (d.trace != nullptr && st->ntrace < st->trace_cap) {
+          double* o = d.trace + (int64_t)st->ntrace * kTraceFields;
+          o[0] = (double)d.k; o[1] = f; o[2] = relerr; o[3] = kkt; o[4] = fmin(a[7], a[15]);
+          o[5] = (double)(negs > 0.0 ? kPhaseExt : kPhaseHals);
+          o[6] = (double)wall_clock64() * st->ns_per_tick;
+          o[7] = negs;
+          st->ntrace += 1;
+        }
+      }
+      *flag = ((final_check != 0 || hit || numerr) ? 1 : 0) | (hit ? 2 : 0);
+    }
+  } else if (threadIdx.x == 0) {
+    *flag = final_check != 0 ? 1 : 0;
+  }
+  __syncthreads();
+  const int fl = *flag;
+  if (writer && threadIdx.x == 0) {
+    if (fl & 1) {
+      st->stop = 1;
+      st->converged = (fl & 2) ? 1 : 0;
+      st->iters = d.k;
+    } else {
+      st->iters = d.k + 1;
+      if (st->phase == kPhaseExt) st->ext_done += 1;
+    }
+  }
+  return (fl & 1) != 0;
+}
+
 // One half of an outer iteration on the rows of A (U with P = X V, G = V^T V,
 // or V with P = X^T U, G = U^T U).  P arrives as `nsplit` float32 partial
 // products (stride pstride) summed here in split order.
@@ -105,18 +211,20 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
     DevState* st, int half, int sweeps, int flags, double* __restrict__ rec,
     double* __restrict__ gpart, const double* __restrict__ headU, int nbU,
     const double* __restrict__ headV, int nbV, unsigned short* __restrict__ pack, int pkp, int pc,
-    int pldt) {
+    int pldt, DecideArgs dec) {
   using TM = Team<KP>;
   constexpr int T = TM::T;
   constexpr int NW = TM::NT / kWave;
-  constexpr int NF = 3 + 8;
+  constexpr int NF = 3 + kRecChkN;
   __shared__ double sG[KP * KP];
   __shared__ __align__(16) float sa[TM::RB][KP + 4];
   __shared__ float sgv[TM::RB][KP + 1];
   __shared__ double sT[KP >= 16 ? TM::RB : 1][KP + 1];
   __shared__ double sinv[KP];
-  __shared__ double sh[NF * NW];
+  __shared__ double sh[(NF > 17 ? NF : 17) * NW];
+  __shared__ int sflag;
   if (st->stop) return;
+  if ((flags & kRowDecide) && check_decide<TM::NT>(dec, 0, st, blockIdx.x == 0, sh, &sflag)) return;
   const bool update = (flags & kRowUpdate) != 0;
   const bool first = (flags & kRowFirst) != 0;
   const bool chk = (flags & kRowWriteCheck) != 0;
@@ -349,8 +457,8 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
       for (int e = 0; e < 16; ++e) o[e] = acc[e];
     }
   }
-  double vals[NF] = {negc, gi2, pg2, ck.pg2, ck.sg, ck.mx, ck.ng2, ck.sq, ck.ap, ck.nneg, ck.mn};
-  const int kind[NF] = {0, 0, 0, 0, 0, 1, 0, 0, 0, 0, 2};
+  double vals[NF] = {negc, gi2, pg2, ck.pg2, ck.sg, ck.mx, ck.ng2, ck.sq, ck.ap, ck.nneg, ck.mn, ck.q};
+  const int kind[NF] = {0, 0, 0, 0, 0, 1, 0, 0, 0, 0, 2, 0};
   double red[NF];
   block_reduce_fields<TM::NT, NF>(vals, kind, sh, red);
   if (threadIdx.x == 0) {
@@ -360,43 +468,18 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
     o[kRecPg] = red[2];
     if (chk) {
 #pragma unroll
-      for (int f = 0; f < 8; ++f) o[kRecChk + f] = red[3 + f];
+      for (int f = 0; f < kRecChkN; ++f) o[kRecChk + f] = red[3 + f];
     }
   }
 }
 
 // G (KP x KP, symmetric, zero padded) = sum over blocks of the partial Grams
-// written by k_rowupdate, in block order.  One wave per upper-triangle entry;
-// lanes take the blocks round robin and combine by butterfly.
+// written by k_rowupdate, in block order (gram_combine: one wave per entry).
 template <int KP>
 __global__ __launch_bounds__(256) void k_gram_fin(const double* __restrict__ gpart, int nparts,
                                                   double* __restrict__ out) {
-  constexpr int NTILE = KP / 4;
-  constexpr int NE = 16 * (NTILE * (NTILE + 1) / 2);
-  const int e = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
-  const int lane = threadIdx.x % kWave;
-  if (e >= NE) return;
-  // a lane's partials in batches of 8 loads in flight, added in block order
-  double s = 0.0;
-  for (int b0 = lane; b0 < nparts; b0 += 8 * kWave) {
-    double v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int b = b0 + u * kWave;
-      v[u] = b < nparts ? gpart[(int64_t)b * NE + e] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (b0 + u * kWave < nparts) s += v[u];
-  }
-  s = wave_sum(s);
-  if (lane == 0) {
-    int ti, tj;
-    gram_tile<KP>(e / 16, ti, tj);
-    const int ii = 4 * ti + (e % 16) / 4, jj = 4 * tj + (e % 4);
-    out[ii * KP + jj] = s;
-    out[jj * KP + ii] = s;
-  }
+  gram_combine(gpart, nparts, KP, out, (int64_t)(blockIdx.x * blockDim.x + threadIdx.x) / kWave,
+               (int64_t)gridDim.x * blockDim.x / kWave);
 }
 
 // PBCD stop test of Algorithm 2 between sweep launches:
@@ -417,120 +500,13 @@ __global__ __launch_bounds__(kT) void k_pbcd_decide(const double* __restrict__ r
   }
 }
 
-// Check of iteration k (the KKT appendix): combine the check records of the
-// U half (input state U^k) and of the V half (V^k) in block order, evaluate
-// f through the expansion 1/2||X||^2 - <U, X V> + 1/2 <U^T U, V^T V>, the
-// relative error and the normalised KKT residual documented in enmf.h,
-// decide whether to stop, append a trace record, and count the iteration.
-// `due` = 0 skips the evaluation (check_every > 1) and only counts.
-__global__ __launch_bounds__(kT) void k_finalize(const double* __restrict__ recU, int nbU,
-                                                 const double* __restrict__ recV, int nbV,
-                                                 const double* __restrict__ G,
-                                                 const double* __restrict__ H, int kp, int k,
-                                                 int due, int final_check, DevState* st,
-                                                 double* __restrict__ trace) {
-  constexpr int NF = 17;
-  __shared__ double sh[NF * (kT / kWave)];
+// The check and stop decision of iteration k as a launch of its own (the
+// final check, and solves whose V pass does not carry kRowDecide).
+__global__ __launch_bounds__(kT) void k_finalize(DecideArgs d, int final_check, DevState* st) {
+  __shared__ double sh[17 * (kT / kWave)];
+  __shared__ int flag;
   if (st->stop) return;
-  bool stop = final_check != 0;
-  bool hit = false;
-  if (due || final_check) {
-    double v[NF];
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const double* rc = side == 0 ? recU : recV;
-      const int nb = side == 0 ? nbU : nbV;
-      double acc[8] = {0.0, 0.0, -INFINITY, 0.0, 0.0, 0.0, 0.0, INFINITY};
-      // a thread's records in batches of 4 with all loads in flight, combined in block order
-      for (int b0 = threadIdx.x; b0 < nb; b0 += 4 * kT) {
-        double w[4][8];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int b = b0 + u * kT;
-          const double* o = rc + (int64_t)(b < nb ? b : 0) * kRecFields + kRecChk;
-#pragma unroll
-          for (int f = 0; f < 8; ++f) w[u][f] = o[f];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (b0 + u * kT < nb) {
-#pragma unroll
-            for (int f = 0; f < 8; ++f)
-              acc[f] = f == 2 ? fmax(acc[f], w[u][f])
-                              : (f == 7 ? fmin(acc[f], w[u][f]) : acc[f] + w[u][f]);
-          }
-        }
-      }
-#pragma unroll
-      for (int f = 0; f < 8; ++f) v[8 * side + f] = acc[f];
-    }
-    // <H, G>: a thread's entries (kp <= 64: at most 16) loaded at once, summed in order
-    double hg = 0.0;
-    {
-      constexpr int PE = 64 * 64 / kT;
-      double hv[PE], gv[PE];
-#pragma unroll
-      for (int u = 0; u < PE; ++u) {
-        const int e = threadIdx.x + u * kT;
-        hv[u] = e < kp * kp ? H[e] : 0.0;
-        gv[u] = e < kp * kp ? G[e] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < PE; ++u)
-        if (threadIdx.x + u * kT < kp * kp) hg = fma(hv[u], gv[u], hg);
-    }
-    v[16] = hg;
-    const int kind[NF] = {0, 0, 1, 0, 0, 0, 0, 2, 0, 0, 1, 0, 0, 0, 0, 2, 0};
-    double a[NF];
-    block_reduce_fields<kT, NF>(v, kind, sh, a);
-    if (threadIdx.x != 0) return;
-    const double nx2 = st->nx2;
-    const double f = 0.5 * nx2 - a[5] + 0.5 * a[16];
-    const double nx = sqrt(nx2);
-    const double nU = sqrt(a[4]), nV = sqrt(a[12]);
-    const double feas = fmax(nU > 0.0 ? sqrt(a[3]) / nU : 0.0, nV > 0.0 ? sqrt(a[11]) / nV : 0.0);
-    const double pgu = (nV > 0.0 && nx > 0.0) ? sqrt(a[0]) / (nx * nV) : 0.0;
-    const double pgv = (nU > 0.0 && nx > 0.0) ? sqrt(a[8]) / (nx * nU) : 0.0;
-    const double kkt = fmax(feas, fmax(pgu, pgv));
-    const double relerr = nx > 0.0 ? sqrt(fmax(2.0 * f, 0.0)) / nx : 0.0;
-    const double negs = a[6] + a[14];
-    st->f = f;
-    st->relerr = relerr;
-    st->kkt = kkt;
-    st->kkt_feas = feas;
-    st->kkt_pg_u = pgu;
-    st->kkt_pg_v = pgv;
-    st->delta_w = fmax(a[2], a[10]);
-    st->sigma_u = a[1];
-    st->sigma_v = a[9];
-    st->sigma_w = a[1] + a[9];
-    st->min_w = fmin(a[7], a[15]);
-    st->re_paper = st->relerr_svd > 0.0 ? relerr / st->relerr_svd : NAN;
-    const bool feasible = negs == 0.0;
-    hit = feasible && ((st->kkt_tol >= 0.0 && kkt <= st->kkt_tol) ||
-                       (st->relerr_tol >= 0.0 && relerr - st->relerr_svd <= st->relerr_tol) ||
-                       st->mode == 3);
-    if (!isfinite(f) || !isfinite(kkt)) st->numeric_error = 1;
-    if (trace != nullptr && st->ntrace < st->trace_cap) {
-      double* o = trace + (int64_t)st->ntrace * kTraceFields;
-      o[0] = (double)k; o[1] = f; o[2] = relerr; o[3] = kkt; o[4] = st->min_w;
-      o[5] = (double)(negs > 0.0 ? kPhaseExt : kPhaseHals);
-      o[6] = (double)wall_clock64() * st->ns_per_tick;
-      o[7] = negs;
-      st->ntrace += 1;
-    }
-    if (hit || st->numeric_error) stop = true;
-  } else if (threadIdx.x != 0) {
-    return;
-  }
-  if (stop) {
-    st->stop = 1;
-    st->converged = hit ? 1 : 0;
-    st->iters = k;
-  } else {
-    st->iters = k + 1;
-    if (st->phase == kPhaseExt) st->ext_done += 1;
-  }
+  (void)check_decide<kT>(d, final_check, st, true, sh, &flag);
 }
 
 __global__ void k_clip(float* __restrict__ A, int64_t count) {
@@ -543,12 +519,13 @@ template <int KP>
 void rowupdate_launch(const float* A, float* Aout, int64_t rows, int r, const float* P, int nsplit,
                       int64_t pstride, const double* G, DevState* st, int half, int sweeps,
                       int flags, double* rec, double* gpart, const double* headU, int nbU,
-                      const double* headV, int nbV, const PackOut& po, hipStream_t s) {
+                      const double* headV, int nbV, const PackOut& po, const DecideArgs& dec,
+                      hipStream_t s) {
   using TM = Team<KP>;
   dim3 g((unsigned)((rows + TM::RB - 1) / TM::RB)), b(TM::NT);
   hipLaunchKernelGGL((k_rowupdate<KP>), g, b, 0, s, A, Aout, rows, r, P, nsplit, pstride, G, st,
                      half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po.p, po.kp, po.c,
-                     po.ldt);
+                     po.ldt, dec);
 }
 
 template <int KP>
@@ -602,15 +579,15 @@ hipError_t launch_rowupdate(const float* A, float* Aout, int64_t rows, int r, in
                             int nsplit, int64_t pstride, const double* G, DevState* st, int half,
                             int sweeps, int flags, double* rec, double* gpart, const double* headU,
                             int nbU, const double* headV, int nbV, hipStream_t s,
-                            const PackOut& po) {
+                            const PackOut& po, const DecideArgs& dec) {
   if (po.p != nullptr && (po.kp < 1 || po.kp > kp || po.c < 8 || po.c % 8 != 0 || po.ldt < po.c ||
                           (po.ldt * 2) % 16 != 0))
     return hipErrorInvalidValue;
   switch (kp) {
-    case 8: rowupdate_launch<8>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po, s); break;
-    case 16: rowupdate_launch<16>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po, s); break;
-    case 32: rowupdate_launch<32>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po, s); break;
-    default: rowupdate_launch<64>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po, s); break;
+    case 8: rowupdate_launch<8>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po, dec, s); break;
+    case 16: rowupdate_launch<16>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po, dec, s); break;
+    case 32: rowupdate_launch<32>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po, dec, s); break;
+    default: rowupdate_launch<64>(A, Aout, rows, r, P, nsplit, pstride, G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po, dec, s); break;
   }
   return hipGetLastError();
 }
@@ -631,12 +608,8 @@ hipError_t launch_pbcd_decide(const double* rec, int nparts, int half, int first
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double* recU, int nbU, const double* recV, int nbV, const double* G,
-                           const double* H, int kp, int k, int due, int final_check, DevState* st,
-                           double* trace, hipStream_t s) {
-  if (kp > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kT), 0, s, recU, nbU, recV, nbV, G, H, kp, k, due,
-                     final_check, st, trace);
+hipError_t launch_finalize(const DecideArgs& d, int final_check, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kT), 0, s, d, final_check, st);
   return hipGetLastError();
 }
 

@@ -235,9 +235,11 @@ __device__ __forceinline__ void gram_tile(int task, int& ti, int& tj) {
 // Check-record accumulators for one row: grad = a G - p (the gradient of
 // eq. 1 through the Gram identity), projected gradient = grad where a > 0
 // and min(grad, 0) where a <= 0 (the KKT appendix).
+// q accumulates a . (a G), the row's share of <A^T A, G> (the quadratic
+// term of the objective expansion).
 struct CheckAcc {
   double pg2 = 0.0, sg = 0.0, mx = -INFINITY, ng2 = 0.0, sq = 0.0, ap = 0.0, nneg = 0.0,
-         mn = INFINITY;
+         mn = INFINITY, q = 0.0;
   __device__ __forceinline__ void add(const float* a, const double* s, const double* p, int c0,
                                       int r) {
 #pragma unroll
@@ -253,6 +255,7 @@ struct CheckAcc {
         sq = fma(av, av, sq);
         ap = fma(av, p[e], ap);
         mn = fmin(mn, av);
+        q = fma(av, s[e], q);
       }
     }
   }
