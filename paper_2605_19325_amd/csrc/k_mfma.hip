@@ -199,11 +199,9 @@ __global__ __launch_bounds__(kT) void k_xv_bf16(const unsigned short* __restrict
     fetch_b(c0);
     load_x(c0, xa);
   }
-  // side job: one Gram-combine entry per wave, its loads behind the first chunk's
-  if (gsrc != nullptr)
-    gram_combine(gsrc, gparts, gkp, gdst,
-                 ((int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y) * (kT / kWave) + w,
-                 (int64_t)gridDim.x * gridDim.y * (kT / kWave));
+  // side job: a Gram combine, one entry per wave, its loads behind the first chunk's
+  const int64_t gwave = ((int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y) * (kT / kWave) + w;
+  if (gsrc != nullptr) gram_combine(gsrc, gparts, gkp, gdst, gwave, (int64_t)gridDim.x * gridDim.y * (kT / kWave));
   if (c0 < c1) store_b(0);
   int buf = 0;
   for (int64_t ch = c0; ch < c1; ++ch) {
@@ -355,11 +353,9 @@ __global__ __launch_bounds__(kT) void k_xv_f32s(const float* __restrict__ X, int
     fetch_b(c0);
     load_x(c0, xa);
   }
-  // side job: one Gram-combine entry per wave, its loads behind the first chunk's
-  if (gsrc != nullptr)
-    gram_combine(gsrc, gparts, gkp, gdst,
-                 ((int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y) * (kT / kWave) + w,
-                 (int64_t)gridDim.x * gridDim.y * (kT / kWave));
+  // side job: a Gram combine, one entry per wave, its loads behind the first chunk's
+  const int64_t gwave = ((int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y) * (kT / kWave) + w;
+  if (gsrc != nullptr) gram_combine(gsrc, gparts, gkp, gdst, gwave, (int64_t)gridDim.x * gridDim.y * (kT / kWave));
   if (c0 < c1) store_b(0);
   int buf = 0;
   for (int64_t ch = c0; ch < c1; ++ch) {
@@ -475,11 +471,9 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
     fetch_a(c0);
     load_x(c0, xa);
   }
-  // side job: one Gram-combine entry per wave, its loads behind the first chunk's
-  if (gsrc != nullptr)
-    gram_combine(gsrc, gparts, gkp, gdst,
-                 ((int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y) * (kT / kWave) + w,
-                 (int64_t)gridDim.x * gridDim.y * (kT / kWave));
+  // side job: a Gram combine, one entry per wave, its loads behind the first chunk's
+  const int64_t gwave = ((int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y) * (kT / kWave) + w;
+  if (gsrc != nullptr) gram_combine(gsrc, gparts, gkp, gdst, gwave, (int64_t)gridDim.x * gridDim.y * (kT / kWave));
   if (c0 < c1) store_a(0);
   int buf = 0;
   for (int64_t ch = c0; ch < c1; ++ch) {
@@ -612,11 +606,9 @@ __global__ __launch_bounds__(kT) void k_xtu_f32s(const float* __restrict__ X, in
     fetch_a(c0);
     load_x(c0, xa);
   }
-  // side job: one Gram-combine entry per wave, its loads behind the first chunk's
-  if (gsrc != nullptr)
-    gram_combine(gsrc, gparts, gkp, gdst,
-                 ((int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y) * (kT / kWave) + w,
-                 (int64_t)gridDim.x * gridDim.y * (kT / kWave));
+  // side job: a Gram combine, one entry per wave, its loads behind the first chunk's
+  const int64_t gwave = ((int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y) * (kT / kWave) + w;
+  if (gsrc != nullptr) gram_combine(gsrc, gparts, gkp, gdst, gwave, (int64_t)gridDim.x * gridDim.y * (kT / kWave));
   if (c0 < c1) store_a(0);
   int buf = 0;
   for (int64_t ch = c0; ch < c1; ++ch) {

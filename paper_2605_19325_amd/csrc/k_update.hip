@@ -88,35 +88,51 @@ __device__ bool check_decide(const DecideArgs& d, int final_check, DevState* st,
   constexpr int NF = 17;
   if (d.due || final_check) {
     double v[NF];
+    // a thread's records of both halves, 4 per half, all loads in flight
+    // together; further batches (more than 4 NT records) follow; combined in
+    // block order
+    double acc[2][kRecChkN];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const double* rc = side == 0 ? d.recU : d.recV;
-      const int nb = side == 0 ? d.nbU : d.nbV;
-      double acc[kRecChkN] = {0.0, 0.0, -INFINITY, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0};
-      // a thread's records in batches of 4 with all loads in flight, combined in block order
-      for (int b0 = threadIdx.x; b0 < nb; b0 += 4 * NT) {
-        double w[4][kRecChkN];
+#pragma unroll
+      for (int f = 0; f < kRecChkN; ++f) acc[side][f] = f == 2 ? -INFINITY : (f == 7 ? INFINITY : 0.0);
+    }
+    const int nbmax = d.nbU > d.nbV ? d.nbU : d.nbV;
+    for (int b0 = threadIdx.x; b0 < nbmax; b0 += 4 * NT) {
+      double w[2][4][kRecChkN];
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const double* rc = side == 0 ? d.recU : d.recV;
+        const int nb = side == 0 ? d.nbU : d.nbV;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int b = b0 + u * NT;
           const double* o = rc + (int64_t)(b < nb ? b : 0) * kRecFields + kRecChk;
 #pragma unroll
-          for (int f = 0; f < kRecChkN; ++f) w[u][f] = o[f];
+          for (int f = 0; f < kRecChkN; ++f) w[side][u][f] = o[f];
         }
+      }
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int nb = side == 0 ? d.nbU : d.nbV;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           if (b0 + u * NT < nb) {
 #pragma unroll
             for (int f = 0; f < kRecChkN; ++f)
-              acc[f] = f == 2 ? fmax(acc[f], w[u][f])
-                              : (f == 7 ? fmin(acc[f], w[u][f]) : acc[f] + w[u][f]);
+              acc[side][f] = f == 2 ? fmax(acc[side][f], w[side][u][f])
+                                    : (f == 7 ? fmin(acc[side][f], w[side][u][f])
+                                              : acc[side][f] + w[side][u][f]);
           }
         }
       }
-#pragma unroll
-      for (int f = 0; f < 8; ++f) v[8 * side + f] = acc[f];
-      if (side == 0) v[16] = acc[8];
     }
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+#pragma unroll
+      for (int f = 0; f < 8; ++f) v[8 * side + f] = acc[side][f];
+    }
+    v[16] = acc[0][8];
     const int kind[NF] = {0, 0, 1, 0, 0, 0, 0, 2, 0, 0, 1, 0, 0, 0, 0, 2, 0};
     double a[NF];
     block_reduce_fields<NT, NF>(v, kind, sh, a);
