@@ -165,7 +165,9 @@ typedef struct {
   int32_t pbcd_max_iter;   /* default 5 */
   int32_t max_iter;        /* outer iterations */
   int32_t check_every;     /* default 1 */
-  int32_t mode;            /* 0 full eNMF; 1 project to the orthant then HALS; 3 stop once feasible */
+  int32_t mode;            /* 0 full eNMF; 1 project to the orthant then HALS; 2 fixed row step
+                              1/||G||_F in the exterior phase (step-size ablation); 3 stop once
+                              feasible (the ablations of the appendix tables and figure 5) */
   int32_t reserved;
 } enmf_iter_opts;
 
@@ -206,7 +208,7 @@ enmf_status enmf_objective_kkt(enmf_ctx* ctx, const enmf_matrix* X, int32_t r, c
  * (tick_budget), so requests that arrive while others run join at the next
  * launch.  A solve's arithmetic does not depend on what else is in flight.
  * Served solves support r <= 32 and r + oversample <= 48, a fixed number of
- * PBCD sweeps (pbcd_eps = 0) and modes 0, 1 and 3.  The request's trace is
+ * PBCD sweeps (pbcd_eps = 0) and modes 0 to 3.  The request's trace is
  * not recorded.
  *
  * Ownership: X, the omega of svd, U_out and V_out are caller-owned device

@@ -22,6 +22,6 @@ from .enmf_ref import (  # noqa: F401
     objective, objective_expanded, relerr, gradients,
     svd_init_exact, svd_init_randomized, fix_signs, balance,
     prox_h, procrustes, rotate, negativity_mass,
-    resolve_steps, push_negatives, pbcd, hals_half, ext_half,
+    resolve_steps, push_negatives, pbcd, fixed_row_step, hals_half, ext_half,
     kkt, iterate, enmf,
 )

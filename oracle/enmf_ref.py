@@ -224,7 +224,7 @@ def push_negatives(W, step):
     return W
 
 
-def pbcd(U, P, G, mask, eps=0.0, max_iter=5):
+def pbcd(U, P, G, mask, eps=0.0, max_iter=5, fixed_step=None):
     """Algorithm 2 (PBCD) with the optimal row steps of eq. d_i.
 
     P = X V and G = V^T V are fixed while V is fixed.  Masked gradient
@@ -234,6 +234,9 @@ def pbcd(U, P, G, mask, eps=0.0, max_iter=5):
     masked entries; unmasked entries are left alone.  The loop stops when
     ||M o grad||_F < eps * ||M o grad_init||_F or after max_iter sweeps.
     Rows are independent (section 3.2), so each sweep updates all rows at once.
+
+    fixed_step: the fixed-step ablation of the appendix tables (one step for
+    every row in place of d_i; see iterate, mode 2).
     """
     U = _f64(U).copy()
     P, G = _f64(P), _f64(G)
@@ -242,9 +245,12 @@ def pbcd(U, P, G, mask, eps=0.0, max_iter=5):
     thr = eps * float(np.linalg.norm(g))
     sweeps = 0
     for _ in range(max_iter):
-        num = np.sum(g * g, axis=1)
-        den = np.einsum("ia,ab,ib->i", g, G, g)
-        d = np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
+        if fixed_step is not None:
+            d = np.full(U.shape[0], float(fixed_step))
+        else:
+            num = np.sum(g * g, axis=1)
+            den = np.einsum("ia,ab,ib->i", g, G, g)
+            d = np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
         U = np.where(mask, np.maximum(0.0, U - d[:, None] * g), U)
         g = M * (U @ G - P)
         sweeps += 1
@@ -253,15 +259,27 @@ def pbcd(U, P, G, mask, eps=0.0, max_iter=5):
     return U, sweeps
 
 
-def ext_half(U, P, G, step, eps=0.0, max_iter=5):
+def fixed_row_step(G):
+    """Step of the fixed-step ablation (the paper gives no value).
+
+    Reading taken: 1 / ||G||_F for the half's Gram G.  Since ||G||_F bounds
+    the largest eigenvalue of G, the Lipschitz constant of the gradient in
+    each row, this projected-gradient step never increases f, and it is at
+    most every row's optimal step d_i (g G g^T <= lambda_max ||g||^2).
+    """
+    nf = float(np.linalg.norm(_f64(G)))
+    return 1.0 / nf if nf > 0 else 0.0
+
+
+def ext_half(U, P, G, step, eps=0.0, max_iter=5, fixed=False):
     """One half of an exterior iteration of Algorithm 3: push, mask, PBCD.
 
     The mask M_{U+} marks nonnegative entries (zero included), computed after
-    the push.
+    the push.  fixed = True takes the fixed row step of fixed_row_step.
     """
     U = push_negatives(U, step)
     mask = U >= 0
-    U, _ = pbcd(U, P, G, mask, eps, max_iter)
+    U, _ = pbcd(U, P, G, mask, eps, max_iter, fixed_row_step(G) if fixed else None)
     return U
 
 
@@ -348,8 +366,9 @@ def iterate(X, U, V, max_iter, ext_iters=10, pbcd_max_iter=5, pbcd_eps=0.0,
     relerr - relerr_svd <= relerr_tol (a negative tolerance disables a test).
 
     mode 0 is the full method; mode 1 clips the rotated factors to the
-    orthant and runs HALS only (the projection ablation); mode 3 stops as soon
-    as the factors are feasible (F-eNMF).
+    orthant and runs HALS only (the projection ablation); mode 2 takes the
+    fixed row step of fixed_row_step in the exterior phase (the step-size
+    ablation); mode 3 stops as soon as the factors are feasible (F-eNMF).
 
     Returns (U, V, report) where report holds the steps, counters, the last
     check and the list of all checks.
@@ -380,9 +399,10 @@ def iterate(X, U, V, max_iter, ext_iters=10, pbcd_max_iter=5, pbcd_eps=0.0,
                 break
         phase = EXT if (U < 0).any() or (V < 0).any() else HALS
         P, G = X @ V, V.T @ V
-        U = ext_half(U, P, G, su, pbcd_eps, pbcd_max_iter) if phase == EXT else hals_half(U, P, G)
+        fixed = mode == 2
+        U = ext_half(U, P, G, su, pbcd_eps, pbcd_max_iter, fixed) if phase == EXT else hals_half(U, P, G)
         Q, H = X.T @ U, U.T @ U
-        V = ext_half(V, Q, H, sv, pbcd_eps, pbcd_max_iter) if phase == EXT else hals_half(V, Q, H)
+        V = ext_half(V, Q, H, sv, pbcd_eps, pbcd_max_iter, fixed) if phase == EXT else hals_half(V, Q, H)
         ext_done += phase == EXT
         k += 1
     report = dict(checks[-1])

@@ -669,7 +669,7 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
   if (o.pbcd_max_iter < 1) o.pbcd_max_iter = 5;
   if (o.check_every < 1) o.check_every = 1;
   if (o.pbcd_eps < 0.0) return fail(c, ENMF_EINVAL, "pbcd_eps must be >= 0");
-  if (o.mode != 0 && o.mode != 1 && o.mode != 3) return fail(c, ENMF_EINVAL, "unsupported mode");
+  if (o.mode < 0 || o.mode > 3) return fail(c, ENMF_EINVAL, "unsupported mode");
   if (trace && trace_cap < 0) return fail(c, ENMF_EINVAL, "bad trace capacity");
   hipStream_t s = c->stream;
   const int kp = row_pad(r);

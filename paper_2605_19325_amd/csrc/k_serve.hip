@@ -393,13 +393,21 @@ __device__ double residual(const XE<XT>* X, int64_t m, int64_t n, int64_t ld, co
 // sm.out the 8 check fields (CheckAcc order) and the negative count of the
 // output rows.
 __device__ void row_pass(float* A, int64_t rows, int r, const float* P, RowSmem& sm, bool update,
-                         bool pre, int phase, double step, int sweeps) {
+                         bool pre, int phase, double step, int sweeps, bool fixed_step) {
   using TM = Team<SKP>;
   constexpr int T = TM::T;
   const int team = threadIdx.x / T, q = threadIdx.x % T, c0 = 8 * q;
   const double* sG = sm.G;
   CheckAcc ck;
   double negc = 0.0;
+  // fixed-step ablation (mode 2): one row step 1/||G||_F in place of d
+  double dfix = -1.0;
+  if (update && phase == kPhaseExt && fixed_step) {
+    double ss = 0.0;
+    for (int e = threadIdx.x; e < SKP * SKP; e += SNT) ss = fma(sG[e], sG[e], ss);
+    ss = block_sum<SNT>(ss, sm.sh);
+    dfix = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+  }
   for (int64_t row0 = 0; row0 < rows; row0 += TM::RB) {
     const int nrow = (int)imin(rows - row0, TM::RB);
     const bool valid = team < nrow;
@@ -481,7 +489,7 @@ __device__ void row_pass(float* A, int64_t rows, int r, const float* P, RowSmem&
         for (int e = 0; e < 8; ++e) den = fma((double)g[e], h[e], den);
         num = team_sum<T>(num);
         den = team_sum<T>(den);
-        const double d = den > 0.0 ? num / den : 0.0;
+        const double d = dfix >= 0.0 ? dfix : (den > 0.0 ? num / den : 0.0);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           if (a[e] >= 0.f) {
@@ -732,7 +740,7 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
     bx_cross<float, float, SKP>(q.U, r, r, q.U, r, r, m, st.H, sm.g);
     xta<XT>(X, m, n, ld, q.U, r, r, q.Z32, r, sm.p);
     load_gram32(st.H, sm.w);
-    row_pass(q.V, n, r, q.Z32, sm.w, false, false, kPhaseHals, 0.0, 0);
+    row_pass(q.V, n, r, q.Z32, sm.w, false, false, kPhaseHals, 0.0, 0, false);
     if (t0) {
       const double d = (double)q.ext_iters - 0.5;
       ctl.step[0] = q.step_u > 0.0 ? q.step_u : fmax(-mnU, 0.0) / d;
@@ -755,7 +763,7 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
     bx_cross<float, float, SKP>(q.V, r, r, q.V, r, r, n, st.G, sm.g);
     xb<XT>(X, m, n, ld, q.V, r, r, q.Y32, r, sm.p);
     load_gram32(st.G, sm.w);
-    row_pass(q.U, m, r, q.Y32, sm.w, false, true, kPhaseHals, 0.0, 0);
+    row_pass(q.U, m, r, q.Y32, sm.w, false, true, kPhaseHals, 0.0, 0, false);
     // check of iteration k (the KKT appendix), same expressions as k_finalize
     double hg = 0.0;
     for (int e = threadIdx.x; e < SKP * SKP; e += SNT) hg = fma(st.H[e], st.G[e], hg);
@@ -806,12 +814,12 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
     if (s_stop) return m * n * (int64_t)r + (m + n) * (int64_t)SKP * SKP;
     const int phase = ctl.iphase;
     // U half: update in place, then H = U^T U and Q = X^T U
-    row_pass(q.U, m, r, q.Y32, sm.w, true, true, phase, ctl.step[0], q.sweeps);
+    row_pass(q.U, m, r, q.Y32, sm.w, true, true, phase, ctl.step[0], q.sweeps, q.mode == 2);
     bx_cross<float, float, SKP>(q.U, r, r, q.U, r, r, m, st.H, sm.g);
     xta<XT>(X, m, n, ld, q.U, r, r, q.Z32, r, sm.p);
     // V half with the new U; KKT partials of V^(k+1)
     load_gram32(st.H, sm.w);
-    row_pass(q.V, n, r, q.Z32, sm.w, true, false, phase, ctl.step[1], q.sweeps);
+    row_pass(q.V, n, r, q.Z32, sm.w, true, false, phase, ctl.step[1], q.sweeps, q.mode == 2);
     if (t0) {
       for (int f = 0; f < 8; ++f) ctl.recV[f] = sm.w.out[f];
       ctl.negsV = sm.w.out[8];

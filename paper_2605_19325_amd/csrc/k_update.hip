@@ -205,7 +205,8 @@ __device__ bool check_decide(const DecideArgs& d, int final_check, DevState* st,
 //   EXT:  (first launch) push negatives by the step (eq. negup); mask of
 //         nonnegative entries; then `sweeps` PBCD sweeps (eqs. pbcdu, d_i):
 //         g = M o (a G - p), d = |g|^2 / (g G g^T) (0 if not positive),
-//         a <- (a - d g)_+ on the mask, unmasked entries unchanged.
+//         a <- (a - d g)_+ on the mask, unmasked entries unchanged.  Mode 2
+//         (the fixed-step ablation) takes d = 1/||G||_F for every row.
 // Flags select the extra work fused into the pass:
 //   kRowHead        phase of this iteration from the negative counts in the
 //                   previous records of both halves (EXT while U or V has a
@@ -354,6 +355,14 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
     }
     have_t = true;
   } else if (update) {
+    // mode 2, the fixed-step ablation: one row step 1/||G||_F in place of d
+    double dfix = -1.0;
+    if (st->mode == 2) {
+      double ss = 0.0;
+      for (int e = threadIdx.x; e < KP * KP; e += TM::NT) ss = fma(sG[e], sG[e], ss);
+      ss = block_sum<TM::NT>(ss, sh);
+      dfix = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+    }
     if (first) {
       const double step = st->step[half];
 #pragma unroll
@@ -385,7 +394,7 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
       for (int e = 0; e < 8; ++e) den = fma((double)g[e], h[e], den);
       num = team_sum<T>(num);
       den = team_sum<T>(den);
-      const double d = den > 0.0 ? num / den : 0.0;
+      const double d = dfix >= 0.0 ? dfix : (den > 0.0 ? num / den : 0.0);
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         if (a[e] >= 0.f) {

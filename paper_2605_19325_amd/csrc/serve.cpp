@@ -317,7 +317,7 @@ enmf_status check_request(enmf_server* s, const enmf_request* q) {
   const enmf_iter_opts& it = q->it;
   if (it.max_iter < 0) return fail_srv(s, ENMF_EINVAL, "max_iter must be >= 0");
   if (it.pbcd_eps != 0.0) return fail_srv(s, ENMF_EINVAL, "served solves use a fixed PBCD sweep count");
-  if (it.mode != 0 && it.mode != 1 && it.mode != 3) return fail_srv(s, ENMF_EINVAL, "unsupported mode");
+  if (it.mode < 0 || it.mode > 3) return fail_srv(s, ENMF_EINVAL, "unsupported mode");
   if (!q->U_out || !q->V_out) return fail_srv(s, ENMF_EINVAL, "null output pointer");
   return ENMF_OK;
 }

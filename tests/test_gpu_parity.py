@@ -124,6 +124,25 @@ def test_iterate_parity_fp32(lib, small, iters):
         assert rep["kkt"] <= 1e-5 and abs(rep["kkt"] - ro["kkt"]) <= 1e-6
 
 
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_iterate_ablation_modes(lib, small, mode):
+    """Mode 1 (project to the orthant, then HALS), mode 2 (fixed row step
+    1/||G||_F in the exterior phase) and mode 3 (stop once feasible) against
+    the oracle run of the same mode."""
+    X, r, om = small
+    say(f"iterate mode {mode} vs the oracle, 60 iterations from the rotated point")
+    U0, V0, rso = _rotated_start(X, r, om)
+    Uo, Vo, ro = O.iterate(X, U0, V0, max_iter=60, relerr_svd=rso, mode=mode)
+    U, V = to_dev(U0), to_dev(V0)
+    rep = lib.iterate(to_dev(X), U, V, max_iter=60, relerr_svd=rso, mode=mode)
+    say(f"  iters {rep['iters']} (oracle {ro['iters']}) ext {rep['ext_iters_done']} "
+        f"|dU|/|U| {rel(host(U), Uo):.2e} |dV|/|V| {rel(host(V), Vo):.2e}")
+    assert rep["iters"] == ro["iters"] and rep["ext_iters_done"] == ro["ext_iters_done"]
+    assert rep["converged"] == int(ro["converged"])
+    assert rel(host(U), Uo) <= 1e-4 and rel(host(V), Vo) <= 1e-4
+    assert float(U.min()) >= 0.0 and float(V.min()) >= 0.0
+
+
 def test_iterate_pbcd_eps_path(lib, small):
     X, r, om = small
     say("iterate parity with the PBCD eps stop (multi-launch sweeps)")

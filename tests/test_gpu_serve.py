@@ -64,6 +64,22 @@ def test_served_fp32_tracks_oracle(server):
     assert abs(res["kkt"] - ro["kkt"]) <= 1e-5
 
 
+@pytest.mark.parametrize("mode", [2, 3])
+def test_served_ablation_modes(server, mode):
+    X, r = inputs.config_small()
+    om = inputs.omega(X.shape[1], r + 10, 7)
+    say(f"served fp32 500x400 r=10, mode {mode}, 60 iterations vs oracle")
+    t, U, V = server.submit(to_dev(X), r, to_dev(om), rot_max_iter=20, rot_tol=0.0, max_iter=60,
+                            mode=mode)
+    res = server.wait(t)
+    Uo, Vo, ro = O.enmf(X, r, om, rot_max_iter=20, rot_tol=0.0, max_iter=60, mode=mode)
+    say(f"  iters {res['iters']} (oracle {ro['iters']}) relerr {res['relerr']:.8e} "
+        f"oracle {ro['relerr']:.8e}")
+    assert res["status"] == 0
+    assert res["iters"] == ro["iters"] and res["ext_iters_done"] == ro["ext_iters_done"]
+    assert rel(host(U), Uo) <= 1e-4 and rel(host(V), Vo) <= 1e-4
+
+
 def test_served_bf16_reaches_oracle_error(lib, server):
     X, r = inputs.config_small()
     om = inputs.omega(X.shape[1], r + 10, 7)

@@ -345,6 +345,75 @@ def test_pbcd_masked_gradient_stop():
     assert np.all(U1[mask] >= 0) and np.array_equal(U1[~mask], U[~mask])
 
 
+# ---------------------------------------------------------------------------
+# Fixed-step ablation (mode 2): the step is 1 / ||G||_F (reading; the paper
+# gives no value)
+# ---------------------------------------------------------------------------
+
+def check_fixed_step(pbcd, fixed_row_step):
+    """Pins of the fixed-step exterior update, independent of its code:
+    (a) r = 1: 1/||G||_F is the optimal step 1/G_11, so the update equals the
+        optimal-step one;
+    (b) the fixed step is at most every row's optimal step, since
+        g G g^T <= lambda_max(G) |g|^2 <= ||G||_F |g|^2;
+    (c) the masked projected-gradient step with step <= 1/lambda_max never
+        increases f: checked against f evaluated literally over 6 sweeps."""
+    rng = np.random.default_rng(21)
+    X = rng.random((30, 20))
+    U1 = rng.standard_normal((30, 1))
+    V1 = rng.random((20, 1))
+    m1 = U1 >= 0
+    P1, G1 = X @ V1, V1.T @ V1
+    a, _ = pbcd(U1, P1, G1, m1, 0.0, 3, fixed_row_step(G1))
+    b, _ = O.pbcd(U1, P1, G1, m1, 0.0, 3)
+    if not np.allclose(a, b, rtol=1e-12, atol=1e-14):
+        return False
+    U = rng.standard_normal((30, 4))
+    V = rng.random((20, 4))
+    mask = U >= 0
+    P, G = X @ V, V.T @ V
+    g = mask * (U @ G - P)
+    den = np.einsum("ia,ab,ib->i", g, G, g)
+    live = den > 0                      # rows with a nonzero masked gradient
+    dstar = np.sum(g[live] * g[live], 1) / den[live]
+    step = fixed_row_step(G)
+    if not (step > 0 and live.sum() >= 20 and np.all(step <= dstar * (1 + 1e-12))):
+        return False
+    f_prev = float(np.sum((X - U @ V.T) ** 2))
+    W = U.copy()
+    for _ in range(6):
+        W, _ = pbcd(W, P, G, mask, 0.0, 1, step)
+        f = float(np.sum((X - W @ V.T) ** 2))
+        if f > f_prev * (1 + 1e-13):
+            return False
+        f_prev = f
+    return np.array_equal(W[~mask], U[~mask]) and np.all(W[mask] >= 0)
+
+
+def test_fixed_step_pins():
+    assert check_fixed_step(O.pbcd, O.fixed_row_step)
+
+
+def test_fixed_step_catches_planted_mistake():
+    # a step from the trace of G instead of its norm stays safe but breaks (a);
+    # twice the step breaks (b)
+    assert not check_fixed_step(O.pbcd, lambda G: 1.0 / max(np.trace(G), 1e-300) / 2.0)
+    assert not check_fixed_step(O.pbcd, lambda G: 2.0 * O.fixed_row_step(G))
+
+
+def test_fixed_step_mode_reaches_feasibility():
+    X, r = I.config_small()
+    om = I.omega(400, r + 10, 7)
+    Us, Vs, _, rs = O.svd_init_randomized(X, r, om)
+    U0, V0, *_ = O.rotate(Us, Vs, max_iter=20, tol=0)
+    U, V, rep = O.iterate(X, U0, V0, max_iter=40, mode=2, relerr_svd=rs)
+    U0b, V0b, rep0 = O.iterate(X, U0, V0, max_iter=40, mode=0, relerr_svd=rs)
+    assert rep["ext_iters_done"] == rep0["ext_iters_done"] == 10
+    assert U.min() >= 0 and V.min() >= 0
+    # a different exterior trajectory: the factors differ from the optimal-step run
+    assert np.linalg.norm(U - U0b) > 1e-6 * np.linalg.norm(U0b)
+
+
 def test_pin9_exterior_phase_length_and_monotone_negatives():
     X, r = I.config_small()
     om = I.omega(400, r + 10, 7)
