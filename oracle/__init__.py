@@ -25,3 +25,7 @@ from .enmf_ref import (  # noqa: F401
     resolve_steps, push_negatives, pbcd, fixed_row_step, hals_half, ext_half,
     kkt, iterate, enmf,
 )
+from .enmc_ref import (  # noqa: F401
+    masked_objective, masked_gradients, masked_relerr, softimpute_als, enmc_init,
+    masked_pbcd, masked_kkt, enmc_iterate, enmc,
+)
