@@ -199,6 +199,53 @@ typedef struct {
 enmf_status enmf_objective_kkt(enmf_ctx* ctx, const enmf_matrix* X, int32_t r, const float* U,
                                const float* V, double relerr_svd, enmf_kkt* out_host);
 
+/* Exterior nonnegative matrix completion (eNMC; the appendix "Exterior NMC
+ * algorithm").  fhat(U, V) = 1/2 ||M o (X - U V^T)||_F^2 over the entries
+ * marked observed in M, with grad_U = (M o (U V^T - X)) V and
+ * grad_V = (M o (U V^T - X))^T U.
+ *
+ * X: float32 (ENMF_F32 only).  The mask is one bit per entry, row-major:
+ * bit (j % 32) of word bits[i * ld_words + j / 32] is 1 when X[i][j] is
+ * observed; ld_words >= ceil(n / 32).  Unobserved entries of X are never
+ * read as data (they may hold anything, NaN included). */
+typedef struct {
+  const uint32_t* bits;    /* device */
+  int64_t ld_words;
+} enmf_mask;
+
+/* Line 2 of Algorithm eNMC: the rank-r randomized SVD (as enmf_svd_init) of
+ * the zero-filled M o X, then als_iters softImpute-ALS iterations at
+ * lambda = 0: U <- U + R_U (V^T V)^-1 with R_U = (M o (X - U V^T)) V, then the
+ * same for V with the new U (an EM step on the imputed matrix).  U (m x r) and
+ * V (n x r) are caller-owned device outputs.  fhat_host (optional) receives
+ * fhat at the result.  Uses a workspace copy of M o X (m x n float32).
+ * ENMF_ENUMERIC if a Gram is singular. */
+enmf_status enmf_enmc_init(enmf_ctx* ctx, const enmf_matrix* X, const enmf_mask* M, int32_t r,
+                           const enmf_svd_opts* svd, int32_t als_iters, float* U, float* V,
+                           double* fhat_host);
+
+/* The masked gradients of fhat at (U, V): gU (m x r) = (M o (U V^T - X)) V
+ * and gV (n x r) = (M o (U V^T - X))^T U, float32 accumulate in a fixed order
+ * (either output may be NULL), and fhat (host, optional).  Synchronises. */
+enmf_status enmf_enmc_grad(enmf_ctx* ctx, const enmf_matrix* X, const enmf_mask* M, int32_t r,
+                           const float* U, const float* V, float* gU, float* gV, double* fhat_host);
+
+/* The loop of Algorithm eNMC from rotated factors (enmf_rotate): every
+ * iteration pushes the negative entries of U by the fixed step (eq. negup;
+ * step_u, or resolved as in enmf_iterate), then runs pbcd_max_iter masked
+ * PBCD sweeps on U: g = M_U+ o grad_U, row step
+ * d_i = |g_i|^2 / sum over observed j of (g_i . v_j)^2, U_i <- (U_i - d_i g_i)_+
+ * on M_U+; then the same for V with the new U.  There is no HALS stage.
+ * Every iteration is checked first (f, the error over the observed entries
+ * |M o (X - U V^T)| / |M o X|, and the normalised KKT residual of enmf.h with
+ * the masked gradients); the loop stops when U, V >= 0 and kkt <= kkt_tol, or
+ * after max_iter iterations.  Uses opts->max_iter, ext_iters, pbcd_max_iter,
+ * kkt_tol, step_u, step_v; the other fields must be zero.  U and V are
+ * updated in place.  Synchronises once per iteration. */
+enmf_status enmf_enmc_iterate(enmf_ctx* ctx, const enmf_matrix* X, const enmf_mask* M, int32_t r,
+                              float* U, float* V, const enmf_iter_opts* opts,
+                              enmf_iter_report* report_host);
+
 /* ---- serving (many solves of uneven shape in flight together) ----
  * A server runs Algorithm 3 end to end (randomized SVD init, ADMM rotation,
  * exterior phase and HALS with the KKT check, final objective) for every

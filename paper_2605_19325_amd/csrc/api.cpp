@@ -17,7 +17,8 @@ namespace {
 enum Slot {
   S_BP, S_AP, S_SPLIT, S_P, S_Q, S_GPART, S_G, S_H, S_RUPART, S_XPART, S_U2, S_GPU, S_GPV, S_STAT, S_UD, S_RES,
   S_Y, S_QM64, S_QM32, S_Z, S_QN64, S_QN32, S_TMP64, S_T, S_C, S_COLP, S_COLS, S_SIG, S_TU, S_TV,
-  S_W64, S_YA, S_ZA, S_BA, S_R, S_NEGP, S_WSQ, S_MPART, N_SLOTS
+  S_W64, S_YA, S_ZA, S_BA, S_R, S_NEGP, S_WSQ, S_MPART,
+  S_EX, S_ERU, S_ERV, S_EE, S_ERSS, S_ECU, S_ECV, S_EG, S_EGI, S_EST, S_ESTAT, N_SLOTS
 };
 
 constexpr int kTimingPairs = 64;   // sampled launches per kind and iterate call
@@ -946,6 +947,243 @@ enmf_status enmf_time_products(enmf_ctx* c, const enmf_matrix* X, int32_t k, int
   (void)hipEventDestroy(e2);
   if (xv_ms) *xv_ms = a / reps;
   if (xtu_ms) *xtu_ms = b / reps;
+  return ENMF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Exterior nonnegative matrix completion (the appendix "Exterior NMC
+// algorithm"): host sequencing of the masked kernels of k_enmc.hip.
+// ---------------------------------------------------------------------------
+namespace {
+
+enmf_status check_mask(enmf_ctx* c, const enmf_matrix* X, const enmf_mask* M) {
+  if (!M || !M->bits) return fail(c, ENMF_EINVAL, "mask is null");
+  if (M->ld_words < (X->n + 31) / 32) return fail(c, ENMF_EINVAL, "mask rows shorter than ceil(n/32) words");
+  if (reinterpret_cast<uintptr_t>(M->bits) % 4 != 0) return fail(c, ENMF_EINVAL, "mask not 4-byte aligned");
+  if (X->dtype != ENMF_F32) return fail(c, ENMF_EINVAL, "eNMC takes float32 X");
+  return ENMF_OK;
+}
+
+// Buffers of the masked kernels at (m, n, r).
+struct EnmcBufs {
+  EnmcPlan pu, pv;
+  float *RU, *RV;
+  double *E, *rss, *cu, *cv, *G, *Gi;
+  int* bad;
+  EnmcState* st;
+  int ncu, ncv;
+};
+
+enmf_status enmc_bufs(enmf_ctx* c, int64_t m, int64_t n, int r, EnmcBufs& b) {
+  b.pu = enmc_plan(m, n, 0);
+  b.pv = enmc_plan(m, n, 1);
+  WS(RU, float, S_ERU, (int64_t)b.pu.splits * m * r * 4);
+  WS(RV, float, S_ERV, (int64_t)b.pv.splits * n * r * 4);
+  const int64_t ne = std::max((int64_t)b.pu.splits * m, (int64_t)b.pv.splits * n);
+  WS(E, double, S_EE, ne * 8);
+  WS(rss, double, S_ERSS, b.pu.out_tiles * b.pu.splits * 8);
+  b.ncu = enmc_check_blocks(m * r);
+  b.ncv = enmc_check_blocks(n * r);
+  WS(cu, double, S_ECU, (int64_t)b.ncu * 5 * 8);
+  WS(cv, double, S_ECV, (int64_t)b.ncv * 5 * 8);
+  WS(G, double, S_EG, (int64_t)r * r * 8);
+  WS(Gi, double, S_EGI, (int64_t)r * r * 8 + 256);
+  WS(st, EnmcState, S_EST, sizeof(EnmcState));
+  b.RU = RU; b.RV = RV; b.E = E; b.rss = rss; b.cu = cu; b.cv = cv; b.G = G; b.Gi = Gi;
+  b.bad = reinterpret_cast<int*>(reinterpret_cast<char*>(Gi) + (int64_t)r * r * 8);
+  b.st = st;
+  return ENMF_OK;
+}
+
+// Ginv of the Gram of A (rows x r); sets *bad on a singular Gram.
+enmf_status gram_inverse(enmf_ctx* c, const float* A, int64_t rows, int r, EnmcBufs& b) {
+  TRY(do_gram(c, A, 0, r, rows, r, r, b.G));
+  CK(launch_spd_inverse(b.G, r, r, b.Gi, b.bad, c->stream));
+  return ENMF_OK;
+}
+
+// fhat = 1/2 sum of the masked squared residuals at (U, V).
+enmf_status enmc_objective(enmf_ctx* c, const enmf_matrix* X, const enmf_mask* M, int r,
+                           const float* U, const float* V, EnmcBufs& b, double* f) {
+  CK(launch_mres(0, static_cast<const float*>(X->data), X->m, X->n, X->ld, M->bits, M->ld_words, U, V, r,
+                 b.RU, b.rss, c->stream));
+  const int64_t nr = b.pu.out_tiles * b.pu.splits;
+  std::vector<double> h(nr);
+  CK(hipMemcpyAsync(h.data(), b.rss, nr * 8, hipMemcpyDeviceToHost, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  double sum = 0.0;
+  for (double v : h) sum += v;
+  *f = 0.5 * sum;
+  return ENMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+enmf_status enmf_enmc_init(enmf_ctx* c, const enmf_matrix* X, const enmf_mask* M, int32_t r,
+                           const enmf_svd_opts* svd, int32_t als_iters, float* U, float* V,
+                           double* fhat_host) {
+  TRY(check_ctx(c));
+  TRY(check_matrix(c, X));
+  TRY(check_mask(c, X, M));
+  if (!U || !V || !svd) return fail(c, ENMF_EINVAL, "null pointer");
+  const int64_t m = X->m, n = X->n;
+  if (r < 1 || r > ENMF_MAX_RANK || r > m || r > n) return fail(c, ENMF_EINVAL, "r out of range");
+  if (als_iters < 0) return fail(c, ENMF_EINVAL, "als_iters must be >= 0");
+  hipStream_t s = c->stream;
+  const float* Xf = static_cast<const float*>(X->data);
+  WS(X0, float, S_EX, m * n * 4);
+  CK(launch_mask_x(Xf, m, n, X->ld, M->bits, M->ld_words, X0, s));
+  enmf_matrix Xz{X0, m, n, n, ENMF_F32, 0};
+  std::vector<double> sg(r);
+  double rsvd = 0.0;
+  TRY(enmf_svd_init(c, &Xz, r, svd, U, V, sg.data(), &rsvd));
+  EnmcBufs b;
+  TRY(enmc_bufs(c, m, n, r, b));
+  CK(hipMemsetAsync(b.bad, 0, 4, s));
+  for (int it = 0; it < als_iters; ++it) {
+    // U <- U + R_U (V^T V)^-1, then V <- V + R_V (U^T U)^-1 with the new U
+    TRY(gram_inverse(c, V, n, r, b));
+    CK(launch_mres(0, Xf, m, n, X->ld, M->bits, M->ld_words, U, V, r, b.RU, nullptr, s));
+    CK(launch_als_step(U, m, r, b.RU, b.pu.splits, b.Gi, r, s));
+    TRY(gram_inverse(c, U, m, r, b));
+    CK(launch_mres(1, Xf, m, n, X->ld, M->bits, M->ld_words, U, V, r, b.RV, nullptr, s));
+    CK(launch_als_step(V, n, r, b.RV, b.pv.splits, b.Gi, r, s));
+  }
+  int bad = 0;
+  CK(hipMemcpyAsync(&bad, b.bad, 4, hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  if (bad) return fail(c, ENMF_ENUMERIC, "singular Gram in softImpute-ALS");
+  if (fhat_host) TRY(enmc_objective(c, X, M, r, U, V, b, fhat_host));
+  return ENMF_OK;
+}
+
+enmf_status enmf_enmc_grad(enmf_ctx* c, const enmf_matrix* X, const enmf_mask* M, int32_t r,
+                           const float* U, const float* V, float* gU, float* gV, double* fhat_host) {
+  TRY(check_ctx(c));
+  TRY(check_matrix(c, X));
+  TRY(check_mask(c, X, M));
+  if (!U || !V) return fail(c, ENMF_EINVAL, "null pointer");
+  const int64_t m = X->m, n = X->n;
+  if (r < 1 || r > ENMF_MAX_RANK || r > m || r > n) return fail(c, ENMF_EINVAL, "r out of range");
+  hipStream_t s = c->stream;
+  const float* Xf = static_cast<const float*>(X->data);
+  EnmcBufs b;
+  TRY(enmc_bufs(c, m, n, r, b));
+  CK(launch_mres(0, Xf, m, n, X->ld, M->bits, M->ld_words, U, V, r, b.RU, b.rss, s));
+  if (gU) CK(launch_sum_neg(b.RU, b.pu.splits, m * r, gU, s));
+  if (gV) {
+    CK(launch_mres(1, Xf, m, n, X->ld, M->bits, M->ld_words, U, V, r, b.RV, nullptr, s));
+    CK(launch_sum_neg(b.RV, b.pv.splits, n * r, gV, s));
+  }
+  const int64_t nr = b.pu.out_tiles * b.pu.splits;
+  std::vector<double> h(nr);
+  CK(hipMemcpyAsync(h.data(), b.rss, nr * 8, hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  double sum = 0.0;
+  for (double v : h) sum += v;
+  if (fhat_host) *fhat_host = 0.5 * sum;
+  return ENMF_OK;
+}
+
+enmf_status enmf_enmc_iterate(enmf_ctx* c, const enmf_matrix* X, const enmf_mask* M, int32_t r,
+                              float* U, float* V, const enmf_iter_opts* opts,
+                              enmf_iter_report* rep) {
+  TRY(check_ctx(c));
+  TRY(check_matrix(c, X));
+  TRY(check_mask(c, X, M));
+  if (!U || !V || !opts) return fail(c, ENMF_EINVAL, "null pointer");
+  const int64_t m = X->m, n = X->n;
+  if (r < 1 || r > ENMF_MAX_RANK || r > m || r > n) return fail(c, ENMF_EINVAL, "r out of range");
+  enmf_iter_opts o = *opts;
+  if (o.max_iter < 0) return fail(c, ENMF_EINVAL, "max_iter must be >= 0");
+  if (o.pbcd_eps != 0.0 || o.mode != 0 || o.relerr_tol > 0.0)
+    return fail(c, ENMF_EINVAL, "eNMC takes a fixed sweep count, mode 0 and no relerr stop");
+  if (o.ext_iters < 1) o.ext_iters = 10;
+  if (o.pbcd_max_iter < 1) o.pbcd_max_iter = 5;
+  hipStream_t s = c->stream;
+  const float* Xf = static_cast<const float*>(X->data);
+  const uint32_t* bits = M->bits;
+  const int64_t ldm = M->ld_words;
+  EnmcBufs b;
+  TRY(enmc_bufs(c, m, n, r, b));
+
+  // ||M o X||^2 and the push sizes (as in enmf_iterate)
+  WS(X0, float, S_EX, m * n * 4);
+  CK(launch_mask_x(Xf, m, n, X->ld, bits, ldm, X0, s));
+  enmf_matrix Xz{X0, m, n, n, ENMF_F32, 0};
+  double nx2 = 0.0;
+  TRY(read_sumsq_x(c, &Xz, &nx2));
+  const int fbU = factor_blocks(m * r), fbV = factor_blocks(n * r);
+  WS(stat, double, S_ESTAT, 4 * (int64_t)(fbU + fbV) * 8);
+  CK(launch_factor_stats(U, m * r, r, stat, 0, fbU, s));
+  CK(launch_factor_stats(V, n * r, r, stat, fbU, fbV, s));
+  std::vector<double> hs(4 * (fbU + fbV));
+  CK(hipMemcpyAsync(hs.data(), stat, hs.size() * 8, hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  double mnU = INFINITY, mnV = INFINITY;
+  for (int q = 0; q < fbU; ++q) mnU = std::min(mnU, hs[4 * q + 1]);
+  for (int q = fbU; q < fbU + fbV; ++q) mnV = std::min(mnV, hs[4 * q + 1]);
+  const double dd = (double)o.ext_iters - 0.5;
+  const double su = o.step_u > 0.0 ? o.step_u : std::max(-mnU, 0.0) / dd;
+  const double sv = o.step_v > 0.0 ? o.step_v : std::max(-mnV, 0.0) / dd;
+
+  EnmcState h;
+  std::memset(&h, 0, sizeof(h));
+  h.nx2 = nx2;
+  h.kkt_tol = o.kkt_tol;
+  CK(hipMemcpyAsync(b.st, &h, sizeof(h), hipMemcpyHostToDevice, s));
+  int ext_done = 0;
+  const int64_t nrss = b.pu.out_tiles * b.pu.splits;
+  for (int k = 0; k <= o.max_iter; ++k) {
+    // check of (U^k, V^k)
+    CK(launch_mres(0, Xf, m, n, X->ld, bits, ldm, U, V, r, b.RU, b.rss, s));
+    CK(launch_mres(1, Xf, m, n, X->ld, bits, ldm, U, V, r, b.RV, nullptr, s));
+    CK(launch_enmc_check(U, m, r, b.RU, b.pu.splits, b.cu, s));
+    CK(launch_enmc_check(V, n, r, b.RV, b.pv.splits, b.cv, s));
+    CK(launch_enmc_finalize(b.rss, (int)nrss, b.cu, b.ncu, b.cv, b.ncv, k, k == o.max_iter ? 1 : 0,
+                            b.st, s));
+    CK(hipMemcpyAsync(&h, b.st, sizeof(h), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    if (h.stop) break;
+    if (h.negs > 0.0) ext_done += 1;
+    // U half: push, then masked PBCD sweeps (the check's R_U serves the
+    // first sweep when the push changed nothing)
+    if (h.negs_u > 0.0) CK(launch_enmc_push(U, m * r, su, nullptr, s));
+    for (int t = 0; t < o.pbcd_max_iter; ++t) {
+      if (t > 0 || h.negs_u > 0.0)
+        CK(launch_mres(0, Xf, m, n, X->ld, bits, ldm, U, V, r, b.RU, nullptr, s));
+      CK(launch_menergy(0, m, n, bits, ldm, U, V, r, b.RU, b.pu.splits, b.E, s));
+      CK(launch_enmc_step(U, m, r, b.RU, b.pu.splits, b.E, b.pu.splits, -1.0, s));
+    }
+    // V half with the new U
+    if (h.negs - h.negs_u > 0.0) CK(launch_enmc_push(V, n * r, sv, nullptr, s));
+    for (int t = 0; t < o.pbcd_max_iter; ++t) {
+      CK(launch_mres(1, Xf, m, n, X->ld, bits, ldm, U, V, r, b.RV, nullptr, s));
+      CK(launch_menergy(1, m, n, bits, ldm, U, V, r, b.RV, b.pv.splits, b.E, s));
+      CK(launch_enmc_step(V, n, r, b.RV, b.pv.splits, b.E, b.pv.splits, -1.0, s));
+    }
+  }
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->iters = h.iters;
+    rep->ext_iters_done = ext_done;
+    rep->phase = h.negs > 0.0 ? kPhaseExt : kPhaseHals;
+    rep->converged = h.converged;
+    rep->step_u = su;
+    rep->step_v = sv;
+    rep->f = h.f;
+    rep->relerr = h.relerr;
+    rep->re_paper = NAN;
+    rep->kkt = h.kkt;
+    rep->kkt_feas = h.kkt_feas;
+    rep->kkt_pg_u = h.kkt_pg_u;
+    rep->kkt_pg_v = h.kkt_pg_v;
+  }
+  if (h.numeric_error) return fail(c, ENMF_ENUMERIC, "non-finite objective or KKT residual");
   return ENMF_OK;
 }
 

@@ -207,4 +207,44 @@ hipError_t launch_pbcd_decide(const double* rec, int nparts, int half, int first
 hipError_t launch_finalize(const DecideArgs& d, int final_check, DevState* st, hipStream_t s);
 hipError_t launch_clip(float* A, int64_t count, hipStream_t s);
 
+// ---- exterior nonnegative matrix completion (k_enmc.hip) ----
+// State of an eNMC solve on the device (scalars of the last check).
+struct EnmcState {
+  double nx2, f, relerr, kkt, kkt_feas, kkt_pg_u, kkt_pg_v, min_w, negs, negs_u, kkt_tol;
+  int32_t iters, stop, converged, numeric_error;
+};
+// Grid of a masked product: out_tiles 64-row (column) tiles x `splits`
+// contraction ranges of tiles_per_split tiles.
+struct EnmcPlan {
+  int64_t out_tiles = 0;
+  int splits = 1, tiles_per_split = 1;
+};
+EnmcPlan enmc_plan(int64_t m, int64_t n, int cols);
+// cols = 0: out = (M o (X - U V^T)) V as plan.splits partials of m x r;
+// cols = 1: out = (M o (X - U V^T))^T U as partials of n x r.  rss: one
+// double per block (out_tiles x splits), or null.
+hipError_t launch_mres(int cols, const float* X, int64_t m, int64_t n, int64_t ld,
+                       const uint32_t* bits, int64_t ldm, const float* U, const float* V, int r,
+                       float* out, double* rss, hipStream_t s);
+// Masked row energies of the PBCD step (partials of m or n doubles).
+hipError_t launch_menergy(int cols, int64_t m, int64_t n, const uint32_t* bits, int64_t ldm,
+                          const float* U, const float* V, int r, const float* Rp, int nsplit,
+                          double* out, hipStream_t s);
+int enmc_push_blocks(int64_t count);
+hipError_t launch_enmc_push(float* A, int64_t count, double step, double* negs, hipStream_t s);
+hipError_t launch_enmc_step(float* A, int64_t rows, int r, const float* Rp, int nsplit,
+                            const double* Ep, int esplit, double dfix, hipStream_t s);
+hipError_t launch_als_step(float* A, int64_t rows, int r, const float* Rp, int nsplit,
+                           const double* Ginv, int kp, hipStream_t s);
+hipError_t launch_spd_inverse(const double* G, int r, int kp, double* Ginv, int* bad, hipStream_t s);
+hipError_t launch_mask_x(const float* X, int64_t m, int64_t n, int64_t ld, const uint32_t* bits,
+                         int64_t ldm, float* out, hipStream_t s);
+hipError_t launch_sum_neg(const float* p, int nsplit, int64_t stride, float* out, hipStream_t s);
+int enmc_check_blocks(int64_t count);
+hipError_t launch_enmc_check(const float* A, int64_t rows, int r, const float* Rp, int nsplit,
+                             double* part, hipStream_t s);
+hipError_t launch_enmc_finalize(const double* rss, int nrss, const double* cu, int ncu,
+                                const double* cv, int ncv, int k, int final_check, EnmcState* st,
+                                hipStream_t s);
+
 }  // namespace enmf

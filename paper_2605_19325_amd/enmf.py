@@ -10,6 +10,7 @@ import ctypes
 import os
 from ctypes import POINTER, Structure, byref, c_char_p, c_double, c_int32, c_int64, c_void_p
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -40,6 +41,10 @@ class SvdOpts(Structure):
 class RotateOpts(Structure):
     _fields_ = [("rho0", c_double), ("tol", c_double), ("max_iter", c_int32),
                 ("check_every", c_int32)]
+
+
+class MaskArg(Structure):
+    _fields_ = [("bits", c_void_p), ("ld_words", c_int64)]
 
 
 class IterOpts(Structure):
@@ -98,6 +103,12 @@ SIGNATURES = [
                                POINTER(IterOpts), POINTER(IterReport), c_void_p, c_int32]),
     ("enmf_objective_kkt", c_int32, [c_void_p, POINTER(Matrix), c_int32, c_void_p, c_void_p,
                                      c_double, POINTER(Kkt)]),
+    ("enmf_enmc_init", c_int32, [c_void_p, POINTER(Matrix), POINTER(MaskArg), c_int32,
+                                 POINTER(SvdOpts), c_int32, c_void_p, c_void_p, POINTER(c_double)]),
+    ("enmf_enmc_grad", c_int32, [c_void_p, POINTER(Matrix), POINTER(MaskArg), c_int32, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
+    ("enmf_enmc_iterate", c_int32, [c_void_p, POINTER(Matrix), POINTER(MaskArg), c_int32, c_void_p,
+                                    c_void_p, POINTER(IterOpts), POINTER(IterReport)]),
     ("enmf_time_products", c_int32, [c_void_p, POINTER(Matrix), c_int32, c_int32,
                                      POINTER(c_double), POINTER(c_double)]),
     ("enmf_kernel_timing", c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double),
@@ -152,6 +163,27 @@ def matrix(X):
     if X.dtype not in _DTYPES:
         raise ValueError("X dtype must be float32, bfloat16 or float16")
     return Matrix(X.data_ptr(), X.shape[0], X.shape[1], X.stride(0), _DTYPES[X.dtype], 0)
+
+
+def pack_mask(observed):
+    """Bit mask of the observed entries in the layout of enmf_mask: bit j % 32
+    of word [i][j / 32] (numpy bool array in, int32 numpy array of shape
+    (m, ceil(n / 32)) out).  Layout only: no arithmetic of the method."""
+    obs = np.asarray(observed, dtype=bool)
+    m, n = obs.shape
+    words = (n + 31) // 32
+    pad = np.zeros((m, words * 32), dtype=bool)
+    pad[:, :n] = obs
+    packed = np.packbits(pad, axis=1, bitorder="little")
+    return np.ascontiguousarray(packed).view("<u4").view(np.int32).reshape(m, words)
+
+
+def _mask(mask_words, m, n):
+    words = (n + 31) // 32
+    if (mask_words.dtype != torch.int32 or mask_words.dim() != 2 or mask_words.shape[0] != m or
+            mask_words.shape[1] < words or mask_words.stride(1) != 1 or not mask_words.is_cuda):
+        raise ValueError("mask must be an int32 device tensor of shape (m, >= ceil(n/32))")
+    return MaskArg(mask_words.data_ptr(), mask_words.stride(0))
 
 
 class Context:
@@ -232,6 +264,52 @@ class Context:
         o = SvdOpts(omega.data_ptr(), oversample, power_iters)
         self._call(self._lib.enmf_svd_init, byref(M), r, byref(o), _ptr(U), _ptr(V), sig, byref(rel))
         return U, V, [sig[i] for i in range(r)], rel.value
+
+    def enmc_init(self, X, mask_words, r, omega, oversample=10, power_iters=2, als_iters=50):
+        """eNMC start: randomized SVD of the zero-filled X, then softImpute-ALS.
+        mask_words: int32 device tensor (m x ceil(n/32)) from pack_mask."""
+        M = matrix(X)
+        m, n = X.shape
+        mk = _mask(mask_words, m, n)
+        _factor(omega, n, r + oversample, "omega")
+        U = torch.empty((m, r), dtype=torch.float32, device=X.device)
+        V = torch.empty((n, r), dtype=torch.float32, device=X.device)
+        f = c_double()
+        o = SvdOpts(omega.data_ptr(), oversample, power_iters)
+        self._call(self._lib.enmf_enmc_init, byref(M), byref(mk), r, byref(o), als_iters, _ptr(U),
+                   _ptr(V), byref(f))
+        return U, V, f.value
+
+    def enmc_grad(self, X, mask_words, U, V):
+        """Masked gradients (gU, gV) and fhat at (U, V)."""
+        M = matrix(X)
+        m, n = X.shape
+        mk = _mask(mask_words, m, n)
+        r = U.shape[1]
+        _factor(U, m, r, "U")
+        _factor(V, n, r, "V")
+        gU = torch.empty((m, r), dtype=torch.float32, device=X.device)
+        gV = torch.empty((n, r), dtype=torch.float32, device=X.device)
+        f = c_double()
+        self._call(self._lib.enmf_enmc_grad, byref(M), byref(mk), r, _ptr(U), _ptr(V), _ptr(gU),
+                   _ptr(gV), byref(f))
+        return gU, gV, f.value
+
+    def enmc_iterate(self, X, mask_words, U, V, max_iter, ext_iters=10, pbcd_max_iter=5,
+                     kkt_tol=-1.0, step_u=0.0, step_v=0.0):
+        """The eNMC loop (push, masked PBCD) in place on U and V."""
+        M = matrix(X)
+        m, n = X.shape
+        mk = _mask(mask_words, m, n)
+        r = U.shape[1]
+        _factor(U, m, r, "U")
+        _factor(V, n, r, "V")
+        o = IterOpts(step_u, step_v, 0.0, -1.0, kkt_tol, 0.0, ext_iters, pbcd_max_iter, max_iter,
+                     1, 0, 0)
+        rep = IterReport()
+        self._call(self._lib.enmf_enmc_iterate, byref(M), byref(mk), r, _ptr(U), _ptr(V), byref(o),
+                   byref(rep))
+        return {name: getattr(rep, name) for name, _ in IterReport._fields_}
 
     def rotate(self, U, V, rho0=1.0, max_iter=100, tol=1e-10, check_every=10):
         m, r = U.shape

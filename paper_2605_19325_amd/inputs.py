@@ -218,3 +218,17 @@ def haar_orthogonal(r, seed, reflect=False):
     if (np.linalg.det(Q) < 0) != reflect:
         Q[:, 0] = -Q[:, 0]
     return Q
+
+
+def completion(m, n, r, density, seed, noise=0.01):
+    """Matrix-completion workload (eNMC, the recommendation-shaped stand-in for
+    rating data): X = U* V*^T + U[0, noise] with U*, V* ~ |N(0, 1)| (each
+    entry zeroed with probability 0.5), observed entries drawn independently
+    with probability `density`.  Returns (X float32 with NaN at the
+    unobserved entries, observed mask bool)."""
+    X, _, _ = lowrank_plus_noise(m, n, r, seed, noise=noise)
+    rng = np.random.default_rng(seed + 7)
+    obs = rng.random((m, n)) < density
+    X = X.astype(np.float32)
+    X[~obs] = np.nan
+    return X, obs
