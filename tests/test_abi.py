@@ -25,7 +25,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for want in ("enmf_svd_init", "enmf_rotate", "enmf_iterate", "enmf_objective_kkt",
-                 "enmf_xv", "enmf_xtu", "enmf_gram", "enmf_convert", "enmf_create"):
+                 "enmf_xv", "enmf_xtu", "enmf_gram", "enmf_convert", "enmf_create",
+                 "enmf_serve_start", "enmf_enmc_init", "enmf_enmc_grad", "enmf_enmc_iterate"):
         assert want in names
 
 
@@ -49,7 +50,8 @@ def test_status_strings():
 STRUCTS = [("enmf_matrix", enmf.Matrix), ("enmf_svd_opts", enmf.SvdOpts),
            ("enmf_rotate_opts", enmf.RotateOpts), ("enmf_iter_opts", enmf.IterOpts),
            ("enmf_iter_report", enmf.IterReport), ("enmf_kkt", enmf.Kkt),
-           ("enmf_serve_opts", enmf.ServeOpts), ("enmf_request", enmf.Request)]
+           ("enmf_serve_opts", enmf.ServeOpts), ("enmf_request", enmf.Request),
+           ("enmf_mask", enmf.MaskArg)]
 
 
 def test_struct_layouts_match_header(tmp_path):
