@@ -130,12 +130,62 @@ __global__ void k_apply_small(const TA* __restrict__ A, int64_t lda, int64_t row
   }
 }
 
-// T = E diag(lambda^-1/2) (zero for lambda <= tau * lambda_max): Q = A T has
-// orthonormal columns when A^T A = Gm (range finder orthonormalisation).
+// T with Q = A T orthonormal when A^T A = Gm (range finder orthonormalisation;
+// only the span of Q is used).  Well-conditioned Gm: the Cholesky factor
+// Gm = L L^T and T = L^-T (every pivot above 1e-10 of the largest diagonal
+// entry).  Otherwise T = E diag(lambda^-1/2) from the eigenpairs (Jacobi),
+// zero for lambda <= tau * lambda_max, which drops dependent directions.
 __global__ __launch_bounds__(kT) void k_orth_factor(const double* __restrict__ Gm, int k, double tau,
                                                     double* __restrict__ T) {
   __shared__ JacobiSmem sm;
-  for (int e = threadIdx.x; e < k * k; e += kT) sm.S[(e / k) * JacobiSmem::LD + e % k] = Gm[e];
+  __shared__ int fallback;
+  __shared__ double dmax;
+  constexpr int LD = JacobiSmem::LD;
+  constexpr double kCholTau = 1e-10;
+  for (int e = threadIdx.x; e < k * k; e += kT) sm.S[(e / k) * LD + e % k] = Gm[e];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double d = 0.0;
+    for (int a = 0; a < k; ++a) d = fmax(d, sm.S[a * LD + a]);
+    dmax = d;
+    fallback = d > 0.0 ? 0 : 1;
+  }
+  // right-looking Cholesky in the lower triangle
+  for (int p = 0; p < k; ++p) {
+    __syncthreads();
+    if (threadIdx.x == 0 && !fallback) {
+      const double d = sm.S[p * LD + p];
+      if (d > kCholTau * dmax) sm.S[p * LD + p] = sqrt(d);
+      else fallback = 1;
+    }
+    __syncthreads();
+    if (fallback) break;
+    const double piv = sm.S[p * LD + p];
+    for (int i = p + 1 + threadIdx.x; i < k; i += kT) sm.S[i * LD + p] /= piv;
+    __syncthreads();
+    const int w = k - p - 1;
+    for (int e = threadIdx.x; e < w * w; e += kT) {
+      const int i = p + 1 + e / w, j = p + 1 + e % w;
+      if (j <= i) sm.S[i * LD + j] = fma(-sm.S[i * LD + p], sm.S[j * LD + p], sm.S[i * LD + j]);
+    }
+  }
+  __syncthreads();
+  if (!fallback) {
+    // column j of L^-1 by forward substitution (one thread per column); T[a][j] = (L^-1)[j][a]
+    // (the column is kept in row j of the eigenvector array, unused on this path)
+    if (threadIdx.x < k) {
+      const int j = threadIdx.x;
+      double* x = sm.E + j * LD;
+      for (int i = 0; i < k; ++i) {
+        double v = i == j ? 1.0 : 0.0;
+        for (int l = j; l < i; ++l) v = fma(-sm.S[i * LD + l], x[l], v);
+        x[i] = i < j ? 0.0 : v / sm.S[i * LD + i];
+      }
+      for (int i = 0; i < k; ++i) T[j * k + i] = x[i];
+    }
+    return;
+  }
+  for (int e = threadIdx.x; e < k * k; e += kT) sm.S[(e / k) * LD + e % k] = Gm[e];
   __syncthreads();
   jacobi_eig<kMaxW>(sm, k);
   const double lmax = eigval<kMaxW>(sm, 0);
