@@ -47,7 +47,8 @@ typedef enum {
   ENMF_ECLOSED = 6    /* enmf_serve_submit after enmf_serve_stop began */
 } enmf_status;
 
-typedef enum { ENMF_F32 = 0, ENMF_BF16 = 1, ENMF_F16 = 2 } enmf_dtype;
+/* Storage of X.  ENMF_CSR: a sparse X uploaded with enmf_sparse_create. */
+typedef enum { ENMF_F32 = 0, ENMF_BF16 = 1, ENMF_F16 = 2, ENMF_CSR = 3 } enmf_dtype;
 
 /* Largest supported rank and oversampled width (r + oversample). */
 #define ENMF_MAX_RANK 64
@@ -56,7 +57,9 @@ typedef enum { ENMF_F32 = 0, ENMF_BF16 = 1, ENMF_F16 = 2 } enmf_dtype;
 typedef struct enmf_ctx enmf_ctx;
 
 /* Data matrix X (eq. 1).  data: device pointer to m rows of ld elements of
- * the given dtype; only the first n of each row are read.  X >= 0. */
+ * the given dtype; only the first n of each row are read.  X >= 0.
+ * dtype ENMF_CSR: data is an enmf_sparse handle (below) made on the same
+ * device, m and n are its shape and ld is ignored. */
 typedef struct {
   const void* data;
   int64_t m, n, ld;
@@ -199,6 +202,41 @@ typedef struct {
 enmf_status enmf_objective_kkt(enmf_ctx* ctx, const enmf_matrix* X, int32_t r, const float* U,
                                const float* V, double relerr_svd, enmf_kkt* out_host);
 
+/* ---- sparse X (the sparse text collections of the experiments section and
+ * the large sparse Reuters table, 97% to 99.84% zeros) ----
+ * The method reads X only through X V, X^T U, ||X||_F^2 and the objective,
+ * so a sparse X runs every call that takes an enmf_matrix except the eNMC
+ * calls, enmf_convert and the server: enmf_xv, enmf_xtu, enmf_svd_init,
+ * enmf_iterate, enmf_objective_kkt and the instrumentation.  Its products
+ * accumulate in float32 in storage order (rows longer than 1024 nonzeros in
+ * pieces of 1024, summed in order), with the same result on every run.  The
+ * objective of a sparse X is evaluated in the expanded form
+ * f = 1/2 (sum over the nonzeros of x (x - 2 u_i . v_j) + <U^T U, V^T V>)
+ * in float64, whose rounding error is of order 1e-16 (||X||^2 + ||U V^T||^2)
+ * rather than 1e-16 f.
+ *
+ * enmf_sparse_create copies X, given in compressed-sparse-row form in host
+ * memory, to the context's device, in that form and transposed (compressed
+ * columns), plus the work partition of the products.  rowptr_host: m + 1
+ * offsets, rowptr[0] = 0, nondecreasing, rowptr[m] = nnz.  colind_host: nnz
+ * column indices, strictly increasing within each row (no duplicates), in
+ * [0, n).  vals_host: nnz finite values (X >= 0 is the caller's contract).
+ * 1 <= m, n < 2^31, nnz >= 0.  The handle owns its device copies (about
+ * 16 nnz + 16 (m + n) bytes) and keeps no pointer to the host arrays; it can
+ * be used by any context on its device until enmf_sparse_destroy, which must
+ * not be called while work that reads it is still queued.  ENMF_EINVAL for
+ * a malformed matrix (the first offending row in enmf_last_error),
+ * ENMF_ENOMEM if the device copies do not fit.  Synchronises the context's
+ * stream.  *out is NULL on failure. */
+typedef struct enmf_sparse enmf_sparse;
+
+enmf_status enmf_sparse_create(enmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz,
+                               const int64_t* rowptr_host, const int32_t* colind_host,
+                               const float* vals_host, enmf_sparse** out);
+
+/* Free the device copies of a sparse X (NULL is ignored). */
+void enmf_sparse_destroy(enmf_sparse* sp);
+
 /* Exterior nonnegative matrix completion (eNMC; the appendix "Exterior NMC
  * algorithm").  fhat(U, V) = 1/2 ||M o (X - U V^T)||_F^2 over the entries
  * marked observed in M, with grad_U = (M o (U V^T - X)) V and
@@ -254,7 +292,7 @@ enmf_status enmf_enmc_iterate(enmf_ctx* ctx, const enmf_matrix* X, const enmf_ma
  * launch gives every running solve one workgroup and a bounded amount of work
  * (tick_budget), so requests that arrive while others run join at the next
  * launch.  A solve's arithmetic does not depend on what else is in flight.
- * Served solves support r <= 32 and r + oversample <= 48, a fixed number of
+ * Served solves take dense X and support r <= 32 and r + oversample <= 48, a fixed number of
  * PBCD sweeps (pbcd_eps = 0) and modes 0 to 3.  The request's trace is
  * not recorded.
  *

@@ -13,7 +13,8 @@ the reading taken; the full list of readings is kept with the design
 notes of the repository.
 
 Parity status: all functions are pinned by the CPU tests in
-``tests/test_oracle_pins.py`` except the global optimality of the ADMM
+``tests/test_oracle_pins.py``, ``tests/test_oracle_enmc.py`` and
+``tests/test_oracle_sparse.py`` except the global optimality of the ADMM
 rotation for r > 2 (an NP-hard problem; parity unpinned).
 """
 
@@ -28,4 +29,7 @@ from .enmf_ref import (  # noqa: F401
 from .enmc_ref import (  # noqa: F401
     masked_objective, masked_gradients, masked_relerr, softimpute_als, enmc_init,
     masked_pbcd, masked_kkt, enmc_iterate, enmc,
+)
+from .sparse_ref import (  # noqa: F401
+    csr_to_dense, csr_rows_times, csr_cols_times, csr_sumsq,
 )

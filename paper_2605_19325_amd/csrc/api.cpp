@@ -18,7 +18,8 @@ enum Slot {
   S_BP, S_AP, S_SPLIT, S_P, S_Q, S_GPART, S_G, S_H, S_RUPART, S_XPART, S_U2, S_GPU, S_GPV, S_STAT, S_UD, S_RES,
   S_Y, S_QM64, S_QM32, S_Z, S_QN64, S_QN32, S_TMP64, S_T, S_C, S_COLP, S_COLS, S_SIG, S_TU, S_TV,
   S_W64, S_YA, S_ZA, S_BA, S_R, S_NEGP, S_WSQ, S_MPART,
-  S_EX, S_ERU, S_ERV, S_EE, S_ERSS, S_ECU, S_ECV, S_EG, S_EGI, S_EST, S_ESTAT, N_SLOTS
+  S_EX, S_ERU, S_ERV, S_EE, S_ERSS, S_ECU, S_ECV, S_EG, S_EGI, S_EST, S_ESTAT, S_SPX, S_SPG,
+  N_SLOTS
 };
 
 constexpr int kTimingPairs = 64;   // sampled launches per kind and iterate call
@@ -49,6 +50,7 @@ struct enmf_ctx {
 
 
 int enmf::ctx_device(const enmf_ctx* c) { return c->device; }
+hipStream_t enmf::ctx_stream(const enmf_ctx* c) { return c->stream; }
 void enmf::ctx_set_error(enmf_ctx* c, const char* msg) { c->err = msg; }
 
 namespace {
@@ -107,6 +109,13 @@ enmf_status check_ctx(enmf_ctx* c) {
 enmf_status check_matrix(enmf_ctx* c, const enmf_matrix* X) {
   if (!X || !X->data) return fail(c, ENMF_EINVAL, "X is null");
   if (X->m < 1 || X->n < 1) return fail(c, ENMF_EINVAL, "X must have m >= 1 and n >= 1");
+  if (const SparseX* sp = sparse_of(X)) {
+    if (sp->magic != kSparseMagic) return fail(c, ENMF_EINVAL, "X is not a sparse X handle");
+    if (sp->device != c->device) return fail(c, ENMF_EINVAL, "sparse X lives on another device");
+    if (sp->csr.rows != X->m || sp->csr.cols != X->n)
+      return fail(c, ENMF_EINVAL, "X shape differs from the sparse X handle's");
+    return ENMF_OK;
+  }
   if (X->ld < X->n) return fail(c, ENMF_EINVAL, "X leading dimension must be >= n");
   if (X->dtype != ENMF_F32 && X->dtype != ENMF_BF16 && X->dtype != ENMF_F16)
     return fail(c, ENMF_EINVAL, "unsupported X dtype");
@@ -118,11 +127,15 @@ enmf_status check_matrix(enmf_ctx* c, const enmf_matrix* X) {
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 bool use_mfma(const enmf_ctx* c, const enmf_matrix* X, int k) {
-  return c->use_mfma && mfma_eligible(X->dtype, k);
+  return c->use_mfma && X->dtype != ENMF_CSR && mfma_eligible(X->dtype, k);
 }
 
 // Split-partial bytes needed by either form of the products at width k.
 size_t split_bytes(const enmf_ctx* c, const enmf_matrix* X, int k) {
+  if (const SparseX* sp = sparse_of(X)) {
+    const int64_t ns = sp->csr.nslots > sp->csc.nslots ? sp->csr.nslots : sp->csc.nslots;
+    return (size_t)ns * k * 4;
+  }
   size_t a = 0, b = 0, pa = 0, pb = 0;
   if (use_mfma(c, X, k)) {
     mfma_xv_ws(X->dtype, X->m, X->n, k, &pa, &a);
@@ -134,8 +147,17 @@ size_t split_bytes(const enmf_ctx* c, const enmf_matrix* X, int k) {
   return a > b ? a : b;
 }
 
+// out = F B for one orientation of a sparse X.
+enmf_status do_spmm(enmf_ctx* c, const enmf_matrix* X, const SparseForm& f, const float* B, int k,
+                    float* out) {
+  WS(part, float, S_SPLIT, split_bytes(c, X, k));
+  CK(launch_spmm(f, B, k, part, out, c->stream));
+  return ENMF_OK;
+}
+
 // P = X B (B: n x k, ld k).
 enmf_status do_xv(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, float* P) {
+  if (const SparseX* sp = sparse_of(X)) return do_spmm(c, X, sp->csr, B, k, P);
   if (use_mfma(c, X, k)) {
     size_t pb = 0, sb = 0;
     mfma_xv_ws(X->dtype, X->m, X->n, k, &pb, &sb);
@@ -160,6 +182,7 @@ enmf_status do_xv(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, floa
 
 // Q = X^T A (A: m x k, ld k).
 enmf_status do_xtu(enmf_ctx* c, const enmf_matrix* X, const float* A, int k, float* Q) {
+  if (const SparseX* sp = sparse_of(X)) return do_spmm(c, X, sp->csc, A, k, Q);
   if (use_mfma(c, X, k)) {
     size_t pb = 0, sb = 0;
     mfma_xtu_ws(X->dtype, X->m, X->n, k, &pb, &sb);
@@ -199,7 +222,13 @@ enmf_status xv_parts(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, f
                      const GramJob* gj = nullptr) {
   hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
   int ns = 1;
-  if (use_mfma(c, X, k)) {
+  if (const SparseX* sp = sparse_of(X)) {
+    if (e0) CK(hipEventRecord(e0, c->stream));
+    TRY(do_spmm(c, X, sp->csr, B, k, P_out));
+    if (e1) CK(hipEventRecord(e1, c->stream));
+    out->p = P_out;
+    if (gj) CK(launch_gram_fin(gj->src, gj->nparts, gj->kp, gj->dst, c->stream));
+  } else if (use_mfma(c, X, k)) {
     size_t pb = 0, sb = 0;
     mfma_xv_ws(X->dtype, X->m, X->n, k, &pb, &sb);
     WS(pack, void, S_BP, pb);
@@ -232,7 +261,13 @@ enmf_status xtu_parts(enmf_ctx* c, const enmf_matrix* X, const float* A, int k, 
                       const GramJob* gj = nullptr) {
   hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
   int ns = 1;
-  if (use_mfma(c, X, k)) {
+  if (const SparseX* sp = sparse_of(X)) {
+    if (e0) CK(hipEventRecord(e0, c->stream));
+    TRY(do_spmm(c, X, sp->csc, A, k, Q_out));
+    if (e1) CK(hipEventRecord(e1, c->stream));
+    out->p = Q_out;
+    if (gj) CK(launch_gram_fin(gj->src, gj->nparts, gj->kp, gj->dst, c->stream));
+  } else if (use_mfma(c, X, k)) {
     size_t pb = 0, sb = 0;
     mfma_xtu_ws(X->dtype, X->m, X->n, k, &pb, &sb);
     WS(pack, void, S_AP, pb);
@@ -295,9 +330,30 @@ enmf_status do_orth(enmf_ctx* c, const float* A32, int64_t N, int k, double* out
   return ENMF_OK;
 }
 
+// Sparse X: f = 1/2 (sum over the nonzeros of x (x - 2 u_i . v_j) + <U^T U, V^T V>)
+// in float64, synchronising.
+enmf_status sparse_objective(enmf_ctx* c, const SparseX* sp, int r, const float* U, const float* V,
+                             double* f) {
+  hipStream_t s = c->stream;
+  WS(part, double, S_SPX, 1024 * 8);
+  WS(g, double, S_SPG, 2 * r * r * 8);
+  WS(o, double, S_SIG, 64 * 8);
+  TRY(do_gram(c, U, 0, r, sp->csr.rows, r, r, g));
+  TRY(do_gram(c, V, 0, r, sp->csr.cols, r, r, g + r * r));
+  const int np = launch_sparse_cross(sp->csr, U, V, r, part, s);
+  if (np < 0) return fail(c, ENMF_EDEVICE, "sparse cross-term launch failed");
+  CK(launch_sparse_objective(part, np, g, g + r * r, r, o, s));
+  double v = 0.0;
+  CK(hipMemcpyAsync(&v, o, 8, hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  *f = 0.5 * v;
+  return ENMF_OK;
+}
+
 // Direct residual f = 1/2 ||X - U V^T||^2 (float64), synchronising.
 enmf_status direct_objective(enmf_ctx* c, const enmf_matrix* X, int r, const float* U,
                              const float* V, double* f) {
+  if (const SparseX* sp = sparse_of(X)) return sparse_objective(c, sp, r, U, V, f);
   hipStream_t s = c->stream;
   const int kp = pad_width(r);
   WS(Ud, double, S_UD, X->m * kp * 8);
@@ -315,11 +371,22 @@ enmf_status direct_objective(enmf_ctx* c, const enmf_matrix* X, int r, const flo
   return ENMF_OK;
 }
 
+// Partials of ||X||^2 (at most 1024) into xp; *nx receives their count.
+enmf_status sumsq_parts(enmf_ctx* c, const enmf_matrix* X, double* xp, int* nx) {
+  if (const SparseX* sp = sparse_of(X)) {
+    *nx = launch_sparse_sumsq(sp->csr, xp, c->stream);
+    if (*nx < 0) return fail(c, ENMF_EDEVICE, "sparse sum-of-squares launch failed");
+    return ENMF_OK;
+  }
+  CK(launch_sumsq_x(X->data, X->dtype, X->m, X->n, X->ld, xp, nx, c->stream));
+  return ENMF_OK;
+}
+
 enmf_status read_sumsq_x(enmf_ctx* c, const enmf_matrix* X, double* nx2) {
   WS(xp, double, S_XPART, 1024 * 8);
   WS(o, double, S_SIG, 64 * 8);
   int nx = 0;
-  CK(launch_sumsq_x(X->data, X->dtype, X->m, X->n, X->ld, xp, &nx, c->stream));
+  TRY(sumsq_parts(c, X, xp, &nx));
   CK(launch_sum_parts(xp, nx, 1, 1, o, c->stream));
   CK(hipMemcpyAsync(nx2, o, 8, hipMemcpyDeviceToHost, c->stream));
   CK(hipStreamSynchronize(c->stream));
@@ -599,21 +666,26 @@ enmf_status iter_setup(enmf_ctx* c, const enmf_matrix* X, int r, const float* U,
   WS(xp, double, S_XPART, 1024 * 8);
   b.stat = stat; b.xpart = xp;
   // pre-size the shared split buffers so the loop never reallocates
-  const int kpw = pad_width(r);
-  const int64_t rows_pad = round_up(n, xv_tile_width(X->dtype));
-  size_t pbx = (size_t)rows_pad * kpw * 4, pbu = (size_t)m * kpw * 4;
-  if (use_mfma(c, X, r)) {
-    size_t t = 0;
-    mfma_xv_ws(X->dtype, m, n, r, &pbx, &t);
-    mfma_xtu_ws(X->dtype, m, n, r, &pbu, &t);
+  if (sparse_of(X)) {
+    if (!ws(c, S_SPLIT, split_bytes(c, X, r)))
+      return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
+  } else {
+    const int kpw = pad_width(r);
+    const int64_t rows_pad = round_up(n, xv_tile_width(X->dtype));
+    size_t pbx = (size_t)rows_pad * kpw * 4, pbu = (size_t)m * kpw * 4;
+    if (use_mfma(c, X, r)) {
+      size_t t = 0;
+      mfma_xv_ws(X->dtype, m, n, r, &pbx, &t);
+      mfma_xtu_ws(X->dtype, m, n, r, &pbu, &t);
+    }
+    if (!ws(c, S_BP, pbx) || !ws(c, S_AP, pbu))
+      return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
+    size_t sb = split_bytes(c, X, r);
+    const size_t sv = (size_t)xv_splits(m, n, X->dtype) * m * r * 4;
+    const size_t su = (size_t)xtu_splits(m, n) * n * r * 4;
+    if (!use_mfma(c, X, r)) sb = sv > su ? sv : su;
+    if (!ws(c, S_SPLIT, sb)) return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
   }
-  if (!ws(c, S_BP, pbx) || !ws(c, S_AP, pbu))
-    return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
-  size_t sb = split_bytes(c, X, r);
-  const size_t sv = (size_t)xv_splits(m, n, X->dtype) * m * r * 4;
-  const size_t su = (size_t)xtu_splits(m, n) * n * r * 4;
-  if (!use_mfma(c, X, r)) sb = sv > su ? sv : su;
-  if (!ws(c, S_SPLIT, sb)) return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
 
   DevState h;
   std::memset(&h, 0, sizeof(h));
@@ -626,7 +698,7 @@ enmf_status iter_setup(enmf_ctx* c, const enmf_matrix* X, int r, const float* U,
   CK(hipMemcpyAsync(c->st, &h, sizeof(h), hipMemcpyHostToDevice, s));
   CK(hipStreamSynchronize(s));
   int nx = 0;
-  CK(launch_sumsq_x(X->data, X->dtype, m, n, X->ld, xp, &nx, s));
+  TRY(sumsq_parts(c, X, xp, &nx));
   CK(launch_factor_stats(U, m * r, r, stat, 0, b.fbU, s));
   CK(launch_factor_stats(V, n * r, r, stat, b.fbU, b.fbV, s));
   CK(launch_setup_state(stat, b.fbU, b.fbV, xp, nx, o.step_u, o.step_v, o.ext_iters, c->st, s));
@@ -902,7 +974,8 @@ enmf_status enmf_time_products(enmf_ctx* c, const enmf_matrix* X, int32_t k, int
   const int64_t m = X->m, n = X->n;
   const int kp = pad_width(k);
   const bool mf = use_mfma(c, X, k);
-  const int64_t rows_pad = round_up(n, xv_tile_width(X->dtype));
+  const SparseX* sp = sparse_of(X);
+  const int64_t rows_pad = sp ? n : round_up(n, xv_tile_width(X->dtype));
   size_t pbx = (size_t)rows_pad * kp * 4, pbu = (size_t)m * kp * 4, t = 0;
   if (mf) {
     mfma_xv_ws(X->dtype, m, n, k, &pbx, &t);
@@ -917,12 +990,14 @@ enmf_status enmf_time_products(enmf_ctx* c, const enmf_matrix* X, int32_t k, int
   CK(hipMemsetAsync(Z, 0, (m > n ? m : n) * k * 4, s));
   CK(hipMemsetAsync(Bp, 0, pbx, s));
   CK(hipMemsetAsync(Ap, 0, pbu, s));
-  const int sx = xv_splits(m, n, X->dtype), su = xtu_splits(m, n);
+  const int sx = sp ? 1 : xv_splits(m, n, X->dtype), su = sp ? 1 : xtu_splits(m, n);
   auto run_xv = [&](int pack) {
+    if (sp) return launch_spmm(sp->csr, Z, k, part, P, s);
     return mf ? launch_xv_mfma(X->data, X->dtype, m, n, X->ld, Z, k, Bp, part, P, s, 0, pack)
               : launch_xv(X->data, X->dtype, m, n, X->ld, Bp, k, kp, sx, part, P, s, 0);
   };
   auto run_xtu = [&](int pack) {
+    if (sp) return launch_spmm(sp->csc, Z, k, part, Q, s);
     return mf ? launch_xtu_mfma(X->data, X->dtype, m, n, X->ld, Z, k, Ap, part, Q, s, 0, pack)
               : launch_xtu(X->data, X->dtype, m, n, X->ld, Ap, k, kp, su, part, Q, s, 0);
   };

@@ -89,6 +89,7 @@ inline int pad_width(int k) {
 
 // Context accessors for the serving front end (api.cpp).
 int ctx_device(const enmf_ctx* c);
+hipStream_t ctx_stream(const enmf_ctx* c);
 void ctx_set_error(enmf_ctx* c, const char* msg);
 
 // ---------------------------------------------------------------------------
@@ -179,6 +180,9 @@ hipError_t launch_polar(const double* Mf, int r, int kp, double* R, DevState* st
 int factor_blocks(int64_t count);
 // Padded width of the r x r Grams consumed by the row-update and check kernels.
 int row_pad(int r);
+// Blocks of a row pass: one per block of rows, at most kRowBlocksMax (the
+// blocks then loop over the row blocks).
+constexpr int64_t kRowBlocksMax = 1024;
 int rowupdate_blocks(int64_t rows, int kp);
 // float64 entries of one block's partial Gram at padded width kp.
 int gram_part_len(int kp);
@@ -206,6 +210,56 @@ hipError_t launch_pbcd_decide(const double* rec, int nparts, int half, int first
                               hipStream_t s);
 hipError_t launch_finalize(const DecideArgs& d, int final_check, DevState* st, hipStream_t s);
 hipError_t launch_clip(float* A, int64_t count, hipStream_t s);
+
+// ---- sparse X (k_sparse.hip) ----
+// One orientation of a sparse X on the device: `rows` compressed rows over
+// `cols` columns (CSR of X, or CSR of X^T for the transposed product), and a
+// partition of the nonzeros into work items.  Item t covers the nonzeros
+// [item_p0[t], item_p0[t + 1]) of row item_row[t]; a row has one item, or
+// several of at most kSpChunk nonzeros when it is longer.  A single item
+// writes its output row directly (item_slot = -1); the items of a longer row
+// write partial rows to slots [split_s0[q], split_s0[q + 1]) of a workspace,
+// summed in slot order into row split_row[q].  Every row, empty ones too, has
+// at least one item, so every output row is written.
+constexpr int64_t kSpChunk = 1024;
+struct SparseForm {
+  int64_t rows = 0, cols = 0, nnz = 0;
+  int64_t* ptr = nullptr;      // rows + 1
+  int32_t* idx = nullptr;      // nnz column indices, increasing within a row
+  float* val = nullptr;        // nnz
+  int64_t nitems = 0, nslots = 0, nsplit = 0;
+  int64_t* item_p0 = nullptr;  // nitems + 1
+  int32_t* item_row = nullptr;
+  int32_t* item_slot = nullptr;
+  int32_t* split_row = nullptr;   // nsplit
+  int32_t* split_s0 = nullptr;    // nsplit + 1
+};
+// out (rows x k, leading dimension k) = F B with B (cols x k, leading
+// dimension k), float32 accumulation in storage order; part: nslots * k
+// floats of workspace.  1 <= k <= 128.
+hipError_t launch_spmm(const SparseForm& f, const float* B, int k, float* part, float* out,
+                       hipStream_t s);
+// The two orientations of one sparse X (enmf_sparse_create).
+constexpr uint64_t kSparseMagic = 0x656e6d6673707273ull;
+struct SparseX {
+  uint64_t magic = kSparseMagic;
+  int device = 0;
+  SparseForm csr;    // rows of X: X B
+  SparseForm csc;    // rows of X^T: X^T A
+};
+// The sparse X of a matrix descriptor (dtype ENMF_CSR), or null.
+const SparseX* sparse_of(const enmf_matrix* X);
+// Partial sums (float64) of the squares of the stored values: returns the
+// number of partials written to part (at most 1024).
+int launch_sparse_sumsq(const SparseForm& f, double* part, hipStream_t s);
+// Partials of sum over the nonzeros of x_ij (x_ij - 2 u_i . v_j) in float64
+// (U: rows x r, V: cols x r, float32); returns the number written (<= 1024).
+int launch_sparse_cross(const SparseForm& f, const float* U, const float* V, int r, double* part,
+                        hipStream_t s);
+// out[0] = sum of the nparts partials + sum_ab GU[a][b] GV[a][b] (r x r,
+// leading dimension r): 2 f for the expanded objective.
+hipError_t launch_sparse_objective(const double* part, int nparts, const double* GU,
+                                   const double* GV, int r, double* out, hipStream_t s);
 
 // ---- exterior nonnegative matrix completion (k_enmc.hip) ----
 // State of an eNMC solve on the device (scalars of the last check).
@@ -248,3 +302,6 @@ hipError_t launch_enmc_finalize(const double* rss, int nrss, const double* cu, i
                                 hipStream_t s);
 
 }  // namespace enmf
+
+// The opaque handle of include/enmf.h.
+struct enmf_sparse : enmf::SparseX {};

@@ -311,11 +311,13 @@ __global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, 
   const bool valid = rr < AG::RB && rr < nrow;
   const double rho = st->rho;
   const double irho = 1.0 / rho;
-  double neg = 0.0;
-  if (valid) {
-    double wr[8];
+  // W R for the block's rows (8 columns per thread), then back into Ws so
+  // that the elementwise steps below run over the rows as one flat,
+  // coalesced range
+  double wr[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) wr[e] = 0.0;
+  for (int e = 0; e < 8; ++e) wr[e] = 0.0;
+  if (valid) {
     const double* w = Ws + rr * KP;
     for (int a = 0; a < KP; ++a) {
       const double x = w[a];
@@ -323,19 +325,28 @@ __global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, 
 #pragma unroll
       for (int e = 0; e < 8; ++e) wr[e] = fma(x, rrow[e], wr[e]);
     }
-    const int64_t i = row0 + rr;
+  }
+  __syncthreads();
+  if (valid) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int64_t idx = i * KP + c0 + e;
-      double y = 0.0;
-      if (step > 0) y = Y[idx] + rho * (Z[idx] - wr[e]);
-      const double b = wr[e] - y * irho;
-      const double z = b > 0.0 ? b : (b >= -irho ? 0.0 : b + irho);
-      Y[idx] = y;
-      Z[idx] = z;
-      B[idx] = z + y * irho;
-      neg += wr[e] < 0.0 ? -wr[e] : 0.0;
-    }
+    for (int e = 0; e < 8; ++e) Ws[rr * KP + c0 + e] = wr[e];
+  }
+  __syncthreads();
+  double neg = 0.0;
+  const int cnt = (int)nrow * KP;
+  double* Yb = Y + row0 * KP;
+  double* Zb = Z + row0 * KP;
+  double* Bb = B + row0 * KP;
+  for (int e = threadIdx.x; e < cnt; e += kT) {
+    const double w = Ws[e];
+    double y = 0.0;
+    if (step > 0) y = Yb[e] + rho * (Zb[e] - w);
+    const double b = w - y * irho;
+    const double z = b > 0.0 ? b : (b >= -irho ? 0.0 : b + irho);
+    Yb[e] = y;
+    Zb[e] = z;
+    Bb[e] = z + y * irho;
+    neg += w < 0.0 ? -w : 0.0;
   }
   neg = block_sum<kT>(neg, sh);
   if (threadIdx.x == 0) negpart[blockIdx.x] = neg;

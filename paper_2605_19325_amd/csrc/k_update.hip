@@ -221,8 +221,8 @@ __device__ bool check_decide(const DecideArgs& d, int final_check, DevState* st,
 // the last chunk.
 // The result goes to Aout (which may be A).  rec[b] = {#negative of the
 // output, |M o grad|^2 before the sweeps, |M o grad|^2 after, 0, check...}.
-template <int KP>
-__global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
+template <int KP, bool LOOP>
+__global__ __launch_bounds__(Team<KP>::NT, (LOOP && KP == 64) ? 2 : 1) void k_rowupdate(
     const float* A, float* Aout, int64_t rows, int r,
     const float* __restrict__ P, int nsplit, int64_t pstride, const double* __restrict__ G,
     DevState* st, int half, int sweeps, int flags, double* __restrict__ rec,
@@ -264,10 +264,21 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
   }
   if (update && !first && (phase == kPhaseHals || st->pbcd_done[half])) return;
   const int team = threadIdx.x / T, q = threadIdx.x % T, c0 = 8 * q;
-  const bool valid = (int64_t)blockIdx.x * TM::RB + team < rows;
   const bool needG = update || chk;
-  const int64_t row0 = (int64_t)blockIdx.x * TM::RB;
+  constexpr int NTILE = KP / 4;
+  constexpr int NTASK = NTILE * (NTILE + 1) / 2;
+  static_assert(NTASK <= TM::NT, "one Gram tile per thread");
+  const bool gram = (flags & kRowGram) != 0;
+  CheckAcc ck;
+  double gi2 = 0.0, pg2 = 0.0, negc = 0.0;
+  // blocks of TM::RB rows, grid-strided (LOOP) when there are more than
+  // kRowBlocksMax of them: the records and partial Grams stay one per
+  // launched block however many rows there are
+  const int64_t nrb = (rows + TM::RB - 1) / TM::RB;
+  for (int64_t rb = blockIdx.x; rb < nrb; rb = LOOP ? rb + gridDim.x : nrb) {
+  const int64_t row0 = rb * TM::RB;
   const int nrow = (int)(rows - row0 < TM::RB ? rows - row0 : TM::RB);
+  const bool valid = team < nrow;
 
   float a[8];
   double p[8];
@@ -293,8 +304,6 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
       row_times_g<KP>(src[team], sG, c0, out);
     }
   };
-  CheckAcc ck;
-  double gi2 = 0.0, pg2 = 0.0;
   double t[8];
   bool have_t = false;   // t == a G for the current a
   if (chk && pre) {
@@ -385,7 +394,7 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
         num = fma((double)g[e], (double)g[e], num);
         sgv[team][c0 + e] = g[e];
       }
-      if (sw == 0 && first) gi2 = num;
+      if (sw == 0 && first) gi2 += num;
       __syncthreads();
       double h[8];
       times_g(sgv, h);
@@ -423,7 +432,6 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
     }
     if (chk && !pre && valid) ck.add(a, t, p, c0, r);
   }
-  double negc = 0.0;
   if (valid) {
 #pragma unroll
     for (int e = 0; e < 8; ++e)
@@ -446,7 +454,7 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
   }
   if (pack != nullptr) {
     const int64_t chunk_end = (rows + pc - 1) / pc * pc;
-    const int64_t end = blockIdx.x == gridDim.x - 1 ? chunk_end : row0 + TM::RB;
+    const int64_t end = rb == nrb - 1 ? chunk_end : row0 + TM::RB;
     const int nruns = (int)((end - row0) / 8);
     const int64_t term = (int64_t)pkp * pldt;
     for (int task = threadIdx.x; task < pkp * nruns; task += TM::NT) {
@@ -458,30 +466,30 @@ __global__ __launch_bounds__(Team<KP>::NT) void k_rowupdate(
       store_split_run8(v, pack + (row / pc) * 3 * term + (int64_t)c * pldt + row % pc, term);
     }
   }
-  if (flags & kRowGram) {
-    constexpr int NTILE = KP / 4;
-    constexpr int NTASK = NTILE * (NTILE + 1) / 2;
-    for (int task = threadIdx.x; task < NTASK; task += TM::NT) {
-      int ti, tj;
-      gram_tile<KP>(task, ti, tj);
-      double acc[16];
+  if (gram && threadIdx.x < NTASK) {
+    // this row block's part, added to the block's running partial Gram
+    int ti, tj;
+    gram_tile<KP>(threadIdx.x, ti, tj);
+    double gacc[16];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[e] = 0.0;
-      for (int row = 0; row < TM::RB; ++row) {
-        const float4 x = *reinterpret_cast<const float4*>(&sa[row][4 * ti]);
-        const float4 y = *reinterpret_cast<const float4*>(&sa[row][4 * tj]);
-        const double xv[4] = {(double)x.x, (double)x.y, (double)x.z, (double)x.w};
-        const double yv[4] = {(double)y.x, (double)y.y, (double)y.z, (double)y.w};
+    for (int e = 0; e < 16; ++e) gacc[e] = 0.0;
+    for (int row = 0; row < TM::RB; ++row) {
+      const float4 x = *reinterpret_cast<const float4*>(&sa[row][4 * ti]);
+      const float4 y = *reinterpret_cast<const float4*>(&sa[row][4 * tj]);
+      const double xv[4] = {(double)x.x, (double)x.y, (double)x.z, (double)x.w};
+      const double yv[4] = {(double)y.x, (double)y.y, (double)y.z, (double)y.w};
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[4 * u + v] = fma(xv[u], yv[v], acc[4 * u + v]);
-      }
-      double* o = gpart + (int64_t)blockIdx.x * (16 * NTASK) + 16 * task;
-#pragma unroll
-      for (int e = 0; e < 16; ++e) o[e] = acc[e];
+        for (int v = 0; v < 4; ++v) gacc[4 * u + v] = fma(xv[u], yv[v], gacc[4 * u + v]);
     }
+    double* o = gpart + (int64_t)blockIdx.x * (16 * NTASK) + 16 * threadIdx.x;
+    const bool again = rb != blockIdx.x;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) o[e] = again ? o[e] + gacc[e] : gacc[e];
   }
+  __syncthreads();   // the next row block restages the shared arrays
+  }  // row blocks
   double vals[NF] = {negc, gi2, pg2, ck.pg2, ck.sg, ck.mx, ck.ng2, ck.sq, ck.ap, ck.nneg, ck.mn, ck.q};
   const int kind[NF] = {0, 0, 0, 0, 0, 1, 0, 0, 0, 0, 2, 0};
   double red[NF];
@@ -547,10 +555,16 @@ void rowupdate_launch(const float* A, float* Aout, int64_t rows, int r, const fl
                       const double* headV, int nbV, const PackOut& po, const DecideArgs& dec,
                       hipStream_t s) {
   using TM = Team<KP>;
-  dim3 g((unsigned)((rows + TM::RB - 1) / TM::RB)), b(TM::NT);
-  hipLaunchKernelGGL((k_rowupdate<KP>), g, b, 0, s, A, Aout, rows, r, P, nsplit, pstride, G, st,
-                     half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po.p, po.kp, po.c,
-                     po.ldt, dec);
+  const int nb = rowupdate_blocks(rows, KP);
+  dim3 g((unsigned)nb), b(TM::NT);
+  if ((int64_t)nb * TM::RB >= rows)
+    hipLaunchKernelGGL((k_rowupdate<KP, false>), g, b, 0, s, A, Aout, rows, r, P, nsplit, pstride,
+                       G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po.p, po.kp,
+                       po.c, po.ldt, dec);
+  else
+    hipLaunchKernelGGL((k_rowupdate<KP, true>), g, b, 0, s, A, Aout, rows, r, P, nsplit, pstride,
+                       G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po.p, po.kp,
+                       po.c, po.ldt, dec);
 }
 
 template <int KP>
@@ -578,7 +592,8 @@ int factor_blocks(int64_t count) {
 
 int rowupdate_blocks(int64_t rows, int kp) {
   const int rb = kp / 8 <= 4 ? 64 : 32;
-  return (int)((rows + rb - 1) / rb);
+  const int64_t nrb = (rows + rb - 1) / rb;
+  return (int)(nrb < kRowBlocksMax ? nrb : kRowBlocksMax);
 }
 
 hipError_t launch_factor_stats(const float* A, int64_t count, int r, double* part, int block_offset,

@@ -16,7 +16,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libenmf.so")
 
-F32, BF16, F16 = 0, 1, 2
+F32, BF16, F16, CSR = 0, 1, 2, 3
 _DTYPES = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}
 MAX_RANK = 64
 MAX_WIDTH = 80
@@ -103,6 +103,9 @@ SIGNATURES = [
                                POINTER(IterOpts), POINTER(IterReport), c_void_p, c_int32]),
     ("enmf_objective_kkt", c_int32, [c_void_p, POINTER(Matrix), c_int32, c_void_p, c_void_p,
                                      c_double, POINTER(Kkt)]),
+    ("enmf_sparse_create", c_int32, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p,
+                                     c_void_p, POINTER(c_void_p)]),
+    ("enmf_sparse_destroy", None, [c_void_p]),
     ("enmf_enmc_init", c_int32, [c_void_p, POINTER(Matrix), POINTER(MaskArg), c_int32,
                                  POINTER(SvdOpts), c_int32, c_void_p, c_void_p, POINTER(c_double)]),
     ("enmf_enmc_grad", c_int32, [c_void_p, POINTER(Matrix), POINTER(MaskArg), c_int32, c_void_p,
@@ -155,8 +158,41 @@ def _factor(t, rows, r, name):
     return t
 
 
+class SparseX:
+    """A sparse X on the device (enmf_sparse handle), made by Context.sparse.
+
+    Accepted wherever the calls take X (products, svd_init, iterate,
+    objective_kkt, solve, time_products); `shape`, `nnz` and `device` mirror
+    a dense tensor's.
+    """
+
+    def __init__(self, lib, handle, m, n, nnz, device):
+        self._lib = lib
+        self._h = handle
+        self.shape = (m, n)
+        self.nnz = nnz
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            torch.cuda.synchronize(self.device)
+            self._lib.enmf_sparse_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def matrix(X):
-    """enmf_matrix view of a 2-D row-major CUDA tensor (float32, bfloat16 or float16)."""
+    """enmf_matrix view of a 2-D row-major CUDA tensor (float32, bfloat16 or
+    float16) or of a SparseX."""
+    if isinstance(X, SparseX):
+        if not X._h:
+            raise ValueError("sparse X has been closed")
+        return Matrix(X._h.value, X.shape[0], X.shape[1], 0, CSR, 0)
     _dev(X, "X")
     if X.dim() != 2 or X.stride(1) != 1:
         raise ValueError("X must be a 2-D tensor with unit column stride")
@@ -217,6 +253,22 @@ class Context:
 
     def synchronize(self):
         self._call(self._lib.enmf_synchronize)
+
+    def sparse(self, rowptr, colind, vals, shape):
+        """Upload a compressed-sparse-row X (host arrays: int64 rowptr of m + 1
+        offsets, int32 column indices increasing within each row, float32
+        values) to this context's device."""
+        m, n = int(shape[0]), int(shape[1])
+        rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+        ci = np.ascontiguousarray(colind, dtype=np.int32)
+        vv = np.ascontiguousarray(vals, dtype=np.float32)
+        if rp.ndim != 1 or rp.size != m + 1 or ci.ndim != 1 or vv.ndim != 1 or ci.size != vv.size:
+            raise ValueError("rowptr must hold m + 1 offsets and colind, vals nnz entries each")
+        h = c_void_p()
+        torch.cuda.current_stream(self.device).synchronize()
+        self._call(self._lib.enmf_sparse_create, m, n, int(ci.size), rp.ctypes.data_as(c_void_p),
+                   ci.ctypes.data_as(c_void_p), vv.ctypes.data_as(c_void_p), byref(h))
+        return SparseX(self._lib, h, m, n, int(ci.size), torch.device("cuda", self.device))
 
     # ---- building blocks ----
     def convert(self, X32, dtype=torch.bfloat16):

@@ -232,3 +232,73 @@ def completion(m, n, r, density, seed, noise=0.01):
     X = X.astype(np.float32)
     X[~obs] = np.nan
     return X, obs
+
+
+def text_counts(m=804414, n=47236, mean_row_nnz=108.0, seed=1006, topics=40, doc_topics=2,
+                background=0.15, zipf_shift=10.0, zipf_power=1.0, topic_shift=3.0, topic_power=1.3,
+                row_sigma=0.9, count_rate=0.7):
+    """Sparse term-document X in compressed-sparse-row form, the stand-in for
+    the paper's sparse text collections (the Reuters matrix, 804,414 x 47,236
+    with 99.84% zeros, at the defaults; the Verb counts at small shapes).
+
+    Topic model: each of `topics` topics ranks the terms by its own random
+    permutation, and a background distribution by another; term weights
+    follow Zipf-Mandelbrot laws, p(rank) proportional to
+    1 / (rank + topic_shift)^topic_power in a topic and
+    1 / (rank + zipf_shift)^zipf_power in the background.
+    Row i (a document) takes round(LogNormal) terms (mean mean_row_nnz,
+    log-sd row_sigma, clipped to [1, n]) and `doc_topics` distinct topics with
+    Dirichlet(1) weights; each term comes from the background with
+    probability `background`, else from one of the row's topics by weight.
+    Repeated terms are merged, so rows keep slightly fewer (the defaults give
+    about 0.16% density).  Values are TF-IDF-like: (1 + ln c) ln(1 + m / d_j)
+    with count c = 1 + Poisson(count_rate) and d_j the number of rows holding
+    term j, and each row is scaled to unit Euclidean norm.
+    Returns (rowptr int64 (m + 1), colind int32, vals float32), columns
+    strictly increasing within each row.
+    """
+    rng = np.random.default_rng(seed)
+    mu = np.log(mean_row_nnz) - 0.5 * row_sigma ** 2
+    lens = np.clip(np.rint(rng.lognormal(mu, row_sigma, m)), 1, n).astype(np.int64)
+    ranks = np.arange(n, dtype=np.float64)
+    w = 1.0 / (ranks + zipf_shift) ** zipf_power
+    cdf = np.cumsum(w / w.sum())
+    wt = 1.0 / (ranks + topic_shift) ** topic_power
+    cdf_t = np.cumsum(wt / wt.sum())
+    perms = np.stack([rng.permutation(n) for _ in range(topics + 1)]).astype(np.int32)
+    nt = min(doc_topics, topics)
+    dtop = np.argsort(rng.random((m, topics)), axis=1)[:, :nt] + 1
+    dw = np.cumsum(rng.dirichlet(np.ones(nt), size=m), axis=1)
+    total = int(lens.sum())
+    keys = np.empty(total, dtype=np.int64)
+    rows = np.repeat(np.arange(m, dtype=np.int64), lens)
+    step = 1 << 24
+    for a in range(0, total, step):
+        b = min(total, a + step)
+        rw = rows[a:b]
+        bg = rng.random(b - a) < background
+        u = rng.random(b - a)
+        rank = np.where(bg, np.searchsorted(cdf, u, side="right"),
+                        np.searchsorted(cdf_t, u, side="right"))
+        rank = np.minimum(rank, n - 1)
+        pick = (rng.random(b - a)[:, None] > dw[rw, :-1]).sum(axis=1)
+        topic = np.where(bg, 0, dtop[rw, pick])
+        keys[a:b] = rw * n + perms[topic, rank]
+    del rows
+    keys = np.unique(keys)
+    rows = keys // n
+    cols = (keys - rows * n).astype(np.int32)
+    del keys
+    df = np.bincount(cols, minlength=n)
+    idf = np.log1p(m / np.maximum(df, 1))
+    vals = (1.0 + np.log1p(rng.poisson(count_rate, cols.size))) * idf[cols]
+    norms = np.sqrt(np.bincount(rows, weights=vals * vals, minlength=m))
+    vals /= norms[rows]
+    rowptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=m), out=rowptr[1:])
+    return rowptr, cols, vals.astype(np.float32)
+
+
+def config_text(seed=1006):
+    """Reuters-shaped sparse X (804,414 x 47,236, about 0.16% nonzero), r = 40."""
+    return text_counts(seed=seed), (804414, 47236), 40

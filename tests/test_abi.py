@@ -26,7 +26,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for want in ("enmf_svd_init", "enmf_rotate", "enmf_iterate", "enmf_objective_kkt",
                  "enmf_xv", "enmf_xtu", "enmf_gram", "enmf_convert", "enmf_create",
-                 "enmf_serve_start", "enmf_enmc_init", "enmf_enmc_grad", "enmf_enmc_iterate"):
+                 "enmf_serve_start", "enmf_enmc_init", "enmf_enmc_grad", "enmf_enmc_iterate",
+                 "enmf_sparse_create", "enmf_sparse_destroy"):
         assert want in names
 
 

@@ -143,6 +143,35 @@ def test_iterate_ablation_modes(lib, small, mode):
     assert float(U.min()) >= 0.0 and float(V.min()) >= 0.0
 
 
+@pytest.mark.parametrize("m,n,r,iters,mode", [(40000, 60, 33, 1, 0), (40000, 60, 33, 12, 1),
+                                              (70000, 40, 12, 1, 0), (70000, 40, 12, 12, 1)])
+def test_iterate_parity_many_rows(lib, m, n, r, iters, mode):
+    """More row blocks than the row pass launches blocks (32,768 rows at
+    r > 32, 65,536 at r <= 32): each block then loops over several row blocks
+    and accumulates its records and partial Gram.  Fit rank = true rank.  One
+    exterior iteration (push, PBCD, the check) and twelve of projection plus
+    HALS: over several exterior iterations a matrix this tall always has
+    negative entries that the push brings within float32 rounding of zero,
+    where the two sides may take different masks."""
+    say(f"iterate parity, {m}x{n} r={r}, {iters} iterations mode {mode}: looping row passes")
+    X, _, _ = inputs.lowrank_plus_noise(m, n, r, seed=m + r)
+    om = inputs.omega(n, r + 10, r)
+    U0, V0, rso = _rotated_start(X, r, om)
+    Uo, Vo, ro = O.iterate(X, U0, V0, max_iter=iters, relerr_svd=rso, mode=mode)
+    U, V = to_dev(U0), to_dev(V0)
+    rep = lib.iterate(to_dev(X), U, V, max_iter=iters, relerr_svd=rso, mode=mode)
+    say(f"  |dU|/|U| {rel(host(U), Uo):.2e} |dV|/|V| {rel(host(V), Vo):.2e} "
+        f"ext {rep['ext_iters_done']} (oracle {ro['ext_iters_done']}) f {rep['f']:.9e} "
+        f"oracle {ro['f']:.9e} kkt {rep['kkt']:.6e} oracle {ro['kkt']:.6e}")
+    assert rep["iters"] == iters and rep["ext_iters_done"] == ro["ext_iters_done"]
+    assert rel(host(U), Uo) <= 1e-4 and rel(host(V), Vo) <= 1e-4
+    assert abs(rep["kkt"] - ro["kkt"]) <= 1e-4 * ro["kkt"]
+    k = lib.objective_kkt(to_dev(X), U, V, rso)
+    ref = O.kkt(X, host(U), host(V))
+    for key in ("f", "kkt", "kkt_pg_u", "kkt_pg_v"):
+        assert abs(k[key] - ref[key]) <= 1e-6 * max(1.0, abs(ref[key])), key
+
+
 def test_iterate_pbcd_eps_path(lib, small):
     X, r, om = small
     say("iterate parity with the PBCD eps stop (multi-launch sweeps)")
