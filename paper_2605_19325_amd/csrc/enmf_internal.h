@@ -215,20 +215,23 @@ hipError_t launch_clip(float* A, int64_t count, hipStream_t s);
 // One orientation of a sparse X on the device: `rows` compressed rows over
 // `cols` columns (CSR of X, or CSR of X^T for the transposed product), and a
 // partition of the nonzeros into work items.  Item t covers the nonzeros
-// [item_p0[t], item_p0[t + 1]) of row item_row[t]; a row has one item, or
-// several of at most kSpChunk nonzeros when it is longer.  A single item
-// writes its output row directly (item_slot = -1); the items of a longer row
-// write partial rows to slots [split_s0[q], split_s0[q + 1]) of a workspace,
-// summed in slot order into row split_row[q].  Every row, empty ones too, has
-// at least one item, so every output row is written.
+// [item_p0[t], item_p1[t]) of row item_row[t]: a piece of the row that stays
+// within one panel of kSpPanel columns and holds at most kSpChunk nonzeros.
+// A row of one item writes its output row directly (item_slot = -1); the
+// items of a longer row write partial rows to slots
+// [split_s0[q], split_s0[q + 1]) of a workspace, summed in slot order into row
+// split_row[q].  Every row, empty ones too, has at least one item, so every
+// output row is written.  Items are stored panel by panel.
 constexpr int64_t kSpChunk = 1024;
+constexpr int64_t kSpPanel = 65536;
 struct SparseForm {
   int64_t rows = 0, cols = 0, nnz = 0;
   int64_t* ptr = nullptr;      // rows + 1
   int32_t* idx = nullptr;      // nnz column indices, increasing within a row
   float* val = nullptr;        // nnz
   int64_t nitems = 0, nslots = 0, nsplit = 0;
-  int64_t* item_p0 = nullptr;  // nitems + 1
+  int64_t* item_p0 = nullptr;  // nitems
+  int64_t* item_p1 = nullptr;  // nitems
   int32_t* item_row = nullptr;
   int32_t* item_slot = nullptr;
   int32_t* split_row = nullptr;   // nsplit

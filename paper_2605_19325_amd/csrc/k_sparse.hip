@@ -4,7 +4,9 @@
 //
 // Product layout: the nonzeros of one orientation (CSR of X for X B, CSR of
 // X^T for X^T A) are cut into work items of at most kSpChunk nonzeros, never
-// spanning two rows (SparseForm).  A group of G lanes takes one item: the
+// spanning two rows or two panels of kSpPanel columns, and stored panel by
+// panel (SparseForm): the blocks in flight then gather from one panel's rows
+// of B, which stay in the last-level cache while X streams past.  A group of G lanes takes one item: the
 // group loads G (index, value) pairs at a time with one coalesced load, hands
 // them out lane to lane, and every lane gathers its column(s) c, c + G of the
 // referenced rows of B, eight rows in flight.  Each output entry is a float32
@@ -23,6 +25,7 @@ constexpr int kUnroll = 8;
 
 struct SpmmArgs {
   const int64_t* item_p0;
+  const int64_t* item_p1;
   const int32_t* item_row;
   const int32_t* item_slot;
   const int32_t* idx;
@@ -54,7 +57,7 @@ __global__ __launch_bounds__(kSt) void k_spmm(SpmmArgs a) {
   const int lane = threadIdx.x % G;
   const int64_t it = (int64_t)blockIdx.x * NG + threadIdx.x / G;
   if (it >= a.nitems) return;
-  const int64_t p0 = a.item_p0[it], p1 = a.item_p0[it + 1];
+  const int64_t p0 = a.item_p0[it], p1 = a.item_p1[it];
   const int k = a.k;
   float acc[KC];
 #pragma unroll
@@ -133,6 +136,7 @@ __global__ __launch_bounds__(kSt) void k_sp_sumsq(const float* __restrict__ v, i
 // items), lane c holding column c of the item's partial row of X V, as in
 // k_spmm; the lanes then take its dot product with u_i.  r <= 64.
 __global__ __launch_bounds__(kSt) void k_sp_cross(const int64_t* __restrict__ item_p0,
+                                                  const int64_t* __restrict__ item_p1,
                                                   const int32_t* __restrict__ item_row,
                                                   int64_t nitems, const int32_t* __restrict__ idx,
                                                   const float* __restrict__ val,
@@ -145,7 +149,7 @@ __global__ __launch_bounds__(kSt) void k_sp_cross(const int64_t* __restrict__ it
   double sx2 = 0.0, s = 0.0;
   for (int64_t it = (int64_t)blockIdx.x * (kSt / kWave) + threadIdx.x / kWave; it < nitems;
        it += nw) {
-    const int64_t p0 = item_p0[it], p1 = item_p0[it + 1];
+    const int64_t p0 = item_p0[it], p1 = item_p1[it];
     const double u = lane < r ? (double)U[(int64_t)item_row[it] * r + lane] : 0.0;
     double acc = 0.0;
     for (int64_t base = p0; base < p1; base += kWave) {
@@ -207,7 +211,7 @@ hipError_t spmm_launch(const SpmmArgs& a, hipStream_t s) {
 hipError_t launch_spmm(const SparseForm& f, const float* B, int k, float* part, float* out,
                        hipStream_t s) {
   if (k < 1 || k > 2 * kWave) return hipErrorInvalidValue;
-  SpmmArgs a{f.item_p0, f.item_row, f.item_slot, f.idx, f.val, f.nitems, B, k, part, out};
+  SpmmArgs a{f.item_p0, f.item_p1, f.item_row, f.item_slot, f.idx, f.val, f.nitems, B, k, part, out};
   hipError_t e;
   if (k <= 16) e = spmm_launch<16, 1>(a, s);
   else if (k <= 32) e = spmm_launch<32, 1>(a, s);
@@ -229,8 +233,8 @@ int launch_sparse_sumsq(const SparseForm& f, double* part, hipStream_t s) {
 int launch_sparse_cross(const SparseForm& f, const float* U, const float* V, int r, double* part,
                         hipStream_t s) {
   const int nb = reduce_blocks(f.nitems, kSt / kWave);
-  hipLaunchKernelGGL(k_sp_cross, dim3(nb), dim3(kSt), 0, s, f.item_p0, f.item_row, f.nitems, f.idx,
-                     f.val, U, V, r, part);
+  hipLaunchKernelGGL(k_sp_cross, dim3(nb), dim3(kSt), 0, s, f.item_p0, f.item_p1, f.item_row,
+                     f.nitems, f.idx, f.val, U, V, r, part);
   return hipGetLastError() == hipSuccess ? nb : -1;
 }
 

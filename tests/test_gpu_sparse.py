@@ -4,8 +4,9 @@ text collections) against the FP64 oracle, through the C ABI.
 * X B and X^T A element by element under the float32 accumulation bound
   (n_i + 4) 2^-24 (|X| |B|)_ic, n_i the nonzeros of the output's row, on
   ragged shapes, empty rows and columns, an all-zero X, every lane-group
-  width (k <= 16, <= 32, <= 64, > 64) and rows and columns longer than the
-  1024-nonzero pieces; the result is the same on every run;
+  width (k <= 16, <= 32, <= 64, > 64), rows and columns longer than the
+  1024-nonzero pieces and rows and columns cut at the 65,536-wide panels of
+  the gathered factor; the result is the same on every run;
 * svd_init, the iteration (1, 12 and 200 iterations from the oracle's
   rotated point), objective/KKT and a whole solve against the oracle on the
   dense matrix the compressed rows describe, to the bars of the dense
@@ -84,6 +85,8 @@ def product_bound(Xd, B, counts):
     (2500, 60, 40, 0.05, {"long_cols": (0, 33, 59)}),
     (400, 350, 80, 0.03, {}),
     (64, 64, 64, 0.9, {}),
+    (70000, 300, 16, 0.01, {"long_cols": (5,)}),
+    (300, 70000, 24, 0.01, {"long_rows": (3,)}),
 ])
 def test_sparse_products_parity(lib, m, n, k, density, extra):
     say(f"sparse products {m}x{n} k={k} density {density} {extra}")
