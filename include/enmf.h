@@ -148,6 +148,38 @@ enmf_status enmf_rotate(enmf_ctx* ctx, int64_t m, int64_t n, int32_t r, float* U
                         const enmf_rotate_opts* opts, double* R_host, int32_t* steps_host,
                         double* neg_mass_before_host, double* neg_mass_after_host);
 
+/* ---- generalized rotation (the appendix section on exact NMF: eq5, its split
+ * form eq:admm_form_2 and Algorithm alg:rsr) ----
+ * Orthogonal R1, R2 and a positive diagonal Lambda minimising the negativity
+ * mass sum h(.) of (U R1 Lambda R2, V R1 Lambda^-1 R2), h(q) = max(0, -q), a
+ * pair with the same product U V^T.  ADMM on the split variables
+ * W1 = [U; V] R1, W2 = [W11 Lambda; W12 Lambda^-1], W3 = W2 R2 with scaled
+ * duals M, N, P: per step W3 (prox of h) and W1 (closed form), then R1
+ * (Procrustes of [U; V]^T (W1 + M)) and W2 (closed form), then R2 (Procrustes
+ * of W2^T (W3 + P)) and each lambda_i (the positive root of the appendix's
+ * quartic with the least objective; a column whose U or V part is zero keeps
+ * its lambda), then the duals.  rho = gamma = t = rho0 sqrt((m+n) r) / ||[U; V]||_F,
+ * start R1 = R2 = I, Lambda = I, W1 = W2 = W3 = [U; V], duals 0.  Stops when
+ * |R1' - R1|_F + |R2' - R2|_F + |lambda' - lambda|_2 <= tol, or after
+ * max_iter steps (tol = 0 runs exactly max_iter).  All state is float64; one
+ * workgroup runs every step in one launch, for the small exact-NMF instances
+ * the method is meant for (m + n in the hundreds).  U (m x r) and V (n x r),
+ * float32, are replaced in place.  Outputs (host, each may be NULL): R1 and R2
+ * (r x r row-major), lambda (r), steps, and the negativity mass before and
+ * after.  1 <= r <= ENMF_MAX_RANK.  Workspace: 7 (m + n) KP float64, KP = r
+ * padded to 16, 32 or 64.  Synchronises the stream. */
+typedef struct {
+  double rho0;        /* default 1.0 */
+  double tol;         /* default 1e-10 */
+  int32_t max_iter;   /* default 500 */
+  int32_t reserved;
+} enmf_grot_opts;
+
+enmf_status enmf_rotate_general(enmf_ctx* ctx, int64_t m, int64_t n, int32_t r, float* U, float* V,
+                                const enmf_grot_opts* opts, double* R1_host, double* lambda_host,
+                                double* R2_host, int32_t* steps_host, double* neg_mass_before_host,
+                                double* neg_mass_after_host);
+
 /* ---- blocks (iii)-(iv): exterior phase and HALS (sections 3.2-3.3, Algorithms 2-3) ----
  * One iteration = U half then V half (the V half uses the new U, eq. t_i).
  * Phase per iteration: EXT while U or V has a negative entry (push negatives

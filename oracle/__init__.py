@@ -14,7 +14,7 @@ notes of the repository.
 
 Parity status: all functions are pinned by the CPU tests in
 ``tests/test_oracle_pins.py``, ``tests/test_oracle_enmc.py`` and
-``tests/test_oracle_sparse.py`` except the global optimality of the ADMM
+``tests/test_oracle_sparse.py`` and ``tests/test_oracle_grot.py`` except the global optimality of the ADMM
 rotation for r > 2 (an NP-hard problem; parity unpinned).
 """
 
@@ -32,4 +32,7 @@ from .enmc_ref import (  # noqa: F401
 )
 from .sparse_ref import (  # noqa: F401
     csr_to_dense, csr_rows_times, csr_cols_times, csr_sumsq,
+)
+from .grot_ref import (  # noqa: F401
+    rotate_general, lambda_update, lambda_objective, update_w1, update_w2,
 )

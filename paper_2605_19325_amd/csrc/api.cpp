@@ -19,7 +19,7 @@ enum Slot {
   S_Y, S_QM64, S_QM32, S_Z, S_QN64, S_QN32, S_TMP64, S_T, S_C, S_COLP, S_COLS, S_SIG, S_TU, S_TV,
   S_W64, S_YA, S_ZA, S_BA, S_R, S_NEGP, S_WSQ, S_MPART,
   S_EX, S_ERU, S_ERV, S_EE, S_ERSS, S_ECU, S_ECV, S_EG, S_EGI, S_EST, S_ESTAT, S_SPX, S_SPG,
-  N_SLOTS
+  S_GW, S_GOUT, N_SLOTS
 };
 
 constexpr int kTimingPairs = 64;   // sampled launches per kind and iterate call
@@ -627,6 +627,36 @@ enmf_status enmf_rotate(enmf_ctx* c, int64_t m, int64_t n, int32_t r, float* U, 
   if (steps_host) *steps_host = steps;
   if (neg_before_host) *neg_before_host = before[3];
   if (neg_after_host) *neg_after_host = after[3];
+  return ENMF_OK;
+}
+
+enmf_status enmf_rotate_general(enmf_ctx* c, int64_t m, int64_t n, int32_t r, float* U, float* V,
+                                const enmf_grot_opts* o, double* R1_host, double* lambda_host,
+                                double* R2_host, int32_t* steps_host, double* neg_before_host,
+                                double* neg_after_host) {
+  TRY(check_ctx(c));
+  if (!U || !V) return fail(c, ENMF_EINVAL, "null pointer");
+  if (m < 1 || n < 1 || r < 1 || r > ENMF_MAX_RANK) return fail(c, ENMF_EINVAL, "bad shape");
+  enmf_grot_opts d{1.0, 1e-10, 500, 0};
+  if (o) d = *o;
+  if (!(d.rho0 > 0.0) || d.max_iter < 0 || !(d.tol >= 0.0))
+    return fail(c, ENMF_EINVAL, "bad generalized rotation opts");
+  hipStream_t s = c->stream;
+  const int kp = grot_pad(r);
+  const int64_t N = m + n;
+  WS(gw, double, S_GW, 7 * N * kp * 8);
+  WS(out, double, S_GOUT, (4 + 2 * r * r + r) * 8);
+  // U and V are read into float64 before any output row is written
+  CK(launch_grot(U, m, V, n, r, d.rho0, d.tol, d.max_iter, gw, U, V, out, s));
+  std::vector<double> h(4 + 2 * r * r + r);
+  CK(hipMemcpyAsync(h.data(), out, h.size() * 8, hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  if (neg_before_host) *neg_before_host = h[0];
+  if (neg_after_host) *neg_after_host = h[1];
+  if (steps_host) *steps_host = (int32_t)h[2];
+  if (R1_host) std::memcpy(R1_host, h.data() + 4, r * r * 8);
+  if (R2_host) std::memcpy(R2_host, h.data() + 4 + r * r, r * r * 8);
+  if (lambda_host) std::memcpy(lambda_host, h.data() + 4 + 2 * r * r, r * 8);
   return ENMF_OK;
 }
 

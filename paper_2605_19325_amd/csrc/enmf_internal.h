@@ -264,6 +264,15 @@ int launch_sparse_cross(const SparseForm& f, const float* U, const float* V, int
 hipError_t launch_sparse_objective(const double* part, int nparts, const double* GU,
                                    const double* GV, int r, double* out, hipStream_t s);
 
+// ---- generalized rotation (k_grot.hip) ----
+int grot_pad(int r);
+// One workgroup runs every ADMM step of Algorithm alg:rsr.  ws: 7 (m + n)
+// grot_pad(r) doubles; out: 4 + 2 r^2 + r doubles (negativity mass before,
+// after, steps, unused, R1, R2, lambda).
+hipError_t launch_grot(const float* U, int64_t m, const float* V, int64_t n, int r, double rho0,
+                       double tol, int max_iter, double* ws, float* Uout, float* Vout, double* out,
+                       hipStream_t s);
+
 // ---- exterior nonnegative matrix completion (k_enmc.hip) ----
 // State of an eNMC solve on the device (scalars of the last check).
 struct EnmcState {

@@ -43,6 +43,10 @@ class RotateOpts(Structure):
                 ("check_every", c_int32)]
 
 
+class GrotOpts(Structure):
+    _fields_ = [("rho0", c_double), ("tol", c_double), ("max_iter", c_int32), ("reserved", c_int32)]
+
+
 class MaskArg(Structure):
     _fields_ = [("bits", c_void_p), ("ld_words", c_int64)]
 
@@ -99,6 +103,10 @@ SIGNATURES = [
     ("enmf_rotate", c_int32, [c_void_p, c_int64, c_int64, c_int32, c_void_p, c_void_p,
                               POINTER(RotateOpts), POINTER(c_double), POINTER(c_int32),
                               POINTER(c_double), POINTER(c_double)]),
+    ("enmf_rotate_general", c_int32, [c_void_p, c_int64, c_int64, c_int32, c_void_p, c_void_p,
+                                      POINTER(GrotOpts), POINTER(c_double), POINTER(c_double),
+                                      POINTER(c_double), POINTER(c_int32), POINTER(c_double),
+                                      POINTER(c_double)]),
     ("enmf_iterate", c_int32, [c_void_p, POINTER(Matrix), c_int32, c_void_p, c_void_p,
                                POINTER(IterOpts), POINTER(IterReport), c_void_p, c_int32]),
     ("enmf_objective_kkt", c_int32, [c_void_p, POINTER(Matrix), c_int32, c_void_p, c_void_p,
@@ -375,6 +383,24 @@ class Context:
         self._call(self._lib.enmf_rotate, m, n, r, _ptr(U), _ptr(V), byref(o), R, byref(steps),
                    byref(g0), byref(g1))
         return dict(R=[R[i] for i in range(r * r)], steps=steps.value, neg_mass_before=g0.value,
+                    neg_mass_after=g1.value)
+
+    def rotate_general(self, U, V, rho0=1.0, max_iter=500, tol=1e-10):
+        """Generalized rotation (R1, Lambda, R2) in place on U and V."""
+        m, r = U.shape
+        n = V.shape[0]
+        _factor(U, m, r, "U")
+        _factor(V, n, r, "V")
+        o = GrotOpts(rho0, tol, max_iter, 0)
+        R1 = (c_double * (r * r))()
+        R2 = (c_double * (r * r))()
+        lam = (c_double * r)()
+        steps = c_int32()
+        g0, g1 = c_double(), c_double()
+        self._call(self._lib.enmf_rotate_general, m, n, r, _ptr(U), _ptr(V), byref(o), R1, lam, R2,
+                   byref(steps), byref(g0), byref(g1))
+        return dict(R1=np.array(R1[:]).reshape(r, r), lam=np.array(lam[:]),
+                    R2=np.array(R2[:]).reshape(r, r), steps=steps.value, neg_mass_before=g0.value,
                     neg_mass_after=g1.value)
 
     def iterate(self, X, U, V, max_iter, ext_iters=10, pbcd_max_iter=5, pbcd_eps=0.0,

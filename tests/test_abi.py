@@ -27,7 +27,7 @@ def test_header_declares_the_boundary():
     for want in ("enmf_svd_init", "enmf_rotate", "enmf_iterate", "enmf_objective_kkt",
                  "enmf_xv", "enmf_xtu", "enmf_gram", "enmf_convert", "enmf_create",
                  "enmf_serve_start", "enmf_enmc_init", "enmf_enmc_grad", "enmf_enmc_iterate",
-                 "enmf_sparse_create", "enmf_sparse_destroy"):
+                 "enmf_sparse_create", "enmf_sparse_destroy", "enmf_rotate_general"):
         assert want in names
 
 
@@ -52,7 +52,7 @@ STRUCTS = [("enmf_matrix", enmf.Matrix), ("enmf_svd_opts", enmf.SvdOpts),
            ("enmf_rotate_opts", enmf.RotateOpts), ("enmf_iter_opts", enmf.IterOpts),
            ("enmf_iter_report", enmf.IterReport), ("enmf_kkt", enmf.Kkt),
            ("enmf_serve_opts", enmf.ServeOpts), ("enmf_request", enmf.Request),
-           ("enmf_mask", enmf.MaskArg)]
+           ("enmf_mask", enmf.MaskArg), ("enmf_grot_opts", enmf.GrotOpts)]
 
 
 def test_struct_layouts_match_header(tmp_path):
