@@ -92,17 +92,56 @@ struct GrotShared {
   double red[kG / kWave];
 };
 
-// sum over rows i of A[i][a] (B[i][b] + C[i][b]) into S.X[a][b] (zero padded).
+// S.X[a][b] = sum over rows i of A[i][a] (B[i][b] + C[i][b]) (zero padded
+// past r), on the float64 matrix cores: chunks of KP rows of both operands
+// are staged in S.X and S.T (free until the Procrustes step), and each wave
+// accumulates its 16 x 16 tiles over the chunks (lane (i, g) = (l % 16, l / 16)
+// supplies A[k][16 ti + i] and B[k][16 tj + i] of each 4-row step and receives
+// D[g + 4 v][i] in accumulator element v).
 template <int KP>
 __device__ void cross_gram(const double* A, const double* B, const double* C, int64_t N, int r,
                            GrotShared<KP>& S) {
-  for (int e = threadIdx.x; e < KP * KP; e += kG) {
-    const int a = e / KP, b = e % KP;
-    double s = 0.0;
-    if (a < r && b < r) {
-      for (int64_t i = 0; i < N; ++i) s = fma(A[i * KP + a], B[i * KP + b] + C[i * KP + b], s);
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int NTL = KP / 16;
+  constexpr int NTILE = NTL * NTL;
+  constexpr int PERW = (NTILE + 3) / 4;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int i = lane % 16, g = lane / 16;
+  d4 acc[PERW];
+#pragma unroll
+  for (int u = 0; u < PERW; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t row0 = 0; row0 < N; row0 += KP) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < KP * KP; e += kG) {
+      const int rr = e / KP, c = e % KP;
+      const int64_t row = row0 + rr;
+      const bool in = row < N && c < r;
+      S.X[rr][c] = in ? A[row * KP + c] : 0.0;
+      S.T[rr][c] = in ? B[row * KP + c] + C[row * KP + c] : 0.0;
     }
-    S.X[a][b] = s;
+    __syncthreads();
+#pragma unroll 2
+    for (int k0 = 0; k0 < KP; k0 += 4) {
+#pragma unroll
+      for (int u = 0; u < PERW; ++u) {
+        const int tile = w + 4 * u;
+        if (tile < NTILE) {
+          const int ti = tile / NTL, tj = tile % NTL;
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(S.X[k0 + g][16 * ti + i],
+                                                        S.T[k0 + g][16 * tj + i], acc[u], 0, 0, 0);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PERW; ++u) {
+    const int tile = w + 4 * u;
+    if (tile < NTILE) {
+      const int ti = tile / NTL, tj = tile % NTL;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S.X[16 * ti + g + 4 * v][16 * tj + i] = acc[u][v];
+    }
   }
 }
 
