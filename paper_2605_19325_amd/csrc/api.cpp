@@ -17,7 +17,7 @@ namespace {
 enum Slot {
   S_BP, S_AP, S_SPLIT, S_P, S_Q, S_GPART, S_G, S_H, S_RUPART, S_XPART, S_U2, S_GPU, S_GPV, S_STAT, S_UD, S_RES,
   S_Y, S_QM64, S_QM32, S_Z, S_QN64, S_QN32, S_TMP64, S_T, S_C, S_COLP, S_COLS, S_SIG, S_TU, S_TV,
-  S_W64, S_YA, S_ZA, S_BA, S_R, S_NEGP, S_WSQ, S_MPART,
+  S_W64, S_YA, S_ZA, S_R, S_WSQ, S_MPART,
   S_EX, S_ERU, S_ERV, S_EE, S_ERSS, S_ECU, S_ECV, S_EG, S_EGI, S_EST, S_ESTAT, S_SPX, S_SPG,
   S_GW, S_GOUT, N_SLOTS
 };
@@ -570,11 +570,9 @@ enmf_status enmf_rotate(enmf_ctx* c, int64_t m, int64_t n, int32_t r, float* U, 
   WS(W, double, S_W64, N * kp * 8);
   WS(Ya, double, S_YA, N * kp * 8);
   WS(Za, double, S_ZA, N * kp * 8);
-  WS(Ba, double, S_BA, N * kp * 8);
   WS(R, double, S_R, kp * kp * 8);
-  WS(negp, double, S_NEGP, (int64_t)admm_rows_blocks(N, kp) * 8);
   WS(wsq, double, S_WSQ, 512 * 8);
-  const int nbm = gram_blocks(N);
+  const int nbm = admm_rows_blocks(N, kp);
   WS(mpart, double, S_MPART, (int64_t)nbm * r * r * 8);
   WS(Mf, double, S_C, kp * kp * 8);
   WS(stat, double, S_STAT, 4 * 512 * 8);
@@ -599,8 +597,7 @@ enmf_status enmf_rotate(enmf_ctx* c, int64_t m, int64_t n, int32_t r, float* U, 
 
   int steps = 0;
   for (int t = 0; t < d.max_iter; ++t) {
-    CK(launch_admm_rows(W, N, r, kp, R, Ya, Za, Ba, c->st, t, negp, s));
-    CK(launch_tsgram(W, 1, kp, Ba, 1, kp, N, r, r, mpart, 0, nbm, s));
+    CK(launch_admm_rows(W, N, r, kp, R, Ya, Za, c->st, t, mpart, s));
     CK(launch_gram_finalize(mpart, nbm, r, r, kp, Mf, s));
     CK(launch_polar(Mf, r, kp, R, c->st, s));
     steps = t + 1;

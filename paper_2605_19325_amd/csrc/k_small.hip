@@ -280,76 +280,140 @@ __global__ void k_rho_init(const double* __restrict__ part, int nparts, int64_t 
   st->dR = INFINITY;
 }
 
-// Rows of the ADMM step (Algorithm 1): with WR = W R^k,
-//   Y <- Y + rho (Z - WR)        (the dual update of the previous step; step > 0)
-//   b = WR - Y / rho,  Z = prox_h(b) (eq. 7),  B = Z + Y / rho.
-// R is kp x kp float64 (zero padded), staged in LDS with the block's rows of
-// W; KP/8 threads share a row, 8 columns each, so every thread runs 8
-// independent dot products of length KP.  negpart[b] = sum h(WR) over the
-// block's rows.
+// One ADMM step of Algorithm 1 (eq. 7) on the rows of W = [U; V] (N x KP,
+// float64, zero padded), fused with the Procrustes operand: per row block,
+// W R (KP/8 threads per row, 8 columns each, R staged in LDS), then over the
+// block's rows as one flat, coalesced range
+//   Y <- Y + rho (Z - W R)  (Y = 0 at step 0),  b = W R - Y / rho,
+//   Z <- prox of h at b (eq. 7),  B = Z + Y / rho,
+// and B is only kept in LDS: the block adds the block's share of W^T B to its
+// r x r float64 partial (on the float64 matrix cores, 16 x 16 tiles over
+// 4-row steps; a thread per entry at KP = 8).  Blocks loop over row blocks
+// (grid of admm_rows_blocks); part[b] receives block b's partial.
 template <int KP> struct AdmmGeom {
   static constexpr int CG = KP / 8;        // threads per row
-  static constexpr int RB = kT / CG;       // rows per block
+  static constexpr int RB = kT / CG;       // rows per row block
 };
 
 template <int KP>
-__global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, int64_t N,
+__global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, int64_t N, int r,
                                                   const double* __restrict__ R,
                                                   double* __restrict__ Y, double* __restrict__ Z,
-                                                  double* __restrict__ B, const DevState* st,
-                                                  int step, double* __restrict__ negpart) {
+                                                  const DevState* st, int step,
+                                                  double* __restrict__ part) {
   using AG = AdmmGeom<KP>;
-  __shared__ double sh[kT / kWave];
+  constexpr int NE = (KP * KP + kT - 1) / kT;     // partial-Gram entries per thread (KP = 8)
+  constexpr bool MF = KP % 16 == 0;               // partial Gram on the float64 matrix cores
+  constexpr int RBP = (AG::RB + 3) / 4 * 4;       // rows padded to whole 4-row MFMA steps
+  constexpr int NTL = KP / 16, NTILE = NTL * NTL, PERW = (NTILE + 3) / 4;
+  typedef double d4 __attribute__((ext_vector_type(4)));
   __shared__ double Rs[KP * KP];
-  __shared__ double Ws[AG::RB * KP];
-  const int64_t row0 = (int64_t)blockIdx.x * AG::RB;
-  const int64_t nrow = N - row0 < AG::RB ? N - row0 : AG::RB;
+  __shared__ double Ws[RBP * KP];
+  __shared__ double Bs[RBP * KP];
   for (int e = threadIdx.x; e < KP * KP; e += kT) Rs[e] = R[e];
-  for (int e = threadIdx.x; e < AG::RB * KP; e += kT) Ws[e] = e < nrow * KP ? W[row0 * KP + e] : 0.0;
-  __syncthreads();
-  const int rr = threadIdx.x / AG::CG, c0 = 8 * (threadIdx.x % AG::CG);
-  const bool valid = rr < AG::RB && rr < nrow;
   const double rho = st->rho;
   const double irho = 1.0 / rho;
-  // W R for the block's rows (8 columns per thread), then back into Ws so
-  // that the elementwise steps below run over the rows as one flat,
-  // coalesced range
-  double wr[8];
+  const int rr = threadIdx.x / AG::CG, c0 = 8 * (threadIdx.x % AG::CG);
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int li = lane % 16, lg = lane / 16;
+  double gacc[MF ? 1 : NE];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) wr[e] = 0.0;
-  if (valid) {
-    const double* w = Ws + rr * KP;
-    for (int a = 0; a < KP; ++a) {
-      const double x = w[a];
-      const double* rrow = Rs + a * KP + c0;
+  for (int q = 0; q < (MF ? 1 : NE); ++q) gacc[q] = 0.0;
+  d4 macc[MF ? PERW : 1];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) wr[e] = fma(x, rrow[e], wr[e]);
+  for (int u = 0; u < (MF ? PERW : 1); ++u) macc[u] = d4{0.0, 0.0, 0.0, 0.0};
+  const int64_t nrb = (N + AG::RB - 1) / AG::RB;
+  for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
+    const int64_t row0 = rb * AG::RB;
+    const int64_t nrow = N - row0 < AG::RB ? N - row0 : AG::RB;
+    __syncthreads();
+    for (int e = threadIdx.x; e < RBP * KP; e += kT) {
+      Ws[e] = e < nrow * KP ? W[row0 * KP + e] : 0.0;
+      if (e >= AG::RB * KP) Bs[e] = 0.0;
+    }
+    __syncthreads();
+    double wr[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) wr[e] = 0.0;
+    if (rr < nrow) {
+      const double* w = Ws + rr * KP;
+      for (int a = 0; a < KP; ++a) {
+        const double x = w[a];
+        const double* rrow = Rs + a * KP + c0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) wr[e] = fma(x, rrow[e], wr[e]);
+      }
+    }
+    if (rr < AG::RB) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Bs[rr * KP + c0 + e] = wr[e];
+    }
+    __syncthreads();
+    const int cnt = (int)nrow * KP;
+    double* Yb = Y + row0 * KP;
+    double* Zb = Z + row0 * KP;
+    for (int e = threadIdx.x; e < cnt; e += kT) {
+      const double w = Bs[e];
+      double y = 0.0;
+      if (step > 0) y = Yb[e] + rho * (Zb[e] - w);
+      const double b = w - y * irho;
+      const double z = b > 0.0 ? b : (b >= -irho ? 0.0 : b + irho);
+      Yb[e] = y;
+      Zb[e] = z;
+      Bs[e] = z + y * irho;
+    }
+    __syncthreads();
+    if constexpr (MF) {
+      // tile (ti, tj) += sum over the block's rows of W[row][16 ti + i] B[row][16 tj + j];
+      // lane (i, g) supplies W[k + g][16 ti + i] and B[k + g][16 tj + i] of each 4-row step
+      for (int k0 = 0; k0 < RBP; k0 += 4) {
+#pragma unroll
+        for (int u = 0; u < PERW; ++u) {
+          const int tile = wv + 4 * u;
+          if (tile < NTILE) {
+            const int ti = tile / NTL, tj = tile % NTL;
+            macc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ws[(k0 + lg) * KP + 16 * ti + li],
+                                                           Bs[(k0 + lg) * KP + 16 * tj + li], macc[u],
+                                                           0, 0, 0);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const int e = threadIdx.x + q * kT;
+        if (e < KP * KP) {
+          const int a = e / KP, c = e % KP;
+          double s = gacc[q];
+          for (int row = 0; row < (int)nrow; ++row) s = fma(Ws[row * KP + a], Bs[row * KP + c], s);
+          gacc[q] = s;
+        }
+      }
     }
   }
-  __syncthreads();
-  if (valid) {
+  double* o = part + (int64_t)blockIdx.x * r * r;
+  if constexpr (MF) {
+    // lane (i, g) holds D[g + 4 v][i] of each of its tiles
 #pragma unroll
-    for (int e = 0; e < 8; ++e) Ws[rr * KP + c0 + e] = wr[e];
+    for (int u = 0; u < PERW; ++u) {
+      const int tile = wv + 4 * u;
+      if (tile < NTILE) {
+        const int ti = tile / NTL, tj = tile % NTL;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = 16 * ti + lg + 4 * v, c = 16 * tj + li;
+          if (a < r && c < r) o[a * r + c] = macc[u][v];
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = threadIdx.x + q * kT;
+      const int a = e / KP, c = e % KP;
+      if (e < KP * KP && a < r && c < r) o[a * r + c] = gacc[q];
+    }
   }
-  __syncthreads();
-  double neg = 0.0;
-  const int cnt = (int)nrow * KP;
-  double* Yb = Y + row0 * KP;
-  double* Zb = Z + row0 * KP;
-  double* Bb = B + row0 * KP;
-  for (int e = threadIdx.x; e < cnt; e += kT) {
-    const double w = Ws[e];
-    double y = 0.0;
-    if (step > 0) y = Yb[e] + rho * (Zb[e] - w);
-    const double b = w - y * irho;
-    const double z = b > 0.0 ? b : (b >= -irho ? 0.0 : b + irho);
-    Yb[e] = y;
-    Zb[e] = z;
-    Bb[e] = z + y * irho;
-    neg += w < 0.0 ? -w : 0.0;
-  }
-  neg = block_sum<kT>(neg, sh);
-  if (threadIdx.x == 0) negpart[blockIdx.x] = neg;
 }
 
 // R <- polar factor of M (r x r, leading dimension kp): the orthogonal
@@ -497,21 +561,20 @@ hipError_t launch_rho_init(const double* part, int nparts, int64_t N, int r, dou
 
 int admm_rows_blocks(int64_t N, int kp) {
   const int rb = kT / (kp / 8);
-  return (int)((N + rb - 1) / rb);
+  const int64_t b = (N + rb - 1) / rb;
+  return (int)(b < 2048 ? b : 2048);
 }
 
 hipError_t launch_admm_rows(const double* W, int64_t N, int r, int kp, const double* R, double* Y,
-                            double* Z, double* B, DevState* st, int step, double* negpart,
-                            hipStream_t s) {
-  (void)r;
+                            double* Z, DevState* st, int step, double* part, hipStream_t s) {
   dim3 g((unsigned)admm_rows_blocks(N, kp)), b(kT);
   switch (kp) {
-    case 8: hipLaunchKernelGGL((k_admm_rows<8>), g, b, 0, s, W, N, R, Y, Z, B, st, step, negpart); break;
-    case 16: hipLaunchKernelGGL((k_admm_rows<16>), g, b, 0, s, W, N, R, Y, Z, B, st, step, negpart); break;
-    case 32: hipLaunchKernelGGL((k_admm_rows<32>), g, b, 0, s, W, N, R, Y, Z, B, st, step, negpart); break;
-    case 48: hipLaunchKernelGGL((k_admm_rows<48>), g, b, 0, s, W, N, R, Y, Z, B, st, step, negpart); break;
-    case 64: hipLaunchKernelGGL((k_admm_rows<64>), g, b, 0, s, W, N, R, Y, Z, B, st, step, negpart); break;
-    default: hipLaunchKernelGGL((k_admm_rows<80>), g, b, 0, s, W, N, R, Y, Z, B, st, step, negpart); break;
+    case 8: hipLaunchKernelGGL((k_admm_rows<8>), g, b, 0, s, W, N, r, R, Y, Z, st, step, part); break;
+    case 16: hipLaunchKernelGGL((k_admm_rows<16>), g, b, 0, s, W, N, r, R, Y, Z, st, step, part); break;
+    case 32: hipLaunchKernelGGL((k_admm_rows<32>), g, b, 0, s, W, N, r, R, Y, Z, st, step, part); break;
+    case 48: hipLaunchKernelGGL((k_admm_rows<48>), g, b, 0, s, W, N, r, R, Y, Z, st, step, part); break;
+    case 64: hipLaunchKernelGGL((k_admm_rows<64>), g, b, 0, s, W, N, r, R, Y, Z, st, step, part); break;
+    default: hipLaunchKernelGGL((k_admm_rows<80>), g, b, 0, s, W, N, r, R, Y, Z, st, step, part); break;
   }
   return hipGetLastError();
 }
