@@ -139,24 +139,25 @@ __device__ __forceinline__ double eigvec(const JacobiT<MAXW>& sm, int a, int j) 
 // T is scratch.  Returns false (X untouched) when ||M||_F is 0 or not finite.
 //
 // Both products run on v_mfma_f64_16x16x4f64, 16 x 16 output tiles dealt
-// round robin to the 4 waves.  Lane (i, g) = (l % 16, l / 16) supplies
+// round robin to the NT / 64 waves of the workgroup (red: NT / 64 doubles).  Lane (i, g) = (l % 16, l / 16) supplies
 // A[i][g] and B[g][i] of each 16 x 4 by 4 x 16 step and receives
 // D[g + 4 v][i] in accumulator element v.
-template <int KP>
+template <int KP, int NT = kBlk>
 __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double* red) {
   typedef double d4 __attribute__((ext_vector_type(4)));
   constexpr int NTL = KP / 16;                  // tiles per side
   constexpr int NTILE = NTL * NTL;
-  constexpr int PERW = (NTILE + 3) / 4;         // tiles per wave
+  constexpr int NW = NT / kWave;                // waves
+  constexpr int PERW = (NTILE + NW - 1) / NW;   // tiles per wave
   static_assert(KP % 16 == 0, "polar_ns_block needs KP a multiple of 16");
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int i = lane % 16, g = lane / 16;
   double nrm = 0.0;
-  for (int e = threadIdx.x; e < KP * KP; e += kBlk) nrm = fma(X[e / KP][e % KP], X[e / KP][e % KP], nrm);
-  nrm = sqrt(block_sum<kBlk>(nrm, red));
+  for (int e = threadIdx.x; e < KP * KP; e += NT) nrm = fma(X[e / KP][e % KP], X[e / KP][e % KP], nrm);
+  nrm = sqrt(block_sum<NT>(nrm, red));
   if (!(nrm > 0.0) || !isfinite(nrm)) return false;
   const double sc = 1.5 / nrm;
-  for (int e = threadIdx.x; e < KP * KP; e += kBlk) X[e / KP][e % KP] *= sc;
+  for (int e = threadIdx.x; e < KP * KP; e += NT) X[e / KP][e % KP] *= sc;
   __syncthreads();
   for (int it = 0; it < 100; ++it) {
     // T = X^T X: tile (ti, tj) = sum over k of X[k][16 ti + i] X[k][16 tj + j].
@@ -169,7 +170,7 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
       for (int k0 = 0; k0 < KP; k0 += 4) {
 #pragma unroll
         for (int u = 0; u < PERW; ++u) {
-          const int tile = w + 4 * u;
+          const int tile = w + NW * u;
           if (tile < NTILE) {
             const int ti = tile / NTL, tj = tile % NTL;
             acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[k0 + g][16 * ti + i], X[k0 + g][16 * tj + i],
@@ -179,7 +180,7 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
       }
 #pragma unroll
       for (int u = 0; u < PERW; ++u) {
-        const int tile = w + 4 * u;
+        const int tile = w + NW * u;
         if (tile < NTILE) {
           const int ti = tile / NTL, tj = tile % NTL;
 #pragma unroll
@@ -199,7 +200,7 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
       for (int k0 = 0; k0 < KP; k0 += 4) {
 #pragma unroll
         for (int u = 0; u < PERW; ++u) {
-          const int tile = w + 4 * u;
+          const int tile = w + NW * u;
           if (tile < NTILE) {
             const int ti = tile / NTL, tj = tile % NTL;
             acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[16 * ti + i][k0 + g], T[k0 + g][16 * tj + i],
@@ -209,7 +210,7 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
       }
 #pragma unroll
       for (int u = 0; u < PERW; ++u) {
-        const int tile = w + 4 * u;
+        const int tile = w + NW * u;
         if (tile < NTILE) {
           const int ti = tile / NTL, tj = tile % NTL;
 #pragma unroll
@@ -221,10 +222,10 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
         }
       }
     }
-    d2 = block_sum<kBlk>(d2, red);   // also orders every read of X before the writes below
+    d2 = block_sum<NT>(d2, red);   // also orders every read of X before the writes below
 #pragma unroll
     for (int u = 0; u < PERW; ++u) {
-      const int tile = w + 4 * u;
+      const int tile = w + NW * u;
       if (tile < NTILE) {
         const int ti = tile / NTL, tj = tile % NTL;
 #pragma unroll

@@ -420,30 +420,37 @@ __global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, 
 // Procrustes solution C D^T of section 3.1 (W^T B = C S D^T), by
 // polar_ns_block.  Records ||R_new - R_old||_F in st->dR.  R is kp x kp,
 // zero padded.
+// Threads of k_polar_ns: one wave per 16 x 16 tile of the product (at least 4
+// waves), so that each wave runs one short MFMA chain per product.
+template <int KP> constexpr int polar_threads() {
+  return (KP / 16) * (KP / 16) * kWave < kT ? kT : (KP / 16) * (KP / 16) * kWave;
+}
+
 template <int KP>
-__global__ __launch_bounds__(kT) void k_polar_ns(const double* __restrict__ Mf, int r, int kp,
+__global__ __launch_bounds__(polar_threads<KP>()) void k_polar_ns(const double* __restrict__ Mf, int r, int kp,
                                                  double* __restrict__ R, DevState* st) {
   __shared__ double X[KP][KP + 1];
   __shared__ double T[KP][KP + 1];
-  __shared__ double red[kT / kWave];
-  for (int e = threadIdx.x; e < KP * KP; e += kT) {
+  constexpr int NT = polar_threads<KP>();
+  __shared__ double red[NT / kWave];
+  for (int e = threadIdx.x; e < KP * KP; e += NT) {
     const int a = e / KP, c = e % KP;
     X[a][c] = (a < r && c < r) ? Mf[a * kp + c] : 0.0;
   }
   __syncthreads();
-  if (!polar_ns_block<KP>(X, T, red)) {
+  if (!polar_ns_block<KP, NT>(X, T, red)) {
     if (threadIdx.x == 0) st->dR = 0.0;
     return;
   }
   double d2 = 0.0;
-  for (int e = threadIdx.x; e < kp * kp; e += kT) {
+  for (int e = threadIdx.x; e < kp * kp; e += NT) {
     const int a = e / kp, c = e % kp;
     const double v = (a < r && c < r) ? X[a][c] : 0.0;
     const double dv = v - R[e];
     d2 = fma(dv, dv, d2);
     R[e] = v;
   }
-  d2 = block_sum<kT>(d2, red);
+  d2 = block_sum<NT>(d2, red);
   if (threadIdx.x == 0) st->dR = sqrt(d2);
 }
 
@@ -582,10 +589,18 @@ hipError_t launch_admm_rows(const double* W, int64_t N, int r, int kp, const dou
 hipError_t launch_polar(const double* Mf, int r, int kp, double* R, DevState* st, hipStream_t s) {
   switch (pad_width(r)) {
     case 8:
-    case 16: hipLaunchKernelGGL((k_polar_ns<16>), dim3(1), dim3(kT), 0, s, Mf, r, kp, R, st); break;
-    case 32: hipLaunchKernelGGL((k_polar_ns<32>), dim3(1), dim3(kT), 0, s, Mf, r, kp, R, st); break;
-    case 48: hipLaunchKernelGGL((k_polar_ns<48>), dim3(1), dim3(kT), 0, s, Mf, r, kp, R, st); break;
-    default: hipLaunchKernelGGL((k_polar_ns<64>), dim3(1), dim3(kT), 0, s, Mf, r, kp, R, st); break;
+    case 16:
+      hipLaunchKernelGGL((k_polar_ns<16>), dim3(1), dim3(polar_threads<16>()), 0, s, Mf, r, kp, R, st);
+      break;
+    case 32:
+      hipLaunchKernelGGL((k_polar_ns<32>), dim3(1), dim3(polar_threads<32>()), 0, s, Mf, r, kp, R, st);
+      break;
+    case 48:
+      hipLaunchKernelGGL((k_polar_ns<48>), dim3(1), dim3(polar_threads<48>()), 0, s, Mf, r, kp, R, st);
+      break;
+    default:
+      hipLaunchKernelGGL((k_polar_ns<64>), dim3(1), dim3(polar_threads<64>()), 0, s, Mf, r, kp, R, st);
+      break;
   }
   return hipGetLastError();
 }
