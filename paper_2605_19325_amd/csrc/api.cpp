@@ -256,9 +256,11 @@ enmf_status xv_parts(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, f
 }
 
 // Q = X^T A as partials (A: m x k, ld k).
+// dec: the check and stop decision of the iteration, taken inside the
+// matrix-core product (see launch_xtu_mfma); ignored by the other forms.
 enmf_status xtu_parts(enmf_ctx* c, const enmf_matrix* X, const float* A, int k, float* Q_out,
                       Parts* out, hipEvent_t* ev = nullptr, bool packed = false,
-                      const GramJob* gj = nullptr) {
+                      const GramJob* gj = nullptr, const DecideArgs* dec = nullptr) {
   hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
   int ns = 1;
   if (const SparseX* sp = sparse_of(X)) {
@@ -273,7 +275,7 @@ enmf_status xtu_parts(enmf_ctx* c, const enmf_matrix* X, const float* A, int k, 
     WS(pack, void, S_AP, pb);
     WS(part, float, S_SPLIT, sb);
     CK(launch_xtu_mfma(X->data, X->dtype, X->m, X->n, X->ld, A, k, pack, part, Q_out, c->stream, 0,
-                       packed ? 0 : 1, &ns, &c->st->stop, e0, e1, gj));
+                       packed ? 0 : 1, &ns, &c->st->stop, e0, e1, gj, dec, c->st));
     out->p = ns > 1 ? part : Q_out;
   } else {
     const int kp = pad_width(k);
@@ -846,17 +848,19 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
         CK(launch_pbcd_decide(b.recU(cur), b.nbU, 0, t == 0, st, s));
       }
     }
-    // X^T U^(k+1) runs before the check of iteration k; the V pass takes the
-    // decision first and leaves V^k in place on a stop
-    TRY(xtu_parts(c, X, Ub[prev], r, b.Q, &pp, sample(1, k), mf, &gjH));
+    // X^T U^(k+1) runs before the check of iteration k.  The decision is
+    // taken by the matrix-core product's first block, else at the head of the
+    // V pass; either way the V pass leaves V^k in place on a stop.
+    TRY(xtu_parts(c, X, Ub[prev], r, b.Q, &pp, sample(1, k), mf, &gjH, mf ? &dec : nullptr));
+    const int vdec = mf ? 0 : kRowDecide;
     if (fixed) {
       CK(launch_rowupdate(V, V, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, o.pbcd_max_iter,
-                          kRowDecide | kRowUpdate | kRowFirst | kRowGram | kRowWriteCheck,
+                          vdec | kRowUpdate | kRowFirst | kRowGram | kRowWriteCheck,
                           b.recV(cur), b.gpV, nullptr, 0, nullptr, 0, s, poV, dec));
     } else {
       for (int t = 0; t < o.pbcd_max_iter; ++t) {
         const int fl = kRowUpdate | kRowWantPg | kRowGram | kRowWriteCheck |
-                       (t == 0 ? kRowFirst | kRowDecide : 0);
+                       (t == 0 ? kRowFirst | vdec : 0);
         CK(launch_rowupdate(V, V, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, 1, fl, b.recV(cur),
                             b.gpV, nullptr, 0, nullptr, 0, s, poV, dec));
         CK(launch_pbcd_decide(b.recV(cur), b.nbV, 1, t == 0, st, s));

@@ -32,6 +32,7 @@
 
 #include "dev_common.h"
 #include "enmf_internal.h"
+#include "decide.h"
 
 namespace enmf {
 
@@ -417,8 +418,16 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
                                                  int64_t chunks_per_split, int64_t nchunks, int vec,
                                                  float* __restrict__ out, int64_t split_stride,
     const int32_t* __restrict__ stop,
-    const double* __restrict__ gsrc, int gparts, int gkp, double* __restrict__ gdst) {
+    const double* __restrict__ gsrc, int gparts, int gkp, double* __restrict__ gdst,
+    DecideArgs dec, DevState* dst) {
   if (stop != nullptr && *stop) return;
+  // side job of the first block, before its own loads: the check and stop
+  // decision of the iteration (the blocks that start later see a stop and return)
+  if (dst != nullptr && blockIdx.x == 0 && blockIdx.y == 0) {
+    __shared__ double dsh[17 * (kT / kWave)];
+    __shared__ int dflag;
+    (void)check_decide<kT>(dec, 0, dst, true, dsh, &dflag);
+  }
   constexpr int NT = KP / 16;
   constexpr int CH = 3 * KP * kAtLd;
   __shared__ __align__(16) unsigned short As[2][CH];
@@ -553,8 +562,16 @@ __global__ __launch_bounds__(kT) void k_xtu_f32s(const float* __restrict__ X, in
                                                  int vec, float* __restrict__ out,
                                                  int64_t split_stride,
                                                  const int32_t* __restrict__ stop,
-    const double* __restrict__ gsrc, int gparts, int gkp, double* __restrict__ gdst) {
+    const double* __restrict__ gsrc, int gparts, int gkp, double* __restrict__ gdst,
+    DecideArgs dec, DevState* dst) {
   if (stop != nullptr && *stop) return;
+  // side job of the first block, before its own loads: the check and stop
+  // decision of the iteration (the blocks that start later see a stop and return)
+  if (dst != nullptr && blockIdx.x == 0 && blockIdx.y == 0) {
+    __shared__ double dsh[17 * (kT / kWave)];
+    __shared__ int dflag;
+    (void)check_decide<kT>(dec, 0, dst, true, dsh, &dflag);
+  }
   constexpr int NT = KP / 16;
   constexpr int CH = 3 * KP * kAtLd;
   __shared__ __align__(16) unsigned short As[2][CH];
@@ -926,8 +943,11 @@ hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t l
 hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* A,
                            int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
                            int do_pack, int* nsplit, const int32_t* stop,
-                           hipEvent_t ev0, hipEvent_t ev1, const GramJob* gj) {
+                           hipEvent_t ev0, hipEvent_t ev1, const GramJob* gj,
+                           const DecideArgs* dec, DevState* st) {
   const int KP = mfma_kp(k);
+  const DecideArgs da = dec ? *dec : DecideArgs();
+  DevState* dst_state = dec ? st : nullptr;
   const double* gsrc = gj ? gj->src : nullptr;
   const int gparts = gj ? gj->nparts : 0, gkp = gj ? gj->kp : 0;
   double* gdst = gj ? gj->dst : nullptr;
@@ -948,11 +968,11 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
     const unsigned short* At = reinterpret_cast<const unsigned short*>(pack);
     if (ev0) (void)hipEventRecord(ev0, s);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xtu_f32s<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
-      case 32: hipLaunchKernelGGL((k_xtu_f32s<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
-      case 48: hipLaunchKernelGGL((k_xtu_f32s<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
-      case 64: hipLaunchKernelGGL((k_xtu_f32s<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
-      default: hipLaunchKernelGGL((k_xtu_f32s<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
+      case 16: hipLaunchKernelGGL((k_xtu_f32s<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
+      case 32: hipLaunchKernelGGL((k_xtu_f32s<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
+      case 48: hipLaunchKernelGGL((k_xtu_f32s<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
+      case 64: hipLaunchKernelGGL((k_xtu_f32s<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
+      default: hipLaunchKernelGGL((k_xtu_f32s<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
     }
     if (ev1) (void)hipEventRecord(ev1, s);
   } else {
@@ -970,11 +990,11 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
     const unsigned short* At = reinterpret_cast<const unsigned short*>(pack);
     if (ev0) (void)hipEventRecord(ev0, s);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xtu_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
-      case 32: hipLaunchKernelGGL((k_xtu_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
-      case 48: hipLaunchKernelGGL((k_xtu_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
-      case 64: hipLaunchKernelGGL((k_xtu_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
-      default: hipLaunchKernelGGL((k_xtu_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst); break;
+      case 16: hipLaunchKernelGGL((k_xtu_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
+      case 32: hipLaunchKernelGGL((k_xtu_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
+      case 48: hipLaunchKernelGGL((k_xtu_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
+      case 64: hipLaunchKernelGGL((k_xtu_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
+      default: hipLaunchKernelGGL((k_xtu_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
     }
     if (ev1) (void)hipEventRecord(ev1, s);
   }
