@@ -1,8 +1,8 @@
 // The check and stop decision of one outer iteration (the KKT appendix and
 // the stopping rule of Algorithm 3), taken by one whole workgroup from the
-// per-block check records of both halves.  Shared by the row pass (which
-// takes it at its head) and the X^T U product (which can take it as a side
-// job in its first block).
+// per-block check records of both halves, and the phase decision at the start
+// of an iteration.  Shared by the row passes and the matrix-core X^T U product,
+// which takes the check as a side job in its first block.
 #pragma once
 
 #include <math.h>
@@ -133,6 +133,26 @@ __device__ inline bool check_decide(const DecideArgs& d, int final_check, DevSta
     }
   }
   return (fl & 1) != 0;
+}
+
+// Phase of an outer iteration (Algorithm 3): EXT while U or V has a negative
+// entry, from the negative counts in the latest records of both halves
+// (headU, headV).  The writer stores the phase and the count in st and clears
+// the PBCD stop flags.  NT threads; sh holds NT / 64 doubles.
+template <int NT>
+__device__ inline int take_phase(const double* headU, int nbU, const double* headV, int nbV,
+                                 DevState* st, bool writer, double* sh) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nbU; b += NT) s += headU[(int64_t)b * kRecFields + kRecNeg];
+  for (int b = threadIdx.x; b < nbV; b += NT) s += headV[(int64_t)b * kRecFields + kRecNeg];
+  s = block_sum<NT>(s, sh);
+  const int phase = s > 0.0 ? kPhaseExt : kPhaseHals;
+  if (writer && threadIdx.x == 0) {
+    st->negs = (int)s;
+    st->phase = phase;
+    st->pbcd_done[0] = st->pbcd_done[1] = 0;
+  }
+  return phase;
 }
 
 }  // namespace enmf

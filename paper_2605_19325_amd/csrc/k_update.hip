@@ -128,16 +128,7 @@ __global__ __launch_bounds__(Team<KP>::NT, (LOOP && KP == 64) ? 2 : 1) void k_ro
   const bool want_pg = (flags & kRowWantPg) != 0;
   int phase;
   if (flags & kRowHead) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nbU; b += TM::NT) s += headU[(int64_t)b * kRecFields + kRecNeg];
-    for (int b = threadIdx.x; b < nbV; b += TM::NT) s += headV[(int64_t)b * kRecFields + kRecNeg];
-    s = block_sum<TM::NT>(s, sh);
-    phase = s > 0.0 ? kPhaseExt : kPhaseHals;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      st->negs = (int)s;
-      st->phase = phase;
-      st->pbcd_done[0] = st->pbcd_done[1] = 0;
-    }
+    phase = take_phase<TM::NT>(headU, nbU, headV, nbV, st, blockIdx.x == 0, sh);
   } else {
     phase = st->phase;
   }
