@@ -37,7 +37,7 @@ SAMPLE_PERIOD = 8            # every 8th outer iteration's streaming kernels are
 # passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters' reading for a device copy of
 # known size (profiles/k_xv_f32s_k_xtu_f32s_image_patch_4096x10000_r49_hbm_traffic.txt).  They describe
 # the kernel source they were taken on and are reported only while it is unchanged.
-TRAFFIC = {"k_mfma_sha256_16": "9231eac801687350", "k_xv_f32s": 218.20e6, "k_xtu_f32s": 214.40e6}
+TRAFFIC = {"k_mfma_sha256_16": "83171d3a94a0728a", "k_xv_f32s": 218.09e6, "k_xtu_f32s": 214.49e6}
 
 
 def parse():
