@@ -337,7 +337,7 @@ enmf_status do_orth(enmf_ctx* c, const float* A32, int64_t N, int k, double* out
 enmf_status sparse_objective(enmf_ctx* c, const SparseX* sp, int r, const float* U, const float* V,
                              double* f) {
   hipStream_t s = c->stream;
-  WS(part, double, S_SPX, 1024 * 8);
+  WS(part, double, S_SPX, (int64_t)kSpCrossBlocks * 8);
   WS(g, double, S_SPG, 2 * r * r * 8);
   WS(o, double, S_SIG, 64 * 8);
   TRY(do_gram(c, U, 0, r, sp->csr.rows, r, r, g));

@@ -262,7 +262,9 @@ const SparseX* sparse_of(const enmf_matrix* X);
 // number of partials written to part (at most 1024).
 int launch_sparse_sumsq(const SparseForm& f, double* part, hipStream_t s);
 // Partials of sum over the nonzeros of x_ij (x_ij - 2 u_i . v_j) in float64
-// (U: rows x r, V: cols x r, float32); returns the number written (<= 1024).
+// (U: rows x r, V: cols x r, float32, r <= 64); returns the number written
+// (at most kSpCrossBlocks).
+constexpr int kSpCrossBlocks = 8192;
 int launch_sparse_cross(const SparseForm& f, const float* U, const float* V, int r, double* part,
                         hipStream_t s);
 // out[0] = sum of the nparts partials + sum_ab GU[a][b] GV[a][b] (r x r,

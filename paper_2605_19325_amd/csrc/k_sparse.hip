@@ -192,9 +192,9 @@ __global__ __launch_bounds__(kSt) void k_sp_objective(const double* __restrict__
   if (threadIdx.x == 0) out[0] = s;
 }
 
-int reduce_blocks(int64_t work, int64_t per_block) {
+int reduce_blocks(int64_t work, int64_t per_block, int64_t cap) {
   const int64_t b = (work + per_block - 1) / per_block;
-  return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+  return (int)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
 template <int G, int KC>
@@ -225,14 +225,14 @@ hipError_t launch_spmm(const SparseForm& f, const float* B, int k, float* part, 
 }
 
 int launch_sparse_sumsq(const SparseForm& f, double* part, hipStream_t s) {
-  const int nb = reduce_blocks(f.nnz, 4 * kSt);
+  const int nb = reduce_blocks(f.nnz, 4 * kSt, 1024);
   hipLaunchKernelGGL(k_sp_sumsq, dim3(nb), dim3(kSt), 0, s, f.val, f.nnz, part);
   return hipGetLastError() == hipSuccess ? nb : -1;
 }
 
 int launch_sparse_cross(const SparseForm& f, const float* U, const float* V, int r, double* part,
                         hipStream_t s) {
-  const int nb = reduce_blocks(f.nitems, kSt / kWave);
+  const int nb = reduce_blocks(f.nitems, kSt / kWave, kSpCrossBlocks);
   hipLaunchKernelGGL(k_sp_cross, dim3(nb), dim3(kSt), 0, s, f.item_p0, f.item_p1, f.item_row,
                      f.nitems, f.idx, f.val, U, V, r, part);
   return hipGetLastError() == hipSuccess ? nb : -1;
