@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only time the two X-streaming kernels (for hardware-counter passes)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
+    ap.add_argument("--streaming-only", action="store_true",
+                    help="run only the ratings-shape product timings (for counter runs)")
     ap.add_argument("--no-streaming", action="store_true",
                     help="skip the ratings-shaped streaming-kernel leg")
     ap.add_argument("--no-enmc", action="store_true", help="skip the matrix-completion (eNMC) leg")
@@ -302,6 +304,11 @@ def main():
     from paper_2605_19325_amd import enmf, inputs
 
     dev = torch.device("cuda:0")
+    if args.streaming_only:
+        ctx = enmf.Context(0)
+        print(json.dumps({"hbm_streaming": ratings_streaming(ctx, torch)}), flush=True)
+        ctx.close()
+        return
     X_np, r = inputs.config_image()
     m, n = X_np.shape
     om_np = inputs.omega(n, r + OVERSAMPLE, 1)
