@@ -142,9 +142,20 @@ __device__ inline bool check_decide(const DecideArgs& d, int final_check, DevSta
 template <int NT>
 __device__ inline int take_phase(const double* headU, int nbU, const double* headV, int nbV,
                                  DevState* st, bool writer, double* sh) {
+  // counts are whole numbers, so the order of the sum does not matter; the
+  // loads of both halves, two strides at a time, are in flight together
   double s = 0.0;
-  for (int b = threadIdx.x; b < nbU; b += NT) s += headU[(int64_t)b * kRecFields + kRecNeg];
-  for (int b = threadIdx.x; b < nbV; b += NT) s += headV[(int64_t)b * kRecFields + kRecNeg];
+  const int nbmax = nbU > nbV ? nbU : nbV;
+  for (int b0 = threadIdx.x; b0 < nbmax; b0 += 2 * NT) {
+    double x[4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int b = b0 + u * NT;
+      x[2 * u] = b < nbU ? headU[(int64_t)b * kRecFields + kRecNeg] : 0.0;
+      x[2 * u + 1] = b < nbV ? headV[(int64_t)b * kRecFields + kRecNeg] : 0.0;
+    }
+    s += (x[0] + x[1]) + (x[2] + x[3]);
+  }
   s = block_sum<NT>(s, sh);
   const int phase = s > 0.0 ? kPhaseExt : kPhaseHals;
   if (writer && threadIdx.x == 0) {

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(Team<KP>::NT, (LOOP && KP == 64) ? 2 : 1) void k_ro
   constexpr int T = TM::T;
   constexpr int NW = TM::NT / kWave;
   constexpr int NF = 3 + kRecChkN;
-  __shared__ double sG[KP * KP];
+  __shared__ __align__(16) double sG[KP * KP];
   __shared__ __align__(16) float sa[TM::RB][KP + 4];
   __shared__ float sgv[TM::RB][KP + 1];
   __shared__ double sT[KP >= 16 ? TM::RB : 1][KP + 1];
@@ -150,9 +150,31 @@ __global__ __launch_bounds__(Team<KP>::NT, (LOOP && KP == 64) ? 2 : 1) void k_ro
   const int nrow = (int)(rows - row0 < TM::RB ? rows - row0 : TM::RB);
   const bool valid = team < nrow;
 
+  // out = (row of `src` owned by this team) G, through the matrix cores when KP >= 16
+  auto times_g = [&](auto src, double* out) {
+    if constexpr (KP >= 16) {
+      block_times_g<KP>(src, sG, sT);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) out[e] = sT[team][c0 + e];
+    } else {
+      row_times_g<KP>(src[team], sG, c0, out);
+    }
+  };
   float a[8];
   double p[8];
-  stage_block<KP, KP + 4, KP + 1>(G, sG, A, sa, P, nsplit, pstride, sgv, row0, nrow, r, needG);
+  double t[8];
+  bool have_t = false;   // t == a G for the current a
+  // t = a G for the input rows, when the check at the input state or HALS
+  // wants it, is formed while the split partials of P are still arriving
+  // (not in the looping variant, whose registers would spill)
+  const bool early_t = !LOOP && needG && ((chk && pre) || (update && phase == kPhaseHals));
+  stage_block<KP, KP + 4, KP + 1>(G, sG, A, sa, P, nsplit, pstride, sgv, row0, nrow, r, needG,
+                                  [&] {
+                                    if (early_t) {
+                                      times_g(sa, t);
+                                      have_t = true;
+                                    }
+                                  });
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     a[e] = sa[team][c0 + e];
@@ -164,24 +186,14 @@ __global__ __launch_bounds__(Team<KP>::NT, (LOOP && KP == 64) ? 2 : 1) void k_ro
     sinv[threadIdx.x] = gjj > 0.0 ? 1.0 / gjj : 0.0;
   }
   __syncthreads();
-  // out = (row of `src` owned by this team) G, through the matrix cores when KP >= 16
-  auto times_g = [&](auto src, double* out) {
-    if constexpr (KP >= 16) {
-      block_times_g<KP>(src, sG, sT);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) out[e] = sT[team][c0 + e];
-    } else {
-      row_times_g<KP>(src[team], sG, c0, out);
-    }
-  };
-  double t[8];
-  bool have_t = false;   // t == a G for the current a
   if (chk && pre) {
+    if (!have_t) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) sa[team][c0 + e] = a[e];
-    __syncthreads();
-    times_g(sa, t);
-    have_t = true;
+      for (int e = 0; e < 8; ++e) sa[team][c0 + e] = a[e];
+      __syncthreads();
+      times_g(sa, t);
+      have_t = true;
+    }
     if (valid) ck.add(a, t, p, c0, r);
   }
 
@@ -316,10 +328,29 @@ __global__ __launch_bounds__(Team<KP>::NT, (LOOP && KP == 64) ? 2 : 1) void k_ro
     constexpr int PER = TM::RB * KP / TM::NT;
     const int cnt = nrow * r;
     float* base = Aout + row0 * r;
+    if (!LOOP && cnt % 4 == 0 && aligned16(Aout)) {
+      // 16-byte stores of four consecutive elements (row0 * r is a multiple
+      // of 4); the looping variant keeps element stores for its registers
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = threadIdx.x + u * TM::NT;
-      if (e < cnt) base[e] = sa[e / r][e % r];
+      for (int u = 0; u < PER / 4; ++u) {
+        const int e = 4 * ((int)threadIdx.x + u * TM::NT);
+        if (e < cnt) {
+          int row = e / r, col = e - row * r;
+          float x[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            x[c] = sa[row][col];
+            if (++col == r) { col = 0; ++row; }
+          }
+          *reinterpret_cast<float4*>(base + e) = make_float4(x[0], x[1], x[2], x[3]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + u * TM::NT;
+        if (e < cnt) base[e] = sa[e / r][e % r];
+      }
     }
   }
   if (pack != nullptr) {
@@ -490,6 +521,7 @@ hipError_t launch_rowupdate(const float* A, float* Aout, int64_t rows, int r, in
                             int sweeps, int flags, double* rec, double* gpart, const double* headU,
                             int nbU, const double* headV, int nbV, hipStream_t s,
                             const PackOut& po, const DecideArgs& dec) {
+  if (G != nullptr && (reinterpret_cast<uintptr_t>(G) & 15) != 0) return hipErrorInvalidValue;
   if (po.p != nullptr && (po.kp < 1 || po.kp > kp || po.c < 8 || po.c % 8 != 0 || po.ldt < po.c ||
                           (po.ldt * 2) % 16 != 0))
     return hipErrorInvalidValue;

@@ -87,79 +87,163 @@ __device__ __forceinline__ void stage_rows(const float* __restrict__ src, int ns
   __syncthreads();
 }
 
-// One row block's inputs in a single pass: G (KP x KP float64) into sG and,
-// as stage_rows does, the block's rows of A into sa and of the summed split
-// partials of P into sp (the latter two only with_g for G and P).  All
-// loads of G, A and the first partial are issued before any is consumed,
-// so their latencies overlap; the partial sums keep split order.
-template <int KP, int LDA, int LDP>
-__device__ __forceinline__ void stage_block(const double* __restrict__ G, double* sG,
-                                            const float* __restrict__ A, float (*sa)[LDA],
-                                            const float* __restrict__ P, int nsplit,
-                                            int64_t pstride, float (*sp)[LDP], int64_t row0,
-                                            int nrow, int r, bool with_g) {
+// A thread's PER elements of a block's contiguous range of cnt > 0 floats
+// at base: element e(u, c) = 4 (threadIdx.x + u NT) + c, u < PER / 4,
+// c < 4.  With VEC (base 16-byte aligned, cnt a multiple of 4) each group
+// of four is one 16-byte load.  Addresses past the range are clamped into
+// it, so every load is issued unconditionally and all stay in flight
+// together; the values of elements e >= cnt are unspecified and callers
+// never store them (scatter_quads).
+template <int NT, int PER, bool VEC>
+__device__ __forceinline__ void load_quads(const float* __restrict__ base, int cnt, float* v) {
+  static_assert(PER % 4 == 0, "whole quads per thread");
+#pragma unroll
+  for (int u = 0; u < PER / 4; ++u) {
+    const int e = 4 * ((int)threadIdx.x + u * NT);
+    if constexpr (VEC) {
+      const float4 x = *reinterpret_cast<const float4*>(base + (e < cnt ? e : 0));
+      v[4 * u] = x.x;
+      v[4 * u + 1] = x.y;
+      v[4 * u + 2] = x.z;
+      v[4 * u + 3] = x.w;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[4 * u + c] = base[e + c < cnt ? e + c : 0];
+    }
+  }
+}
+
+__device__ __forceinline__ bool aligned16(const void* p) {
+  return (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+}
+
+// Scatter of a thread's load_quads elements e < cnt into LDS rows of width r.
+template <int NT, int PER, int LD>
+__device__ __forceinline__ void scatter_quads(float (*dst)[LD], const float* v, int cnt, int r) {
+#pragma unroll
+  for (int u = 0; u < PER / 4; ++u) {
+    const int e = 4 * ((int)threadIdx.x + u * NT);
+    if (e < cnt) {
+      int row = e / r, col = e - row * r;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (e + c < cnt) dst[row][col] = v[4 * u + c];
+        if (++col == r) { col = 0; ++row; }
+      }
+    }
+  }
+}
+
+// One row block's inputs: G (KP x KP float64; G and sG 16-byte aligned)
+// into sG, the block's rows of A into sa and (with_g, as for G) the summed
+// split partials of P into sp; columns >= r and rows >= nrow are zero
+// (nrow >= 1).  The
+// loads of G, A, the first partial and the first batch of SB further
+// partials are issued together, with no branch between them.  Once G and A
+// are in LDS, mid() runs (all threads; it may use sG and sa) while the
+// partials are still in flight; then the partials are summed in split order
+// and stored.  Rows and partials are read in 16-byte groups (load_quads)
+// when their layout allows.
+template <int KP, int LDA, int LDP, bool VEC, typename MID>
+__device__ __forceinline__ void stage_block_impl(const double* __restrict__ G, double* sG,
+                                                 const float* __restrict__ A, float (*sa)[LDA],
+                                                 const float* __restrict__ P, int nsplit,
+                                                 int64_t pstride, float (*sp)[LDP], int64_t row0,
+                                                 int nrow, int r, bool with_g, MID&& mid) {
   using TM = Team<KP>;
   constexpr int PER = TM::RB * KP / TM::NT;
-  constexpr int PG = KP * KP / TM::NT;
+  constexpr int PG = KP * KP / TM::NT;   // Gram entries per thread, in pairs when even
+  constexpr bool G2 = PG % 2 == 0;
+  constexpr int SB = 8;
   static_assert(KP * KP % TM::NT == 0, "Gram tile must split evenly over the block");
   const int cnt = nrow * r;
-  double gv[PG];
-  float av[PER], pv[PER];
-  if (with_g) {
-#pragma unroll
-    for (int u = 0; u < PG; ++u) gv[u] = G[threadIdx.x + u * TM::NT];
-  }
   const float* abase = A + row0 * r;
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = threadIdx.x + u * TM::NT;
-    av[u] = e < cnt ? abase[e] : 0.f;
-  }
-  if (with_g) {
-    const float* pbase = P + row0 * r;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = threadIdx.x + u * TM::NT;
-      pv[u] = e < cnt ? pbase[e] : 0.f;
-    }
-    constexpr int SB = 8;
-    for (int sp0 = 1; sp0 < nsplit; sp0 += SB) {
-      float w[SB][PER];
-#pragma unroll
-      for (int b = 0; b < SB; ++b) {
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int e = threadIdx.x + u * TM::NT;
-          w[b][u] = (sp0 + b < nsplit && e < cnt) ? pbase[(int64_t)(sp0 + b) * pstride + e] : 0.f;
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < SB; ++b) {
-        if (sp0 + b < nsplit) {
-#pragma unroll
-          for (int u = 0; u < PER; ++u) pv[u] += w[b][u];
-        }
-      }
-    }
-  }
+  float av[PER];
   for (int e = threadIdx.x; e < TM::RB * KP; e += TM::NT) {
     sa[e / KP][e % KP] = 0.f;
     if (with_g) sp[e / KP][e % KP] = 0.f;
   }
-  if (with_g) {
+  if (!with_g) {
+    load_quads<TM::NT, PER, VEC>(abase, cnt, av);
+    __syncthreads();
+    scatter_quads<TM::NT, PER, LDA>(sa, av, cnt, r);
+    __syncthreads();
+    return;
+  }
+  const float* pbase = P + row0 * r;
+  double gv[PG];
+  float pv[PER], w[SB][PER];
+  // partials in batches of SB splits, all of a batch's loads issued before
+  // the first is added (the additions keep split order); splits past the
+  // last re-read the last one and are not added
+  auto load_batch = [&](int sp0) {
+#pragma unroll
+    for (int b = 0; b < SB; ++b) {
+      const int sb = sp0 + b < nsplit ? sp0 + b : nsplit - 1;
+      load_quads<TM::NT, PER, VEC>(pbase + (int64_t)sb * pstride, cnt, w[b]);
+    }
+  };
+  auto add_batch = [&](int sp0) {
+#pragma unroll
+    for (int b = 0; b < SB; ++b) {
+      if (sp0 + b < nsplit) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) pv[u] += w[b][u];
+      }
+    }
+  };
+  if constexpr (G2) {
+#pragma unroll
+    for (int u = 0; u < PG / 2; ++u) {
+      const double2 x = reinterpret_cast<const double2*>(G)[threadIdx.x + u * TM::NT];
+      gv[2 * u] = x.x;
+      gv[2 * u + 1] = x.y;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < PG; ++u) gv[u] = G[threadIdx.x + u * TM::NT];
+  }
+  load_quads<TM::NT, PER, VEC>(abase, cnt, av);
+  // G and A are issued first, so that their wait leaves the partials in flight
+  __builtin_amdgcn_sched_barrier(0);
+  load_quads<TM::NT, PER, VEC>(pbase, cnt, pv);
+  load_batch(1);   // unconditional: a branch here would make the waits for G and A cover it
+  if constexpr (G2) {
+#pragma unroll
+    for (int u = 0; u < PG / 2; ++u)
+      reinterpret_cast<double2*>(sG)[threadIdx.x + u * TM::NT] = make_double2(gv[2 * u], gv[2 * u + 1]);
+  } else {
 #pragma unroll
     for (int u = 0; u < PG; ++u) sG[threadIdx.x + u * TM::NT] = gv[u];
   }
   __syncthreads();
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = threadIdx.x + u * TM::NT;
-    if (e < cnt) {
-      sa[e / r][e % r] = av[u];
-      if (with_g) sp[e / r][e % r] = pv[u];
-    }
-  }
+  scatter_quads<TM::NT, PER, LDA>(sa, av, cnt, r);
   __syncthreads();
+  mid();
+  add_batch(1);
+  for (int sp0 = 1 + SB; sp0 < nsplit; sp0 += SB) {
+    load_batch(sp0);
+    add_batch(sp0);
+  }
+  scatter_quads<TM::NT, PER, LDP>(sp, pv, cnt, r);
+  __syncthreads();
+}
+
+template <int KP, int LDA, int LDP, typename MID>
+__device__ __forceinline__ void stage_block(const double* __restrict__ G, double* sG,
+                                            const float* __restrict__ A, float (*sa)[LDA],
+                                            const float* __restrict__ P, int nsplit,
+                                            int64_t pstride, float (*sp)[LDP], int64_t row0,
+                                            int nrow, int r, bool with_g, MID&& mid) {
+  // row0 is a multiple of the block's row count, so row0 * r keeps a
+  // 16-byte aligned matrix aligned; the choice is the same for the whole
+  // block, and each variant keeps all of its loads in flight together
+  const bool vec = nrow * r % 4 == 0 && aligned16(A) &&
+                   (!with_g || (aligned16(P) && pstride % 4 == 0));
+  if (vec)
+    stage_block_impl<KP, LDA, LDP, true>(G, sG, A, sa, P, nsplit, pstride, sp, row0, nrow, r, with_g, mid);
+  else
+    stage_block_impl<KP, LDA, LDP, false>(G, sG, A, sa, P, nsplit, pstride, sp, row0, nrow, r, with_g, mid);
 }
 
 // s[e] = sum_b row[b] G[b][c0+e] for the 8 columns c0..c0+7 (G symmetric).
@@ -268,9 +352,17 @@ __device__ __forceinline__ void block_reduce_fields(double* v, const int* kind, 
                                                     double* out) {
   constexpr int NW = NT / kWave;
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  // the same xor tree as wave_sum / wave_max / wave_min, with the fields
+  // innermost so that their lane exchanges are in flight together
 #pragma unroll
-  for (int f = 0; f < NF; ++f)
-    v[f] = kind[f] == 1 ? wave_max(v[f]) : (kind[f] == 2 ? wave_min(v[f]) : wave_sum(v[f]));
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    double x[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) x[f] = __shfl_xor(v[f], o);
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+      v[f] = kind[f] == 1 ? fmax(v[f], x[f]) : (kind[f] == 2 ? fmin(v[f], x[f]) : v[f] + x[f]);
+  }
   __syncthreads();
   if (lane == 0) {
 #pragma unroll
