@@ -345,23 +345,49 @@ struct CheckAcc {
   }
 };
 
+// v moved across lanes by the data-parallel-primitive pattern CTRL (a
+// v_mov_b32_dpp pair); lanes of rows outside ROWMASK keep `old`.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_move(double v, double old) {
+  const long long vi = __double_as_longlong(v), oi = __double_as_longlong(old);
+  const int lo = __builtin_amdgcn_update_dpp((int)oi, (int)vi, CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(oi >> 32), (int)(vi >> 32), CTRL, ROWMASK, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double reduce_op(int kind, double a, double b) {
+  return kind == 1 ? fmax(a, b) : (kind == 2 ? fmin(a, b) : a + b);
+}
+
 // Fixed-order reduction of NF per-thread values over a block of NT threads.
 // kind[f]: 0 sum, 1 max, 2 min.  The result lands in out[] of thread 0.
+// Within a wave the fields go through the same lane moves, all in
+// registers: pairs (quad_perm 1,0,3,2), pairs of pairs (quad_perm
+// 2,3,0,1), the two quads of each half row (row_half_mirror) and the two
+// halves of each row (row_mirror) leave every lane with its 16-lane row's
+// value; row 0 then joins row 1 and row 2 joins row 3 (row_bcast:15), rows
+// 0-1 join rows 2-3 (row_bcast:31), and lane 63 holds the wave's value.
+// The waves' values are combined in wave order by thread 0.
 template <int NT, int NF>
 __device__ __forceinline__ void block_reduce_fields(double* v, const int* kind, double* sh,
                                                     double* out) {
   constexpr int NW = NT / kWave;
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  // the same xor tree as wave_sum / wave_max / wave_min, with the fields
-  // innermost so that their lane exchanges are in flight together
 #pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    double x[NF];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) x[f] = __shfl_xor(v[f], o);
-#pragma unroll
-    for (int f = 0; f < NF; ++f)
-      v[f] = kind[f] == 1 ? fmax(v[f], x[f]) : (kind[f] == 2 ? fmin(v[f], x[f]) : v[f] + x[f]);
+  for (int f = 0; f < NF; ++f) {
+    double x = v[f];
+    const int k = kind[f];
+    x = reduce_op(k, x, dpp_move<0xB1, 0xF>(x, x));
+    x = reduce_op(k, x, dpp_move<0x4E, 0xF>(x, x));
+    x = reduce_op(k, x, dpp_move<0x141, 0xF>(x, x));
+    x = reduce_op(k, x, dpp_move<0x140, 0xF>(x, x));
+    // rows left out of a broadcast take the identity of the operation
+    x = reduce_op(k, x, dpp_move<0x142, 0xA>(x, k == 0 ? 0.0 : x));
+    x = reduce_op(k, x, dpp_move<0x143, 0xC>(x, k == 0 ? 0.0 : x));
+    const long long xi = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)xi, kWave - 1);
+    const int hi = __builtin_amdgcn_readlane((int)(xi >> 32), kWave - 1);
+    v[f] = __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
   }
   __syncthreads();
   if (lane == 0) {
@@ -373,8 +399,7 @@ __device__ __forceinline__ void block_reduce_fields(double* v, const int* kind, 
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       double t = sh[f * NW];
-      for (int i = 1; i < NW; ++i)
-        t = kind[f] == 1 ? fmax(t, sh[f * NW + i]) : (kind[f] == 2 ? fmin(t, sh[f * NW + i]) : t + sh[f * NW + i]);
+      for (int i = 1; i < NW; ++i) t = reduce_op(kind[f], t, sh[f * NW + i]);
       out[f] = t;
     }
   }
