@@ -367,7 +367,43 @@ __global__ __launch_bounds__(Team<KP>::NT, (LOOP && KP == 64) ? 2 : 1) void k_ro
       store_split_run8(v, pack + (row / pc) * 3 * term + (int64_t)c * pldt + row % pc, term);
     }
   }
-  if (gram && threadIdx.x < NTASK) {
+  if constexpr (KP >= 16) {
+    if (gram) {
+      // this row block's part, added to the block's running partial Gram:
+      // the upper 16 x 16 tiles of sa^T sa on the matrix cores (one wave per
+      // tile, round robin), stored as the upper 4 x 4 tiles that k_gram_fin
+      // combines.  Lane (i, g) supplies sa[k0 + g][16 TI + i] and
+      // sa[k0 + g][16 TJ + i] and receives entry (16 TI + g + 4 v, 16 TJ + i).
+      typedef double d4 __attribute__((ext_vector_type(4)));
+      constexpr int TB = KP / 16;
+      constexpr int NBT = TB * (TB + 1) / 2;
+      constexpr int NWG = TM::NT / kWave;
+      const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+      const int i = lane % 16, g = lane / 16;
+      double* ob = gpart + (int64_t)blockIdx.x * (16 * NTASK);
+      const bool again = rb != blockIdx.x;
+      for (int bt = wv; bt < NBT; bt += NWG) {
+        int TI = 0, rem = bt;
+        while (rem >= TB - TI) { rem -= TB - TI; ++TI; }
+        const int TJ = TI + rem;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int k0 = 0; k0 < TM::RB; k0 += 4)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)sa[k0 + g][16 * TI + i],
+                                                     (double)sa[k0 + g][16 * TJ + i], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int R = 16 * TI + g + 4 * v, C = 16 * TJ + i;
+          const int ti = R / 4, tj = C / 4;
+          if (ti <= tj) {
+            const int task = ti * NTILE - ti * (ti - 1) / 2 + (tj - ti);
+            double* o = ob + 16 * task + 4 * (R % 4) + (C % 4);
+            *o = again ? *o + acc[v] : acc[v];
+          }
+        }
+      }
+    }
+  } else if (gram && threadIdx.x < NTASK) {
     // this row block's part, added to the block's running partial Gram
     int ti, tj;
     gram_tile<KP>(threadIdx.x, ti, tj);

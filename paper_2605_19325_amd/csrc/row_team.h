@@ -278,20 +278,18 @@ __device__ __forceinline__ void block_times_g(const float (*A)[LDA], const doubl
   const int i = lane % 16, g = lane / 16;
   constexpr int PERW = (NTILE + NW - 1) / NW;
   __syncthreads();
-  // a wave's tiles advance together through k (independent MFMA chains)
+  // a wave's tiles one after the other, each one chain over k
   d4 acc[PERW];
 #pragma unroll
-  for (int u = 0; u < PERW; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-  for (int k0 = 0; k0 < KP; k0 += 4) {
-#pragma unroll
-    for (int u = 0; u < PERW; ++u) {
-      const int tile = w + NW * u;
-      if (tile < NTILE) {
-        const int ti = tile / TC, tj = tile % TC;
+  for (int u = 0; u < PERW; ++u) {
+    acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+    const int tile = w + NW * u;
+    if (tile < NTILE) {
+      const int ti = tile / TC, tj = tile % TC;
+#pragma unroll 4
+      for (int k0 = 0; k0 < KP; k0 += 4)
         acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)A[16 * ti + i][k0 + g],
                                                       sG[(k0 + g) * KP + 16 * tj + i], acc[u], 0, 0, 0);
-      }
     }
   }
 #pragma unroll
