@@ -172,6 +172,32 @@ def test_iterate_parity_many_rows(lib, m, n, r, iters, mode):
         assert abs(k[key] - ref[key]) <= 1e-6 * max(1.0, abs(ref[key])), key
 
 
+@pytest.mark.parametrize("m,n,r,iters,mode", [(1001, 517, 49, 1, 0), (1001, 517, 49, 12, 1),
+                                              (1001, 517, 13, 1, 0), (1001, 517, 13, 12, 1)])
+def test_iterate_parity_ragged_blocks(lib, m, n, r, iters, mode):
+    """Row counts whose last row block holds a number of entries that is not a
+    multiple of 4 (at r = 49, 32-row blocks: 9 rows of U and 5 of V in the
+    last block; at r = 13, 64-row blocks: 41 and 5), so that block stages
+    its rows and split partials element by element while the others read
+    16-byte groups.  r = 49 runs the matrix-core products (the stop decision
+    in X^T U), r = 13 the vector-ALU ones (the decision in the V pass).  One
+    exterior iteration and twelve of projection plus HALS, as for the tall
+    matrices above."""
+    say(f"iterate parity, {m}x{n} r={r}, {iters} iterations mode {mode}: ragged last row blocks")
+    X, _, _ = inputs.lowrank_plus_noise(m, n, r, seed=m + n + r)
+    om = inputs.omega(n, r + 10, r)
+    U0, V0, rso = _rotated_start(X, r, om)
+    Uo, Vo, ro = O.iterate(X, U0, V0, max_iter=iters, relerr_svd=rso, mode=mode)
+    U, V = to_dev(U0), to_dev(V0)
+    rep = lib.iterate(to_dev(X), U, V, max_iter=iters, relerr_svd=rso, mode=mode)
+    say(f"  |dU|/|U| {rel(host(U), Uo):.2e} |dV|/|V| {rel(host(V), Vo):.2e} "
+        f"ext {rep['ext_iters_done']} (oracle {ro['ext_iters_done']}) kkt {rep['kkt']:.6e} "
+        f"oracle {ro['kkt']:.6e}")
+    assert rep["iters"] == iters and rep["ext_iters_done"] == ro["ext_iters_done"]
+    assert rel(host(U), Uo) <= 1e-4 and rel(host(V), Vo) <= 1e-4
+    assert abs(rep["kkt"] - ro["kkt"]) <= 1e-4 * ro["kkt"]
+
+
 def test_iterate_pbcd_eps_path(lib, small):
     X, r, om = small
     say("iterate parity with the PBCD eps stop (multi-launch sweeps)")
