@@ -90,40 +90,81 @@ __device__ __forceinline__ void upper_tile(int task, int ntile, int& ti, int& tj
   tj = i + rem;
 }
 
+// v moved across lanes by the data-parallel-primitive pattern CTRL (a
+// v_mov_b32_dpp pair); lanes of rows outside ROWMASK keep `old`.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_move(double v, double old) {
+  const long long vi = __double_as_longlong(v), oi = __double_as_longlong(old);
+  const int lo = __builtin_amdgcn_update_dpp((int)oi, (int)vi, CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(oi >> 32), (int)(vi >> 32), CTRL, ROWMASK, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wave in a fixed order, all in registers: pairs
+// (quad_perm 1,0,3,2), pairs of pairs (quad_perm 2,3,0,1), the two quads of
+// each half row (row_half_mirror), the two halves of each row (row_mirror),
+// then row 0 into row 1 and row 2 into row 3 (row_bcast:15) and rows 0-1
+// into rows 2-3 (row_bcast:31).  The total is valid in lane 63.
+__device__ __forceinline__ double wave_sum_last(double x) {
+  x += dpp_move<0xB1, 0xF>(x, x);
+  x += dpp_move<0x4E, 0xF>(x, x);
+  x += dpp_move<0x141, 0xF>(x, x);
+  x += dpp_move<0x140, 0xF>(x, x);
+  x += dpp_move<0x142, 0xA>(x, 0.0);
+  x += dpp_move<0x143, 0xC>(x, 0.0);
+  return x;
+}
+
 // out (kp x kp, symmetric, float64) = sum of nparts partial Grams, each the
 // upper 4x4 tiles of one row block (16 doubles per tile, tiles in upper_tile
-// order).  One wave per entry: lane l adds parts l, l + 64, ... in order
-// (8 loads in flight), then the wave combines by butterfly.  The calling
-// wave takes entries wave, wave + nwaves, ...
+// order).  One wave per group of 4 consecutive entries (a 32-byte run of
+// each part): lane l adds parts l, l + 64, ... in order (4 parts, 8 loads, in
+// flight at a time), then the wave combines each entry (wave_sum_last).
+// The calling wave takes groups wave, wave + nwaves, ...
 __device__ __forceinline__ void gram_combine(const double* __restrict__ gpart, int nparts, int kp,
                                              double* __restrict__ out, int64_t wave,
                                              int64_t nwaves) {
   const int ntile = kp / 4;
   const int ne = 16 * (ntile * (ntile + 1) / 2);
   const int lane = threadIdx.x % kWave;
-  for (int64_t e = wave; e < ne; e += nwaves) {
-    double s = 0.0;
-    for (int b0 = lane; b0 < nparts; b0 += 8 * kWave) {
-      double v[8];
+  for (int64_t q = wave; 4 * q < ne; q += nwaves) {
+    const int64_t e0 = 4 * q;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b0 = lane; b0 < nparts; b0 += 4 * kWave) {
+      double2 v[4][2];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 4; ++u) {
         const int b = b0 + u * kWave;
-        v[u] = b < nparts ? gpart[(int64_t)b * ne + e] : 0.0;
+        const double2* src = reinterpret_cast<const double2*>(gpart + (int64_t)(b < nparts ? b : 0) * ne + e0);
+        v[u][0] = src[0];
+        v[u][1] = src[1];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (b0 + u * kWave < nparts) s += v[u];
+      for (int u = 0; u < 4; ++u) {
+        if (b0 + u * kWave < nparts) {
+          s[0] += v[u][0].x;
+          s[1] += v[u][0].y;
+          s[2] += v[u][1].x;
+          s[3] += v[u][1].y;
+        }
+      }
     }
-    s = wave_sum(s);
-    if (lane == 0) {
-      int ti, tj;
-      upper_tile((int)(e / 16), ntile, ti, tj);
-      const int ii = 4 * ti + (int)(e % 16) / 4, jj = 4 * tj + (int)(e % 4);
-      out[ii * kp + jj] = s;
-      out[jj * kp + ii] = s;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s[c] = wave_sum_last(s[c]);
+    if (lane == kWave - 1) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t e = e0 + c;
+        int ti, tj;
+        upper_tile((int)(e / 16), ntile, ti, tj);
+        const int ii = 4 * ti + (int)(e % 16) / 4, jj = 4 * tj + (int)(e % 4);
+        out[ii * kp + jj] = s[c];
+        out[jj * kp + ii] = s[c];
+      }
     }
   }
 }
+
 
 // Fixed-order block reductions for blocks of NT threads (NT a multiple of 64).
 // `sh` must hold NT/64 doubles.  The result is valid in every thread.

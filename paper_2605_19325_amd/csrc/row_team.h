@@ -343,16 +343,6 @@ struct CheckAcc {
   }
 };
 
-// v moved across lanes by the data-parallel-primitive pattern CTRL (a
-// v_mov_b32_dpp pair); lanes of rows outside ROWMASK keep `old`.
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ double dpp_move(double v, double old) {
-  const long long vi = __double_as_longlong(v), oi = __double_as_longlong(old);
-  const int lo = __builtin_amdgcn_update_dpp((int)oi, (int)vi, CTRL, ROWMASK, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(oi >> 32), (int)(vi >> 32), CTRL, ROWMASK, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
 __device__ __forceinline__ double reduce_op(int kind, double a, double b) {
   return kind == 1 ? fmax(a, b) : (kind == 2 ? fmin(a, b) : a + b);
 }
