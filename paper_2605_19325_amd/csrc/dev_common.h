@@ -100,20 +100,26 @@ __device__ __forceinline__ double dpp_move(double v, double old) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Sum over the 64 lanes of a wave in a fixed order, all in registers: pairs
-// (quad_perm 1,0,3,2), pairs of pairs (quad_perm 2,3,0,1), the two quads of
-// each half row (row_half_mirror), the two halves of each row (row_mirror),
-// then row 0 into row 1 and row 2 into row 3 (row_bcast:15) and rows 0-1
-// into rows 2-3 (row_bcast:31).  The total is valid in lane 63.
-__device__ __forceinline__ double wave_sum_last(double x) {
-  x += dpp_move<0xB1, 0xF>(x, x);
-  x += dpp_move<0x4E, 0xF>(x, x);
-  x += dpp_move<0x141, 0xF>(x, x);
-  x += dpp_move<0x140, 0xF>(x, x);
-  x += dpp_move<0x142, 0xA>(x, 0.0);
-  x += dpp_move<0x143, 0xC>(x, 0.0);
+// Reduction (KIND 0 sum, 1 max, 2 min) over the 64 lanes of a wave in a
+// fixed order, all in registers: pairs (quad_perm 1,0,3,2), pairs of pairs
+// (quad_perm 2,3,0,1), the two quads of each half row (row_half_mirror), the
+// two halves of each row (row_mirror), then row 0 into row 1 and row 2 into
+// row 3 (row_bcast:15) and rows 0-1 into rows 2-3 (row_bcast:31); rows left
+// out of a broadcast take the identity.  The result is valid in lane 63.
+// Every lane of the wave must be active.
+template <int KIND>
+__device__ __forceinline__ double wave_reduce_last(double x) {
+  auto op = [](double a, double b) { return KIND == 1 ? fmax(a, b) : (KIND == 2 ? fmin(a, b) : a + b); };
+  x = op(x, dpp_move<0xB1, 0xF>(x, x));
+  x = op(x, dpp_move<0x4E, 0xF>(x, x));
+  x = op(x, dpp_move<0x141, 0xF>(x, x));
+  x = op(x, dpp_move<0x140, 0xF>(x, x));
+  x = op(x, dpp_move<0x142, 0xA>(x, KIND == 0 ? 0.0 : x));
+  x = op(x, dpp_move<0x143, 0xC>(x, KIND == 0 ? 0.0 : x));
   return x;
 }
+
+__device__ __forceinline__ double wave_sum_last(double x) { return wave_reduce_last<0>(x); }
 
 // out (kp x kp, symmetric, float64) = sum of nparts partial Grams, each the
 // upper 4x4 tiles of one row block (16 doubles per tile, tiles in upper_tile
@@ -166,46 +172,32 @@ __device__ __forceinline__ void gram_combine(const double* __restrict__ gpart, i
 }
 
 
-// Fixed-order block reductions for blocks of NT threads (NT a multiple of 64).
-// `sh` must hold NT/64 doubles.  The result is valid in every thread.
-template <int NT>
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  v = wave_sum(v);
+// Fixed-order block reductions for blocks of NT threads (NT a multiple of 64,
+// every thread active): wave_reduce_last in each wave, then the waves' values
+// in wave order.  `sh` must hold NT/64 doubles.  The result is valid in every
+// thread.
+template <int KIND, int NT>
+__device__ __forceinline__ double block_reduce(double v, double* sh) {
+  v = wave_reduce_last<KIND>(v);
   const int w = threadIdx.x / kWave;
   __syncthreads();
-  if ((threadIdx.x % kWave) == 0) sh[w] = v;
+  if ((threadIdx.x % kWave) == kWave - 1) sh[w] = v;
   __syncthreads();
-  double t = 0.0;
+  double t = sh[0];
 #pragma unroll
-  for (int i = 0; i < NT / kWave; ++i) t += sh[i];
+  for (int i = 1; i < NT / kWave; ++i)
+    t = KIND == 1 ? fmax(t, sh[i]) : (KIND == 2 ? fmin(t, sh[i]) : t + sh[i]);
   return t;
 }
 
 template <int NT>
-__device__ __forceinline__ double block_max(double v, double* sh) {
-  v = wave_max(v);
-  const int w = threadIdx.x / kWave;
-  __syncthreads();
-  if ((threadIdx.x % kWave) == 0) sh[w] = v;
-  __syncthreads();
-  double t = sh[0];
-#pragma unroll
-  for (int i = 1; i < NT / kWave; ++i) t = fmax(t, sh[i]);
-  return t;
-}
+__device__ __forceinline__ double block_sum(double v, double* sh) { return block_reduce<0, NT>(v, sh); }
 
 template <int NT>
-__device__ __forceinline__ double block_min(double v, double* sh) {
-  v = wave_min(v);
-  const int w = threadIdx.x / kWave;
-  __syncthreads();
-  if ((threadIdx.x % kWave) == 0) sh[w] = v;
-  __syncthreads();
-  double t = sh[0];
-#pragma unroll
-  for (int i = 1; i < NT / kWave; ++i) t = fmin(t, sh[i]);
-  return t;
-}
+__device__ __forceinline__ double block_max(double v, double* sh) { return block_reduce<1, NT>(v, sh); }
+
+template <int NT>
+__device__ __forceinline__ double block_min(double v, double* sh) { return block_reduce<2, NT>(v, sh); }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
