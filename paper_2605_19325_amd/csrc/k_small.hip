@@ -95,22 +95,50 @@ __global__ __launch_bounds__(kT) void k_tsgram(const TA* __restrict__ A, int64_t
     }
 }
 
-// out (kp x kp, zero padded) = sum_b part[b] (ka x kb).  One wave per output
-// element: lane l adds partials l, l+64, ... in order, then a butterfly sum,
-// so the result does not depend on scheduling.
+// out (kp x kp, zero padded) = sum_b part[b] (ka x kb).  One wave per group
+// of 4 consecutive entries of the ka x kb partials: lane l adds partials l,
+// l + 64, ... in order (4 partials, 16 loads, in flight at a time), then the
+// wave sums each entry (wave_sum_last), so the result does not depend on
+// scheduling.  The padding entries are written as zeros by the grid.
 __global__ void k_gram_finalize(const double* __restrict__ part, int nparts, int ka, int kb, int kp,
                                 double* __restrict__ out) {
-  const int e = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int lane = threadIdx.x % kWave;
-  if (e >= kp * kp) return;
-  const int a = e / kp, c = e % kp;
-  double s = 0.0;
-  if (a < ka && c < kb) {
-    const int64_t ne = (int64_t)ka * kb;
-    for (int b = lane; b < nparts; b += kWave) s += part[b * ne + a * kb + c];
+  const int64_t ne = (int64_t)ka * kb;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < kp * kp; e += gridDim.x * blockDim.x) {
+    const int a = e / kp, c = e % kp;
+    if (a >= ka || c >= kb) out[e] = 0.0;
   }
-  s = wave_sum(s);
-  if (lane == 0) out[e] = s;
+  const int lane = threadIdx.x % kWave;
+  const int64_t e0 = 4 * ((int64_t)(blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  if (e0 >= ne) return;   // whole waves
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b0 = lane; b0 < nparts; b0 += 4 * kWave) {
+    double v[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = b0 + u * kWave;
+      const double* src = part + (int64_t)(b < nparts ? b : 0) * ne;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[u][c] = src[e0 + c < ne ? e0 + c : ne - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (b0 + u * kWave < nparts) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s[c] += v[u][c];
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) s[c] = wave_sum_last(s[c]);
+  if (lane == kWave - 1) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (e0 + c < ne) {
+        const int a = (int)((e0 + c) / kb), cc = (int)((e0 + c) % kb);
+        out[a * kp + cc] = s[c];
+      }
+    }
+  }
 }
 
 // out[i][c] = sum_a A[i][a] T[a][c] for c < kb (float64 arithmetic).
@@ -499,7 +527,7 @@ hipError_t launch_tsgram(const void* A, int a_is_f64, int64_t lda, const void* B
 
 hipError_t launch_gram_finalize(const double* part, int nparts, int ka, int kb, int kp, double* out,
                                 hipStream_t s) {
-  const int waves = kp * kp;
+  const int waves = (ka * kb + 3) / 4;
   hipLaunchKernelGGL(k_gram_finalize, dim3((waves + 3) / 4), dim3(256), 0, s, part, nparts, ka, kb,
                      kp, out);
   return hipGetLastError();
