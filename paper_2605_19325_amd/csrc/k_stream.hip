@@ -311,14 +311,29 @@ __global__ __launch_bounds__(kThreads) void k_sumsq(const void* __restrict__ Xv,
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// out[f] = sum_b part[b * stride + f] for f < nfields, b in order.
+// out[f] = sum_b part[b * stride + f] for f < nfields.  One wave per field:
+// lane l adds parts l, l + 64, ... in order (8 loads in flight), then the
+// wave sums its lanes (wave_sum_last), so the result does not depend on
+// scheduling.
 __global__ void k_sum_parts(const double* __restrict__ part, int nparts, int stride, int nfields,
                             double* __restrict__ out) {
-  const int f = threadIdx.x;
-  if (f >= nfields) return;
+  const int f = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  const int lane = threadIdx.x % kWave;
+  if (f >= nfields) return;   // whole waves
   double s = 0.0;
-  for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * stride + f];
-  out[f] = s;
+  for (int b0 = lane; b0 < nparts; b0 += 8 * kWave) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = b0 + u * kWave;
+      v[u] = part[(int64_t)(b < nparts ? b : 0) * stride + f];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (b0 + u * kWave < nparts) s += v[u];
+  }
+  s = wave_sum_last(s);
+  if (lane == kWave - 1) out[f] = s;
 }
 
 __device__ __forceinline__ unsigned short f32_to_bf16_rne(float x) {
@@ -536,7 +551,9 @@ hipError_t launch_sumsq_x(const void* X, int xt, int64_t m, int64_t n, int64_t l
 
 hipError_t launch_sum_parts(const double* part, int nparts, int stride, int nfields, double* out,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, nparts, stride, nfields, out);
+  if (nfields < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_parts, dim3((nfields + 3) / 4), dim3(256), 0, s, part, nparts, stride,
+                     nfields, out);
   return hipGetLastError();
 }
 
