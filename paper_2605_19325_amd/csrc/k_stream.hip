@@ -256,6 +256,7 @@ __global__ void k_pad_cols(const float* __restrict__ in, int64_t rows_in, int k,
 
 // Direct residual: part[b] = sum over this block's (i, j) of (X_ij - U_i . V_j)^2,
 // with the dot product and the square accumulated in float64.  Lane = column j.
+// KP is a multiple of 4.
 template <int XT, int KP>
 __global__ __launch_bounds__(kThreads) void k_residual(const void* __restrict__ Xv, int64_t m,
                                                        int64_t n, int64_t ld,
@@ -277,9 +278,12 @@ __global__ __launch_bounds__(kThreads) void k_residual(const void* __restrict__ 
   if (valid) {
     for (int64_t i = r0; i < r1; ++i) {
       const double* __restrict__ urow = Ud + i * KP;
-      double d = 0.0;
+      // four interleaved partial dot products (columns c mod 4), so that the
+      // fma chain per entry is KP / 4 long
+      double d4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int c = 0; c < KP; ++c) d = fma(urow[c], v[c], d);
+      for (int c = 0; c < KP; ++c) d4[c % 4] = fma(urow[c], v[c], d4[c % 4]);
+      const double d = (d4[0] + d4[1]) + (d4[2] + d4[3]);
       const double e = (double)to_f32<XT>(X[i * ld + j]) - d;
       acc = fma(e, e, acc);
     }
