@@ -393,17 +393,18 @@ __global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, 
     __syncthreads();
     if constexpr (MF) {
       // tile (ti, tj) += sum over the block's rows of W[row][16 ti + i] B[row][16 tj + j];
-      // lane (i, g) supplies W[k + g][16 ti + i] and B[k + g][16 tj + i] of each 4-row step
-      for (int k0 = 0; k0 < RBP; k0 += 4) {
+      // lane (i, g) supplies W[k + g][16 ti + i] and B[k + g][16 tj + i] of each 4-row step;
+      // a wave's tiles one after the other, each one chain over the rows
 #pragma unroll
-        for (int u = 0; u < PERW; ++u) {
-          const int tile = wv + 4 * u;
-          if (tile < NTILE) {
-            const int ti = tile / NTL, tj = tile % NTL;
+      for (int u = 0; u < PERW; ++u) {
+        const int tile = wv + 4 * u;
+        if (tile < NTILE) {
+          const int ti = tile / NTL, tj = tile % NTL;
+#pragma unroll 4
+          for (int k0 = 0; k0 < RBP; k0 += 4)
             macc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ws[(k0 + lg) * KP + 16 * ti + li],
                                                            Bs[(k0 + lg) * KP + 16 * tj + li], macc[u],
                                                            0, 0, 0);
-          }
         }
       }
     } else {
