@@ -137,13 +137,12 @@ __device__ __forceinline__ void scatter_quads(float (*dst)[LD], const float* v, 
 // One row block's inputs: G (KP x KP float64; G and sG 16-byte aligned)
 // into sG, the block's rows of A into sa and (with_g, as for G) the summed
 // split partials of P into sp; columns >= r and rows >= nrow are zero
-// (nrow >= 1).  The
-// loads of G, A, the first partial and the first batch of SB further
-// partials are issued together, with no branch between them.  Once G and A
-// are in LDS, mid() runs (all threads; it may use sG and sa) while the
-// partials are still in flight; then the partials are summed in split order
-// and stored.  Rows and partials are read in 16-byte groups (load_quads)
-// when their layout allows.
+// (nrow >= 1).  The loads of G, A, the first partial and the first batch of
+// SB further partials are issued together, with no branch between them.
+// Once G and A are in LDS, mid() runs (all threads; it may use sG and sa)
+// while the partials are still in flight; then the partials are summed in
+// split order and stored.  Rows and partials are read in 16-byte groups
+// (load_quads) when their layout allows.
 template <int KP, int LDA, int LDP, bool VEC, typename MID>
 __device__ __forceinline__ void stage_block_impl(const double* __restrict__ G, double* sG,
                                                  const float* __restrict__ A, float (*sa)[LDA],
@@ -343,42 +342,23 @@ struct CheckAcc {
   }
 };
 
-__device__ __forceinline__ double reduce_op(int kind, double a, double b) {
-  return kind == 1 ? fmax(a, b) : (kind == 2 ? fmin(a, b) : a + b);
-}
-
-// Fixed-order reduction of NF per-thread values over a block of NT threads.
-// kind[f]: 0 sum, 1 max, 2 min.  The result lands in out[] of thread 0.
-// Within a wave the fields go through the same lane moves, all in
-// registers: pairs (quad_perm 1,0,3,2), pairs of pairs (quad_perm
-// 2,3,0,1), the two quads of each half row (row_half_mirror) and the two
-// halves of each row (row_mirror) leave every lane with its 16-lane row's
-// value; row 0 then joins row 1 and row 2 joins row 3 (row_bcast:15), rows
-// 0-1 join rows 2-3 (row_bcast:31), and lane 63 holds the wave's value.
-// The waves' values are combined in wave order by thread 0.
+// Fixed-order reduction of NF per-thread values over a block of NT threads
+// (every thread active).  kind[f]: 0 sum, 1 max, 2 min.  Each wave reduces
+// every field with wave_reduce_last (register lane moves; the fields'
+// moves are independent and overlap), lane 63 stores the wave's values, and
+// thread 0 combines the waves in wave order.  The result lands in out[] of
+// thread 0.
 template <int NT, int NF>
 __device__ __forceinline__ void block_reduce_fields(double* v, const int* kind, double* sh,
                                                     double* out) {
   constexpr int NW = NT / kWave;
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
 #pragma unroll
-  for (int f = 0; f < NF; ++f) {
-    double x = v[f];
-    const int k = kind[f];
-    x = reduce_op(k, x, dpp_move<0xB1, 0xF>(x, x));
-    x = reduce_op(k, x, dpp_move<0x4E, 0xF>(x, x));
-    x = reduce_op(k, x, dpp_move<0x141, 0xF>(x, x));
-    x = reduce_op(k, x, dpp_move<0x140, 0xF>(x, x));
-    // rows left out of a broadcast take the identity of the operation
-    x = reduce_op(k, x, dpp_move<0x142, 0xA>(x, k == 0 ? 0.0 : x));
-    x = reduce_op(k, x, dpp_move<0x143, 0xC>(x, k == 0 ? 0.0 : x));
-    const long long xi = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_readlane((int)xi, kWave - 1);
-    const int hi = __builtin_amdgcn_readlane((int)(xi >> 32), kWave - 1);
-    v[f] = __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-  }
+  for (int f = 0; f < NF; ++f)
+    v[f] = kind[f] == 1 ? wave_reduce_last<1>(v[f])
+                        : (kind[f] == 2 ? wave_reduce_last<2>(v[f]) : wave_reduce_last<0>(v[f]));
   __syncthreads();
-  if (lane == 0) {
+  if (lane == kWave - 1) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) sh[f * NW + w] = v[f];
   }
@@ -387,7 +367,8 @@ __device__ __forceinline__ void block_reduce_fields(double* v, const int* kind, 
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       double t = sh[f * NW];
-      for (int i = 1; i < NW; ++i) t = reduce_op(kind[f], t, sh[f * NW + i]);
+      for (int i = 1; i < NW; ++i)
+        t = kind[f] == 1 ? fmax(t, sh[f * NW + i]) : (kind[f] == 2 ? fmin(t, sh[f * NW + i]) : t + sh[f * NW + i]);
       out[f] = t;
     }
   }
