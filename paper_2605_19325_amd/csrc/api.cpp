@@ -46,6 +46,9 @@ struct enmf_ctx {
   int pending_k[2][kTimingPairs] = {};            // outer iteration of each recorded pair
   double timing_sum[2] = {0.0, 0.0};
   int timing_n[2] = {0, 0};
+  // the iterate loop's look at the device stop flag (pinned copy and its event)
+  int32_t* stop_host = nullptr;
+  hipEvent_t stop_ev = nullptr;
 };
 
 
@@ -448,6 +451,8 @@ void enmf_destroy(enmf_ctx* c) {
     if (b.p) (void)hipFree(b.p);
   if (c->st) (void)hipFree(c->st);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  if (c->stop_ev) (void)hipEventDestroy(c->stop_ev);
+  if (c->stop_host) (void)hipHostFree(c->stop_host);
   delete c;
 }
 
@@ -803,6 +808,17 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
     mfma_pack_layout(X->dtype, 1, r, &poU.kp, &poU.c, &poU.ldt);
   }
 
+  if (!c->stop_host) {
+    void* ph = nullptr;
+    if (hipHostMalloc(&ph, 64) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, ENMF_ENOMEM, "pinned host allocation failed (stop flag)");
+    }
+    c->stop_host = static_cast<int32_t*>(ph);
+  }
+  if (!c->stop_ev) CK(hipEventCreateWithFlags(&c->stop_ev, hipEventDisableTiming));
+  bool stop_copied = false;
+
   auto sample = [&](int kind, int k) -> hipEvent_t* {
     if (c->timing_period <= 0 || k % c->timing_period != 0 || c->pending[kind] >= kTimingPairs)
       return nullptr;
@@ -867,10 +883,16 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
       }
     }
     if ((k + 1) % 32 == 0) {
-      int32_t stop = 0;
-      CK(hipMemcpyAsync(&stop, &st->stop, 4, hipMemcpyDeviceToHost, s));
-      CK(hipStreamSynchronize(s));
-      if (stop) break;
+      // The stop flag is copied to pinned memory here and looked at one check
+      // later, once the device has passed this point, so the queue never drains
+      // for the look; launches after a stop return at once on the device flag.
+      if (stop_copied) {
+        CK(hipEventSynchronize(c->stop_ev));
+        if (*c->stop_host) break;
+      }
+      CK(hipMemcpyAsync(c->stop_host, &st->stop, 4, hipMemcpyDeviceToHost, s));
+      CK(hipEventRecord(c->stop_ev, s));
+      stop_copied = true;
     }
   }
   DevState h;
