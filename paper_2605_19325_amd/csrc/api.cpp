@@ -561,6 +561,20 @@ enmf_status enmf_svd_init(enmf_ctx* c, const enmf_matrix* X, int32_t r, const en
   return ENMF_OK;
 }
 
+// The pinned word and event through which a loop looks at a device stop flag.
+enmf_status ensure_stop_copy(enmf_ctx* c) {
+  if (!c->stop_host) {
+    void* ph = nullptr;
+    if (hipHostMalloc(&ph, 64) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, ENMF_ENOMEM, "pinned host allocation failed (stop flag)");
+    }
+    c->stop_host = static_cast<int32_t*>(ph);
+  }
+  if (!c->stop_ev) CK(hipEventCreateWithFlags(&c->stop_ev, hipEventDisableTiming));
+  return ENMF_OK;
+}
+
 enmf_status enmf_rotate(enmf_ctx* c, int64_t m, int64_t n, int32_t r, float* U, float* V,
                         const enmf_rotate_opts* o, double* R_host, int32_t* steps_host,
                         double* neg_before_host, double* neg_after_host) {
@@ -602,17 +616,25 @@ enmf_status enmf_rotate(enmf_ctx* c, int64_t m, int64_t n, int32_t r, float* U, 
   CK(hipMemcpyAsync(R, eye.data(), kp * kp * 8, hipMemcpyHostToDevice, s));
   CK(hipStreamSynchronize(s));
 
-  int steps = 0;
+  // The tolerance stop is taken on the device by the polar step of each check
+  // step (later steps return at once).  The host looks at the stop flag one
+  // check late, through a pinned copy, so that its look never drains the queue.
+  TRY(ensure_stop_copy(c));
+  bool stop_copied = false;
+  int launched = 0;
   for (int t = 0; t < d.max_iter; ++t) {
     CK(launch_admm_rows(W, N, r, kp, R, Ya, Za, c->st, t, mpart, s));
     CK(launch_gram_finalize(mpart, nbm, r, r, kp, Mf, s));
-    CK(launch_polar(Mf, r, kp, R, c->st, s));
-    steps = t + 1;
-    if (d.tol > 0.0 && (steps % d.check_every == 0)) {
-      double dR = 0.0;
-      CK(hipMemcpyAsync(&dR, &c->st->dR, 8, hipMemcpyDeviceToHost, s));
-      CK(hipStreamSynchronize(s));
-      if (dR <= d.tol) break;
+    CK(launch_polar(Mf, r, kp, R, c->st, s, d.tol, d.check_every, t));
+    launched = t + 1;
+    if (d.tol > 0.0 && (launched % d.check_every == 0)) {
+      if (stop_copied) {
+        CK(hipEventSynchronize(c->stop_ev));
+        if (*c->stop_host) break;
+      }
+      CK(hipMemcpyAsync(c->stop_host, &c->st->rot_stop, 4, hipMemcpyDeviceToHost, s));
+      CK(hipEventRecord(c->stop_ev, s));
+      stop_copied = true;
     }
   }
   CK(launch_apply_small(W, 1, kp, m, r, R, kp, r, U, 0, r, s));
@@ -624,7 +646,10 @@ enmf_status enmf_rotate(enmf_ctx* c, int64_t m, int64_t n, int32_t r, float* U, 
   CK(hipMemcpyAsync(after, tot, 32, hipMemcpyDeviceToHost, s));
   std::vector<double> Rh(kp * kp);
   CK(hipMemcpyAsync(Rh.data(), R, kp * kp * 8, hipMemcpyDeviceToHost, s));
+  int32_t rs[2] = {0, 0};
+  CK(hipMemcpyAsync(rs, &c->st->rot_stop, 8, hipMemcpyDeviceToHost, s));
   CK(hipStreamSynchronize(s));
+  const int steps = rs[0] ? rs[1] : launched;
   if (R_host)
     for (int a = 0; a < r; ++a)
       for (int b = 0; b < r; ++b) R_host[a * r + b] = Rh[a * kp + b];
@@ -808,15 +833,7 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
     mfma_pack_layout(X->dtype, 1, r, &poU.kp, &poU.c, &poU.ldt);
   }
 
-  if (!c->stop_host) {
-    void* ph = nullptr;
-    if (hipHostMalloc(&ph, 64) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(c, ENMF_ENOMEM, "pinned host allocation failed (stop flag)");
-    }
-    c->stop_host = static_cast<int32_t*>(ph);
-  }
-  if (!c->stop_ev) CK(hipEventCreateWithFlags(&c->stop_ev, hipEventDisableTiming));
+  TRY(ensure_stop_copy(c));
   bool stop_copied = false;
 
   auto sample = [&](int kind, int k) -> hipEvent_t* {

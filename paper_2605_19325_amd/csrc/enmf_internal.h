@@ -36,7 +36,8 @@ struct DevState {
   int32_t mode;
   int32_t numeric_error;
   int32_t negs;          // negative entries in U and V at the last head
-  int32_t pad_[2];
+  int32_t rot_stop;      // set by a rotation step at a check within the tolerance; later steps return
+  int32_t rot_steps;     // ADMM steps of the rotation when rot_stop was set
 };
 
 // Per-block record written by the row-update kernel (float64 fields):
@@ -180,7 +181,10 @@ int admm_rows_blocks(int64_t N, int kp);
 hipError_t launch_admm_rows(const double* W, int64_t N, int r, int kp, const double* R, double* Y,
                             double* Z, DevState* st, int step, double* part, hipStream_t s);
 // R <- polar factor of Mf (r x r, leading dimension kp); R is kp x kp.
-hipError_t launch_polar(const double* Mf, int r, int kp, double* R, DevState* st, hipStream_t s);
+// tol > 0: at steps with (step + 1) % check_every == 0, a change ||R_new - R_old||_F <= tol
+// sets st->rot_stop and st->rot_steps = step + 1.
+hipError_t launch_polar(const double* Mf, int r, int kp, double* R, DevState* st, hipStream_t s,
+                        double tol = 0.0, int check_every = 1, int step = 0);
 
 // k_update.hip
 int factor_blocks(int64_t count);

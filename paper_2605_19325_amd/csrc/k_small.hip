@@ -306,6 +306,8 @@ __global__ void k_rho_init(const double* __restrict__ part, int nparts, int64_t 
   for (int b = 0; b < nparts; ++b) s += part[b];
   st->rho = s > 0.0 ? rho0 * sqrt((double)N * r) / sqrt(s) : 1.0;
   st->dR = INFINITY;
+  st->rot_stop = 0;
+  st->rot_steps = 0;
 }
 
 // One ADMM step of Algorithm 1 (eq. 7) on the rows of W = [U; V] (N x KP,
@@ -335,6 +337,7 @@ __global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, 
   constexpr int RBP = (AG::RB + 3) / 4 * 4;       // rows padded to whole 4-row MFMA steps
   constexpr int NTL = KP / 16, NTILE = NTL * NTL, PERW = (NTILE + 3) / 4;
   typedef double d4 __attribute__((ext_vector_type(4)));
+  if (st->rot_stop) return;   // the rotation stopped at an earlier check
   __shared__ double Rs[KP * KP];
   __shared__ double Ws[RBP * KP];
   __shared__ double Bs[RBP * KP];
@@ -457,18 +460,28 @@ template <int KP> constexpr int polar_threads() {
 
 template <int KP>
 __global__ __launch_bounds__(polar_threads<KP>()) void k_polar_ns(const double* __restrict__ Mf, int r, int kp,
-                                                 double* __restrict__ R, DevState* st) {
+                                                 double* __restrict__ R, DevState* st,
+                                                 double tol, int check_every, int step) {
   __shared__ double X[KP][KP + 1];
   __shared__ double T[KP][KP + 1];
   constexpr int NT = polar_threads<KP>();
   __shared__ double red[NT / kWave];
+  if (st->rot_stop) return;
+  // the change of R, and the tolerance stop at a check step (thread 0)
+  auto record = [&](double dR) {
+    st->dR = dR;
+    if (tol > 0.0 && (step + 1) % check_every == 0 && dR <= tol) {
+      st->rot_stop = 1;
+      st->rot_steps = step + 1;
+    }
+  };
   for (int e = threadIdx.x; e < KP * KP; e += NT) {
     const int a = e / KP, c = e % KP;
     X[a][c] = (a < r && c < r) ? Mf[a * kp + c] : 0.0;
   }
   __syncthreads();
   if (!polar_ns_block<KP, NT>(X, T, red)) {
-    if (threadIdx.x == 0) st->dR = 0.0;
+    if (threadIdx.x == 0) record(0.0);
     return;
   }
   double d2 = 0.0;
@@ -480,7 +493,7 @@ __global__ __launch_bounds__(polar_threads<KP>()) void k_polar_ns(const double* 
     R[e] = v;
   }
   d2 = block_sum<NT>(d2, red);
-  if (threadIdx.x == 0) st->dR = sqrt(d2);
+  if (threadIdx.x == 0) record(sqrt(d2));
 }
 
 template <typename TA, typename TB, int KP>
@@ -615,20 +628,25 @@ hipError_t launch_admm_rows(const double* W, int64_t N, int r, int kp, const dou
   return hipGetLastError();
 }
 
-hipError_t launch_polar(const double* Mf, int r, int kp, double* R, DevState* st, hipStream_t s) {
+hipError_t launch_polar(const double* Mf, int r, int kp, double* R, DevState* st, hipStream_t s,
+                        double tol, int check_every, int step) {
   switch (pad_width(r)) {
     case 8:
     case 16:
-      hipLaunchKernelGGL((k_polar_ns<16>), dim3(1), dim3(polar_threads<16>()), 0, s, Mf, r, kp, R, st);
+      hipLaunchKernelGGL((k_polar_ns<16>), dim3(1), dim3(polar_threads<16>()), 0, s, Mf, r, kp, R, st,
+                         tol, check_every, step);
       break;
     case 32:
-      hipLaunchKernelGGL((k_polar_ns<32>), dim3(1), dim3(polar_threads<32>()), 0, s, Mf, r, kp, R, st);
+      hipLaunchKernelGGL((k_polar_ns<32>), dim3(1), dim3(polar_threads<32>()), 0, s, Mf, r, kp, R, st,
+                         tol, check_every, step);
       break;
     case 48:
-      hipLaunchKernelGGL((k_polar_ns<48>), dim3(1), dim3(polar_threads<48>()), 0, s, Mf, r, kp, R, st);
+      hipLaunchKernelGGL((k_polar_ns<48>), dim3(1), dim3(polar_threads<48>()), 0, s, Mf, r, kp, R, st,
+                         tol, check_every, step);
       break;
     default:
-      hipLaunchKernelGGL((k_polar_ns<64>), dim3(1), dim3(polar_threads<64>()), 0, s, Mf, r, kp, R, st);
+      hipLaunchKernelGGL((k_polar_ns<64>), dim3(1), dim3(polar_threads<64>()), 0, s, Mf, r, kp, R, st,
+                         tol, check_every, step);
       break;
   }
   return hipGetLastError();
