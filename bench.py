@@ -37,7 +37,7 @@ SAMPLE_PERIOD = 8            # every 8th outer iteration's streaming kernels are
 # rocprofv3 passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters' reading for a device copy
 # of known size (profiles/k_xv_f32s_k_xtu_f32s_image_patch_4096x10000_r49_hbm_traffic.txt).  They describe
 # the kernel source they were taken on and are reported only while it is unchanged.
-TRAFFIC = {"k_mfma_sha256_16": "3c4459a81dc8c2ca", "k_xv_f32s": 222.37e6, "k_xtu_f32s": 217.04e6}
+TRAFFIC = {"k_mfma_sha256_16": "8930153b2b075505", "k_xv_f32s": 222.46e6, "k_xtu_f32s": 216.89e6}
 
 
 def parse():
