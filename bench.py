@@ -1,16 +1,21 @@
 """Benchmark of the eNMF hot path on one MI355X.
 
-One step = one whole solve (randomized SVD init, ADMM rotation, 500 outer
-iterations of the exterior phase + HALS, final objective/KKT check) of the
-image-patch workload: X = 4096 pixels x 10000 samples (float32), r = 49.
-Inputs are resident in HBM before the timed region.  Prints one JSON line.
+One step = one whole solve of the ratings workload, X = 100000 users x 20000
+items, r = 20: randomized SVD init, ADMM rotation (100 steps or the 1e-10
+tolerance), 100 outer iterations of the exterior phase + HALS with the check
+of every iteration, final objective.  The headline is the bfloat16-storage
+form (X streamed as bfloat16, float32 accumulation, float64 r x r steps); the
+plain float32 form of the same solve is reported beside it.  Inputs are
+resident in HBM before the timed region.  Prints one JSON line.
 
-Extra fields: time-to-relative-error (to within 1e-3 of the error the
-500-iteration run reaches), the streaming kernels' roofline figures, the
-matrix-completion, sparse-X (Reuters-shaped) and generalized-rotation legs,
-the served stream, and
-the FP64 oracle timed on a bounded sample of the same workload on the host
-cores.
+Extra fields: time to the oracle's relative error + 1e-3 (the stored FP64
+oracle solve of the same workload), iterate-only iterations/s, the roofline of
+the dominant streaming kernel timed inside the solves, the image-patch,
+small and spectrogram workloads, the ablation modes, the streaming products
+at the ratings shape, the matrix-completion, sparse-X and
+generalized-rotation legs, the served stream against the same requests solved
+one by one, and the FP64 oracle timed on a bounded sample of the headline
+workload on the host cores.
 """
 
 import argparse
@@ -26,18 +31,20 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "time-to-rel-err (s), iters/s, HBM GB/s frac; served p50/p99 solve latency"
-ITERS = 500
-RANK = 49
+ITERS = 100                  # outer iterations of the ratings solve
+RANK = 20
+OMEGA_SEED = 4
 OVERSAMPLE = 10
 POWER_ITERS = 2
 PEAK_FP32_TFLOPS = 157.3     # MI355X fp32 vector / matrix, dense
 PEAK_HBM_GBS = 8000.0
-SAMPLE_PERIOD = 8            # every 8th outer iteration's streaming kernels are event-timed
-# HBM bytes per launch of the float32 streaming kernels inside a solve of this workload, from two
-# rocprofv3 passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters' reading for a device copy
-# of known size (profiles/k_xv_f32s_k_xtu_f32s_image_patch_4096x10000_r49_hbm_traffic.txt).  They describe
-# the kernel source they were taken on and are reported only while it is unchanged.
-TRAFFIC = {"k_mfma_sha256_16": "8930153b2b075505", "k_xv_f32s": 222.46e6, "k_xtu_f32s": 216.89e6}
+SAMPLE_PERIOD = 4            # every 4th outer iteration's streaming kernels are event-timed
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+# HBM bytes per launch of the streaming kernels inside the ratings solve, from two rocprofv3
+# passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters' reading for a device copy of
+# known size (profiles/k_xv_k_xtu_ratings_100000x20000_r20_hbm_traffic.txt).  They describe the
+# kernel source they were taken on and are reported only while it is unchanged.
+TRAFFIC = {"k_mfma_sha256_16": None}
 
 
 def parse():
@@ -46,14 +53,17 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-rows", type=int, default=10000,
+                    help="rows of the ratings matrix the CPU oracle baseline runs on")
+    ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--kernels-only", action="store_true",
-                    help="only time the two X-streaming kernels (for hardware-counter passes)")
+                    help="only a short ratings solve per form and a calibration copy (counter runs)")
+    ap.add_argument("--headline-only", action="store_true", help="only the ratings solve")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
-    ap.add_argument("--streaming-only", action="store_true",
-                    help="run only the ratings-shape product timings (for counter runs)")
-    ap.add_argument("--no-streaming", action="store_true",
-                    help="skip the ratings-shaped streaming-kernel leg")
+    ap.add_argument("--no-image", action="store_true", help="skip the image-patch leg")
+    ap.add_argument("--no-small", action="store_true", help="skip the small-workload leg")
+    ap.add_argument("--no-spectrogram", action="store_true", help="skip the spectrogram leg")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the ablation-mode leg")
     ap.add_argument("--no-enmc", action="store_true", help="skip the matrix-completion (eNMC) leg")
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse-X (Reuters-shaped) leg")
     ap.add_argument("--no-grot", action="store_true", help="skip the generalized-rotation leg")
@@ -61,29 +71,53 @@ def parse():
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="open-loop arrival rate as a fraction of the closed-loop solves/s")
     ap.add_argument("--serve-slots", type=int, default=256)
+    ap.add_argument("--serve-plain", type=int, default=256,
+                    help="requests of the stream also solved one by one by the float32 form")
     return ap.parse_args()
 
 
-def cpu_baseline(X, om, iters):
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+def read_golden(name):
+    """Scalars of a stored oracle solve (tests/golden; written by the
+    scripts there, which call only the oracle)."""
+    out = {}
+    for line in open(os.path.join(GOLDEN, name)):
+        tok = line.split()
+        if len(tok) == 2 and not line.startswith("#"):
+            try:
+                out[tok[0]] = float(tok[1])
+            except ValueError:
+                out[tok[0]] = tok[1] == "True"
+    return out
+
+
+def cpu_baseline(X, om, rows, iters):
+    """The FP64 oracle, as it stands, on a bounded sample of the ratings solve:
+    its first `rows` rows (the same generator's rows), SVD init, 100-step
+    rotation and `iters` iterations, each phase scaled to the full shape by
+    the size it is linear in (X passes: m n; rotation: m + n)."""
     import threadpoolctl
 
     import oracle as O
+    m, n = X.shape
+    Xs = X[:rows].astype(np.float64)
     t0 = time.perf_counter()
-    Us, Vs, sigma, rsvd = O.svd_init_randomized(X, RANK, om, POWER_ITERS)
+    Us, Vs, sigma, rsvd = O.svd_init_randomized(Xs, RANK, om, POWER_ITERS)
     t1 = time.perf_counter()
     U, V, *_ = O.rotate(Us, Vs, 1.0, 100, 1e-10)
     t2 = time.perf_counter()
-    O.iterate(X, U, V, max_iter=iters, check_every=iters)
+    O.iterate(Xs, U, V, max_iter=iters, check_every=1)
     t3 = time.perf_counter()
+    fx, fr = m / rows, (m + n) / (rows + n)
     per_iter = (t3 - t2) / iters
-    full = (t1 - t0) + (t2 - t1) + ITERS * per_iter
+    full = fx * (t1 - t0) + fr * (t2 - t1) + ITERS * fx * per_iter
     threads = max([d.get("num_threads", 1) for d in threadpoolctl.threadpool_info()] or [1])
     return {
         "value": ITERS / full, "unit": "iters/s", "cores": threads, "kind": "oracle",
-        "sample": (f"svd init ({t1 - t0:.2f} s) + 100-step rotation ({t2 - t1:.2f} s) + {iters} "
-                   f"iterations ({t3 - t2:.2f} s) of the same 4096x10000 r=49 solve; value = "
-                   f"{ITERS} / (init + rotation + {ITERS} x measured s/iteration)"),
+        "sample": (f"FP64 oracle on the first {rows} of the {m} rows of the same ratings matrix: "
+                   f"svd init {t1 - t0:.2f} s, 100-step rotation {t2 - t1:.2f} s, {iters} "
+                   f"iterations (checked each) {t3 - t2:.2f} s; scaled to {m}x{n} by m n for the "
+                   f"init and the iterations and by m + n for the rotation; value = {ITERS} / "
+                   f"(init + rotation + {ITERS} iterations) = {ITERS} / {full:.1f} s"),
     }
 
 
@@ -99,23 +133,245 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def ratings_streaming(ctx, torch, m=100000, n=20000, r=20):
-    """HBM view of the streaming products at the ratings shape (X 100000 x 20000,
-    r = 20), where they are bound by HBM: bfloat16 (4 GB) and float32 (8 GB) X,
-    average device time per launch over 5 launches.  X's values do not change
-    the timing, so it is filled on the device."""
-    X = torch.rand((m, n), device="cuda:0", dtype=torch.float32)
-    f_xv, f_xtu = ctx.time_products(X, r, reps=5)
-    Xb = ctx.convert(X, torch.bfloat16)
-    del X
+def product_gbs(X, r, ms):
+    m, n = X.shape
+    return (m * n * X.element_size() + (m + n) * r * 4) / (ms * 1e-3) / 1e9
+
+
+def streaming(ctx, Xf, Xb, r):
+    """The streaming products alone at the ratings shape, where they are bound
+    by HBM: float32 (8 GB) and bfloat16 (4 GB) X, average device time per launch
+    over 5 launches, as GB/s of X against 8 TB/s."""
+    m, n = Xf.shape
+    f_xv, f_xtu = ctx.time_products(Xf, r, reps=5)
     b_xv, b_xtu = ctx.time_products(Xb, r, reps=5)
-    del Xb
-    torch.cuda.empty_cache()
-    out = {"workload": f"ratings-shaped X {m}x{n}, r={r}", "peak_gbs": PEAK_HBM_GBS}
+    out = {"workload": f"ratings X {m}x{n}, r={r}", "peak_gbs": PEAK_HBM_GBS}
     for name, ms, esz in (("bf16_xv", b_xv, 2), ("bf16_xtu", b_xtu, 2), ("f32_xv", f_xv, 4),
                           ("f32_xtu", f_xtu, 4)):
         gbs = m * n * esz / (ms * 1e-3) / 1e9
         out[name] = {"ms": round(ms, 4), "gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    return out
+
+
+def time_solves(ctx, torch, solve, steps, warmup):
+    for _ in range(warmup):
+        solve()
+    torch.cuda.synchronize()
+    ctx.kernel_timing(SAMPLE_PERIOD)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rep = solve()[2]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    xv_ms, xtu_ms, samples = ctx.kernel_timing(0)
+    return ms, xv_ms, xtu_ms, samples, rep
+
+
+def phase_split(ctx, torch, X, r, om, iters, **kw):
+    """One solve with events around its phases: (init + rotation s, iterate s, report)."""
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    U, V, sg, rsvd = ctx.svd_init(X, r, om, OVERSAMPLE, POWER_ITERS)
+    rot = ctx.rotate(U, V)
+    e[1].record()
+    kw.setdefault("relerr_svd", rsvd)
+    rep = ctx.iterate(X, U, V, max_iter=iters, **kw)
+    e[2].record()
+    torch.cuda.synchronize()
+    rep["rotation"] = rot
+    rep["relerr_svd"] = rsvd
+    return e[0].elapsed_time(e[1]) / 1e3, e[1].elapsed_time(e[2]) / 1e3, rep, U, V
+
+
+def time_to_target(ctx, torch, X, r, om, target, max_iter, reps=3):
+    """Wall time of a whole solve (SVD init launch to the first check at which
+    U, V >= 0 and the relative error is <= target), median of `reps` runs.
+    The in-loop relative error is against the X the solve streams."""
+    times, rep = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U, V, rep = ctx.solve(X, r, om, OVERSAMPLE, POWER_ITERS, max_iter=max_iter, check_every=1,
+                              relerr_svd=0.0, relerr_tol=target)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ok = rep["converged"] == 1 and rep["relerr"] <= target
+    return (float(np.median(times)) if ok else None), rep["iters"], U, V
+
+
+def ratings_form(ctx, torch, X, Xf, om, r, args, ref, target):
+    """One form (X's storage) of the ratings solve: timed steps, phase split,
+    time to the oracle's error, in-solve product timings."""
+    def solve():
+        return ctx.solve(X, r, om, OVERSAMPLE, POWER_ITERS, max_iter=ITERS, check_every=1)
+
+    ms, xv_ms, xtu_ms, samples, rep = time_solves(ctx, torch, solve, args.steps, args.warmup)
+    init_s, iter_s, rep2, U, V = phase_split(ctx, torch, X, r, om, ITERS, check_every=1)
+    k32 = ctx.objective_kkt(Xf, U, V, rep2["relerr_svd"])        # against the float32 X
+    tte, tte_iters, _, _ = time_to_target(ctx, torch, X, r, om, target, ITERS)
+    return {
+        "ms_per_solve": round(ms, 3), "iters_per_s": round(ITERS * 1e3 / ms, 2),
+        "iterate_iters_per_s": round(ITERS / iter_s, 2), "init_rotation_s": round(init_s, 5),
+        "time_to_relerr_s": None if tte is None else round(tte, 5), "iters_to_relerr": tte_iters,
+        "relerr_target": target,
+        "relerr_final": k32["relerr"], "kkt_final": k32["kkt"], "relerr_svd": rep2["relerr_svd"],
+        "oracle_relerr": ref["relerr"], "oracle_kkt": ref["kkt"],
+        "abs_relerr_diff_vs_oracle": abs(k32["relerr"] - ref["relerr"]),
+        "ext_iters": rep2["ext_iters_done"], "rotation_steps": rep2["rotation"]["steps"],
+        "xv_ms": round(xv_ms, 5), "xtu_ms": round(xtu_ms, 5), "samples": samples,
+        "xv_gbs": round(product_gbs(X, r, xv_ms), 1), "xtu_gbs": round(product_gbs(X, r, xtu_ms), 1),
+    }
+
+
+def roofline(X, r, form):
+    """Dominant kernel of a form: the slower of the two streaming products,
+    timed inside the timed solves; algorithmic bytes of one launch = X once
+    plus the factor read and the product written (float32)."""
+    m, n = X.shape
+    bf = X.element_size() == 2
+    names = ("k_xv_bf16", "k_xtu_bf16") if bf else ("k_xv_f32s", "k_xtu_f32s")
+    times = (form["xv_ms"], form["xtu_ms"])
+    d = 0 if times[0] >= times[1] else 1
+    alg = m * n * X.element_size() + (m + n) * r * 4
+    achieved = alg / (times[d] * 1e-3) / 1e9
+    traffic = None
+    if TRAFFIC.get("k_mfma_sha256_16") and kernel_source_hash() == TRAFFIC["k_mfma_sha256_16"]:
+        traffic = TRAFFIC.get(names[d])
+    other = alg / (times[1 - d] * 1e-3) / 1e9
+    return {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": names[d],
+        "algorithmic_bytes": alg, "launch_ms": round(times[d], 5),
+        "other_product": {"kernel": names[1 - d], "launch_ms": round(times[1 - d], 5),
+                          "achieved": round(other, 1), "frac": round(other / PEAK_HBM_GBS, 4)},
+    }
+
+
+def image_leg(ctx, torch, inputs, args):
+    """Image-patch workload 4096 x 10000, float32 X, r = 49, 500 iterations:
+    whole solves, and the time to the stored oracle solve's relative error
+    + 1e-3.  X (164 MB) fits the 256 MB last-level cache, so the product rates
+    are effective rates, not HBM measurements."""
+    dev = torch.device("cuda:0")
+    X_np, r = inputs.config_image()
+    X = torch.from_numpy(X_np).to(dev)
+    om = torch.from_numpy(inputs.omega(X.shape[1], r + OVERSAMPLE, 1)).to(dev)
+    ref = read_golden("image_oracle.txt")
+    iters = 500
+
+    def solve():
+        return ctx.solve(X, r, om, OVERSAMPLE, POWER_ITERS, max_iter=iters, check_every=1)
+
+    ms, xv_ms, xtu_ms, samples, rep = time_solves(ctx, torch, solve, max(2, args.steps // 2), 1)
+    init_s, iter_s, rep2, U, V = phase_split(ctx, torch, X, r, om, iters, check_every=1)
+    target = ref["relerr"] + 1e-3
+    tte, tte_iters, _, _ = time_to_target(ctx, torch, X, r, om, target, iters)
+    out = {
+        "workload": "image-patch X 4096x10000 fp32, r=49, 500 iterations per solve",
+        "ms_per_solve": round(ms, 3), "iters_per_s": round(iters * 1e3 / ms, 2),
+        "iterate_iters_per_s": round(iters / iter_s, 2), "init_rotation_s": round(init_s, 5),
+        "time_to_relerr_s": None if tte is None else round(tte, 5), "iters_to_relerr": tte_iters,
+        "relerr_target": target, "relerr_final": rep2["relerr"], "kkt_final": rep2["kkt"],
+        "oracle_relerr": ref["relerr"], "oracle_kkt": ref["kkt"],
+        "rel_f_diff_vs_oracle": abs(rep2["f"] - ref["f"]) / ref["f"],
+        "xv_ms": round(xv_ms, 5), "xtu_ms": round(xtu_ms, 5),
+        "xv_effective_gbs": round(product_gbs(X, r, xv_ms), 1),
+        "xtu_effective_gbs": round(product_gbs(X, r, xtu_ms), 1),
+        "rotation_steps": rep2["rotation"]["steps"],
+    }
+    del X
+    return out
+
+
+def small_leg(ctx, torch, inputs):
+    """Small workload 500 x 400, r = 10, 200 iterations: launch-bound (X is
+    0.8 MB); microseconds per outer iteration of enmf_iterate."""
+    dev = torch.device("cuda:0")
+    X_np, r = inputs.config_small()
+    X = torch.from_numpy(X_np).to(dev)
+    om = torch.from_numpy(inputs.omega(X.shape[1], r + OVERSAMPLE, 7)).to(dev)
+    iters = 200
+    for _ in range(2):
+        phase_split(ctx, torch, X, r, om, iters)
+    runs = [phase_split(ctx, torch, X, r, om, iters) for _ in range(5)]
+    init_s = float(np.median([a for a, _, _, _, _ in runs]))
+    iter_s = float(np.median([b for _, b, _, _, _ in runs]))
+    rep = runs[-1][2]
+    return {"workload": "small X 500x400 fp32, r=10, 200 iterations", "r": r,
+            "init_rotation_ms": round(init_s * 1e3, 4), "iterate_ms": round(iter_s * 1e3, 4),
+            "us_per_iteration": round(iter_s * 1e6 / iters, 3), "relerr_final": rep["relerr"],
+            "kkt_final": rep["kkt"]}
+
+
+def spectrogram_leg(ctx, torch, inputs):
+    """Spectrogram workload 513 x 20000, r = 40: the bfloat16-storage form
+    against the float32 form at equal error, the stored oracle solve's
+    relative error + 1e-3 (the oracle ran to KKT <= 1e-5)."""
+    dev = torch.device("cuda:0")
+    X_np, r = inputs.config_spectrogram()
+    Xf = torch.from_numpy(X_np).to(dev)
+    Xb = ctx.convert(Xf, torch.bfloat16)
+    om = torch.from_numpy(inputs.omega(X_np.shape[1], r + OVERSAMPLE, 3)).to(dev)
+    ref = read_golden("spectrogram_oracle.txt")
+    target = ref["relerr"] + 1e-3
+    out = {"workload": "spectrogram X 513x20000, r=40", "relerr_target": target,
+           "oracle_relerr": ref["relerr"]}
+    for name, X in (("bf16", Xb), ("f32", Xf)):
+        time_to_target(ctx, torch, X, r, om, target, 1500, reps=1)      # warm
+        tte, iters, U, V = time_to_target(ctx, torch, X, r, om, target, 1500)
+        k32 = ctx.objective_kkt(Xf, U, V)
+        out[name] = {"time_to_relerr_s": None if tte is None else round(tte, 5),
+                     "iters_to_relerr": iters, "relerr_at_stop": k32["relerr"],
+                     "kkt_at_stop": k32["kkt"]}
+    if out["bf16"]["time_to_relerr_s"] and out["f32"]["time_to_relerr_s"]:
+        out["f32_over_bf16_time"] = round(out["f32"]["time_to_relerr_s"] /
+                                          out["bf16"]["time_to_relerr_s"], 3)
+    return out
+
+
+def ablation_leg(ctx, torch, inputs):
+    """The ablation modes of the appendix tables (mode 0 the full method,
+    1 projection then HALS, 2 the fixed row step, 3 F-eNMF: stop once feasible)
+    from the same rotated start, on the image-patch (float32, 500 iterations)
+    and spectrogram (bfloat16, 1500 iterations) workloads: final relative error,
+    and the time from the first check to the first feasible check within the
+    stored mode-0 oracle error + 1e-3 (device clock of the check records)."""
+    dev = torch.device("cuda:0")
+    out = {}
+    cases = (("image", inputs.config_image, 1, "image_oracle.txt", 500, None),
+             ("spectrogram", inputs.config_spectrogram, 3, "spectrogram_oracle.txt", 1500,
+              torch.bfloat16))
+    for name, gen, seed, gold, iters, dt in cases:
+        X_np, r = gen()
+        X = torch.from_numpy(X_np).to(dev)
+        Xf = X
+        if dt is not None:
+            X = ctx.convert(Xf, dt)
+        om = torch.from_numpy(inputs.omega(X_np.shape[1], r + OVERSAMPLE, seed)).to(dev)
+        U0, V0, _, rsvd = ctx.svd_init(X, r, om, OVERSAMPLE, POWER_ITERS)
+        ctx.rotate(U0, V0)
+        target = read_golden(gold)["relerr"] + 1e-3
+        res = {"relerr_target": target}
+        for mode in (0, 1, 2, 3):
+            U, V = U0.clone(), V0.clone()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rep = ctx.iterate(X, U, V, max_iter=iters, check_every=1, relerr_svd=rsvd, mode=mode,
+                              trace_cap=iters + 1)
+            e1.record()
+            torch.cuda.synchronize()
+            tr = rep["trace"].cpu().numpy()
+            tr = tr[:int(np.count_nonzero(tr[:, 6]))]
+            hit = np.flatnonzero((tr[:, 2] <= target) & (tr[:, 7] == 0))
+            k32 = ctx.objective_kkt(Xf, U, V, rsvd)
+            res[f"mode{mode}"] = {
+                "iters": rep["iters"], "ext_iters": rep["ext_iters_done"],
+                "seconds": round(e0.elapsed_time(e1) / 1e3, 5), "relerr_final": k32["relerr"],
+                "kkt_final": k32["kkt"],
+                "time_to_relerr_s": round(float(tr[hit[0], 6] - tr[0, 6]) * 1e-9, 5) if hit.size else None,
+                "iters_to_relerr": int(tr[hit[0], 0]) if hit.size else None}
+        out[name] = res
+        del X, Xf
     return out
 
 
@@ -245,20 +501,27 @@ def grot_leg(ctx, torch, inputs, steps=500):
     return out
 
 
-def served(ctx, torch, inputs, enmf, count, load, slots):
+def served(ctx, torch, inputs, enmf, count, load, slots, plain):
     """Served stream: `count` requests (m, n log-uniform in [64, 2048], r in 4..32,
     bfloat16 X), each solved to relerr - relerr_svd <= 1e-3, KKT <= 1e-5 or 300
     iterations.  A closed-loop pass (all submitted at once) gives the saturated
     solves/s; an open-loop pass with Poisson arrivals at `load` times that rate
-    gives the latency distribution (submission to completion)."""
+    gives the latency distribution (submission to completion).  Beside it, the
+    first `plain` requests of the stream solved one at a time by the plain
+    float32 form (enmf_svd_init, enmf_rotate, enmf_iterate on float32 X, same
+    stopping rule): their service times, and the latencies of a one-at-a-time
+    server replayed over those service times at the same arrival rate."""
     dev = torch.device("cuda:0")
     reqs = inputs.serve_stream(count)
-    data = []
-    for q in reqs:
+    data, plain_data = [], []
+    for i, q in enumerate(reqs):
         X, _, _ = inputs.lowrank_plus_noise(q["m"], q["n"], q["r"], q["seed"])
-        Xb = ctx.convert(torch.from_numpy(X).to(dev), torch.bfloat16)
+        Xf = torch.from_numpy(X).to(dev)
+        Xb = ctx.convert(Xf, torch.bfloat16)
         om = torch.from_numpy(inputs.omega(q["n"], q["r"] + 10, q["seed"] + 1)).to(dev)
         data.append((Xb, q["r"], om))
+        if i < plain:
+            plain_data.append((Xf, q["r"], om))
     torch.cuda.synchronize()
     opts = dict(max_iter=300, relerr_tol=1e-3, kkt_tol=1e-5)
 
@@ -284,19 +547,63 @@ def served(ctx, torch, inputs, enmf, count, load, slots):
 
     wall_c, lat_c, iters_c, conv_c = run(None)
     sat = count / wall_c
-    arr = inputs.poisson_arrivals(count, load * sat, 7)
+    rate = load * sat
+    arr = inputs.poisson_arrivals(count, rate, 7)
     wall_o, lat_o, iters_o, conv_o = run(arr)
-    return {
+    out = {
         "requests": count, "dtype": "bf16", "slots": slots,
         "saturated_solves_per_s": round(sat, 2),
-        "load": load, "arrival_rate_per_s": round(load * sat, 2),
+        "load": load, "arrival_rate_per_s": round(rate, 2),
         "solves_per_s": round(count / wall_o, 2),
+        "sustained": bool(count / wall_o >= 0.97 * rate),
         "p50_latency_s": round(float(np.percentile(lat_o, 50)), 5),
         "p99_latency_s": round(float(np.percentile(lat_o, 99)), 5),
         "mean_iters": round(float(iters_o.mean()), 2), "converged_frac": round(conv_o, 4),
         "closed_loop_p50_s": round(float(np.percentile(lat_c, 50)), 5),
         "closed_loop_p99_s": round(float(np.percentile(lat_c, 99)), 5),
     }
+    if plain_data:
+        for Xf, r, om in plain_data[:4]:                  # warm the kernels of each shape class
+            ctx.solve(Xf, r, om, max_iter=5)
+        svc, its = [], []
+        for Xf, r, om in plain_data:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, rep = ctx.solve(Xf, r, om, **opts)
+            torch.cuda.synchronize()
+            svc.append(time.perf_counter() - t0)
+            its.append(rep["iters"])
+        svc = np.array(svc)
+        done, lat = 0.0, []
+        for a, t in zip(arr[:len(svc)], svc):
+            done = max(done, a) + t
+            lat.append(done - a)
+        out["plain_fp32"] = {
+            "requests": len(svc), "mean_iters": round(float(np.mean(its)), 2),
+            "service_p50_s": round(float(np.percentile(svc, 50)), 5),
+            "service_p99_s": round(float(np.percentile(svc, 99)), 5),
+            "one_at_a_time_solves_per_s": round(len(svc) / float(svc.sum()), 2),
+            "replayed_p50_latency_s": round(float(np.percentile(lat, 50)), 5),
+            "replayed_p99_latency_s": round(float(np.percentile(lat, 99)), 5),
+            "served_p50_same_requests_s": round(float(np.percentile(lat_o[:len(svc)], 50)), 5),
+            "served_p99_same_requests_s": round(float(np.percentile(lat_o[:len(svc)], 99)), 5),
+        }
+    return out
+
+
+def kernels_only(ctx, torch, Xf, Xb, om, r):
+    """For hardware-counter passes: a 10-iteration ratings solve per form (the
+    products carry their side jobs, as in the timed solves), then a plain
+    device copy of the float32 X (known bytes) to calibrate the counters."""
+    for X in (Xb, Xf):
+        ctx.solve(X, r, om, OVERSAMPLE, POWER_ITERS, max_iter=10, check_every=1)
+    torch.cuda.synchronize()
+    Y = torch.empty_like(Xb)
+    for _ in range(10):
+        Y.copy_(Xb)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": 2 * Xb.numel() * Xb.element_size(),
+                      "m": Xf.shape[0], "n": Xf.shape[1], "r": r}), flush=True)
 
 
 def main():
@@ -310,115 +617,69 @@ def main():
     from paper_2605_19325_amd import enmf, inputs
 
     dev = torch.device("cuda:0")
-    if args.streaming_only:
-        ctx = enmf.Context(0)
-        print(json.dumps({"hbm_streaming": ratings_streaming(ctx, torch)}), flush=True)
-        ctx.close()
-        return
-    X_np, r = inputs.config_image()
-    m, n = X_np.shape
-    om_np = inputs.omega(n, r + OVERSAMPLE, 1)
     ctx = enmf.Context(0)
-    X = torch.from_numpy(X_np).to(dev)
+    X_np = inputs.ratings()
+    m, n = X_np.shape
+    r = RANK
+    om_np = inputs.omega(n, r + OVERSAMPLE, OMEGA_SEED)
+    Xf = torch.from_numpy(X_np).to(dev)
+    Xb = ctx.convert(Xf, torch.bfloat16)
     om = torch.from_numpy(om_np).to(dev)
     torch.cuda.synchronize()
     if args.kernels_only:
-        xv_ms, xtu_ms = ctx.time_products(X, r, reps=20)
-        # a short solve: its products carry the Gram side jobs, as in the timed solves
-        ctx.solve(X, r, om, OVERSAMPLE, POWER_ITERS, max_iter=40, check_every=1)
-        torch.cuda.synchronize()
-        # a plain device copy of X (known bytes) to calibrate the HBM counters
-        Y = torch.empty_like(X)
-        for _ in range(20):
-            Y.copy_(X)
-        torch.cuda.synchronize()
-        print(json.dumps({"xv_ms": xv_ms, "xtu_ms": xtu_ms, "m": m, "n": n, "r": r,
-                          "copy_bytes": 2 * X.numel() * X.element_size()}), flush=True)
+        kernels_only(ctx, torch, Xf, Xb, om, r)
         return
-
-    def step(trace_cap=0):
-        U, V, rep = ctx.solve(X, r, om, OVERSAMPLE, POWER_ITERS, max_iter=ITERS, check_every=1,
-                              trace_cap=trace_cap)
-        return U, V, rep
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    # the solves sample their streaming kernels with HIP events on the library stream
-    ctx.kernel_timing(SAMPLE_PERIOD)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    xv_ms, xtu_ms, samples = ctx.kernel_timing(0)
-
-    # one traced solve (untimed) for time-to-relative-error and the final figures
-    s0 = torch.cuda.Event(enable_timing=True)
-    s1 = torch.cuda.Event(enable_timing=True)
-    s0.record()
-    U, V, svd_sigma, rsvd = ctx.svd_init(X, r, om, OVERSAMPLE, POWER_ITERS)
-    rot = ctx.rotate(U, V)
-    s1.record()
-    rep = ctx.iterate(X, U, V, max_iter=ITERS, check_every=1, relerr_svd=rsvd, trace_cap=ITERS + 1)
-    torch.cuda.synchronize()
-    init_s = s0.elapsed_time(s1) / 1e3
-    tr = rep["trace"].cpu().numpy()
-    nrec = int(np.count_nonzero(tr[:, 6]))
-    tr = tr[:nrec]
-    target = rep["relerr"] + 1e-3
-    hit = np.flatnonzero((tr[:, 2] <= target) & (tr[:, 7] == 0))
-    tte = init_s + (tr[hit[0], 6] - tr[0, 6]) * 1e-9 if hit.size else None
-
-    # dominant kernels: the two X-streaming products at width r, timed inside the solves.
-    # Both run as three-term bfloat16 splits on the matrix cores, whose floor here (six term
-    # products at the padded width) lies below the HBM floor, so the bound is HBM: the
-    # algorithmic bytes of one launch are X, the factor read and the product written.
-    flops = 2.0 * m * n * r
-    xbytes = m * n * X.element_size()
-    dom_ms = max(xv_ms, xtu_ms)
-    kernel = "k_xtu_f32s" if xtu_ms >= xv_ms else "k_xv_f32s"
-    alg = xbytes + (n * r * 4 + m * r * 4)
-    achieved = alg / (dom_ms * 1e-3) / 1e9
-    traffic = TRAFFIC[kernel] if kernel_source_hash() == TRAFFIC["k_mfma_sha256_16"] else None
-    roof = {
-        "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-        "kernel": kernel, "algorithmic_bytes": alg,
-        "xv_ms": round(xv_ms, 5), "xtu_ms": round(xtu_ms, 5), "samples": samples,
-        "fp32_equiv_tflops": round(flops / (dom_ms * 1e-3) / 1e12, 2),
-        "fp32_equiv_frac": round(flops / (dom_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
-    }
-
+    ref = read_golden("ratings_oracle.txt")
+    target = ref["relerr"] + 1e-3
+    bf = ratings_form(ctx, torch, Xb, Xf, om, r, args, ref, target)
+    f32 = ratings_form(ctx, torch, Xf, Xf, om, r, args, ref, target)
     out = {
-        "metric": METRIC, "value": round(ITERS * 1e3 / ms_per_step, 2), "unit": "iters/s",
+        "metric": METRIC, "value": bf["iters_per_s"], "unit": "iters/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "image-patch X 4096x10000 fp32, r=49, 500 iterations per solve",
+        "ms_per_step": bf["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16",
+        "dtype_detail": ("X stored and streamed as bfloat16; the float32 factor split into three "
+                         "bfloat16 terms on the bf16 matrix cores, float32 accumulation; float64 "
+                         "Grams, rotation, range-finder orthonormalisation and checks"),
+        "data": "synthetic",
+        "config": {"workload": "ratings X 100000x20000 (bf16 storage), r=20, 100 iterations per solve",
                    "m": m, "n": n, "r": r, "iters": ITERS, "oversample": OVERSAMPLE,
-                   "power_iters": POWER_ITERS},
-        "time_to_relerr_s": None if tte is None else round(float(tte), 5),
-        "relerr_final": rep["relerr"], "relerr_svd": rsvd, "kkt_final": rep["kkt"],
-        "ext_iters": rep["ext_iters_done"], "rotation_steps": rot["steps"],
-        "roofline": roof,
+                   "power_iters": POWER_ITERS, "omega_seed": OMEGA_SEED},
+        "time_to_relerr_s": bf["time_to_relerr_s"],
+        "relerr_final": bf["relerr_final"], "kkt_final": bf["kkt_final"],
+        "roofline": roofline(Xb, r, bf),
+        "bf16_form": bf,
+        "fp32_form": dict(f32, dtype_detail=(
+            "float32 X; both operands split into three bfloat16 terms, the six largest of the nine "
+            "term products on the bf16 matrix cores, float32 accumulation (per-element bound "
+            "2^-21 |x||b|)"), roofline=roofline(Xf, r, f32)),
     }
-    del X, om
+    if f32["time_to_relerr_s"] and bf["time_to_relerr_s"]:
+        out["fp32_over_bf16_time_to_relerr"] = round(f32["time_to_relerr_s"] / bf["time_to_relerr_s"], 3)
+    out["hbm_streaming"] = streaming(ctx, Xf, Xb, r)
+    del Xf, Xb
     torch.cuda.empty_cache()
-    if not args.no_streaming:
-        out["hbm_streaming"] = ratings_streaming(ctx, torch)
-    if not args.no_enmc:
-        out["enmc"] = enmc_leg(ctx, torch, inputs, enmf)
-    if not args.no_sparse:
-        out["sparse"] = sparse_leg(ctx, torch, inputs)
-    if not args.no_grot:
-        out["generalized_rotation"] = grot_leg(ctx, torch, inputs)
-    if not args.no_serve:
-        out["served"] = served(ctx, torch, inputs, enmf, args.serve_requests, args.serve_load,
-                               args.serve_slots)
+    if not args.headline_only:
+        if not args.no_image:
+            out["image"] = image_leg(ctx, torch, inputs, args)
+        if not args.no_small:
+            out["small"] = small_leg(ctx, torch, inputs)
+        if not args.no_spectrogram:
+            out["spectrogram"] = spectrogram_leg(ctx, torch, inputs)
+        if not args.no_ablation:
+            out["ablation"] = ablation_leg(ctx, torch, inputs)
+        torch.cuda.empty_cache()
+        if not args.no_enmc:
+            out["enmc"] = enmc_leg(ctx, torch, inputs, enmf)
+        if not args.no_sparse:
+            out["sparse"] = sparse_leg(ctx, torch, inputs)
+        if not args.no_grot:
+            out["generalized_rotation"] = grot_leg(ctx, torch, inputs)
+        if not args.no_serve:
+            out["served"] = served(ctx, torch, inputs, enmf, args.serve_requests, args.serve_load,
+                                   args.serve_slots, args.serve_plain)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(X_np, om_np, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(X_np, om_np, args.cpu_rows, args.cpu_iters)
     print(json.dumps(out), flush=True)
     ctx.close()
 

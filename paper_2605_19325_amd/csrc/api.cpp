@@ -562,7 +562,7 @@ enmf_status enmf_svd_init(enmf_ctx* c, const enmf_matrix* X, int32_t r, const en
 }
 
 // The pinned word and event through which a loop looks at a device stop flag.
-enmf_status ensure_stop_copy(enmf_ctx* c) {
+static enmf_status ensure_stop_copy(enmf_ctx* c) {
   if (!c->stop_host) {
     void* ph = nullptr;
     if (hipHostMalloc(&ph, 64) != hipSuccess) {

@@ -19,6 +19,7 @@ factor (float32 X).
 """
 
 import os
+import sys
 
 import numpy as np
 import pytest
@@ -26,6 +27,9 @@ import torch
 
 import oracle as O
 from paper_2605_19325_amd import inputs
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import fullsize_oracle as F  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -107,6 +111,32 @@ def test_image_solve_tracks_oracle(lib, image):
     assert abs(rep["relerr"] - ro["relerr"]) <= 1e-5 * ro["relerr"]
 
 
+def sampled_rows_rel(T, rows, want):
+    got = host(T[torch.from_numpy(rows).to(DEV)])
+    return rel(got, want)
+
+
+def test_image_500_iterations_vs_oracle(lib, image):
+    """The benchmarked solve (SVD init, default rotation, 500 iterations)
+    against the oracle's, stored in tests/golden/image_oracle.txt by
+    make_image_oracle.py."""
+    X, r, om = image
+    ref = F.read("image_oracle.txt")
+    say("image-patch 4096x10000 fp32: the 500-iteration solve vs the stored oracle solve")
+    U, V, rep = lib.solve(torch.from_numpy(X).to(DEV), r, torch.from_numpy(om).to(DEV),
+                          max_iter=500, check_every=1)
+    du, dv = sampled_rows_rel(U, *ref["U"]), sampled_rows_rel(V, *ref["V"])
+    say(f"  f {rep['f']:.10e} oracle {ref['f']:.10e} relerr {rep['relerr']:.10e} oracle "
+        f"{ref['relerr']:.10e} kkt {rep['kkt']:.4e} oracle {ref['kkt']:.4e} rows U {du:.2e} V {dv:.2e} "
+        f"rotation steps {rep['rotation']['steps']} (oracle {int(ref['rot_steps'])})")
+    assert rep["iters"] == 500 and rep["ext_iters_done"] == int(ref["ext_iters_done"])
+    assert rep["rotation"]["steps"] == int(ref["rot_steps"])
+    assert abs(rep["f"] - ref["f"]) <= 1e-5 * ref["f"]
+    assert abs(rep["relerr"] - ref["relerr"]) <= 1e-5 * ref["relerr"]
+    assert abs(rep["kkt"] - ref["kkt"]) <= 1e-6
+    assert du <= 1e-4 and dv <= 1e-4
+
+
 # ---------------------------------------------------------------------------
 # spectrogram 513 x 20000, r = 40, bfloat16 X
 # ---------------------------------------------------------------------------
@@ -183,3 +213,47 @@ def test_ratings_bf16_solve_invariants(lib, ratings):
     assert hals.size >= 10
     assert hals[-1] < hals[0]
     assert np.all(np.diff(hals) <= 1e-4 * hals[:-1])
+
+
+def ratings_solve(lib, Xd, r, om):
+    """The ratings solve of the stored oracle run: SVD init (test matrix seed
+    4), default rotation, 100 iterations checked every 10."""
+    return lib.solve(Xd, r, om, max_iter=100, check_every=10)
+
+
+def test_ratings_fp32_vs_oracle(lib, ratings):
+    X, r = ratings
+    ref = F.read("ratings_oracle.txt")
+    say("ratings 100000x20000 fp32: the 100-iteration solve vs the stored oracle solve")
+    om = torch.from_numpy(inputs.omega(X.shape[1], r + 10, 4)).to(DEV)
+    Xd = torch.from_numpy(X).to(DEV)
+    U, V, rep = ratings_solve(lib, Xd, r, om)
+    du, dv = sampled_rows_rel(U, *ref["U"]), sampled_rows_rel(V, *ref["V"])
+    say(f"  f {rep['f']:.10e} oracle {ref['f']:.10e} relerr {rep['relerr']:.10e} oracle "
+        f"{ref['relerr']:.10e} kkt {rep['kkt']:.4e} oracle {ref['kkt']:.4e} rows U {du:.2e} V {dv:.2e} "
+        f"ext {rep['ext_iters_done']} rotation steps {rep['rotation']['steps']}")
+    assert rep["iters"] == 100 and rep["ext_iters_done"] == int(ref["ext_iters_done"])
+    assert abs(rep["f"] - ref["f"]) <= 1e-5 * ref["f"]
+    assert du <= 1e-4 and dv <= 1e-4
+
+
+def test_ratings_bf16_vs_oracle_and_fp32(lib, ratings):
+    """The bfloat16 form of the same solve reaches the oracle's relative
+    error (measured against the float32 X) within 1e-3, and the float32
+    form's within 1e-3; KKT as low as the oracle's where that is <= 1e-5."""
+    X, r = ratings
+    ref = F.read("ratings_oracle.txt")
+    say("ratings 100000x20000 bf16: the 100-iteration solve vs the oracle and the fp32 form")
+    om = torch.from_numpy(inputs.omega(X.shape[1], r + 10, 4)).to(DEV)
+    Xd = torch.from_numpy(X).to(DEV)
+    Xb = lib.convert(Xd, torch.bfloat16)
+    torch.cuda.empty_cache()
+    U, V, rep = ratings_solve(lib, Xb, r, om)
+    k32 = lib.objective_kkt(Xd, U, V, rep["relerr_svd"])      # against the float32 X
+    say(f"  bf16 relerr {k32['relerr']:.8e} (oracle {ref['relerr']:.8e}) kkt {k32['kkt']:.3e} "
+        f"(oracle {ref['kkt']:.3e}) ext {rep['ext_iters_done']}")
+    assert rep["iters"] == 100
+    assert abs(k32["relerr"] - ref["relerr"]) <= 1e-3
+    assert float(U.min()) >= 0.0 and float(V.min()) >= 0.0
+    if ref["kkt"] <= 1e-5:
+        assert k32["kkt"] <= 1e-5

@@ -330,6 +330,32 @@ def test_pin7_catches_planted_mistake():
     assert not check_pbcd_row(wrong)
 
 
+def check_mask_at_zero(ext_half):
+    """Entries at exactly zero after the push are inside the mask and move."""
+    g = load_golden("mask_zero.txt")
+    x, V = g["x"], g["V"]
+    G, P = V.T @ V, (x @ V)[None, :]
+    for case in ("C", "D"):
+        u = g[case + ".u"][None, :]
+        for sweeps in (1, 5):
+            out = ext_half(u, P, G, float(g[case + ".step"][0]), 0.0, sweeps)
+            if not np.allclose(out[0], g[case + ".u_new"], atol=1e-14):
+                return False
+    return True
+
+
+def test_mask_takes_zero_entries():
+    assert check_mask_at_zero(O.ext_half)
+
+
+def test_mask_at_zero_catches_strict_mask():
+    def strict(U, P, G, step, eps=0.0, max_iter=5, fixed=False):   # mask = U > 0
+        U = O.push_negatives(U, step)
+        U, _ = O.pbcd(U, P, G, U > 0, eps, max_iter)
+        return U
+    assert not check_mask_at_zero(strict)
+
+
 def test_pbcd_masked_gradient_stop():
     X, r = I.config_small()
     Us, Vs, _, _ = O.svd_init_exact(X, r)
