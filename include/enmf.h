@@ -105,6 +105,20 @@ enmf_status enmf_convert(enmf_ctx* ctx, const float* x32, int64_t m, int64_t n, 
 enmf_status enmf_xv(enmf_ctx* ctx, const enmf_matrix* X, const float* B, int32_t k, float* P);
 enmf_status enmf_xtu(enmf_ctx* ctx, const enmf_matrix* X, const float* A, int32_t k, float* Q);
 
+/* enmf_xv without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and result as enmf_xv (bitwise), dense
+ * X only (float32, bfloat16 or float16).  The packed factor and the split
+ * partials live in a fixed 64 MiB device array that the library holds on each
+ * device from the first enmf_create on that device until the process ends;
+ * nothing is allocated by the call.  A shape whose scratch would exceed
+ * 64 MiB returns ENMF_ENOMEM before any launch (enmf_last_error gives the
+ * bytes needed).  Every call on one device shares that array and leaves its
+ * contents behind: calls that overlap on one device (two streams, two
+ * threads, two contexts) race and must be serialised by the caller.  A sparse
+ * X returns ENMF_EINVAL. */
+enmf_status enmf_xv_static(enmf_ctx* ctx, const enmf_matrix* X, const float* B, int32_t k, float* P);
+
 /* Gram matrix G = A^T A (k x k, float64, row-major) of the float32 rows x k
  * matrix A, accumulated in float64 (the r x r Grams V^T V, U^T U). */
 enmf_status enmf_gram(enmf_ctx* ctx, const float* A, int64_t rows, int32_t k, double* G);

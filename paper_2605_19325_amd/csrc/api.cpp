@@ -434,6 +434,12 @@ enmf_status enmf_create(enmf_ctx** out, int32_t device, void* hip_stream) {
     delete c;
     return ENMF_ENOMEM;
   }
+  if (static_scratch_setup(device) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(c->st);
+    delete c;
+    return ENMF_EDEVICE;
+  }
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
     c->ns_per_tick = 1e6 / (double)khz;
@@ -486,6 +492,45 @@ enmf_status enmf_xv(enmf_ctx* c, const enmf_matrix* X, const float* B, int32_t k
   if (!B || !P) return fail(c, ENMF_EINVAL, "null pointer");
   if (k < 1 || k > ENMF_MAX_WIDTH) return fail(c, ENMF_EINVAL, "k out of range");
   return do_xv(c, X, B, k, P);
+}
+
+enmf_status enmf_xv_static(enmf_ctx* c, const enmf_matrix* X, const float* B, int32_t k, float* P) {
+  TRY(check_ctx(c));
+  TRY(check_matrix(c, X));
+  if (!B || !P) return fail(c, ENMF_EINVAL, "null pointer");
+  if (k < 1 || k > ENMF_MAX_WIDTH) return fail(c, ENMF_EINVAL, "k out of range");
+  if (sparse_of(X)) return fail(c, ENMF_EINVAL, "enmf_xv_static takes a dense X only");
+  unsigned char* base = static_cast<unsigned char*>(static_scratch(c->device));
+  if (!base) return fail(c, ENMF_EDEVICE, "static scratch not set up on this device");
+  // the same kernels and launch plan as enmf_xv, with the packed factor and the
+  // split partials carved out of the fixed scratch instead of the workspace
+  const bool mf = use_mfma(c, X, k);
+  size_t pack = 0, part = 0;
+  int splits = 1, kp = 0;
+  int64_t rows_pad = 0;
+  if (mf) {
+    mfma_xv_ws(X->dtype, X->m, X->n, k, &pack, &part);
+  } else {
+    kp = pad_width(k);
+    rows_pad = round_up(X->n, xv_tile_width(X->dtype));
+    pack = (size_t)rows_pad * kp * 4;
+    splits = xv_splits(X->m, X->n, X->dtype);
+    part = splits > 1 ? (size_t)splits * X->m * k * 4 : 0;
+  }
+  const size_t off = (pack + 255) / 256 * 256;
+  if (off + part > kStaticScratchBytes)
+    return fail(c, ENMF_ENOMEM,
+                "enmf_xv_static needs " + std::to_string(off + part) + " bytes of scratch at this shape; "
+                "the fixed scratch holds " + std::to_string(kStaticScratchBytes));
+  float* pp = part ? reinterpret_cast<float*>(base + off) : nullptr;
+  if (mf) {
+    CK(launch_xv_mfma(X->data, X->dtype, X->m, X->n, X->ld, B, k, base, pp, P, c->stream, 1, 1));
+  } else {
+    float* Bp = reinterpret_cast<float*>(base);
+    CK(launch_pad_rows_cols(B, X->n, k, kp, rows_pad, Bp, c->stream));
+    CK(launch_xv(X->data, X->dtype, X->m, X->n, X->ld, Bp, k, kp, splits, pp, P, c->stream));
+  }
+  return ENMF_OK;
 }
 
 enmf_status enmf_xtu(enmf_ctx* c, const enmf_matrix* X, const float* A, int32_t k, float* Q) {

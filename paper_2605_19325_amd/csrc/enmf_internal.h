@@ -88,6 +88,14 @@ inline int pad_width(int k) {
   return 80;
 }
 
+// Fixed device scratch of the allocation-free product (static_scratch.hip):
+// 64 MiB per device, held until the process ends.  static_scratch_setup takes
+// the device's address of the array once (at context creation); static_scratch
+// returns it, or null before the set-up.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+hipError_t static_scratch_setup(int device);
+void* static_scratch(int device);
+
 // Context accessors for the serving front end (api.cpp).
 int ctx_device(const enmf_ctx* c);
 hipStream_t ctx_stream(const enmf_ctx* c);

@@ -96,6 +96,7 @@ SIGNATURES = [
     ("enmf_convert", c_int32, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_int32, c_void_p,
                                c_int64]),
     ("enmf_xv", c_int32, [c_void_p, POINTER(Matrix), c_void_p, c_int32, c_void_p]),
+    ("enmf_xv_static", c_int32, [c_void_p, POINTER(Matrix), c_void_p, c_int32, c_void_p]),
     ("enmf_xtu", c_int32, [c_void_p, POINTER(Matrix), c_void_p, c_int32, c_void_p]),
     ("enmf_gram", c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p]),
     ("enmf_svd_init", c_int32, [c_void_p, POINTER(Matrix), c_int32, POINTER(SvdOpts), c_void_p,
@@ -295,6 +296,20 @@ class Context:
         _factor(B, X.shape[1], k, "B")
         P = torch.empty((X.shape[0], k), dtype=torch.float32, device=X.device)
         self._call(self._lib.enmf_xv, byref(M), _ptr(B), k, _ptr(P))
+        return P
+
+    def xv_static(self, X, B, P=None):
+        """P = X B through enmf_xv_static (no device allocation by the library).
+        P may be passed in (float32, X.shape[0] x k) so that nothing at all is
+        allocated by the call."""
+        M = matrix(X)
+        k = B.shape[1]
+        _factor(B, X.shape[1], k, "B")
+        if P is None:
+            P = torch.empty((X.shape[0], k), dtype=torch.float32, device=X.device)
+        else:
+            _factor(P, X.shape[0], k, "P")
+        self._call(self._lib.enmf_xv_static, byref(M), _ptr(B), k, _ptr(P))
         return P
 
     def xtu(self, X, A):
