@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse-X (Reuters-shaped) leg")
     ap.add_argument("--no-grot", action="store_true", help="skip the generalized-rotation leg")
     ap.add_argument("--serve-requests", type=int, default=4096)
-    ap.add_argument("--serve-load", type=float, default=0.8,
+    ap.add_argument("--serve-load", type=float, default=0.6,
                     help="open-loop arrival rate as a fraction of the closed-loop solves/s")
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--serve-plain", type=int, default=256,
@@ -285,22 +285,26 @@ def image_leg(ctx, torch, inputs, args):
 
 def small_leg(ctx, torch, inputs):
     """Small workload 500 x 400, r = 10, 200 iterations: launch-bound (X is
-    0.8 MB); microseconds per outer iteration of enmf_iterate."""
+    0.8 MB); microseconds per outer iteration of enmf_iterate with every
+    kernel launched directly (the default) and with the loop body replayed
+    from a captured graph."""
     dev = torch.device("cuda:0")
     X_np, r = inputs.config_small()
     X = torch.from_numpy(X_np).to(dev)
     om = torch.from_numpy(inputs.omega(X.shape[1], r + OVERSAMPLE, 7)).to(dev)
     iters = 200
-    for _ in range(2):
-        phase_split(ctx, torch, X, r, om, iters)
-    runs = [phase_split(ctx, torch, X, r, om, iters) for _ in range(5)]
-    init_s = float(np.median([a for a, _, _, _, _ in runs]))
-    iter_s = float(np.median([b for _, b, _, _, _ in runs]))
-    rep = runs[-1][2]
-    return {"workload": "small X 500x400 fp32, r=10, 200 iterations", "r": r,
-            "init_rotation_ms": round(init_s * 1e3, 4), "iterate_ms": round(iter_s * 1e3, 4),
-            "us_per_iteration": round(iter_s * 1e6 / iters, 3), "relerr_final": rep["relerr"],
-            "kkt_final": rep["kkt"]}
+    out = {"workload": "small X 500x400 fp32, r=10, 200 iterations", "r": r}
+    for name, replay in (("direct", 0), ("graph", 1)):
+        for _ in range(2):
+            phase_split(ctx, torch, X, r, om, iters, graph_replay=replay)
+        runs = [phase_split(ctx, torch, X, r, om, iters, graph_replay=replay) for _ in range(5)]
+        init_s = float(np.median([a for a, _, _, _, _ in runs]))
+        iter_s = float(np.median([b for _, b, _, _, _ in runs]))
+        rep = runs[-1][2]
+        out[name] = {"init_rotation_ms": round(init_s * 1e3, 4), "iterate_ms": round(iter_s * 1e3, 4),
+                     "us_per_iteration": round(iter_s * 1e6 / iters, 3),
+                     "relerr_final": rep["relerr"], "kkt_final": rep["kkt"]}
+    return out
 
 
 def spectrogram_leg(ctx, torch, inputs):
@@ -525,8 +529,8 @@ def served(ctx, torch, inputs, enmf, count, load, slots, plain):
     torch.cuda.synchronize()
     opts = dict(max_iter=300, relerr_tol=1e-3, kkt_tol=1e-5)
 
-    def run(arrivals):
-        srv = enmf.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=slots)
+    def run(arrivals, direct=0):
+        srv = enmf.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=slots, direct_launch=direct)
         try:
             t0 = time.perf_counter()
             tickets = []
@@ -547,12 +551,14 @@ def served(ctx, torch, inputs, enmf, count, load, slots, plain):
 
     wall_c, lat_c, iters_c, conv_c = run(None)
     sat = count / wall_c
+    wall_d, _, _, _ = run(None, direct=1)          # the same ticks launched one by one
     rate = load * sat
     arr = inputs.poisson_arrivals(count, rate, 7)
     wall_o, lat_o, iters_o, conv_o = run(arr)
     out = {
         "requests": count, "dtype": "bf16", "slots": slots,
         "saturated_solves_per_s": round(sat, 2),
+        "saturated_solves_per_s_direct_launches": round(count / wall_d, 2),
         "load": load, "arrival_rate_per_s": round(rate, 2),
         "solves_per_s": round(count / wall_o, 2),
         "sustained": bool(count / wall_o >= 0.97 * rate),

@@ -217,7 +217,10 @@ typedef struct {
   int32_t mode;            /* 0 full eNMF; 1 project to the orthant then HALS; 2 fixed row step
                               1/||G||_F in the exterior phase (step-size ablation); 3 stop once
                               feasible (the ablations of the appendix tables and figure 5) */
-  int32_t reserved;
+  int32_t graph_replay;    /* 0: every kernel is launched directly; 1: the launches of two
+                              iterations are captured once per call into a HIP graph (kernel
+                              nodes only) and replayed for every later pair.  Same results bit
+                              for bit.  Ignored by enmf_enmc_iterate and served requests. */
 } enmf_iter_opts;
 
 typedef struct {
@@ -334,10 +337,15 @@ enmf_status enmf_enmc_iterate(enmf_ctx* ctx, const enmf_matrix* X, const enmf_ma
  * A server runs Algorithm 3 end to end (randomized SVD init, ADMM rotation,
  * exterior phase and HALS with the KKT check, final objective) for every
  * submitted request.  Requests are admitted into slots as slots and device
- * memory free up, and all admitted solves advance together: each device
- * launch gives every running solve one workgroup and a bounded amount of work
- * (tick_budget), so requests that arrive while others run join at the next
- * launch.  A solve's arithmetic does not depend on what else is in flight.
+ * memory free up, and all admitted solves advance together: each tick gives
+ * every running solve one workgroup and a bounded amount of work
+ * (tick_budget).  A worker thread replays a captured HIP graph of
+ * ticks_per_launch ticks (kernel nodes only) again and again without waiting
+ * for it: the slot status is copied to pinned host memory after each replay
+ * and read one replay later, and newly admitted solves are uploaded between
+ * replays, so requests that arrive while others run join at the next replay
+ * and the device never idles on the host.  A solve's arithmetic does not
+ * depend on what else is in flight, on the tick budget or on the launch form.
  * Served solves take dense X and support r <= 32 and r + oversample <= 48, a fixed number of
  * PBCD sweeps (pbcd_eps = 0) and modes 0 to 3.  The request's trace is
  * not recorded.
@@ -355,7 +363,10 @@ typedef struct enmf_server enmf_server;
 typedef struct {
   uint64_t hbm_budget_bytes;  /* device arena for admitted solves' workspace; 0 = 1 GiB */
   int32_t max_slots;          /* solves in flight, one workgroup each; 0 = 512 */
-  int32_t tick_budget;        /* work per solve per launch, in units of 2^20 multiply-adds; 0 = 64 */
+  int32_t tick_budget;        /* work per solve per tick, in units of 2^20 multiply-adds; 0 = 64 */
+  int32_t ticks_per_launch;   /* ticks per replay of the captured tick graph; 0 = 4 */
+  int32_t direct_launch;      /* 0: each group of ticks is one replay of a captured HIP graph;
+                                 1: the same kernels launched one by one (no graph) */
 } enmf_serve_opts;
 
 typedef struct {

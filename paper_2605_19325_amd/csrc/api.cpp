@@ -49,6 +49,8 @@ struct enmf_ctx {
   // the iterate loop's look at the device stop flag (pinned copy and its event)
   int32_t* stop_host = nullptr;
   hipEvent_t stop_ev = nullptr;
+  // private stream on which the iterate loop body is captured into a graph
+  hipStream_t cap_stream = nullptr;
 };
 
 
@@ -459,6 +461,7 @@ void enmf_destroy(enmf_ctx* c) {
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->stop_ev) (void)hipEventDestroy(c->stop_ev);
   if (c->stop_host) (void)hipHostFree(c->stop_host);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 
@@ -805,7 +808,8 @@ enmf_status iter_setup(enmf_ctx* c, const enmf_matrix* X, int r, const float* U,
   TRY(sumsq_parts(c, X, xp, &nx));
   CK(launch_factor_stats(U, m * r, r, stat, 0, b.fbU, s));
   CK(launch_factor_stats(V, n * r, r, stat, b.fbU, b.fbV, s));
-  CK(launch_setup_state(stat, b.fbU, b.fbV, xp, nx, o.step_u, o.step_v, o.ext_iters, c->st, s));
+  CK(launch_setup_state(stat, b.fbU, b.fbV, xp, nx, o.step_u, o.step_v, o.ext_iters, o.check_every,
+                        c->st, s));
   return ENMF_OK;
 }
 
@@ -847,6 +851,7 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
   if (o.check_every < 1) o.check_every = 1;
   if (o.pbcd_eps < 0.0) return fail(c, ENMF_EINVAL, "pbcd_eps must be >= 0");
   if (o.mode < 0 || o.mode > 3) return fail(c, ENMF_EINVAL, "unsupported mode");
+  if (o.graph_replay != 0 && o.graph_replay != 1) return fail(c, ENMF_EINVAL, "graph_replay must be 0 or 1");
   if (trace && trace_cap < 0) return fail(c, ENMF_EINVAL, "bad trace capacity");
   hipStream_t s = c->stream;
   const int kp = row_pad(r);
@@ -897,22 +902,20 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
   TRY(xtu_parts(c, X, U, r, b.Q, &pp, nullptr, mf, &gjH));
   CK(launch_rowupdate(V, V, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, 0,
                       kRowGram | kRowWriteCheck, b.recV(1), b.gpV, nullptr, 0, nullptr, 0, s, poV));
-  for (int k = 0; k <= o.max_iter; ++k) {
+  // One outer iteration k < max_iter, enqueued on c->stream.  devk: the
+  // launches take k (and whether it is checked) from the device state, so
+  // that the same launches can be replayed from a graph for any k of the same
+  // parity; the U pass then always writes its check partials.
+  auto body = [&](int k, bool devk) -> enmf_status {
+    const hipStream_t s = c->stream;
     const int cur = k & 1, prev = cur ^ 1;
-    const bool last = k == o.max_iter;
-    const bool due = (k % o.check_every == 0) || last;
+    const bool due = devk || (k % o.check_every == 0);
     DecideArgs dec;
     dec.recU = b.recU(cur); dec.nbU = b.nbU;
     dec.recV = b.recV(prev); dec.nbV = b.nbV;
-    dec.k = k; dec.due = due ? 1 : 0; dec.trace = trace;
-    TRY(xv_parts(c, X, V, r, b.P, &pp, sample(0, k), mf, &gjG));
+    dec.k = devk ? -1 : k; dec.due = due ? 1 : 0; dec.trace = trace;
+    TRY(xv_parts(c, X, V, r, b.P, &pp, devk ? nullptr : sample(0, k), mf, &gjG));
     const int head = kRowHead | kRowCheckPre | (due ? kRowWriteCheck : 0);
-    if (last) {
-      CK(launch_rowupdate(Ub[cur], Ub[cur], m, r, kp, pp.p, pp.n, pp.stride, b.G, st, 0, 0, head,
-                          b.recU(cur), b.gpU, b.recU(prev), b.nbU, b.recV(prev), b.nbV, s));
-      CK(launch_finalize(dec, 1, st, s));
-      break;
-    }
     if (fixed) {
       CK(launch_rowupdate(Ub[cur], Ub[prev], m, r, kp, pp.p, pp.n, pp.stride, b.G, st, 0,
                           o.pbcd_max_iter, head | kRowUpdate | kRowFirst | kRowGram, b.recU(cur),
@@ -929,7 +932,8 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
     // X^T U^(k+1) runs before the check of iteration k.  The decision is
     // taken by the matrix-core product's first block, else at the head of the
     // V pass; either way the V pass leaves V^k in place on a stop.
-    TRY(xtu_parts(c, X, Ub[prev], r, b.Q, &pp, sample(1, k), mf, &gjH, mf ? &dec : nullptr));
+    TRY(xtu_parts(c, X, Ub[prev], r, b.Q, &pp, devk ? nullptr : sample(1, k), mf, &gjH,
+                  mf ? &dec : nullptr));
     const int vdec = mf ? 0 : kRowDecide;
     if (fixed) {
       CK(launch_rowupdate(V, V, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, o.pbcd_max_iter,
@@ -944,22 +948,97 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
         CK(launch_pbcd_decide(b.recV(cur), b.nbV, 1, t == 0, st, s));
       }
     }
-    if ((k + 1) % 32 == 0) {
+    return ENMF_OK;
+  };
+
+  // graph_replay: the loop body of two iterations (odd k, then even k) is
+  // captured once on a private stream and replayed for every pair after the
+  // first iteration; the first, a trailing odd one and the final check are
+  // launched directly.  Kernel sampling needs the events of each launch, so a
+  // sampled call launches directly.
+  const bool graphs = o.graph_replay == 1 && c->timing_period <= 0 && o.max_iter >= 5;
+  hipGraphExec_t gx = nullptr;
+  auto capture_pair = [&](int k) -> bool {
+    if (!c->cap_stream &&
+        hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      c->cap_stream = nullptr;
+      return false;
+    }
+    const hipStream_t saved = c->stream;
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    c->stream = c->cap_stream;
+    enmf_status bs = body(k, true);
+    if (bs == ENMF_OK) bs = body(k + 1, true);
+    c->stream = saved;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (bs == ENMF_OK && e == hipSuccess) e = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (bs != ENMF_OK || e != hipSuccess) {
+      (void)hipGetLastError();
+      c->err.clear();
+      gx = nullptr;
+      return false;
+    }
+    return true;
+  };
+  bool use_graph = graphs;
+  int k = 0, next_look = 32;
+  bool stopped = false;
+  while (k < o.max_iter) {
+    if (use_graph && (k & 1) && k + 1 < o.max_iter) {
+      if (!gx && !capture_pair(k)) {
+        use_graph = false;
+        continue;
+      }
+      CK(hipGraphLaunch(gx, s));
+      k += 2;
+    } else {
+      const enmf_status bs = body(k, false);
+      if (bs != ENMF_OK) {
+        if (gx) (void)hipGraphExecDestroy(gx);
+        return bs;
+      }
+      k += 1;
+    }
+    if (k >= next_look) {
+      next_look += 32;
       // The stop flag is copied to pinned memory here and looked at one check
       // later, once the device has passed this point, so the queue never drains
       // for the look; launches after a stop return at once on the device flag.
       if (stop_copied) {
         CK(hipEventSynchronize(c->stop_ev));
-        if (*c->stop_host) break;
+        if (*c->stop_host) {
+          stopped = true;
+          break;
+        }
       }
       CK(hipMemcpyAsync(c->stop_host, &st->stop, 4, hipMemcpyDeviceToHost, s));
       CK(hipEventRecord(c->stop_ev, s));
       stop_copied = true;
     }
   }
+  if (!stopped) {
+    // the last check (k = max_iter) only: the state of the last iteration
+    const int cur = o.max_iter & 1, prev = cur ^ 1;
+    DecideArgs dec;
+    dec.recU = b.recU(cur); dec.nbU = b.nbU;
+    dec.recV = b.recV(prev); dec.nbV = b.nbV;
+    dec.k = o.max_iter; dec.due = 1; dec.trace = trace;
+    TRY(xv_parts(c, X, V, r, b.P, &pp, sample(0, o.max_iter), mf, &gjG));
+    CK(launch_rowupdate(Ub[cur], Ub[cur], m, r, kp, pp.p, pp.n, pp.stride, b.G, st, 0, 0,
+                        kRowHead | kRowCheckPre | kRowWriteCheck, b.recU(cur), b.gpU, b.recU(prev),
+                        b.nbU, b.recV(prev), b.nbV, s));
+    CK(launch_finalize(dec, 1, st, s));
+  }
   DevState h;
   CK(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
   CK(hipStreamSynchronize(s));
+  if (gx) (void)hipGraphExecDestroy(gx);
   for (int kind = 0; kind < 2; ++kind) {
     for (int q = 0; q < c->pending[kind]; ++q) {
       float ms = 0.f;

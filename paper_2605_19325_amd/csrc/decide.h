@@ -26,7 +26,11 @@ template <int NT>
 __device__ inline bool check_decide(const DecideArgs& d, int final_check, DevState* st, bool writer,
                              double* sh, int* flag) {
   constexpr int NF = 17;
-  if (d.due || final_check) {
+  // k < 0 (a loop body replayed from a graph): the iteration comes from the
+  // state, published by this iteration's U pass, and due from the check period
+  const int k = d.k >= 0 ? d.k : st->kcur;
+  const int due = d.k >= 0 ? d.due : (k % st->check_every == 0 ? 1 : 0);
+  if (due || final_check) {
     double v[NF];
     // a thread's records of both halves, 4 per half, all loads in flight
     // together; further batches (more than 4 NT records) follow; combined in
@@ -108,7 +112,7 @@ __device__ inline bool check_decide(const DecideArgs& d, int final_check, DevSta
         if (numerr) st->numeric_error = 1;
         if (d.trace != nullptr && st->ntrace < st->trace_cap) {
           double* o = d.trace + (int64_t)st->ntrace * kTraceFields;
-          o[0] = (double)d.k; o[1] = f; o[2] = relerr; o[3] = kkt; o[4] = fmin(a[7], a[15]);
+          o[0] = (double)k; o[1] = f; o[2] = relerr; o[3] = kkt; o[4] = fmin(a[7], a[15]);
           o[5] = (double)(negs > 0.0 ? kPhaseExt : kPhaseHals);
           o[6] = (double)wall_clock64() * st->ns_per_tick;
           o[7] = negs;
@@ -126,9 +130,9 @@ __device__ inline bool check_decide(const DecideArgs& d, int final_check, DevSta
     if (fl & 1) {
       st->stop = 1;
       st->converged = (fl & 2) ? 1 : 0;
-      st->iters = d.k;
+      st->iters = k;
     } else {
-      st->iters = d.k + 1;
+      st->iters = k + 1;
       if (st->phase == kPhaseExt) st->ext_done += 1;
     }
   }
@@ -162,6 +166,7 @@ __device__ inline int take_phase(const double* headU, int nbU, const double* hea
     st->negs = (int)s;
     st->phase = phase;
     st->pbcd_done[0] = st->pbcd_done[1] = 0;
+    st->kcur = st->iters;   // the iteration this U pass belongs to
   }
   return phase;
 }

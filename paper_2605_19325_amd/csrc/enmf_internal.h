@@ -38,6 +38,8 @@ struct DevState {
   int32_t negs;          // negative entries in U and V at the last head
   int32_t rot_stop;      // set by a rotation step at a check within the tolerance; later steps return
   int32_t rot_steps;     // ADMM steps of the rotation when rot_stop was set
+  int32_t check_every;   // check period of the iterate loop
+  int32_t kcur;          // outer iteration in progress (published by the U pass's phase decision)
 };
 
 // Per-block record written by the row-update kernel (float64 fields):
@@ -71,7 +73,7 @@ struct DecideArgs {
   int nbU = 0;
   const double* recV = nullptr;   // check records of V^k (the previous V pass)
   int nbV = 0;
-  int k = 0, due = 0;
+  int k = 0, due = 0;     // k < 0: take k from DevState::kcur and due from its check period
   double* trace = nullptr;
 };
 
@@ -208,7 +210,7 @@ hipError_t launch_factor_stats(const float* A, int64_t count, int r, double* par
                                int nblocks, hipStream_t s);
 hipError_t launch_setup_state(const double* statpart, int nbU, int nbV, const double* xpart,
                               int nxpart, double step_u, double step_v, int ext_iters,
-                              DevState* st, hipStream_t s);
+                              int check_every, DevState* st, hipStream_t s);
 // Destination of the packed split factor a row pass can write for the next
 // matrix-core product (layout from mfma_pack_layout); p == nullptr: none.
 struct PackOut {

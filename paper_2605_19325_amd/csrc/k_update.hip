@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kT) void k_factor_stats(const float* __restrict__ A
 // decided later from the row-update records, like every other iteration's.
 __global__ void k_setup_state(const double* __restrict__ stat, int nbU, int nbV,
                               const double* __restrict__ xpart, int nx, double step_u,
-                              double step_v, int ext_iters, DevState* st) {
+                              double step_v, int ext_iters, int check_every, DevState* st) {
   if (threadIdx.x != 0) return;
   double nx2 = 0.0;
   for (int b = 0; b < nx; ++b) nx2 += xpart[b];
@@ -72,6 +72,8 @@ __global__ void k_setup_state(const double* __restrict__ stat, int nbU, int nbV,
   st->ntrace = 0;
   st->numeric_error = 0;
   st->pbcd_done[0] = st->pbcd_done[1] = 0;
+  st->check_every = check_every > 0 ? check_every : 1;
+  st->kcur = 0;
 }
 
 // One half of an outer iteration on the rows of A (U with P = X V, G = V^T V,
@@ -101,7 +103,7 @@ __global__ void k_setup_state(const double* __restrict__ stat, int nbU, int nbV,
 // The result goes to Aout (which may be A).  rec[b] = {#negative of the
 // output, |M o grad|^2 before the sweeps, |M o grad|^2 after, 0, check...}.
 template <int KP, bool LOOP>
-__global__ __launch_bounds__(Team<KP>::NT, (LOOP && KP == 64) ? 2 : 1) void k_rowupdate(
+__global__ __launch_bounds__(Team<KP>::NT, (LOOP && KP >= 32) ? 2 : 1) void k_rowupdate(
     const float* A, float* Aout, int64_t rows, int r,
     const float* __restrict__ P, int nsplit, int64_t pstride, const double* __restrict__ G,
     DevState* st, int half, int sweeps, int flags, double* __restrict__ rec,
@@ -544,9 +546,9 @@ hipError_t launch_factor_stats(const float* A, int64_t count, int r, double* par
 
 hipError_t launch_setup_state(const double* statpart, int nbU, int nbV, const double* xpart,
                               int nxpart, double step_u, double step_v, int ext_iters,
-                              DevState* st, hipStream_t s) {
+                              int check_every, DevState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_setup_state, dim3(1), dim3(64), 0, s, statpart, nbU, nbV, xpart, nxpart,
-                     step_u, step_v, ext_iters, st);
+                     step_u, step_v, ext_iters, check_every, st);
   return hipGetLastError();
 }
 

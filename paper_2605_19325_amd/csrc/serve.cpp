@@ -1,7 +1,10 @@
 // Host side of the serving loop: admission by device-memory footprint,
 // slot assignment, and the launch loop that advances every running solve by
-// one tick (k_serve.hip) until it finishes.  One worker thread per server
-// drives the device; submit and poll only touch the queues under the lock.
+// ticks (k_serve.hip) until it finishes.  One worker thread per server
+// drives the device: it replays a captured graph of a few ticks, copies the
+// slot status to pinned memory behind it and reads that copy one replay
+// later, so the device queue never drains for the host's look.  Submit and
+// poll only touch the queues under the lock.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -97,6 +100,7 @@ struct Running {
   uint64_t ticket = 0;
   int xt = 0;
   int64_t off = 0, bytes = 0;
+  uint64_t admit_seq = 0;     // first replay that runs this solve
   Clock::time_point t_submit;
 };
 
@@ -117,8 +121,13 @@ struct enmf_server {
   Arena* arena = nullptr;
   ServeSlot* d_slots = nullptr;
   ServeStatus* d_status = nullptr;
-  ServeStatus* h_status = nullptr;   // pinned
-  ServeSlot* h_stage = nullptr;      // pinned staging of newly admitted slots
+  ServeStatus* h_ring[2] = {nullptr, nullptr};   // pinned status copies of alternate replays
+  ServeStatus* h_init = nullptr;     // pinned: the status each newly admitted slot starts from
+  ServeSlot* h_stage = nullptr;      // pinned staging of newly admitted slots, one per slot
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int ticks = 4;                     // ticks per replay
+  bool direct = false;               // launch the ticks one by one instead of replaying a graph
+  hipGraphExec_t graphs[8] = {};     // per set of X storage types in flight (bit per type)
   std::vector<Running> slots;
   std::deque<Pending> pending;
   std::unordered_map<uint64_t, Result> done;
@@ -215,12 +224,52 @@ void fail_all(enmf_server* s, const std::string& msg) {
   s->cv.notify_all();
 }
 
+// The ticks of one replay for the X storage types in `mask`: ticks x (one
+// launch per type) over every slot; slots of another type or not running
+// return at once, so the sequence does not change with the slots in flight.
+hipError_t enqueue_ticks(enmf_server* s, int mask) {
+  for (int t = 0; t < s->ticks; ++t)
+    for (int xt = 0; xt < 3; ++xt)
+      if (mask >> xt & 1) {
+        const hipError_t e = launch_serve_tick(xt, s->d_slots, s->d_status, s->max_slots, s->budget,
+                                               s->stream);
+        if (e != hipSuccess) return e;
+      }
+  return hipSuccess;
+}
+
+// One replay of the tick sequence: the captured graph for this set of
+// storage types (captured and instantiated at its first use), or the same
+// launches one by one.
+hipError_t replay(enmf_server* s, int mask) {
+  if (s->direct) return enqueue_ticks(s, mask);
+  hipGraphExec_t& ex = s->graphs[mask];
+  if (!ex) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t le = enqueue_ticks(s, mask);
+    e = hipStreamEndCapture(s->stream, &g);
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      ex = nullptr;
+      return e;
+    }
+  }
+  return hipGraphLaunch(ex, s->stream);
+}
+
 void worker_loop(enmf_server* s) {
   (void)hipSetDevice(s->device);
   std::vector<int> fresh;
+  uint64_t seq = 0;          // replays enqueued so far
+  int inflight = -1;         // ring entry of the replay whose status is not read yet
+  uint64_t inflight_seq = 0;
+  int cur = 0;
   for (;;) {
-    int hi = 0;
-    bool types[3] = {false, false, false};
+    int mask = 0;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       for (;;) {
@@ -241,52 +290,68 @@ void worker_loop(enmf_server* s) {
           r.off = off;
           r.bytes = p.bytes;
           r.t_submit = p.t_submit;
-          build_slot(s, p, off, &s->h_stage[fresh.size()]);
+          r.admit_seq = seq;
+          build_slot(s, p, off, &s->h_stage[slot]);
           fresh.push_back(slot);
           s->pending.pop_front();
         }
-        bool any = false;
         for (int i = 0; i < s->max_slots; ++i)
-          if (s->slots[i].used) { any = true; hi = i + 1; types[s->slots[i].xt] = true; }
-        if (any || !fresh.empty()) break;
+          if (s->slots[i].used) mask |= 1 << s->slots[i].xt;
+        if (mask || inflight >= 0) break;
         if (s->stopping && s->pending.empty()) return;
         s->cv.wait(lk);
       }
     }
-    // upload the new slots and mark them running
+    // upload the new slots and mark them running (ordered before the next replay)
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < fresh.size() && e == hipSuccess; ++i) {
       const int slot = fresh[i];
-      e = hipMemcpyAsync(s->d_slots + slot, &s->h_stage[i], offsetof(ServeSlot, s) + sizeof(ServeScalars),
+      e = hipMemcpyAsync(s->d_slots + slot, &s->h_stage[slot], offsetof(ServeSlot, s) + sizeof(ServeScalars),
                          hipMemcpyHostToDevice, s->stream);
-      if (e == hipSuccess) {
-        ServeStatus st{};
-        st.status = kSlotRunning;
-        s->h_status[slot] = st;
-        e = hipMemcpyAsync(s->d_status + slot, &s->h_status[slot], sizeof(ServeStatus),
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(s->d_status + slot, &s->h_init[slot], sizeof(ServeStatus),
                            hipMemcpyHostToDevice, s->stream);
+    }
+    int launched = -1;
+    if (mask && e == hipSuccess) {
+      e = replay(s, mask);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(s->h_ring[cur], s->d_status, s->max_slots * sizeof(ServeStatus),
+                           hipMemcpyDeviceToHost, s->stream);
+      if (e == hipSuccess) e = hipEventRecord(s->ev[cur], s->stream);
+      if (e == hipSuccess) {
+        launched = cur;
+        ++seq;
       }
     }
-    for (int xt = 0; xt < 3 && e == hipSuccess; ++xt)
-      if (types[xt]) e = launch_serve_tick(xt, s->d_slots, s->d_status, hi, s->budget, s->stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(s->h_status, s->d_status, hi * sizeof(ServeStatus), hipMemcpyDeviceToHost,
-                         s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    // read the status of the previous replay (finished, or about to, while
+    // this one runs)
+    int done_ring = inflight;
+    const uint64_t done_seq = inflight_seq;
+    if (e == hipSuccess && done_ring >= 0) e = hipEventSynchronize(s->ev[done_ring]);
+    inflight = launched;
+    inflight_seq = seq - 1;
+    if (launched >= 0) cur ^= 1;
     const auto now = Clock::now();
     std::unique_lock<std::mutex> lk(s->mu);
     if (e != hipSuccess) {
+      (void)hipStreamSynchronize(s->stream);
+      (void)hipGetLastError();
+      inflight = -1;
       fail_all(s, std::string("serving launch failed: ") + hipGetErrorString(e));
       if (s->stopping) return;
       continue;
     }
+    if (done_ring < 0) continue;
+    const ServeStatus* hs = s->h_ring[done_ring];
     bool finished = false;
-    for (int i = 0; i < hi; ++i) {
+    for (int i = 0; i < s->max_slots; ++i) {
       Running& r = s->slots[i];
-      if (!r.used || s->h_status[i].status != kSlotDone) continue;
+      // a slot admitted after that replay still shows its previous occupant
+      if (!r.used || r.admit_seq > done_seq || hs[i].status != kSlotDone) continue;
       Result res;
-      fill_report(s->h_status[i], &res.rep);
-      res.status = s->h_status[i].numeric_error ? ENMF_ENUMERIC : ENMF_OK;
+      fill_report(hs[i], &res.rep);
+      res.status = hs[i].numeric_error ? ENMF_ENUMERIC : ENMF_OK;
       res.latency_s = std::chrono::duration<double>(now - r.t_submit).count();
       s->done[r.ticket] = res;
       s->arena->release(r.off, r.bytes);
@@ -332,19 +397,26 @@ enmf_status enmf_serve_start(enmf_ctx* c, const enmf_serve_opts* opts, enmf_serv
   if (!c) return ENMF_EINVAL;
   enmf_serve_opts o{};
   if (opts) o = *opts;
-  if (o.max_slots < 0 || o.tick_budget < 0) return ENMF_EINVAL;
+  if (o.max_slots < 0 || o.tick_budget < 0 || o.ticks_per_launch < 0 ||
+      (o.direct_launch != 0 && o.direct_launch != 1))
+    return ENMF_EINVAL;
   auto* s = new enmf_server();
   s->device = ctx_device(c);
   s->max_slots = o.max_slots > 0 ? o.max_slots : 512;
   s->budget = (int64_t)(o.tick_budget > 0 ? o.tick_budget : 64) << 20;
+  s->ticks = o.ticks_per_launch > 0 ? o.ticks_per_launch : 4;
+  s->direct = o.direct_launch == 1;
   const int64_t arena_bytes = o.hbm_budget_bytes > 0 ? (int64_t)o.hbm_budget_bytes : (1LL << 30);
   auto bail = [&](enmf_status st, const char* msg) {
     ctx_set_error(c, msg);
     if (s->d_slots) (void)hipFree(s->d_slots);
     if (s->d_status) (void)hipFree(s->d_status);
     if (s->arena_base) (void)hipFree(s->arena_base);
-    if (s->h_status) (void)hipHostFree(s->h_status);
+    for (ServeStatus* h : {s->h_ring[0], s->h_ring[1], s->h_init})
+      if (h) (void)hipHostFree(h);
     if (s->h_stage) (void)hipHostFree(s->h_stage);
+    for (hipEvent_t ev : s->ev)
+      if (ev) (void)hipEventDestroy(ev);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
     return st;
@@ -362,12 +434,22 @@ enmf_status enmf_serve_start(enmf_ctx* c, const enmf_serve_opts* opts, enmf_serv
     (void)hipGetLastError();
     return bail(ENMF_ENOMEM, "serving slot allocation failed");
   }
-  if (hipHostMalloc(&s->h_status, sizeof(ServeStatus) * s->max_slots) != hipSuccess ||
+  if (hipHostMalloc(&s->h_ring[0], sizeof(ServeStatus) * s->max_slots) != hipSuccess ||
+      hipHostMalloc(&s->h_ring[1], sizeof(ServeStatus) * s->max_slots) != hipSuccess ||
+      hipHostMalloc(&s->h_init, sizeof(ServeStatus) * s->max_slots) != hipSuccess ||
       hipHostMalloc(&s->h_stage, sizeof(ServeSlot) * s->max_slots) != hipSuccess) {
     (void)hipGetLastError();
     return bail(ENMF_ENOMEM, "pinned host allocation failed");
   }
-  if (hipMemset(s->d_status, 0, sizeof(ServeStatus) * s->max_slots) != hipSuccess)
+  if (hipEventCreateWithFlags(&s->ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ev[1], hipEventDisableTiming) != hipSuccess)
+    return bail(ENMF_EDEVICE, "event creation failed");
+  // every slot starts idle; a newly admitted slot's status is uploaded from h_init
+  std::memset(s->h_init, 0, sizeof(ServeStatus) * s->max_slots);
+  for (int i = 0; i < s->max_slots; ++i) s->h_init[i].status = kSlotRunning;
+  std::memset(s->h_ring[0], 0, sizeof(ServeStatus) * s->max_slots);
+  if (hipMemcpy(s->d_status, s->h_ring[0], sizeof(ServeStatus) * s->max_slots,
+                hipMemcpyHostToDevice) != hipSuccess)
     return bail(ENMF_EDEVICE, "status initialisation failed");
   s->arena = new Arena(arena_bytes);
   s->slots.resize(s->max_slots);
@@ -429,11 +511,14 @@ enmf_status enmf_serve_stop(enmf_server* s) {
   const bool failed = s->failed;
   (void)hipSetDevice(s->device);
   (void)hipStreamSynchronize(s->stream);
+  for (hipGraphExec_t g : s->graphs)
+    if (g) (void)hipGraphExecDestroy(g);
   (void)hipFree(s->d_slots);
   (void)hipFree(s->d_status);
   (void)hipFree(s->arena_base);
-  (void)hipHostFree(s->h_status);
+  for (ServeStatus* h : {s->h_ring[0], s->h_ring[1], s->h_init}) (void)hipHostFree(h);
   (void)hipHostFree(s->h_stage);
+  for (hipEvent_t ev : s->ev) (void)hipEventDestroy(ev);
   (void)hipStreamDestroy(s->stream);
   delete s->arena;
   delete s;

@@ -55,7 +55,7 @@ class IterOpts(Structure):
     _fields_ = [("step_u", c_double), ("step_v", c_double), ("pbcd_eps", c_double),
                 ("relerr_tol", c_double), ("kkt_tol", c_double), ("relerr_svd", c_double),
                 ("ext_iters", c_int32), ("pbcd_max_iter", c_int32), ("max_iter", c_int32),
-                ("check_every", c_int32), ("mode", c_int32), ("reserved", c_int32)]
+                ("check_every", c_int32), ("mode", c_int32), ("graph_replay", c_int32)]
 
 
 class IterReport(Structure):
@@ -74,7 +74,7 @@ class Kkt(Structure):
 
 class ServeOpts(Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", c_int32),
-                ("tick_budget", c_int32)]
+                ("tick_budget", c_int32), ("ticks_per_launch", c_int32), ("direct_launch", c_int32)]
 
 
 class Request(Structure):
@@ -420,14 +420,14 @@ class Context:
 
     def iterate(self, X, U, V, max_iter, ext_iters=10, pbcd_max_iter=5, pbcd_eps=0.0,
                 step_u=0.0, step_v=0.0, check_every=1, kkt_tol=-1.0, relerr_tol=-1.0,
-                relerr_svd=0.0, mode=0, trace_cap=0):
+                relerr_svd=0.0, mode=0, trace_cap=0, graph_replay=0):
         M = matrix(X)
         m, n = X.shape
         r = U.shape[1]
         _factor(U, m, r, "U")
         _factor(V, n, r, "V")
         o = IterOpts(step_u, step_v, pbcd_eps, relerr_tol, kkt_tol, relerr_svd, ext_iters,
-                     pbcd_max_iter, max_iter, check_every, mode, 0)
+                     pbcd_max_iter, max_iter, check_every, mode, int(graph_replay))
         rep = IterReport()
         trace = None
         if trace_cap > 0:
@@ -487,11 +487,12 @@ class Server:
     them until then.
     """
 
-    def __init__(self, ctx, hbm_budget_bytes=0, max_slots=0, tick_budget=0):
+    def __init__(self, ctx, hbm_budget_bytes=0, max_slots=0, tick_budget=0, ticks_per_launch=0,
+                 direct_launch=0):
         self._lib = ctx._lib
         self._ctx = ctx
         h = c_void_p()
-        o = ServeOpts(hbm_budget_bytes, max_slots, tick_budget)
+        o = ServeOpts(hbm_budget_bytes, max_slots, tick_budget, ticks_per_launch, direct_launch)
         st = self._lib.enmf_serve_start(ctx._h, byref(o), byref(h))
         if st != 0:
             raise EnmfError(st, self._lib.enmf_last_error(ctx._h).decode())

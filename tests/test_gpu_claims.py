@@ -3,6 +3,8 @@
 * Repeatability: two runs of enmf_iterate on the same input give bitwise the
   same factors and report (every reduction runs in a fixed order, no atomics),
   on the matrix-core path (r >= 16) and the vector-ALU path.
+* The loop body replayed from a captured HIP graph gives bitwise the result
+  of direct launches.
 * Resume: 200 iterations equal 100 + 100 when the second call is given the
   push sizes the first one reported (the state of the loop is U, V and the
   resolved steps only).
@@ -85,6 +87,39 @@ def test_iterate_resume(lib, problem):
     assert r2["step_u"] == r1["step_u"] and r2["step_v"] == r1["step_v"]
     assert torch.equal(Ua, Ub) and torch.equal(Va, Vb)
     assert r2["f"] == ra["f"] and r2["kkt"] == ra["kkt"]
+
+
+@pytest.mark.parametrize("opts", [dict(max_iter=61), dict(max_iter=60, check_every=3),
+                                  dict(max_iter=300, kkt_tol=1e-5),
+                                  dict(max_iter=40, pbcd_eps=0.3, pbcd_max_iter=4),
+                                  dict(max_iter=64, mode=3)],
+                         ids=["odd", "check3", "kkt_stop", "pbcd_eps", "mode3"])
+def test_iterate_graph_replay_matches_direct(lib, problem, opts):
+    """The loop body replayed from a captured graph against every kernel
+    launched directly (the default): the same factors, report and trace bit
+    for bit, with the trailing odd iteration, a check period, a stop inside a
+    replayed pair, the PBCD tolerance sweeps and the stop at feasibility.
+    The graph is replayed up to 149 times in one call, with the host's stop
+    look (a copy and an event) between replays."""
+    X, r, U0, V0, rso = problem
+    say(f"graph replay vs direct launches {X.shape} r={r} {opts}")
+    Xd = to_dev(X)
+    outs = []
+    for replay in (0, 1):
+        U, V = to_dev(U0), to_dev(V0)
+        rep = lib.iterate(Xd, U, V, relerr_svd=rso, trace_cap=opts["max_iter"] + 1,
+                          graph_replay=replay, **opts)
+        outs.append((U, V, rep))
+    (U1, V1, r1), (U2, V2, r2) = outs
+    say(f"  iters {r1['iters']} / {r2['iters']} converged {r1['converged']} kkt {r1['kkt']:.3e}")
+    assert torch.equal(U1, U2) and torch.equal(V1, V2)
+    for key in ("f", "kkt", "relerr", "iters", "ext_iters_done", "converged", "step_u", "step_v"):
+        assert r1[key] == r2[key], key
+    t1, t2 = r1["trace"].cpu().numpy(), r2["trace"].cpu().numpy()
+    n1 = int(np.count_nonzero(t1[:, 6]))
+    assert n1 == int(np.count_nonzero(t2[:, 6])) and n1 > 0
+    cols = [0, 1, 2, 3, 4, 5, 7]            # every field but the device clock
+    assert np.array_equal(t1[:n1][:, cols], t2[:n1][:, cols])
 
 
 @pytest.mark.parametrize("bad", [float("nan"), float("inf")])

@@ -7,7 +7,10 @@ test matrix omega:
 * bfloat16 X: the oracle's relative error within 1e-3 and a KKT residual <= 1e-5.
 
 A request gives bitwise the same factors when it runs alone, in a mix of
-uneven requests of several dtypes, and under a different tick budget.
+uneven requests of several dtypes, under a different tick budget, and with
+its ticks launched one by one instead of replayed from a captured graph.
+Requests at the large end of the stream (about 2048 x 2048, r = 30-32) meet
+the same bar as the small ones.
 Errors: r beyond the served range, a workspace that can never fit, and an
 unknown ticket.
 """
@@ -140,11 +143,16 @@ def test_same_result_alone_and_in_the_mix(lib):
         U3, V3, r3 = run(srv, mix[:6])
     finally:
         srv.stop()
-    say(f"  iters {r1['iters']} {r2['iters']} {r3['iters']}  relerr {r1['relerr']:.6e}")
-    assert np.array_equal(U1, U2) and np.array_equal(V1, V2)
-    assert np.array_equal(U1, U3) and np.array_equal(V1, V3)
-    assert r1["iters"] == r2["iters"] == r3["iters"]
-    assert r1["relerr"] == r2["relerr"] == r3["relerr"]
+    # the same ticks launched one by one instead of replayed from a graph, one per replay
+    srv = enmf.Server(lib, max_slots=8, tick_budget=3, ticks_per_launch=1, direct_launch=1)
+    try:
+        U4, V4, r4 = run(srv, mix[6:10])
+    finally:
+        srv.stop()
+    say(f"  iters {r1['iters']} {r2['iters']} {r3['iters']} {r4['iters']}  relerr {r1['relerr']:.6e}")
+    for Ux, Vx, rx in ((U2, V2, r2), (U3, V3, r3), (U4, V4, r4)):
+        assert np.array_equal(U1, Ux) and np.array_equal(V1, Vx)
+        assert r1["iters"] == rx["iters"] and r1["relerr"] == rx["relerr"]
 
 
 def test_served_stream_sample_matches_oracle(lib, server):
@@ -164,6 +172,30 @@ def test_served_stream_sample_matches_oracle(lib, server):
         say(f"  {q['m']}x{q['n']} r={q['r']}: iters {res['iters']} relerr {err:.5e} "
             f"oracle {ro['relerr']:.5e} ({ro['iters']} iters) latency {res['latency_s']:.3f} s")
         assert res["status"] == 0
+        assert abs(err - ro["relerr"]) <= 1e-3
+        assert host(U).min() >= 0 and host(V).min() >= 0
+
+
+def test_served_large_requests_match_oracle(lib, server):
+    """Requests at the large end of the served stream (m, n near 2048, r near
+    32, bfloat16 X), submitted together: each reaches the oracle's relative
+    error within 1e-3 (against the float32 X), with nonnegative factors."""
+    say("served large requests (bf16, ~2048 x 2048, r 30-32) vs the oracle")
+    shapes = [(2048, 1900, 32, 3101), (1850, 2048, 30, 3102), (2000, 2000, 32, 3103)]
+    live = []
+    for m, n, r, seed in shapes:
+        X, _, _ = inputs.lowrank_plus_noise(m, n, r, seed)
+        om = inputs.omega(n, r + 10, seed + 1)
+        Xb = lib.convert(to_dev(X), torch.bfloat16)
+        t, U, V = server.submit(Xb, r, to_dev(om), max_iter=300, relerr_tol=1e-3, kkt_tol=1e-5)
+        live.append((m, n, r, X, om, t, U, V))
+    for m, n, r, X, om, t, U, V in live:
+        res = server.wait(t, timeout=300.0)
+        Uo, Vo, ro = O.enmf(X, r, om, max_iter=300, relerr_tol=1e-3, kkt_tol=1e-5)
+        err = O.relerr(X, host(U), host(V))
+        say(f"  {m}x{n} r={r}: iters {res['iters']} relerr {err:.6e} oracle {ro['relerr']:.6e} "
+            f"({ro['iters']} iters) kkt {res['kkt']:.2e} latency {res['latency_s']:.3f} s")
+        assert res["status"] == 0 and res["converged"] == 1
         assert abs(err - ro["relerr"]) <= 1e-3
         assert host(U).min() >= 0 and host(V).min() >= 0
 
