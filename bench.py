@@ -40,6 +40,7 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X fp32 vector / matrix, dense
 PEAK_HBM_GBS = 8000.0
 SAMPLE_PERIOD = 4            # every 4th outer iteration's streaming kernels are event-timed
 GOLDEN = os.path.join(ROOT, "tests", "golden")
+XT_MIN_BYTES = 512 << 20     # X at least this large: enmf_iterate runs X B on a transposed copy
 # HBM bytes per launch of the streaming kernels inside the ratings solve, from two rocprofv3
 # passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters' reading for a device copy of
 # known size (profiles/k_xv_k_xtu_ratings_100000x20000_r20_hbm_traffic.txt).  They describe the
@@ -74,6 +75,11 @@ def parse():
     ap.add_argument("--serve-plain", type=int, default=256,
                     help="requests of the stream also solved one by one by the float32 form")
     return ap.parse_args()
+
+
+def log(msg):
+    """Progress of the run on stderr (the JSON line goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def read_golden(name):
@@ -230,6 +236,9 @@ def roofline(X, r, form):
     m, n = X.shape
     bf = X.element_size() == 2
     names = ("k_xv_bf16", "k_xtu_bf16") if bf else ("k_xv_f32s", "k_xtu_f32s")
+    if m * n * X.element_size() >= XT_MIN_BYTES:
+        # X B runs as X^T A on the transposed copy that enmf_iterate makes of X
+        names = (names[1] + " (X B on the transposed copy)", names[1] + " (X^T A)")
     times = (form["xv_ms"], form["xtu_ms"])
     d = 0 if times[0] >= times[1] else 1
     alg = m * n * X.element_size() + (m + n) * r * 4
@@ -549,12 +558,16 @@ def served(ctx, torch, inputs, enmf, count, load, slots, plain):
         conv = float(np.mean([x["converged"] for x in res]))
         return wall, lat, iters, conv
 
+    log(f"  served: closed loop, {count} requests")
     wall_c, lat_c, iters_c, conv_c = run(None)
     sat = count / wall_c
+    log("  served: closed loop with direct launches")
     wall_d, _, _, _ = run(None, direct=1)          # the same ticks launched one by one
     rate = load * sat
     arr = inputs.poisson_arrivals(count, rate, 7)
+    log(f"  served: open loop at {rate:.0f} requests/s")
     wall_o, lat_o, iters_o, conv_o = run(arr)
+    log("  served: the plain float32 form, one request at a time")
     out = {
         "requests": count, "dtype": "bf16", "slots": slots,
         "saturated_solves_per_s": round(sat, 2),
@@ -624,6 +637,7 @@ def main():
 
     dev = torch.device("cuda:0")
     ctx = enmf.Context(0)
+    log("generating the ratings matrix")
     X_np = inputs.ratings()
     m, n = X_np.shape
     r = RANK
@@ -637,7 +651,9 @@ def main():
         return
     ref = read_golden("ratings_oracle.txt")
     target = ref["relerr"] + 1e-3
+    log("ratings solve, bfloat16 X")
     bf = ratings_form(ctx, torch, Xb, Xf, om, r, args, ref, target)
+    log("ratings solve, float32 X")
     f32 = ratings_form(ctx, torch, Xf, Xf, om, r, args, ref, target)
     out = {
         "metric": METRIC, "value": bf["iters_per_s"], "unit": "iters/s",
@@ -662,30 +678,41 @@ def main():
     }
     if f32["time_to_relerr_s"] and bf["time_to_relerr_s"]:
         out["fp32_over_bf16_time_to_relerr"] = round(f32["time_to_relerr_s"] / bf["time_to_relerr_s"], 3)
+    log("streaming products")
     out["hbm_streaming"] = streaming(ctx, Xf, Xb, r)
     del Xf, Xb
     torch.cuda.empty_cache()
     if not args.headline_only:
         if not args.no_image:
+            log("image-patch leg")
             out["image"] = image_leg(ctx, torch, inputs, args)
         if not args.no_small:
+            log("small leg")
             out["small"] = small_leg(ctx, torch, inputs)
         if not args.no_spectrogram:
+            log("spectrogram leg")
             out["spectrogram"] = spectrogram_leg(ctx, torch, inputs)
         if not args.no_ablation:
+            log("ablation leg")
             out["ablation"] = ablation_leg(ctx, torch, inputs)
         torch.cuda.empty_cache()
         if not args.no_enmc:
+            log("matrix-completion leg")
             out["enmc"] = enmc_leg(ctx, torch, inputs, enmf)
         if not args.no_sparse:
+            log("sparse leg (generating the term-document matrix)")
             out["sparse"] = sparse_leg(ctx, torch, inputs)
         if not args.no_grot:
+            log("generalized-rotation leg")
             out["generalized_rotation"] = grot_leg(ctx, torch, inputs)
         if not args.no_serve:
+            log("served leg")
             out["served"] = served(ctx, torch, inputs, enmf, args.serve_requests, args.serve_load,
                                    args.serve_slots, args.serve_plain)
     if not args.no_cpu:
+        log("cpu baseline (the oracle on a row slice)")
         out["cpu_baseline"] = cpu_baseline(X_np, om_np, args.cpu_rows, args.cpu_iters)
+    log("done")
     print(json.dumps(out), flush=True)
     ctx.close()
 

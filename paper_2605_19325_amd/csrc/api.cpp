@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -19,7 +20,7 @@ enum Slot {
   S_Y, S_QM64, S_QM32, S_Z, S_QN64, S_QN32, S_TMP64, S_T, S_C, S_COLP, S_COLS, S_SIG, S_TU, S_TV,
   S_W64, S_YA, S_ZA, S_R, S_WSQ, S_MPART,
   S_EX, S_ERU, S_ERV, S_EE, S_ERSS, S_ECU, S_ECV, S_EG, S_EGI, S_EST, S_ESTAT, S_SPX, S_SPG,
-  S_GW, S_GOUT, N_SLOTS
+  S_GW, S_GOUT, S_XT, N_SLOTS
 };
 
 constexpr int kTimingPairs = 64;   // sampled launches per kind and iterate call
@@ -39,6 +40,9 @@ struct enmf_ctx {
   DevState* st = nullptr;
   double ns_per_tick = 10.0;
   bool use_mfma = true;   // ENMF_FORCE_VALU=1 at creation selects the vector-ALU products
+  // X B of enmf_iterate through X^T A on a transposed copy of X when X holds at
+  // least this many bytes (ENMF_XT_MIN_BYTES at creation; default 512 MiB)
+  int64_t xt_min_bytes = int64_t(512) << 20;
   // in-solve sampling of the streaming kernels (enmf_kernel_timing)
   int timing_period = 0;
   std::vector<hipEvent_t> events;       // pool: [kind][pair][2]
@@ -135,6 +139,22 @@ bool use_mfma(const enmf_ctx* c, const enmf_matrix* X, int k) {
   return c->use_mfma && X->dtype != ENMF_CSR && mfma_eligible(X->dtype, k);
 }
 
+// A transposed copy of a dense X (n x m, leading dimension ld) that X B runs on.
+struct XTCopy {
+  const void* data = nullptr;
+  int64_t ld = 0;
+};
+
+// X B through X^T A on a transposed copy: dense X on the matrix cores whose
+// storage exceeds the last-level cache by far (xt_min_bytes).  The X^T A
+// kernel reads X in whole row runs and streams it closer to the HBM roof
+// than X B's operand-layout loads.
+bool use_xt(const enmf_ctx* c, const enmf_matrix* X, int k) {
+  if (!use_mfma(c, X, k) || c->xt_min_bytes <= 0) return false;
+  const int64_t esz = X->dtype == ENMF_F32 ? 4 : 2;
+  return X->m * X->n * esz >= c->xt_min_bytes;
+}
+
 // Split-partial bytes needed by either form of the products at width k.
 size_t split_bytes(const enmf_ctx* c, const enmf_matrix* X, int k) {
   if (const SparseX* sp = sparse_of(X)) {
@@ -224,10 +244,19 @@ struct Parts {
 // as a launch of its own after it).
 enmf_status xv_parts(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, float* P_out,
                      Parts* out, hipEvent_t* ev = nullptr, bool packed = false,
-                     const GramJob* gj = nullptr) {
+                     const GramJob* gj = nullptr, const XTCopy* xt = nullptr) {
   hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
   int ns = 1;
-  if (const SparseX* sp = sparse_of(X)) {
+  if (xt != nullptr && xt->data != nullptr) {
+    // P = X B = (X^T)^T B: the X^T A kernel on the transposed copy (n x m)
+    size_t pb = 0, sb = 0;
+    mfma_xtu_ws(X->dtype, X->n, X->m, k, &pb, &sb);
+    WS(pack, void, S_BP, pb);
+    WS(part, float, S_SPLIT, sb);
+    CK(launch_xtu_mfma(xt->data, X->dtype, X->n, X->m, xt->ld, B, k, pack, part, P_out, c->stream, 0,
+                       packed ? 0 : 1, &ns, &c->st->stop, e0, e1, gj, nullptr, nullptr));
+    out->p = ns > 1 ? part : P_out;
+  } else if (const SparseX* sp = sparse_of(X)) {
     if (e0) CK(hipEventRecord(e0, c->stream));
     TRY(do_spmm(c, X, sp->csr, B, k, P_out));
     if (e1) CK(hipEventRecord(e1, c->stream));
@@ -447,6 +476,7 @@ enmf_status enmf_create(enmf_ctx** out, int32_t device, void* hip_stream) {
     c->ns_per_tick = 1e6 / (double)khz;
   const char* fv = std::getenv("ENMF_FORCE_VALU");
   c->use_mfma = !(fv && fv[0] == '1');
+  if (const char* xb = std::getenv("ENMF_XT_MIN_BYTES")) c->xt_min_bytes = std::atoll(xb);
   *out = c;
   return ENMF_OK;
 }
@@ -780,14 +810,21 @@ enmf_status iter_setup(enmf_ctx* c, const enmf_matrix* X, int r, const float* U,
     const int kpw = pad_width(r);
     const int64_t rows_pad = round_up(n, xv_tile_width(X->dtype));
     size_t pbx = (size_t)rows_pad * kpw * 4, pbu = (size_t)m * kpw * 4;
+    size_t sbt = 0;
     if (use_mfma(c, X, r)) {
       size_t t = 0;
       mfma_xv_ws(X->dtype, m, n, r, &pbx, &t);
       mfma_xtu_ws(X->dtype, m, n, r, &pbu, &t);
+      if (use_xt(c, X, r)) {
+        size_t px = 0;
+        mfma_xtu_ws(X->dtype, n, m, r, &px, &sbt);   // X B on the transposed copy
+        if (px > pbx) pbx = px;
+      }
     }
     if (!ws(c, S_BP, pbx) || !ws(c, S_AP, pbu))
       return fail(c, ENMF_ENOMEM, "device workspace allocation failed");
     size_t sb = split_bytes(c, X, r);
+    if (sbt > sb) sb = sbt;
     const size_t sv = (size_t)xv_splits(m, n, X->dtype) * m * r * 4;
     const size_t su = (size_t)xtu_splits(m, n) * n * r * 4;
     if (!use_mfma(c, X, r)) sb = sv > su ? sv : su;
@@ -870,15 +907,28 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
   // matrix-core products: each row pass also writes its output rows as the
   // next product's packed factor (U for X^T U, V for X V)
   const bool mf = use_mfma(c, X, r);
+  // X B through X^T A on a transposed copy of X, made once for the call
+  XTCopy xtc;
+  const bool tx = use_xt(c, X, r);
+  if (tx) {
+    const int64_t ldt = round_up(m, 8);
+    WS(xtb, unsigned char, S_XT, (size_t)n * ldt * esize(X->dtype));
+    CK(launch_transpose(X->data, X->dtype, m, n, X->ld, xtb, ldt, s));
+    xtc.data = xtb;
+    xtc.ld = ldt;
+  }
+  const XTCopy* xtp = tx ? &xtc : nullptr;
   PackOut poU, poV;
   if (mf) {
     size_t pbx = 0, pbu = 0, t = 0;
-    mfma_xv_ws(X->dtype, m, n, r, &pbx, &t);
+    if (tx) mfma_xtu_ws(X->dtype, n, m, r, &pbx, &t);
+    else mfma_xv_ws(X->dtype, m, n, r, &pbx, &t);
     mfma_xtu_ws(X->dtype, m, n, r, &pbu, &t);
     WS(bp, unsigned short, S_BP, pbx);
     WS(ap, unsigned short, S_AP, pbu);
     poV.p = bp;
-    mfma_pack_layout(X->dtype, 0, r, &poV.kp, &poV.c, &poV.ldt);
+    // V is packed for whichever kernel runs X B
+    mfma_pack_layout(X->dtype, tx ? 1 : 0, r, &poV.kp, &poV.c, &poV.ldt);
     poU.p = ap;
     mfma_pack_layout(X->dtype, 1, r, &poU.kp, &poU.c, &poU.ldt);
   }
@@ -914,7 +964,7 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
     dec.recU = b.recU(cur); dec.nbU = b.nbU;
     dec.recV = b.recV(prev); dec.nbV = b.nbV;
     dec.k = devk ? -1 : k; dec.due = due ? 1 : 0; dec.trace = trace;
-    TRY(xv_parts(c, X, V, r, b.P, &pp, devk ? nullptr : sample(0, k), mf, &gjG));
+    TRY(xv_parts(c, X, V, r, b.P, &pp, devk ? nullptr : sample(0, k), mf, &gjG, xtp));
     const int head = kRowHead | kRowCheckPre | (due ? kRowWriteCheck : 0);
     if (fixed) {
       CK(launch_rowupdate(Ub[cur], Ub[prev], m, r, kp, pp.p, pp.n, pp.stride, b.G, st, 0,
@@ -1029,7 +1079,7 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
     dec.recU = b.recU(cur); dec.nbU = b.nbU;
     dec.recV = b.recV(prev); dec.nbV = b.nbV;
     dec.k = o.max_iter; dec.due = 1; dec.trace = trace;
-    TRY(xv_parts(c, X, V, r, b.P, &pp, sample(0, o.max_iter), mf, &gjG));
+    TRY(xv_parts(c, X, V, r, b.P, &pp, sample(0, o.max_iter), mf, &gjG, xtp));
     CK(launch_rowupdate(Ub[cur], Ub[cur], m, r, kp, pp.p, pp.n, pp.stride, b.G, st, 0, 0,
                         kRowHead | kRowCheckPre | kRowWriteCheck, b.recU(cur), b.gpU, b.recU(prev),
                         b.nbU, b.recV(prev), b.nbV, s));

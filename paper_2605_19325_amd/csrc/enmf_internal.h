@@ -132,6 +132,9 @@ hipError_t launch_sumsq_x(const void* X, int xt, int64_t m, int64_t n, int64_t l
                           int* nparts, hipStream_t s);
 hipError_t launch_sum_parts(const double* part, int nparts, int stride, int nfields, double* out,
                             hipStream_t s);
+// XT (n x m, leading dimension ldt) = X^T, X of storage type xt.
+hipError_t launch_transpose(const void* X, int xt, int64_t m, int64_t n, int64_t ld, void* XT,
+                            int64_t ldt, hipStream_t s);
 hipError_t launch_convert(const float* x, int64_t m, int64_t n, int64_t ldi, int to, void* out,
                           int64_t ldo, hipStream_t s);
 

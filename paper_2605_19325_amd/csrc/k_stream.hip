@@ -255,12 +255,17 @@ __global__ void k_pad_cols(const float* __restrict__ in, int64_t rows_in, int k,
 }
 
 // Direct residual: part[b] = sum over this block's (i, j) of (X_ij - U_i . V_j)^2,
-// with the dot product and the square accumulated in float64.  Lane = column j.
-// KP is a multiple of 4.
+// with the dot product and the square accumulated in float64.  Lane = column
+// j, whose row of V (KP values, zero past r) sits in registers; the rows of U
+// (float64, row stride ldu) are uniform across the block, so they arrive
+// through scalar loads as instruction operands.  Rows go RB at a time, their
+// x values loaded before the first dot product, so that enough of the X
+// stream is in flight (one 2- or 4-byte load per lane and row).  KP is a
+// multiple of 4.
 template <int XT, int KP>
 __global__ __launch_bounds__(kThreads) void k_residual(const void* __restrict__ Xv, int64_t m,
                                                        int64_t n, int64_t ld,
-                                                       const double* __restrict__ Ud,
+                                                       const double* __restrict__ Ud, int ldu,
                                                        const float* __restrict__ V, int r,
                                                        int64_t rows_per_split,
                                                        double* __restrict__ part) {
@@ -269,47 +274,98 @@ __global__ __launch_bounds__(kThreads) void k_residual(const void* __restrict__ 
   const ET* __restrict__ X = reinterpret_cast<const ET*>(Xv);
   const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool valid = j < n;
+  const int64_t jc = valid ? j : 0;   // in-bounds column for the loads of idle lanes
   double v[KP];
 #pragma unroll
   for (int c = 0; c < KP; ++c) v[c] = (valid && c < r) ? (double)V[j * r + c] : 0.0;
   const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
   const int64_t r1 = r0 + rows_per_split < m ? r0 + rows_per_split : m;
+  constexpr int RB = KP <= 32 ? 16 : 8;
   double acc = 0.0;
-  if (valid) {
-    for (int64_t i = r0; i < r1; ++i) {
-      const double* __restrict__ urow = Ud + i * KP;
-      // four interleaved partial dot products (columns c mod 4), so that the
-      // fma chain per entry is KP / 4 long
-      double d4[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i0 = r0; i0 < r1; i0 += RB) {
+    float xs[RB];
 #pragma unroll
-      for (int c = 0; c < KP; ++c) d4[c % 4] = fma(urow[c], v[c], d4[c % 4]);
-      const double d = (d4[0] + d4[1]) + (d4[2] + d4[3]);
-      const double e = (double)to_f32<XT>(X[i * ld + j]) - d;
-      acc = fma(e, e, acc);
+    for (int q = 0; q < RB; ++q) {
+      const int64_t i = i0 + q < r1 ? i0 + q : r1 - 1;
+      xs[q] = to_f32<XT>(X[i * ld + jc]);
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      if (i0 + q < r1) {
+        const double* __restrict__ urow = Ud + (i0 + q) * ldu;
+        // four interleaved partial dot products (columns c mod 4)
+        double d4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < KP; ++c) d4[c % 4] = fma(urow[c], v[c], d4[c % 4]);
+        const double d = (d4[0] + d4[1]) + (d4[2] + d4[3]);
+        const double e = (double)xs[q] - d;
+        acc = valid ? fma(e, e, acc) : acc;
+      }
     }
   }
   const double t = block_sum<kThreads>(acc, sh);
   if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
 }
 
-// part[b] = sum of x^2 over the rows of block b.
+// part[b] = sum of x^2 over the rows of block b, accumulated in float64.  The
+// block's rows are walked as one row-major range of 16-byte vectors (vec: rows
+// 16-byte aligned) or of elements, thread t taking every kThreads-th one with
+// four loads in flight; its (row, position) advances without a division.  A
+// row whose length is not a whole number of vectors adds its last elements
+// separately.
 template <int XT>
 __global__ __launch_bounds__(kThreads) void k_sumsq(const void* __restrict__ Xv, int64_t m,
                                                     int64_t n, int64_t ld, int64_t rows_per_block,
-                                                    double* __restrict__ part) {
+                                                    int vec, double* __restrict__ part) {
   __shared__ double sh[kThreads / kWave];
   using ET = typename XElem<XT>::T;
+  constexpr int EPV = 16 / sizeof(ET);
   const ET* __restrict__ X = reinterpret_cast<const ET*>(Xv);
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t r1 = r0 + rows_per_block < m ? r0 + rows_per_block : m;
+  // units per row: whole vectors, or elements
+  const int64_t nu = vec ? n / EPV : n;
   double acc = 0.0;
-  for (int64_t i = r0; i < r1; ++i) {
-    float rowacc = 0.f;
-    for (int64_t j = threadIdx.x; j < n; j += kThreads) {
-      const float x = to_f32<XT>(X[i * ld + j]);
-      rowacc = fmaf(x, x, rowacc);
+  if (nu > 0) {
+    int64_t i = r0 + threadIdx.x / nu, p = threadIdx.x % nu;
+    while (i < r1) {
+      uint4 q[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (i < r1) {
+          if (vec) {
+            q[u] = *reinterpret_cast<const uint4*>(X + i * ld + p * EPV);
+          } else {
+            const float x = to_f32<XT>(X[i * ld + p]);
+            q[u] = make_uint4(__float_as_uint(x), 0u, 0u, 0u);
+          }
+          p += kThreads;
+          while (p >= nu) { p -= nu; ++i; }
+        } else {
+          q[u] = make_uint4(0u, 0u, 0u, 0u);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (vec) {
+          float xs[8];
+          unpack<XT>(q[u], xs);
+#pragma unroll
+          for (int e = 0; e < EPV; ++e) acc = fma((double)xs[e], (double)xs[e], acc);
+        } else {
+          const double x = (double)__uint_as_float(q[u].x);
+          acc = fma(x, x, acc);
+        }
+      }
     }
-    acc += (double)rowacc;
+  }
+  if (vec) {
+    const int64_t tail = n - (n / EPV) * EPV;
+    if (threadIdx.x < tail)
+      for (int64_t i = r0; i < r1; ++i) {
+        const double x = (double)to_f32<XT>(X[i * ld + (n / EPV) * EPV + threadIdx.x]);
+        acc = fma(x, x, acc);
+      }
   }
   const double t = block_sum<kThreads>(acc, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -365,6 +421,57 @@ __global__ void k_convert(const float* __restrict__ x, int64_t m, int64_t n, int
   }
 }
 
+// XT (n x m, ld ldt) = X^T for X (m x n, ld ld), element type ET (2 or 4
+// bytes).  One block moves a 64 x 64 tile through LDS: thread t reads 16
+// consecutive elements of input row t / 4 and writes 16 consecutive elements
+// of output row t / 4, with 16-byte accesses where the rows allow them.
+template <typename ET>
+__global__ __launch_bounds__(256) void k_transpose(const ET* __restrict__ X, int64_t m, int64_t n,
+                                                   int64_t ld, ET* __restrict__ XT, int64_t ldt,
+                                                   int vin, int vout) {
+  constexpr int EPV = 16 / sizeof(ET);
+  __shared__ ET tile[64][64 + EPV];
+  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+  const int rr = threadIdx.x / 4, seg = 16 * (threadIdx.x % 4);
+  {
+    const int64_t i = i0 + rr, j = j0 + seg;
+    ET v[16];
+    if (vin && i < m && j + 16 <= n) {
+#pragma unroll
+      for (int q = 0; q < 16 / EPV; ++q) {
+        const uint4 w = *reinterpret_cast<const uint4*>(X + i * ld + j + q * EPV);
+        __builtin_memcpy(&v[q * EPV], &w, 16);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = (i < m && j + e < n) ? X[i * ld + j + e] : ET(0);
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) tile[rr][seg + e] = v[e];
+  }
+  __syncthreads();
+  {
+    const int64_t jo = j0 + rr, io = i0 + seg;   // output row jo, columns io ..
+    if (jo < n) {
+      ET v[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = tile[seg + e][rr];
+      if (vout && io + 16 <= m) {
+#pragma unroll
+        for (int q = 0; q < 16 / EPV; ++q) {
+          uint4 w;
+          __builtin_memcpy(&w, &v[q * EPV], 16);
+          *reinterpret_cast<uint4*>(XT + jo * ldt + io + q * EPV) = w;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+          if (io + e < m) XT[jo * ldt + io + e] = v[e];
+      }
+    }
+  }
+}
+
 int grid_for(int64_t count, int threads = 256, int cap = 8192) {
   int64_t g = (count + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -417,14 +524,15 @@ void xtu_dispatch_kp(int kp, dim3 grid, const void* X, int64_t m, int64_t n, int
 
 template <int XT>
 void residual_dispatch(int kp, dim3 grid, const void* X, int64_t m, int64_t n, int64_t ld,
-                       const double* Ud, const float* V, int r, int64_t rps, double* part,
+                       const double* Ud, int ldu, const float* V, int r, int64_t rps, double* part,
                        hipStream_t s) {
   switch (kp) {
-    case 8: hipLaunchKernelGGL((k_residual<XT, 8>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, V, r, rps, part); break;
-    case 16: hipLaunchKernelGGL((k_residual<XT, 16>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, V, r, rps, part); break;
-    case 32: hipLaunchKernelGGL((k_residual<XT, 32>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, V, r, rps, part); break;
-    case 48: hipLaunchKernelGGL((k_residual<XT, 48>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, V, r, rps, part); break;
-    default: hipLaunchKernelGGL((k_residual<XT, 64>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, V, r, rps, part); break;
+    case 8: hipLaunchKernelGGL((k_residual<XT, 8>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); break;
+    case 16: hipLaunchKernelGGL((k_residual<XT, 16>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); break;
+    case 24: hipLaunchKernelGGL((k_residual<XT, 24>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); break;
+    case 32: hipLaunchKernelGGL((k_residual<XT, 32>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); break;
+    case 48: hipLaunchKernelGGL((k_residual<XT, 48>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); break;
+    default: hipLaunchKernelGGL((k_residual<XT, 64>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); break;
   }
 }
 
@@ -521,7 +629,9 @@ hipError_t launch_xtu(const void* X, int xt, int64_t m, int64_t n, int64_t ld, c
 // Residual partials: Ud is U padded to kp float64 columns (m rows).
 hipError_t launch_residual(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const double* Ud,
                            const float* V, int r, double* part, int* nparts, hipStream_t s) {
-  const int kp = pad_width(r) > 64 ? 64 : pad_width(r);
+  // Ud has pad_width(r) columns; the kernel reads the first kp (>= r) of them
+  const int ldu = pad_width(r);
+  const int kp = r <= 8 ? 8 : r <= 16 ? 16 : r <= 24 ? 24 : r <= 32 ? 32 : r <= 48 ? 48 : 64;
   const int64_t cb = (n + kThreads - 1) / kThreads;
   int64_t sp = (kTargetBlocks + cb - 1) / cb;
   if (sp > m) sp = m;
@@ -530,9 +640,9 @@ hipError_t launch_residual(const void* X, int xt, int64_t m, int64_t n, int64_t 
   sp = (m + rps - 1) / rps;
   dim3 grid((unsigned)cb, (unsigned)sp);
   switch (xt) {
-    case ENMF_F32: residual_dispatch<0>(kp, grid, X, m, n, ld, Ud, V, r, rps, part, s); break;
-    case ENMF_BF16: residual_dispatch<1>(kp, grid, X, m, n, ld, Ud, V, r, rps, part, s); break;
-    default: residual_dispatch<2>(kp, grid, X, m, n, ld, Ud, V, r, rps, part, s); break;
+    case ENMF_F32: residual_dispatch<0>(kp, grid, X, m, n, ld, Ud, ldu, V, r, rps, part, s); break;
+    case ENMF_BF16: residual_dispatch<1>(kp, grid, X, m, n, ld, Ud, ldu, V, r, rps, part, s); break;
+    default: residual_dispatch<2>(kp, grid, X, m, n, ld, Ud, ldu, V, r, rps, part, s); break;
   }
   *nparts = (int)(cb * sp);
   return hipGetLastError();
@@ -544,10 +654,12 @@ hipError_t launch_sumsq_x(const void* X, int xt, int64_t m, int64_t n, int64_t l
   if (nb < 1) nb = 1;
   const int64_t rpb = (m + nb - 1) / nb;
   nb = (m + rpb - 1) / rpb;
+  const int esz = xt == ENMF_F32 ? 4 : 2;
+  const int vec = (reinterpret_cast<uintptr_t>(X) % 16 == 0 && (ld * esz) % 16 == 0) ? 1 : 0;
   switch (xt) {
-    case ENMF_F32: hipLaunchKernelGGL((k_sumsq<0>), dim3((unsigned)nb), dim3(kThreads), 0, s, X, m, n, ld, rpb, part); break;
-    case ENMF_BF16: hipLaunchKernelGGL((k_sumsq<1>), dim3((unsigned)nb), dim3(kThreads), 0, s, X, m, n, ld, rpb, part); break;
-    default: hipLaunchKernelGGL((k_sumsq<2>), dim3((unsigned)nb), dim3(kThreads), 0, s, X, m, n, ld, rpb, part); break;
+    case ENMF_F32: hipLaunchKernelGGL((k_sumsq<0>), dim3((unsigned)nb), dim3(kThreads), 0, s, X, m, n, ld, rpb, vec, part); break;
+    case ENMF_BF16: hipLaunchKernelGGL((k_sumsq<1>), dim3((unsigned)nb), dim3(kThreads), 0, s, X, m, n, ld, rpb, vec, part); break;
+    default: hipLaunchKernelGGL((k_sumsq<2>), dim3((unsigned)nb), dim3(kThreads), 0, s, X, m, n, ld, rpb, vec, part); break;
   }
   *nparts = (int)nb;
   return hipGetLastError();
@@ -558,6 +670,23 @@ hipError_t launch_sum_parts(const double* part, int nparts, int stride, int nfie
   if (nfields < 1) return hipSuccess;
   hipLaunchKernelGGL(k_sum_parts, dim3((nfields + 3) / 4), dim3(256), 0, s, part, nparts, stride,
                      nfields, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const void* X, int xt, int64_t m, int64_t n, int64_t ld, void* XT,
+                            int64_t ldt, hipStream_t s) {
+  const int esz = xt == ENMF_F32 ? 4 : 2;
+  const int vin = (reinterpret_cast<uintptr_t>(X) % 16 == 0 && (ld * esz) % 16 == 0) ? 1 : 0;
+  const int vout = (reinterpret_cast<uintptr_t>(XT) % 16 == 0 && (ldt * esz) % 16 == 0) ? 1 : 0;
+  const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((m + 63) / 64));
+  if (grid.y > 65535u) return hipErrorInvalidValue;
+  if (xt == ENMF_F32)
+    hipLaunchKernelGGL((k_transpose<float>), grid, dim3(256), 0, s, reinterpret_cast<const float*>(X),
+                       m, n, ld, reinterpret_cast<float*>(XT), ldt, vin, vout);
+  else
+    hipLaunchKernelGGL((k_transpose<unsigned short>), grid, dim3(256), 0, s,
+                       reinterpret_cast<const unsigned short*>(X), m, n, ld,
+                       reinterpret_cast<unsigned short*>(XT), ldt, vin, vout);
   return hipGetLastError();
 }
 

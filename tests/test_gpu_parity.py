@@ -259,6 +259,61 @@ def test_iterate_parity_ragged_blocks(lib, m, n, r, iters, mode):
     assert abs(rep["kkt"] - ro["kkt"]) <= 1e-4 * ro["kkt"]
 
 
+@pytest.fixture(scope="module")
+def lib_xt():
+    """A context whose enmf_iterate runs X B through the X^T A kernel on a
+    transposed copy of X at every size (by default only for X of 512 MiB and
+    more, where it is faster)."""
+    import os
+    old = os.environ.get("ENMF_XT_MIN_BYTES")
+    os.environ["ENMF_XT_MIN_BYTES"] = "1"
+    try:
+        ctx = enmf.Context()
+    finally:
+        if old is None:
+            del os.environ["ENMF_XT_MIN_BYTES"]
+        else:
+            os.environ["ENMF_XT_MIN_BYTES"] = old
+    yield ctx
+    ctx.close()
+
+
+@pytest.mark.parametrize("m,n,r,iters,mode,dt", [(1001, 517, 49, 12, 1, "f32"), (1001, 517, 49, 1, 0, "f32"),
+                                                (400, 300, 49, 60, 2, "f32"), (777, 1290, 20, 60, 2, "f32"),
+                                                (1001, 517, 49, 200, 0, "bf16")])
+def test_iterate_transposed_copy(lib_xt, m, n, r, iters, mode, dt):
+    """X B through the X^T A kernel on a transposed copy of X (the form the
+    large workloads take): the same bars as the direct product, float32
+    factors within 1e-4 and f within 1e-5 of the oracle (shapes whose last
+    row and column tiles are ragged), and for bfloat16 X the oracle's
+    relative error within 1e-3 with nonnegative factors; graph replays give
+    the same bits."""
+    say(f"iterate through the transposed copy, {m}x{n} r={r}, {iters} iterations mode {mode} {dt}")
+    X, _, _ = inputs.lowrank_plus_noise(m, n, r, seed=m + n + r)
+    om = inputs.omega(n, r + 10, r)
+    U0, V0, rso = _rotated_start(X, r, om)
+    Uo, Vo, ro = O.iterate(X, U0, V0, max_iter=iters, relerr_svd=rso, mode=mode)
+    Xd = to_dev(X) if dt == "f32" else lib_xt.convert(to_dev(X), torch.bfloat16)
+    outs = []
+    for replay in (0, 1):
+        U, V = to_dev(U0), to_dev(V0)
+        rep = lib_xt.iterate(Xd, U, V, max_iter=iters, relerr_svd=rso, mode=mode, graph_replay=replay)
+        outs.append((U, V, rep))
+    (U, V, rep), (U2, V2, _) = outs
+    assert torch.equal(U, U2) and torch.equal(V, V2)
+    say(f"  |dU|/|U| {rel(host(U), Uo):.2e} |dV|/|V| {rel(host(V), Vo):.2e} f {rep['f']:.9e} "
+        f"oracle {ro['f']:.9e}")
+    assert rep["iters"] == ro["iters"]
+    if dt == "f32":
+        assert rep["ext_iters_done"] == ro["ext_iters_done"]
+        assert rel(host(U), Uo) <= 1e-4 and rel(host(V), Vo) <= 1e-4
+        if mode == 2:
+            assert abs(rep["f"] - ro["f"]) <= 1e-5 * ro["f"]
+    else:
+        assert abs(O.relerr(X, host(U), host(V)) - ro["relerr"]) <= 1e-3
+        assert float(U.min()) >= 0.0 and float(V.min()) >= 0.0
+
+
 def test_iterate_pbcd_eps_path(lib, small):
     X, r, om = small
     say("iterate parity with the PBCD eps stop (multi-launch sweeps)")
