@@ -45,7 +45,9 @@ XT_MIN_BYTES = 512 << 20     # X at least this large: enmf_iterate runs X B on a
 # passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters' reading for a device copy of
 # known size (profiles/k_xv_k_xtu_ratings_100000x20000_r20_hbm_traffic.txt).  They describe the
 # kernel source they were taken on and are reported only while it is unchanged.
-TRAFFIC = {"k_mfma_sha256_16": None}
+TRAFFIC = {"k_mfma_sha256_16": "754a4cc2f9140798",
+           "k_xtu_bf16 (X^T A)": 4532.79e6, "k_xtu_bf16 (X B on the transposed copy)": 4343.24e6,
+           "k_xtu_f32s (X^T A)": 8288.86e6, "k_xtu_f32s (X B on the transposed copy)": 8107.64e6}
 
 
 def parse():
@@ -60,6 +62,9 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only a short ratings solve per form and a calibration copy (counter runs)")
     ap.add_argument("--headline-only", action="store_true", help="only the ratings solve")
+    ap.add_argument("--streaming-only", action="store_true",
+                    help="only the four products alone at the ratings shape (for counter runs)")
+    ap.add_argument("--no-streaming", action="store_true", help="skip the products-alone leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
     ap.add_argument("--no-image", action="store_true", help="skip the image-patch leg")
     ap.add_argument("--no-small", action="store_true", help="skip the small-workload leg")
@@ -71,7 +76,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-load", type=float, default=0.6,
                     help="open-loop arrival rate as a fraction of the closed-loop solves/s")
-    ap.add_argument("--serve-slots", type=int, default=256)
+    ap.add_argument("--serve-slots", type=int, default=512)
     ap.add_argument("--serve-plain", type=int, default=256,
                     help="requests of the stream also solved one by one by the float32 form")
     return ap.parse_args()
@@ -542,31 +547,40 @@ def served(ctx, torch, inputs, enmf, count, load, slots, plain):
         srv = enmf.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=slots, direct_launch=direct)
         try:
             t0 = time.perf_counter()
-            tickets = []
+            tickets, sub = [], []
             for i, (Xb, r, om) in enumerate(data):
                 if arrivals is not None:
                     wait = arrivals[i] - (time.perf_counter() - t0)
                     if wait > 0:
                         time.sleep(wait)
+                sub.append(time.perf_counter() - t0)
                 tickets.append(srv.submit(Xb, r, om, **opts)[0])
             res = [srv.wait(t, timeout=600.0) for t in tickets]
             wall = time.perf_counter() - t0
         finally:
             srv.stop()
         lat = np.array([x["latency_s"] for x in res])
+        done = np.array(sub) + lat                   # completion times from the first submission
         iters = np.array([x["iters"] for x in res])
         conv = float(np.mean([x["converged"] for x in res]))
-        return wall, lat, iters, conv
+        return wall, lat, iters, conv, np.array(sub), done
 
     log(f"  served: closed loop, {count} requests")
-    wall_c, lat_c, iters_c, conv_c = run(None)
+    wall_c, lat_c, iters_c, conv_c, _, _ = run(None)
     sat = count / wall_c
     log("  served: closed loop with direct launches")
-    wall_d, _, _, _ = run(None, direct=1)          # the same ticks launched one by one
+    wall_d, *_ = run(None, direct=1)          # the same ticks launched one by one
     rate = load * sat
     arr = inputs.poisson_arrivals(count, rate, 7)
     log(f"  served: open loop at {rate:.0f} requests/s")
-    wall_o, lat_o, iters_o, conv_o = run(arr)
+    wall_o, lat_o, iters_o, conv_o, sub_o, done_o = run(arr)
+    # completion and arrival rates over the last three quarters of the
+    # arrivals (the server has filled by then; the drain after the last
+    # arrival is left out, as it would not exist in an endless stream)
+    ta, tb = float(sub_o[count // 4]), float(sub_o[-1])
+    span = tb - ta
+    steady = float(np.count_nonzero((done_o > ta) & (done_o <= tb))) / span if span > 0 else 0.0
+    arriving = (count - 1 - count // 4) / span if span > 0 else 0.0
     log("  served: the plain float32 form, one request at a time")
     out = {
         "requests": count, "dtype": "bf16", "slots": slots,
@@ -574,7 +588,14 @@ def served(ctx, torch, inputs, enmf, count, load, slots, plain):
         "saturated_solves_per_s_direct_launches": round(count / wall_d, 2),
         "load": load, "arrival_rate_per_s": round(rate, 2),
         "solves_per_s": round(count / wall_o, 2),
-        "sustained": bool(count / wall_o >= 0.97 * rate),
+        "solves_per_s_while_arriving": round(steady, 2),
+        "arrivals_per_s_same_window": round(arriving, 2),
+        # no queue growth: the last quarter of the requests waits no longer
+        # than the first, and solves keep pace with arrivals
+        "sustained": bool(np.median(lat_o[-count // 4:]) <= 1.5 * np.median(lat_o[:count // 4])
+                          and steady >= 0.97 * arriving),
+        "p50_latency_first_quarter_s": round(float(np.median(lat_o[:count // 4])), 5),
+        "p50_latency_last_quarter_s": round(float(np.median(lat_o[-count // 4:])), 5),
         "p50_latency_s": round(float(np.percentile(lat_o, 50)), 5),
         "p99_latency_s": round(float(np.percentile(lat_o, 99)), 5),
         "mean_iters": round(float(iters_o.mean()), 2), "converged_frac": round(conv_o, 4),
@@ -637,6 +658,13 @@ def main():
 
     dev = torch.device("cuda:0")
     ctx = enmf.Context(0)
+    if args.streaming_only:
+        # the products' timing does not depend on X's values, so X is filled on the device
+        Xf = torch.rand((100000, 20000), device=dev, dtype=torch.float32)
+        Xb = ctx.convert(Xf, torch.bfloat16)
+        print(json.dumps({"hbm_streaming": streaming(ctx, Xf, Xb, RANK)}), flush=True)
+        ctx.close()
+        return
     log("generating the ratings matrix")
     X_np = inputs.ratings()
     m, n = X_np.shape
@@ -678,8 +706,9 @@ def main():
     }
     if f32["time_to_relerr_s"] and bf["time_to_relerr_s"]:
         out["fp32_over_bf16_time_to_relerr"] = round(f32["time_to_relerr_s"] / bf["time_to_relerr_s"], 3)
-    log("streaming products")
-    out["hbm_streaming"] = streaming(ctx, Xf, Xb, r)
+    if not args.no_streaming:
+        log("streaming products")
+        out["hbm_streaming"] = streaming(ctx, Xf, Xb, r)
     del Xf, Xb
     torch.cuda.empty_cache()
     if not args.headline_only:

@@ -255,56 +255,91 @@ __global__ void k_pad_cols(const float* __restrict__ in, int64_t rows_in, int k,
 }
 
 // Direct residual: part[b] = sum over this block's (i, j) of (X_ij - U_i . V_j)^2,
-// with the dot product and the square accumulated in float64.  Lane = column
-// j, whose row of V (KP values, zero past r) sits in registers; the rows of U
-// (float64, row stride ldu) are uniform across the block, so they arrive
-// through scalar loads as instruction operands.  Rows go RB at a time, their
-// x values loaded before the first dot product, so that enough of the X
-// stream is in flight (one 2- or 4-byte load per lane and row).  KP is a
-// multiple of 4.
-template <int XT, int KP>
-__global__ __launch_bounds__(kThreads) void k_residual(const void* __restrict__ Xv, int64_t m,
-                                                       int64_t n, int64_t ld,
-                                                       const double* __restrict__ Ud, int ldu,
-                                                       const float* __restrict__ V, int r,
-                                                       int64_t rows_per_split,
-                                                       double* __restrict__ part) {
+// with the dot products on the float64 matrix cores (v_mfma_f64_16x16x4f64)
+// and the squares accumulated in float64.  A
+// wave owns 64 columns (four 16 x 16 output tiles) and walks the block's rows
+// 16 at a time: U V^T of a 16-row group is KS = ceil(r / 4) steps of 4 for
+// each tile, with the wave's V operands held in registers for the whole
+// kernel and the group's U operands loaded from the float64 copy of U.  Lane
+// (i, g) supplies U[row i][4s + g] and V[col i][4s + g] and receives the
+// entries (rows g + 4v, column i) of each tile, then subtracts them from X
+// (the next group's x values are in flight meanwhile) and adds the squares
+// in float64.  Rows past r1 and columns past n add nothing.
+template <int XT, int KS>
+__global__ __launch_bounds__(kThreads) void k_residual_mfma(const void* __restrict__ Xv, int64_t m,
+                                                            int64_t n, int64_t ld,
+                                                            const double* __restrict__ Ud, int ldu,
+                                                            const float* __restrict__ V, int r,
+                                                            int64_t rows_per_split,
+                                                            double* __restrict__ part) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
   __shared__ double sh[kThreads / kWave];
   using ET = typename XElem<XT>::T;
   const ET* __restrict__ X = reinterpret_cast<const ET*>(Xv);
-  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const bool valid = j < n;
-  const int64_t jc = valid ? j : 0;   // in-bounds column for the loads of idle lanes
-  double v[KP];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int i = lane % 16, g = lane / 16;
+  const int64_t col0 = (int64_t)blockIdx.x * kThreads + 64 * w;
+  double vb[4][KS];
 #pragma unroll
-  for (int c = 0; c < KP; ++c) v[c] = (valid && c < r) ? (double)V[j * r + c] : 0.0;
-  const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
-  const int64_t r1 = r0 + rows_per_split < m ? r0 + rows_per_split : m;
-  constexpr int RB = KP <= 32 ? 16 : 8;
-  double acc = 0.0;
-  for (int64_t i0 = r0; i0 < r1; i0 += RB) {
-    float xs[RB];
+  for (int t = 0; t < 4; ++t) {
+    const int64_t j = col0 + 16 * t + i;
 #pragma unroll
-    for (int q = 0; q < RB; ++q) {
-      const int64_t i = i0 + q < r1 ? i0 + q : r1 - 1;
-      xs[q] = to_f32<XT>(X[i * ld + jc]);
-    }
-#pragma unroll
-    for (int q = 0; q < RB; ++q) {
-      if (i0 + q < r1) {
-        const double* __restrict__ urow = Ud + (i0 + q) * ldu;
-        // four interleaved partial dot products (columns c mod 4)
-        double d4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int c = 0; c < KP; ++c) d4[c % 4] = fma(urow[c], v[c], d4[c % 4]);
-        const double d = (d4[0] + d4[1]) + (d4[2] + d4[3]);
-        const double e = (double)xs[q] - d;
-        acc = valid ? fma(e, e, acc) : acc;
-      }
+    for (int q = 0; q < KS; ++q) {
+      const int c = 4 * q + g;
+      vb[t][q] = (j < n && c < r) ? (double)V[j * r + c] : 0.0;
     }
   }
-  const double t = block_sum<kThreads>(acc, sh);
-  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t r1 = r0 + rows_per_split < m ? r0 + rows_per_split : m;
+  // x of rows row0 + g + 4v, columns col0 + 16t + i (clamped into the matrix)
+  auto load_x = [&](int64_t row0, float (&xs)[4][4]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int64_t row = row0 + g + 4 * v;
+      row = row < r1 ? row : r1 - 1;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        int64_t j = col0 + 16 * t + i;
+        j = j < n ? j : n - 1;
+        xs[v][t] = to_f32<XT>(X[row * ld + j]);
+      }
+    }
+  };
+  double acc = 0.0;
+  float xa[4][4], xb[4][4];
+  if (r0 < r1) load_x(r0, xa);
+  for (int64_t row0 = r0; row0 < r1; row0 += 16) {
+    const bool more = row0 + 16 < r1;
+    if (more) load_x(row0 + 16, xb);
+    double ua[KS];
+    {
+      int64_t row = row0 + i;
+      row = row < r1 ? row : r1 - 1;
+#pragma unroll
+      for (int q = 0; q < KS; ++q) ua[q] = Ud[row * ldu + 4 * q + g];   // zero past r
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      d4 d = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < KS; ++q) d = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[q], vb[t][q], d, 0, 0, 0);
+      const bool colok = col0 + 16 * t + i < n;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double e = (double)xa[v][t] - d[v];
+        const bool ok = colok && row0 + g + 4 * v < r1;
+        acc = ok ? fma(e, e, acc) : acc;
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) xa[v][t] = xb[v][t];
+    }
+  }
+  const double tot = block_sum<kThreads>(acc, sh);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = tot;
 }
 
 // part[b] = sum of x^2 over the rows of block b, accumulated in float64.  The
@@ -523,16 +558,21 @@ void xtu_dispatch_kp(int kp, dim3 grid, const void* X, int64_t m, int64_t n, int
 }
 
 template <int XT>
-void residual_dispatch(int kp, dim3 grid, const void* X, int64_t m, int64_t n, int64_t ld,
-                       const double* Ud, int ldu, const float* V, int r, int64_t rps, double* part,
-                       hipStream_t s) {
-  switch (kp) {
-    case 8: hipLaunchKernelGGL((k_residual<XT, 8>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); break;
-    case 16: hipLaunchKernelGGL((k_residual<XT, 16>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); break;
-    case 24: hipLaunchKernelGGL((k_residual<XT, 24>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); break;
-    case 32: hipLaunchKernelGGL((k_residual<XT, 32>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); break;
-    case 48: hipLaunchKernelGGL((k_residual<XT, 48>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); break;
-    default: hipLaunchKernelGGL((k_residual<XT, 64>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); break;
+void residual_dispatch(dim3 grid, const void* X, int64_t m, int64_t n, int64_t ld, const double* Ud,
+                       int ldu, const float* V, int r, int64_t rps, double* part, hipStream_t s) {
+  switch ((r + 3) / 4) {
+    case 1: hipLaunchKernelGGL((k_residual_mfma<XT, 1>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
+    case 2: hipLaunchKernelGGL((k_residual_mfma<XT, 2>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
+    case 3: hipLaunchKernelGGL((k_residual_mfma<XT, 3>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
+    case 4: hipLaunchKernelGGL((k_residual_mfma<XT, 4>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
+    case 5: hipLaunchKernelGGL((k_residual_mfma<XT, 5>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
+    case 6: hipLaunchKernelGGL((k_residual_mfma<XT, 6>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
+    case 7: hipLaunchKernelGGL((k_residual_mfma<XT, 7>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
+    case 8: hipLaunchKernelGGL((k_residual_mfma<XT, 8>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
+    case 9: case 10: case 11: case 12:
+      hipLaunchKernelGGL((k_residual_mfma<XT, 12>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
+    default:
+      hipLaunchKernelGGL((k_residual_mfma<XT, 16>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
   }
 }
 
@@ -629,9 +669,9 @@ hipError_t launch_xtu(const void* X, int xt, int64_t m, int64_t n, int64_t ld, c
 // Residual partials: Ud is U padded to kp float64 columns (m rows).
 hipError_t launch_residual(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const double* Ud,
                            const float* V, int r, double* part, int* nparts, hipStream_t s) {
-  // Ud has pad_width(r) columns; the kernel reads the first kp (>= r) of them
+  // Ud has pad_width(r) columns, zero past r; the kernel reads the first
+  // 4 KS of them (4 KS <= pad_width(r) for every r <= 64)
   const int ldu = pad_width(r);
-  const int kp = r <= 8 ? 8 : r <= 16 ? 16 : r <= 24 ? 24 : r <= 32 ? 32 : r <= 48 ? 48 : 64;
   const int64_t cb = (n + kThreads - 1) / kThreads;
   int64_t sp = (kTargetBlocks + cb - 1) / cb;
   if (sp > m) sp = m;
@@ -640,9 +680,9 @@ hipError_t launch_residual(const void* X, int xt, int64_t m, int64_t n, int64_t 
   sp = (m + rps - 1) / rps;
   dim3 grid((unsigned)cb, (unsigned)sp);
   switch (xt) {
-    case ENMF_F32: residual_dispatch<0>(kp, grid, X, m, n, ld, Ud, ldu, V, r, rps, part, s); break;
-    case ENMF_BF16: residual_dispatch<1>(kp, grid, X, m, n, ld, Ud, ldu, V, r, rps, part, s); break;
-    default: residual_dispatch<2>(kp, grid, X, m, n, ld, Ud, ldu, V, r, rps, part, s); break;
+    case ENMF_F32: residual_dispatch<0>(grid, X, m, n, ld, Ud, ldu, V, r, rps, part, s); break;
+    case ENMF_BF16: residual_dispatch<1>(grid, X, m, n, ld, Ud, ldu, V, r, rps, part, s); break;
+    default: residual_dispatch<2>(grid, X, m, n, ld, Ud, ldu, V, r, rps, part, s); break;
   }
   *nparts = (int)(cb * sp);
   return hipGetLastError();

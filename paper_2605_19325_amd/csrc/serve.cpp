@@ -403,8 +403,8 @@ enmf_status enmf_serve_start(enmf_ctx* c, const enmf_serve_opts* opts, enmf_serv
   auto* s = new enmf_server();
   s->device = ctx_device(c);
   s->max_slots = o.max_slots > 0 ? o.max_slots : 512;
-  s->budget = (int64_t)(o.tick_budget > 0 ? o.tick_budget : 64) << 20;
-  s->ticks = o.ticks_per_launch > 0 ? o.ticks_per_launch : 4;
+  s->budget = (int64_t)(o.tick_budget > 0 ? o.tick_budget : 256) << 20;
+  s->ticks = o.ticks_per_launch > 0 ? o.ticks_per_launch : 1;
   s->direct = o.direct_launch == 1;
   const int64_t arena_bytes = o.hbm_budget_bytes > 0 ? (int64_t)o.hbm_budget_bytes : (1LL << 30);
   auto bail = [&](enmf_status st, const char* msg) {
