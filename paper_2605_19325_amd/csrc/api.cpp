@@ -18,7 +18,7 @@ namespace {
 enum Slot {
   S_BP, S_AP, S_SPLIT, S_P, S_Q, S_GPART, S_G, S_H, S_RUPART, S_XPART, S_U2, S_GPU, S_GPV, S_STAT, S_UD, S_RES,
   S_Y, S_QM64, S_QM32, S_Z, S_QN64, S_QN32, S_TMP64, S_T, S_C, S_COLP, S_COLS, S_SIG, S_TU, S_TV,
-  S_W64, S_YA, S_ZA, S_R, S_WSQ, S_MPART,
+  S_W64, S_ADMM, S_R, S_WSQ, S_MPART,
   S_EX, S_ERU, S_ERV, S_EE, S_ERSS, S_ECU, S_ECV, S_EG, S_EGI, S_EST, S_ESTAT, S_SPX, S_SPG,
   S_GW, S_GOUT, S_XT, N_SLOTS
 };
@@ -667,8 +667,7 @@ enmf_status enmf_rotate(enmf_ctx* c, int64_t m, int64_t n, int32_t r, float* U, 
   const int64_t N = m + n;
   const int kp = pad_width(r);
   WS(W, double, S_W64, N * kp * 8);
-  WS(Ya, double, S_YA, N * kp * 8);
-  WS(Za, double, S_ZA, N * kp * 8);
+  WS(Sa, double, S_ADMM, N * kp * 8);
   WS(R, double, S_R, kp * kp * 8);
   WS(wsq, double, S_WSQ, 512 * 8);
   const int nbm = admm_rows_blocks(N, kp);
@@ -701,7 +700,7 @@ enmf_status enmf_rotate(enmf_ctx* c, int64_t m, int64_t n, int32_t r, float* U, 
   bool stop_copied = false;
   int launched = 0;
   for (int t = 0; t < d.max_iter; ++t) {
-    CK(launch_admm_rows(W, N, r, kp, R, Ya, Za, c->st, t, mpart, s));
+    CK(launch_admm_rows(W, N, r, kp, R, Sa, c->st, t, mpart, s));
     CK(launch_gram_finalize(mpart, nbm, r, r, kp, Mf, s));
     CK(launch_polar(Mf, r, kp, R, c->st, s, d.tol, d.check_every, t));
     launched = t + 1;

@@ -132,23 +132,37 @@ __device__ __forceinline__ double eigvec(const JacobiT<MAXW>& sm, int a, int j) 
   return sm.E[a * JacobiT<MAXW>::LD + sm.perm[j]];
 }
 
-// Polar factor of the KP x KP matrix M held in X (zero padded), in place:
-// the Newton-Schulz iteration X <- 1.5 X - 0.5 X (X^T X) from X0 = 1.5 M /
-// ||M||_F (singular values in (0, 1.5], inside the convergence interval
-// (0, sqrt 3)), in float64 until ||X_{k+1} - X_k||_F^2 <= 1e-26 or 100 steps.
-// T is scratch.  Returns false (X untouched) when ||M||_F is 0 or not finite.
+// Polar factor of the KP x KP matrix M held in X (zero padded past kc rows
+// and columns; kc a multiple of 4), in place: the Newton-Schulz iteration
+// with the scaling of Chen and Chow (2014).  From X0 = M / ||M||_F, whose
+// singular values lie in (0, 1], step k is
+//   X <- (a/2) X (3 I - a^2 X^T X),  a = sqrt(3 / (1 + l + l^2)),
+// where [l, 1] is the interval the singular values are taken to lie in; the
+// step maps it onto [l', 1] with l' = (a l / 2)(3 - a^2 l^2), so l grows
+// about 2.6-fold per step while it is small and a falls to 1 (the plain
+// Newton-Schulz step) as l reaches 1.  l0 = 1e-3; singular values below l0
+// still converge, only later.  Every singular value is mapped into (0, 1]
+// and tends to 1 while the singular vectors stay, so the limit is the polar
+// factor of M.  The iteration stops after the step whose change
+// ||X_{k+1} - X_k||_F^2 is at most 1e-20 (the convergence is quadratic, so
+// the remaining error is of order 1e-20) or after 100 steps.  T is scratch.
+// Returns false (X untouched) when ||M||_F is 0 or not finite.
 //
 // Both products run on v_mfma_f64_16x16x4f64, 16 x 16 output tiles dealt
-// round robin to the NT / 64 waves of the workgroup (red: NT / 64 doubles).  Lane (i, g) = (l % 16, l / 16) supplies
-// A[i][g] and B[g][i] of each 16 x 4 by 4 x 16 step and receives
-// D[g + 4 v][i] in accumulator element v.
+// round robin to the NT / 64 waves of the workgroup (red: NT / 64 doubles),
+// with the contraction over the kc leading rows or columns only.  T = X^T X is
+// symmetric: only its upper tiles are formed, each written to both halves.
+// Lane (i, g) = (l % 16, l / 16) supplies A[i][g] and B[g][i] of each
+// 16 x 4 by 4 x 16 step and receives D[g + 4 v][i] in accumulator element v.
 template <int KP, int NT = kBlk>
-__device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double* red) {
+__device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double* red, int kc = KP) {
   typedef double d4 __attribute__((ext_vector_type(4)));
   constexpr int NTL = KP / 16;                  // tiles per side
   constexpr int NTILE = NTL * NTL;
+  constexpr int NSYM = NTL * (NTL + 1) / 2;     // upper tiles of T
   constexpr int NW = NT / kWave;                // waves
   constexpr int PERW = (NTILE + NW - 1) / NW;   // tiles per wave
+  constexpr int PERWS = (NSYM + NW - 1) / NW;   // upper tiles per wave
   static_assert(KP % 16 == 0, "polar_ns_block needs KP a multiple of 16");
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int i = lane % 16, g = lane / 16;
@@ -156,48 +170,55 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
   for (int e = threadIdx.x; e < KP * KP; e += NT) nrm = fma(X[e / KP][e % KP], X[e / KP][e % KP], nrm);
   nrm = sqrt(block_sum<NT>(nrm, red));
   if (!(nrm > 0.0) || !isfinite(nrm)) return false;
-  const double sc = 1.5 / nrm;
+  const double sc = 1.0 / nrm;
   for (int e = threadIdx.x; e < KP * KP; e += NT) X[e / KP][e % KP] *= sc;
   __syncthreads();
+  double l = 1e-3;
   for (int it = 0; it < 100; ++it) {
-    // T = X^T X: tile (ti, tj) = sum over k of X[k][16 ti + i] X[k][16 tj + j].
+    const double a = sqrt(3.0 / (1.0 + l + l * l));
+    const double c1 = 1.5 * a, c3 = 0.5 * a * a * a;
+    l = 0.5 * a * l * (3.0 - a * a * l * l);
+    // T = X^T X: upper tile (ti, tj) = sum over k of X[k][16 ti + i] X[k][16 tj + j].
     // A wave's tiles advance together through k (independent MFMA chains).
     {
-      d4 acc[PERW];
+      d4 acc[PERWS];
+      int tti[PERWS], ttj[PERWS];
 #pragma unroll
-      for (int u = 0; u < PERW; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-      for (int k0 = 0; k0 < KP; k0 += 4) {
+      for (int u = 0; u < PERWS; ++u) {
+        acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+        int ti = 0, rem = w + NW * u;
+        while (ti < NTL && rem >= NTL - ti) { rem -= NTL - ti; ++ti; }
+        tti[u] = ti;
+        ttj[u] = ti + rem;
+      }
+      for (int k0 = 0; k0 < kc; k0 += 4) {
 #pragma unroll
-        for (int u = 0; u < PERW; ++u) {
-          const int tile = w + NW * u;
-          if (tile < NTILE) {
-            const int ti = tile / NTL, tj = tile % NTL;
-            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[k0 + g][16 * ti + i], X[k0 + g][16 * tj + i],
+        for (int u = 0; u < PERWS; ++u) {
+          if (w + NW * u < NSYM)
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[k0 + g][16 * tti[u] + i], X[k0 + g][16 * ttj[u] + i],
                                                           acc[u], 0, 0, 0);
-          }
         }
       }
 #pragma unroll
-      for (int u = 0; u < PERW; ++u) {
-        const int tile = w + NW * u;
-        if (tile < NTILE) {
-          const int ti = tile / NTL, tj = tile % NTL;
+      for (int u = 0; u < PERWS; ++u) {
+        if (w + NW * u < NSYM) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) T[16 * ti + g + 4 * v][16 * tj + i] = acc[u][v];
+          for (int v = 0; v < 4; ++v) {
+            T[16 * tti[u] + g + 4 * v][16 * ttj[u] + i] = acc[u][v];
+            if (tti[u] != ttj[u]) T[16 * ttj[u] + i][16 * tti[u] + g + 4 * v] = acc[u][v];
+          }
         }
       }
     }
     __syncthreads();
-    // X_new = 1.5 X - 0.5 X T
+    // X_new = c1 X - c3 X T
     double xn[PERW][4];
     double d2 = 0.0;
     {
       d4 acc[PERW];
 #pragma unroll
       for (int u = 0; u < PERW; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-      for (int k0 = 0; k0 < KP; k0 += 4) {
+      for (int k0 = 0; k0 < kc; k0 += 4) {
 #pragma unroll
         for (int u = 0; u < PERW; ++u) {
           const int tile = w + NW * u;
@@ -216,7 +237,7 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const double x = X[16 * ti + g + 4 * v][16 * tj + i];
-            xn[u][v] = 1.5 * x - 0.5 * acc[u][v];
+            xn[u][v] = c1 * x - c3 * acc[u][v];
             d2 = fma(xn[u][v] - x, xn[u][v] - x, d2);
           }
         }
@@ -233,7 +254,7 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
       }
     }
     __syncthreads();
-    if (d2 <= 1e-26) break;
+    if (d2 <= 1e-20) break;
   }
   return true;
 }

@@ -186,13 +186,14 @@ hipError_t launch_pack_w(const float* U, int64_t m, const float* V, int64_t n, i
 hipError_t launch_w_sumsq(const double* W, int64_t count, double* part, int* nparts, hipStream_t s);
 hipError_t launch_rho_init(const double* part, int nparts, int64_t N, int r, double rho0, DevState* st,
                            hipStream_t s);
-// Blocks (and partial Grams) of launch_admm_rows: one per row block, at most 2048.
+// Blocks (and partial Grams) of launch_admm_rows: one per row block, at most 1024.
 int admm_rows_blocks(int64_t N, int kp);
-// One ADMM step on W (N x kp float64) with the current R: updates Y and Z in
-// place and writes admm_rows_blocks(N, kp) partials (r x r float64 each) of
-// W^T (Z + Y / rho) to part.
-hipError_t launch_admm_rows(const double* W, int64_t N, int r, int kp, const double* R, double* Y,
-                            double* Z, DevState* st, int step, double* part, hipStream_t s);
+// One ADMM step on W (N x kp float64) with the current R: updates the state
+// S = Y + rho Z (N x kp float64; not read at step 0) in place and writes
+// admm_rows_blocks(N, kp) partials (r x r float64 each) of W^T (Z + Y / rho)
+// to part.
+hipError_t launch_admm_rows(const double* W, int64_t N, int r, int kp, const double* R, double* S,
+                            DevState* st, int step, double* part, hipStream_t s);
 // R <- polar factor of Mf (r x r, leading dimension kp); R is kp x kp.
 // tol > 0: at steps with (step + 1) % check_every == 0, a change ||R_new - R_old||_F <= tol
 // sets st->rot_stop and st->rot_steps = step + 1.

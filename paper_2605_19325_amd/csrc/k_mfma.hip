@@ -409,7 +409,8 @@ __global__ __launch_bounds__(kT) void k_xv_f32s(const float* __restrict__ X, int
 // j0 + 8 mm + t.  B operand = At[part][16 nt + i][8g .. 8g+7] (transposed
 // chunk in LDS, rows padded to 40).
 // ---------------------------------------------------------------------------
-constexpr int kAtLd = 40;
+constexpr int kAtLd = 40;   // LDS row pitch of the factor chunk (bank spread)
+constexpr int kAtG = 32;    // its row pitch in global memory (unpadded)
 
 template <int KP>
 __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restrict__ X, int64_t m,
@@ -429,7 +430,8 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
     (void)check_decide<kT>(dec, 0, dst, true, dsh, &dflag);
   }
   constexpr int NT = KP / 16;
-  constexpr int CH = 3 * KP * kAtLd;
+  constexpr int CH = 3 * KP * kAtLd;    // LDS elements of one chunk
+  constexpr int CHG = 3 * KP * kAtG;    // global elements of one chunk
   __shared__ __align__(16) unsigned short As[2][CH];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int i = lane % 16, g = lane / 16;
@@ -458,14 +460,16 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
     }
   };
   // factor chunk prefetched into registers, stored to LDS after the MFMAs
-  constexpr int NAQ = (CH / 8 + kT - 1) / kT;
+  // the chunk's 32-element rows are four 16-byte groups in global memory and
+  // the first four of five in LDS
+  constexpr int NAQ = (CHG / 8 + kT - 1) / kT;
   uint4 aq_next[NAQ];
   auto fetch_a = [&](int64_t ch) {
-    const uint4* src = reinterpret_cast<const uint4*>(At + ch * CH);
+    const uint4* src = reinterpret_cast<const uint4*>(At + ch * CHG);
 #pragma unroll
     for (int u = 0; u < NAQ; ++u) {
       const int e = threadIdx.x + u * kT;
-      aq_next[u] = e < CH / 8 ? src[e] : make_uint4(0u, 0u, 0u, 0u);
+      aq_next[u] = e < CHG / 8 ? src[e] : make_uint4(0u, 0u, 0u, 0u);
     }
   };
   auto store_a = [&](int buf) {
@@ -473,7 +477,7 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
 #pragma unroll
     for (int u = 0; u < NAQ; ++u) {
       const int e = threadIdx.x + u * kT;
-      if (e < CH / 8) dst[e] = aq_next[u];
+      if (e < CHG / 8) dst[(e / 4) * (kAtLd / 8) + e % 4] = aq_next[u];
     }
   };
   if (c0 < c1) {
@@ -573,7 +577,8 @@ __global__ __launch_bounds__(kT) void k_xtu_f32s(const float* __restrict__ X, in
     (void)check_decide<kT>(dec, 0, dst, true, dsh, &dflag);
   }
   constexpr int NT = KP / 16;
-  constexpr int CH = 3 * KP * kAtLd;
+  constexpr int CH = 3 * KP * kAtLd;    // LDS elements of one chunk
+  constexpr int CHG = 3 * KP * kAtG;    // global elements of one chunk
   __shared__ __align__(16) unsigned short As[2][CH];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int i = lane % 16, g = lane / 16;
@@ -601,14 +606,16 @@ __global__ __launch_bounds__(kT) void k_xtu_f32s(const float* __restrict__ X, in
         dst[e] = load16<float>(X, m, n, ld, ch * 32 + 8 * g + e, j0 + 4 * i, vec != 0);
     }
   };
-  constexpr int NAQ = (CH / 8 + kT - 1) / kT;
+  // the chunk's 32-element rows are four 16-byte groups in global memory and
+  // the first four of five in LDS
+  constexpr int NAQ = (CHG / 8 + kT - 1) / kT;
   uint4 aq_next[NAQ];
   auto fetch_a = [&](int64_t ch) {
-    const uint4* src = reinterpret_cast<const uint4*>(At + ch * CH);
+    const uint4* src = reinterpret_cast<const uint4*>(At + ch * CHG);
 #pragma unroll
     for (int u = 0; u < NAQ; ++u) {
       const int e = threadIdx.x + u * kT;
-      aq_next[u] = e < CH / 8 ? src[e] : make_uint4(0u, 0u, 0u, 0u);
+      aq_next[u] = e < CHG / 8 ? src[e] : make_uint4(0u, 0u, 0u, 0u);
     }
   };
   auto store_a = [&](int buf) {
@@ -616,7 +623,7 @@ __global__ __launch_bounds__(kT) void k_xtu_f32s(const float* __restrict__ X, in
 #pragma unroll
     for (int u = 0; u < NAQ; ++u) {
       const int e = threadIdx.x + u * kT;
-      if (e < CH / 8) dst[e] = aq_next[u];
+      if (e < CHG / 8) dst[(e / 4) * (kAtLd / 8) + e % 4] = aq_next[u];
     }
   };
   if (c0 < c1) {
@@ -852,7 +859,7 @@ Plan xtu_plan(int xt, int64_t m, int64_t n, int k) {
 
 void mfma_pack_layout(int xt, int xtu, int k, int* kp, int* c, int* ldt) {
   *kp = mfma_kp(k);
-  if (xtu) { *c = 32; *ldt = kAtLd; }
+  if (xtu) { *c = 32; *ldt = kAtG; }
   else if (xt == ENMF_F32) { *c = 32; *ldt = kBt32Ld; }
   else { *c = 64; *ldt = kBtLd; }
 }
@@ -870,7 +877,7 @@ void mfma_xv_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t*
 void mfma_xtu_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes) {
   const int KP = mfma_kp(k);
   const Plan p = xtu_plan(xt, m, n, k);
-  *pack_bytes = (size_t)p.nch * 3 * KP * kAtLd * 2;
+  *pack_bytes = (size_t)p.nch * 3 * KP * kAtG * 2;
   *part_bytes = (size_t)p.splits * n * k * 4;
 }
 
@@ -958,7 +965,7 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
     const int64_t tiles = (n + 255) / 256;
     if (do_pack)
       hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 4 * KP)), dim3(256), 0, s, A, m, k, KP, 32,
-                         kAtLd, nch, (unsigned short*)pack);
+                         kAtG, nch, (unsigned short*)pack);
     const Plan pl = xtu_plan(xt, m, n, k);
     const int cps = (int)pl.cps;
     eff = pl.splits;
@@ -980,7 +987,7 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
     const int64_t nch = (m + 31) / 32;
     if (do_pack)
       hipLaunchKernelGGL(k_pack_split_t, dim3(grid_for(nch * 4 * KP)), dim3(256), 0, s, A, m, k, KP, 32,
-                         kAtLd, nch, (unsigned short*)pack);
+                         kAtG, nch, (unsigned short*)pack);
     const Plan pl = xtu_plan(xt, m, n, k);
     const int64_t cps = pl.cps;
     eff = pl.splits;

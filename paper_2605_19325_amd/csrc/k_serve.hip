@@ -684,7 +684,7 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
         sm.a.X[a][c] = (a < r && c < r) ? st.scratch[e] : 0.0;
       }
       __syncthreads();
-      const bool ok = polar_ns_block<SKP>(sm.a.X, sm.a.T, sm.a.red);
+      const bool ok = polar_ns_block<SKP>(sm.a.X, sm.a.T, sm.a.red, (r + 3) / 4 * 4);
       double d2 = 0.0;
       if (ok) {
         for (int e = threadIdx.x; e < SKP * SKP; e += SNT) {

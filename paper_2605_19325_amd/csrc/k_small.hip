@@ -95,34 +95,41 @@ __global__ __launch_bounds__(kT) void k_tsgram(const TA* __restrict__ A, int64_t
     }
 }
 
-// out (kp x kp, zero padded) = sum_b part[b] (ka x kb).  One wave per group
-// of 4 consecutive entries of the ka x kb partials: lane l adds partials l,
-// l + 64, ... in order (4 partials, 16 loads, in flight at a time), then the
-// wave sums each entry (wave_sum_last), so the result does not depend on
+// out (kp x kp, zero padded) = sum_b part[b] (ka x kb).  One workgroup per
+// group of 4 consecutive entries of the ka x kb partials; wave w of the 4
+// takes the partials of the w-th quarter of [0, nparts), lane l of it adds
+// partials l, l + 64, ... of that quarter in order (4 partials, 16 loads, in
+// flight at a time), the wave sums each entry (wave_sum_last) and thread 0
+// adds the four quarters in order, so the result does not depend on
 // scheduling.  The padding entries are written as zeros by the grid.
-__global__ void k_gram_finalize(const double* __restrict__ part, int nparts, int ka, int kb, int kp,
-                                double* __restrict__ out) {
+__global__ __launch_bounds__(kT) void k_gram_finalize(const double* __restrict__ part, int nparts,
+                                                      int ka, int kb, int kp,
+                                                      double* __restrict__ out) {
+  __shared__ double sq[kT / kWave][4];
   const int64_t ne = (int64_t)ka * kb;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < kp * kp; e += gridDim.x * blockDim.x) {
     const int a = e / kp, c = e % kp;
     if (a >= ka || c >= kb) out[e] = 0.0;
   }
-  const int lane = threadIdx.x % kWave;
-  const int64_t e0 = 4 * ((int64_t)(blockIdx.x * blockDim.x + threadIdx.x) / kWave);
-  if (e0 >= ne) return;   // whole waves
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  constexpr int NW = kT / kWave;
+  const int64_t e0 = 4 * (int64_t)blockIdx.x;
+  if (e0 >= ne) return;   // whole blocks
+  const int per = (nparts + NW - 1) / NW;
+  const int b1 = (w + 1) * per < nparts ? (w + 1) * per : nparts;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b0 = lane; b0 < nparts; b0 += 4 * kWave) {
+  for (int b0 = w * per + lane; b0 < b1; b0 += 4 * kWave) {
     double v[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int b = b0 + u * kWave;
-      const double* src = part + (int64_t)(b < nparts ? b : 0) * ne;
+      const double* src = part + (int64_t)(b < b1 ? b : 0) * ne;
 #pragma unroll
       for (int c = 0; c < 4; ++c) v[u][c] = src[e0 + c < ne ? e0 + c : ne - 1];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      if (b0 + u * kWave < nparts) {
+      if (b0 + u * kWave < b1) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) s[c] += v[u][c];
       }
@@ -132,11 +139,17 @@ __global__ void k_gram_finalize(const double* __restrict__ part, int nparts, int
   for (int c = 0; c < 4; ++c) s[c] = wave_sum_last(s[c]);
   if (lane == kWave - 1) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if (e0 + c < ne) {
-        const int a = (int)((e0 + c) / kb), cc = (int)((e0 + c) % kb);
-        out[a * kp + cc] = s[c];
-      }
+    for (int c = 0; c < 4; ++c) sq[w][c] = s[c];
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int c = threadIdx.x;
+    double t = sq[0][c];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) t += sq[q][c];
+    if (e0 + c < ne) {
+      const int a = (int)((e0 + c) / kb), cc = (int)((e0 + c) % kb);
+      out[a * kp + cc] = t;
     }
   }
 }
@@ -315,8 +328,10 @@ __global__ void k_rho_init(const double* __restrict__ part, int nparts, int64_t 
 // W R (KP/8 threads per row, 8 columns each, R staged in LDS), then over the
 // block's rows as one flat, coalesced range
 //   Y <- Y + rho (Z - W R)  (Y = 0 at step 0),  b = W R - Y / rho,
-//   Z <- prox of h at b (eq. 7),  B = Z + Y / rho,
-// and B is only kept in LDS: the block adds the block's share of W^T B to its
+//   Z <- prox of h at b (eq. 7),  B = Z + Y / rho.
+// The multiplier and the split variable are carried as one array
+// S = Y + rho Z (Y = S - rho W R at the next step), so a step reads W and S
+// and writes S; B is only kept in LDS: the block adds the block's share of W^T B to its
 // r x r float64 partial (on the float64 matrix cores, 16 x 16 tiles over
 // 4-row steps; a thread per entry at KP = 8).  Blocks loop over row blocks
 // (grid of admm_rows_blocks); part[b] receives block b's partial.
@@ -328,7 +343,7 @@ template <int KP> struct AdmmGeom {
 template <int KP>
 __global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, int64_t N, int r,
                                                   const double* __restrict__ R,
-                                                  double* __restrict__ Y, double* __restrict__ Z,
+                                                  double* __restrict__ S,
                                                   const DevState* st, int step,
                                                   double* __restrict__ part) {
   using AG = AdmmGeom<KP>;
@@ -381,16 +396,13 @@ __global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, 
     }
     __syncthreads();
     const int cnt = (int)nrow * KP;
-    double* Yb = Y + row0 * KP;
-    double* Zb = Z + row0 * KP;
+    double* Sb = S + row0 * KP;
     for (int e = threadIdx.x; e < cnt; e += kT) {
       const double w = Bs[e];
-      double y = 0.0;
-      if (step > 0) y = Yb[e] + rho * (Zb[e] - w);
+      const double y = step > 0 ? Sb[e] - rho * w : 0.0;
       const double b = w - y * irho;
       const double z = b > 0.0 ? b : (b >= -irho ? 0.0 : b + irho);
-      Yb[e] = y;
-      Zb[e] = z;
+      Sb[e] = y + rho * z;
       Bs[e] = z + y * irho;
     }
     __syncthreads();
@@ -480,7 +492,7 @@ __global__ __launch_bounds__(polar_threads<KP>()) void k_polar_ns(const double* 
     X[a][c] = (a < r && c < r) ? Mf[a * kp + c] : 0.0;
   }
   __syncthreads();
-  if (!polar_ns_block<KP, NT>(X, T, red)) {
+  if (!polar_ns_block<KP, NT>(X, T, red, (r + 3) / 4 * 4)) {
     if (threadIdx.x == 0) record(0.0);
     return;
   }
@@ -541,9 +553,8 @@ hipError_t launch_tsgram(const void* A, int a_is_f64, int64_t lda, const void* B
 
 hipError_t launch_gram_finalize(const double* part, int nparts, int ka, int kb, int kp, double* out,
                                 hipStream_t s) {
-  const int waves = (ka * kb + 3) / 4;
-  hipLaunchKernelGGL(k_gram_finalize, dim3((waves + 3) / 4), dim3(256), 0, s, part, nparts, ka, kb,
-                     kp, out);
+  const int groups = (ka * kb + 3) / 4;
+  hipLaunchKernelGGL(k_gram_finalize, dim3(groups), dim3(kT), 0, s, part, nparts, ka, kb, kp, out);
   return hipGetLastError();
 }
 
@@ -611,19 +622,19 @@ hipError_t launch_rho_init(const double* part, int nparts, int64_t N, int r, dou
 int admm_rows_blocks(int64_t N, int kp) {
   const int rb = kT / (kp / 8);
   const int64_t b = (N + rb - 1) / rb;
-  return (int)(b < 2048 ? b : 2048);
+  return (int)(b < 1024 ? b : 1024);
 }
 
-hipError_t launch_admm_rows(const double* W, int64_t N, int r, int kp, const double* R, double* Y,
-                            double* Z, DevState* st, int step, double* part, hipStream_t s) {
+hipError_t launch_admm_rows(const double* W, int64_t N, int r, int kp, const double* R, double* S,
+                            DevState* st, int step, double* part, hipStream_t s) {
   dim3 g((unsigned)admm_rows_blocks(N, kp)), b(kT);
   switch (kp) {
-    case 8: hipLaunchKernelGGL((k_admm_rows<8>), g, b, 0, s, W, N, r, R, Y, Z, st, step, part); break;
-    case 16: hipLaunchKernelGGL((k_admm_rows<16>), g, b, 0, s, W, N, r, R, Y, Z, st, step, part); break;
-    case 32: hipLaunchKernelGGL((k_admm_rows<32>), g, b, 0, s, W, N, r, R, Y, Z, st, step, part); break;
-    case 48: hipLaunchKernelGGL((k_admm_rows<48>), g, b, 0, s, W, N, r, R, Y, Z, st, step, part); break;
-    case 64: hipLaunchKernelGGL((k_admm_rows<64>), g, b, 0, s, W, N, r, R, Y, Z, st, step, part); break;
-    default: hipLaunchKernelGGL((k_admm_rows<80>), g, b, 0, s, W, N, r, R, Y, Z, st, step, part); break;
+    case 8: hipLaunchKernelGGL((k_admm_rows<8>), g, b, 0, s, W, N, r, R, S, st, step, part); break;
+    case 16: hipLaunchKernelGGL((k_admm_rows<16>), g, b, 0, s, W, N, r, R, S, st, step, part); break;
+    case 32: hipLaunchKernelGGL((k_admm_rows<32>), g, b, 0, s, W, N, r, R, S, st, step, part); break;
+    case 48: hipLaunchKernelGGL((k_admm_rows<48>), g, b, 0, s, W, N, r, R, S, st, step, part); break;
+    case 64: hipLaunchKernelGGL((k_admm_rows<64>), g, b, 0, s, W, N, r, R, S, st, step, part); break;
+    default: hipLaunchKernelGGL((k_admm_rows<80>), g, b, 0, s, W, N, r, R, S, st, step, part); break;
   }
   return hipGetLastError();
 }

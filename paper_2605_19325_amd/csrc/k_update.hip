@@ -209,10 +209,14 @@ __global__ __launch_bounds__(Team<KP>::NT, (LOOP && KP >= 32) ? 2 : 1) void k_ro
     // Columns in blocks of 8, one block per team lane: the owner runs the
     // block's steps on its own t (no exchange inside the block), then the
     // team takes the 8 changes at once and applies them in column order,
-    // the same fma sequence as one column at a time.  The steps are
+    // the same fma sequence as one column at a time.  Inside the block the
+    // owner adds a change only to the columns still to come (the next step
+    // waits on those) and adds it to the earlier columns after the block;
+    // each t[e] still receives the changes in column order.  The steps are
     // branch-free so that the Gram rows can be read ahead: a padded column
     // (j >= r, zero Gram row and diagonal) or one with G_jj = 0 changes
-    // nothing.
+    // nothing.  The other lanes' update is unconditional too (the owner adds
+    // zeros), so that its Gram rows are read while the changes are exchanged.
     double ig[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) ig[e] = sinv[c0 + e];
@@ -232,18 +236,25 @@ __global__ __launch_bounds__(Team<KP>::NT, (LOOP && KP >= 32) ? 2 : 1) void k_ro
           a[ej] = on ? nv : a[ej];
           dl[ej] = d;
 #pragma unroll
-          for (int e = 0; e < 8; ++e) t[e] = fma(d, gj[e], t[e]);
+          for (int e = ej + 1; e < 8; ++e) t[e] = fma(d, gj[e], t[e]);
+        }
+#pragma unroll
+        for (int ej = 0; ej < 8; ++ej) {
+          const double* gj = sG + (c0 + ej) * KP + c0;
+#pragma unroll
+          for (int e = 0; e <= ej; ++e) t[e] = fma(dl[ej], gj[e], t[e]);
         }
       }
 #pragma unroll
-      for (int ej = 0; ej < 8; ++ej) dl[ej] = __shfl(dl[ej], base + o);
-      if (q != o) {
+      for (int ej = 0; ej < 8; ++ej) {
+        const double x = __shfl(dl[ej], base + o);
+        dl[ej] = q == o ? 0.0 : x;
+      }
 #pragma unroll
-        for (int ej = 0; ej < 8; ++ej) {
-          const double* gj = sG + (8 * o + ej) * KP + c0;
+      for (int ej = 0; ej < 8; ++ej) {
+        const double* gj = sG + (8 * o + ej) * KP + c0;
 #pragma unroll
-          for (int e = 0; e < 8; ++e) t[e] = fma(dl[ej], gj[e], t[e]);
-        }
+        for (int e = 0; e < 8; ++e) t[e] = fma(dl[ej], gj[e], t[e]);
       }
     }
     have_t = true;
