@@ -20,6 +20,7 @@
 #include "block_linalg.h"
 #include "dev_common.h"
 #include "enmf_internal.h"
+#include "mfma_common.h"
 #include "row_team.h"
 #include "serve_internal.h"
 
@@ -60,8 +61,14 @@ struct AdmmSmem {
   double T[SKP][SKP + 1];
   double red[SNT / kWave];
 };
+constexpr int kSvBLd = 72;   // LDS row pitch of a 64-row factor chunk of X B (matrix cores)
+constexpr int kSvALd = 40;   // LDS row pitch of a 32-row factor chunk of X^T A (matrix cores)
+struct MfmaSmem {
+  __align__(16) unsigned short f[2 * 3 * SKB * kSvBLd];
+};
 union ServeSmem {
   ProdSmem p;
+  MfmaSmem mf;
   GramSmem g;
   RowSmem w;
   EigSmem e;
@@ -187,22 +194,270 @@ __device__ void bx_xta(const XE<XT>* __restrict__ X, int64_t m, int64_t n, int64
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// bfloat16 X on the matrix cores (v_mfma_f32_16x16x32_bf16).  The float32
+// factor is split into three bfloat16 terms (hi + mid + lo, within 2^-24 of
+// it; store_split_run8) as it is staged into LDS, so each 32-step of the
+// contraction is three MFMAs per 16 x 16 output tile with float32
+// accumulation, and X is exact in bfloat16.  The next factor chunk travels
+// through registers and reaches the other LDS buffer after the current
+// chunk's MFMAs.  Element v of lane (i, g) = (l % 16, l / 16) of an output
+// tile is D[4g + v][i].
+// ---------------------------------------------------------------------------
+
+// Rows r0 .. r0 + 7 of column c of the rows x k float32 factor F (ld ldf),
+// zero past its rows or columns.
+__device__ __forceinline__ void fetch_run8(const float* __restrict__ F, int64_t rows, int ldf, int k,
+                                           int64_t r0, int c, float (&v)[8]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = (r0 + e < rows && c < k) ? F[(r0 + e) * ldf + c] : 0.f;
+}
+
+// out (m x k, ld ldo) = X (m x n, ld) B (n x k, ld ldb), k <= KP.  Row groups
+// of 256 (4 waves x 4 tiles of 16 rows); chunk = 64 columns of X (two
+// 32-steps).  Lane (i, g) of row tile rt supplies X[row0 + 16 rt + i][64 ch +
+// 32 s + 8g .. +7]; the B operand is Bt[term][16 nt + i][32 s + 8g .. +7] of
+// the LDS chunk (factor column major, rows padded to 72).
+template <int KP>
+__device__ void sv_xb_bf16(const unsigned short* __restrict__ X, int64_t m, int64_t n, int64_t ld,
+                           const float* __restrict__ B, int ldb, int k, float* __restrict__ out,
+                           int ldo, MfmaSmem& sm) {
+  constexpr int NT = KP / 16, RT = 4, CH = 3 * KP * kSvBLd;
+  constexpr int NTASK = KP * 8;   // runs of 8 rows of one column per chunk
+  constexpr int NR = (NTASK + SNT - 1) / SNT;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int i = lane % 16, g = lane / 16;
+  const bool vec = (reinterpret_cast<uintptr_t>(X) & 15) == 0 && ld % 8 == 0;
+  const int64_t nch = (n + 63) / 64;
+  float bv[NR][8];
+  auto fetch_b = [&](int64_t ch) {
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      const int task = threadIdx.x + SNT * u;
+      if (task < NTASK) fetch_run8(B, n, ldb, k, 64 * ch + 8 * (task / KP), task % KP, bv[u]);
+    }
+  };
+  auto store_b = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      const int task = threadIdx.x + SNT * u;
+      if (task < NTASK)
+        store_split_run8(bv[u], sm.f + buf * CH + (task % KP) * kSvBLd + 8 * (task / KP), KP * kSvBLd);
+    }
+  };
+  uint4 xa[RT][2], xn[RT][2];
+  auto load_x = [&](int64_t row0, int64_t ch, uint4 (&dst)[RT][2]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+        dst[rt][s2] = load16<unsigned short>(X, m, n, ld, row0 + 16 * rt + i, 64 * ch + 32 * s2 + 8 * g, vec);
+  };
+  for (int64_t rg = 0; rg < m; rg += 4 * 64) {
+    const int64_t row0 = rg + 64 * w;
+    const bool active = row0 < m;   // wave-uniform
+    f32x4 acc[RT][NT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = zero4();
+    fetch_b(0);
+    store_b(0);
+    if (active) load_x(row0, 0, xa);
+    int buf = 0;
+    for (int64_t ch = 0; ch < nch; ++ch) {
+      __syncthreads();
+      const bool more = ch + 1 < nch;
+      if (more) {
+        fetch_b(ch + 1);
+        if (active) load_x(row0, ch + 1, xn);
+      }
+      if (active) {
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+            for (int hl = 0; hl < 3; ++hl) {
+              const bf16x8 b = as_bf16x8(*reinterpret_cast<const uint4*>(
+                  &sm.f[buf * CH + (hl * KP + 16 * nt + i) * kSvBLd + 32 * s2 + 8 * g]));
+#pragma unroll
+              for (int rt = 0; rt < RT; ++rt)
+                acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(xa[rt][s2]), b, acc[rt][nt], 0, 0, 0);
+            }
+          }
+        }
+      }
+      if (more) {
+        store_b(buf ^ 1);
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) { xa[rt][0] = xn[rt][0]; xa[rt][1] = xn[rt][1]; }
+      }
+      buf ^= 1;
+    }
+    if (active) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int col = 16 * nt + i;
+          if (col < k) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int64_t row = row0 + 16 * rt + 4 * g + v;
+              if (row < m) out[row * ldo + col] = acc[rt][nt][v];
+            }
+          }
+        }
+    }
+    __syncthreads();   // the next row group restages chunk 0
+  }
+}
+
+// out (n x k, ld ldo) = X^T (X m x n, ld) A (m x k, ld lda), k <= KP.  Column
+// groups of 512 (4 waves x 128 columns); chunk = 32 rows of X (one 32-step).
+// Lane (i, g) loads the 8 x 8 block X[32 ch + 8g + e][j0 + 8i .. 8i + 7] (e =
+// 0..7) and transposes it in registers: operand t holds X[32 ch + 8g + 0..7]
+// [j0 + 8i + t], so tile t covers the columns j0 + 8 mm + t (mm = 0..15).  The
+// B operand is At[term][16 nt + i][8g .. 8g + 7] of the LDS chunk (rows
+// padded to 40).  Element v of lane (i, g) in tile t is column j0 + 8 (4g +
+// v) + t, factor column 16 nt + i.
+template <int KP>
+__device__ void sv_xta_bf16(const unsigned short* __restrict__ X, int64_t m, int64_t n, int64_t ld,
+                            const float* __restrict__ A, int lda, int k, float* __restrict__ out,
+                            int ldo, MfmaSmem& sm) {
+  constexpr int NT = KP / 16, CH = 3 * KP * kSvALd;
+  constexpr int NTASK = KP * 4;   // runs of 8 rows of one column per chunk
+  constexpr int NR = (NTASK + SNT - 1) / SNT;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int i = lane % 16, g = lane / 16;
+  const bool vec = (reinterpret_cast<uintptr_t>(X) & 15) == 0 && ld % 8 == 0;
+  const int64_t nch = (m + 31) / 32;
+  float av[NR][8];
+  auto fetch_a = [&](int64_t ch) {
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      const int task = threadIdx.x + SNT * u;
+      if (task < NTASK) fetch_run8(A, m, lda, k, 32 * ch + 8 * (task / KP), task % KP, av[u]);
+    }
+  };
+  auto store_a = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      const int task = threadIdx.x + SNT * u;
+      if (task < NTASK)
+        store_split_run8(av[u], sm.f + buf * CH + (task % KP) * kSvALd + 8 * (task / KP), KP * kSvALd);
+    }
+  };
+  uint4 xa[8], xn[8];
+  auto load_x = [&](int64_t j0, int64_t ch, uint4 (&dst)[8]) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dst[e] = load16<unsigned short>(X, m, n, ld, 32 * ch + 8 * g + e, j0 + 8 * i, vec);
+  };
+  for (int64_t cg = 0; cg < n; cg += 4 * 128) {
+    const int64_t j0 = cg + 128 * w;
+    const bool active = j0 < n;   // wave-uniform
+    f32x4 acc[8][NT];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[t][nt] = zero4();
+    fetch_a(0);
+    store_a(0);
+    if (active) load_x(j0, 0, xa);
+    int buf = 0;
+    for (int64_t ch = 0; ch < nch; ++ch) {
+      __syncthreads();
+      const bool more = ch + 1 < nch;
+      if (more) {
+        fetch_a(ch + 1);
+        if (active) load_x(j0, ch + 1, xn);
+      }
+      if (active) {
+        // op[t] dword d = (X[2d][t], X[2d + 1][t]) of the lane's 8 x 8 block
+        uint4 op[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          unsigned d[4];
+#pragma unroll
+          for (int dd = 0; dd < 4; ++dd) {
+            const uint4& lo = xa[2 * dd];
+            const uint4& hi = xa[2 * dd + 1];
+            const unsigned a = (t / 2 == 0) ? lo.x : (t / 2 == 1) ? lo.y : (t / 2 == 2) ? lo.z : lo.w;
+            const unsigned b = (t / 2 == 0) ? hi.x : (t / 2 == 1) ? hi.y : (t / 2 == 2) ? hi.z : hi.w;
+            d[dd] = (t % 2 == 0) ? __builtin_amdgcn_perm(b, a, 0x05040100u)
+                                 : __builtin_amdgcn_perm(b, a, 0x07060302u);
+          }
+          op[t] = make_uint4(d[0], d[1], d[2], d[3]);
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+          for (int hl = 0; hl < 3; ++hl) {
+            const bf16x8 b = as_bf16x8(*reinterpret_cast<const uint4*>(
+                &sm.f[buf * CH + (hl * KP + 16 * nt + i) * kSvALd + 8 * g]));
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+              acc[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(op[t]), b, acc[t][nt], 0, 0, 0);
+          }
+        }
+      }
+      if (more) {
+        store_a(buf ^ 1);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xa[e] = xn[e];
+      }
+      buf ^= 1;
+    }
+    if (active) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int col = 16 * nt + i;
+          if (col < k) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int64_t j = j0 + 8 * (4 * g + v) + t;
+              if (j < n) out[j * ldo + col] = acc[t][nt][v];
+            }
+          }
+        }
+    }
+    __syncthreads();   // the next column group restages chunk 0
+  }
+}
+
+// Products of the serving steps: bfloat16 X on the matrix cores, float32 and
+// float16 X on the vector ALU.
 template <int XT>
 __device__ void xb(const XE<XT>* X, int64_t m, int64_t n, int64_t ld, const float* B, int ldb, int k,
-                   float* out, int ldo, ProdSmem& sm) {
-  if (k <= 8) bx_xb<XT, 8>(X, m, n, ld, B, ldb, k, out, ldo, sm);
-  else if (k <= 16) bx_xb<XT, 16>(X, m, n, ld, B, ldb, k, out, ldo, sm);
-  else if (k <= 32) bx_xb<XT, 32>(X, m, n, ld, B, ldb, k, out, ldo, sm);
-  else bx_xb<XT, 48>(X, m, n, ld, B, ldb, k, out, ldo, sm);
+                   float* out, int ldo, ServeSmem& sm) {
+  if constexpr (XT == 1) {
+    if (k <= 16) sv_xb_bf16<16>(X, m, n, ld, B, ldb, k, out, ldo, sm.mf);
+    else if (k <= 32) sv_xb_bf16<32>(X, m, n, ld, B, ldb, k, out, ldo, sm.mf);
+    else sv_xb_bf16<48>(X, m, n, ld, B, ldb, k, out, ldo, sm.mf);
+  } else {
+    if (k <= 8) bx_xb<XT, 8>(X, m, n, ld, B, ldb, k, out, ldo, sm.p);
+    else if (k <= 16) bx_xb<XT, 16>(X, m, n, ld, B, ldb, k, out, ldo, sm.p);
+    else if (k <= 32) bx_xb<XT, 32>(X, m, n, ld, B, ldb, k, out, ldo, sm.p);
+    else bx_xb<XT, 48>(X, m, n, ld, B, ldb, k, out, ldo, sm.p);
+  }
 }
 
 template <int XT>
 __device__ void xta(const XE<XT>* X, int64_t m, int64_t n, int64_t ld, const float* A, int lda, int k,
-                    float* out, int ldo, ProdSmem& sm) {
-  if (k <= 8) bx_xta<XT, 8>(X, m, n, ld, A, lda, k, out, ldo, sm);
-  else if (k <= 16) bx_xta<XT, 16>(X, m, n, ld, A, lda, k, out, ldo, sm);
-  else if (k <= 32) bx_xta<XT, 32>(X, m, n, ld, A, lda, k, out, ldo, sm);
-  else bx_xta<XT, 48>(X, m, n, ld, A, lda, k, out, ldo, sm);
+                    float* out, int ldo, ServeSmem& sm) {
+  if constexpr (XT == 1) {
+    if (k <= 16) sv_xta_bf16<16>(X, m, n, ld, A, lda, k, out, ldo, sm.mf);
+    else if (k <= 32) sv_xta_bf16<32>(X, m, n, ld, A, lda, k, out, ldo, sm.mf);
+    else sv_xta_bf16<48>(X, m, n, ld, A, lda, k, out, ldo, sm.mf);
+  } else {
+    if (k <= 8) bx_xta<XT, 8>(X, m, n, ld, A, lda, k, out, ldo, sm.p);
+    else if (k <= 16) bx_xta<XT, 16>(X, m, n, ld, A, lda, k, out, ldo, sm.p);
+    else if (k <= 32) bx_xta<XT, 32>(X, m, n, ld, A, lda, k, out, ldo, sm.p);
+    else bx_xta<XT, 48>(X, m, n, ld, A, lda, k, out, ldo, sm.p);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -552,19 +807,19 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
   if (stage == kStSvd) {
     const int last_orth = 2 * q.power_iters;   // subs 0..last_orth end with an orthonormalisation
     if (sub == 0) {
-      xb<XT>(X, m, n, ld, q.omega, kk, kk, q.Y32, kk, sm.p);
+      xb<XT>(X, m, n, ld, q.omega, kk, kk, q.Y32, kk, sm);
       orth(q.Y32, m, kk, q.Qm64, q.Y32, st.scratch, sm);
     } else if (sub <= last_orth) {
       if (sub & 1) {
-        xta<XT>(X, m, n, ld, q.Y32, kk, kk, q.Z32, kk, sm.p);
+        xta<XT>(X, m, n, ld, q.Y32, kk, kk, q.Z32, kk, sm);
         orth(q.Z32, n, kk, q.Qn64, q.Z32, st.scratch, sm);
       } else {
-        xb<XT>(X, m, n, ld, q.Z32, kk, kk, q.Y32, kk, sm.p);
+        xb<XT>(X, m, n, ld, q.Z32, kk, kk, q.Y32, kk, sm);
         orth(q.Y32, m, kk, q.Qm64, q.Y32, st.scratch, sm);
       }
     } else if (sub == last_orth + 1) {
       // B = Q^T X through Z = X^T Q; SVD of B from the eigenpairs of Z^T Z
-      xta<XT>(X, m, n, ld, q.Y32, kk, kk, q.Z32, kk, sm.p);
+      xta<XT>(X, m, n, ld, q.Y32, kk, kk, q.Z32, kk, sm);
       bx_cross<float, float, SKB>(q.Z32, kk, kk, q.Z32, kk, kk, n, st.scratch, sm.g);
       eig_of(st.scratch, kk, sm.e);
       // column sums of Q (float64, fixed order per column)
@@ -738,7 +993,7 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
     mnV = block_min<SNT>(mnV, red);
     negs = bsum(negs, red);
     bx_cross<float, float, SKP>(q.U, r, r, q.U, r, r, m, st.H, sm.g);
-    xta<XT>(X, m, n, ld, q.U, r, r, q.Z32, r, sm.p);
+    xta<XT>(X, m, n, ld, q.U, r, r, q.Z32, r, sm);
     load_gram32(st.H, sm.w);
     row_pass(q.V, n, r, q.Z32, sm.w, false, false, kPhaseHals, 0.0, 0, false);
     if (t0) {
@@ -761,7 +1016,7 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
     const int k = ctl.k;
     // G = V^T V, P = X V, KKT partials of U^k (pre-update)
     bx_cross<float, float, SKP>(q.V, r, r, q.V, r, r, n, st.G, sm.g);
-    xb<XT>(X, m, n, ld, q.V, r, r, q.Y32, r, sm.p);
+    xb<XT>(X, m, n, ld, q.V, r, r, q.Y32, r, sm);
     load_gram32(st.G, sm.w);
     row_pass(q.U, m, r, q.Y32, sm.w, false, true, kPhaseHals, 0.0, 0, false);
     // check of iteration k (the KKT appendix), same expressions as k_finalize
@@ -816,7 +1071,7 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
     // U half: update in place, then H = U^T U and Q = X^T U
     row_pass(q.U, m, r, q.Y32, sm.w, true, true, phase, ctl.step[0], q.sweeps, q.mode == 2);
     bx_cross<float, float, SKP>(q.U, r, r, q.U, r, r, m, st.H, sm.g);
-    xta<XT>(X, m, n, ld, q.U, r, r, q.Z32, r, sm.p);
+    xta<XT>(X, m, n, ld, q.U, r, r, q.Z32, r, sm);
     // V half with the new U; KKT partials of V^(k+1)
     load_gram32(st.H, sm.w);
     row_pass(q.V, n, r, q.Z32, sm.w, true, false, phase, ctl.step[1], q.sweeps, q.mode == 2);

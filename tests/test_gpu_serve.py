@@ -200,6 +200,46 @@ def test_served_large_requests_match_oracle(lib, server):
         assert host(U).min() >= 0 and host(V).min() >= 0
 
 
+@pytest.mark.parametrize("shape", [(300, 517, 20), (1000, 333, 32), (77, 1100, 7), (640, 640, 16)],
+                         ids=["300x517r20", "1000x333r32", "77x1100r7", "640x640r16"])
+def test_served_bf16_matrix_cores_match_float32_form(lib, server, shape):
+    """The bfloat16 requests run their products on the matrix cores (factor
+    split into three bfloat16 terms), the float32 ones on the vector ALU.  On
+    the same values (X rounded to bfloat16, then widened exactly to float32),
+    at widths 16, 32 and 48 of the range finder and ragged row and column
+    counts, the two give
+    * the same SVD factors within 1e-5 and relative error within 1e-6;
+    * after a 20-step rotation and 30 iterations, the same push count, the
+      same relative error within 1e-6, and factors within max(1e-4, 10 times
+      the move of the oracle's own factors when X changes by 2^-24 relative):
+      these low-rank instances leave a residual of about 0.2% of X, so their
+      factors move far more than their objective."""
+    m, n, r = shape
+    say(f"served bf16 (matrix cores) vs float32 (vector ALU) on the same values, {m}x{n} r={r}")
+    X, _, _ = inputs.lowrank_plus_noise(m, n, r, 4100 + r)
+    om_h = inputs.omega(n, min(r + 10, 48), 4200 + r)
+    om = to_dev(om_h)
+    Xb = lib.convert(to_dev(X), torch.bfloat16)
+    Xf = Xb.float().contiguous()
+    run_opts = dict(max_iter=30, rot_max_iter=20, rot_tol=0.0)
+    Xo = host(Xf)
+    Uo1, Vo1, _ = O.enmf(Xo, r, om_h, **run_opts)
+    sign = np.where(np.random.default_rng(4300 + r).random(Xo.shape) < 0.5, -1.0, 1.0)
+    Uo2, Vo2, _ = O.enmf(Xo * (1.0 + 2.0 ** -24 * sign), r, om_h, **run_opts)
+    move = max(rel(Uo2, Uo1), rel(Vo2, Vo1))
+    for opts, bar in ((dict(max_iter=0, rot_max_iter=0), 1e-5), (run_opts, max(1e-4, 10.0 * move))):
+        tb, Ub, Vb = server.submit(Xb, r, om, oversample=om.shape[1] - r, **opts)
+        tf, Uf, Vf = server.submit(Xf, r, om, oversample=om.shape[1] - r, **opts)
+        rb, rf = server.wait(tb), server.wait(tf)
+        du, dv = rel(host(Ub), host(Uf)), rel(host(Vb), host(Vf))
+        say(f"  {opts}: |dU| {du:.2e} |dV| {dv:.2e} (bar {bar:.1e}; oracle move {move:.1e}) "
+            f"relerr {rb['relerr']:.8e} / {rf['relerr']:.8e}")
+        assert rb["status"] == 0 and rf["status"] == 0
+        assert du <= bar and dv <= bar
+        assert rb["ext_iters_done"] == rf["ext_iters_done"] and rb["iters"] == rf["iters"]
+        assert abs(rb["relerr"] - rf["relerr"]) <= 1e-6
+
+
 def test_serve_rejects_bad_requests(lib):
     say("serve: bad rank, workspace beyond the budget, unknown ticket")
     srv = enmf.Server(lib, hbm_budget_bytes=1 << 20, max_slots=4)
