@@ -55,11 +55,20 @@ struct EigSmem {
   JacobiT<SKB> j;
   double aux[2 * SKB];
 };
+constexpr int kAdmmRB = 128;  // rows per block of the served ADMM step
 struct AdmmSmem {
   double R[SKP * SKP];
-  double X[SKP][SKP + 1];
-  double T[SKP][SKP + 1];
   double red[SNT / kWave];
+  union {
+    struct {                     // the polar step
+      double X[SKP][SKP + 1];
+      double T[SKP][SKP + 1];
+    };
+    struct {                     // the row blocks of the ADMM step
+      float Wb[kAdmmRB * SKP];   // a row block of W = [U*; V*] (row pitch SKP)
+      double Sb[kAdmmRB * SKP];  // its rows of the ADMM state (row pitch r)
+    };
+  };
 };
 constexpr int kSvBLd = 72;   // LDS row pitch of a 64-row factor chunk of X B (matrix cores)
 constexpr int kSvALd = 40;   // LDS row pitch of a 32-row factor chunk of X^T A (matrix cores)
@@ -792,6 +801,106 @@ __device__ void load_gram32(const double* G, RowSmem& sm) {
 }
 
 // ---------------------------------------------------------------------------
+// One ADMM step of Algorithm 1 (eq. 7) over the N = m + n rows of W = [U*;
+// V*] (the float32 factors), KR = r rounded up to 8.  Blocks of kAdmmRB rows
+// pass through LDS: the next block's W and state rows are loaded into
+// registers (flat, coalesced) while the current one is processed, and the
+// new state goes straight back to global memory.  Thread
+// (rl, c) = (t / r, t % r) keeps column c of R in registers and takes rows
+// rl, rl + nl, ... (nl = 256 / r row lanes) of the block: w = (W R)[row][c]
+// (float64, four interleaved partial sums), then the multiplier, prox and B
+// updates with the state carried as S = Y + rho Z (Y = S - rho w; N x r
+// float64, row pitch r), and B[row][c] W[row][:] added to its share of column
+// c of M = W^T B.  The row lanes' shares are then added into X (the polar
+// step's input, which shares LDS with the row blocks) in row-lane order.  R
+// must be in sm.R; ends with a barrier.
+template <int KR>
+__device__ void admm_rows(const ServeReq& q, const ServeScalars& ctl, AdmmSmem& sm, int64_t m,
+                          int64_t N, int r, int step) {
+  constexpr int PW = kAdmmRB * KR / SNT;   // W elements per thread and block
+  constexpr int PS = kAdmmRB * SKP / SNT;  // state elements per thread and block (at most)
+  const double rho = ctl.rho, irho = 1.0 / rho;
+  const int nl = SNT / r;
+  const int rl = threadIdx.x / r, c = threadIdx.x % r;
+  const bool act = rl < nl;
+  __syncthreads();   // R staged
+  double rc[KR], macc[KR];
+#pragma unroll
+  for (int a = 0; a < KR; ++a) {
+    rc[a] = (act && a < r) ? sm.R[a * SKP + c] : 0.0;
+    macc[a] = 0.0;
+  }
+  float wn[PW];
+  double sn[PS];
+  auto fetch = [&](int64_t row0) {
+    const int nrow = (int)imin(N - row0, kAdmmRB);
+#pragma unroll
+    for (int u = 0; u < PW; ++u) {
+      const int e = threadIdx.x + SNT * u;
+      const int rr = e / KR, a = e % KR;
+      const int64_t row = row0 + rr;
+      float v = 0.f;
+      if (rr < nrow && a < r) v = row < m ? q.U[row * r + a] : q.V[(row - m) * r + a];
+      wn[u] = v;
+    }
+    if (step > 0) {
+      const double* src = q.S + row0 * r;
+#pragma unroll
+      for (int u = 0; u < PS; ++u) {
+        const int e = threadIdx.x + SNT * u;
+        sn[u] = e < nrow * r ? src[e] : 0.0;
+      }
+    }
+  };
+  fetch(0);
+  for (int64_t row0 = 0; row0 < N; row0 += kAdmmRB) {
+    const int nrow = (int)imin(N - row0, kAdmmRB);
+    __syncthreads();   // the previous block is consumed
+#pragma unroll
+    for (int u = 0; u < PW; ++u) {
+      const int e = threadIdx.x + SNT * u;
+      sm.Wb[(e / KR) * SKP + e % KR] = wn[u];
+    }
+    if (step > 0) {
+#pragma unroll
+      for (int u = 0; u < PS; ++u) sm.Sb[threadIdx.x + SNT * u] = sn[u];
+    }
+    __syncthreads();
+    // the next block's loads are issued here, after the barrier (a barrier
+    // waits for every load in flight), and meet the compute below
+    if (row0 + kAdmmRB < N) fetch(row0 + kAdmmRB);
+    if (act) {
+      for (int rr = rl; rr < nrow; rr += nl) {
+        double wv[KR];
+#pragma unroll
+        for (int a = 0; a < KR; ++a) wv[a] = (double)sm.Wb[rr * SKP + a];
+        double w4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < KR; ++a) w4[a % 4] = fma(wv[a], rc[a], w4[a % 4]);
+        const double w = (w4[0] + w4[1]) + (w4[2] + w4[3]);
+        const double y = step > 0 ? sm.Sb[rr * r + c] - rho * w : 0.0;
+        const double b = w - y * irho;
+        const double z = b > 0.0 ? b : (b >= -irho ? 0.0 : b + irho);
+        q.S[(row0 + rr) * r + c] = y + rho * z;   // consecutive across the wave
+        const double bb = z + y * irho;
+#pragma unroll
+        for (int a = 0; a < KR; ++a) macc[a] = fma(wv[a], bb, macc[a]);
+      }
+    }
+  }
+  __syncthreads();   // the last block is consumed before X takes its LDS
+  for (int e = threadIdx.x; e < SKP * (SKP + 1); e += SNT) sm.X[e / (SKP + 1)][e % (SKP + 1)] = 0.0;
+  for (int l = 0; l < nl; ++l) {
+    __syncthreads();
+    if (rl == l) {
+#pragma unroll
+      for (int a = 0; a < KR; ++a)
+        if (a < r) sm.X[a][c] += macc[a];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // The state machine.  Each call runs one step and returns its cost in
 // multiply-adds; thread 0 updates ctl, and every path ends at a barrier.
 // ---------------------------------------------------------------------------
@@ -882,21 +991,16 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
     const int64_t N = m + n;
     double* Rs = sm.a.R;
     if (sub == 0) {
-      // W = [U*; V*] (float64, width 32), rho = rho0 sqrt(N r) / ||W||_F, R = I
-      double s = 0.0;
-      for (int64_t e = threadIdx.x; e < N * SKP; e += SNT) {
-        const int64_t i = e / SKP;
-        const int c = (int)(e % SKP);
-        double v = 0.0;
-        if (c < r) v = i < m ? (double)q.U[i * r + c] : (double)q.V[(i - m) * r + c];
-        q.W[e] = v;
-        s = fma(v, v, s);
-      }
-      s = bsum(s, red);
+      // rho = rho0 sqrt(N r) / ||W||_F for W = [U*; V*] (the float32 factors,
+      // read in float64 where needed), R = I
+      double s2 = 0.0;
+      for (int64_t e = threadIdx.x; e < m * r; e += SNT) s2 = fma((double)q.U[e], (double)q.U[e], s2);
+      for (int64_t e = threadIdx.x; e < n * r; e += SNT) s2 = fma((double)q.V[e], (double)q.V[e], s2);
+      s2 = bsum(s2, red);
       for (int e = threadIdx.x; e < SKP * SKP; e += SNT)
         st.R[e] = (e / SKP == e % SKP && e / SKP < r) ? 1.0 : 0.0;
       if (t0) {
-        ctl.rho = s > 0.0 ? q.rho0 * sqrt((double)N * r) / sqrt(s) : 1.0;
+        ctl.rho = s2 > 0.0 ? q.rho0 * sqrt((double)N * r) / sqrt(s2) : 1.0;
         ctl.dR = INFINITY;
         ctl.rot_steps = 0;
         if (q.rot_max_iter > 0) {
@@ -907,37 +1011,16 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
         }
       }
       __syncthreads();
-      return N * SKP;
+      return N * (int64_t)r;
     }
     if (sub == 1) {
-      // one ADMM step (Algorithm 1): rows, then M = W^T B, then R = polar(M)
+      // one ADMM step (Algorithm 1): rows and M = W^T B (admm_rows), then R = polar(M)
       const int step = ctl.rot_steps;
       for (int e = threadIdx.x; e < SKP * SKP; e += SNT) Rs[e] = st.R[e];
-      __syncthreads();
-      const double rho = ctl.rho, irho = 1.0 / rho;
-      for (int64_t i = threadIdx.x; i < N; i += SNT) {
-        double w[SKP];
-#pragma unroll
-        for (int c = 0; c < SKP; ++c) w[c] = q.W[i * SKP + c];
-        for (int c = 0; c < r; ++c) {
-          double wr = 0.0;
-#pragma unroll
-          for (int a = 0; a < SKP; ++a) wr = fma(w[a], Rs[a * SKP + c], wr);
-          double y = 0.0;
-          if (step > 0) y = q.Ya[i * SKP + c] + rho * (q.Za[i * SKP + c] - wr);
-          const double b = wr - y * irho;
-          const double z = b > 0.0 ? b : (b >= -irho ? 0.0 : b + irho);
-          q.Ya[i * SKP + c] = y;
-          q.Za[i * SKP + c] = z;
-          q.Ba[i * SKP + c] = z + y * irho;
-        }
-      }
-      __syncthreads();
-      bx_cross<double, double, SKP>(q.W, SKP, r, q.Ba, SKP, r, N, st.scratch, sm.g);
-      for (int e = threadIdx.x; e < SKP * SKP; e += SNT) {
-        const int a = e / SKP, c = e % SKP;
-        sm.a.X[a][c] = (a < r && c < r) ? st.scratch[e] : 0.0;
-      }
+      if (r <= 8) admm_rows<8>(q, ctl, sm.a, m, N, r, step);
+      else if (r <= 16) admm_rows<16>(q, ctl, sm.a, m, N, r, step);
+      else if (r <= 24) admm_rows<24>(q, ctl, sm.a, m, N, r, step);
+      else admm_rows<32>(q, ctl, sm.a, m, N, r, step);
       __syncthreads();
       const bool ok = polar_ns_block<SKP>(sm.a.X, sm.a.T, sm.a.red, (r + 3) / 4 * 4);
       double d2 = 0.0;
@@ -963,8 +1046,9 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
     // U = W_U R, V = W_V R with the last R
     for (int e = threadIdx.x; e < SKP * SKP; e += SNT) Rs[e] = st.R[e];
     __syncthreads();
-    bx_apply<double, float, SKP>(q.W, SKP, r, m, Rs, r, q.U, r);
-    bx_apply<double, float, SKP>(q.W + m * SKP, SKP, r, n, Rs, r, q.V, r);
+    // in place: each row is read whole before it is written
+    bx_apply<float, float, SKP>(q.U, r, r, m, Rs, r, q.U, r);
+    bx_apply<float, float, SKP>(q.V, r, r, n, Rs, r, q.V, r);
     if (t0) {
       ctl.stage = kStSetup;
       ctl.sub = 0;

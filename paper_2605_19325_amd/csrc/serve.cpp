@@ -32,21 +32,17 @@ int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 
 // Workspace of one served solve, laid out in its arena block.
 struct Layout {
-  int64_t y32, qm64, z32, qn64, w, ya, za, ba, total;
+  int64_t y32, qm64, z32, qn64, s, total;
 };
 
-Layout layout_for(int64_t m, int64_t n, int kk) {
+Layout layout_for(int64_t m, int64_t n, int kk, int r) {
   Layout L;
   int64_t o = 0;
   L.y32 = o;  o += align256(m * kk * 4);
   L.qm64 = o; o += align256(m * kk * 8);
   L.z32 = o;  o += align256(n * kk * 4);
   L.qn64 = o; o += align256(n * kk * 8);
-  const int64_t wb = align256((m + n) * kServeKP * 8);
-  L.w = o;  o += wb;
-  L.ya = o; o += wb;
-  L.za = o; o += wb;
-  L.ba = o; o += wb;
+  L.s = o;    o += align256((m + n) * r * 8);
   L.total = o;
   return L;
 }
@@ -169,7 +165,7 @@ void fill_report(const ServeStatus& h, enmf_iter_report* rep) {
 // Host image of a newly admitted slot: the request and a fresh state.
 void build_slot(enmf_server* s, const Pending& p, int64_t off, ServeSlot* out) {
   const enmf_request& rq = p.req;
-  const Layout L = layout_for(rq.X.m, rq.X.n, rq.r + rq.svd.oversample);
+  const Layout L = layout_for(rq.X.m, rq.X.n, rq.r + rq.svd.oversample, rq.r);
   std::memset(out, 0, offsetof(ServeSlot, s) + sizeof(ServeScalars));
   ServeReq& q = out->q;
   char* base = s->arena_base + off;
@@ -201,10 +197,7 @@ void build_slot(enmf_server* s, const Pending& p, int64_t off, ServeSlot* out) {
   q.Qm64 = reinterpret_cast<double*>(base + L.qm64);
   q.Z32 = reinterpret_cast<float*>(base + L.z32);
   q.Qn64 = reinterpret_cast<double*>(base + L.qn64);
-  q.W = reinterpret_cast<double*>(base + L.w);
-  q.Ya = reinterpret_cast<double*>(base + L.ya);
-  q.Za = reinterpret_cast<double*>(base + L.za);
-  q.Ba = reinterpret_cast<double*>(base + L.ba);
+  q.S = reinterpret_cast<double*>(base + L.s);
   out->s.c.stage = kStSvd;
 }
 
@@ -465,7 +458,7 @@ enmf_status enmf_serve_submit(enmf_server* s, const enmf_request* q, uint64_t* t
   if (s->failed) return fail_srv(s, ENMF_EDEVICE, s->err);
   const enmf_status v = check_request(s, q);
   if (v != ENMF_OK) return v;
-  const int64_t bytes = layout_for(q->X.m, q->X.n, q->r + q->svd.oversample).total;
+  const int64_t bytes = layout_for(q->X.m, q->X.n, q->r + q->svd.oversample, q->r).total;
   if (bytes > s->arena->size())
     return fail_srv(s, ENMF_ENOMEM, "request workspace exceeds the serving memory budget");
   Pending p;

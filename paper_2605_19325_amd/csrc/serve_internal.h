@@ -32,10 +32,7 @@ struct ServeReq {
   double* Qm64;                // m x kk
   float* Z32;                  // n x kk (range finder; later Q = X^T U)
   double* Qn64;                // n x kk
-  double* W;                   // (m + n) x kServeKP, rotation state
-  double* Ya;
-  double* Za;
-  double* Ba;
+  double* S;                   // (m + n) x r, rotation state (Y + rho Z)
 };
 
 // Scalar progress of one solve (copied to LDS for the length of a tick).
