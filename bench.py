@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-load", type=float, default=0.6,
                     help="open-loop arrival rate as a fraction of the closed-loop solves/s")
-    ap.add_argument("--serve-slots", type=int, default=512)
+    ap.add_argument("--serve-slots", type=int, default=1536)
     ap.add_argument("--serve-plain", type=int, default=256,
                     help="requests of the stream also solved one by one by the float32 form")
     return ap.parse_args()

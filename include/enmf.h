@@ -362,7 +362,7 @@ typedef struct enmf_server enmf_server;
 
 typedef struct {
   uint64_t hbm_budget_bytes;  /* device arena for admitted solves' workspace; 0 = 1 GiB */
-  int32_t max_slots;          /* solves in flight, one workgroup each; 0 = 512 */
+  int32_t max_slots;          /* solves in flight, one workgroup each; 0 = 1024 */
   int32_t tick_budget;        /* work per solve per tick, in units of 2^20 multiply-adds; 0 = 256 */
   int32_t ticks_per_launch;   /* ticks per replay of the captured tick graph; 0 = 1 */
   int32_t direct_launch;      /* 0: each group of ticks is one replay of a captured HIP graph;

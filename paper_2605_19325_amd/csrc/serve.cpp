@@ -111,7 +111,7 @@ struct Result {
 struct enmf_server {
   int device = 0;
   hipStream_t stream = nullptr;
-  int max_slots = 512;
+  int max_slots = 1024;
   int64_t budget = 64LL << 20;
   char* arena_base = nullptr;
   Arena* arena = nullptr;
@@ -395,7 +395,7 @@ enmf_status enmf_serve_start(enmf_ctx* c, const enmf_serve_opts* opts, enmf_serv
     return ENMF_EINVAL;
   auto* s = new enmf_server();
   s->device = ctx_device(c);
-  s->max_slots = o.max_slots > 0 ? o.max_slots : 512;
+  s->max_slots = o.max_slots > 0 ? o.max_slots : 1024;
   s->budget = (int64_t)(o.tick_budget > 0 ? o.tick_budget : 256) << 20;
   s->ticks = o.ticks_per_launch > 0 ? o.ticks_per_launch : 1;
   s->direct = o.direct_launch == 1;
