@@ -338,14 +338,14 @@ enmf_status enmf_enmc_iterate(enmf_ctx* ctx, const enmf_matrix* X, const enmf_ma
  * exterior phase and HALS with the KKT check, final objective) for every
  * submitted request.  Requests are admitted into slots as slots and device
  * memory free up, and all admitted solves advance together: each tick gives
- * every running solve one workgroup and a bounded amount of work
- * (tick_budget).  A worker thread replays a captured HIP graph of
+ * every running solve one workgroup for a bounded time (tick_time_us; the
+ * solve yields after the first step that ends past it).  A worker thread replays a captured HIP graph of
  * ticks_per_launch ticks (kernel nodes only) again and again without waiting
  * for it: the slot status is copied to pinned host memory after each replay
  * and read one replay later, and newly admitted solves are uploaded between
  * replays, so requests that arrive while others run join at the next replay
  * and the device never idles on the host.  A solve's arithmetic does not
- * depend on what else is in flight, on the tick budget or on the launch form.
+ * depend on what else is in flight, on the tick time or on the launch form.
  * Served solves take dense X and support r <= 32 and r + oversample <= 48, a fixed number of
  * PBCD sweeps (pbcd_eps = 0) and modes 0 to 3.  The request's trace is
  * not recorded.
@@ -363,7 +363,8 @@ typedef struct enmf_server enmf_server;
 typedef struct {
   uint64_t hbm_budget_bytes;  /* device arena for admitted solves' workspace; 0 = 1 GiB */
   int32_t max_slots;          /* solves in flight, one workgroup each; 0 = 1024 */
-  int32_t tick_budget;        /* work per solve per tick, in units of 2^20 multiply-adds; 0 = 256 */
+  int32_t tick_time_us;       /* time a solve runs per tick before it yields, in microseconds of the
+                                 device's constant 100 MHz clock (at least one step); 0 = 5000 */
   int32_t ticks_per_launch;   /* ticks per replay of the captured tick graph; 0 = 1 */
   int32_t direct_launch;      /* 0: each group of ticks is one replay of a captured HIP graph;
                                  1: the same kernels launched one by one (no graph) */

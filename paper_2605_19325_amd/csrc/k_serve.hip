@@ -6,7 +6,7 @@
 // Algorithms 2-3) with the KKT check of every iteration, and the final
 // objective.  Everything that survives a tick lives in device memory (the
 // slot's state and workspace), so a request computes the same numbers
-// whether it runs alone or beside others, and whatever the tick budget.
+// whether it runs alone or beside others, and however long its ticks are.
 //
 // Within a workgroup every step is a block-level routine: tall-skinny
 // products X B and X^T A stream X in LDS tiles and accumulate in float32
@@ -901,11 +901,11 @@ __device__ void admm_rows(const ServeReq& q, const ServeScalars& ctl, AdmmSmem& 
 }
 
 // ---------------------------------------------------------------------------
-// The state machine.  Each call runs one step and returns its cost in
-// multiply-adds; thread 0 updates ctl, and every path ends at a barrier.
+// The state machine.  Each call runs one step; thread 0 updates ctl, and
+// every path ends at a barrier.
 // ---------------------------------------------------------------------------
 template <int XT>
-__device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& ctl, ServeSmem& sm,
+__device__ void serve_step(const ServeReq& q, ServeState& st, ServeScalars& ctl, ServeSmem& sm,
                               double* red) {
   const XE<XT>* X = reinterpret_cast<const XE<XT>*>(q.X);
   const int64_t m = q.m, n = q.n, ld = q.ld;
@@ -983,8 +983,7 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
       }
     }
     __syncthreads();
-    return sub <= last_orth + 1 ? m * n * (int64_t)kk + (m + n) * (int64_t)kk * kk * 2
-                                : m * n * (int64_t)(r + 1);
+    return;
   }
 
   if (stage == kStRot) {
@@ -1011,7 +1010,7 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
         }
       }
       __syncthreads();
-      return N * (int64_t)r;
+      return;
     }
     if (sub == 1) {
       // one ADMM step (Algorithm 1): rows and M = W^T B (admm_rows), then R = polar(M)
@@ -1041,7 +1040,7 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
         if (tol_hit || step + 1 >= q.rot_max_iter) ctl.sub = 2;
       }
       __syncthreads();
-      return N * (int64_t)SKP * r * 2 + (int64_t)SKP * SKP * SKP * 20;
+      return;
     }
     // U = W_U R, V = W_V R with the last R
     for (int e = threadIdx.x; e < SKP * SKP; e += SNT) Rs[e] = st.R[e];
@@ -1054,7 +1053,7 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
       ctl.sub = 0;
     }
     __syncthreads();
-    return N * (int64_t)r * r;
+    return;
   }
 
   if (stage == kStSetup) {
@@ -1093,7 +1092,7 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
       ctl.stage = kStIter;
     }
     __syncthreads();
-    return m * n * (int64_t)r + (m + n) * (int64_t)SKP * SKP;
+    return;
   }
 
   if (stage == kStIter) {
@@ -1150,7 +1149,7 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
       s_stop = stop ? 1 : 0;
     }
     __syncthreads();
-    if (s_stop) return m * n * (int64_t)r + (m + n) * (int64_t)SKP * SKP;
+    if (s_stop) return;
     const int phase = ctl.iphase;
     // U half: update in place, then H = U^T U and Q = X^T U
     row_pass(q.U, m, r, q.Y32, sm.w, true, true, phase, ctl.step[0], q.sweeps, q.mode == 2);
@@ -1167,7 +1166,7 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
       ctl.iters = k + 1;
     }
     __syncthreads();
-    return 2 * m * n * (int64_t)r + 4 * (m + n) * (int64_t)SKP * SKP;
+    return;
   }
 
   // final objective, evaluated directly
@@ -1179,13 +1178,12 @@ __device__ int64_t serve_step(const ServeReq& q, ServeState& st, ServeScalars& c
     ctl.stage = kStDone;
   }
   __syncthreads();
-  return m * n * (int64_t)r;
 }
 
 template <int XT>
 __global__ __launch_bounds__(SNT) void k_serve_tick(ServeSlot* __restrict__ slots,
                                                     ServeStatus* __restrict__ status, int nslots,
-                                                    int64_t budget) {
+                                                    int64_t time_limit) {
   __shared__ ServeSmem sm;
   __shared__ ServeScalars ctl;
   __shared__ double red[SNT / kWave];
@@ -1196,10 +1194,15 @@ __global__ __launch_bounds__(SNT) void k_serve_tick(ServeSlot* __restrict__ slot
   if (stt->status != kSlotRunning || sl->q.xt != XT) return;
   if (threadIdx.x == 0) ctl = sl->s.c;
   __syncthreads();
-  int64_t spent = 0;
+  // steps until one ends past the slot's time in this tick, read by thread 0
+  // from the constant 100 MHz clock and shared through LDS
+  const long long t_start = wall_clock64();
+  __shared__ int s_more;
   while (ctl.stage != kStDone) {
-    spent += serve_step<XT>(sl->q, sl->s, ctl, sm, red);
-    if (spent >= budget) break;
+    serve_step<XT>(sl->q, sl->s, ctl, sm, red);
+    if (threadIdx.x == 0) s_more = wall_clock64() - t_start < time_limit ? 1 : 0;
+    __syncthreads();
+    if (!s_more) break;
   }
   if (threadIdx.x == 0) {
     sl->s.c = ctl;
@@ -1229,14 +1232,14 @@ __global__ __launch_bounds__(SNT) void k_serve_tick(ServeSlot* __restrict__ slot
 }  // namespace
 
 hipError_t launch_serve_tick(int xt, ServeSlot* slots, ServeStatus* status, int nslots,
-                             int64_t budget, hipStream_t s) {
+                             int64_t time_limit, hipStream_t s) {
   if (nslots < 1) return hipSuccess;
   if (xt == ENMF_F32)
-    hipLaunchKernelGGL((k_serve_tick<0>), dim3(nslots), dim3(SNT), 0, s, slots, status, nslots, budget);
+    hipLaunchKernelGGL((k_serve_tick<0>), dim3(nslots), dim3(SNT), 0, s, slots, status, nslots, time_limit);
   else if (xt == ENMF_BF16)
-    hipLaunchKernelGGL((k_serve_tick<1>), dim3(nslots), dim3(SNT), 0, s, slots, status, nslots, budget);
+    hipLaunchKernelGGL((k_serve_tick<1>), dim3(nslots), dim3(SNT), 0, s, slots, status, nslots, time_limit);
   else
-    hipLaunchKernelGGL((k_serve_tick<2>), dim3(nslots), dim3(SNT), 0, s, slots, status, nslots, budget);
+    hipLaunchKernelGGL((k_serve_tick<2>), dim3(nslots), dim3(SNT), 0, s, slots, status, nslots, time_limit);
   return hipGetLastError();
 }
 

@@ -112,7 +112,7 @@ struct enmf_server {
   int device = 0;
   hipStream_t stream = nullptr;
   int max_slots = 1024;
-  int64_t budget = 64LL << 20;
+  int64_t tick_limit = 500000;   // constant-clock ticks (10 ns) a slot runs per tick
   char* arena_base = nullptr;
   Arena* arena = nullptr;
   ServeSlot* d_slots = nullptr;
@@ -224,7 +224,7 @@ hipError_t enqueue_ticks(enmf_server* s, int mask) {
   for (int t = 0; t < s->ticks; ++t)
     for (int xt = 0; xt < 3; ++xt)
       if (mask >> xt & 1) {
-        const hipError_t e = launch_serve_tick(xt, s->d_slots, s->d_status, s->max_slots, s->budget,
+        const hipError_t e = launch_serve_tick(xt, s->d_slots, s->d_status, s->max_slots, s->tick_limit,
                                                s->stream);
         if (e != hipSuccess) return e;
       }
@@ -390,13 +390,13 @@ enmf_status enmf_serve_start(enmf_ctx* c, const enmf_serve_opts* opts, enmf_serv
   if (!c) return ENMF_EINVAL;
   enmf_serve_opts o{};
   if (opts) o = *opts;
-  if (o.max_slots < 0 || o.tick_budget < 0 || o.ticks_per_launch < 0 ||
+  if (o.max_slots < 0 || o.tick_time_us < 0 || o.ticks_per_launch < 0 ||
       (o.direct_launch != 0 && o.direct_launch != 1))
     return ENMF_EINVAL;
   auto* s = new enmf_server();
   s->device = ctx_device(c);
   s->max_slots = o.max_slots > 0 ? o.max_slots : 1024;
-  s->budget = (int64_t)(o.tick_budget > 0 ? o.tick_budget : 256) << 20;
+  s->tick_limit = (int64_t)(o.tick_time_us > 0 ? o.tick_time_us : 5000) * 100;
   s->ticks = o.ticks_per_launch > 0 ? o.ticks_per_launch : 1;
   s->direct = o.direct_launch == 1;
   const int64_t arena_bytes = o.hbm_budget_bytes > 0 ? (int64_t)o.hbm_budget_bytes : (1LL << 30);

@@ -66,9 +66,10 @@ struct ServeStatus {
 };
 
 // Launch one tick over nslots slots for X stored as xt (ENMF_F32/BF16/F16);
-// slots of another storage type or not running are skipped.  budget bounds
-// the multiply-adds one slot spends in this tick (at least one step runs).
+// slots of another storage type or not running are skipped.  A slot runs
+// steps until one ends time_limit or more ticks of the device's constant
+// 100 MHz clock after the slot started in this tick (at least one step runs).
 hipError_t launch_serve_tick(int xt, ServeSlot* slots, ServeStatus* status, int nslots,
-                             int64_t budget, hipStream_t s);
+                             int64_t time_limit, hipStream_t s);
 
 }  // namespace enmf

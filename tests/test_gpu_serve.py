@@ -7,7 +7,7 @@ test matrix omega:
 * bfloat16 X: the oracle's relative error within 1e-3 and a KKT residual <= 1e-5.
 
 A request gives bitwise the same factors when it runs alone, in a mix of
-uneven requests of several dtypes, under a different tick budget, and with
+uneven requests of several dtypes, under a different tick time, and with
 its ticks launched one by one instead of replayed from a captured graph.
 Requests at the large end of the stream (about 2048 x 2048, r = 30-32) meet
 the same bar as the small ones.
@@ -111,7 +111,7 @@ def _request(i, seed):
 
 
 def test_same_result_alone_and_in_the_mix(lib):
-    say("one request alone, in a mix of 16 uneven requests, and with a small tick budget")
+    say("one request alone, in a mix of 16 uneven requests, and with one step per tick")
     Xa, ra, oma = _request(0, 500)
     Xa_b = lib.convert(to_dev(Xa), torch.bfloat16)
     opts = dict(oversample=oma.shape[1] - ra, max_iter=150, kkt_tol=1e-6)
@@ -138,13 +138,13 @@ def test_same_result_alone_and_in_the_mix(lib):
         U2, V2, r2 = run(srv, mix)
     finally:
         srv.stop()
-    srv = enmf.Server(lib, max_slots=8, tick_budget=1)
+    srv = enmf.Server(lib, max_slots=8, tick_time_us=1)   # one step per tick
     try:
         U3, V3, r3 = run(srv, mix[:6])
     finally:
         srv.stop()
     # the same ticks launched one by one instead of replayed from a graph, one per replay
-    srv = enmf.Server(lib, max_slots=8, tick_budget=3, ticks_per_launch=1, direct_launch=1)
+    srv = enmf.Server(lib, max_slots=8, tick_time_us=3, ticks_per_launch=1, direct_launch=1)
     try:
         U4, V4, r4 = run(srv, mix[6:10])
     finally:
