@@ -524,7 +524,9 @@ def served(ctx, torch, inputs, enmf, count, load, slots, plain):
     bfloat16 X), each solved to relerr - relerr_svd <= 1e-3, KKT <= 1e-5 or 300
     iterations.  A closed-loop pass (all submitted at once) gives the saturated
     solves/s; an open-loop pass with Poisson arrivals at `load` times that rate
-    gives the latency distribution (submission to completion).  Beside it, the
+    gives the latency distribution (submission to completion), and further
+    open-loop passes at 0.5, 0.8 and 0.95 of it the latencies and whether the
+    server keeps pace at those loads.  Beside it, the
     first `plain` requests of the stream solved one at a time by the plain
     float32 form (enmf_svd_init, enmf_rotate, enmf_iterate on float32 X, same
     stopping rule): their service times, and the latencies of a one-at-a-time
@@ -581,6 +583,24 @@ def served(ctx, torch, inputs, enmf, count, load, slots, plain):
     span = tb - ta
     steady = float(np.count_nonzero((done_o > ta) & (done_o <= tb))) / span if span > 0 else 0.0
     arriving = (count - 1 - count // 4) / span if span > 0 else 0.0
+    # the other loads of the served-stream workload (fractions of the saturated rate)
+    sweep = []
+    for frac in (0.5, 0.8, 0.95):
+        log(f"  served: open loop at {frac:.2f} of the saturated rate")
+        arr_f = inputs.poisson_arrivals(count, frac * sat, 8)
+        _, lat_f, _, _, sub_f, done_f = run(arr_f)
+        fa, fb = float(sub_f[count // 4]), float(sub_f[-1])
+        fsp = fb - fa
+        st_f = float(np.count_nonzero((done_f > fa) & (done_f <= fb))) / fsp if fsp > 0 else 0.0
+        ar_f = (count - 1 - count // 4) / fsp if fsp > 0 else 0.0
+        sweep.append({
+            "load": frac, "arrival_rate_per_s": round(frac * sat, 2),
+            "solves_per_s_while_arriving": round(st_f, 2),
+            "sustained": bool(np.median(lat_f[-count // 4:]) <= 1.5 * np.median(lat_f[:count // 4])
+                              and st_f >= 0.97 * ar_f),
+            "p50_latency_s": round(float(np.percentile(lat_f, 50)), 5),
+            "p99_latency_s": round(float(np.percentile(lat_f, 99)), 5),
+        })
     log("  served: the plain float32 form, one request at a time")
     out = {
         "requests": count, "dtype": "bf16", "slots": slots,
@@ -599,6 +619,7 @@ def served(ctx, torch, inputs, enmf, count, load, slots, plain):
         "p50_latency_s": round(float(np.percentile(lat_o, 50)), 5),
         "p99_latency_s": round(float(np.percentile(lat_o, 99)), 5),
         "mean_iters": round(float(iters_o.mean()), 2), "converged_frac": round(conv_o, 4),
+        "open_loop_loads": sweep,
         "closed_loop_p50_s": round(float(np.percentile(lat_c, 50)), 5),
         "closed_loop_p99_s": round(float(np.percentile(lat_c, 99)), 5),
     }
