@@ -103,7 +103,7 @@ __global__ void k_setup_state(const double* __restrict__ stat, int nbU, int nbV,
 // The result goes to Aout (which may be A).  rec[b] = {#negative of the
 // output, |M o grad|^2 before the sweeps, |M o grad|^2 after, 0, check...}.
 template <int KP, bool LOOP>
-__global__ __launch_bounds__(Team<KP>::NT, (LOOP && KP >= 32) ? 2 : 1) void k_rowupdate(
+__global__ __launch_bounds__(Team<KP>::NT, (KP >= 16 && (LOOP ? KP >= 32 : true)) ? 2 : 1) void k_rowupdate(
     const float* A, float* Aout, int64_t rows, int r,
     const float* __restrict__ P, int nsplit, int64_t pstride, const double* __restrict__ G,
     DevState* st, int half, int sweeps, int flags, double* __restrict__ rec,
@@ -221,6 +221,49 @@ __global__ __launch_bounds__(Team<KP>::NT, (LOOP && KP >= 32) ? 2 : 1) void k_ro
 #pragma unroll
     for (int e = 0; e < 8; ++e) ig[e] = sinv[c0 + e];
     const int base = (threadIdx.x % kWave) - q;
+    if constexpr (!LOOP) {
+      // The lane's 8 x 8 block of Gram rows 8o..8o+7 at its own columns is
+      // loaded into registers before the block's steps (for the owner it is
+      // the diagonal block), so the chain of steps waits on no LDS read.
+      // (Not in the looping variant, whose registers would spill.)
+      for (int o = 0; 8 * o < r; ++o) {
+        double g[8][8];
+#pragma unroll
+        for (int ej = 0; ej < 8; ++ej)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) g[ej][e] = sG[(8 * o + ej) * KP + c0 + e];
+        __builtin_amdgcn_sched_barrier(0);
+        double dl[8];
+#pragma unroll
+        for (int ej = 0; ej < 8; ++ej) dl[ej] = 0.0;
+        if (q == o) {
+#pragma unroll
+          for (int ej = 0; ej < 8; ++ej) {
+            const bool on = ig[ej] > 0.0;
+            const double v = (double)a[ej] + (p[ej] - t[ej]) * ig[ej];
+            const float nv = (float)(v > 0.0 ? v : 0.0);
+            const double d = on ? (double)nv - (double)a[ej] : 0.0;
+            a[ej] = on ? nv : a[ej];
+            dl[ej] = d;
+#pragma unroll
+            for (int e = ej + 1; e < 8; ++e) t[e] = fma(d, g[ej][e], t[e]);
+          }
+#pragma unroll
+          for (int ej = 0; ej < 8; ++ej)
+#pragma unroll
+            for (int e = 0; e <= ej; ++e) t[e] = fma(dl[ej], g[ej][e], t[e]);
+        }
+#pragma unroll
+        for (int ej = 0; ej < 8; ++ej) {
+          const double x = __shfl(dl[ej], base + o);
+          dl[ej] = q == o ? 0.0 : x;
+        }
+#pragma unroll
+        for (int ej = 0; ej < 8; ++ej)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) t[e] = fma(dl[ej], g[ej][e], t[e]);
+      }
+    } else
     for (int o = 0; 8 * o < r; ++o) {
       double dl[8];
 #pragma unroll
