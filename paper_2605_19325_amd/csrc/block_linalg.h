@@ -145,7 +145,8 @@ __device__ __forceinline__ double eigvec(const JacobiT<MAXW>& sm, int a, int j) 
 // and tends to 1 while the singular vectors stay, so the limit is the polar
 // factor of M.  The iteration stops after the step whose change
 // ||X_{k+1} - X_k||_F^2 is at most 1e-20 (the convergence is quadratic, so
-// the remaining error is of order 1e-20) or after 100 steps.  T is scratch.
+// the remaining error is of order 1e-20; the change is only summed once l has
+// passed 0.999) or after 100 steps.  T is scratch.
 // Returns false (X untouched) when ||M||_F is 0 or not finite.
 //
 // Both products run on v_mfma_f64_16x16x4f64, 16 x 16 output tiles dealt
@@ -177,6 +178,10 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
   for (int it = 0; it < 100; ++it) {
     const double a = sqrt(3.0 / (1.0 + l + l * l));
     const double c1 = 1.5 * a, c3 = 0.5 * a * a * a;
+    // While a is away from 1 every singular value still moves by far more
+    // than the stopping threshold, so the step change is summed only once
+    // the interval's lower end has passed 0.999 (a within 5e-4 of 1).
+    const bool look = l > 0.999;
     l = 0.5 * a * l * (3.0 - a * a * l * l);
     // T = X^T X: upper tile (ti, tj) = sum over k of X[k][16 ti + i] X[k][16 tj + j].
     // A wave's tiles advance together through k (independent MFMA chains).
@@ -243,7 +248,8 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
         }
       }
     }
-    d2 = block_sum<NT>(d2, red);   // also orders every read of X before the writes below
+    if (look) d2 = block_sum<NT>(d2, red);   // also orders every read of X before the writes below
+    else __syncthreads();
 #pragma unroll
     for (int u = 0; u < PERW; ++u) {
       const int tile = w + NW * u;
@@ -254,7 +260,7 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
       }
     }
     __syncthreads();
-    if (d2 <= 1e-20) break;
+    if (look && d2 <= 1e-20) break;
   }
   return true;
 }
