@@ -43,11 +43,11 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 XT_MIN_BYTES = 512 << 20     # X at least this large: enmf_iterate runs X B on a transposed copy
 # HBM bytes per launch of the streaming kernels inside the ratings solve, from two rocprofv3
 # passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters' reading for a device copy of
-# known size (profiles/k_xv_k_xtu_ratings_100000x20000_r20_hbm_traffic.txt).  They describe the
+# known size (profiles/k_xtu_ratings_100000x20000_r20_hbm_traffic.txt).  They describe the
 # kernel source they were taken on and are reported only while it is unchanged.
-TRAFFIC = {"k_mfma_sha256_16": "754a4cc2f9140798",
-           "k_xtu_bf16 (X^T A)": 4532.79e6, "k_xtu_bf16 (X B on the transposed copy)": 4343.24e6,
-           "k_xtu_f32s (X^T A)": 8288.86e6, "k_xtu_f32s (X B on the transposed copy)": 8107.64e6}
+TRAFFIC = {"k_mfma_sha256_16": "5f0a1fa32e525e4f",
+           "k_xtu_bf16 (X^T A)": 4475.51e6, "k_xtu_bf16 (X B on the transposed copy)": 4343.96e6,
+           "k_xtu_f32s (X^T A)": 8200.38e6, "k_xtu_f32s (X B on the transposed copy)": 8082.31e6}
 
 
 def parse():
@@ -133,7 +133,7 @@ def cpu_baseline(X, om, rows, iters):
 
 
 # the product kernels' source and the headers they include
-TRAFFIC_SOURCES = ("k_mfma.hip", "dev_common.h", "enmf_internal.h", "decide.h", "row_team.h")
+TRAFFIC_SOURCES = ("k_mfma.hip", "mfma_common.h", "dev_common.h", "enmf_internal.h", "decide.h", "row_team.h")
 
 
 def kernel_source_hash():

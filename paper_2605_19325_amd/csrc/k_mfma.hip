@@ -411,7 +411,7 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
     if (interior) {
       const unsigned short* base = X + (ch * 32 + 8 * g) * ld + j0 + 8 * i;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) dst[e] = ldg16(base + e * ld);
+      for (int e = 0; e < 8; ++e) dst[e] = ldg16_nt(base + e * ld);
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e)
@@ -558,7 +558,7 @@ __global__ __launch_bounds__(kT) void k_xtu_f32s(const float* __restrict__ X, in
     if (interior) {
       const float* base = X + (ch * 32 + 8 * g) * ld + j0 + 4 * i;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) dst[e] = ldg16(base + e * ld);
+      for (int e = 0; e < 8; ++e) dst[e] = ldg16_nt(base + e * ld);
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e)

@@ -50,12 +50,18 @@ __device__ __forceinline__ uint4 load16(const ET* __restrict__ X, int64_t rows, 
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// Unconditional 16-byte load of X (interior chunks: no data-dependent
-// masking, so the loads stay in flight until their first use), marked
-// non-temporal: X is streamed once per product, and the hint keeps the caches
-// for the factor chunks that every block re-reads.
+// Unconditional 16-byte load (interior chunks: no data-dependent masking, so
+// the loads stay in flight until their first use).
 template <typename ET>
-__device__ __forceinline__ uint4 ldg16(const ET* p) {
+__device__ __forceinline__ uint4 ldg16(const ET* p) { return *reinterpret_cast<const uint4*>(p); }
+
+// The same, marked non-temporal, for X^T A's loads of X: each wave's loads
+// cover whole cache lines of a row run, X is streamed once per product, and
+// the hint leaves the caches to the factor chunks that every block re-reads.
+// (X B's operand-layout loads take half lines, whose other halves another
+// load reads later, so they keep the plain form.)
+template <typename ET>
+__device__ __forceinline__ uint4 ldg16_nt(const ET* p) {
   typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
   const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
   return make_uint4(v.x, v.y, v.z, v.w);
