@@ -369,9 +369,10 @@ __global__ __launch_bounds__(kT) void k_xv_f32s(const float* __restrict__ X, int
 // chunk in LDS, rows padded to 40).
 // ---------------------------------------------------------------------------
 constexpr int kAtLd = 40;   // LDS row pitch of the factor chunk (bank spread)
+constexpr int64_t kNtMinBytes = (int64_t)512 << 20;   // X from which X^T A loads it non-temporally
 constexpr int kAtG = 32;    // its row pitch in global memory (unpadded)
 
-template <int KP>
+template <int KP, bool NTL>
 __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restrict__ X, int64_t m,
                                                  int64_t n, int64_t ld,
                                                  const unsigned short* __restrict__ At, int k,
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
     if (interior) {
       const unsigned short* base = X + (ch * 32 + 8 * g) * ld + j0 + 8 * i;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) dst[e] = ldg16_nt(base + e * ld);
+      for (int e = 0; e < 8; ++e) dst[e] = NTL ? ldg16_nt(base + e * ld) : ldg16(base + e * ld);
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e)
@@ -518,7 +519,7 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
 // 8g+7] (the transposed split chunk in LDS, rows padded to 40), read once per
 // chunk and shared by the four tiles.
 // ---------------------------------------------------------------------------
-template <int KP>
+template <int KP, bool NTL>
 __global__ __launch_bounds__(kT) void k_xtu_f32s(const float* __restrict__ X, int64_t m, int64_t n,
                                                  int64_t ld, const unsigned short* __restrict__ At,
                                                  int k, int chunks_per_split, int64_t nchunks,
@@ -558,7 +559,7 @@ __global__ __launch_bounds__(kT) void k_xtu_f32s(const float* __restrict__ X, in
     if (interior) {
       const float* base = X + (ch * 32 + 8 * g) * ld + j0 + 4 * i;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) dst[e] = ldg16_nt(base + e * ld);
+      for (int e = 0; e < 8; ++e) dst[e] = NTL ? ldg16_nt(base + e * ld) : ldg16(base + e * ld);
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e)
@@ -743,19 +744,19 @@ const void* xv_kernel(int xt, int KP) {
 const void* xtu_kernel(int xt, int KP) {
   if (xt == ENMF_F32) {
     switch (KP) {
-      case 16: return reinterpret_cast<const void*>(&k_xtu_f32s<16>);
-      case 32: return reinterpret_cast<const void*>(&k_xtu_f32s<32>);
-      case 48: return reinterpret_cast<const void*>(&k_xtu_f32s<48>);
-      case 64: return reinterpret_cast<const void*>(&k_xtu_f32s<64>);
-      default: return reinterpret_cast<const void*>(&k_xtu_f32s<80>);
+      case 16: return reinterpret_cast<const void*>(&k_xtu_f32s<16, false>);
+      case 32: return reinterpret_cast<const void*>(&k_xtu_f32s<32, false>);
+      case 48: return reinterpret_cast<const void*>(&k_xtu_f32s<48, false>);
+      case 64: return reinterpret_cast<const void*>(&k_xtu_f32s<64, false>);
+      default: return reinterpret_cast<const void*>(&k_xtu_f32s<80, false>);
     }
   }
   switch (KP) {
-    case 16: return reinterpret_cast<const void*>(&k_xtu_bf16<16>);
-    case 32: return reinterpret_cast<const void*>(&k_xtu_bf16<32>);
-    case 48: return reinterpret_cast<const void*>(&k_xtu_bf16<48>);
-    case 64: return reinterpret_cast<const void*>(&k_xtu_bf16<64>);
-    default: return reinterpret_cast<const void*>(&k_xtu_bf16<80>);
+    case 16: return reinterpret_cast<const void*>(&k_xtu_bf16<16, false>);
+    case 32: return reinterpret_cast<const void*>(&k_xtu_bf16<32, false>);
+    case 48: return reinterpret_cast<const void*>(&k_xtu_bf16<48, false>);
+    case 64: return reinterpret_cast<const void*>(&k_xtu_bf16<64, false>);
+    default: return reinterpret_cast<const void*>(&k_xtu_bf16<80, false>);
   }
 }
 
@@ -917,7 +918,12 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
   const double* gsrc = gj ? gj->src : nullptr;
   const int gparts = gj ? gj->nparts : 0, gkp = gj ? gj->kp : 0;
   double* gdst = gj ? gj->dst : nullptr;
-  const bool vec = aligned_rows(X, ld, xt == ENMF_F32 ? 4 : 2);
+  // 16-byte loads of X marked non-temporal only where X is far larger than
+  // the last-level cache (where X fits it, the hint would evict the X that
+  // the next product reads from there)
+  const int64_t xbytes = m * n * (xt == ENMF_F32 ? 4 : 2);
+  const int vec = aligned_rows(X, ld, xt == ENMF_F32 ? 4 : 2) ? 1 : 0;
+  const bool ntl = xbytes >= kNtMinBytes;
   int64_t eff = 1;
   if (xt == ENMF_F32) {
     const int64_t nch = (m + 31) / 32;
@@ -934,11 +940,21 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
     const unsigned short* At = reinterpret_cast<const unsigned short*>(pack);
     if (ev0) (void)hipEventRecord(ev0, s);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xtu_f32s<16>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
-      case 32: hipLaunchKernelGGL((k_xtu_f32s<32>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
-      case 48: hipLaunchKernelGGL((k_xtu_f32s<48>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
-      case 64: hipLaunchKernelGGL((k_xtu_f32s<64>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
-      default: hipLaunchKernelGGL((k_xtu_f32s<80>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
+      case 16: if (ntl) hipLaunchKernelGGL((k_xtu_f32s<16, true>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        else hipLaunchKernelGGL((k_xtu_f32s<16, false>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        break;
+      case 32: if (ntl) hipLaunchKernelGGL((k_xtu_f32s<32, true>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        else hipLaunchKernelGGL((k_xtu_f32s<32, false>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        break;
+      case 48: if (ntl) hipLaunchKernelGGL((k_xtu_f32s<48, true>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        else hipLaunchKernelGGL((k_xtu_f32s<48, false>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        break;
+      case 64: if (ntl) hipLaunchKernelGGL((k_xtu_f32s<64, true>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        else hipLaunchKernelGGL((k_xtu_f32s<64, false>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        break;
+      default: if (ntl) hipLaunchKernelGGL((k_xtu_f32s<80, true>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        else hipLaunchKernelGGL((k_xtu_f32s<80, false>), grid, dim3(kT), 0, s, Xf, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        break;
     }
     if (ev1) (void)hipEventRecord(ev1, s);
   } else {
@@ -956,11 +972,21 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
     const unsigned short* At = reinterpret_cast<const unsigned short*>(pack);
     if (ev0) (void)hipEventRecord(ev0, s);
     switch (KP) {
-      case 16: hipLaunchKernelGGL((k_xtu_bf16<16>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
-      case 32: hipLaunchKernelGGL((k_xtu_bf16<32>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
-      case 48: hipLaunchKernelGGL((k_xtu_bf16<48>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
-      case 64: hipLaunchKernelGGL((k_xtu_bf16<64>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
-      default: hipLaunchKernelGGL((k_xtu_bf16<80>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state); break;
+      case 16: if (ntl) hipLaunchKernelGGL((k_xtu_bf16<16, true>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        else hipLaunchKernelGGL((k_xtu_bf16<16, false>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        break;
+      case 32: if (ntl) hipLaunchKernelGGL((k_xtu_bf16<32, true>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        else hipLaunchKernelGGL((k_xtu_bf16<32, false>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        break;
+      case 48: if (ntl) hipLaunchKernelGGL((k_xtu_bf16<48, true>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        else hipLaunchKernelGGL((k_xtu_bf16<48, false>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        break;
+      case 64: if (ntl) hipLaunchKernelGGL((k_xtu_bf16<64, true>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        else hipLaunchKernelGGL((k_xtu_bf16<64, false>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        break;
+      default: if (ntl) hipLaunchKernelGGL((k_xtu_bf16<80, true>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        else hipLaunchKernelGGL((k_xtu_bf16<80, false>), grid, dim3(kT), 0, s, Xb, m, n, ld, At, k, cps, nch, (int)vec, dst, n * k, stop, gsrc, gparts, gkp, gdst, da, dst_state);
+        break;
     }
     if (ev1) (void)hipEventRecord(ev1, s);
   }
