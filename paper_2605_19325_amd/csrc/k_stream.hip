@@ -256,21 +256,25 @@ __global__ void k_pad_cols(const float* __restrict__ in, int64_t rows_in, int k,
 
 // Direct residual: part[b] = sum over this block's (i, j) of (X_ij - U_i . V_j)^2,
 // with the dot products on the float64 matrix cores (v_mfma_f64_16x16x4f64)
-// and the squares accumulated in float64.  A
-// wave owns 64 columns (four 16 x 16 output tiles) and walks the block's rows
-// 16 at a time: U V^T of a 16-row group is KS = ceil(r / 4) steps of 4 for
-// each tile, with the wave's V operands held in registers for the whole
-// kernel and the group's U operands loaded from the float64 copy of U.  Lane
-// (i, g) supplies U[row i][4s + g] and V[col i][4s + g] and receives the
-// entries (rows g + 4v, column i) of each tile, then subtracts them from X
-// (the next group's x values are in flight meanwhile) and adds the squares
-// in float64.  Rows past r1 and columns past n add nothing.
+// and the squares accumulated in float64.  A wave owns 64 columns (four
+// 16 x 16 output tiles) and walks the block's rows 16 at a time: U V^T of a
+// 16-row group is KS = ceil(r / 4) steps of 4 for each tile, with the wave's
+// V operands held in registers for the whole kernel and the group's U
+// operands read from the float64 copy of U (issued once the previous group's
+// matrix-core steps are in).  Lane (i, g)
+// supplies U[row i][4s + g] and receives the entries in rows g + 4v of each
+// tile.  Column i of tile t is column 4i + t of the wave's 64, so a lane's
+// four x values of one row are adjacent in memory: one 8-byte (16-bit X) or
+// 16-byte (float32 X) load per row, issued one group ahead (vec: rows 16-byte
+// aligned).  Groups that reach past the block's rows or the matrix's columns
+// load element by element, clamped into the matrix, and add nothing for
+// entries outside it.
 template <int XT, int KS>
 __global__ __launch_bounds__(kThreads) void k_residual_mfma(const void* __restrict__ Xv, int64_t m,
                                                             int64_t n, int64_t ld,
                                                             const double* __restrict__ Ud, int ldu,
                                                             const float* __restrict__ V, int r,
-                                                            int64_t rows_per_split,
+                                                            int64_t rows_per_split, int vec,
                                                             double* __restrict__ part) {
   typedef double d4 __attribute__((ext_vector_type(4)));
   __shared__ double sh[kThreads / kWave];
@@ -279,10 +283,11 @@ __global__ __launch_bounds__(kThreads) void k_residual_mfma(const void* __restri
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int i = lane % 16, g = lane / 16;
   const int64_t col0 = (int64_t)blockIdx.x * kThreads + 64 * w;
+  const int64_t jl = col0 + 4 * i;                 // the lane's column in tile 0
   double vb[4][KS];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int64_t j = col0 + 16 * t + i;
+    const int64_t j = jl + t;
 #pragma unroll
     for (int q = 0; q < KS; ++q) {
       const int c = 4 * q + g;
@@ -291,51 +296,81 @@ __global__ __launch_bounds__(kThreads) void k_residual_mfma(const void* __restri
   }
   const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
   const int64_t r1 = r0 + rows_per_split < m ? r0 + rows_per_split : m;
-  // x of rows row0 + g + 4v, columns col0 + 16t + i (clamped into the matrix)
-  auto load_x = [&](int64_t row0, float (&xs)[4][4]) {
+  const bool cols_in = col0 + 64 <= n;             // wave-uniform
+  // x of rows row0 + g + 4v (v = 0..3), columns jl .. jl + 3, kept in storage
+  // form until use (float4, or four 16-bit values in a uint2)
+  using Raw = typename std::conditional<XT == 0, float4, uint2>::type;
+  auto load_x = [&](int64_t row0, Raw (&xs)[4]) {
+    if (vec && cols_in && row0 + 16 <= r1) {
+      const ET* __restrict__ base = X + (row0 + g) * ld + jl;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      int64_t row = row0 + g + 4 * v;
-      row = row < r1 ? row : r1 - 1;
+      for (int v = 0; v < 4; ++v) xs[v] = *reinterpret_cast<const Raw*>(base + 4 * v * ld);
+    } else {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        int64_t j = col0 + 16 * t + i;
-        j = j < n ? j : n - 1;
-        xs[v][t] = to_f32<XT>(X[row * ld + j]);
+      for (int v = 0; v < 4; ++v) {
+        int64_t row = row0 + g + 4 * v;
+        row = row < r1 ? row : r1 - 1;
+        ET e[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          int64_t j = jl + t;
+          j = j < n ? j : n - 1;
+          e[t] = X[row * ld + j];
+        }
+        if constexpr (XT == 0) xs[v] = make_float4(e[0], e[1], e[2], e[3]);
+        else xs[v] = make_uint2((unsigned)e[0] | ((unsigned)e[1] << 16), (unsigned)e[2] | ((unsigned)e[3] << 16));
       }
     }
   };
+  auto elem = [&](const Raw& q, int t) -> double {
+    if constexpr (XT == 0) return (double)(t == 0 ? q.x : t == 1 ? q.y : t == 2 ? q.z : q.w);
+    else {
+      const unsigned h = t < 2 ? q.x : q.y;
+      return (double)to_f32<XT>((unsigned short)(t % 2 == 0 ? (h & 0xffffu) : (h >> 16)));
+    }
+  };
+  auto load_u = [&](int64_t row0, double (&u)[KS]) {
+    int64_t row = row0 + i;
+    row = row < r1 ? row : r1 - 1;
+#pragma unroll
+    for (int q = 0; q < KS; ++q) u[q] = Ud[row * ldu + 4 * q + g];   // zero past r
+  };
   double acc = 0.0;
-  float xa[4][4], xb[4][4];
-  if (r0 < r1) load_x(r0, xa);
+  Raw xa[4], xb[4];
+  double ua[KS];
+  if (r0 < r1) {
+    load_x(r0, xa);
+    load_u(r0, ua);
+  }
   for (int64_t row0 = r0; row0 < r1; row0 += 16) {
     const bool more = row0 + 16 < r1;
     if (more) load_x(row0 + 16, xb);
-    double ua[KS];
-    {
-      int64_t row = row0 + i;
-      row = row < r1 ? row : r1 - 1;
-#pragma unroll
-      for (int q = 0; q < KS; ++q) ua[q] = Ud[row * ldu + 4 * q + g];   // zero past r
-    }
+    const bool all_in = cols_in && row0 + 16 <= r1;   // wave-uniform
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       d4 d = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int q = 0; q < KS; ++q) d = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[q], vb[t][q], d, 0, 0, 0);
-      const bool colok = col0 + 16 * t + i < n;
+      if (all_in) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const double e = (double)xa[v][t] - d[v];
-        const bool ok = colok && row0 + g + 4 * v < r1;
-        acc = ok ? fma(e, e, acc) : acc;
+        for (int v = 0; v < 4; ++v) {
+          const double e = elem(xa[v], t) - d[v];
+          acc = fma(e, e, acc);
+        }
+      } else {
+        const bool colok = jl + t < n;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double e = elem(xa[v], t) - d[v];
+          const bool ok = colok && row0 + g + 4 * v < r1;
+          acc = ok ? fma(e, e, acc) : acc;
+        }
       }
     }
     if (more) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) xa[v][t] = xb[v][t];
+      for (int v = 0; v < 4; ++v) xa[v] = xb[v];
+      load_u(row0 + 16, ua);     // after this group's matrix-core steps
     }
   }
   const double tot = block_sum<kThreads>(acc, sh);
@@ -559,20 +594,20 @@ void xtu_dispatch_kp(int kp, dim3 grid, const void* X, int64_t m, int64_t n, int
 
 template <int XT>
 void residual_dispatch(dim3 grid, const void* X, int64_t m, int64_t n, int64_t ld, const double* Ud,
-                       int ldu, const float* V, int r, int64_t rps, double* part, hipStream_t s) {
+                       int ldu, const float* V, int r, int64_t rps, int vec, double* part, hipStream_t s) {
   switch ((r + 3) / 4) {
-    case 1: hipLaunchKernelGGL((k_residual_mfma<XT, 1>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
-    case 2: hipLaunchKernelGGL((k_residual_mfma<XT, 2>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
-    case 3: hipLaunchKernelGGL((k_residual_mfma<XT, 3>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
-    case 4: hipLaunchKernelGGL((k_residual_mfma<XT, 4>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
-    case 5: hipLaunchKernelGGL((k_residual_mfma<XT, 5>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
-    case 6: hipLaunchKernelGGL((k_residual_mfma<XT, 6>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
-    case 7: hipLaunchKernelGGL((k_residual_mfma<XT, 7>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
-    case 8: hipLaunchKernelGGL((k_residual_mfma<XT, 8>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
+    case 1: hipLaunchKernelGGL((k_residual_mfma<XT, 1>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, vec, part); return;
+    case 2: hipLaunchKernelGGL((k_residual_mfma<XT, 2>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, vec, part); return;
+    case 3: hipLaunchKernelGGL((k_residual_mfma<XT, 3>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, vec, part); return;
+    case 4: hipLaunchKernelGGL((k_residual_mfma<XT, 4>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, vec, part); return;
+    case 5: hipLaunchKernelGGL((k_residual_mfma<XT, 5>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, vec, part); return;
+    case 6: hipLaunchKernelGGL((k_residual_mfma<XT, 6>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, vec, part); return;
+    case 7: hipLaunchKernelGGL((k_residual_mfma<XT, 7>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, vec, part); return;
+    case 8: hipLaunchKernelGGL((k_residual_mfma<XT, 8>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, vec, part); return;
     case 9: case 10: case 11: case 12:
-      hipLaunchKernelGGL((k_residual_mfma<XT, 12>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
+      hipLaunchKernelGGL((k_residual_mfma<XT, 12>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, vec, part); return;
     default:
-      hipLaunchKernelGGL((k_residual_mfma<XT, 16>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, part); return;
+      hipLaunchKernelGGL((k_residual_mfma<XT, 16>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ud, ldu, V, r, rps, vec, part); return;
   }
 }
 
@@ -679,10 +714,12 @@ hipError_t launch_residual(const void* X, int xt, int64_t m, int64_t n, int64_t 
   const int64_t rps = (m + sp - 1) / sp;
   sp = (m + rps - 1) / rps;
   dim3 grid((unsigned)cb, (unsigned)sp);
+  const int esz = xt == ENMF_F32 ? 4 : 2;
+  const int vec = (reinterpret_cast<uintptr_t>(X) % 16 == 0 && (ld * esz) % 16 == 0) ? 1 : 0;
   switch (xt) {
-    case ENMF_F32: residual_dispatch<0>(grid, X, m, n, ld, Ud, ldu, V, r, rps, part, s); break;
-    case ENMF_BF16: residual_dispatch<1>(grid, X, m, n, ld, Ud, ldu, V, r, rps, part, s); break;
-    default: residual_dispatch<2>(grid, X, m, n, ld, Ud, ldu, V, r, rps, part, s); break;
+    case ENMF_F32: residual_dispatch<0>(grid, X, m, n, ld, Ud, ldu, V, r, rps, vec, part, s); break;
+    case ENMF_BF16: residual_dispatch<1>(grid, X, m, n, ld, Ud, ldu, V, r, rps, vec, part, s); break;
+    default: residual_dispatch<2>(grid, X, m, n, ld, Ud, ldu, V, r, rps, vec, part, s); break;
   }
   *nparts = (int)(cb * sp);
   return hipGetLastError();

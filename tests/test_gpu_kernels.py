@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle as O
 from paper_2605_19325_amd import enmf, inputs
 
 pytestmark = pytest.mark.gpu
@@ -21,6 +22,10 @@ EPS32 = 2.0 ** -24
 
 def say(msg):
     print(msg, flush=True)
+
+
+def to_dev32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
 
 
 def ref_bound(Xd, Bd, n, split=1):
@@ -133,6 +138,34 @@ def test_gram(lib, rows, k):
     Ad = A.astype(np.float64)
     ref = Ad.T @ Ad
     assert np.allclose(G, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+TORCH_DT = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("m,n,r,pad", [(1, 1, 1, 0), (37, 70, 3, 0), (300, 517, 20, 0), (129, 640, 49, 0),
+                                       (260, 300, 64, 3), (8000, 1280, 20, 8), (20000, 320, 16, 0),
+                                       (6600, 1112, 49, 0)])
+def test_direct_objective(lib, m, n, r, pad, dt):
+    """f = 1/2 ||X - U V^T||^2 of the stored X (the direct float64 residual that
+    objective_kkt reports) against the oracle's objective of the same stored
+    values widened to float64.  The shapes take the 16-row groups of whole
+    64-column runs on aligned rows (vector loads), ragged row groups and column
+    runs, padded and unaligned leading dimensions (element loads), and
+    contraction widths from 1 to 64."""
+    say(f"direct objective {dt} {m}x{n} r={r} ld=n+{pad}")
+    rng = np.random.default_rng(m + n + r)
+    full = torch.from_numpy(rng.random((m, n + pad)).astype(np.float32)).to(TORCH_DT[dt])
+    if pad:
+        full[:, n:] = float("nan")                  # padding must never be read into the result
+    Xh = full[:, :n]
+    U0 = (rng.random((m, r)) / np.sqrt(r)).astype(np.float32)
+    V0 = rng.random((n, r)).astype(np.float32)
+    Xd = full.to(DEV)[:, :n]
+    k = lib.objective_kkt(Xd, to_dev32(U0), to_dev32(V0), 0.5)
+    ref = O.objective(Xh.double().numpy(), U0, V0)
+    assert abs(k["f"] - ref) <= 1e-10 * ref, (k["f"], ref)
 
 
 def test_convert_bf16_rne_bitexact(lib):
