@@ -1,8 +1,9 @@
 """Build libenmf.so in-tree with hipcc for gfx950.
 
 Each translation unit under csrc/ is compiled to an object in parallel, then
-linked into paper_2605_19325_amd/libenmf.so.  Device code is built with the
-packed-FP32 instructions disabled.
+linked into paper_2605_19325_amd/libenmf.so, which exports the enmf_* C ABI
+only (csrc/libenmf.map).  Device code is built with the packed-FP32
+instructions disabled.
 """
 
 import concurrent.futures as cf
@@ -60,7 +61,8 @@ def build(verbose=False, jobs=None):
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}",
+           f"-Wl,--version-script={os.path.join(CSRC, 'libenmf.map')}", "-o", tmp] + objs
     p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if p.returncode != 0:
         raise RuntimeError("link failed:\n" + p.stdout)
