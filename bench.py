@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--serve-load", type=float, default=0.6,
                     help="open-loop arrival rate as a fraction of the closed-loop solves/s")
     ap.add_argument("--serve-slots", type=int, default=1536)
+    ap.add_argument("--serve-wide-min", type=int, default=3 << 20,
+                    help="m n from which a served request runs as a device-wide solve (-1: never)")
     ap.add_argument("--serve-plain", type=int, default=256,
                     help="requests of the stream also solved one by one by the float32 form")
     return ap.parse_args()
@@ -519,14 +521,17 @@ def grot_leg(ctx, torch, inputs, steps=500):
     return out
 
 
-def served(ctx, torch, inputs, enmf, count, load, slots, plain):
+def served(ctx, torch, inputs, enmf, count, load, slots, plain, wide_min):
     """Served stream: `count` requests (m, n log-uniform in [64, 2048], r in 4..32,
     bfloat16 X), each solved to relerr - relerr_svd <= 1e-3, KKT <= 1e-5 or 300
     iterations.  A closed-loop pass (all submitted at once) gives the saturated
     solves/s; an open-loop pass with Poisson arrivals at `load` times that rate
     gives the latency distribution (submission to completion), and further
     open-loop passes at 0.5, 0.8 and 0.95 of it the latencies and whether the
-    server keeps pace at those loads.  Beside it, the
+    server keeps pace at those loads.  Requests of at least `wide_min`
+    elements run as device-wide solves beside the ticks; the closed loop and
+    the open loop at `load` are repeated with every request on the tick path
+    for comparison.  Beside it, the
     first `plain` requests of the stream solved one at a time by the plain
     float32 form (enmf_svd_init, enmf_rotate, enmf_iterate on float32 X, same
     stopping rule): their service times, and the latencies of a one-at-a-time
@@ -545,8 +550,9 @@ def served(ctx, torch, inputs, enmf, count, load, slots, plain):
     torch.cuda.synchronize()
     opts = dict(max_iter=300, relerr_tol=1e-3, kkt_tol=1e-5)
 
-    def run(arrivals, direct=0):
-        srv = enmf.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=slots, direct_launch=direct)
+    def run(arrivals, direct=0, wide=wide_min):
+        srv = enmf.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=slots, direct_launch=direct,
+                          wide_min_elems=wide)
         try:
             t0 = time.perf_counter()
             tickets, sub = [], []
@@ -601,9 +607,24 @@ def served(ctx, torch, inputs, enmf, count, load, slots, plain):
             "p50_latency_s": round(float(np.percentile(lat_f, 50)), 5),
             "p99_latency_s": round(float(np.percentile(lat_f, 99)), 5),
         })
+    log("  served: every request on the tick path, closed loop and the same open loop")
+    wall_t, lat_tc, *_ = run(None, wide=-1)
+    _, lat_t, _, _, sub_t, done_t = run(arr, wide=-1)
+    st_t = float(np.count_nonzero((done_t > ta) & (done_t <= tb))) / span if span > 0 else 0.0
+    tick_only = {
+        "saturated_solves_per_s": round(count / wall_t, 2),
+        "solves_per_s_while_arriving": round(st_t, 2),
+        "sustained": bool(np.median(lat_t[-count // 4:]) <= 1.5 * np.median(lat_t[:count // 4])
+                          and st_t >= 0.97 * arriving),
+        "p50_latency_s": round(float(np.percentile(lat_t, 50)), 5),
+        "p99_latency_s": round(float(np.percentile(lat_t, 99)), 5),
+        "closed_loop_p99_s": round(float(np.percentile(lat_tc, 99)), 5),
+    }
     log("  served: the plain float32 form, one request at a time")
+    wide_n = sum(1 for q in reqs if wide_min > 0 and q["m"] * q["n"] >= wide_min)
     out = {
         "requests": count, "dtype": "bf16", "slots": slots,
+        "wide_min_elems": wide_min, "wide_requests": wide_n,
         "saturated_solves_per_s": round(sat, 2),
         "saturated_solves_per_s_direct_launches": round(count / wall_d, 2),
         "load": load, "arrival_rate_per_s": round(rate, 2),
@@ -622,6 +643,7 @@ def served(ctx, torch, inputs, enmf, count, load, slots, plain):
         "open_loop_loads": sweep,
         "closed_loop_p50_s": round(float(np.percentile(lat_c, 50)), 5),
         "closed_loop_p99_s": round(float(np.percentile(lat_c, 99)), 5),
+        "tick_path_only": tick_only,
     }
     if plain_data:
         for Xf, r, om in plain_data[:4]:                  # warm the kernels of each shape class
@@ -758,7 +780,7 @@ def main():
         if not args.no_serve:
             log("served leg")
             out["served"] = served(ctx, torch, inputs, enmf, args.serve_requests, args.serve_load,
-                                   args.serve_slots, args.serve_plain)
+                                   args.serve_slots, args.serve_plain, args.serve_wide_min)
     if not args.no_cpu:
         log("cpu baseline (the oracle on a row slice)")
         out["cpu_baseline"] = cpu_baseline(X_np, om_np, args.cpu_rows, args.cpu_iters)

@@ -350,6 +350,14 @@ enmf_status enmf_enmc_iterate(enmf_ctx* ctx, const enmf_matrix* X, const enmf_ma
  * PBCD sweeps (pbcd_eps = 0) and modes 0 to 3.  The request's trace is
  * not recorded.
  *
+ * Wide requests (m n >= wide_min_elems) do not take a slot: each runs as one
+ * device-wide solve (the kernels of enmf_svd_init, enmf_rotate and
+ * enmf_iterate, whose products spread over every compute unit) on one of
+ * wide_lanes host threads, each with its own context and stream, beside the
+ * tick loop.  Their workspace lives in those contexts, outside
+ * hbm_budget_bytes.  The path a request takes depends only on its shape, so its
+ * result still does not depend on what else is in flight.
+ *
  * Ownership: X, the omega of svd, U_out and V_out are caller-owned device
  * buffers that must stay valid and untouched until the request has finished
  * (enmf_serve_poll returned something other than ENMF_EBUSY).  U_out and
@@ -368,6 +376,10 @@ typedef struct {
   int32_t ticks_per_launch;   /* ticks per replay of the captured tick graph; 0 = 1 */
   int32_t direct_launch;      /* 0: each group of ticks is one replay of a captured HIP graph;
                                  1: the same kernels launched one by one (no graph) */
+  int64_t wide_min_elems;     /* requests with m n at least this run on the device-wide path (below);
+                                 0 = 3145728, < 0 = none */
+  int32_t wide_lanes;         /* device-wide solves in flight at once; 0 = 2 */
+  int32_t reserved;
 } enmf_serve_opts;
 
 typedef struct {

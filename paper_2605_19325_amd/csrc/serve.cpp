@@ -3,8 +3,10 @@
 // ticks (k_serve.hip) until it finishes.  One worker thread per server
 // drives the device: it replays a captured graph of a few ticks, copies the
 // slot status to pinned memory behind it and reads that copy one replay
-// later, so the device queue never drains for the host's look.  Submit and
-// poll only touch the queues under the lock.
+// later, so the device queue never drains for the host's look.  Wide
+// requests bypass the slots: a few lane threads, each with its own context
+// and stream, run them one at a time as device-wide solves beside the ticks.
+// Submit and poll only touch the queues under the lock.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -14,6 +16,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -126,6 +129,13 @@ struct enmf_server {
   hipGraphExec_t graphs[8] = {};     // per set of X storage types in flight (bit per type)
   std::vector<Running> slots;
   std::deque<Pending> pending;
+  int64_t wide_min = 3LL << 20;        // m n from which a request runs device-wide (0: never)
+  std::vector<hipStream_t> wide_streams;
+  std::vector<enmf_ctx*> wide_ctx;     // one context per lane
+  std::vector<std::thread> wide_workers;
+  std::deque<Pending> wide_pending;
+  std::set<uint64_t> wide_running;
+  std::condition_variable wcv;
   std::unordered_map<uint64_t, Result> done;
   std::mutex mu;
   std::condition_variable cv;
@@ -209,6 +219,9 @@ void fail_all(enmf_server* s, const std::string& msg) {
   r.status = ENMF_EDEVICE;
   for (auto& p : s->pending) s->done[p.ticket] = r;
   s->pending.clear();
+  for (auto& p : s->wide_pending) s->done[p.ticket] = r;
+  s->wide_pending.clear();
+  s->wcv.notify_all();
   for (auto& sl : s->slots)
     if (sl.used) {
       s->done[sl.ticket] = r;
@@ -355,6 +368,56 @@ void worker_loop(enmf_server* s) {
   }
 }
 
+// One request as a device-wide solve on the lane's context: the randomized
+// SVD init, the rotation and the iterations with the request's options (the
+// iterations measured against the init's error floor, kernels launched
+// directly, no trace).
+enmf_status solve_wide(enmf_ctx* c, const enmf_request& q, enmf_iter_report* rep) {
+  double rsvd = 0.0;
+  enmf_status st = enmf_svd_init(c, &q.X, q.r, &q.svd, q.U_out, q.V_out, nullptr, &rsvd);
+  if (st != ENMF_OK) return st;
+  st = enmf_rotate(c, q.X.m, q.X.n, q.r, q.U_out, q.V_out, &q.rot, nullptr, nullptr, nullptr, nullptr);
+  if (st != ENMF_OK) return st;
+  enmf_iter_opts it = q.it;
+  it.relerr_svd = rsvd;
+  it.graph_replay = 0;
+  return enmf_iterate(c, &q.X, q.r, q.U_out, q.V_out, &it, rep, nullptr, 0);
+}
+
+// A wide lane: takes wide requests in arrival order until the server stops
+// and nothing is left.
+void wide_loop(enmf_server* s, int lane) {
+  (void)hipSetDevice(s->device);
+  enmf_ctx* c = s->wide_ctx[lane];
+  for (;;) {
+    Pending p;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->wcv.wait(lk, [&] { return !s->wide_pending.empty() || s->stopping; });
+      if (s->wide_pending.empty()) return;
+      p = s->wide_pending.front();
+      s->wide_pending.pop_front();
+      s->wide_running.insert(p.ticket);
+    }
+    Result res{};
+    res.status = solve_wide(c, p.req, &res.rep);
+    std::string msg = res.status == ENMF_OK ? std::string() : std::string(enmf_last_error(c));
+    // the calls may leave work queued on the lane's stream (the copy of the
+    // final factors): the request is done once it has drained
+    const hipError_t e = hipStreamSynchronize(s->wide_streams[lane]);
+    if (e != hipSuccess && res.status == ENMF_OK) {
+      res.status = ENMF_EDEVICE;
+      msg = std::string("wide-lane stream: ") + hipGetErrorString(e);
+    }
+    res.latency_s = std::chrono::duration<double>(Clock::now() - p.t_submit).count();
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->wide_running.erase(p.ticket);
+    if (!msg.empty()) s->err = msg;
+    s->done[p.ticket] = res;
+    s->cv.notify_all();
+  }
+}
+
 enmf_status check_request(enmf_server* s, const enmf_request* q) {
   if (!q) return fail_srv(s, ENMF_EINVAL, "null request");
   const enmf_matrix& X = q->X;
@@ -390,7 +453,7 @@ enmf_status enmf_serve_start(enmf_ctx* c, const enmf_serve_opts* opts, enmf_serv
   if (!c) return ENMF_EINVAL;
   enmf_serve_opts o{};
   if (opts) o = *opts;
-  if (o.max_slots < 0 || o.tick_time_us < 0 || o.ticks_per_launch < 0 ||
+  if (o.max_slots < 0 || o.tick_time_us < 0 || o.ticks_per_launch < 0 || o.wide_lanes < 0 ||
       (o.direct_launch != 0 && o.direct_launch != 1))
     return ENMF_EINVAL;
   auto* s = new enmf_server();
@@ -399,6 +462,8 @@ enmf_status enmf_serve_start(enmf_ctx* c, const enmf_serve_opts* opts, enmf_serv
   s->tick_limit = (int64_t)(o.tick_time_us > 0 ? o.tick_time_us : 5000) * 100;
   s->ticks = o.ticks_per_launch > 0 ? o.ticks_per_launch : 1;
   s->direct = o.direct_launch == 1;
+  s->wide_min = o.wide_min_elems == 0 ? (3LL << 20) : (o.wide_min_elems < 0 ? 0 : o.wide_min_elems);
+  const int lanes = s->wide_min > 0 ? (o.wide_lanes > 0 ? o.wide_lanes : 2) : 0;
   const int64_t arena_bytes = o.hbm_budget_bytes > 0 ? (int64_t)o.hbm_budget_bytes : (1LL << 30);
   auto bail = [&](enmf_status st, const char* msg) {
     ctx_set_error(c, msg);
@@ -410,6 +475,8 @@ enmf_status enmf_serve_start(enmf_ctx* c, const enmf_serve_opts* opts, enmf_serv
     if (s->h_stage) (void)hipHostFree(s->h_stage);
     for (hipEvent_t ev : s->ev)
       if (ev) (void)hipEventDestroy(ev);
+    for (enmf_ctx* wc : s->wide_ctx) enmf_destroy(wc);
+    for (hipStream_t ws : s->wide_streams) (void)hipStreamDestroy(ws);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
     return st;
@@ -444,9 +511,19 @@ enmf_status enmf_serve_start(enmf_ctx* c, const enmf_serve_opts* opts, enmf_serv
   if (hipMemcpy(s->d_status, s->h_ring[0], sizeof(ServeStatus) * s->max_slots,
                 hipMemcpyHostToDevice) != hipSuccess)
     return bail(ENMF_EDEVICE, "status initialisation failed");
+  for (int l = 0; l < lanes; ++l) {
+    hipStream_t ws = nullptr;
+    if (hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess)
+      return bail(ENMF_EDEVICE, "stream creation failed");
+    s->wide_streams.push_back(ws);
+    enmf_ctx* wc = nullptr;
+    if (enmf_create(&wc, s->device, ws) != ENMF_OK) return bail(ENMF_EDEVICE, "wide-lane context creation failed");
+    s->wide_ctx.push_back(wc);
+  }
   s->arena = new Arena(arena_bytes);
   s->slots.resize(s->max_slots);
   s->worker = std::thread(worker_loop, s);
+  for (int l = 0; l < lanes; ++l) s->wide_workers.emplace_back(wide_loop, s, l);
   *out = s;
   return ENMF_OK;
 }
@@ -458,13 +535,21 @@ enmf_status enmf_serve_submit(enmf_server* s, const enmf_request* q, uint64_t* t
   if (s->failed) return fail_srv(s, ENMF_EDEVICE, s->err);
   const enmf_status v = check_request(s, q);
   if (v != ENMF_OK) return v;
+  Pending p;
+  p.req = *q;
+  p.t_submit = Clock::now();
+  if (s->wide_min > 0 && q->X.m * q->X.n >= s->wide_min) {
+    p.ticket = s->next_ticket++;
+    p.bytes = 0;
+    s->wide_pending.push_back(p);
+    *ticket = p.ticket;
+    s->wcv.notify_one();
+    return ENMF_OK;
+  }
   const int64_t bytes = layout_for(q->X.m, q->X.n, q->r + q->svd.oversample, q->r).total;
   if (bytes > s->arena->size())
     return fail_srv(s, ENMF_ENOMEM, "request workspace exceeds the serving memory budget");
-  Pending p;
   p.ticket = s->next_ticket++;
-  p.req = *q;
-  p.t_submit = Clock::now();
   p.bytes = bytes;
   s->pending.push_back(p);
   *ticket = p.ticket;
@@ -488,6 +573,9 @@ enmf_status enmf_serve_poll(enmf_server* s, uint64_t ticket, enmf_iter_report* r
     if (p.ticket == ticket) return ENMF_EBUSY;
   for (const auto& r : s->slots)
     if (r.used && r.ticket == ticket) return ENMF_EBUSY;
+  for (const auto& p : s->wide_pending)
+    if (p.ticket == ticket) return ENMF_EBUSY;
+  if (s->wide_running.count(ticket)) return ENMF_EBUSY;
   return fail_srv(s, ENMF_EINVAL, "unknown ticket");
 }
 
@@ -500,7 +588,11 @@ enmf_status enmf_serve_stop(enmf_server* s) {
     s->stopping = true;
   }
   s->cv.notify_all();
+  s->wcv.notify_all();
   if (s->worker.joinable()) s->worker.join();
+  for (std::thread& t : s->wide_workers)
+    if (t.joinable()) t.join();
+  for (enmf_ctx* wc : s->wide_ctx) enmf_destroy(wc);
   const bool failed = s->failed;
   (void)hipSetDevice(s->device);
   (void)hipStreamSynchronize(s->stream);
@@ -512,6 +604,7 @@ enmf_status enmf_serve_stop(enmf_server* s) {
   for (ServeStatus* h : {s->h_ring[0], s->h_ring[1], s->h_init}) (void)hipHostFree(h);
   (void)hipHostFree(s->h_stage);
   for (hipEvent_t ev : s->ev) (void)hipEventDestroy(ev);
+  for (hipStream_t ws : s->wide_streams) (void)hipStreamDestroy(ws);
   (void)hipStreamDestroy(s->stream);
   delete s->arena;
   delete s;

@@ -74,7 +74,8 @@ class Kkt(Structure):
 
 class ServeOpts(Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", c_int32),
-                ("tick_time_us", c_int32), ("ticks_per_launch", c_int32), ("direct_launch", c_int32)]
+                ("tick_time_us", c_int32), ("ticks_per_launch", c_int32), ("direct_launch", c_int32),
+                ("wide_min_elems", ctypes.c_int64), ("wide_lanes", c_int32), ("reserved", c_int32)]
 
 
 class Request(Structure):
@@ -488,11 +489,12 @@ class Server:
     """
 
     def __init__(self, ctx, hbm_budget_bytes=0, max_slots=0, tick_time_us=0, ticks_per_launch=0,
-                 direct_launch=0):
+                 direct_launch=0, wide_min_elems=0, wide_lanes=0):
         self._lib = ctx._lib
         self._ctx = ctx
         h = c_void_p()
-        o = ServeOpts(hbm_budget_bytes, max_slots, tick_time_us, ticks_per_launch, direct_launch)
+        o = ServeOpts(hbm_budget_bytes, max_slots, tick_time_us, ticks_per_launch, direct_launch,
+                      wide_min_elems, wide_lanes, 0)
         st = self._lib.enmf_serve_start(ctx._h, byref(o), byref(h))
         if st != 0:
             raise EnmfError(st, self._lib.enmf_last_error(ctx._h).decode())

@@ -10,7 +10,9 @@ A request gives bitwise the same factors when it runs alone, in a mix of
 uneven requests of several dtypes, under a different tick time, and with
 its ticks launched one by one instead of replayed from a captured graph.
 Requests at the large end of the stream (about 2048 x 2048, r = 30-32) meet
-the same bar as the small ones.
+the same bar as the small ones, on the tick path and on the device-wide path
+that wide requests take by default; a wide request gives bitwise the result
+of the library's own solve calls with the same options, alone or in a mix.
 Errors: r beyond the served range, a workspace that can never fit, and an
 unknown ticket.
 """
@@ -45,7 +47,8 @@ def host(t):
 
 @pytest.fixture(scope="module")
 def server(lib):
-    srv = enmf.Server(lib, hbm_budget_bytes=1 << 30, max_slots=64)
+    # every request on the tick path (one workgroup per solve), whatever its size
+    srv = enmf.Server(lib, hbm_budget_bytes=1 << 30, max_slots=64, wide_min_elems=-1)
     yield srv
     srv.stop()
 
@@ -242,7 +245,7 @@ def test_served_bf16_matrix_cores_match_float32_form(lib, server, shape):
 
 def test_serve_rejects_bad_requests(lib):
     say("serve: bad rank, workspace beyond the budget, unknown ticket")
-    srv = enmf.Server(lib, hbm_budget_bytes=1 << 20, max_slots=4)
+    srv = enmf.Server(lib, hbm_budget_bytes=1 << 20, max_slots=4, wide_min_elems=-1)
     try:
         X = to_dev(np.ones((100, 80), np.float32))
         with pytest.raises(enmf.EnmfError) as e:
@@ -255,5 +258,85 @@ def test_serve_rejects_bad_requests(lib):
         with pytest.raises(enmf.EnmfError) as e:
             srv.poll(12345)
         assert e.value.status == 1
+    finally:
+        srv.stop()
+
+
+WIDE = [(1100, 1000, 20, "bf16", 3201), (2048, 1900, 32, "bf16", 3202), (1300, 900, 12, "f32", 3203)]
+
+
+def _wide_inputs(lib, m, n, r, dt, seed):
+    X, _, _ = inputs.lowrank_plus_noise(m, n, r, seed)
+    om = inputs.omega(n, r + 10, seed + 1)
+    Xd = to_dev(X) if dt == "f32" else lib.convert(to_dev(X), torch.bfloat16)
+    return X, om, Xd
+
+
+def test_wide_requests_run_the_device_wide_solve(lib):
+    """Requests of at least wide_min_elems elements take the device-wide path:
+    each one's factors and report are bitwise those of the library's own
+    svd_init, rotate and iterate calls with the same options, when it runs
+    alone and when it is submitted among narrow requests that take slots."""
+    say("wide requests: served alone, in a mix, and the same solve called directly")
+    opts = dict(max_iter=300, relerr_tol=1e-3, kkt_tol=1e-5)
+    data = [(m, n, r, *_wide_inputs(lib, m, n, r, dt, seed)) for m, n, r, dt, seed in WIDE]
+    direct = []
+    for m, n, r, X, om, Xd in data:
+        U, V, rep = lib.solve(Xd, r, to_dev(om), **opts)
+        direct.append((host(U), host(V), rep))
+    srv = enmf.Server(lib, max_slots=16, wide_min_elems=1 << 20, wide_lanes=2)
+    try:
+        alone = []
+        for m, n, r, X, om, Xd in data:
+            t, U, V = srv.submit(Xd, r, to_dev(om), **opts)
+            res = srv.wait(t, timeout=300.0)
+            alone.append((host(U), host(V), res))
+        live, narrow = [], []
+        for i, (m, n, r, X, om, Xd) in enumerate(data):
+            for j in range(3):
+                Xs, rs, oms = _request(j, 700 + 10 * (3 * i + j))
+                narrow.append(srv.submit(lib.convert(to_dev(Xs), torch.bfloat16), rs, to_dev(oms),
+                                         oversample=oms.shape[1] - rs, max_iter=150))
+            live.append(srv.submit(Xd, r, to_dev(om), **opts))
+        mixed = []
+        for t, U, V in live:
+            res = srv.wait(t, timeout=300.0)
+            mixed.append((host(U), host(V), res))
+        for t, _, _ in narrow:
+            assert srv.wait(t)["status"] == 0
+    finally:
+        srv.stop()
+    for (m, n, r, *_), d, a, x in zip(data, direct, alone, mixed):
+        say(f"  {m}x{n} r={r}: iters {d[2]['iters']} relerr {d[2]['relerr']:.8e} "
+            f"latency alone {a[2]['latency_s']:.4f} s, in the mix {x[2]['latency_s']:.4f} s")
+        for got in (a, x):
+            assert got[2]["status"] == 0
+            assert np.array_equal(got[0], d[0]) and np.array_equal(got[1], d[1])
+            for key in ("iters", "ext_iters_done", "converged", "relerr", "f", "kkt"):
+                assert got[2][key] == d[2][key], key
+
+
+def test_wide_large_requests_match_oracle(lib):
+    """The large end of the served stream on the device-wide path meets the
+    oracle bar of the tick path: relative error within 1e-3 of the oracle's
+    (against the float32 X) and nonnegative factors."""
+    say("wide requests (bf16, ~2048 x 2048, r 30-32) vs the oracle")
+    shapes = [(2048, 1900, 32, 3101), (2000, 2000, 32, 3103)]
+    srv = enmf.Server(lib, max_slots=4)
+    try:
+        live = []
+        for m, n, r, seed in shapes:
+            X, om, Xb = _wide_inputs(lib, m, n, r, "bf16", seed)
+            t, U, V = srv.submit(Xb, r, to_dev(om), max_iter=300, relerr_tol=1e-3, kkt_tol=1e-5)
+            live.append((m, n, r, X, om, t, U, V))
+        for m, n, r, X, om, t, U, V in live:
+            res = srv.wait(t, timeout=300.0)
+            Uo, Vo, ro = O.enmf(X, r, om, max_iter=300, relerr_tol=1e-3, kkt_tol=1e-5)
+            err = O.relerr(X, host(U), host(V))
+            say(f"  {m}x{n} r={r}: iters {res['iters']} relerr {err:.6e} oracle {ro['relerr']:.6e} "
+                f"latency {res['latency_s']:.4f} s")
+            assert res["status"] == 0
+            assert abs(err - ro["relerr"]) <= 1e-3
+            assert host(U).min() >= 0 and host(V).min() >= 0
     finally:
         srv.stop()
