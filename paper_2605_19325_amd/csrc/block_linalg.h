@@ -132,6 +132,34 @@ __device__ __forceinline__ double eigvec(const JacobiT<MAXW>& sm, int a, int j) 
   return sm.E[a * JacobiT<MAXW>::LD + sm.perm[j]];
 }
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 output tile on the float64 matrix cores: acc + sum over q < N
+// of the 16 x 4 by 4 x 16 steps whose operands ld(q, a, b) reads from LDS,
+// as straight-line code (all reads issued first, each MFMA waits only for
+// its own pair).
+template <int N, typename LD>
+__device__ __forceinline__ f64x4 tile_chain(const LD& ld, f64x4 acc) {
+  double a[N], b[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) ld(q, a[q], b[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc, 0, 0, 0);
+  return acc;
+}
+
+// The same chain over n <= NK steps, n known only at run time (one
+// straight-line chain per count, chosen by wave-uniform compares).
+template <int NK, typename LD>
+__device__ __forceinline__ f64x4 tile_chain_n(int n, const LD& ld, f64x4 acc) {
+  if constexpr (NK == 0) {
+    return acc;
+  } else {
+    if (n >= NK) return tile_chain<NK>(ld, acc);
+    return tile_chain_n<NK - 1>(n, ld, acc);
+  }
+}
+
 // Polar factor of the KP x KP matrix M held in X (zero padded past kc rows
 // and columns; kc a multiple of 4), in place: the Newton-Schulz iteration
 // with the scaling of Chen and Chow (2014).  From X0 = M / ||M||_F, whose
@@ -151,7 +179,8 @@ __device__ __forceinline__ double eigvec(const JacobiT<MAXW>& sm, int a, int j) 
 //
 // Both products run on v_mfma_f64_16x16x4f64, 16 x 16 output tiles dealt
 // round robin to the NT / 64 waves of the workgroup (red: NT / 64 doubles),
-// with the contraction over the kc leading rows or columns only.  T = X^T X is
+// with the contraction over the kc leading rows or columns only, one
+// straight-line chain per tile (tile_chain_n).  T = X^T X is
 // symmetric: only its upper tiles are formed, each written to both halves.
 // Lane (i, g) = (l % 16, l / 16) supplies A[i][g] and B[g][i] of each
 // 16 x 4 by 4 x 16 step and receives D[g + 4 v][i] in accumulator element v.
@@ -164,6 +193,7 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
   constexpr int NW = NT / kWave;                // waves
   constexpr int PERW = (NTILE + NW - 1) / NW;   // tiles per wave
   constexpr int PERWS = (NSYM + NW - 1) / NW;   // upper tiles per wave
+  constexpr int NK = KP / 4;                    // contraction steps at most
   static_assert(KP % 16 == 0, "polar_ns_block needs KP a multiple of 16");
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int i = lane % 16, g = lane / 16;
@@ -183,36 +213,24 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
     // the interval's lower end has passed 0.999 (a within 5e-4 of 1).
     const bool look = l > 0.999;
     l = 0.5 * a * l * (3.0 - a * a * l * l);
-    // T = X^T X: upper tile (ti, tj) = sum over k of X[k][16 ti + i] X[k][16 tj + j].
-    // A wave's tiles advance together through k (independent MFMA chains).
-    {
-      d4 acc[PERWS];
-      int tti[PERWS], ttj[PERWS];
+    // T = X^T X: upper tile (ti, tj) = sum over k of X[k][16 ti + i] X[k][16 tj + j],
+    // each tile one MFMA chain over the kc contraction rows.
 #pragma unroll
-      for (int u = 0; u < PERWS; ++u) {
-        acc[u] = d4{0.0, 0.0, 0.0, 0.0};
-        int ti = 0, rem = w + NW * u;
-        while (ti < NTL && rem >= NTL - ti) { rem -= NTL - ti; ++ti; }
-        tti[u] = ti;
-        ttj[u] = ti + rem;
-      }
-      for (int k0 = 0; k0 < kc; k0 += 4) {
+    for (int u = 0; u < PERWS; ++u) {
+      const int tile = w + NW * u;
+      if (tile >= NSYM) break;   // wave-uniform
+      int ti = 0, rem = tile;
+      while (ti < NTL && rem >= NTL - ti) { rem -= NTL - ti; ++ti; }
+      const int tj = ti + rem;
+      const auto ld = [&](int q, double& a, double& b) {
+        a = X[4 * q + g][16 * ti + i];
+        b = X[4 * q + g][16 * tj + i];
+      };
+      const d4 acc = tile_chain_n<NK>(kc / 4, ld, d4{0.0, 0.0, 0.0, 0.0});
 #pragma unroll
-        for (int u = 0; u < PERWS; ++u) {
-          if (w + NW * u < NSYM)
-            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[k0 + g][16 * tti[u] + i], X[k0 + g][16 * ttj[u] + i],
-                                                          acc[u], 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < PERWS; ++u) {
-        if (w + NW * u < NSYM) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            T[16 * tti[u] + g + 4 * v][16 * ttj[u] + i] = acc[u][v];
-            if (tti[u] != ttj[u]) T[16 * ttj[u] + i][16 * tti[u] + g + 4 * v] = acc[u][v];
-          }
-        }
+      for (int v = 0; v < 4; ++v) {
+        T[16 * ti + g + 4 * v][16 * tj + i] = acc[v];
+        if (ti != tj) T[16 * tj + i][16 * ti + g + 4 * v] = acc[v];
       }
     }
     __syncthreads();
@@ -223,16 +241,16 @@ __device__ bool polar_ns_block(double (*X)[KP + 1], double (*T)[KP + 1], double*
       d4 acc[PERW];
 #pragma unroll
       for (int u = 0; u < PERW; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < kc; k0 += 4) {
 #pragma unroll
-        for (int u = 0; u < PERW; ++u) {
-          const int tile = w + NW * u;
-          if (tile < NTILE) {
-            const int ti = tile / NTL, tj = tile % NTL;
-            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[16 * ti + i][k0 + g], T[k0 + g][16 * tj + i],
-                                                          acc[u], 0, 0, 0);
-          }
-        }
+      for (int u = 0; u < PERW; ++u) {
+        const int tile = w + NW * u;
+        if (tile >= NTILE) break;   // wave-uniform
+        const int ti = tile / NTL, tj = tile % NTL;
+        const auto ld = [&](int q, double& a, double& b) {
+          a = X[16 * ti + i][4 * q + g];
+          b = T[4 * q + g][16 * tj + i];
+        };
+        acc[u] = tile_chain_n<NK>(kc / 4, ld, acc[u]);
       }
 #pragma unroll
       for (int u = 0; u < PERW; ++u) {
