@@ -338,6 +338,7 @@ __global__ void k_rho_init(const double* __restrict__ part, int nparts, int64_t 
 template <int KP> struct AdmmGeom {
   static constexpr int CG = KP / 8;        // threads per row
   static constexpr int RB = kT / CG;       // rows per row block
+  static_assert(RB * KP <= 8 * kT, "a row block holds at most 8 state entries per thread");
 };
 
 template <int KP>
@@ -372,6 +373,16 @@ __global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, 
   for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
     const int64_t row0 = rb * AG::RB;
     const int64_t nrow = N - row0 < AG::RB ? N - row0 : AG::RB;
+    const int cnt = (int)nrow * KP;
+    double* Sb = S + row0 * KP;
+    // the state entries this thread updates below (at most 8: RB KP <= 8 kT),
+    // read now so that their latency overlaps the staging and W R
+    double sv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = threadIdx.x + q * kT;
+      sv[q] = step > 0 && e < cnt ? Sb[e] : 0.0;
+    }
     __syncthreads();
     for (int e = threadIdx.x; e < RBP * KP; e += kT) {
       Ws[e] = e < nrow * KP ? W[row0 * KP + e] : 0.0;
@@ -395,15 +406,17 @@ __global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, 
       for (int e = 0; e < 8; ++e) Bs[rr * KP + c0 + e] = wr[e];
     }
     __syncthreads();
-    const int cnt = (int)nrow * KP;
-    double* Sb = S + row0 * KP;
-    for (int e = threadIdx.x; e < cnt; e += kT) {
-      const double w = Bs[e];
-      const double y = step > 0 ? Sb[e] - rho * w : 0.0;
-      const double b = w - y * irho;
-      const double z = b > 0.0 ? b : (b >= -irho ? 0.0 : b + irho);
-      Sb[e] = y + rho * z;
-      Bs[e] = z + y * irho;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = threadIdx.x + q * kT;
+      if (e < cnt) {
+        const double w = Bs[e];
+        const double y = step > 0 ? sv[q] - rho * w : 0.0;
+        const double b = w - y * irho;
+        const double z = b > 0.0 ? b : (b >= -irho ? 0.0 : b + irho);
+        Sb[e] = y + rho * z;
+        Bs[e] = z + y * irho;
+      }
     }
     __syncthreads();
     if constexpr (MF) {
@@ -415,7 +428,7 @@ __global__ __launch_bounds__(kT) void k_admm_rows(const double* __restrict__ W, 
         const int tile = wv + 4 * u;
         if (tile < NTILE) {
           const int ti = tile / NTL, tj = tile % NTL;
-#pragma unroll 4
+#pragma unroll
           for (int k0 = 0; k0 < RBP; k0 += 4)
             macc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ws[(k0 + lg) * KP + 16 * ti + li],
                                                            Bs[(k0 + lg) * KP + 16 * tj + li], macc[u],
