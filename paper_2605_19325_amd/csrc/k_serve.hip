@@ -1231,6 +1231,32 @@ __global__ __launch_bounds__(SNT) void k_serve_tick(ServeSlot* __restrict__ slot
 
 }  // namespace
 
+namespace {
+
+// Admission batch: workgroup b copies staged record b into its slot's record
+// head and status (8-byte words).
+__global__ __launch_bounds__(256) void k_serve_admit(const ServeAdmit* __restrict__ staged,
+                                                     ServeSlot* __restrict__ slots,
+                                                     ServeStatus* __restrict__ status) {
+  const ServeAdmit& a = staged[blockIdx.x];
+  const int slot = a.slot;
+  const uint64_t* hs = reinterpret_cast<const uint64_t*>(a.head);
+  uint64_t* hd = reinterpret_cast<uint64_t*>(slots + slot);
+  for (int w = threadIdx.x; w < (int)(kSlotHeadBytes / 8); w += blockDim.x) hd[w] = hs[w];
+  const uint64_t* ss = reinterpret_cast<const uint64_t*>(&a.status);
+  uint64_t* sd = reinterpret_cast<uint64_t*>(status + slot);
+  for (int w = threadIdx.x; w < (int)(sizeof(ServeStatus) / 8); w += blockDim.x) sd[w] = ss[w];
+}
+
+}  // namespace
+
+hipError_t launch_serve_admit(const ServeAdmit* staged, int count, ServeSlot* slots, ServeStatus* status,
+                              hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_serve_admit, dim3(count), dim3(256), 0, s, staged, slots, status);
+  return hipGetLastError();
+}
+
 hipError_t launch_serve_tick(int xt, ServeSlot* slots, ServeStatus* status, int nslots,
                              int64_t time_limit, hipStream_t s) {
   if (nslots < 1) return hipSuccess;

@@ -123,6 +123,10 @@ struct enmf_server {
   ServeStatus* h_ring[2] = {nullptr, nullptr};   // pinned status copies of alternate replays
   ServeStatus* h_init = nullptr;     // pinned: the status each newly admitted slot starts from
   ServeSlot* h_stage = nullptr;      // pinned staging of newly admitted slots, one per slot
+  ServeAdmit* h_admit[2] = {nullptr, nullptr};   // pinned admission batches, used in turn
+  hipEvent_t admit_ev[2] = {nullptr, nullptr};   // recorded after each batch's upload
+  int admit_buf = 0;
+  ServeAdmit* d_admit = nullptr;     // the batch on the device (one, read in stream order)
   hipEvent_t ev[2] = {nullptr, nullptr};
   int ticks = 4;                     // ticks per replay
   bool direct = false;               // launch the ticks one by one instead of replaying a graph
@@ -308,15 +312,26 @@ void worker_loop(enmf_server* s) {
         s->cv.wait(lk);
       }
     }
-    // upload the new slots and mark them running (ordered before the next replay)
+    // upload the new slots and mark them running (ordered before the next
+    // replay): one batch copy and one scatter launch, the pinned batch buffer
+    // reused once the upload that last read it has run
     hipError_t e = hipSuccess;
-    for (size_t i = 0; i < fresh.size() && e == hipSuccess; ++i) {
-      const int slot = fresh[i];
-      e = hipMemcpyAsync(s->d_slots + slot, &s->h_stage[slot], offsetof(ServeSlot, s) + sizeof(ServeScalars),
-                         hipMemcpyHostToDevice, s->stream);
+    if (!fresh.empty()) {
+      const int buf = s->admit_buf;
+      s->admit_buf ^= 1;
+      e = hipEventSynchronize(s->admit_ev[buf]);
+      ServeAdmit* ha = s->h_admit[buf];
+      for (size_t i = 0; i < fresh.size(); ++i) {
+        const int slot = fresh[i];
+        ha[i].slot = slot;
+        ha[i].status = s->h_init[slot];
+        std::memcpy(ha[i].head, &s->h_stage[slot], kSlotHeadBytes);
+      }
       if (e == hipSuccess)
-        e = hipMemcpyAsync(s->d_status + slot, &s->h_init[slot], sizeof(ServeStatus),
-                           hipMemcpyHostToDevice, s->stream);
+        e = hipMemcpyAsync(s->d_admit, ha, fresh.size() * sizeof(ServeAdmit), hipMemcpyHostToDevice,
+                           s->stream);
+      if (e == hipSuccess) e = launch_serve_admit(s->d_admit, (int)fresh.size(), s->d_slots, s->d_status, s->stream);
+      if (e == hipSuccess) e = hipEventRecord(s->admit_ev[buf], s->stream);
     }
     int launched = -1;
     if (mask && e == hipSuccess) {
@@ -469,11 +484,16 @@ enmf_status enmf_serve_start(enmf_ctx* c, const enmf_serve_opts* opts, enmf_serv
     ctx_set_error(c, msg);
     if (s->d_slots) (void)hipFree(s->d_slots);
     if (s->d_status) (void)hipFree(s->d_status);
+    if (s->d_admit) (void)hipFree(s->d_admit);
     if (s->arena_base) (void)hipFree(s->arena_base);
     for (ServeStatus* h : {s->h_ring[0], s->h_ring[1], s->h_init})
       if (h) (void)hipHostFree(h);
     if (s->h_stage) (void)hipHostFree(s->h_stage);
+    for (ServeAdmit* h : s->h_admit)
+      if (h) (void)hipHostFree(h);
     for (hipEvent_t ev : s->ev)
+      if (ev) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : s->admit_ev)
       if (ev) (void)hipEventDestroy(ev);
     for (enmf_ctx* wc : s->wide_ctx) enmf_destroy(wc);
     for (hipStream_t ws : s->wide_streams) (void)hipStreamDestroy(ws);
@@ -490,19 +510,24 @@ enmf_status enmf_serve_start(enmf_ctx* c, const enmf_serve_opts* opts, enmf_serv
     return bail(ENMF_ENOMEM, "serving arena allocation failed");
   }
   if (hipMalloc(&s->d_slots, sizeof(ServeSlot) * s->max_slots) != hipSuccess ||
-      hipMalloc(&s->d_status, sizeof(ServeStatus) * s->max_slots) != hipSuccess) {
+      hipMalloc(&s->d_status, sizeof(ServeStatus) * s->max_slots) != hipSuccess ||
+      hipMalloc(&s->d_admit, sizeof(ServeAdmit) * s->max_slots) != hipSuccess) {
     (void)hipGetLastError();
     return bail(ENMF_ENOMEM, "serving slot allocation failed");
   }
   if (hipHostMalloc(&s->h_ring[0], sizeof(ServeStatus) * s->max_slots) != hipSuccess ||
       hipHostMalloc(&s->h_ring[1], sizeof(ServeStatus) * s->max_slots) != hipSuccess ||
       hipHostMalloc(&s->h_init, sizeof(ServeStatus) * s->max_slots) != hipSuccess ||
-      hipHostMalloc(&s->h_stage, sizeof(ServeSlot) * s->max_slots) != hipSuccess) {
+      hipHostMalloc(&s->h_stage, sizeof(ServeSlot) * s->max_slots) != hipSuccess ||
+      hipHostMalloc(&s->h_admit[0], sizeof(ServeAdmit) * s->max_slots) != hipSuccess ||
+      hipHostMalloc(&s->h_admit[1], sizeof(ServeAdmit) * s->max_slots) != hipSuccess) {
     (void)hipGetLastError();
     return bail(ENMF_ENOMEM, "pinned host allocation failed");
   }
   if (hipEventCreateWithFlags(&s->ev[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&s->ev[1], hipEventDisableTiming) != hipSuccess)
+      hipEventCreateWithFlags(&s->ev[1], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->admit_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->admit_ev[1], hipEventDisableTiming) != hipSuccess)
     return bail(ENMF_EDEVICE, "event creation failed");
   // every slot starts idle; a newly admitted slot's status is uploaded from h_init
   std::memset(s->h_init, 0, sizeof(ServeStatus) * s->max_slots);
@@ -600,10 +625,13 @@ enmf_status enmf_serve_stop(enmf_server* s) {
     if (g) (void)hipGraphExecDestroy(g);
   (void)hipFree(s->d_slots);
   (void)hipFree(s->d_status);
+  (void)hipFree(s->d_admit);
   (void)hipFree(s->arena_base);
   for (ServeStatus* h : {s->h_ring[0], s->h_ring[1], s->h_init}) (void)hipHostFree(h);
   (void)hipHostFree(s->h_stage);
+  for (ServeAdmit* h : s->h_admit) (void)hipHostFree(h);
   for (hipEvent_t ev : s->ev) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : s->admit_ev) (void)hipEventDestroy(ev);
   for (hipStream_t ws : s->wide_streams) (void)hipStreamDestroy(ws);
   (void)hipStreamDestroy(s->stream);
   delete s->arena;

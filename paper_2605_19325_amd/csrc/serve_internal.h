@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace enmf {
@@ -64,6 +65,27 @@ struct ServeStatus {
   int32_t status, stage, iters, ext_done, converged, phase, rot_steps, numeric_error;
   double f, relerr, kkt, kkt_feas, kkt_pg_u, kkt_pg_v, delta_w, sigma_w, step_u, step_v, relerr_svd;
 };
+
+// Bytes of a slot record the host writes at admission: the request and the
+// scalar progress (the rest of the state is written by the solve itself).
+constexpr size_t kSlotHeadBytes = offsetof(ServeSlot, s) + sizeof(ServeScalars);
+static_assert(kSlotHeadBytes % 8 == 0 && sizeof(ServeStatus) % 8 == 0, "records copied in 8-byte words");
+
+// One newly admitted solve as uploaded in a batch: its slot, its starting
+// status and the head of its slot record.
+struct ServeAdmit {
+  int32_t slot, pad0;
+  ServeStatus status;
+  unsigned char head[kSlotHeadBytes];
+};
+static_assert(offsetof(ServeAdmit, status) % 8 == 0 && offsetof(ServeAdmit, head) % 8 == 0 &&
+                  sizeof(ServeAdmit) % 8 == 0,
+              "admission records copied in 8-byte words");
+
+// Copy `count` staged admissions (device) into their slot records and
+// statuses, one workgroup per admission.
+hipError_t launch_serve_admit(const ServeAdmit* staged, int count, ServeSlot* slots, ServeStatus* status,
+                              hipStream_t s);
 
 // Launch one tick over nslots slots for X stored as xt (ENMF_F32/BF16/F16);
 // slots of another storage type or not running are skipped.  A slot runs
