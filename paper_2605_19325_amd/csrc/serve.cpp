@@ -417,8 +417,8 @@ void wide_loop(enmf_server* s, int lane) {
     Result res{};
     res.status = solve_wide(c, p.req, &res.rep);
     std::string msg = res.status == ENMF_OK ? std::string() : std::string(enmf_last_error(c));
-    // the calls may leave work queued on the lane's stream (the copy of the
-    // final factors): the request is done once it has drained
+    // the request is reported done only once nothing it queued on the
+    // lane's stream can still be running
     const hipError_t e = hipStreamSynchronize(s->wide_streams[lane]);
     if (e != hipSuccess && res.status == ENMF_OK) {
       res.status = ENMF_EDEVICE;
