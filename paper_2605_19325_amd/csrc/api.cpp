@@ -979,8 +979,8 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
       }
     }
     // X^T U^(k+1) runs before the check of iteration k.  The decision is
-    // taken by the matrix-core product's first block, else at the head of the
-    // V pass; either way the V pass leaves V^k in place on a stop.
+    // taken by a side workgroup of the matrix-core product, else at the head
+    // of the V pass; either way the V pass leaves V^k in place on a stop.
     TRY(xtu_parts(c, X, Ub[prev], r, b.Q, &pp, devk ? nullptr : sample(1, k), mf, &gjH,
                   mf ? &dec : nullptr));
     const int vdec = mf ? 0 : kRowDecide;

@@ -2,7 +2,8 @@
 // the stopping rule of Algorithm 3), taken by one whole workgroup from the
 // per-block check records of both halves, and the phase decision at the start
 // of an iteration.  Shared by the row passes and the matrix-core X^T U product,
-// which takes the check as a side job in its first block.
+// which takes the check as a side job (in its first workgroup, or for
+// bfloat16 X in a workgroup of its own after the streaming ones).
 #pragma once
 
 #include <math.h>

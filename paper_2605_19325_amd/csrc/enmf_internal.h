@@ -157,8 +157,9 @@ hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t l
                           int do_pack, int* nsplit = nullptr, const int32_t* stop = nullptr,
                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                           const GramJob* gj = nullptr);
-// dec (with st): the check and stop decision of the iteration, taken by the
-// first block as a side job (the row pass that follows then skips it).
+// dec (with st): the check and stop decision of the iteration, taken as a side
+// job (the row pass that follows then skips it): by the first block, or for
+// bfloat16 X, together with gj's Gram combine, by an extra grid row.
 hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* A,
                            int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
                            int do_pack, int* nsplit = nullptr, const int32_t* stop = nullptr,

@@ -360,6 +360,34 @@ __global__ __launch_bounds__(kT) void k_xv_f32s(const float* __restrict__ X, int
     for (int nt = 0; nt < NT; ++nt) store_tile_rows(o, m, k, row0 + 16 * rt, 16 * nt, acc[rt][nt]);
 }
 
+// Side jobs of the bfloat16 X^T A launch (the stop decision and a Gram
+// combine), when it carries them, run in one extra row of workgroups at the
+// end of the grid, which the dispatcher hands out after every streaming
+// workgroup: block 0 of the row takes the check and stop decision of the
+// iteration, the others the Gram combine (one entry group per wave; all of
+// the row when it has one block).  Returns true in that row.  (The float32
+// kernels keep their side jobs in their first workgroups, where the Gram
+// combine overlaps the first chunk loads: the extra row measured slower for
+// them and about 1% faster for bfloat16 X at the ratings shape.)
+__device__ __forceinline__ bool xtu_side_row(const double* __restrict__ gsrc, int gparts, int gkp,
+                                             double* __restrict__ gdst, const DecideArgs& dec,
+                                             DevState* dst) {
+  if ((gsrc == nullptr && dst == nullptr) || blockIdx.y != gridDim.y - 1) return false;
+  const int w = threadIdx.x / kWave;
+  if (dst != nullptr && blockIdx.x == 0) {
+    __shared__ double dsh[17 * (kT / kWave)];
+    __shared__ int dflag;
+    (void)check_decide<kT>(dec, 0, dst, true, dsh, &dflag);
+  }
+  if (gsrc != nullptr) {
+    const int g0 = (dst != nullptr && gridDim.x > 1) ? 1 : 0;
+    if ((int)blockIdx.x >= g0)
+      gram_combine(gsrc, gparts, gkp, gdst, (int64_t)(blockIdx.x - g0) * (kT / kWave) + w,
+                   (int64_t)(gridDim.x - g0) * (kT / kWave));
+  }
+  return true;
+}
+
 // ---------------------------------------------------------------------------
 // bfloat16 X: Q = X^T A with A = Ahi + Amid + Alo.  Block = 4 waves x 128 columns;
 // chunk = 32 rows (one MFMA step).  Lane (i, g) loads the 8 x 8 block
@@ -382,13 +410,7 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
     const double* __restrict__ gsrc, int gparts, int gkp, double* __restrict__ gdst,
     DecideArgs dec, DevState* dst) {
   if (stop != nullptr && *stop) return;
-  // side job of the first block, before its own loads: the check and stop
-  // decision of the iteration (the blocks that start later see a stop and return)
-  if (dst != nullptr && blockIdx.x == 0 && blockIdx.y == 0) {
-    __shared__ double dsh[17 * (kT / kWave)];
-    __shared__ int dflag;
-    (void)check_decide<kT>(dec, 0, dst, true, dsh, &dflag);
-  }
+  if (xtu_side_row(gsrc, gparts, gkp, gdst, dec, dst)) return;
   constexpr int NT = KP / 16;
   constexpr int CH = 3 * KP * kAtLd;    // LDS elements of one chunk
   constexpr int CHG = 3 * KP * kAtG;    // global elements of one chunk
@@ -444,9 +466,6 @@ __global__ __launch_bounds__(kT) void k_xtu_bf16(const unsigned short* __restric
     fetch_a(c0);
     load_x(c0, xa);
   }
-  // side job: a Gram combine, one entry per wave, its loads behind the first chunk's
-  const int64_t gwave = ((int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y) * (kT / kWave) + w;
-  if (gsrc != nullptr) gram_combine(gsrc, gparts, gkp, gdst, gwave, (int64_t)gridDim.x * gridDim.y * (kT / kWave));
   if (c0 < c1) store_a(0);
   int buf = 0;
   for (int64_t ch = c0; ch < c1; ++ch) {
@@ -967,7 +986,9 @@ hipError_t launch_xtu_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t 
     const int64_t cps = pl.cps;
     eff = pl.splits;
     float* dst = eff > 1 ? part : out;
-    dim3 grid((unsigned)tiles, (unsigned)eff);
+    // side jobs, if any, in one more grid row (xtu_side_row)
+    const unsigned side = (gsrc != nullptr || dst_state != nullptr) ? 1u : 0u;
+    dim3 grid((unsigned)tiles, (unsigned)eff + side);
     const unsigned short* Xb = reinterpret_cast<const unsigned short*>(X);
     const unsigned short* At = reinterpret_cast<const unsigned short*>(pack);
     if (ev0) (void)hipEventRecord(ev0, s);
