@@ -45,9 +45,9 @@ XT_MIN_BYTES = 512 << 20     # X at least this large: enmf_iterate runs X B on a
 # passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters' reading for a device copy of
 # known size (profiles/k_xtu_ratings_100000x20000_r20_hbm_traffic.txt).  They describe the
 # kernel source they were taken on and are reported only while it is unchanged.
-TRAFFIC = {"k_mfma_sha256_16": "50dc824cd3a34e79",
-           "k_xtu_bf16 (X^T A)": 4475.55e6, "k_xtu_bf16 (X B on the transposed copy)": 4343.69e6,
-           "k_xtu_f32s (X^T A)": 8200.38e6, "k_xtu_f32s (X B on the transposed copy)": 8082.46e6}
+TRAFFIC = {"k_mfma_sha256_16": "32dc41465121a157",
+           "k_xtu_bf16 (X^T A)": 4478.14e6, "k_xtu_bf16 (X B on the transposed copy)": 4346.73e6,
+           "k_xtu_f32s (X^T A)": 8200.33e6, "k_xtu_f32s (X B on the transposed copy)": 8082.45e6}
 
 
 def parse():
