@@ -57,7 +57,9 @@ typedef enum { ENMF_F32 = 0, ENMF_BF16 = 1, ENMF_F16 = 2, ENMF_CSR = 3 } enmf_dt
 typedef struct enmf_ctx enmf_ctx;
 
 /* Data matrix X (eq. 1).  data: device pointer to m rows of ld elements of
- * the given dtype; only the first n of each row are read.  X >= 0.
+ * the given dtype; only the first n of each row are read.  X >= 0.  Rows
+ * that start on 128-byte lines (ld * element size a multiple of 128) are
+ * streamed without fetching lines that straddle two rows' runs. 
  * dtype ENMF_CSR: data is an enmf_sparse handle (below) made on the same
  * device, m and n are its shape and ld is ignored. */
 typedef struct {

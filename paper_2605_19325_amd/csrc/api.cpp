@@ -910,7 +910,10 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
   XTCopy xtc;
   const bool tx = use_xt(c, X, r);
   if (tx) {
-    const int64_t ldt = round_up(m, 8);
+    // rows of the copy start on 128-byte lines (64 elements covers both
+    // storage widths): a row pitch that is an odd multiple of 64 bytes makes
+    // every other row's runs straddle one more line than they cover
+    const int64_t ldt = round_up(m, 64);
     WS(xtb, unsigned char, S_XT, (size_t)n * ldt * esize(X->dtype));
     CK(launch_transpose(X->data, X->dtype, m, n, X->ld, xtb, ldt, s));
     xtc.data = xtb;

@@ -211,6 +211,24 @@ def matrix(X):
     return Matrix(X.data_ptr(), X.shape[0], X.shape[1], X.stride(0), _DTYPES[X.dtype], 0)
 
 
+def pitched(X):
+    """Copy of a 2-D CUDA tensor whose rows start on 128-byte lines (leading
+    dimension rounded up to 128 bytes), returned as the m x n view.  Rows of a
+    pitch that is an odd multiple of 64 bytes (n = 10000 in float32, n = 20000
+    in 16-bit storage) make every other row's runs straddle one more line
+    than they cover, and the streaming products fetch those lines too."""
+    _dev(X, "X")
+    if X.dim() != 2:
+        raise ValueError("X must be a 2-D tensor")
+    m, n = X.shape
+    per = 128 // X.element_size()
+    ld = (n + per - 1) // per * per
+    buf = torch.empty((m, ld), dtype=X.dtype, device=X.device)
+    out = buf[:, :n]
+    out.copy_(X)
+    return out
+
+
 def pack_mask(observed):
     """Bit mask of the observed entries in the layout of enmf_mask: bit j % 32
     of word [i][j / 32] (numpy bool array in, int32 numpy array of shape
@@ -286,7 +304,9 @@ class Context:
         if X32.dtype != torch.float32 or X32.dim() != 2 or X32.stride(1) != 1:
             raise ValueError("X32 must be a 2-D float32 tensor with unit column stride")
         m, n = X32.shape
-        ld = (n + 7) // 8 * 8
+        # each row starts on a 128-byte line, so the products' row runs fetch
+        # no line they do not use
+        ld = (n + 63) // 64 * 64
         buf = torch.empty((m, ld), dtype=dtype, device=X32.device)
         self._call(self._lib.enmf_convert, _ptr(X32), m, n, X32.stride(0), _DTYPES[dtype], _ptr(buf), ld)
         return buf[:, :n]

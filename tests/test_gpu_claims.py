@@ -71,6 +71,30 @@ def test_iterate_is_bitwise_repeatable(lib, problem):
         assert r1[key] == r2[key], key
 
 
+@pytest.mark.parametrize("dt", [torch.float32, torch.bfloat16], ids=["f32", "bf16"])
+def test_iterate_independent_of_pitch(lib, problem, dt):
+    """X with its rows on 128-byte lines (enmf.pitched) gives bitwise the
+    factors and report of the same values at the tight pitch: the pitch
+    changes which lines a product fetches, not what it adds up or in what
+    order."""
+    X, r, U0, V0, rso = problem
+    Xd = to_dev(X)
+    if dt == torch.bfloat16:
+        Xd = lib.convert(Xd, dt).contiguous()
+    Xp = enmf.pitched(Xd)
+    say(f"pitch {X.shape} r={r} {dt}: ld {Xd.stride(0)} against {Xp.stride(0)}")
+    assert Xp.stride(0) * Xp.element_size() % 128 == 0 and torch.equal(Xp, Xd)
+    outs = []
+    for Xa in (Xd, Xp):
+        U, V = to_dev(U0), to_dev(V0)
+        rep = lib.iterate(Xa, U, V, max_iter=40, relerr_svd=rso)
+        outs.append((U, V, rep))
+    (U1, V1, r1), (U2, V2, r2) = outs
+    assert torch.equal(U1, U2) and torch.equal(V1, V2)
+    for key in ("f", "kkt", "relerr", "iters", "ext_iters_done"):
+        assert r1[key] == r2[key], key
+
+
 def test_iterate_resume(lib, problem):
     X, r, U0, V0, rso = problem
     say(f"resume {X.shape} r={r}: 200 iterations against 100 + 100")
