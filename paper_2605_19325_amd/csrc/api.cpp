@@ -244,7 +244,8 @@ struct Parts {
 // as a launch of its own after it).
 enmf_status xv_parts(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, float* P_out,
                      Parts* out, hipEvent_t* ev = nullptr, bool packed = false,
-                     const GramJob* gj = nullptr, const XTCopy* xt = nullptr) {
+                     const GramJob* gj = nullptr, const XTCopy* xt = nullptr,
+                     const float* prepadded = nullptr) {
   hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
   int ns = 1;
   if (xt != nullptr && xt->data != nullptr) {
@@ -272,17 +273,20 @@ enmf_status xv_parts(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, f
     out->p = ns > 1 ? part : P_out;
   } else {
     const int kp = pad_width(k);
-    const int64_t rows_pad = round_up(X->n, xv_tile_width(X->dtype));
-    WS(Bp, float, S_BP, rows_pad * kp * 4);
-    CK(launch_pad_rows_cols(B, X->n, k, kp, rows_pad, Bp, c->stream));
+    const float* Bp = prepadded;
+    if (Bp == nullptr) {
+      const int64_t rows_pad = round_up(X->n, xv_tile_width(X->dtype));
+      WS(Bw, float, S_BP, rows_pad * kp * 4);
+      CK(launch_pad_rows_cols(B, X->n, k, kp, rows_pad, Bw, c->stream));
+      Bp = Bw;
+    }
     const int splits = xv_splits(X->m, X->n, X->dtype);
     WS(part, float, S_SPLIT, (int64_t)splits * X->m * k * 4);
     if (e0) CK(hipEventRecord(e0, c->stream));
     CK(launch_xv(X->data, X->dtype, X->m, X->n, X->ld, Bp, k, kp, splits, part, P_out, c->stream, 0,
-                 &ns));
+                 &ns, gj));
     if (e1) CK(hipEventRecord(e1, c->stream));
     out->p = ns > 1 ? part : P_out;
-    if (gj) CK(launch_gram_fin(gj->src, gj->nparts, gj->kp, gj->dst, c->stream));
   }
   out->n = ns;
   out->stride = X->m * k;
@@ -294,7 +298,8 @@ enmf_status xv_parts(enmf_ctx* c, const enmf_matrix* X, const float* B, int k, f
 // matrix-core product (see launch_xtu_mfma); ignored by the other forms.
 enmf_status xtu_parts(enmf_ctx* c, const enmf_matrix* X, const float* A, int k, float* Q_out,
                       Parts* out, hipEvent_t* ev = nullptr, bool packed = false,
-                      const GramJob* gj = nullptr, const DecideArgs* dec = nullptr) {
+                      const GramJob* gj = nullptr, const DecideArgs* dec = nullptr,
+                      const float* prepadded = nullptr) {
   hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
   int ns = 1;
   if (const SparseX* sp = sparse_of(X)) {
@@ -313,16 +318,19 @@ enmf_status xtu_parts(enmf_ctx* c, const enmf_matrix* X, const float* A, int k, 
     out->p = ns > 1 ? part : Q_out;
   } else {
     const int kp = pad_width(k);
-    WS(Ap, float, S_AP, X->m * kp * 4);
-    CK(launch_pad_cols(A, X->m, k, kp, Ap, c->stream));
+    const float* Ap = prepadded;
+    if (Ap == nullptr) {
+      WS(Aw, float, S_AP, X->m * kp * 4);
+      CK(launch_pad_cols(A, X->m, k, kp, Aw, c->stream));
+      Ap = Aw;
+    }
     const int splits = xtu_splits(X->m, X->n);
     WS(part, float, S_SPLIT, (int64_t)splits * X->n * k * 4);
     if (e0) CK(hipEventRecord(e0, c->stream));
     CK(launch_xtu(X->data, X->dtype, X->m, X->n, X->ld, Ap, k, kp, splits, part, Q_out, c->stream, 0,
-                  &ns));
+                  &ns, gj));
     if (e1) CK(hipEventRecord(e1, c->stream));
     out->p = ns > 1 ? part : Q_out;
-    if (gj) CK(launch_gram_fin(gj->src, gj->nparts, gj->kp, gj->dst, c->stream));
   }
   out->n = ns;
   out->stride = X->n * k;
@@ -934,6 +942,20 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
     poU.p = ap;
     mfma_pack_layout(X->dtype, 1, r, &poU.kp, &poU.c, &poU.ldt);
   }
+  // vector-ALU products: the row passes also write U and V zero-padded to the
+  // products' width (rows of V up to the X B tile width), so no padding
+  // launch precedes each product; the padding rows and columns stay zero
+  float* padU = nullptr;
+  float* padV = nullptr;
+  if (!mf && !tx && X->dtype != ENMF_CSR && pad_width(r) == kp) {
+    const int64_t rows_pad = round_up(n, xv_tile_width(X->dtype));
+    WS(pv, float, S_BP, rows_pad * kp * 4);
+    WS(pu, float, S_AP, m * kp * 4);
+    CK(launch_pad_rows_cols(V, n, r, kp, rows_pad, pv, s));
+    CK(launch_pad_cols(U, m, r, kp, pu, s));
+    padV = poV.pad = pv;
+    padU = poU.pad = pu;
+  }
 
   TRY(ensure_stop_copy(c));
   bool stop_copied = false;
@@ -951,7 +973,7 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
   gjH.src = b.gpU; gjH.nparts = b.nbU; gjH.kp = kp; gjH.dst = b.H;
   CK(launch_rowupdate(U, U, m, r, kp, nullptr, 1, 0, nullptr, st, 0, 0, kRowGram, b.recU(1), b.gpU,
                       nullptr, 0, nullptr, 0, s, poU));
-  TRY(xtu_parts(c, X, U, r, b.Q, &pp, nullptr, mf, &gjH));
+  TRY(xtu_parts(c, X, U, r, b.Q, &pp, nullptr, mf, &gjH, nullptr, padU));
   CK(launch_rowupdate(V, V, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, 0,
                       kRowGram | kRowWriteCheck, b.recV(1), b.gpV, nullptr, 0, nullptr, 0, s, poV));
   // One outer iteration k < max_iter, enqueued on c->stream.  devk: the
@@ -966,7 +988,7 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
     dec.recU = b.recU(cur); dec.nbU = b.nbU;
     dec.recV = b.recV(prev); dec.nbV = b.nbV;
     dec.k = devk ? -1 : k; dec.due = due ? 1 : 0; dec.trace = trace;
-    TRY(xv_parts(c, X, V, r, b.P, &pp, devk ? nullptr : sample(0, k), mf, &gjG, xtp));
+    TRY(xv_parts(c, X, V, r, b.P, &pp, devk ? nullptr : sample(0, k), mf, &gjG, xtp, padV));
     const int head = kRowHead | kRowCheckPre | (due ? kRowWriteCheck : 0);
     if (fixed) {
       CK(launch_rowupdate(Ub[cur], Ub[prev], m, r, kp, pp.p, pp.n, pp.stride, b.G, st, 0,
@@ -985,7 +1007,7 @@ enmf_status enmf_iterate(enmf_ctx* c, const enmf_matrix* X, int32_t r, float* U,
     // taken by a side workgroup of the matrix-core product, else at the head
     // of the V pass; either way the V pass leaves V^k in place on a stop.
     TRY(xtu_parts(c, X, Ub[prev], r, b.Q, &pp, devk ? nullptr : sample(1, k), mf, &gjH,
-                  mf ? &dec : nullptr));
+                  mf ? &dec : nullptr, padU));
     const int vdec = mf ? 0 : kRowDecide;
     if (fixed) {
       CK(launch_rowupdate(V, V, n, r, kp, pp.p, pp.n, pp.stride, b.H, st, 1, o.pbcd_max_iter,

@@ -120,12 +120,21 @@ hipError_t launch_pad_cols_f64(const float* in, int64_t rows, int k, int kp, dou
 // `reduce` = 0 launches only the streaming kernel (split partials are left in part).
 // With reduce = 0 and nsplit != nullptr the product is left as *nsplit
 // partials (part when *nsplit > 1, else out) of stride rows * k.
+
+// A Gram combine (gram_combine) a product runs on the side:
+// dst (kp x kp) = sum of the nparts partial Grams at src.
+struct GramJob {
+  const double* src = nullptr;
+  int nparts = 0, kp = 0;
+  double* dst = nullptr;
+};
+// With gj, the Gram combine runs as a side job in one more grid row.
 hipError_t launch_xv(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* Bp, int k,
                      int kp, int splits, float* part, float* out, hipStream_t s, int reduce = 1,
-                     int* nsplit = nullptr);
+                     int* nsplit = nullptr, const GramJob* gj = nullptr);
 hipError_t launch_xtu(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* Ap, int k,
                       int kp, int splits, float* part, float* out, hipStream_t s, int reduce = 1,
-                      int* nsplit = nullptr);
+                      int* nsplit = nullptr, const GramJob* gj = nullptr);
 hipError_t launch_residual(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const double* Ud,
                            const float* V, int r, double* part, int* nparts, hipStream_t s);
 hipError_t launch_sumsq_x(const void* X, int xt, int64_t m, int64_t n, int64_t ld, double* part,
@@ -145,13 +154,6 @@ bool mfma_eligible(int xt, int k);
 void mfma_pack_layout(int xt, int xtu, int k, int* kp, int* c, int* ldt);
 void mfma_xv_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes);
 void mfma_xtu_ws(int xt, int64_t m, int64_t n, int k, size_t* pack_bytes, size_t* part_bytes);
-// A Gram combine (gram_combine) a matrix-core product runs on the side:
-// dst (kp x kp) = sum of the nparts partial Grams at src.
-struct GramJob {
-  const double* src = nullptr;
-  int nparts = 0, kp = 0;
-  double* dst = nullptr;
-};
 hipError_t launch_xv_mfma(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* B,
                           int k, void* pack, float* part, float* out, hipStream_t s, int reduce,
                           int do_pack, int* nsplit = nullptr, const int32_t* stop = nullptr,
@@ -221,6 +223,9 @@ hipError_t launch_setup_state(const double* statpart, int nbU, int nbV, const do
 struct PackOut {
   unsigned short* p = nullptr;
   int kp = 0, c = 0, ldt = 0;
+  // the output rows also as float32 rows of the row pass's KP (columns past
+  // r zero), the layout the vector-ALU products read
+  float* pad = nullptr;
 };
 // One row pass (flags from RowFlags).  P: nsplit partials of stride pstride.
 // rec: kRecFields doubles per block; gpart: gram_part_len(kp) doubles per

@@ -105,13 +105,26 @@ __device__ __forceinline__ void load_tile(const typename XElem<XT>::T* __restric
   }
 }
 
+// Side job of the vector-ALU products: with a Gram job, the grid has one
+// more row of workgroups after the split rows, and those combine the previous
+// row pass's partial Grams (gram_combine, one wave per group of entries)
+// instead of streaming X.  Returns true in those workgroups.
+__device__ __forceinline__ bool xv_gram_side(const GramJob& gj) {
+  if (gj.src == nullptr || blockIdx.y != gridDim.y - 1) return false;
+  gram_combine(gj.src, gj.nparts, gj.kp, gj.dst,
+               (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave,
+               (int64_t)gridDim.x * (kThreads / kWave));
+  return true;
+}
+
 // P_part[s] (rows i0..i0+63, k columns) = X[i0.., tiles of split s] * Bp.
 // Bp: zero-padded copy of B, KP floats per row, rows up to the tiled width.
 template <int XT, int KP>
 __global__ __launch_bounds__(kThreads) void k_xv(const void* __restrict__ Xv, int64_t m, int64_t n,
                                                  int64_t ld, const float* __restrict__ Bp, int k,
                                                  int tiles_per_split, int64_t ntiles, int vec,
-                                                 float* __restrict__ out, int64_t split_stride) {
+                                                 float* __restrict__ out, int64_t split_stride,
+                                                 GramJob gj) {
   using T = Tile<XT>;
   using ET = typename T::ET;
   constexpr int kTileBytes = kRows * T::LDT * (int)sizeof(ET);
@@ -119,6 +132,7 @@ __global__ __launch_bounds__(kThreads) void k_xv(const void* __restrict__ Xv, in
   constexpr int kSmem = kTileBytes > kRedBytes ? kTileBytes : kRedBytes;
   __shared__ __align__(16) unsigned char smem[kSmem];
   ET* tile = reinterpret_cast<ET*>(smem);
+  if (xv_gram_side(gj)) return;
 
   const ET* __restrict__ X = reinterpret_cast<const ET*>(Xv);
   const int lane = threadIdx.x % kWave;
@@ -190,8 +204,9 @@ template <int XT, int KP>
 __global__ __launch_bounds__(kThreads) void k_xtu(const void* __restrict__ Xv, int64_t m, int64_t n,
                                                   int64_t ld, const float* __restrict__ Ap, int k,
                                                   int64_t rows_per_split, float* __restrict__ out,
-                                                  int64_t split_stride) {
+                                                  int64_t split_stride, GramJob gj) {
   using ET = typename XElem<XT>::T;
+  if (xv_gram_side(gj)) return;
   const ET* __restrict__ X = reinterpret_cast<const ET*>(Xv);
   const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool valid = j < n;
@@ -550,45 +565,45 @@ int grid_for(int64_t count, int threads = 256, int cap = 8192) {
 
 template <int XT, int KP>
 void xv_launch(dim3 grid, const void* X, int64_t m, int64_t n, int64_t ld, const float* Bp, int k,
-               int tps, int64_t ntiles, float* out, int64_t stride, hipStream_t s) {
+               int tps, int64_t ntiles, float* out, int64_t stride, hipStream_t s, GramJob gj) {
   const int vec = (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
                   ((ld * (int64_t)sizeof(typename XElem<XT>::T)) % 16 == 0);
   hipLaunchKernelGGL((k_xv<XT, KP>), grid, dim3(kThreads), 0, s, X, m, n, ld, Bp, k, tps, ntiles,
-                     vec, out, stride);
+                     vec, out, stride, gj);
 }
 
 template <int XT, int KP>
 void xtu_launch(dim3 grid, const void* X, int64_t m, int64_t n, int64_t ld, const float* Ap, int k,
-                int64_t rps, float* out, int64_t stride, hipStream_t s) {
+                int64_t rps, float* out, int64_t stride, hipStream_t s, GramJob gj) {
   hipLaunchKernelGGL((k_xtu<XT, KP>), grid, dim3(kThreads), 0, s, X, m, n, ld, Ap, k, rps, out,
-                     stride);
+                     stride, gj);
 }
 
 template <int XT>
 void xv_dispatch_kp(int kp, dim3 grid, const void* X, int64_t m, int64_t n, int64_t ld,
                     const float* Bp, int k, int tps, int64_t ntiles, float* out, int64_t stride,
-                    hipStream_t s) {
+                    hipStream_t s, GramJob gj) {
   switch (kp) {
-    case 8: xv_launch<XT, 8>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s); break;
-    case 16: xv_launch<XT, 16>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s); break;
-    case 32: xv_launch<XT, 32>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s); break;
-    case 48: xv_launch<XT, 48>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s); break;
-    case 64: xv_launch<XT, 64>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s); break;
-    default: xv_launch<XT, 80>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s); break;
+    case 8: xv_launch<XT, 8>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s, gj); break;
+    case 16: xv_launch<XT, 16>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s, gj); break;
+    case 32: xv_launch<XT, 32>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s, gj); break;
+    case 48: xv_launch<XT, 48>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s, gj); break;
+    case 64: xv_launch<XT, 64>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s, gj); break;
+    default: xv_launch<XT, 80>(grid, X, m, n, ld, Bp, k, tps, ntiles, out, stride, s, gj); break;
   }
 }
 
 template <int XT>
 void xtu_dispatch_kp(int kp, dim3 grid, const void* X, int64_t m, int64_t n, int64_t ld,
                      const float* Ap, int k, int64_t rps, float* out, int64_t stride,
-                     hipStream_t s) {
+                     hipStream_t s, GramJob gj) {
   switch (kp) {
-    case 8: xtu_launch<XT, 8>(grid, X, m, n, ld, Ap, k, rps, out, stride, s); break;
-    case 16: xtu_launch<XT, 16>(grid, X, m, n, ld, Ap, k, rps, out, stride, s); break;
-    case 32: xtu_launch<XT, 32>(grid, X, m, n, ld, Ap, k, rps, out, stride, s); break;
-    case 48: xtu_launch<XT, 48>(grid, X, m, n, ld, Ap, k, rps, out, stride, s); break;
-    case 64: xtu_launch<XT, 64>(grid, X, m, n, ld, Ap, k, rps, out, stride, s); break;
-    default: xtu_launch<XT, 80>(grid, X, m, n, ld, Ap, k, rps, out, stride, s); break;
+    case 8: xtu_launch<XT, 8>(grid, X, m, n, ld, Ap, k, rps, out, stride, s, gj); break;
+    case 16: xtu_launch<XT, 16>(grid, X, m, n, ld, Ap, k, rps, out, stride, s, gj); break;
+    case 32: xtu_launch<XT, 32>(grid, X, m, n, ld, Ap, k, rps, out, stride, s, gj); break;
+    case 48: xtu_launch<XT, 48>(grid, X, m, n, ld, Ap, k, rps, out, stride, s, gj); break;
+    case 64: xtu_launch<XT, 64>(grid, X, m, n, ld, Ap, k, rps, out, stride, s, gj); break;
+    default: xtu_launch<XT, 80>(grid, X, m, n, ld, Ap, k, rps, out, stride, s, gj); break;
   }
 }
 
@@ -657,7 +672,8 @@ hipError_t launch_pad_cols_f64(const float* in, int64_t rows, int k, int kp, dou
 // part must hold splits*m*k floats when splits > 1.
 hipError_t launch_xv(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* Bp, int k,
                      int kp, int splits, float* part, float* out, hipStream_t s, int reduce,
-                     int* nsplit) {
+                     int* nsplit, const GramJob* gj) {
+  const GramJob g = gj != nullptr ? *gj : GramJob();
   const int64_t tw = xv_tile_width(xt);
   const int64_t ntiles = (n + tw - 1) / tw;
   const int tps = (int)((ntiles + splits - 1) / splits);
@@ -665,11 +681,11 @@ hipError_t launch_xv(const void* X, int xt, int64_t m, int64_t n, int64_t ld, co
   const int64_t rb = (m + kRows - 1) / kRows;
   float* dst = eff > 1 ? part : out;
   const int64_t stride = m * k;
-  dim3 grid((unsigned)rb, (unsigned)eff);
+  dim3 grid((unsigned)rb, (unsigned)(eff + (g.src != nullptr ? 1 : 0)));
   switch (xt) {
-    case ENMF_F32: xv_dispatch_kp<0>(kp, grid, X, m, n, ld, Bp, k, tps, ntiles, dst, stride, s); break;
-    case ENMF_BF16: xv_dispatch_kp<1>(kp, grid, X, m, n, ld, Bp, k, tps, ntiles, dst, stride, s); break;
-    default: xv_dispatch_kp<2>(kp, grid, X, m, n, ld, Bp, k, tps, ntiles, dst, stride, s); break;
+    case ENMF_F32: xv_dispatch_kp<0>(kp, grid, X, m, n, ld, Bp, k, tps, ntiles, dst, stride, s, g); break;
+    case ENMF_BF16: xv_dispatch_kp<1>(kp, grid, X, m, n, ld, Bp, k, tps, ntiles, dst, stride, s, g); break;
+    default: xv_dispatch_kp<2>(kp, grid, X, m, n, ld, Bp, k, tps, ntiles, dst, stride, s, g); break;
   }
   hipError_t e = hipGetLastError();
   if (nsplit) *nsplit = (e == hipSuccess && !reduce) ? (int)eff : 1;
@@ -681,17 +697,18 @@ hipError_t launch_xv(const void* X, int xt, int64_t m, int64_t n, int64_t ld, co
 
 hipError_t launch_xtu(const void* X, int xt, int64_t m, int64_t n, int64_t ld, const float* Ap, int k,
                       int kp, int splits, float* part, float* out, hipStream_t s, int reduce,
-                     int* nsplit) {
+                     int* nsplit, const GramJob* gj) {
+  const GramJob g = gj != nullptr ? *gj : GramJob();
   const int64_t rps = (m + splits - 1) / splits;
   const int eff = (int)((m + rps - 1) / rps);
   const int64_t cb = (n + kThreads - 1) / kThreads;
   float* dst = eff > 1 ? part : out;
   const int64_t stride = n * k;
-  dim3 grid((unsigned)cb, (unsigned)eff);
+  dim3 grid((unsigned)cb, (unsigned)(eff + (g.src != nullptr ? 1 : 0)));
   switch (xt) {
-    case ENMF_F32: xtu_dispatch_kp<0>(kp, grid, X, m, n, ld, Ap, k, rps, dst, stride, s); break;
-    case ENMF_BF16: xtu_dispatch_kp<1>(kp, grid, X, m, n, ld, Ap, k, rps, dst, stride, s); break;
-    default: xtu_dispatch_kp<2>(kp, grid, X, m, n, ld, Ap, k, rps, dst, stride, s); break;
+    case ENMF_F32: xtu_dispatch_kp<0>(kp, grid, X, m, n, ld, Ap, k, rps, dst, stride, s, g); break;
+    case ENMF_BF16: xtu_dispatch_kp<1>(kp, grid, X, m, n, ld, Ap, k, rps, dst, stride, s, g); break;
+    default: xtu_dispatch_kp<2>(kp, grid, X, m, n, ld, Ap, k, rps, dst, stride, s, g); break;
   }
   hipError_t e = hipGetLastError();
   if (nsplit) *nsplit = (e == hipSuccess && !reduce) ? (int)eff : 1;

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(Team<KP>::NT, (KP >= 16 && (LOOP ? KP >= 32 : true)
     DevState* st, int half, int sweeps, int flags, double* __restrict__ rec,
     double* __restrict__ gpart, const double* __restrict__ headU, int nbU,
     const double* __restrict__ headV, int nbV, unsigned short* __restrict__ pack, int pkp, int pc,
-    int pldt, DecideArgs dec) {
+    int pldt, float* __restrict__ padout, DecideArgs dec) {
   using TM = Team<KP>;
   constexpr int T = TM::T;
   constexpr int NW = TM::NT / kWave;
@@ -408,6 +408,15 @@ __global__ __launch_bounds__(Team<KP>::NT, (KP >= 16 && (LOOP ? KP >= 32 : true)
         if (e < cnt) base[e] = sa[e / r][e % r];
       }
     }
+    if (padout != nullptr) {
+      // rows of KP floats: the first r columns of the output, zeros after
+      float* pb = padout + row0 * KP;
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + u * TM::NT;
+        if (e < nrow * KP) pb[e] = e % KP < r ? sa[e / KP][e % KP] : 0.f;
+      }
+    }
   }
   if (pack != nullptr) {
     const int64_t chunk_end = (rows + pc - 1) / pc * pc;
@@ -553,11 +562,11 @@ void rowupdate_launch(const float* A, float* Aout, int64_t rows, int r, const fl
   if ((int64_t)nb * TM::RB >= rows)
     hipLaunchKernelGGL((k_rowupdate<KP, false>), g, b, 0, s, A, Aout, rows, r, P, nsplit, pstride,
                        G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po.p, po.kp,
-                       po.c, po.ldt, dec);
+                       po.c, po.ldt, po.pad, dec);
   else
     hipLaunchKernelGGL((k_rowupdate<KP, true>), g, b, 0, s, A, Aout, rows, r, P, nsplit, pstride,
                        G, st, half, sweeps, flags, rec, gpart, headU, nbU, headV, nbV, po.p, po.kp,
-                       po.c, po.ldt, dec);
+                       po.c, po.ldt, po.pad, dec);
 }
 
 template <int KP>
