@@ -45,9 +45,9 @@ XT_MIN_BYTES = 512 << 20     # X at least this large: enmf_iterate runs X B on a
 # passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters' reading for a device copy of
 # known size (profiles/k_xtu_ratings_100000x20000_r20_hbm_traffic.txt).  They describe the
 # kernel source they were taken on and are reported only while it is unchanged.
-TRAFFIC = {"k_mfma_sha256_16": "32dc41465121a157",
-           "k_xtu_bf16 (X^T A)": 4211.70e6, "k_xtu_bf16 (X B on the transposed copy)": 4079.93e6,
-           "k_xtu_f32s (X^T A)": 8200.34e6, "k_xtu_f32s (X B on the transposed copy)": 8082.88e6}
+TRAFFIC = {"k_mfma_sha256_16": "b32d5ba64809d952",
+           "k_xtu_bf16 (X^T A)": 4211.78e6, "k_xtu_bf16 (X B on the transposed copy)": 4079.86e6,
+           "k_xtu_f32s (X^T A)": 8200.35e6, "k_xtu_f32s (X B on the transposed copy)": 8082.71e6}
 
 
 def parse():
